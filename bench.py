@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the unsplit PPM step on one MI355X.
+
+A step is one pass of the hot path over the level: ghost fill, CFL time step
+on the device, and the step itself (primitive conversion, flattening, PPM
+reconstruction, characteristic tracing, 12 two-shock Riemann solves per zone
+with corner-transport corrections, conservative update).  The default
+workload is the 256^3 single-box FP64 problem (gamma 5/3, random-mode density
+times a planar Sod jump, constant random velocity, periodic); inputs are
+synthetic and seeded and are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is zone-updates/s (valid zones x steps / s).
+`roofline` reports the stage kernel that takes the most time, with its
+algorithmic FP64 flops per launch divided by its mean launch time (HIP events
+on the stream the kernels run on) against the FP64 vector peak.
+`cpu_baseline` times the serial CPU reference evaluation on a bounded window
+of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/s per PPM step: batched vs plain per-box; adjoint/forward cost"
+
+# Algorithmic FP64 flops (add/sub, mul, div, sqrt; min/max not counted) per
+# unit of work of each stage kernel, counted by the op-counting instantiation
+# of the reference evaluation on windows of this workload's state
+# (oracle/opcount.py cfg2).  Units: see stage_units().
+FLOPS_PER_UNIT = {"prim": 15.0, "flatten": 64.99, "trace": 388.27, "riemann1": 168.06,
+                  "riemann2": 246.06, "riemann3": 276.06, "update": 45.0}
+# MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_units(n):
+    """Units each stage kernel processes on one box of valid extents n."""
+    import numpy as np
+    w = np.asarray(n, dtype=np.int64)
+    e = w + 2
+    r1 = sum((w[d] + 1) * np.prod([e[t] for t in range(3) if t != d]) for d in range(3))
+    r2 = sum((w[d] + 1) * w[t] * e[3 - d - t] for d in range(3) for t in range(3) if t != d)
+    r3 = sum((w[d] + 1) * np.prod([w[t] for t in range(3) if t != d]) for d in range(3))
+    return {"prim": int(np.prod(w + 8)), "flatten": int(np.prod(e)), "trace": int(3 * np.prod(e)),
+            "riemann1": int(r1), "riemann2": int(r2), "riemann3": int(r3), "update": int(np.prod(w))}
+
+
+def make_workload(name):
+    from paper_1008_2801_amd import inputs as I
+    if name == "cfg2":
+        return I.cfg2()
+    if name == "cfg2-small":
+        return I.cfg2(64)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(wl, window_edge, gamma):
+    """Serial oracle on one step of a cubic window of the workload."""
+    import numpy as np
+    from oracle import oracle as O
+    lay = wl.layout
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    p = O.params(gamma=gamma)
+    s, _ = O.max_wavespeed(st[0], wl.dx, p)
+    dt = p.cfl / s
+    lo = (0, 0, 0)
+    hi = (window_edge - 1,) * 3
+    t0 = time.perf_counter()
+    O.step(st[0], dt, wl.dx, p, window=(lo, hi))
+    sec = time.perf_counter() - t0
+    zones = window_edge ** 3
+    return {"value": zones / sec, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one step of the same workload on the {window_edge}^3 window of valid zones "
+                      f"at the box corner (serial C++ reference, -O2, 1 thread), {sec:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--cpu-window", type=int, default=160)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU box distribution is a design, not an implementation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1008_2801_amd import ppm as P
+
+    if args.calibrate_copy:
+        n = (1 << 30) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                          "copies": 3}))
+        return
+
+    wl = make_workload(args.workload)
+    lay = wl.layout
+    print(f"bench: workload {wl.name} {lay.n(0)} x {lay.nbox} box(es), building state", file=sys.stderr,
+          flush=True)
+    lev = P.Level(lay)
+    U = torch.from_numpy(wl.arena).to("cuda")
+    V = lev.new_state()
+    p = P.params(gamma=wl.gamma, precision=wl.precision)
+    lev.ensure_workspace(p.precision)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def step(a, b):
+        lev.fill_boundary(a)
+        lev.compute_dt(a, wl.dx, p, out=dtv)
+        lev.hydro_step(a, b, wl.dx, p, dt_dev=dtv)
+        return b, a
+
+    for _ in range(args.warmup):
+        U, V = step(U, V)
+    torch.cuda.synchronize()
+    lev.profile_read()
+    lev.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        U, V = step(U, V)
+    e1.record()
+    torch.cuda.synchronize()
+    lev.profile_enable(False)
+    ms = e0.elapsed_time(e1)
+    prof = lev.profile_read()
+    flags = lev.check_status()
+    zones = lay.valid_zones()
+    value = zones * args.steps / (ms / 1e3)
+
+    # dominant stage kernel and its arithmetic roofline
+    units = {k: 0 for k in FLOPS_PER_UNIT}
+    for b in range(lay.nbox):
+        for k, v in stage_units(lay.n(b)).items():
+            units[k] += v
+    stages = {k: prof[k] for k in FLOPS_PER_UNIT}
+    dom = max(stages, key=lambda k: stages[k][0])
+    t_ms, cnt = stages[dom]
+    mean_s = t_ms / cnt / 1e3
+    flops = FLOPS_PER_UNIT[dom] * units[dom]
+    achieved = flops / mean_s / 1e12
+    step_flops = sum(FLOPS_PER_UNIT[k] * units[k] for k in FLOPS_PER_UNIT)
+    out = {
+        "metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if p.precision == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {lay.n(0)[0]}^3 single box, FP64, gamma {wl.gamma:.4g}, "
+                               "random-mode density x planar Sod jump, periodic, CFL 0.5, plain step",
+                   "valid_zones": zones, "boxes": lay.nbox},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops},
+        "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
+        "step_flop_rate_tflops": step_flops * args.steps / (ms / 1e3) / 1e12,
+        "status_flags": flags,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU reference on a window", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_window, wl.gamma)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

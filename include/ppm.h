@@ -1,0 +1,183 @@
+/*
+ * ppm.h -- C ABI of the MI355X (gfx950) unsplit PPM hydro step.
+ *
+ * The library advances the 3-D gamma-law Euler equations by one explicit
+ * unsplit Godunov step on the rectangular boxes (FABs) of one refinement
+ * level: the "fully explicit advance of a hyperbolic system of conservation
+ * laws" of the paper's compressible code (Sec. 1), on its MultiFAB / FAB data
+ * model with ghost cells filled from intersecting grids, the intersections
+ * found by a hash sort of the boxes and cached (Sec. 2).
+ *
+ * The discretisation (PPM with the Colella-Woodward limiter and flattening,
+ * characteristic tracing, a two-shock Riemann solver with a fixed Newton
+ * count, 12-solve corner-transport-upwind corrections, conservative update)
+ * is the classical one the paper's code is built on; the paper itself only
+ * names the advance.
+ *
+ * Conventions shared by every entry point:
+ *  - All device pointers are HIP device memory owned by the caller.  The
+ *    library owns only the context (box metadata, fill plan, tile lists,
+ *    a few bytes of device constants and status flags).
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*, 0 = the null stream) and never synchronise, except
+ *    ppm_check_status and the autotuner.
+ *  - Every call returns PPM_OK or an error code; on error nothing was
+ *    enqueued and ppm_last_error(ctx) describes it.
+ *
+ * State arena: one contiguous float64 buffer for the whole level.  Box b
+ * (valid extents n = hi - lo + 1, stored extents N = n + 8) starts at
+ * element off[b] (ppm_layout_offsets) and holds 5 components (rho, rho u,
+ * rho v, rho w, rho E) in the order [c][k][j][i]: element
+ *   off[b] + ((c*Nz + k+4)*Ny + j+4)*Nx + i+4
+ * is zone (i, j, k) of box b, i in [-4, nx+3] (4 ghost zones per side).
+ *
+ * Flux arena of axis d: box b starts at element foff_d[b]
+ * (ppm_flux_offsets) and holds 5 components over the face-centred extents
+ * (n_d + 1 along d, n along the others), order [c][k][j][i]; face i along x
+ * lies between zones i-1 and i.  Fluxes are per unit area per unit time,
+ * time-centred (the F^{n+1/2} of the update).
+ */
+#ifndef PPM_H
+#define PPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PPM_OK = 0,
+  PPM_EINVAL = 1,    /* invalid argument; nothing enqueued */
+  PPM_EHIP = 2,      /* HIP runtime error (string kept in ppm_last_error) */
+  PPM_ENONPHYS = 3   /* status flags raised (ppm_check_status only) */
+};
+
+enum { PPM_BC_PERIODIC = 0, PPM_BC_OUTFLOW = 1, PPM_BC_REFLECT = 2 };
+
+/* status flags accumulated on the device */
+enum { PPM_FLAG_NONPHYS = 1, /* rho <= 0, p <= 0 or a non-finite value in an input state */
+       PPM_FLAG_FLOOR = 2 }; /* a density/pressure floor bound inside the step */
+
+/* launch forms of the step */
+enum { PPM_LAUNCH_BATCHED = 0, /* each stage: one launch over the tile list of all boxes */
+       PPM_LAUNCH_PER_BOX = 1  /* each stage: one launch per box (the plain baseline) */ };
+
+typedef struct { int32_t lo[3], hi[3]; } ppm_box; /* inclusive valid zones, global index space */
+
+typedef struct {
+  int32_t nbox;
+  const ppm_box* boxes;  /* disjoint, tiling `domain` exactly */
+  ppm_box domain;
+  int32_t bc[6];         /* x-lo, x-hi, y-lo, y-hi, z-lo, z-hi; periodic axes need both faces periodic */
+  int32_t ngrow;         /* ghost width; must be 4 */
+} ppm_layout;
+
+typedef struct {
+  double gamma;          /* > 1 */
+  double cfl;            /* Courant number of the dt rule, in (0, 1) */
+  double small_dens, small_pres; /* floors (> 0) */
+  double grav[3];        /* constant gravity, Heun source; zeros: none */
+  int32_t limiter;       /* 1: MC slopes + CW84 limiter; 0: unlimited (smooth) */
+  int32_t flattening;    /* 1: CW84 shock flattening (needs limiter = 1) */
+  int32_t riemann_iters; /* fixed Newton iterations of the two-shock solver, 0..16 */
+  int32_t precision;     /* 0: FP64 throughout; 1: FP32 reconstruction, FP64 fluxes/update */
+} ppm_params;
+
+typedef struct ppm_ctx ppm_ctx;
+typedef struct ppm_graph ppm_graph;
+
+/* Context for one level layout (paper Sec. 2: replicated box metadata).
+ * Validates the layout (disjoint boxes tiling the domain, ngrow == 4, box
+ * and domain extents >= 4 along reflecting/outflow axes), builds or reuses
+ * the ghost-fill plan (hash-sorted intersections, cached across contexts)
+ * and the tile lists, and uploads them.  Allocates device memory for them.
+ * Returns PPM_EINVAL for an invalid layout, PPM_EHIP on allocation failure. */
+int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out);
+int ppm_ctx_destroy(ppm_ctx* ctx);
+const char* ppm_last_error(const ppm_ctx* ctx);
+
+/* off[0..nbox]: element offsets of each box in the state arena; off[nbox]
+ * is the arena length.  Caller provides nbox+1 int64 slots. */
+int ppm_layout_offsets(const ppm_ctx* ctx, int64_t* off);
+/* The same for the flux arena of axis d (0..2). */
+int ppm_flux_offsets(const ppm_ctx* ctx, int32_t d, int64_t* off);
+
+/* Device scratch for the step, owned by the caller: bytes needed for the
+ * given precision, then the buffer to use (kept until replaced; must stay
+ * allocated while work that uses it is in flight).  The step returns
+ * PPM_EINVAL if no large-enough workspace is set. */
+size_t ppm_workspace_bytes(const ppm_ctx* ctx, int32_t precision);
+int ppm_set_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* O1 -- ghost fill (paper Sec. 2: filling ghost cells from intersecting
+ * grids).  Writes the 4-deep ghost shells (faces, edges, corners) of every
+ * box of U from the owning boxes of their images: periodic axes wrap,
+ * outflow faces copy the nearest valid zone, reflecting faces mirror about
+ * the wall with the normal momentum negated.  In place; valid zones are
+ * read, ghost zones written.  mode: PPM_LAUNCH_BATCHED (one launch) or
+ * PPM_LAUNCH_PER_BOX (one launch per destination box). */
+int ppm_fill_boundary(ppm_ctx* ctx, double* U, int32_t mode, void* stream);
+
+/* O11 -- CFL rule.  Writes to dt_dev[0] the time step
+ *   dt = cfl / max over valid zones and axes of (|u_d| + c) / h_d
+ * computed in FP64 from U (valid zones only; ghosts not read), and to
+ * dt_dev[1] the maximum signal speed.  dt_dev: 2 device doubles. */
+int ppm_compute_dt(ppm_ctx* ctx, const double* U, const double dx[3], const ppm_params* params,
+                   double* dt_dev, void* stream);
+
+/* O2-O10 -- one unsplit PPM step (the hot path).  Reads U (valid and ghost
+ * zones; ghosts must be filled), writes the valid zones of Unew (ghosts of
+ * Unew untouched).  dt: the time step, or, if dt_dev is non-null, read on
+ * the device from dt_dev[0] (dt is then ignored).  flux: null, or three
+ * flux-arena pointers (any may be null) that receive F^{n+1/2}.  U and Unew
+ * must not overlap.  Needs a workspace (ppm_set_workspace).  Raises
+ * PPM_FLAG_* on the device (ppm_check_status). */
+int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                   const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                   void* stream);
+
+/* Batched form captured in a HIP graph: nsteps steps alternating
+ * A -> B -> A ..., each step = [fill, CFL dt on the device, step].  After
+ * an even nsteps the result is in A, after an odd nsteps in B.  The graph
+ * keeps the pointers; launches replay it on the stream. */
+int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3],
+                     const ppm_params* params, int32_t nsteps, void* stream, ppm_graph** out);
+int ppm_graph_launch(ppm_graph* g, void* stream);
+int ppm_graph_destroy(ppm_graph* g);
+
+/* Stage timing with HIP events recorded on the caller's stream around each
+ * batched fill, dt and step stage launch while enabled (per-box launches are
+ * not timed).  ppm_profile_read waits for the recorded events, writes the
+ * summed milliseconds and the number of timed launches of each stage to
+ * ms[PPM_PROF_NTAGS] and count[PPM_PROF_NTAGS], and forgets them. */
+enum { PPM_PROF_FILL = 0, PPM_PROF_DT, PPM_PROF_PRIM, PPM_PROF_FLATTEN, PPM_PROF_TRACE,
+       PPM_PROF_RIEMANN1, PPM_PROF_RIEMANN2, PPM_PROF_RIEMANN3, PPM_PROF_UPDATE, PPM_PROF_NTAGS };
+int ppm_profile_enable(ppm_ctx* ctx, int32_t on);
+int ppm_profile_read(ppm_ctx* ctx, double* ms, int64_t* count);
+
+/* Synchronises the stream, returns the accumulated PPM_FLAG_* bits in
+ * *flags and clears them.  Returns PPM_ENONPHYS if any flag was set. */
+int ppm_check_status(ppm_ctx* ctx, void* stream, int32_t* flags);
+
+/* ---- the ghost-fill plan on the host (no device work, no GPU needed) --- */
+/* Builds the fill plan of a layout: brute = 0 takes it from the plan cache
+ * (hash-sorted intersections, paper Sec. 2, built on a miss), brute != 0
+ * builds it by all-pairs box intersection, O(N^2).  Writes up to max
+ * descriptors of 20 int32 each to out20 (may be null) and the descriptor
+ * count to *count.  Descriptor: dst box, src box, dst lo[3], dst hi[3]
+ * (destination-box-local zone indices), per-axis map src = a*dst + c as
+ * a[3], c[3] (source-box-local), sign mask (bit d: momentum d negated),
+ * zone count, 4 reserved.  Both forms list the same descriptors in the same
+ * order.  PPM_EINVAL for an invalid layout. */
+int ppm_plan_build(const ppm_layout* layout, int32_t brute, int32_t max, int32_t* out20, int32_t* count);
+/* Executes the cached plan of the layout on a host copy of the state arena. */
+int ppm_fill_boundary_host(const ppm_layout* layout, double* U_host);
+/* Plan cache statistics: lookups, hits, entries. */
+int ppm_plan_cache_stats(int64_t* lookups, int64_t* hits, int32_t* entries);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PPM_H */

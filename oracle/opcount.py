@@ -1,0 +1,100 @@
+"""TEST INFRASTRUCTURE -- algorithmic operation counts per unit of work.
+
+Runs the op-counting instantiation of the oracle on windows of a workload's
+initial state and divides each stage's floating-point operation count by the
+number of units that stage processes on the window, giving the per-unit
+figures used for the arithmetic roofline of the step's kernels.  A flop is
+one add/sub, mul, div or sqrt (min/max/abs/compare are not counted).
+
+Units (window of valid extents w, traced region w + 2 per axis):
+  prim      zones of the primitive region, prod(w + 8)
+  flatten   traced zones, prod(w + 2)
+  trace     traced (zone, axis) pairs, 3 prod(w + 2)
+  riemann1  normal-predictor faces, sum_d (w_d + 1) prod_{t != d} (w_t + 2)
+  riemann2  single-transverse faces, sum over (d, t) of (w_d + 1) w_t (w_r + 2)
+  riemann3  final faces, sum_d (w_d + 1) w_t1 w_t2
+  update    valid zones, prod(w)
+The GPU kernel riemann2 also forms the corrected states (oracle stage
+"transverse1"), riemann3 likewise ("transverse2"); their counts are merged.
+
+Usage: python oracle/opcount.py [cfg2|cfg3|cfg4|cfg5] -> JSON on stdout.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+sys.path = [q for q in sys.path if os.path.abspath(q or ".") != HERE]
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1008_2801_amd import inputs as I  # noqa: E402
+
+KERNELS = {"prim": ["prim"], "flatten": ["flatten"], "trace": ["trace"], "riemann1": ["riemann1"],
+           "riemann2": ["transverse1", "riemann2"], "riemann3": ["transverse2", "riemann3"],
+           "update": ["update"]}
+
+
+def units(w):
+    w = np.asarray(w, dtype=np.int64)
+    e = w + 2
+    r1 = sum((w[d] + 1) * np.prod([e[t] for t in range(3) if t != d]) for d in range(3))
+    r2 = 0
+    for d in range(3):
+        for t in range(3):
+            if t != d:
+                r = 3 - d - t
+                r2 += (w[d] + 1) * w[t] * e[r]
+    r3 = sum((w[d] + 1) * np.prod([w[t] for t in range(3) if t != d]) for d in range(3))
+    return {"prim": int(np.prod(w + 8)), "flatten": int(np.prod(e)), "trace": int(3 * np.prod(e)),
+            "riemann1": int(r1), "riemann2": int(r2), "riemann3": int(r3), "update": int(np.prod(w))}
+
+
+def per_unit(U, dx, p, windows):
+    tot = {k: 0 for k in KERNELS}
+    cnt = {k: 0 for k in KERNELS}
+    kinds = {k: np.zeros(len(O.OPKINDS), dtype=np.int64) for k in KERNELS}
+    for lo, hi in windows:
+        _, counts, _ = O.step_count(U, 1e-3, dx, p, window=(lo, hi))
+        u = units(np.array(hi) - np.array(lo) + 1)
+        for k, stages in KERNELS.items():
+            c = sum(counts[O.STAGES.index(s)] for s in stages)
+            kinds[k] += c
+            tot[k] += int(c[:4].sum())
+            cnt[k] += u[k]
+    return ({k: tot[k] / cnt[k] for k in KERNELS},
+            {k: {O.OPKINDS[i]: kinds[k][i] / cnt[k] for i in range(len(O.OPKINDS))} for k in KERNELS})
+
+
+def main(name="cfg2"):
+    if name == "cfg2":
+        wl = I.cfg2(64)  # same recipe (seed, modes, jump, velocity draws) on a 64^3 box
+    elif name == "cfg3":
+        wl = I.cfg3()
+    elif name == "cfg4":
+        wl = I.cfg4(64)
+    else:
+        wl = I.cfg5(2, 32)
+    lay = wl.layout
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    U = st[0]
+    n = lay.n(0)
+    rng = np.random.default_rng(0)
+    w = 12
+    windows = []
+    for _ in range(6):
+        lo = [int(rng.integers(0, n[d] - w)) for d in range(3)]
+        windows.append((tuple(lo), tuple(v + w - 1 for v in lo)))
+    p = O.params(gamma=wl.gamma, grav=wl.grav)
+    flops, kinds = per_unit(U, wl.dx, p, windows)
+    print(json.dumps({"workload": name, "windows": windows, "flops_per_unit": flops,
+                      "ops_per_unit_by_kind": kinds}, indent=1))
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:])

@@ -1,0 +1,756 @@
+// Host side of the library: level context, ghost-fill plan (hash-sorted box
+// intersections with a plan cache), tile lists, the C ABI of ppm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ppm_internal.h"
+
+using namespace ppm;
+
+namespace {
+
+struct IBox {
+  int lo[3], hi[3];
+};
+
+// The ghost-fill plan of a layout: copy descriptors grouped by destination
+// box, with the exclusive prefix of their zone counts.
+struct Plan {
+  std::vector<FillDesc> desc;
+  std::vector<long long> start;   // ndesc + 1
+  std::vector<int> box_desc;      // nbox + 1: descriptor range of each destination box
+};
+
+struct LayoutKey {
+  std::vector<int> v;  // nbox, boxes, domain, bc, ngrow
+  size_t hash = 0;
+  bool operator==(const LayoutKey& o) const { return hash == o.hash && v == o.v; }
+};
+
+LayoutKey make_key(const ppm_layout& L) {
+  LayoutKey k;
+  k.v.push_back(L.nbox);
+  for (int b = 0; b < L.nbox; ++b)
+    for (int d = 0; d < 3; ++d) { k.v.push_back(L.boxes[b].lo[d]); k.v.push_back(L.boxes[b].hi[d]); }
+  for (int d = 0; d < 3; ++d) { k.v.push_back(L.domain.lo[d]); k.v.push_back(L.domain.hi[d]); }
+  for (int f = 0; f < 6; ++f) k.v.push_back(L.bc[f]);
+  k.v.push_back(L.ngrow);
+  size_t h = 1469598103934665603ull;  // FNV-1a over the words
+  for (int x : k.v) { h ^= (size_t)(unsigned)x; h *= 1099511628211ull; }
+  k.hash = h;
+  return k;
+}
+
+// -------------------------------------------------------- validation -------
+std::string validate_layout(const ppm_layout& L) {
+  if (L.nbox < 1 || !L.boxes) return "layout: no boxes";
+  if (L.ngrow != NG) return "layout: ngrow must be 4";
+  long long dvol = 1;
+  int ext[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = L.domain.hi[d] - L.domain.lo[d] + 1;
+    if (ext[d] < NG) return "layout: domain extent below the ghost width";
+    dvol *= ext[d];
+    const bool pl = L.bc[2 * d] == PPM_BC_PERIODIC, ph = L.bc[2 * d + 1] == PPM_BC_PERIODIC;
+    if (pl != ph) return "layout: a periodic axis needs both faces periodic";
+    for (int s = 0; s < 2; ++s)
+      if (L.bc[2 * d + s] < 0 || L.bc[2 * d + s] > 2) return "layout: unknown boundary code";
+  }
+  long long vol = 0;
+  for (int b = 0; b < L.nbox; ++b) {
+    long long v = 1;
+    for (int d = 0; d < 3; ++d) {
+      const int n = L.boxes[b].hi[d] - L.boxes[b].lo[d] + 1;
+      if (n < 1) return "layout: empty box";
+      if (L.boxes[b].lo[d] < L.domain.lo[d] || L.boxes[b].hi[d] > L.domain.hi[d])
+        return "layout: box outside the domain";
+      v *= n;
+    }
+    vol += v;
+  }
+  if (vol != dvol) return "layout: boxes do not tile the domain (volume mismatch)";
+  // disjointness through a painted ownership map of the domain
+  std::vector<int> own((size_t)dvol, -1);
+  for (int b = 0; b < L.nbox; ++b) {
+    const ppm_box& B = L.boxes[b];
+    for (int z = B.lo[2]; z <= B.hi[2]; ++z)
+      for (int y = B.lo[1]; y <= B.hi[1]; ++y)
+        for (int x = B.lo[0]; x <= B.hi[0]; ++x) {
+          const size_t i = ((size_t)(z - L.domain.lo[2]) * ext[1] + (y - L.domain.lo[1])) * ext[0] +
+                           (x - L.domain.lo[0]);
+          if (own[i] >= 0) return "layout: boxes overlap";
+          own[i] = b;
+        }
+  }
+  return "";
+}
+
+// ---------------------------------------------------- plan construction ----
+// Intersections of ghost regions with boxes (paper Sec. 2).  The domain is
+// cut into M rectangular bins at least one box wide per axis; every box is
+// sorted into the bin of its lowest corner, so a box extends no further than
+// the next bin up.  A query region then only looks at the bins from one
+// below its low corner to its high corner: O(N + N^2/M) for all queries
+// instead of O(N^2) all-pairs.
+struct Binner {
+  int dlo[3], ext[3], bs[3], nb[3], maxext[3];
+  std::vector<std::vector<int>> bins;
+  const ppm_layout* L;
+  bool brute;
+
+  Binner(const ppm_layout& lay, bool brute_force) : L(&lay), brute(brute_force) {
+    for (int d = 0; d < 3; ++d) {
+      dlo[d] = lay.domain.lo[d];
+      ext[d] = lay.domain.hi[d] - lay.domain.lo[d] + 1;
+      maxext[d] = 1;
+      for (int b = 0; b < lay.nbox; ++b)
+        maxext[d] = std::max(maxext[d], lay.boxes[b].hi[d] - lay.boxes[b].lo[d] + 1);
+      bs[d] = maxext[d];
+      nb[d] = (ext[d] + bs[d] - 1) / bs[d];
+    }
+    bins.assign((size_t)nb[0] * nb[1] * nb[2], {});
+    for (int b = 0; b < lay.nbox; ++b) {
+      int k[3];
+      for (int d = 0; d < 3; ++d) k[d] = (lay.boxes[b].lo[d] - dlo[d]) / bs[d];
+      bins[((size_t)k[2] * nb[1] + k[1]) * nb[0] + k[0]].push_back(b);
+    }
+  }
+
+  // Boxes intersecting the global region q (inside the domain), in box order.
+  void query(const IBox& q, std::vector<int>& out) const {
+    out.clear();
+    auto hit = [&](int b) {
+      const ppm_box& B = L->boxes[b];
+      for (int d = 0; d < 3; ++d)
+        if (B.hi[d] < q.lo[d] || B.lo[d] > q.hi[d]) return false;
+      return true;
+    };
+    if (brute) {
+      for (int b = 0; b < L->nbox; ++b)
+        if (hit(b)) out.push_back(b);
+      return;
+    }
+    int k0[3], k1[3];
+    for (int d = 0; d < 3; ++d) {
+      k0[d] = std::max(0, (std::max(q.lo[d] - maxext[d] + 1, dlo[d]) - dlo[d]) / bs[d]);
+      k1[d] = std::min(nb[d] - 1, (q.hi[d] - dlo[d]) / bs[d]);
+    }
+    for (int z = k0[2]; z <= k1[2]; ++z)
+      for (int y = k0[1]; y <= k1[1]; ++y)
+        for (int x = k0[0]; x <= k1[0]; ++x)
+          for (int b : bins[((size_t)z * nb[1] + y) * nb[0] + x])
+            if (hit(b)) out.push_back(b);
+    std::sort(out.begin(), out.end());
+  }
+};
+
+Plan build_plan(const ppm_layout& L, bool brute) {
+  Plan P;
+  Binner bin(L, brute);
+  int dlo[3], dhi[3], ext[3];
+  for (int d = 0; d < 3; ++d) {
+    dlo[d] = L.domain.lo[d];
+    dhi[d] = L.domain.hi[d];
+    ext[d] = dhi[d] - dlo[d] + 1;
+  }
+  std::vector<int> found;
+  P.box_desc.push_back(0);
+  for (int b = 0; b < L.nbox; ++b) {
+    const ppm_box& B = L.boxes[b];
+    int n[3];
+    for (int d = 0; d < 3; ++d) n[d] = B.hi[d] - B.lo[d] + 1;
+    // 26 ghost sub-regions of the grown box (box-local), each cut at the
+    // domain faces into pieces wholly inside or wholly outside the domain.
+    for (int sz = -1; sz <= 1; ++sz)
+      for (int sy = -1; sy <= 1; ++sy)
+        for (int sx = -1; sx <= 1; ++sx) {
+          if (sx == 0 && sy == 0 && sz == 0) continue;
+          const int s[3] = {sx, sy, sz};
+          // per axis: up to 3 pieces [a, b] in global coordinates + their map
+          struct Piece { int lo, hi, a, c, refl; };
+          std::vector<Piece> pcs[3];
+          for (int d = 0; d < 3; ++d) {
+            int l, h;
+            if (s[d] < 0) { l = -NG; h = -1; }
+            else if (s[d] == 0) { l = 0; h = n[d] - 1; }
+            else { l = n[d]; h = n[d] + NG - 1; }
+            l += B.lo[d];
+            h += B.lo[d];
+            const int cuts[4] = {l, std::max(l, dlo[d]), std::min(h, dhi[d]) + 1, h + 1};
+            // below the domain
+            if (cuts[0] < cuts[1]) {
+              const int bc = L.bc[2 * d];
+              Piece pc{cuts[0], std::min(cuts[1] - 1, h), 1, 0, 0};
+              if (bc == PPM_BC_PERIODIC) { pc.a = 1; pc.c = ext[d]; }
+              else if (bc == PPM_BC_OUTFLOW) { pc.a = 0; pc.c = dlo[d]; }
+              else { pc.a = -1; pc.c = 2 * dlo[d] - 1; pc.refl = 1; }
+              pcs[d].push_back(pc);
+            }
+            if (cuts[1] < cuts[2]) pcs[d].push_back(Piece{cuts[1], cuts[2] - 1, 1, 0, 0});
+            if (cuts[2] < cuts[3]) {
+              const int bc = L.bc[2 * d + 1];
+              Piece pc{std::max(cuts[2], l), cuts[3] - 1, 1, 0, 0};
+              if (bc == PPM_BC_PERIODIC) { pc.a = 1; pc.c = -ext[d]; }
+              else if (bc == PPM_BC_OUTFLOW) { pc.a = 0; pc.c = dhi[d]; }
+              else { pc.a = -1; pc.c = 2 * dhi[d] + 1; pc.refl = 1; }
+              pcs[d].push_back(pc);
+            }
+          }
+          for (const Piece& px : pcs[0])
+            for (const Piece& py : pcs[1])
+              for (const Piece& pz : pcs[2]) {
+                const Piece* pp[3] = {&px, &py, &pz};
+                IBox img;
+                for (int d = 0; d < 3; ++d) {
+                  const Piece& q = *pp[d];
+                  if (q.a == 1) { img.lo[d] = q.lo + q.c; img.hi[d] = q.hi + q.c; }
+                  else if (q.a == -1) { img.lo[d] = q.c - q.hi; img.hi[d] = q.c - q.lo; }
+                  else { img.lo[d] = q.c; img.hi[d] = q.c; }
+                }
+                bin.query(img, found);
+                for (int sb : found) {
+                  const ppm_box& S = L.boxes[sb];
+                  FillDesc D;
+                  D.dst = b;
+                  D.src = sb;
+                  D.sign = 0;
+                  long long cnt = 1;
+                  for (int d = 0; d < 3; ++d) {
+                    const Piece& q = *pp[d];
+                    const int jl = std::max(img.lo[d], S.lo[d]), jh = std::min(img.hi[d], S.hi[d]);
+                    int gl, gh;
+                    if (q.a == 1) { gl = jl - q.c; gh = jh - q.c; }
+                    else if (q.a == -1) { gl = q.c - jh; gh = q.c - jl; }
+                    else { gl = q.lo; gh = q.hi; }
+                    D.lo[d] = gl - B.lo[d];
+                    D.hi[d] = gh - B.lo[d];
+                    D.a[d] = q.a;
+                    // src_local = a * dst_local + (a * lo_dst + c - lo_src)
+                    D.c[d] = q.a * B.lo[d] + q.c - S.lo[d];
+                    if (q.refl) D.sign |= 1 << d;
+                    cnt *= (gh - gl + 1);
+                  }
+                  D.count = (int)cnt;
+                  P.desc.push_back(D);
+                }
+              }
+        }
+    P.box_desc.push_back((int)P.desc.size());
+  }
+  P.start.resize(P.desc.size() + 1);
+  P.start[0] = 0;
+  for (size_t k = 0; k < P.desc.size(); ++k) P.start[k + 1] = P.start[k] + P.desc[k].count;
+  return P;
+}
+
+// Cache of fill plans keyed by the layout (paper Sec. 2: frequently used
+// communication patterns are kept).  Least-recently-used eviction.
+struct PlanCache {
+  std::mutex mu;
+  std::list<std::pair<LayoutKey, std::shared_ptr<const Plan>>> lru;
+  size_t cap = 16;
+  long long lookups = 0, hits = 0;
+
+  std::shared_ptr<const Plan> get(const ppm_layout& L, bool& hit) {
+    LayoutKey k = make_key(L);
+    std::lock_guard<std::mutex> g(mu);
+    ++lookups;
+    for (auto it = lru.begin(); it != lru.end(); ++it)
+      if (it->first == k) {
+        ++hits;
+        hit = true;
+        lru.splice(lru.begin(), lru, it);
+        return lru.front().second;
+      }
+    hit = false;
+    auto p = std::make_shared<const Plan>(build_plan(L, false));
+    lru.emplace_front(std::move(k), p);
+    if (lru.size() > cap) lru.pop_back();
+    return p;
+  }
+};
+PlanCache& plan_cache() {
+  static PlanCache c;
+  return c;
+}
+
+long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// ============================================================ context =====
+struct ppm_ctx {
+  std::vector<ppm_box> boxes;
+  ppm_layout layout{};
+  std::vector<int64_t> off, foff[3];
+  std::shared_ptr<const Plan> plan;
+  bool plan_hit = false;
+  std::vector<Tile> tilesS, tilesE;
+  std::vector<int> tS_begin, tE_begin;  // nbox + 1
+  long long LS = 0, LE = 0;
+  // device copies
+  DevBox* d_boxes = nullptr;
+  Tile* d_tilesS = nullptr;
+  Tile* d_tilesE = nullptr;
+  FillDesc* d_desc = nullptr;
+  long long* d_start = nullptr;
+  StepConsts* d_consts = nullptr;
+  int* d_flags = nullptr;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  std::string err;
+  // stage timing with HIP events (ppm_profile_enable / ppm_profile_read)
+  struct ProfRec {
+    int tag0, n;
+    std::array<hipEvent_t, STEP_EVENTS> ev;
+  };
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<std::array<hipEvent_t, STEP_EVENTS>> pool;
+
+  // An event set for a record of n events starting at stage tag tag0.
+  ProfRec* begin_rec(int tag0, int n) {
+    std::array<hipEvent_t, STEP_EVENTS> ev{};
+    if (!pool.empty()) {
+      ev = pool.back();
+      pool.pop_back();
+    } else {
+      for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    }
+    recs.push_back(ProfRec{tag0, n, ev});
+    return &recs.back();
+  }
+
+  DevLevel level() const {
+    DevLevel L;
+    L.boxes = d_boxes;
+    L.tilesS = d_tilesS;
+    L.tilesE = d_tilesE;
+    L.desc = d_desc;
+    L.desc_start = d_start;
+    L.consts = d_consts;
+    L.flags = d_flags;
+    L.LS = LS;
+    L.LE = LE;
+    return L;
+  }
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PPM_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return PPM_EHIP;
+  }
+};
+
+struct ppm_graph {
+  ppm_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* dtv = nullptr;  // device [dt, max signal speed] of the step being replayed
+};
+
+namespace {
+template <class T> hipError_t upload(T** dst, const std::vector<T>& v) {
+  const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+std::string validate_params(const ppm_params* p) {
+  if (!p) return "params: null";
+  if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return "params: gamma must be > 1";
+  if (!(p->small_dens > 0.0) || !(p->small_pres > 0.0)) return "params: floors must be > 0";
+  if (p->riemann_iters < 0 || p->riemann_iters > 16) return "params: riemann_iters must be in [0, 16]";
+  if (p->precision != 0 && p->precision != 1) return "params: precision must be 0 or 1";
+  if ((p->limiter != 0 && p->limiter != 1) || (p->flattening != 0 && p->flattening != 1))
+    return "params: limiter/flattening must be 0 or 1";
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(p->grav[d])) return "params: gravity must be finite";
+  return "";
+}
+
+std::string validate_dx(const double dx[3]) {
+  if (!dx) return "dx: null";
+  for (int d = 0; d < 3; ++d)
+    if (!(dx[d] > 0.0) || !std::isfinite(dx[d])) return "dx: spacings must be positive and finite";
+  return "";
+}
+}  // namespace
+
+extern "C" {
+
+int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
+  if (!layout || !out) return PPM_EINVAL;
+  *out = nullptr;
+  std::string msg = validate_layout(*layout);
+  if (!msg.empty()) {
+    std::fprintf(stderr, "ppm_ctx_create: %s\n", msg.c_str());
+    return PPM_EINVAL;
+  }
+  auto ctx = std::make_unique<ppm_ctx>();
+  ctx->boxes.assign(layout->boxes, layout->boxes + layout->nbox);
+  ctx->layout = *layout;
+  ctx->layout.boxes = ctx->boxes.data();
+  const int nb = layout->nbox;
+  ctx->plan = plan_cache().get(ctx->layout, ctx->plan_hit);
+
+  std::vector<DevBox> db(nb);
+  ctx->off.assign(nb + 1, 0);
+  for (int d = 0; d < 3; ++d) ctx->foff[d].assign(nb + 1, 0);
+  long long ps = 0, pe = 0;
+  ctx->tS_begin.push_back(0);
+  ctx->tE_begin.push_back(0);
+  for (int b = 0; b < nb; ++b) {
+    int n[3];
+    for (int d = 0; d < 3; ++d) n[d] = layout->boxes[b].hi[d] - layout->boxes[b].lo[d] + 1;
+    const long long NS = (long long)(n[0] + 2 * NG) * (n[1] + 2 * NG) * (n[2] + 2 * NG);
+    const long long NE = (long long)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
+    for (int d = 0; d < 3; ++d) db[b].n[d] = n[d];
+    db[b].pad = 0;
+    db[b].soff = ctx->off[b];
+    db[b].poff = ps;
+    db[b].eoff = pe;
+    ctx->off[b + 1] = ctx->off[b] + 5 * NS;
+    for (int d = 0; d < 3; ++d) {
+      long long fe = 5;
+      for (int e = 0; e < 3; ++e) fe *= n[e] + (e == d ? 1 : 0);
+      db[b].foff[d] = ctx->foff[d][b];
+      ctx->foff[d][b + 1] = ctx->foff[d][b] + fe;
+    }
+    for (long long s = 0; s < NS; s += TILE) ctx->tilesS.push_back(Tile{b, (int)s});
+    for (long long s = 0; s < NE; s += TILE) ctx->tilesE.push_back(Tile{b, (int)s});
+    ctx->tS_begin.push_back((int)ctx->tilesS.size());
+    ctx->tE_begin.push_back((int)ctx->tilesE.size());
+    ps += NS;
+    pe += NE;
+  }
+  ctx->LS = round_up(ps, 64);
+  ctx->LE = round_up(pe, 64);
+
+  hipError_t e;
+  if ((e = upload(&ctx->d_boxes, db)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess ||
+      (e = upload(&ctx->d_desc, ctx->plan->desc)) != hipSuccess ||
+      (e = upload(&ctx->d_start, ctx->plan->start)) != hipSuccess ||
+      (e = hipMalloc((void**)&ctx->d_consts, sizeof(StepConsts))) != hipSuccess ||
+      (e = hipMalloc((void**)&ctx->d_flags, 256)) != hipSuccess ||
+      (e = hipMemset(ctx->d_flags, 0, 256)) != hipSuccess ||
+      (e = hipMemset(ctx->d_consts, 0, sizeof(StepConsts))) != hipSuccess) {
+    std::fprintf(stderr, "ppm_ctx_create: %s\n", hipGetErrorString(e));
+    ppm_ctx_destroy(ctx.release());
+    return PPM_EHIP;
+  }
+  *out = ctx.release();
+  return PPM_OK;
+}
+
+int ppm_ctx_destroy(ppm_ctx* ctx) {
+  if (!ctx) return PPM_OK;
+  for (auto& r : ctx->recs) ctx->pool.push_back(r.ev);
+  for (auto& ev : ctx->pool)
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  (void)hipFree(ctx->d_boxes);
+  (void)hipFree(ctx->d_tilesS);
+  (void)hipFree(ctx->d_tilesE);
+  (void)hipFree(ctx->d_desc);
+  (void)hipFree(ctx->d_start);
+  (void)hipFree(ctx->d_consts);
+  (void)hipFree(ctx->d_flags);
+  delete ctx;
+  return PPM_OK;
+}
+
+const char* ppm_last_error(const ppm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ppm_layout_offsets(const ppm_ctx* ctx, int64_t* off) {
+  if (!ctx || !off) return PPM_EINVAL;
+  std::copy(ctx->off.begin(), ctx->off.end(), off);
+  return PPM_OK;
+}
+
+int ppm_flux_offsets(const ppm_ctx* ctx, int32_t d, int64_t* off) {
+  if (!ctx || !off || d < 0 || d > 2) return PPM_EINVAL;
+  std::copy(ctx->foff[d].begin(), ctx->foff[d].end(), off);
+  return PPM_OK;
+}
+
+size_t ppm_workspace_bytes(const ppm_ctx* ctx, int32_t precision) {
+  if (!ctx) return 0;
+  const size_t s = precision == 1 ? sizeof(float) : sizeof(double);
+  return s * (size_t)(P_PLANES * ctx->LS + E_PLANES * ctx->LE);
+}
+
+int ppm_set_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return PPM_EINVAL;
+  if (((uintptr_t)dev_ptr) % 256 != 0) return ctx->fail(PPM_EINVAL, "workspace must be 256-byte aligned");
+  ctx->work = dev_ptr;
+  ctx->work_bytes = dev_ptr ? bytes : 0;
+  return PPM_OK;
+}
+
+int ppm_fill_boundary(ppm_ctx* ctx, double* U, int32_t mode, void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  if (!U) return ctx->fail(PPM_EINVAL, "fill: null state");
+  if (mode != PPM_LAUNCH_BATCHED && mode != PPM_LAUNCH_PER_BOX) return ctx->fail(PPM_EINVAL, "fill: bad mode");
+  hipStream_t s = (hipStream_t)stream;
+  const DevLevel L = ctx->level();
+  const Plan& P = *ctx->plan;
+  if (mode == PPM_LAUNCH_BATCHED) {
+    ppm_ctx::ProfRec* r = ctx->prof ? ctx->begin_rec(PROF_FILL, 2) : nullptr;
+    if (r) (void)hipEventRecord(r->ev[0], s);
+    const int rc = ctx->hip(launch_fill(L, U, 0, (int)P.desc.size(), 0, P.start.back(), s), "fill");
+    if (r) (void)hipEventRecord(r->ev[1], s);
+    return rc;
+  }
+  for (int b = 0; b < ctx->layout.nbox; ++b) {
+    const int d0 = P.box_desc[b], d1 = P.box_desc[b + 1];
+    const int rc = ctx->hip(launch_fill(L, U, d0, d1, P.start[d0], P.start[d1], s), "fill");
+    if (rc) return rc;
+  }
+  return PPM_OK;
+}
+
+int ppm_compute_dt(ppm_ctx* ctx, const double* U, const double dx[3], const ppm_params* params,
+                   double* dt_dev, void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  std::string m = validate_params(params);
+  if (m.empty()) m = validate_dx(dx);
+  if (m.empty() && !(params->cfl > 0.0 && params->cfl < 1.0)) m = "params: cfl must be in (0, 1)";
+  if (m.empty() && (!U || !dt_dev)) m = "compute_dt: null pointer";
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  ppm_ctx::ProfRec* r = ctx->prof ? ctx->begin_rec(PROF_DT, 2) : nullptr;
+  if (r) (void)hipEventRecord(r->ev[0], (hipStream_t)stream);
+  const int rc = ctx->hip(launch_compute_dt(ctx->level(), 0, (int)ctx->tilesE.size(), U, dx, params->gamma,
+                                            params->small_pres, params->cfl, dt_dev, (hipStream_t)stream),
+                          "compute_dt");
+  if (r) (void)hipEventRecord(r->ev[1], (hipStream_t)stream);
+  return rc;
+}
+
+int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                   const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                   void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  std::string m = validate_params(params);
+  if (m.empty()) m = validate_dx(dx);
+  if (m.empty() && (!U || !Unew)) m = "step: null state";
+  if (m.empty() && !dt_dev && !(dt > 0.0 && std::isfinite(dt))) m = "step: dt must be positive and finite";
+  if (m.empty() && mode != PPM_LAUNCH_BATCHED && mode != PPM_LAUNCH_PER_BOX) m = "step: bad mode";
+  const size_t alen = (size_t)ctx->off.back() * sizeof(double);
+  if (m.empty()) {
+    const char* a = (const char*)U;
+    const char* b = (const char*)Unew;
+    if (a < b + alen && b < a + alen) m = "step: U and Unew overlap (the step is out of place)";
+  }
+  if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, params->precision)))
+    m = "step: workspace missing or too small (ppm_set_workspace)";
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  hipStream_t s = (hipStream_t)stream;
+  const DevLevel L = ctx->level();
+  int rc = ctx->hip(launch_step_consts(L, dt, dt_dev, dx, params->grav, s), "step consts");
+  if (rc) return rc;
+  const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
+  auto run = [&](int tS0, int tS1, int tE0, int tE1, hipEvent_t* ev) {
+    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, U, Unew, flux, ctx->work,
+                                params->gamma, params->small_dens, params->small_pres, params->limiter,
+                                params->flattening, params->riemann_iters, grav, params->grav, s, ev),
+                    "step");
+  };
+  if (mode == PPM_LAUNCH_BATCHED) {
+    ppm_ctx::ProfRec* r = ctx->prof ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
+    return run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), r ? r->ev.data() : nullptr);
+  }
+  for (int b = 0; b < ctx->layout.nbox; ++b) {
+    rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], nullptr);
+    if (rc) return rc;
+  }
+  return PPM_OK;
+}
+
+int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], const ppm_params* params,
+                     int32_t nsteps, void* stream, ppm_graph** out) {
+  if (!ctx || !out) return PPM_EINVAL;
+  *out = nullptr;
+  std::string m = validate_params(params);
+  if (m.empty()) m = validate_dx(dx);
+  if (m.empty() && (nsteps < 1 || !Ua || !Ub)) m = "graph: need nsteps >= 1 and two state buffers";
+  if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, params->precision)))
+    m = "graph: workspace missing or too small (ppm_set_workspace)";
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  hipStream_t s = (hipStream_t)stream;
+  double* dtv = nullptr;
+  hipError_t e = hipMalloc((void**)&dtv, 2 * sizeof(double));
+  if (e != hipSuccess) return ctx->hip(e, "graph alloc");
+  auto g = std::make_unique<ppm_graph>();
+  g->ctx = ctx;
+  e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { (void)hipFree(dtv); return ctx->hip(e, "graph capture"); }
+  int rc = PPM_OK;
+  for (int k = 0; k < nsteps && rc == PPM_OK; ++k) {
+    double* src = (k % 2 == 0) ? Ua : Ub;
+    double* dst = (k % 2 == 0) ? Ub : Ua;
+    rc = ppm_fill_boundary(ctx, src, PPM_LAUNCH_BATCHED, stream);
+    if (!rc) rc = ppm_compute_dt(ctx, src, dx, params, dtv, stream);
+    if (!rc) rc = ppm_hydro_step(ctx, src, dst, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, stream);
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (rc || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipFree(dtv);
+    return rc ? rc : ctx->hip(e, "graph end capture");
+  }
+  e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    (void)hipFree(dtv);
+    return ctx->hip(e, "graph instantiate");
+  }
+  g->graph = graph;
+  g->dtv = dtv;
+  *out = g.release();
+  return PPM_OK;
+}
+
+int ppm_graph_launch(ppm_graph* g, void* stream) {
+  if (!g || !g->exec) return PPM_EINVAL;
+  return g->ctx->hip(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+}
+
+int ppm_graph_destroy(ppm_graph* g) {
+  if (!g) return PPM_OK;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  (void)hipFree(g->dtv);
+  delete g;
+  return PPM_OK;
+}
+
+int ppm_profile_enable(ppm_ctx* ctx, int32_t on) {
+  if (!ctx) return PPM_EINVAL;
+  ctx->prof = on != 0;
+  return PPM_OK;
+}
+
+int ppm_profile_read(ppm_ctx* ctx, double* ms, int64_t* count) {
+  if (!ctx || !ms || !count) return PPM_EINVAL;
+  for (int k = 0; k < PROF_NTAGS; ++k) { ms[k] = 0.0; count[k] = 0; }
+  for (auto& r : ctx->recs) {
+    hipError_t e = hipEventSynchronize(r.ev[r.n - 1]);
+    if (e != hipSuccess) return ctx->hip(e, "profile_read");
+    for (int i = 0; i + 1 < r.n; ++i) {
+      float t = 0.f;
+      e = hipEventElapsedTime(&t, r.ev[i], r.ev[i + 1]);
+      if (e != hipSuccess) return ctx->hip(e, "profile_read");
+      ms[r.tag0 + i] += t;
+      count[r.tag0 + i] += 1;
+    }
+  }
+  for (auto& r : ctx->recs) ctx->pool.push_back(r.ev);
+  ctx->recs.clear();
+  return PPM_OK;
+}
+
+int ppm_check_status(ppm_ctx* ctx, void* stream, int32_t* flags) {
+  if (!ctx || !flags) return PPM_EINVAL;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipMemcpy(flags, ctx->d_flags, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, sizeof(int32_t));
+  if (e != hipSuccess) return ctx->hip(e, "check_status");
+  return *flags ? PPM_ENONPHYS : PPM_OK;
+}
+
+static void desc_to20(const FillDesc& D, int32_t* o) {
+  o[0] = D.dst; o[1] = D.src;
+  for (int d = 0; d < 3; ++d) {
+    o[2 + d] = D.lo[d]; o[5 + d] = D.hi[d]; o[8 + d] = D.a[d]; o[11 + d] = D.c[d];
+  }
+  o[14] = D.sign; o[15] = D.count;
+  o[16] = o[17] = o[18] = o[19] = 0;
+}
+
+int ppm_plan_build(const ppm_layout* layout, int32_t brute, int32_t max, int32_t* out20, int32_t* count) {
+  if (!layout || !count) return PPM_EINVAL;
+  const std::string m = validate_layout(*layout);
+  if (!m.empty()) {
+    std::fprintf(stderr, "ppm_plan_build: %s\n", m.c_str());
+    return PPM_EINVAL;
+  }
+  std::shared_ptr<const Plan> P;
+  if (brute) {
+    P = std::make_shared<const Plan>(build_plan(*layout, true));
+  } else {
+    bool hit = false;
+    P = plan_cache().get(*layout, hit);
+  }
+  *count = (int32_t)P->desc.size();
+  for (int32_t k = 0; k < *count && k < max && out20; ++k) desc_to20(P->desc[k], out20 + 20 * k);
+  return PPM_OK;
+}
+
+int ppm_fill_boundary_host(const ppm_layout* layout, double* U) {
+  if (!layout || !U) return PPM_EINVAL;
+  const std::string m = validate_layout(*layout);
+  if (!m.empty()) {
+    std::fprintf(stderr, "ppm_fill_boundary_host: %s\n", m.c_str());
+    return PPM_EINVAL;
+  }
+  bool hit = false;
+  std::shared_ptr<const Plan> P = plan_cache().get(*layout, hit);
+  const ppm_box* B = layout->boxes;
+  std::vector<long long> off(layout->nbox + 1, 0);
+  for (int b = 0; b < layout->nbox; ++b) {
+    long long ns = 5;
+    for (int d = 0; d < 3; ++d) ns *= B[b].hi[d] - B[b].lo[d] + 1 + 2 * NG;
+    off[b + 1] = off[b] + ns;
+  }
+  for (const FillDesc& D : P->desc) {
+    int dn[3], sn[3];
+    for (int d = 0; d < 3; ++d) {
+      dn[d] = B[D.dst].hi[d] - B[D.dst].lo[d] + 1 + 2 * NG;
+      sn[d] = B[D.src].hi[d] - B[D.src].lo[d] + 1 + 2 * NG;
+    }
+    const long long dNS = (long long)dn[0] * dn[1] * dn[2], sNS = (long long)sn[0] * sn[1] * sn[2];
+    for (int z = D.lo[2]; z <= D.hi[2]; ++z)
+      for (int y = D.lo[1]; y <= D.hi[1]; ++y)
+        for (int x = D.lo[0]; x <= D.hi[0]; ++x) {
+          const int sx = D.a[0] * x + D.c[0], sy = D.a[1] * y + D.c[1], sz = D.a[2] * z + D.c[2];
+          const long long di = off[D.dst] + ((long long)(z + NG) * dn[1] + (y + NG)) * dn[0] + (x + NG);
+          const long long si = off[D.src] + ((long long)(sz + NG) * sn[1] + (sy + NG)) * sn[0] + (sx + NG);
+          for (int c = 0; c < 5; ++c) {
+            const double v = U[si + c * sNS];
+            const bool neg = c >= 1 && c <= 3 && ((D.sign >> (c - 1)) & 1);
+            U[di + c * dNS] = neg ? -v : v;
+          }
+        }
+  }
+  return PPM_OK;
+}
+
+int ppm_plan_cache_stats(int64_t* lookups, int64_t* hits, int32_t* entries) {
+  PlanCache& c = plan_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  if (lookups) *lookups = c.lookups;
+  if (hits) *hits = c.hits;
+  if (entries) *entries = (int32_t)c.lru.size();
+  return PPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Internal definitions shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "ppm.h"
+
+namespace ppm {
+
+constexpr int NG = 4;        // ghost zones per side
+constexpr int TILE = 256;    // zones per tile == threads per workgroup
+constexpr int NXCD = 8;      // MI355X: 8 accelerator complex dies, 32 CUs each
+
+// Per-box metadata on the device.
+struct DevBox {
+  int n[3];           // valid extents
+  int pad;
+  long long soff;     // element offset of the box in the state arena
+  long long poff;     // offset in each plane of the primitive arena (stored grid, (n+8)^3)
+  long long eoff;     // offset in each plane of the traced-grid arenas ((n+2)^3)
+  long long foff[3];  // element offsets in the three flux arenas
+};
+
+// A tile: TILE consecutive linear zones of one box's grid.
+struct Tile {
+  int box;
+  int start;
+};
+
+// One copy of the ghost-fill plan: the dst-box-local region [lo, hi] takes
+// its values from src-box-local zone a*x + c (per axis, a in {1, -1, 0}),
+// negating the momentum components flagged in sign.
+struct FillDesc {
+  int dst, src;
+  int lo[3], hi[3];
+  int a[3], c[3];
+  int sign;
+  int count;
+};
+
+// Per-step constants formed on the device from dt (so that a graph can take
+// dt from device memory).  The reconstruction copies exist in FP64 and FP32.
+struct StepConsts {
+  double dt, hdt;
+  double dtdx[3];
+  double d_dtdx[3], d_dt2h[3], d_dt3h[3], d_hdtg[3];
+  float f_dtdx[3], f_dt2h[3], f_dt3h[3], f_hdtg[3];
+};
+
+// Gas and scheme constants in the reconstruction scalar, formed on the host
+// in FP64 from gamma and the floors, rounded once to S.
+template <class S> struct Gas {
+  S gamma, gm1, gm1inv, beta, small_dens, small_pres;
+  int limiter, flattening, iters, grav;
+};
+
+// Number of planes in the traced-grid (E) arena: flattening 1, traces 30,
+// stage-1 fluxes 15, stage-2 fluxes 30, final fluxes 15.
+constexpr int E_FLAT = 0;
+constexpr int E_TRACE = 1;          // + (d*2 + side)*5 + m, side 0 = high face, 1 = low face
+constexpr int E_F1 = E_TRACE + 30;  // + d*5 + m
+constexpr int E_F2 = E_F1 + 15;     // + pair*5 + m, pair = 2*d + (t > d ? t-1 : t)
+constexpr int E_F3 = E_F2 + 30;     // + d*5 + m
+constexpr int E_PLANES = E_F3 + 15;
+constexpr int P_PLANES = 6;         // rho, u, v, w, p, c
+
+// Launch-side views of the context's device data.
+struct DevLevel {
+  const DevBox* boxes;
+  const Tile* tilesS;  // tiles over the stored grids
+  const Tile* tilesE;  // tiles over the traced grids
+  const FillDesc* desc;
+  const long long* desc_start;  // exclusive prefix of zone counts, ndesc+1
+  StepConsts* consts;
+  int* flags;
+  long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
+};
+
+}  // namespace ppm
+
+// Kernel launchers (ppm_kernels.hip).  Each returns the hipError_t of the launch.
+namespace ppm {
+hipError_t launch_step_consts(const DevLevel& L, double dt, const double* dt_dev, const double h[3],
+                              const double g[3], hipStream_t s);
+hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_end, long long zone_begin,
+                       long long zone_end, hipStream_t s);
+hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, const double* U,
+                             const double h[3], double gamma, double small_pres, double cfl,
+                             double* dt_dev, hipStream_t s);
+// The step stages over E-tiles [tE0, tE1) and S-tiles [tS0, tS1).
+hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1,
+                       const double* U, double* Unew, double* const* flux, void* work,
+                       const double gamma, const double small_dens, const double small_pres,
+                       int limiter, int flattening, int iters, int grav, const double g[3],
+                       hipStream_t s, hipEvent_t* ev);
+// Events recorded by launch_step when ev is non-null: before each of the 7
+// stage kernels and after the last (STEP_EVENTS in all).
+constexpr int STEP_EVENTS = 8;
+constexpr int PROF_FILL = PPM_PROF_FILL, PROF_DT = PPM_PROF_DT, PROF_PRIM = PPM_PROF_PRIM,
+              PROF_NTAGS = PPM_PROF_NTAGS;
+}  // namespace ppm

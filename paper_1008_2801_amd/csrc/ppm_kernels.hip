@@ -1,0 +1,940 @@
+// gfx950 kernels of the unsplit PPM step.
+//
+// The step runs as a chain of stages, each one launch over a flat tile list
+// (all boxes of the level, or one box for the per-box form):
+//   prim     conserved -> primitive on every stored zone            (O2)
+//   flatten  shock-flattening coefficient on the traced zones        (O3)
+//   trace    PPM parabolas + characteristic tracing, one axis/thread (O4, O5)
+//   riemann1 normal-predictor fluxes F^d                             (O7)
+//   riemann2 single-transverse corrected states, fluxes F^{d|t}      (O8)
+//   riemann3 double-transverse corrected states, fluxes F^{d,n+1/2}  (O9)
+//   update   conservative update in FP64 (+ Heun gravity source)     (O10)
+// Intermediates live in structure-of-arrays planes in HBM (one plane per
+// quantity, every box's grid contiguous inside a plane), so each lane of a
+// wavefront touches consecutive addresses on every load and store.
+//
+// Every formula is evaluated in the same order as the definition of the
+// method (no contraction: built with -ffp-contract=off; IEEE division and
+// square root), so that the FP64 results agree with a serial evaluation of
+// the same definition to the last bit.
+#include <hip/hip_runtime.h>
+
+#include "ppm_internal.h"
+
+namespace ppm {
+namespace {
+
+// ------------------------------------------------------------ helpers ------
+template <class S> __device__ __forceinline__ S smax(S a, S b) { return (a < b) ? b : a; }
+template <class S> __device__ __forceinline__ S smin(S a, S b) { return (b < a) ? b : a; }
+template <class S> __device__ __forceinline__ S sabs(S a) { return (a < S(0)) ? -a : a; }
+__device__ __forceinline__ double ssqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float ssqrt(float x) { return __builtin_sqrtf(x); }
+template <class S> __device__ __forceinline__ S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
+
+#define HALF S(0.5)
+#define ONE S(1.0)
+#define TWO S(2.0)
+#define THREE S(3.0)
+#define SIX S(6.0)
+#define SIXTH S(1.0 / 6.0)
+#define TWO3 S(2.0 / 3.0)
+#define C033 S(0.33)
+#define TEN S(10.0)
+#define C075 S(0.75)
+
+template <class S> struct SC;
+template <> struct SC<double> {
+  __device__ static const double* dtdx(const StepConsts* c) { return c->d_dtdx; }
+  __device__ static const double* dt2h(const StepConsts* c) { return c->d_dt2h; }
+  __device__ static const double* dt3h(const StepConsts* c) { return c->d_dt3h; }
+  __device__ static const double* hdtg(const StepConsts* c) { return c->d_hdtg; }
+};
+template <> struct SC<float> {
+  __device__ static const float* dtdx(const StepConsts* c) { return c->f_dtdx; }
+  __device__ static const float* dt2h(const StepConsts* c) { return c->f_dt2h; }
+  __device__ static const float* dt3h(const StepConsts* c) { return c->f_dt3h; }
+  __device__ static const float* hdtg(const StepConsts* c) { return c->f_hdtg; }
+};
+
+// Tile index of this workgroup.  Consecutive workgroups are dealt round-robin
+// to the 8 XCDs; remapping gives each XCD a contiguous run of tiles so that
+// the stencil neighbours of a tile sit in the same XCD's L2.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = (ntiles + NXCD - 1) / NXCD;
+  const int b = blockIdx.x;
+  const int t = (b % NXCD) * per + b / NXCD;
+  return (t < ntiles) ? t : -1;
+}
+__host__ inline int xcd_grid(int ntiles) { return ((ntiles + NXCD - 1) / NXCD) * NXCD; }
+
+__device__ __forceinline__ void raise_flags(int* flags, int fl) {
+  if (fl) atomicOr(flags, fl);
+}
+
+// ------------------------------------------------------- O6: Riemann -------
+// Fan sampling on the left side of the contact for (rho, u, p) with the
+// normal velocity oriented so that the side is the left one.  The right
+// side is the mirror image: the caller negates u, u* on entry and u on exit
+// (exact in IEEE arithmetic).
+template <class S>
+__device__ __forceinline__ void sample_side(S ro, S uo, S po, S C, S W, S iW, S us, S p, const Gas<S>& G,
+                                            S& r_, S& u_, S& p_, int& fl) {
+  const S irho = ONE / ro;
+  const S vstar = irho - (p - po) * (iW * iW);
+  S rs = ONE / vstar;
+  if (!(vstar > S(0)) || rs < G.small_dens) { fl |= PPM_FLAG_FLOOR; rs = G.small_dens; }
+  const S cst = ssqrt(G.gamma * p / rs);
+  const S co = C * irho;
+  r_ = ro; u_ = uo; p_ = po;
+  if (p > po) {
+    const S sh = uo - W * irho;
+    if (!(sh >= S(0))) { r_ = rs; u_ = us; p_ = p; }
+  } else {
+    const S hd = uo - co, tl = us - cst;
+    if (hd >= S(0)) {
+    } else if (tl <= S(0)) {
+      r_ = rs; u_ = us; p_ = p;
+    } else {
+      const S w = -hd / (tl - hd);
+      r_ = (ONE - w) * ro + w * rs;
+      u_ = (ONE - w) * uo + w * us;
+      p_ = (ONE - w) * po + w * p;
+    }
+  }
+}
+
+// Two-shock Riemann solver: flux F (xyz component order) at a face normal
+// to d from primitive states L and R (rho, u, v, w, p).
+template <int d, class S>
+__device__ __forceinline__ void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl) {
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  const S rl = L[0], ul = L[1 + d], pl = L[4];
+  const S rr = R[0], ur = R[1 + d], pr = R[4];
+  const S cl = ssqrt(G.gamma * pl * rl);
+  const S cr = ssqrt(G.gamma * pr * rr);
+  S p = ((cr * pl + cl * pr) + (cl * cr) * (ul - ur)) / (cl + cr);
+  if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
+  p = smax(p, G.small_pres);
+  const S ipl = ONE / pl, ipr = ONE / pr;
+  for (int it = 0; it < G.iters; ++it) {
+    const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
+    const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
+    const S iwl = ONE / wl, iwr = ONE / wr;
+    const S xl = cl * iwl, xr = cr * iwr;
+    const S izl = HALF * iwl * (ONE + xl * xl);
+    const S izr = HALF * iwr * (ONE + xr * xr);
+    const S usl = ul - (p - pl) * iwl;
+    const S usr = ur + (p - pr) * iwr;
+    p = p - (usr - usl) / (izl + izr);
+    if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
+    p = smax(p, G.small_pres);
+  }
+  const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
+  const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
+  const S iwl = ONE / wl, iwr = ONE / wr;
+  const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
+
+  S g0, g1, g2, g3, g4;
+  if (us != S(0)) {
+    const bool left = us > S(0);
+    const S ro = left ? rl : rr;
+    const S uo = left ? ul : -ur;
+    const S po = left ? pl : pr;
+    const S C = left ? cl : cr;
+    const S W = left ? wl : wr;
+    const S iW = left ? iwl : iwr;
+    const S uss = left ? us : -us;
+    S r_, u_, p_;
+    sample_side(ro, uo, po, C, W, iW, uss, p, G, r_, u_, p_, fl);
+    g0 = r_;
+    g1 = left ? u_ : -u_;
+    g2 = p_;
+    g3 = left ? L[1 + t1] : R[1 + t1];
+    g4 = left ? L[1 + t2] : R[1 + t2];
+  } else {  // u* == 0: both sides averaged
+    S ra, ua, pa, rb, ub, pb;
+    sample_side(rl, ul, pl, cl, wl, iwl, us, p, G, ra, ua, pa, fl);
+    sample_side(rr, -ur, pr, cr, wr, iwr, -us, p, G, rb, ub, pb, fl);
+    ub = -ub;
+    g0 = HALF * (ra + rb);
+    g1 = HALF * (ua + ub);
+    g2 = HALF * (pa + pb);
+    g3 = HALF * (L[1 + t1] + R[1 + t1]);
+    g4 = HALF * (L[1 + t2] + R[1 + t2]);
+  }
+  const S m = g0 * g1;
+  const S e = g2 * G.gm1inv + HALF * g0 * ((g1 * g1 + g3 * g3) + g4 * g4);
+  F[0] = m;
+  F[1 + d] = m * g1 + g2;
+  F[1 + t1] = m * g3;
+  F[1 + t2] = m * g4;
+  F[4] = g1 * (e + g2);
+}
+
+// ------------------------------------------------------------ O4: PPM ------
+template <class S>
+__device__ __forceinline__ S ppm_slope(S am, S a0, S ap, int limiter) {
+  const S dc = HALF * (ap - am);
+  if (!limiter) return dc;
+  const S dl = a0 - am, dr = ap - a0;
+  if (dl * dr > S(0)) return scopysign(smin(smin(sabs(dc), TWO * sabs(dl)), TWO * sabs(dr)), dc);
+  return S(0);
+}
+
+template <class S>
+__device__ __forceinline__ void ppm_parabola(S am2, S am1, S a0, S ap1, S ap2, S phi, const Gas<S>& G,
+                                             S& aL, S& aR, S& a6) {
+  const S sm = ppm_slope(am2, am1, a0, G.limiter);
+  const S s0 = ppm_slope(am1, a0, ap1, G.limiter);
+  const S sp = ppm_slope(a0, ap1, ap2, G.limiter);
+  aL = HALF * (am1 + a0) - (s0 - sm) * SIXTH;
+  aR = HALF * (a0 + ap1) - (sp - s0) * SIXTH;
+  if (G.limiter) {
+    if (G.flattening) {
+      const S omp = ONE - phi;
+      aL = phi * aL + omp * a0;
+      aR = phi * aR + omp * a0;
+    }
+    if ((aR - a0) * (a0 - aL) <= S(0)) {
+      aL = a0;
+      aR = a0;
+    } else {
+      const S dq = aR - aL;
+      const S t = dq * (a0 - HALF * (aL + aR));
+      const S d2 = dq * dq * SIXTH;
+      if (t > d2) {
+        aL = THREE * a0 - TWO * aR;
+      } else if (-d2 > t) {
+        aR = THREE * a0 - TWO * aL;
+      }
+    }
+  }
+  a6 = SIX * a0 - THREE * (aL + aR);
+}
+
+template <class S> __device__ __forceinline__ S ppm_ip(S aR, S da, S a6, S sg) {
+  return aR - HALF * sg * (da - (ONE - TWO3 * sg) * a6);
+}
+template <class S> __device__ __forceinline__ S ppm_im(S aL, S da, S a6, S sg) {
+  return aL + HALF * sg * (da + (ONE - TWO3 * sg) * a6);
+}
+
+// ---------------------------------------------------------- O5: tracing ----
+template <class S>
+__device__ __forceinline__ void trace_edge(const S ref[5], S a1, S a2, S a3, S at1, S at2, S cor, S c2,
+                                           int mn, int m1, int m2, const Gas<S>& G, const S* hdtg,
+                                           S q[5], int& fl) {
+  q[0] = ref[0] - ((a1 + a3) + a2);
+  q[mn] = ref[mn] + cor * (a1 - a3);
+  q[4] = ref[4] - c2 * (a1 + a3);
+  q[m1] = ref[m1] - at1;
+  q[m2] = ref[m2] - at2;
+  if (G.grav) {
+    q[1] = q[1] + hdtg[0];
+    q[2] = q[2] + hdtg[1];
+    q[3] = q[3] + hdtg[2];
+  }
+  if (q[0] < G.small_dens) fl |= PPM_FLAG_FLOOR;
+  if (q[4] < G.small_pres) fl |= PPM_FLAG_FLOOR;
+  q[0] = smax(q[0], G.small_dens);
+  q[4] = smax(q[4], G.small_pres);
+}
+
+template <int d, class S>
+__device__ __forceinline__ void trace_zone(const S aL[5], const S aR[5], const S a6[5], S r, S un, S c,
+                                           S dtdx, const Gas<S>& G, const S* hdtg, S qp[5],
+                                           S qm[5], int& fl) {
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  constexpr int mn = 1 + d, m1 = 1 + t1, m2 = 1 + t2;
+  S da[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) da[m] = aR[m] - aL[m];
+  const S rc = r * c, c2 = c * c, ic2 = ONE / c2, hic2 = HALF * ic2, cor = c / r;
+  const S l1 = un - c, l2 = un, l3 = un + c;
+  const S zero = S(0);
+  {
+    const S s1 = smax(l1, zero) * dtdx, s2 = smax(l2, zero) * dtdx, s3 = smax(l3, zero) * dtdx;
+    S ref[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) ref[m] = ppm_ip(aR[m], da[m], a6[m], s3);
+    S a1 = zero, a2 = zero, a3 = zero, at1 = zero, at2 = zero;
+    if (l1 > zero) {
+      const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], s1);
+      const S du = ref[mn] - ppm_ip(aR[mn], da[mn], a6[mn], s1);
+      a1 = (dp - rc * du) * hic2;
+    }
+    if (l2 > zero) {
+      const S dr = ref[0] - ppm_ip(aR[0], da[0], a6[0], s2);
+      const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], s2);
+      a2 = dr - dp * ic2;
+      at1 = ref[m1] - ppm_ip(aR[m1], da[m1], a6[m1], s2);
+      at2 = ref[m2] - ppm_ip(aR[m2], da[m2], a6[m2], s2);
+    }
+    if (l3 > zero) {
+      const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], s3);
+      const S du = ref[mn] - ppm_ip(aR[mn], da[mn], a6[mn], s3);
+      a3 = (dp + rc * du) * hic2;
+    }
+    trace_edge(ref, a1, a2, a3, at1, at2, cor, c2, mn, m1, m2, G, hdtg, qp, fl);
+  }
+  {
+    const S s1 = smax(-l1, zero) * dtdx, s2 = smax(-l2, zero) * dtdx, s3 = smax(-l3, zero) * dtdx;
+    S ref[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) ref[m] = ppm_im(aL[m], da[m], a6[m], s1);
+    S a1 = zero, a2 = zero, a3 = zero, at1 = zero, at2 = zero;
+    if (l1 < zero) {
+      const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], s1);
+      const S du = ref[mn] - ppm_im(aL[mn], da[mn], a6[mn], s1);
+      a1 = (dp - rc * du) * hic2;
+    }
+    if (l2 < zero) {
+      const S dr = ref[0] - ppm_im(aL[0], da[0], a6[0], s2);
+      const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], s2);
+      a2 = dr - dp * ic2;
+      at1 = ref[m1] - ppm_im(aL[m1], da[m1], a6[m1], s2);
+      at2 = ref[m2] - ppm_im(aL[m2], da[m2], a6[m2], s2);
+    }
+    if (l3 < zero) {
+      const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], s3);
+      const S du = ref[mn] - ppm_im(aL[mn], da[mn], a6[mn], s3);
+      a3 = (dp + rc * du) * hic2;
+    }
+    trace_edge(ref, a1, a2, a3, at1, at2, cor, c2, mn, m1, m2, G, hdtg, qm, fl);
+  }
+}
+
+// ------------------------------------------------ conversions (O2, O8) -----
+template <class S>
+__device__ __forceinline__ void prim_to_cons(const S q[5], const Gas<S>& G, S U[5]) {
+  U[0] = q[0];
+  U[1] = q[0] * q[1];
+  U[2] = q[0] * q[2];
+  U[3] = q[0] * q[3];
+  U[4] = q[4] * G.gm1inv + HALF * q[0] * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
+}
+
+template <class S>
+__device__ __forceinline__ void cons_to_prim_floor(const S U[5], const Gas<S>& G, S q[5], int& fl) {
+  if (U[0] < G.small_dens) fl |= PPM_FLAG_FLOOR;
+  const S r = smax(U[0], G.small_dens);
+  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
+  const S ke = HALF * r * ((u * u + v * v) + w * w);
+  S p = G.gm1 * (U[4] - ke);
+  if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
+  p = smax(p, G.small_pres);
+  q[0] = r; q[1] = u; q[2] = v; q[3] = w; q[4] = p;
+}
+
+// Zone geometry of a tile lane on the traced grid of a box: E = n + 2 per
+// axis, slot s <-> zone s - 1.
+struct EZone {
+  int x[3];     // zone coordinates, -1..n
+  int E[3];
+  long long e;  // linear index in the box's traced grid
+};
+
+__device__ __forceinline__ bool ezone(const Tile& tl, const DevBox& B, EZone& z) {
+  z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
+  const long long tot = (long long)z.E[0] * z.E[1] * z.E[2];
+  const long long idx = (long long)tl.start + threadIdx.x;
+  if (idx >= tot) return false;
+  z.e = idx;
+  const int i = (int)(idx % z.E[0]);
+  const long long r = idx / z.E[0];
+  z.x[0] = i - 1;
+  z.x[1] = (int)(r % z.E[1]) - 1;
+  z.x[2] = (int)(r / z.E[1]) - 1;
+  return true;
+}
+
+// Linear stride along axis d of a grid with extents E.
+__device__ __forceinline__ long long stride(const int E[3], int d) {
+  return d == 0 ? 1 : (d == 1 ? (long long)E[0] : (long long)E[0] * E[1]);
+}
+
+// ------------------------------------------------------------- kernels -----
+__global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, const double* dt_dev,
+                                                    double h0, double h1, double h2, double g0,
+                                                    double g1, double g2) {
+  if (threadIdx.x != 0) return;
+  const double t = dt_dev ? dt_dev[0] : dt;
+  const double h[3] = {h0, h1, h2}, g[3] = {g0, g1, g2};
+  c->dt = t;
+  c->hdt = 0.5 * t;
+  for (int d = 0; d < 3; ++d) {
+    c->dtdx[d] = t / h[d];
+    c->d_dtdx[d] = t / h[d];
+    c->d_dt2h[d] = t / (2.0 * h[d]);
+    c->d_dt3h[d] = t / (3.0 * h[d]);
+    c->d_hdtg[d] = 0.5 * t * g[d];
+    c->f_dtdx[d] = (float)c->d_dtdx[d];
+    c->f_dt2h[d] = (float)c->d_dt2h[d];
+    c->f_dt3h[d] = (float)c->d_dt3h[d];
+    c->f_hdtg[d] = (float)c->d_hdtg[d];
+  }
+}
+
+// O2 on every stored zone: (rho, u, v, w, p, c) planes.
+template <class S>
+__global__ void __launch_bounds__(TILE) k_prim(const Tile* __restrict__ tiles, int ntiles,
+                                               const DevBox* __restrict__ boxes,
+                                               const double* __restrict__ U, S* __restrict__ prim,
+                                               long long LS, Gas<S> G, int* flags) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const DevBox B = boxes[tl.box];
+  const long long NS = (long long)(B.n[0] + 2 * NG) * (B.n[1] + 2 * NG) * (B.n[2] + 2 * NG);
+  const long long idx = (long long)tl.start + threadIdx.x;
+  if (idx >= NS) return;
+  const double* u = U + B.soff + idx;
+  S uc[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) uc[c] = (S)u[c * NS];
+  int fl = 0;
+  const S r = uc[0];
+  const S vx = uc[1] / r, vy = uc[2] / r, vz = uc[3] / r;
+  const S ke = HALF * r * ((vx * vx + vy * vy) + vz * vz);
+  S p = G.gm1 * (uc[4] - ke);
+  bool fin = true;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) fin = fin && __builtin_isfinite(uc[c]);
+  if (!fin || !(r > S(0)) || !(p > S(0))) fl |= PPM_FLAG_NONPHYS;
+  if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
+  p = smax(p, G.small_pres);
+  S* q = prim + B.poff + idx;
+  q[0] = r;
+  q[LS] = vx;
+  q[2 * LS] = vy;
+  q[3 * LS] = vz;
+  q[4 * LS] = p;
+  q[5 * LS] = ssqrt(G.gamma * p / r);
+  raise_flags(flags, fl);
+}
+
+// Primitive-plane index of zone x of box B (stored grid).
+__device__ __forceinline__ long long pidx(const DevBox& B, int x, int y, int z) {
+  return B.poff + ((long long)(z + NG) * (B.n[1] + 2 * NG) + (y + NG)) * (B.n[0] + 2 * NG) + (x + NG);
+}
+
+// O3 on the traced zones.
+template <class S>
+__global__ void __launch_bounds__(TILE) k_flatten(const Tile* __restrict__ tiles, int ntiles,
+                                                  const DevBox* __restrict__ boxes,
+                                                  const S* __restrict__ prim, long long LS,
+                                                  S* __restrict__ work, long long LE, Gas<S> G) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  S phi = ONE;
+  if (G.flattening) {
+    const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+    const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
+    const S* pp = prim + 4 * LS + base;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const long long st = stride(NS, d);
+      const S* uu = prim + (1 + d) * LS + base;
+      S p[7], u[5];
+#pragma unroll
+      for (int o = -3; o <= 3; ++o) p[o + 3] = pp[o * st];
+#pragma unroll
+      for (int o = -2; o <= 2; ++o) u[o + 2] = uu[o * st];
+      // shock-detector coefficient at offset o (p index o+3, u index o+2)
+      auto chit = [&](int o) -> S {
+        const S dp1 = p[o + 4] - p[o + 2];
+        const S dp2 = p[o + 5] - p[o + 1];
+        const S zeta = sabs(dp1) / smax(sabs(dp2), G.small_pres);
+        const S zz = smin(smax(TEN * (zeta - C075), S(0)), ONE);
+        const bool compress = (u[o + 1] - u[o + 3]) > S(0);
+        const bool strong = sabs(dp1) > C033 * smin(p[o + 4], p[o + 2]);
+        return (compress && strong) ? zz : S(0);
+      };
+      const S dp1 = p[4] - p[2];
+      S chi;
+      if (dp1 > S(0)) chi = smax(chit(0), chit(-1));
+      else if (dp1 < S(0)) chi = smax(chit(0), chit(1));
+      else chi = smax(smax(chit(-1), chit(0)), chit(1));
+      phi = (d == 0) ? (ONE - chi) : smin(phi, ONE - chi);
+    }
+  }
+  work[E_FLAT * LE + B.eoff + z.e] = phi;
+}
+
+// O4 + O5 for one axis (blockIdx.y) on the traced zones.
+template <int d, class S>
+__device__ __forceinline__ void trace_body(const Tile* __restrict__ tiles, int ntiles,
+                                           const DevBox* __restrict__ boxes, const S* __restrict__ prim,
+                                           long long LS, S* __restrict__ work, long long LE, const Gas<S>& G,
+                                           const StepConsts* __restrict__ sc, int* flags) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+  const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
+  const long long st = stride(NS, d);
+  const S phi = work[E_FLAT * LE + B.eoff + z.e];
+  S aL[5], aR[5], a6[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* a = prim + m * LS + base;
+    ppm_parabola(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, G, aL[m], aR[m], a6[m]);
+  }
+  const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
+  S qp[5], qm[5];
+  int fl = 0;
+  trace_zone<d>(aL, aR, a6, r, un, c, SC<S>::dtdx(sc)[d], G, SC<S>::hdtg(sc), qp, qm, fl);
+  S* w = work + B.eoff + z.e;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE] = qp[m];
+    w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE] = qm[m];
+  }
+  raise_flags(flags, fl);
+}
+
+template <class S>
+__global__ void __launch_bounds__(TILE) k_trace(const Tile* __restrict__ tiles, int ntiles,
+                                                const DevBox* __restrict__ boxes,
+                                                const S* __restrict__ prim, long long LS,
+                                                S* __restrict__ work, long long LE, Gas<S> G,
+                                                const StepConsts* __restrict__ sc, int* flags) {
+  switch (blockIdx.y) {
+    case 0: trace_body<0>(tiles, ntiles, boxes, prim, LS, work, LE, G, sc, flags); break;
+    case 1: trace_body<1>(tiles, ntiles, boxes, prim, LS, work, LE, G, sc, flags); break;
+    default: trace_body<2>(tiles, ntiles, boxes, prim, LS, work, LE, G, sc, flags); break;
+  }
+}
+
+// O7: F^d at d-face slots x_d in [0, n], transverse in [-1, n].
+template <int d, class S>
+__device__ __forceinline__ void riemann1_body(const Tile* __restrict__ tiles, int ntiles,
+                                              const DevBox* __restrict__ boxes, S* __restrict__ work,
+                                              long long LE, const Gas<S>& G, int* flags) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0) return;
+  const long long st = stride(z.E, d);
+  const S* w = work + B.eoff + z.e;
+  S L[5], R[5], F[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    L[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - st];
+    R[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
+  }
+  int fl = 0;
+  riemann<d>(L, R, G, F, fl);
+  S* f = work + B.eoff + z.e;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) f[(E_F1 + d * 5 + m) * LE] = F[m];
+  raise_flags(flags, fl);
+}
+
+template <class S>
+__global__ void __launch_bounds__(TILE) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
+                                                   const DevBox* __restrict__ boxes,
+                                                   S* __restrict__ work, long long LE, Gas<S> G,
+                                                   int* flags) {
+  switch (blockIdx.y) {
+    case 0: riemann1_body<0>(tiles, ntiles, boxes, work, LE, G, flags); break;
+    case 1: riemann1_body<1>(tiles, ntiles, boxes, work, LE, G, flags); break;
+    default: riemann1_body<2>(tiles, ntiles, boxes, work, LE, G, flags); break;
+  }
+}
+
+__host__ __device__ constexpr int pair_index(int d, int t) { return 2 * d + (t > d ? t - 1 : t); }
+
+// O8: for the pair (d, t) = blockIdx.y: states of axis d corrected by the
+// stage-1 t-flux difference (dt/3h_t), then F^{d|t} at d-face slots x_d in
+// [0, n], x_t in [0, n-1], the remaining axis in [-1, n].
+template <int d, int t, class S>
+__device__ __forceinline__ void riemann2_body(const Tile* __restrict__ tiles, int ntiles,
+                                              const DevBox* __restrict__ boxes, S* __restrict__ work,
+                                              long long LE, const Gas<S>& G,
+                                              const StepConsts* __restrict__ sc, int* flags) {
+  constexpr int pr = pair_index(d, t);
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0 || z.x[t] < 0 || z.x[t] >= B.n[t]) return;
+  const long long sd = stride(z.E, d), stt = stride(z.E, t);
+  const S c3 = SC<S>::dt3h(sc)[t];
+  const S* w = work + B.eoff + z.e;
+  int fl = 0;
+  S L[5], R[5];
+  {  // high-face state of zone x - e_d
+    S qe[5], ue[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qe[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
+    prim_to_cons(qe, G, ue);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const S* f = w + (E_F1 + t * 5 + m) * LE - sd;
+      ue[m] = ue[m] - c3 * (f[stt] - f[0]);
+    }
+    cons_to_prim_floor(ue, G, L, fl);
+  }
+  {  // low-face state of zone x
+    S qe[5], ue[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qe[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
+    prim_to_cons(qe, G, ue);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const S* f = w + (E_F1 + t * 5 + m) * LE;
+      ue[m] = ue[m] - c3 * (f[stt] - f[0]);
+    }
+    cons_to_prim_floor(ue, G, R, fl);
+  }
+  S F[5];
+  riemann<d>(L, R, G, F, fl);
+  S* o = work + B.eoff + z.e;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) o[(E_F2 + pr * 5 + m) * LE] = F[m];
+  raise_flags(flags, fl);
+}
+
+template <class S>
+__global__ void __launch_bounds__(TILE) k_riemann2(const Tile* __restrict__ tiles, int ntiles,
+                                                   const DevBox* __restrict__ boxes,
+                                                   S* __restrict__ work, long long LE, Gas<S> G,
+                                                   const StepConsts* __restrict__ sc, int* flags) {
+  switch (blockIdx.y) {
+    case 0: riemann2_body<0, 1>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 1: riemann2_body<0, 2>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 2: riemann2_body<1, 0>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 3: riemann2_body<1, 2>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 4: riemann2_body<2, 0>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    default: riemann2_body<2, 1>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+  }
+}
+
+// O9: states of axis d corrected by F^{t1|t2} and F^{t2|t1} (dt/2h), then
+// the final fluxes at d-face slots x_d in [0, n], transverse valid.
+template <int d, class S>
+__device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, int ntiles,
+                                              const DevBox* __restrict__ boxes, S* __restrict__ work,
+                                              long long LE, const Gas<S>& G,
+                                              const StepConsts* __restrict__ sc, double* fx, double* fy,
+                                              double* fz, int* flags) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0 || z.x[t1] < 0 || z.x[t1] >= B.n[t1] || z.x[t2] < 0 || z.x[t2] >= B.n[t2]) return;
+  const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
+  const S c1 = SC<S>::dt2h(sc)[t1], c2 = SC<S>::dt2h(sc)[t2];
+  constexpr int p12 = pair_index(t1, t2), p21 = pair_index(t2, t1);
+  const S* w = work + B.eoff + z.e;
+  int fl = 0;
+  S L[5], R[5];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const long long off = side == 0 ? -sd : 0;
+    S qe[5], ue[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qe[m] = w[(E_TRACE + (d * 2 + side) * 5 + m) * LE + off];
+    prim_to_cons(qe, G, ue);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const S* fa = w + (E_F2 + p12 * 5 + m) * LE + off;
+      const S* fb = w + (E_F2 + p21 * 5 + m) * LE + off;
+      ue[m] = ue[m] - c1 * (fa[s1] - fa[0]) - c2 * (fb[s2] - fb[0]);
+    }
+    cons_to_prim_floor(ue, G, side == 0 ? L : R, fl);
+  }
+  S F[5];
+  riemann<d>(L, R, G, F, fl);
+  S* o = work + B.eoff + z.e;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) o[(E_F3 + d * 5 + m) * LE] = F[m];
+  double* fo = d == 0 ? fx : (d == 1 ? fy : fz);
+  if (fo) {
+    int fe[3] = {B.n[0], B.n[1], B.n[2]};
+    fe[d] += 1;
+    const long long FN = (long long)fe[0] * fe[1] * fe[2];
+    const long long li = ((long long)z.x[2] * fe[1] + z.x[1]) * fe[0] + z.x[0];
+    double* q = fo + B.foff[d] + li;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) q[m * FN] = (double)F[m];
+  }
+  raise_flags(flags, fl);
+}
+
+template <class S>
+__global__ void __launch_bounds__(TILE) k_riemann3(const Tile* __restrict__ tiles, int ntiles,
+                                                   const DevBox* __restrict__ boxes,
+                                                   S* __restrict__ work, long long LE, Gas<S> G,
+                                                   const StepConsts* __restrict__ sc,
+                                                   double* fx, double* fy, double* fz, int* flags) {
+  switch (blockIdx.y) {
+    case 0: riemann3_body<0>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+    case 1: riemann3_body<1>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+    default: riemann3_body<2>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+  }
+}
+
+// O10: conservative update in FP64 (+ Heun source) on the valid zones.
+template <class S>
+__global__ void __launch_bounds__(TILE) k_update(const Tile* __restrict__ tiles, int ntiles,
+                                                 const DevBox* __restrict__ boxes,
+                                                 const double* __restrict__ U, double* __restrict__ Unew,
+                                                 const S* __restrict__ work, long long LE,
+                                                 const StepConsts* __restrict__ sc, int grav,
+                                                 double g0, double g1, double g2) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[0] < 0 || z.x[0] >= B.n[0] || z.x[1] < 0 || z.x[1] >= B.n[1] || z.x[2] < 0 ||
+      z.x[2] >= B.n[2])
+    return;
+  const long long sy = z.E[0], sz = (long long)z.E[0] * z.E[1];
+  const double dtdx0 = sc->dtdx[0], dtdx1 = sc->dtdx[1], dtdx2 = sc->dtdx[2];
+  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
+  const long long NS = (long long)N0 * N1 * N2;
+  const long long ui = B.soff + ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
+  const S* w = work + B.eoff + z.e;
+  double un[5], uo[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* f0 = w + (E_F3 + 0 * 5 + m) * LE;
+    const S* f1 = w + (E_F3 + 1 * 5 + m) * LE;
+    const S* f2 = w + (E_F3 + 2 * 5 + m) * LE;
+    const double fxd = (double)f0[1] - (double)f0[0];
+    const double fyd = (double)f1[sy] - (double)f1[0];
+    const double fzd = (double)f2[sz] - (double)f2[0];
+    uo[m] = U[ui + m * NS];
+    un[m] = uo[m] - ((dtdx0 * fxd + dtdx1 * fyd) + dtdx2 * fzd);
+  }
+  if (grav) {
+    const double adt = sc->dt, hdt = sc->hdt;
+    double s0[5], s1[5];
+    s0[1] = uo[0] * g0;
+    s0[2] = uo[0] * g1;
+    s0[3] = uo[0] * g2;
+    s0[4] = (uo[1] * g0 + uo[2] * g1) + uo[3] * g2;
+#pragma unroll
+    for (int m = 1; m < 5; ++m) un[m] = un[m] + adt * s0[m];
+    s1[1] = un[0] * g0;
+    s1[2] = un[0] * g1;
+    s1[3] = un[0] * g2;
+    s1[4] = (un[1] * g0 + un[2] * g1) + un[3] * g2;
+#pragma unroll
+    for (int m = 1; m < 5; ++m) un[m] = un[m] + hdt * (s1[m] - s0[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Unew[ui + m * NS] = un[m];
+}
+
+// O11: max over valid zones and axes of (|u_d| + c)/h_d, FP64.  A fixed grid
+// strides over the tiles; each lane keeps a running max, the workgroup
+// reduces it with wave64 shuffles and LDS, and one atomic max per workgroup
+// (on the bit pattern: non-negative doubles order like their unsigned bit
+// patterns) combines the workgroups.  max is exact, so the result does not
+// depend on the order.
+__global__ void __launch_bounds__(TILE) k_wavespeed(const Tile* __restrict__ tiles, int ntiles,
+                                                    const DevBox* __restrict__ boxes,
+                                                    const double* __restrict__ U, double h0, double h1,
+                                                    double h2, double gamma, double gm1,
+                                                    double small_pres,
+                                                    unsigned long long* __restrict__ smax_bits) {
+  double s = 0.0;
+  for (int tt = blockIdx.x; tt < ntiles; tt += gridDim.x) {
+    const Tile tl = tiles[tt];
+    const DevBox B = boxes[tl.box];
+    EZone z;
+    if (ezone(tl, B, z) && z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] &&
+        z.x[2] >= 0 && z.x[2] < B.n[2]) {
+      const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
+      const long long NS = (long long)N0 * N1 * N2;
+      const double* u = U + B.soff + ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
+      const double r = u[0];
+      const double vx = u[NS] / r, vy = u[2 * NS] / r, vz = u[3 * NS] / r;
+      const double ke = 0.5 * r * ((vx * vx + vy * vy) + vz * vz);
+      double p = gm1 * (u[4 * NS] - ke);
+      p = smax(p, small_pres);
+      const double c = __builtin_sqrt(gamma * p / r);
+      const double sx = (sabs(vx) + c) / h0;
+      const double sy = (sabs(vy) + c) / h1;
+      const double sz = (sabs(vz) + c) / h2;
+      s = smax(smax(smax(s, sx), sy), sz);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) s = smax(s, __shfl_xor(s, off, 64));
+  __shared__ double wmax[TILE / 64];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (int w = 1; w < TILE / 64; ++w) m = smax(m, wmax[w]);
+    atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void __launch_bounds__(64) k_zero_u64(unsigned long long* p) {
+  if (threadIdx.x == 0) p[0] = 0ull;
+}
+
+__global__ void __launch_bounds__(64) k_finish_dt(double* dt_dev, double cfl) {
+  if (threadIdx.x == 0) {
+    const double s = __longlong_as_double((long long)(((unsigned long long*)dt_dev)[1]));
+    dt_dev[1] = s;
+    dt_dev[0] = cfl / s;
+  }
+}
+
+// O1: ghost fill over the plan.  One lane per destination ghost zone; the
+// descriptor of a lane is found by binary search in the zone-count prefix.
+__global__ void __launch_bounds__(TILE) k_fill(const FillDesc* __restrict__ desc,
+                                               const long long* __restrict__ start, int d0, int d1,
+                                               long long z0, long long z1,
+                                               const DevBox* __restrict__ boxes, double* U) {
+  const long long gidx = z0 + (long long)blockIdx.x * TILE + threadIdx.x;
+  if (gidx >= z1) return;
+  int lo = d0, hi = d1 - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= gidx) lo = mid; else hi = mid - 1;
+  }
+  const FillDesc D = desc[lo];
+  const long long l = gidx - start[lo];
+  const int ex = D.hi[0] - D.lo[0] + 1, ey = D.hi[1] - D.lo[1] + 1;
+  const int x = D.lo[0] + (int)(l % ex);
+  const int y = D.lo[1] + (int)((l / ex) % ey);
+  const int zz = D.lo[2] + (int)(l / ((long long)ex * ey));
+  const int sx = D.a[0] * x + D.c[0], sy = D.a[1] * y + D.c[1], sz = D.a[2] * zz + D.c[2];
+  const DevBox Bd = boxes[D.dst], Bs = boxes[D.src];
+  const int dN0 = Bd.n[0] + 2 * NG, dN1 = Bd.n[1] + 2 * NG, dN2 = Bd.n[2] + 2 * NG;
+  const int sN0 = Bs.n[0] + 2 * NG, sN1 = Bs.n[1] + 2 * NG, sN2 = Bs.n[2] + 2 * NG;
+  const long long dNS = (long long)dN0 * dN1 * dN2, sNS = (long long)sN0 * sN1 * sN2;
+  const long long di = Bd.soff + ((long long)(zz + NG) * dN1 + (y + NG)) * dN0 + (x + NG);
+  const long long si = Bs.soff + ((long long)(sz + NG) * sN1 + (sy + NG)) * sN0 + (sx + NG);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double v = U[si + c * sNS];
+    const bool neg = c >= 1 && c <= 3 && ((D.sign >> (c - 1)) & 1);
+    U[di + c * dNS] = neg ? -v : v;
+  }
+}
+
+template <class S>
+Gas<S> make_gas(double gamma, double small_dens, double small_pres, int limiter, int flattening, int iters,
+                int grav) {
+  Gas<S> G;
+  G.gamma = S(gamma);
+  G.gm1 = S(gamma - 1.0);
+  G.gm1inv = S(1.0 / (gamma - 1.0));
+  G.beta = S((gamma + 1.0) / (2.0 * gamma));
+  G.small_dens = S(small_dens);
+  G.small_pres = S(small_pres);
+  G.limiter = limiter;
+  G.flattening = flattening && limiter;
+  G.iters = iters;
+  G.grav = grav;
+  return G;
+}
+
+template <class S>
+hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, const double* U, double* Unew,
+                     double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
+                     hipEvent_t* ev) {
+  S* prim = (S*)work;
+  S* ework = prim + P_PLANES * L.LS;
+  const int nS = tS1 - tS0, nE = tE1 - tE0;
+  const Tile* TS = L.tilesS + tS0;
+  const Tile* TE = L.tilesE + tE0;
+  if (nS <= 0 || nE <= 0) return hipSuccess;
+  const dim3 blk(TILE);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(k_prim<S>, dim3(xcd_grid(nS)), blk, 0, s, TS, nS, L.boxes, U, prim, L.LS, G, L.flags);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  hipLaunchKernelGGL(k_flatten<S>, dim3(xcd_grid(nE)), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework, L.LE, G);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  hipLaunchKernelGGL(k_trace<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework, L.LE,
+                     G, L.consts, L.flags);
+  if (ev) (void)hipEventRecord(ev[3], s);
+  hipLaunchKernelGGL(k_riemann1<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
+                     L.flags);
+  if (ev) (void)hipEventRecord(ev[4], s);
+  hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 6), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
+                     L.consts, L.flags);
+  double* fx = flux ? flux[0] : nullptr;
+  double* fy = flux ? flux[1] : nullptr;
+  double* fz = flux ? flux[2] : nullptr;
+  if (ev) (void)hipEventRecord(ev[5], s);
+  hipLaunchKernelGGL(k_riemann3<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
+                     L.consts, fx, fy, fz, L.flags);
+  if (ev) (void)hipEventRecord(ev[6], s);
+  hipLaunchKernelGGL(k_update<S>, dim3(xcd_grid(nE)), blk, 0, s, TE, nE, L.boxes, U, Unew,
+                     (const S*)ework, L.LE, L.consts, G.grav, g[0], g[1], g[2]);
+  if (ev) (void)hipEventRecord(ev[7], s);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step_consts(const DevLevel& L, double dt, const double* dt_dev, const double h[3],
+                              const double g[3], hipStream_t s) {
+  hipLaunchKernelGGL(k_step_consts, dim3(1), dim3(64), 0, s, L.consts, dt, dt_dev, h[0], h[1], h[2], g[0],
+                     g[1], g[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_end, long long zone_begin,
+                       long long zone_end, hipStream_t s) {
+  if (desc_end <= desc_begin || zone_end <= zone_begin) return hipSuccess;
+  const long long nz = zone_end - zone_begin;
+  const unsigned grid = (unsigned)((nz + TILE - 1) / TILE);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(TILE), 0, s, L.desc, L.desc_start, desc_begin, desc_end,
+                     zone_begin, zone_end, L.boxes, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, const double* U,
+                             const double h[3], double gamma, double small_pres, double cfl,
+                             double* dt_dev, hipStream_t s) {
+  unsigned long long* bits = (unsigned long long*)(dt_dev + 1);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, bits);
+  const int n = tile_end - tile_begin;
+  if (n > 0)
+    hipLaunchKernelGGL(k_wavespeed, dim3(n < 2048 ? n : 2048), dim3(TILE), 0, s, L.tilesE + tile_begin, n, L.boxes, U,
+                       h[0], h[1], h[2], gamma, gamma - 1.0, small_pres, bits);
+  hipLaunchKernelGGL(k_finish_dt, dim3(1), dim3(64), 0, s, dt_dev, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, const double* U,
+                       double* Unew, double* const* flux, void* work, const double gamma,
+                       const double small_dens, const double small_pres, int limiter, int flattening,
+                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev) {
+  if (precision == 1)
+    return step_impl<float>(L, tS0, tS1, tE0, tE1, U, Unew, flux, work,
+                            make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
+                            g, s, ev);
+  return step_impl<double>(L, tS0, tS1, tE0, tE1, U, Unew, flux, work,
+                           make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
+                           g, s, ev);
+}
+
+}  // namespace ppm

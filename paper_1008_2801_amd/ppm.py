@@ -1,0 +1,355 @@
+"""Python binding of the C ABI in include/ppm.h (argument marshalling only).
+
+Every step of the path runs in the HIP kernels of libppm.so; this module
+converts Python/torch arguments into pointers and sizes.  PyTorch provides
+device memory and the current stream.  There is no CPU fallback: if the
+library is missing, or no GPU is present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import inputs as _inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libppm.so")
+
+PPM_OK, PPM_EINVAL, PPM_EHIP, PPM_ENONPHYS = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+FLAG_NONPHYS, FLAG_FLOOR = 1, 2
+BATCHED, PER_BOX = 0, 1
+
+# Every exported symbol of include/ppm.h.
+SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_offsets",
+           "ppm_flux_offsets", "ppm_workspace_bytes", "ppm_set_workspace", "ppm_fill_boundary",
+           "ppm_compute_dt", "ppm_hydro_step", "ppm_graph_create", "ppm_graph_launch",
+           "ppm_graph_destroy", "ppm_check_status", "ppm_plan_build", "ppm_fill_boundary_host",
+           "ppm_plan_cache_stats", "ppm_profile_enable", "ppm_profile_read")
+PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
+
+
+class PPMError(RuntimeError):
+    pass
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3)]
+
+
+class LayoutC(ctypes.Structure):
+    _fields_ = [("nbox", ctypes.c_int32), ("boxes", ctypes.POINTER(Box)), ("domain", Box),
+                ("bc", ctypes.c_int32 * 6), ("ngrow", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("small_dens", ctypes.c_double), ("small_pres", ctypes.c_double),
+                ("grav", ctypes.c_double * 3), ("limiter", ctypes.c_int32),
+                ("flattening", ctypes.c_int32), ("riemann_iters", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+def params(gamma=1.4, cfl=0.5, small_dens=1e-12, small_pres=1e-12, grav=(0.0, 0.0, 0.0), limiter=1,
+           flattening=1, riemann_iters=3, precision=0):
+    p = Params()
+    p.gamma, p.cfl, p.small_dens, p.small_pres = gamma, cfl, small_dens, small_pres
+    for d in range(3):
+        p.grav[d] = float(grav[d])
+    p.limiter, p.flattening, p.riemann_iters, p.precision = limiter, flattening, riemann_iters, precision
+    return p
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_dp3 = ctypes.c_double * 3
+
+
+def lib():
+    """Load libppm.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PPMError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ppm_ctx_create.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(_vp)]
+        L.ppm_ctx_destroy.argtypes = [_vp]
+        L.ppm_last_error.argtypes = [_vp]
+        L.ppm_last_error.restype = ctypes.c_char_p
+        L.ppm_layout_offsets.argtypes = [_vp, _i64p]
+        L.ppm_flux_offsets.argtypes = [_vp, ctypes.c_int32, _i64p]
+        L.ppm_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
+        L.ppm_workspace_bytes.restype = ctypes.c_size_t
+        L.ppm_set_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.ppm_fill_boundary.argtypes = [_vp, _vp, ctypes.c_int32, _vp]
+        L.ppm_compute_dt.argtypes = [_vp, _vp, _dp3, ctypes.POINTER(Params), _vp, _vp]
+        L.ppm_hydro_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_double, _vp, _dp3,
+                                     ctypes.POINTER(Params), ctypes.c_int32, _vp]
+        L.ppm_graph_create.argtypes = [_vp, _vp, _vp, _dp3, ctypes.POINTER(Params), ctypes.c_int32, _vp,
+                                       ctypes.POINTER(_vp)]
+        L.ppm_graph_launch.argtypes = [_vp, _vp]
+        L.ppm_graph_destroy.argtypes = [_vp]
+        L.ppm_check_status.argtypes = [_vp, _vp, _i32p]
+        L.ppm_plan_build.argtypes = [ctypes.POINTER(LayoutC), ctypes.c_int32, ctypes.c_int32, _i32p, _i32p]
+        L.ppm_fill_boundary_host.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
+        L.ppm_plan_cache_stats.argtypes = [_i64p, _i64p, _i32p]
+        L.ppm_profile_enable.argtypes = [_vp, ctypes.c_int32]
+        L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        for name in SYMBOLS:
+            f = getattr(L, name)
+            if name not in ("ppm_last_error", "ppm_workspace_bytes"):
+                f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def layout_struct(layout):
+    """ppm_layout for an inputs.Layout (the struct keeps its box array alive)."""
+    nb = layout.nbox
+    arr = (Box * nb)()
+    for b in range(nb):
+        for d in range(3):
+            arr[b].lo[d] = int(layout.lo[b, d])
+            arr[b].hi[d] = int(layout.hi[b, d])
+    L = LayoutC()
+    L.nbox = nb
+    L.boxes = ctypes.cast(arr, ctypes.POINTER(Box))
+    for d in range(3):
+        L.domain.lo[d] = int(layout.domain_lo[d])
+        L.domain.hi[d] = int(layout.domain_hi[d])
+    for f in range(6):
+        L.bc[f] = int(layout.bc[f])
+    L.ngrow = int(layout.ngrow)
+    L._keep = arr
+    return L
+
+
+def plan_build(layout, brute=False):
+    """Fill-plan descriptors as an (ndesc, 20) int32 array (host only)."""
+    L = layout_struct(layout)
+    cnt = ctypes.c_int32(0)
+    rc = lib().ppm_plan_build(ctypes.byref(L), int(brute), 0, None, ctypes.byref(cnt))
+    if rc != PPM_OK:
+        raise PPMError(f"ppm_plan_build failed ({rc})")
+    out = np.zeros((cnt.value, 20), dtype=np.int32)
+    rc = lib().ppm_plan_build(ctypes.byref(L), int(brute), cnt.value,
+                              out.ctypes.data_as(_i32p), ctypes.byref(cnt))
+    if rc != PPM_OK:
+        raise PPMError(f"ppm_plan_build failed ({rc})")
+    return out
+
+
+def fill_boundary_host(layout, arena):
+    """Executes the cached fill plan on a host float64 arena (in place)."""
+    assert arena.dtype == np.float64 and arena.flags.c_contiguous
+    L = layout_struct(layout)
+    rc = lib().ppm_fill_boundary_host(ctypes.byref(L), arena.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != PPM_OK:
+        raise PPMError(f"ppm_fill_boundary_host failed ({rc})")
+    return arena
+
+
+def plan_cache_stats():
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    lib().ppm_plan_cache_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return a.value, b.value, c.value
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Level:
+    """A level (MultiFAB) on the GPU: the library context for a layout plus
+    a torch-owned workspace.  States are torch float64 CUDA tensors of
+    length arena_len laid out as in include/ppm.h."""
+
+    def __init__(self, layout):
+        import torch
+        self.layout = layout
+        self._L = layout_struct(layout)
+        h = ctypes.c_void_p()
+        rc = lib().ppm_ctx_create(ctypes.byref(self._L), ctypes.byref(h))
+        if rc != PPM_OK:
+            raise PPMError(f"ppm_ctx_create failed ({rc})")
+        self.ctx = h
+        nb = layout.nbox
+        off = np.zeros(nb + 1, dtype=np.int64)
+        lib().ppm_layout_offsets(self.ctx, off.ctypes.data_as(_i64p))
+        self.offsets = off
+        self.flux_offsets = []
+        for d in range(3):
+            fo = np.zeros(nb + 1, dtype=np.int64)
+            lib().ppm_flux_offsets(self.ctx, d, fo.ctypes.data_as(_i64p))
+            self.flux_offsets.append(fo)
+        assert np.array_equal(off, layout.offsets()), "arena offsets differ from the layout's"
+        self._work = None
+        self._work_prec = None
+        self.device = torch.device("cuda")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().ppm_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def arena_len(self):
+        return int(self.offsets[-1])
+
+    def _check(self, rc, what):
+        if rc != PPM_OK:
+            msg = lib().ppm_last_error(self.ctx)
+            raise PPMError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def workspace_bytes(self, precision=0):
+        return int(lib().ppm_workspace_bytes(self.ctx, int(precision)))
+
+    def ensure_workspace(self, precision=0):
+        import torch
+        need = self.workspace_bytes(precision)
+        if self._work is None or self._work.numel() < need:
+            self._work = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self._work.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(lib().ppm_set_workspace(self.ctx, ctypes.c_void_p(aligned), need), "ppm_set_workspace")
+        self._work_prec = precision
+
+    def new_state(self):
+        import torch
+        return torch.full((self.arena_len,), float("nan"), dtype=torch.float64, device=self.device)
+
+    def new_fluxes(self):
+        import torch
+        return [torch.zeros(int(self.flux_offsets[d][-1]), dtype=torch.float64, device=self.device)
+                for d in range(3)]
+
+    def fill_boundary(self, U, mode=BATCHED, stream=None):
+        self._check(lib().ppm_fill_boundary(self.ctx, _ptr(U), int(mode), _stream(stream)), "ppm_fill_boundary")
+
+    def compute_dt(self, U, dx, p, out=None, stream=None):
+        import torch
+        out = torch.zeros(2, dtype=torch.float64, device=self.device) if out is None else out
+        self._check(lib().ppm_compute_dt(self.ctx, _ptr(U), _dp3(*dx), ctypes.byref(p), _ptr(out),
+                                         _stream(stream)), "ppm_compute_dt")
+        return out
+
+    def hydro_step(self, U, Unew, dx, p, dt=0.0, dt_dev=None, fluxes=None, mode=BATCHED, stream=None):
+        if self._work is None or self._work_prec != p.precision or self._work.numel() < self.workspace_bytes(p.precision):
+            self.ensure_workspace(p.precision)
+        fl = None
+        if fluxes is not None:
+            fl = (_vp * 3)(*[f.data_ptr() if f is not None else None for f in fluxes])
+        self._check(lib().ppm_hydro_step(self.ctx, _ptr(U), _ptr(Unew), fl, float(dt), _ptr(dt_dev),
+                                         _dp3(*dx), ctypes.byref(p), int(mode), _stream(stream)),
+                    "ppm_hydro_step")
+
+    def profile_enable(self, on=True):
+        self._check(lib().ppm_profile_enable(self.ctx, int(bool(on))), "ppm_profile_enable")
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} of the launches timed since the last read."""
+        n = len(PROF_TAGS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self._check(lib().ppm_profile_read(self.ctx, ms, cnt), "ppm_profile_read")
+        return {PROF_TAGS[k]: (ms[k], cnt[k]) for k in range(n)}
+
+    def check_status(self, stream=None):
+        f = ctypes.c_int32(0)
+        rc = lib().ppm_check_status(self.ctx, _stream(stream), ctypes.byref(f))
+        if rc not in (PPM_OK, PPM_ENONPHYS):
+            self._check(rc, "ppm_check_status")
+        return f.value
+
+    def graph(self, Ua, Ub, dx, p, nsteps, stream=None):
+        return Graph(self, Ua, Ub, dx, p, nsteps, stream)
+
+    def box_view(self, U, b):
+        """Box b of a state tensor as (5, Nz, Ny, Nx)."""
+        o = self.offsets
+        return U[int(o[b]):int(o[b + 1])].view(self.layout.stored_shape(b))
+
+    def flux_view(self, F, d, b):
+        nx, ny, nz = self.layout.n(b)
+        e = [nx, ny, nz]
+        e[d] += 1
+        o = self.flux_offsets[d]
+        return F[int(o[b]):int(o[b + 1])].view(5, e[2], e[1], e[0])
+
+
+class Graph:
+    """nsteps batched steps [fill, dt, step] captured in a HIP graph, A -> B -> A ..."""
+
+    def __init__(self, level, Ua, Ub, dx, p, nsteps, stream=None):
+        import torch
+        level.ensure_workspace(p.precision)
+        self.level = level
+        self._keep = (Ua, Ub)
+        g = ctypes.c_void_p()
+        # capture needs a stream other than the legacy null stream
+        cap = torch.cuda.Stream() if stream is None else stream
+        cap.wait_stream(torch.cuda.current_stream())
+        level._check(lib().ppm_graph_create(level.ctx, _ptr(Ua), _ptr(Ub), _dp3(*dx), ctypes.byref(p),
+                                            int(nsteps), _stream(cap), ctypes.byref(g)),
+                     "ppm_graph_create")
+        torch.cuda.current_stream().wait_stream(cap)
+        self.g = g
+        self.nsteps = nsteps
+
+    def launch(self, stream=None):
+        self.level._check(lib().ppm_graph_launch(self.g, _stream(stream)), "ppm_graph_launch")
+
+    def close(self):
+        if getattr(self, "g", None):
+            lib().ppm_graph_destroy(self.g)
+            self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_levels = {}
+
+
+def hydro_step(boxes, U, dt, dx, gamma, bc=(0, 0, 0, 0, 0, 0), domain=None, fluxes=True, **kw):
+    """One step of a level: (U', fluxes) = hydro_step(boxes, U, dt, dx, gamma, bc).
+
+    boxes: list of (lo, hi) inclusive index triples tiling the domain (the
+    bounding box of the boxes unless `domain` is given); U: float64 CUDA
+    tensor state arena (ghosts need not be filled: the fill runs first);
+    returns the new state (ghosts unfilled) and, if fluxes, the three flux
+    arenas.  Extra keyword arguments go to params()."""
+    import torch
+    lo = np.array([b[0] for b in boxes], dtype=np.int64)
+    hi = np.array([b[1] for b in boxes], dtype=np.int64)
+    if domain is None:
+        domain = (tuple(lo.min(axis=0)), tuple(hi.max(axis=0)))
+    lay = _inputs.Layout(lo, hi, tuple(domain[0]), tuple(domain[1]), tuple(bc))
+    key = (lo.tobytes(), hi.tobytes(), tuple(domain[0]), tuple(domain[1]), tuple(bc))
+    lev = _levels.get(key)
+    if lev is None:
+        lev = _levels[key] = Level(lay)
+    p = params(gamma=gamma, **kw)
+    Uf = U.clone()
+    lev.fill_boundary(Uf)
+    Un = lev.new_state()
+    F = lev.new_fluxes() if fluxes else None
+    lev.hydro_step(Uf, Un, dx, p, dt=dt, fluxes=F)
+    return Un, F

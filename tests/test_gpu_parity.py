@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path through the C ABI against the oracle on the same
+seeded inputs.  FP64 bar: per-field max |gpu - oracle| / max |oracle| <= 1e-12
+(the path evaluates the same formulas in the same order, so the results are
+expected to agree bit for bit; the tolerance is the stated bar)."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1008_2801_amd import inputs as I  # noqa: E402
+from paper_1008_2801_amd import ppm as P  # noqa: E402
+from tests.helpers import interior, field_errors  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def gpu_run(wl, nsteps, mode=P.BATCHED, fluxes=False, dt=None, **pk):
+    """nsteps of [fill, dt, step] on the GPU; returns (level, host arena, dts, flags, last fluxes)."""
+    lev = P.Level(wl.layout)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision, **pk)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    dts, F = [], None
+    for _ in range(nsteps):
+        lev.fill_boundary(U, mode)
+        if dt is None:
+            lev.compute_dt(U, wl.dx, p, out=dtv)
+        else:
+            dtv[0] = dt
+        F = lev.new_fluxes() if fluxes else None
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, fluxes=F, mode=mode)
+        dts.append(float(dtv[0].item()))
+        U, V = V, U
+    flags = lev.check_status()
+    return lev, U.cpu().numpy(), dts, flags, F
+
+
+def oracle_run(wl, nsteps, dt=None, fluxes=False, **pk):
+    lay = wl.layout
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    p = O.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision, **pk)
+    return O.advance(lay.boxes(), lay.domain(), lay.bc, st, nsteps, wl.dx, p, dt=dt, fluxes=fluxes)
+
+
+def compare_level(wl, arena, ostates, tol=TOL):
+    worst = 0.0
+    nbits = 0
+    for b in range(wl.layout.nbox):
+        g = interior(wl.layout.view(arena, b))
+        o = interior(ostates[b])
+        worst = max(worst, field_errors(g, o).max())
+        nbits += int(np.count_nonzero(g != o))
+    assert worst <= tol, (worst, nbits)
+    return worst, nbits
+
+
+def test_cfg1_full_run_matches_oracle():
+    """32^3 advected wave, 10 steps at CFL 0.5 (the small configuration)."""
+    wl = I.cfg1()
+    _, arena, dts, flags, _ = gpu_run(wl, 10)
+    ost, odts, ofl, _ = oracle_run(wl, 10)
+    assert flags == 0 and ofl == 0
+    assert dts == odts
+    worst, nbits = compare_level(wl, arena, ost)
+    print(f"cfg1: max field error {worst:.3e}, differing values {nbits}")
+
+
+@pytest.mark.parametrize("limiter,iters", [(1, 3), (0, 3), (1, 0), (1, 8)])
+def test_scheme_options_match_oracle(limiter, iters):
+    wl = I.cfg2(24)
+    _, arena, dts, flags, _ = gpu_run(wl, 3, limiter=limiter, riemann_iters=iters)
+    ost, odts, ofl, _ = oracle_run(wl, 3, limiter=limiter, riemann_iters=iters)
+    assert dts == odts and flags == ofl
+    compare_level(wl, arena, ost)
+
+
+def test_fluxes_match_oracle():
+    wl = I.cfg2(20)
+    lev, arena, dts, flags, F = gpu_run(wl, 1, fluxes=True)
+    ost, odts, ofl, OF = oracle_run(wl, 1, fluxes=True)
+    for d in range(3):
+        g = lev.flux_view(F[d], d, 0).cpu().numpy()
+        o = OF[0][d]
+        err = np.abs(g - o).max() / np.abs(o).max()
+        assert err <= TOL, (d, err)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (0, 0, 0, 0, 2, 2), (1, 1, 2, 2, 0, 0)])
+def test_fill_matches_oracle_fill_bitwise(bc):
+    rng = np.random.default_rng(12)
+    lay = I.tensor_tiling(rng.integers(4, 11, 3), rng.integers(4, 11, 2), rng.integers(4, 11, 3), bc=bc)
+    arena = rng.normal(size=lay.arena_len())
+    lev = P.Level(lay)
+    for mode in (P.BATCHED, P.PER_BOX):
+        U = torch.from_numpy(arena).cuda()
+        lev.fill_boundary(U, mode)
+        g = U.cpu().numpy()
+        st = [lay.view(arena, b).copy() for b in range(lay.nbox)]
+        O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+        for b in range(lay.nbox):
+            assert np.array_equal(lay.view(g, b), st[b])
+
+
+def _uneven_level(seed=5, bc=(0, 0, 0, 0, 0, 0), sizes=(8, 12, 16)):
+    rng = np.random.default_rng(seed)
+    lay = I.tensor_tiling(rng.choice(sizes, 3), rng.choice(sizes, 2), rng.choice(sizes, 2), bc=bc)
+    L = tuple((np.array(lay.domain_hi) + 1) / 64.0)
+    S = [I.ModeSum(rng, 6, 3, L) for _ in range(5)]
+
+    def prim(x, y, z):
+        return (1.25 + 0.75 * S[0](x, y, z), 0.5 * S[1](x, y, z), 0.5 * S[2](x, y, z), 0.5 * S[3](x, y, z),
+                1.25 + 0.75 * S[4](x, y, z))
+    h = (1.0 / 64,) * 3
+    return I.Workload("uneven", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 2)
+
+
+def test_multibox_batched_and_per_box_match_oracle_and_each_other():
+    wl = _uneven_level()
+    _, a_b, dts_b, fl_b, _ = gpu_run(wl, 2, mode=P.BATCHED)
+    _, a_p, dts_p, fl_p, _ = gpu_run(wl, 2, mode=P.PER_BOX)
+    assert np.array_equal(a_b, a_p) or np.array_equal(np.nan_to_num(a_b), np.nan_to_num(a_p))
+    ost, odts, ofl, _ = oracle_run(wl, 2)
+    assert dts_b == odts
+    compare_level(wl, a_b, ost)
+
+
+def test_reflecting_walls_and_gravity_match_oracle():
+    wl = _uneven_level(seed=7, bc=(0, 0, 0, 0, 2, 2))
+    wl.grav = (0.0, 0.0, -1.0)
+    _, arena, dts, flags, _ = gpu_run(wl, 2)
+    ost, odts, ofl, _ = oracle_run(wl, 2)
+    assert dts == odts and flags == ofl == 0
+    compare_level(wl, arena, ost)
+
+
+def test_fp32_reconstruction_matches_oracle_fp32_mode():
+    wl = I.cfg1(16)
+    wl.precision = 1
+    _, arena, dts, flags, _ = gpu_run(wl, 3)
+    ost, odts, ofl, _ = oracle_run(wl, 3)
+    worst, nbits = compare_level(wl, arena, ost, tol=1e-6)
+    print(f"fp32 mode: max field error vs oracle fp32 mode {worst:.3e}, differing values {nbits}")
+    wl.precision = 0
+    o64, _, _, _ = oracle_run(wl, 3)
+    err = max(field_errors(interior(wl.layout.view(arena, 0)), interior(o64[0])))
+    assert err < 1e-5
+    print(f"fp32 mode vs fp64 oracle: {err:.3e}")
+
+
+def test_uniform_state_preserved_bitwise_on_gpu():
+    wl = I.uniform(12, rho=1.7, vel=(0.4, -0.3, 0.2), p=0.6)
+    _, arena, _, flags, _ = gpu_run(wl, 3)
+    assert flags == 0
+    assert np.array_equal(interior(wl.layout.view(arena, 0)), interior(wl.layout.view(wl.arena, 0)))
+
+
+def test_conservation_on_gpu():
+    wl = _uneven_level(seed=9)
+    _, arena, _, flags, _ = gpu_run(wl, 3)
+    for c in range(5):
+        s0 = math.fsum(np.concatenate([interior(wl.layout.view(wl.arena, b))[c].ravel()
+                                       for b in range(wl.layout.nbox)]))
+        s1 = math.fsum(np.concatenate([interior(wl.layout.view(arena, b))[c].ravel()
+                                       for b in range(wl.layout.nbox)]))
+        sc = math.fsum(np.abs(np.concatenate([interior(wl.layout.view(wl.arena, b))[c].ravel()
+                                              for b in range(wl.layout.nbox)])))
+        assert abs(s1 - s0) <= 1e-13 * sc
+
+
+def test_graph_replay_matches_eager_steps():
+    """Two captured steps A -> B -> A, replayed three times with eager work and
+    synchronisation in between; every replay equals two eager steps."""
+    wl = I.cfg2(16)
+    lev = P.Level(wl.layout)
+    p = P.params(gamma=wl.gamma)
+    A = torch.from_numpy(wl.arena).cuda()
+    B = lev.new_state()
+    g = lev.graph(A, B, wl.dx, p, 2)
+    cur = wl.arena.copy()
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        got = A.cpu().numpy()
+        ref = gpu_run(I.Workload(wl.name, wl.layout, cur.copy(), wl.dx, wl.gamma, 2), 2)[1]
+        assert np.array_equal(interior(wl.layout.view(got, 0)), interior(wl.layout.view(ref, 0))), rep
+        cur = got.copy()
+    g.close()
+
+
+def test_nan_poisoned_workspace_does_not_leak():
+    wl = I.cfg2(16)
+    lev = P.Level(wl.layout)
+    p = P.params(gamma=wl.gamma)
+    lev.ensure_workspace(0)
+    lev._work.view(torch.uint8).fill_(0xFF)  # all-ones bytes: NaN doubles everywhere
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    lev.fill_boundary(U)
+    dtv = lev.compute_dt(U, wl.dx, p)
+    lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv)
+    got = V.cpu().numpy()
+    _, ref, _, _, _ = gpu_run(wl, 1)
+    assert np.array_equal(interior(wl.layout.view(got, 0)), interior(wl.layout.view(ref, 0)))
+    assert lev.check_status() == 0
+
+
+def test_runs_are_deterministic():
+    wl = _uneven_level(seed=11)
+    a = gpu_run(wl, 2)[1]
+    b = gpu_run(wl, 2)[1]
+    assert np.array_equal(np.nan_to_num(a), np.nan_to_num(b))
+
+
+def test_invalid_arguments_are_rejected():
+    wl = I.cfg1(8)
+    lev = P.Level(wl.layout)
+    p = P.params(gamma=1.4)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    with pytest.raises(P.PPMError):
+        lev.hydro_step(U, U, wl.dx, p, dt=0.01)          # in place
+    with pytest.raises(P.PPMError):
+        lev.hydro_step(U, V, wl.dx, p, dt=-1.0)          # dt <= 0
+    with pytest.raises(P.PPMError):
+        lev.hydro_step(U, V, wl.dx, P.params(gamma=1.0), dt=0.01)
+    with pytest.raises(P.PPMError):
+        lev.hydro_step(U, V, (0.1, 0.0, 0.1), p, dt=0.01)
+    bad = I.Layout(np.array([[0, 0, 0], [2, 0, 0]]), np.array([[3, 3, 3], [5, 3, 3]]), (0, 0, 0), (5, 3, 3))
+    with pytest.raises(P.PPMError):
+        P.Level(bad)
+
+
+def test_nonphysical_input_raises_flag():
+    wl = I.cfg1(8)
+    U0 = wl.arena.copy()
+    lay = wl.layout
+    v = lay.view(U0, 0)
+    v[0, 6, 6, 6] = -1.0
+    wl2 = I.Workload("bad", lay, U0, wl.dx, wl.gamma, 1)
+    _, _, _, flags, _ = gpu_run(wl2, 1, dt=1e-3)
+    assert flags & P.FLAG_NONPHYS
+
+
+# --------------------------------------------------- full-size sampling ----
+def _sample_windows(n, rng, k, w=2):
+    out = []
+    for _ in range(k):
+        lo = tuple(int(rng.integers(0, n[d] - w + 1)) for d in range(3))
+        out.append((lo, tuple(v + w - 1 for v in lo)))
+    # corners and the jump planes of the Sod set-up
+    out.append(((0, 0, 0), (1, 1, 1)))
+    out.append(((n[0] - 2, n[1] - 2, n[2] - 2), (n[0] - 1, n[1] - 1, n[2] - 1)))
+    out.append(((n[0] // 2 - 1, 5, 9), (n[0] // 2, 6, 10)))
+    return out
+
+
+def test_cfg2_full_size_sampled_windows():
+    """256^3 FP64, one step as bench.py runs it; the oracle recomputes sampled
+    windows of the output one by one; the whole output is checked for
+    conservation."""
+    wl = I.cfg2()
+    lev, arena, dts, flags, _ = gpu_run(wl, 1)
+    assert flags == 0
+    lay = wl.layout
+    st = [lay.view(wl.arena, 0).copy()]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    p = O.params(gamma=wl.gamma)
+    s, _ = O.max_wavespeed(st[0], wl.dx, p)
+    assert dts[0] == p.cfl / s
+    got = lay.view(arena, 0)
+    rng = np.random.default_rng(1)
+    for lo, hi in _sample_windows(lay.n(0), rng, 12):
+        ref, _, _ = O.step(st[0], dts[0], wl.dx, p, window=(lo, hi))
+        sl = (slice(None),) + tuple(slice(lo[d] + 4, hi[d] + 5) for d in (2, 1, 0))
+        err = np.abs(got[sl] - ref[sl]).max() / np.abs(ref[sl]).max()
+        assert err <= TOL, (lo, hi, err)
+    for c in range(5):
+        s0 = math.fsum(interior(lay.view(wl.arena, 0))[c].ravel())
+        s1 = math.fsum(interior(got)[c].ravel())
+        sc = math.fsum(np.abs(interior(lay.view(wl.arena, 0))[c]).ravel())
+        assert abs(s1 - s0) <= 1e-13 * sc

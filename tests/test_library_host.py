@@ -1,0 +1,89 @@
+"""Host-side logic of the library (no GPU): the C ABI loads and exports every
+declared symbol; the hash-sorted fill plan equals the all-pairs plan and,
+executed on the host, reproduces the oracle's ghost fill; the plan cache
+is hit on repeated layouts; invalid layouts are rejected."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1008_2801_amd import inputs as I
+from paper_1008_2801_amd import ppm as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "ppm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ppm_[a-z_0-9]+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 17
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(P.SYMBOLS)
+
+
+def _layouts():
+    rng = np.random.default_rng(3)
+    out = [I.cfg3_layout()[0],
+           I.tensor_tiling([16] * 4, [16] * 4, [16] * 4, bc=(0, 0, 0, 0, 2, 2)),
+           I.single_box(8)]
+    for bc in [(1, 1, 0, 0, 2, 2), (2, 2, 1, 1, 0, 0), (1, 1, 1, 1, 1, 1)]:
+        out.append(I.tensor_tiling(rng.integers(4, 9, 3), rng.integers(4, 9, 4), rng.integers(4, 9, 2), bc=bc))
+    return out
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_hash_sorted_plan_equals_all_pairs_plan(k):
+    lay = _layouts()[k]
+    a = P.plan_build(lay)
+    b = P.plan_build(lay, brute=True)
+    assert np.array_equal(a, b)
+    # every ghost zone of every box is written exactly once
+    assert a[:, 15].sum() == lay.stored_zones() - lay.valid_zones()
+
+
+@pytest.mark.parametrize("k", range(1, 6))
+def test_plan_executed_on_host_equals_oracle_fill(k):
+    lay = _layouts()[k]
+    rng = np.random.default_rng(k)
+    arena = np.full(lay.arena_len(), np.nan)
+    for b in range(lay.nbox):
+        v = lay.view(arena, b)
+        g = 4
+        v[:, g:-g, g:-g, g:-g] = rng.normal(size=v[:, g:-g, g:-g, g:-g].shape)
+    mine = P.fill_boundary_host(lay, arena.copy())
+    st = [lay.view(arena, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    for b in range(lay.nbox):
+        assert np.array_equal(lay.view(mine, b), st[b])
+
+
+def test_plan_cache_hits_on_repeated_layout():
+    lay = I.tensor_tiling([5, 6], [7, 4], [4, 9])
+    l0, h0, _ = P.plan_cache_stats()
+    P.plan_build(lay)
+    P.plan_build(lay)
+    l1, h1, e1 = P.plan_cache_stats()
+    # plan_build queries twice (count, then descriptors): 4 lookups, 3 hits
+    assert l1 - l0 == 4 and h1 - h0 == 3 and e1 >= 1
+
+
+@pytest.mark.parametrize("lo,hi,dom,bc", [
+    ([[0, 0, 0], [2, 0, 0]], [[3, 3, 3], [5, 3, 3]], ((0, 0, 0), (5, 3, 3)), (0,) * 6),   # overlap
+    ([[0, 0, 0]], [[3, 3, 3]], ((0, 0, 0), (4, 3, 3)), (0,) * 6),                          # gap
+    ([[0, 0, 0]], [[3, 3, 3]], ((0, 0, 0), (3, 3, 3)), (0, 1, 0, 0, 0, 0)),                # half periodic
+    ([[0, 0, 0]], [[2, 3, 3]], ((0, 0, 0), (2, 3, 3)), (0,) * 6),                          # extent < 4
+])
+def test_invalid_layouts_rejected(lo, hi, dom, bc):
+    lay = I.Layout(np.array(lo), np.array(hi), dom[0], dom[1], bc)
+    with pytest.raises(P.PPMError):
+        P.plan_build(lay)
