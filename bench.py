@@ -60,6 +60,98 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def level_rates(wl, steps, warmup, precision, per_box=True):
+    """zone-updates/s of one workload in three launch forms: batched eager
+    (one launch per stage over all boxes), per-box eager (one launch per
+    stage per box) and a HIP graph of `steps` batched steps."""
+    import torch
+    from paper_1008_2801_amd import ppm as P
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+    lev.ensure_workspace(precision)
+    U0 = torch.from_numpy(wl.arena).to("cuda")
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    zones = lay.valid_zones()
+    out = {}
+    forms = (("batched", P.BATCHED), ("per_box", P.PER_BOX)) if per_box else (("batched", P.BATCHED),)
+    for name, mode in forms:
+        U = U0.clone()
+        V = lev.new_state()
+        for k in range(warmup + steps):
+            if k == warmup:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            lev.fill_boundary(U, mode)
+            lev.compute_dt(U, wl.dx, p, out=dtv)
+            lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, mode=mode)
+            U, V = V, U
+        torch.cuda.synchronize()
+        out[name] = zones * steps / (time.perf_counter() - t0)
+    A = U0.clone()
+    B = lev.new_state()
+    g = lev.graph(A, B, wl.dx, p, steps)
+    g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch()
+    torch.cuda.synchronize()
+    out["graph"] = zones * steps / (time.perf_counter() - t0)
+    out["flags"] = lev.check_status()
+    g.close()
+    lev.close()
+    lev._work = None
+    del A, B, U0, U, V, g, lev
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_costs(wl, nsteps, every, reps=3):
+    """Per-step forward and adjoint times (the adjoint includes its own
+    recompute of the forward intermediates) and the whole checkpointed
+    roll-out, forward vs backward."""
+    import torch
+    from paper_1008_2801_amd import ppm as P
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav)
+    U = torch.from_numpy(wl.arena).to("cuda")
+    lev.fill_boundary(U)
+    V = lev.new_state()
+    dtv = lev.compute_dt(U, wl.dx, p)
+    W = torch.randn_like(U)
+    Ub = torch.empty_like(U)
+    lev.ensure_workspace(0)
+    lev.ensure_adjoint_workspace()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    t_fwd = timed(lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
+    t_adj = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv))
+    U0 = torch.from_numpy(wl.arena).to("cuda").requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    UT = P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    UT.backward(torch.ones_like(UT))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    flags = lev.check_status()
+    lev.close()
+    return {"forward_step_ms": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "rollout_steps": nsteps, "checkpoint_every": every, "rollout_forward_s": t1 - t0,
+            "rollout_backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0), "flags": flags}
+
+
 def cpu_baseline(wl, window_edge, gamma):
     """Serial oracle on one step of a cubic window of the workload."""
     import numpy as np
@@ -89,6 +181,8 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--cpu-window", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 512-box batched / per-box / graph measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -175,6 +269,35 @@ def main():
         "step_flop_rate_tflops": step_flops * args.steps / (ms / 1e3) / 1e12,
         "status_flags": flags,
     }
+    if not args.no_extras:
+        del lev, U, V
+        torch.cuda.empty_cache()
+        from paper_1008_2801_amd import inputs as I
+        print("bench: 512-box level (batched / per-box / graph)", file=sys.stderr, flush=True)
+        w3 = I.cfg3()
+        extra = {"workload": f"cfg3: 512 boxes, edges from {{16,24,32,48,64}} (seed 3), "
+                             f"{w3.layout.valid_zones()} valid zones, gamma 1.4, periodic, 20 steps",
+                 "unit": "zone-updates/s"}
+        for prec, tag in ((0, "fp64"), (1, "fp32_reconstruction")):
+            r = level_rates(w3, 20, 2, prec)
+            extra[tag] = r
+            extra[tag]["batched_over_per_box"] = r["batched"] / r["per_box"]
+        out["multibox"] = extra
+        print("bench: adjoint cost on the 128^3 differentiation workload", file=sys.stderr, flush=True)
+        w4 = I.cfg4()
+        a = adjoint_costs(w4, 20, 5)
+        a["workload"] = "cfg4: 128^3 single box, FP64, gamma 1.4, smooth modes of amplitude 0.05, periodic"
+        out["adjoint"] = a
+        del w4
+        print("bench: 512^3 Rayleigh-Taylor level (512 boxes of 64^3)", file=sys.stderr, flush=True)
+        w5 = I.cfg5()
+        rt = {"workload": "cfg5: 512 boxes of 64^3 (512^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "
+                          "10 steps", "unit": "zone-updates/s"}
+        for prec, tag in ((1, "fp32_reconstruction"), (0, "fp64")):
+            r = level_rates(w5, 10, 1, prec, per_box=False)
+            rt[tag] = r
+        out["rayleigh_taylor"] = rt
+        del w5
     if not args.no_cpu_baseline:
         print("bench: timing the CPU reference on a window", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_window, wl.gamma)

@@ -138,6 +138,21 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
                    const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
                    void* stream);
 
+/* Adjoint of one FP64 step (precision 0), dt and every branch decision of
+ * the forward step frozen: given the step's input U (ghosts filled, as for
+ * ppm_hydro_step) and the adjoint Unew_bar of the new state's valid zones,
+ * writes to U_bar the adjoint of U's valid zones -- the transpose of the
+ * step's Jacobian applied to Unew_bar, the ghost-fill transpose included
+ * (ghost adjoints are added into the zones they were copied from) -- and
+ * zeros U_bar's ghost zones.  The forward intermediates are recomputed
+ * into the step workspace (ppm_set_workspace); the reverse stages use a
+ * second caller-owned workspace (ppm_adjoint_workspace_bytes).  U_bar must
+ * not overlap U or Unew_bar.  Deterministic: no atomics. */
+size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx);
+int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
+int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
+                           const double* dt_dev, const double dx[3], const ppm_params* params, void* stream);
+
 /* Batched form captured in a HIP graph: nsteps steps alternating
  * A -> B -> A ..., each step = [fill, CFL dt on the device, step].  After
  * an even nsteps the result is in A, after an odd nsteps in B.  The graph

@@ -1,0 +1,664 @@
+// gfx950 kernels of the adjoint (reverse-mode derivative) of one step,
+// dt frozen and every branch decision frozen at the forward values.
+//
+// Given the step's input state U (ghosts filled) and the adjoint Ub' of the
+// new state's valid zones, the adjoint of U's valid zones is formed as
+//   recompute: prim, flatten, trace, riemann1, riemann2   (forward kernels)
+//   adj_update    Ub' -> adjoint of the pre-source state (Ufb) + direct part
+//   adj_riemann3  final fluxes' adjoint -> corrected-state adjoints (U3b)
+//                 and traced-state adjoints
+//   adj_riemann2  stage-2 fluxes' adjoint (from U3b) -> U2b, traced states
+//   adj_riemann1  stage-1 fluxes' adjoint (from U2b) -> traced states
+//   adj_trace     per axis: traced-state adjoints -> per-zone contributions
+//                 to the primitives of the 5-zone stencil, then a gather
+//   adj_flatten   flattening adjoint -> pressure stencil, then a gather
+//   adj_prim      primitive adjoints -> conserved adjoints (all stored zones)
+//   adj_fill      ghost adjoints gathered into their owning valid zones
+// Every reverse stage writes only the entries it owns or accumulates through
+// a gather in a fixed order: no atomics, results reproducible bit for bit.
+#include <hip/hip_runtime.h>
+
+#include "ppm_device.h"
+#include "ppm_internal.h"
+#include "ppm_math.h"
+#include "ppm_vjp.h"
+
+namespace ppm {
+namespace {
+
+// Adjoint workspace planes: traced grid (A_*) and stored grid (AS_*).
+constexpr int A_UF = 0;              // 5: adjoint of the pre-source state (valid zones, else 0)
+constexpr int A_TB = A_UF + 5;       // 30: traced-state adjoints [d][side][m]
+constexpr int A_U3 = A_TB + 30;      // 30: stage-3 corrected-state adjoints [d][side][m]
+constexpr int A_U2 = A_U3 + 30;      // 60: stage-2 corrected-state adjoints [pair][side][m]
+constexpr int A_GT = A_U2 + 60;      // 25: trace contributions [m][offset + 2]
+constexpr int A_CB = A_GT + 25;      // 1: sound-speed adjoint of the current axis
+constexpr int A_PHB = A_CB + 1;      // 1: flattening-coefficient adjoint
+constexpr int A_GF = A_PHB + 1;      // 7: flattening contributions to p [offset + 3]
+constexpr int A_SEL = A_GF + 7;      // 1: axis selected by the flattening minimum (-1: none)
+constexpr int A_EPLANES = A_SEL + 1;
+constexpr int AS_QB = 0;             // 6: primitive adjoints (rho, u, v, w, p, c)
+constexpr int AS_UB = 6;             // 5: conserved adjoints
+constexpr int A_SPLANES = 11;
+
+__device__ __forceinline__ bool in_e(const int x[3], const DevBox& B) {
+  return x[0] >= -1 && x[0] <= B.n[0] && x[1] >= -1 && x[1] <= B.n[1] && x[2] >= -1 && x[2] <= B.n[2];
+}
+__device__ __forceinline__ long long eidx(const DevBox& B, int x, int y, int z) {
+  return ((long long)(z + 1) * (B.n[1] + 2) + (y + 1)) * (B.n[0] + 2) + (x + 1);
+}
+
+__global__ void __launch_bounds__(TILE) k_zero(double* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * TILE + threadIdx.x; i < n; i += (long long)gridDim.x * TILE)
+    p[i] = 0.0;
+}
+
+// Adjoint of the update and of the Heun source.
+__global__ void __launch_bounds__(TILE) k_adj_update(const Tile* __restrict__ tiles, int ntiles,
+                                                     const DevBox* __restrict__ boxes,
+                                                     const double* __restrict__ Ubn, double* __restrict__ aw,
+                                                     long long LE, double* __restrict__ as, long long LS,
+                                                     const StepConsts* __restrict__ sc, int grav, double g0,
+                                                     double g1, double g2) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  double* uf = aw + A_UF * LE + B.eoff + z.e;
+  const bool valid = z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] && z.x[2] >= 0 &&
+                     z.x[2] < B.n[2];
+  if (!valid) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) uf[m * LE] = 0.0;
+    return;
+  }
+  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
+  const long long NS = (long long)N0 * N1 * N2;
+  const long long li = ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
+  double ub[5], u1b[5], ud[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) { ub[m] = Ubn[B.soff + li + m * NS]; u1b[m] = ub[m]; ud[m] = 0.0; }
+  if (grav) {
+    const double dt = sc->dt, hdt = sc->hdt;
+    // S^T V for the constant-gravity source S(U) = (0, rho g, (rho u).g)
+    auto st = [&](const double v[5], double o[5]) {
+      o[0] = (g0 * v[1] + g1 * v[2]) + g2 * v[3];
+      o[1] = g0 * v[4];
+      o[2] = g1 * v[4];
+      o[3] = g2 * v[4];
+      o[4] = 0.0;
+    };
+    double s[5], s1[5];
+    st(ub, s);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) u1b[m] = ub[m] + hdt * s[m];
+    st(u1b, s1);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) ud[m] = dt * s1[m] - hdt * s[m];
+  }
+  double* ubs = as + AS_UB * LS + B.poff + li;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    uf[m * LE] = u1b[m];
+    ubs[m * LS] = u1b[m] + ud[m];
+  }
+}
+
+// Corrected state of axis d at zone offset `off` from the lane's zone,
+// forward stage-3 form (traced state minus both stage-2 flux differences).
+template <int d, class S>
+__device__ __forceinline__ void r3_state(const S* w, long long LE, long long off, int side, long long s1,
+                                         long long s2, S c1, S c2, const Gas<S>& G, S qe[5], S ue[5]) {
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  constexpr int p12 = pair_index(t1, t2), p21 = pair_index(t2, t1);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) qe[m] = w[(E_TRACE + (d * 2 + side) * 5 + m) * LE + off];
+  prim_to_cons(qe, G, ue);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* fa = w + (E_F2 + p12 * 5 + m) * LE + off;
+    const S* fb = w + (E_F2 + p21 * 5 + m) * LE + off;
+    ue[m] = ue[m] - c1 * (fa[s1] - fa[0]) - c2 * (fb[s2] - fb[0]);
+  }
+}
+
+template <int d>
+__device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int ntiles,
+                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const StepConsts* __restrict__ sc) {
+  using S = double;
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0 || z.x[t1] < 0 || z.x[t1] >= B.n[t1] || z.x[t2] < 0 || z.x[t2] >= B.n[t2]) return;
+  const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
+  const S c1 = sc->d_dt2h[t1], c2 = sc->d_dt2h[t2];
+  const S* w = work + B.eoff + z.e;
+  double* a = aw + B.eoff + z.e;
+  S Fb[5];
+  const double dtdx = sc->dtdx[d];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Fb[m] = dtdx * (a[(A_UF + m) * LE] - a[(A_UF + m) * LE - sd]);
+  S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
+  int fl = 0;
+  r3_state<d>(w, LE, -sd, 0, s1, s2, c1, c2, G, qeL, ueL);
+  r3_state<d>(w, LE, 0, 1, s1, s2, c1, c2, G, qeR, ueR);
+  cons_to_prim_floor(ueL, G, L, fl);
+  cons_to_prim_floor(ueR, G, R, fl);
+  S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
+  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
+  cons_to_prim_floor_vjp(ueL, G, Lb, uLb);
+  cons_to_prim_floor_vjp(ueR, G, Rb, uRb);
+  S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
+  prim_to_cons_vjp(qeL, G, uLb, tLb);
+  prim_to_cons_vjp(qeR, G, uRb, tRb);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    a[(A_U3 + (d * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
+    a[(A_U3 + (d * 2 + 1) * 5 + m) * LE] = uRb[m];
+    a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
+    a[(A_TB + (d * 2 + 1) * 5 + m) * LE] += tRb[m];
+  }
+}
+
+__global__ void __launch_bounds__(TILE) k_adj_r3(const Tile* __restrict__ tiles, int ntiles,
+                                                 const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                                 long long LE, double* __restrict__ aw, Gas<double> G,
+                                                 const StepConsts* __restrict__ sc) {
+  switch (blockIdx.y) {
+    case 0: adj_r3_body<0>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 1: adj_r3_body<1>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    default: adj_r3_body<2>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+  }
+}
+
+// Stage-2 pair (d, t).
+template <int d, int t>
+__device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int ntiles,
+                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const StepConsts* __restrict__ sc) {
+  using S = double;
+  constexpr int pr = pair_index(d, t);
+  constexpr int r = 3 - d - t;
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0 || z.x[t] < 0 || z.x[t] >= B.n[t]) return;
+  const long long sd = stride(z.E, d), stt = stride(z.E, t);
+  const S c3 = sc->d_dt3h[t];
+  const S* w = work + B.eoff + z.e;
+  double* a = aw + B.eoff + z.e;
+  // F2^{d|t} adjoint from the stage-3 states of axis r (difference along d)
+  S Fb[5];
+  const double c2d = sc->d_dt2h[d];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const double* up = a + (A_U3 + (r * 2 + 0) * 5 + m) * LE;
+    const double* um = a + (A_U3 + (r * 2 + 1) * 5 + m) * LE;
+    Fb[m] = c2d * ((up[0] + um[0]) - (up[-sd] + um[-sd]));
+  }
+  S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
+  int fl = 0;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    qeL[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
+    qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
+  }
+  prim_to_cons(qeL, G, ueL);
+  prim_to_cons(qeR, G, ueR);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* fL = w + (E_F1 + t * 5 + m) * LE - sd;
+    const S* fR = w + (E_F1 + t * 5 + m) * LE;
+    ueL[m] = ueL[m] - c3 * (fL[stt] - fL[0]);
+    ueR[m] = ueR[m] - c3 * (fR[stt] - fR[0]);
+  }
+  cons_to_prim_floor(ueL, G, L, fl);
+  cons_to_prim_floor(ueR, G, R, fl);
+  S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
+  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
+  cons_to_prim_floor_vjp(ueL, G, Lb, uLb);
+  cons_to_prim_floor_vjp(ueR, G, Rb, uRb);
+  S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
+  prim_to_cons_vjp(qeL, G, uLb, tLb);
+  prim_to_cons_vjp(qeR, G, uRb, tRb);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    a[(A_U2 + (pr * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
+    a[(A_U2 + (pr * 2 + 1) * 5 + m) * LE] = uRb[m];
+    a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
+    a[(A_TB + (d * 2 + 1) * 5 + m) * LE] += tRb[m];
+  }
+}
+
+// Two launches: phase 0 runs pairs (0,1), (1,0), (2,0); phase 1 runs (0,2),
+// (1,2), (2,1) -- within a launch every pair has its own axis d, so the
+// traced-state accumulations never meet.
+__global__ void __launch_bounds__(TILE) k_adj_r2(const Tile* __restrict__ tiles, int ntiles,
+                                                 const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                                 long long LE, double* __restrict__ aw, Gas<double> G,
+                                                 const StepConsts* __restrict__ sc, int phase) {
+  const int k = blockIdx.y;
+  if (phase == 0) {
+    if (k == 0) adj_r2_body<0, 1>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+    else if (k == 1) adj_r2_body<1, 0>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+    else adj_r2_body<2, 0>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+  } else {
+    if (k == 0) adj_r2_body<0, 2>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+    else if (k == 1) adj_r2_body<1, 2>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+    else adj_r2_body<2, 1>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+  }
+}
+
+template <int d>
+__device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int ntiles,
+                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const StepConsts* __restrict__ sc) {
+  using S = double;
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  constexpr int da = (d == 0) ? 1 : 0, db = (d == 2) ? 1 : 2;  // the two axes whose pairs use F1^d
+  constexpr int pa = pair_index(da, d), pb = pair_index(db, d);
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0) return;
+  const long long sd = stride(z.E, d);
+  const S* w = work + B.eoff + z.e;
+  double* a = aw + B.eoff + z.e;
+  const double c3 = sc->d_dt3h[d];
+  S Fb[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const double* ap = a + (A_U2 + (pa * 2 + 0) * 5 + m) * LE;
+    const double* am = a + (A_U2 + (pa * 2 + 1) * 5 + m) * LE;
+    const double* bp = a + (A_U2 + (pb * 2 + 0) * 5 + m) * LE;
+    const double* bm = a + (A_U2 + (pb * 2 + 1) * 5 + m) * LE;
+    const double sa = (ap[0] + am[0]) - (ap[-sd] + am[-sd]);
+    const double sb = (bp[0] + bm[0]) - (bp[-sd] + bm[-sd]);
+    Fb[m] = c3 * sa + c3 * sb;
+  }
+  S L[5], R[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    L[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
+    R[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
+  }
+  S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
+  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += Lb[m];
+    a[(A_TB + (d * 2 + 1) * 5 + m) * LE] += Rb[m];
+  }
+}
+
+__global__ void __launch_bounds__(TILE) k_adj_r1(const Tile* __restrict__ tiles, int ntiles,
+                                                 const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                                 long long LE, double* __restrict__ aw, Gas<double> G,
+                                                 const StepConsts* __restrict__ sc) {
+  switch (blockIdx.y) {
+    case 0: adj_r1_body<0>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 1: adj_r1_body<1>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    default: adj_r1_body<2>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+  }
+}
+
+// Trace adjoint of axis d: per traced zone, the contributions to the
+// primitives of its 5-zone stencil along d (A_GT), the sound speed (A_CB)
+// and the flattening coefficient (A_PHB, accumulated over the axes).
+template <int d>
+__global__ void __launch_bounds__(TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
+                                                    const DevBox* __restrict__ boxes,
+                                                    const double* __restrict__ prim, long long LS,
+                                                    const double* __restrict__ work, long long LE,
+                                                    double* __restrict__ aw, Gas<double> G,
+                                                    const StepConsts* __restrict__ sc) {
+  using S = double;
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+  const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
+  const long long st = stride(NS, d);
+  const S phi = work[E_FLAT * LE + B.eoff + z.e];
+  double* a = aw + B.eoff + z.e;
+  S as5[5][5], aL[5], aR[5], a6[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* p = prim + m * LS + base;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) as5[m][o] = p[(o - 2) * st];
+    ppm_parabola(as5[m][0], as5[m][1], as5[m][2], as5[m][3], as5[m][4], phi, G, aL[m], aR[m], a6[m]);
+  }
+  const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
+  S qpb[5], qmb[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    qpb[m] = a[(A_TB + (d * 2 + 0) * 5 + m) * LE];
+    qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
+  }
+  S aLb[5] = {0, 0, 0, 0, 0}, aRb[5] = {0, 0, 0, 0, 0}, a6b[5] = {0, 0, 0, 0, 0}, rb = 0, unb = 0, cb = 0;
+  trace_zone_vjp<d>(aL, aR, a6, r, un, c, sc->d_dtdx[d], G, sc->d_hdtg, qpb, qmb, aLb, aRb, a6b, rb, unb, cb);
+  S phib = 0;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    S ab[5] = {0, 0, 0, 0, 0};
+    ppm_parabola_vjp(as5[m], phi, G, aLb[m], aRb[m], a6b[m], ab, phib);
+    if (m == 0) ab[2] += rb;
+    if (m == 1 + d) ab[2] += unb;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) a[(A_GT + m * 5 + o) * LE] = ab[o];
+  }
+  a[A_CB * LE] = cb;
+  a[A_PHB * LE] += phib;
+}
+
+// Gather of the trace contributions of axis d into the primitive adjoints of
+// every stored zone: qb_m(j) += sum over o of GT[m][o](j - o e_d).
+template <int d>
+__global__ void __launch_bounds__(TILE) k_adj_gather_trace(const Tile* __restrict__ tilesS, int ntiles,
+                                                           const DevBox* __restrict__ boxes,
+                                                           const double* __restrict__ aw, long long LE,
+                                                           double* __restrict__ as, long long LS) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tilesS[tt];
+  const DevBox B = boxes[tl.box];
+  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+  const long long tot = (long long)NS[0] * NS[1] * NS[2];
+  const long long idx = (long long)tl.start + threadIdx.x;
+  if (idx >= tot) return;
+  int j[3];
+  j[0] = (int)(idx % NS[0]) - NG;
+  j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
+  j[2] = (int)(idx / ((long long)NS[0] * NS[1])) - NG;
+  double acc[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int o = -2; o <= 2; ++o) {
+    int y[3] = {j[0], j[1], j[2]};
+    y[d] -= o;
+    if (!in_e(y, B)) continue;
+    const double* g = aw + B.eoff + eidx(B, y[0], y[1], y[2]);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) acc[m] += g[(A_GT + m * 5 + (o + 2)) * LE];
+  }
+  double* q = as + AS_QB * LS + B.poff + idx;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) q[m * LS] += acc[m];
+  if (in_e(j, B)) q[5 * LS] += aw[A_CB * LE + B.eoff + eidx(B, j[0], j[1], j[2])];
+}
+
+// Flattening adjoint: the derivative of phi = min_d (1 - chi_d) through the
+// selected axis, the selected shock-detector coefficient and its clamp,
+// into the pressures at offsets -3..3 along that axis (A_GF, A_SEL).
+__global__ void __launch_bounds__(TILE) k_adj_flatten(const Tile* __restrict__ tiles, int ntiles,
+                                                      const DevBox* __restrict__ boxes,
+                                                      const double* __restrict__ prim, long long LS,
+                                                      double* __restrict__ aw, long long LE, Gas<double> G) {
+  using S = double;
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  double* a = aw + B.eoff + z.e;
+  double gf[7] = {0, 0, 0, 0, 0, 0, 0};
+  int sel = -1;
+  if (G.flattening) {
+    const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+    const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
+    S phi = ONE;
+    int dsel = 0, osel = 0;
+    bool live = false;
+    S pd[3][7];
+    int osl[3];
+    bool lv[3];
+    for (int d = 0; d < 3; ++d) {
+      const long long st = stride(NS, d);
+      const S* pp = prim + 4 * LS + base;
+      const S* uu = prim + (1 + d) * LS + base;
+      S p[7], u[5];
+      for (int o = -3; o <= 3; ++o) p[o + 3] = pp[o * st];
+      for (int o = -2; o <= 2; ++o) u[o + 2] = uu[o * st];
+      for (int o = 0; o < 7; ++o) pd[d][o] = p[o];
+      // chit(o): value and whether its derivative is live
+      auto chit = [&](int o, bool& alive) -> S {
+        const S dp1 = p[o + 4] - p[o + 2];
+        const S dp2 = p[o + 5] - p[o + 1];
+        const S zeta = sabs(dp1) / smax(sabs(dp2), G.small_pres);
+        const S x = TEN * (zeta - C075);
+        const S zz = smin(smax(x, S(0)), ONE);
+        const bool compress = (u[o + 1] - u[o + 3]) > S(0);
+        const bool strong = sabs(dp1) > C033 * smin(p[o + 4], p[o + 2]);
+        alive = compress && strong && !(x < S(0)) && !(ONE < x);
+        return (compress && strong) ? zz : S(0);
+      };
+      const S dp1 = p[4] - p[2];
+      bool am, a0, ap;
+      const S cm = chit(-1, am), c0 = chit(0, a0), cp = chit(1, ap);
+      S chi;
+      int o;
+      if (dp1 > S(0)) { chi = smax(c0, cm); o = (c0 < cm) ? -1 : 0; }
+      else if (dp1 < S(0)) { chi = smax(c0, cp); o = (c0 < cp) ? 1 : 0; }
+      else {
+        const S m1 = smax(cm, c0);
+        const int o1 = (cm < c0) ? 0 : -1;
+        chi = smax(m1, cp);
+        o = (m1 < cp) ? 1 : o1;
+      }
+      osl[d] = o;
+      lv[d] = (o == -1) ? am : (o == 0 ? a0 : ap);
+      const S val = ONE - chi;
+      if (d == 0 || val < phi) { phi = val; dsel = d; }
+    }
+    osel = osl[dsel];
+    live = lv[dsel];
+    const double phib = a[A_PHB * LE];
+    if (live && phib != 0.0) {
+      const S* p = pd[dsel];
+      const int o = osel;
+      const S dp1 = p[o + 4] - p[o + 2];
+      const S dp2 = p[o + 5] - p[o + 1];
+      const S a2 = sabs(dp2);
+      const bool use2 = !(a2 < G.small_pres);
+      const S D = smax(a2, G.small_pres);
+      const S zeta = sabs(dp1) / D;
+      const S zetab = -phib * TEN;  // phi = 1 - chi, chi = zz, zz = 10 (zeta - 0.75)
+      const S dp1b = zetab * ((dp1 < S(0)) ? -ONE : ONE) / D;
+      const S Db = -zetab * zeta / D;
+      const S dp2b = use2 ? Db * ((dp2 < S(0)) ? -ONE : ONE) : S(0);
+      // offsets relative to the zone: p index k <-> offset k - 3
+      gf[o + 4] += dp1b;
+      gf[o + 2] -= dp1b;
+      gf[o + 5] += dp2b;
+      gf[o + 1] -= dp2b;
+      sel = dsel;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) a[(A_GF + k) * LE] = gf[k];
+  a[A_SEL * LE] = (double)sel;
+}
+
+__global__ void __launch_bounds__(TILE) k_adj_gather_flatten(const Tile* __restrict__ tilesS, int ntiles,
+                                                             const DevBox* __restrict__ boxes,
+                                                             const double* __restrict__ aw, long long LE,
+                                                             double* __restrict__ as, long long LS) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tilesS[tt];
+  const DevBox B = boxes[tl.box];
+  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+  const long long tot = (long long)NS[0] * NS[1] * NS[2];
+  const long long idx = (long long)tl.start + threadIdx.x;
+  if (idx >= tot) return;
+  int j[3];
+  j[0] = (int)(idx % NS[0]) - NG;
+  j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
+  j[2] = (int)(idx / ((long long)NS[0] * NS[1])) - NG;
+  double acc = 0.0;
+  for (int d = 0; d < 3; ++d)
+    for (int o = -3; o <= 3; ++o) {
+      int y[3] = {j[0], j[1], j[2]};
+      y[d] -= o;
+      if (!in_e(y, B)) continue;
+      const long long e = B.eoff + eidx(B, y[0], y[1], y[2]);
+      if (aw[A_SEL * LE + e] == (double)d) acc += aw[(A_GF + o + 3) * LE + e];
+    }
+  as[(AS_QB + 4) * LS + B.poff + idx] += acc;
+}
+
+// Primitive adjoints -> conserved adjoints on every stored zone.
+__global__ void __launch_bounds__(TILE) k_adj_prim(const Tile* __restrict__ tilesS, int ntiles,
+                                                   const DevBox* __restrict__ boxes, const double* __restrict__ U,
+                                                   double* __restrict__ as, long long LS, Gas<double> G) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tilesS[tt];
+  const DevBox B = boxes[tl.box];
+  const long long NS = (long long)(B.n[0] + 2 * NG) * (B.n[1] + 2 * NG) * (B.n[2] + 2 * NG);
+  const long long idx = (long long)tl.start + threadIdx.x;
+  if (idx >= NS) return;
+  double uc[5], qb[6], ub[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) uc[c] = U[B.soff + idx + c * NS];
+  const double* q = as + AS_QB * LS + B.poff + idx;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) qb[m] = q[m * LS];
+  prim_cell_vjp(uc, G, qb, ub);
+  double* u = as + AS_UB * LS + B.poff + idx;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) u[c * LS] += ub[c];
+}
+
+// Transpose of the ghost fill: every valid zone of a source box sums the
+// adjoints of the ghost zones that copied it (signs of reflections applied),
+// in the fixed order of the plan; writes the result to Ub (valid zones).
+__global__ void __launch_bounds__(TILE) k_adj_fill(const Tile* __restrict__ tiles, int ntiles,
+                                                   const DevBox* __restrict__ boxes,
+                                                   const FillDesc* __restrict__ desc,
+                                                   const int* __restrict__ inv_start, const int* __restrict__ inv_idx,
+                                                   const double* __restrict__ as, long long LS,
+                                                   double* __restrict__ Ub) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[0] < 0 || z.x[0] >= B.n[0] || z.x[1] < 0 || z.x[1] >= B.n[1] || z.x[2] < 0 || z.x[2] >= B.n[2]) return;
+  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
+  const long long NS = (long long)N0 * N1 * N2;
+  const long long li = ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
+  double acc[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) acc[c] = as[(AS_UB + c) * LS + B.poff + li];
+  for (int k = inv_start[tl.box]; k < inv_start[tl.box + 1]; ++k) {
+    const FillDesc D = desc[inv_idx[k]];
+    int lo[3], hi[3];
+    bool hit = true;
+    for (int d = 0; d < 3 && hit; ++d) {
+      const int y = z.x[d];
+      if (D.a[d] == 1) { lo[d] = hi[d] = y - D.c[d]; }
+      else if (D.a[d] == -1) { lo[d] = hi[d] = D.c[d] - y; }
+      else { if (y != D.c[d]) hit = false; lo[d] = D.lo[d]; hi[d] = D.hi[d]; }
+      if (hit && (lo[d] < D.lo[d] || hi[d] > D.hi[d])) hit = false;
+    }
+    if (!hit) continue;
+    const DevBox Bd = boxes[D.dst];
+    const int M0 = Bd.n[0] + 2 * NG, M1 = Bd.n[1] + 2 * NG;
+    for (int x2 = lo[2]; x2 <= hi[2]; ++x2)
+      for (int x1 = lo[1]; x1 <= hi[1]; ++x1)
+        for (int x0 = lo[0]; x0 <= hi[0]; ++x0) {
+          const long long gi = Bd.poff + ((long long)(x2 + NG) * M1 + (x1 + NG)) * M0 + (x0 + NG);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            const double v = as[(AS_UB + c) * LS + gi];
+            const bool neg = c >= 1 && c <= 3 && ((D.sign >> (c - 1)) & 1);
+            acc[c] += neg ? -v : v;
+          }
+        }
+  }
+#pragma unroll
+  for (int c = 0; c < 5; ++c) Ub[B.soff + li + c * NS] = acc[c];
+}
+
+}  // namespace
+
+size_t adjoint_workspace_doubles(long long LS, long long LE) {
+  return (size_t)(A_SPLANES * LS + A_EPLANES * LE);
+}
+
+hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
+                          const void* work, void* awork, double gamma, double small_dens, double small_pres,
+                          int limiter, int flattening, int iters, int grav, const double g[3], long long ULEN,
+                          hipStream_t s) {
+  const double* w = (const double*)work;
+  const double* prim = w;
+  const double* ework = w + P_PLANES * L.LS;
+  double* as = (double*)awork;
+  double* aw = as + A_SPLANES * L.LS;
+  Gas<double> G;
+  G.gamma = gamma;
+  G.gm1 = gamma - 1.0;
+  G.gm1inv = 1.0 / (gamma - 1.0);
+  G.beta = (gamma + 1.0) / (2.0 * gamma);
+  G.small_dens = small_dens;
+  G.small_pres = small_pres;
+  G.limiter = limiter;
+  G.flattening = flattening && limiter;
+  G.iters = iters;
+  G.grav = grav;
+  const dim3 blk(TILE);
+  const unsigned zg = 4096;
+  // zero: all stored-grid planes, and the traced-grid planes that are
+  // accumulated or read where not written
+  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, as, (long long)A_SPLANES * L.LS);
+  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, aw + A_TB * L.LE, (long long)(30 + 30 + 60) * L.LE);
+  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, aw + A_PHB * L.LE, (long long)L.LE);
+  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, Ub, ULEN);
+  const int gE = xcd_grid(nE), gS = xcd_grid(nS);
+  hipLaunchKernelGGL(k_adj_update, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS, L.consts,
+                     grav, g[0], g[1], g[2]);
+  hipLaunchKernelGGL(k_adj_r3, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r2, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts, 0);
+  hipLaunchKernelGGL(k_adj_r2, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts, 1);
+  hipLaunchKernelGGL(k_adj_r1, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_trace<0>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
+                     L.consts);
+  hipLaunchKernelGGL(k_adj_gather_trace<0>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
+  hipLaunchKernelGGL(k_adj_trace<1>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
+                     L.consts);
+  hipLaunchKernelGGL(k_adj_gather_trace<1>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
+  hipLaunchKernelGGL(k_adj_trace<2>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
+                     L.consts);
+  hipLaunchKernelGGL(k_adj_gather_trace<2>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
+  hipLaunchKernelGGL(k_adj_flatten, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
+  hipLaunchKernelGGL(k_adj_gather_flatten, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
+  hipLaunchKernelGGL(k_adj_prim, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, U, as, L.LS, G);
+  hipLaunchKernelGGL(k_adj_fill, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, L.desc, L.inv_start, L.inv_idx, as,
+                     L.LS, Ub);
+  return hipGetLastError();
+}
+
+}  // namespace ppm

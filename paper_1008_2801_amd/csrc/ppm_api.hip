@@ -304,6 +304,10 @@ struct ppm_ctx {
   Tile* d_tilesE = nullptr;
   FillDesc* d_desc = nullptr;
   long long* d_start = nullptr;
+  int* d_inv_start = nullptr;
+  int* d_inv_idx = nullptr;
+  void* awork = nullptr;
+  size_t awork_bytes = 0;
   StepConsts* d_consts = nullptr;
   int* d_flags = nullptr;
   void* work = nullptr;
@@ -341,6 +345,8 @@ struct ppm_ctx {
     L.desc_start = d_start;
     L.consts = d_consts;
     L.flags = d_flags;
+    L.inv_start = d_inv_start;
+    L.inv_idx = d_inv_idx;
     L.LS = LS;
     L.LE = LE;
     return L;
@@ -443,8 +449,19 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
   ctx->LS = round_up(ps, 64);
   ctx->LE = round_up(pe, 64);
 
+  // inverse of the fill plan: descriptors grouped by source box
+  std::vector<int> inv_start(nb + 1, 0), inv_idx;
+  for (const FillDesc& D : ctx->plan->desc) inv_start[D.src + 1]++;
+  for (int b = 0; b < nb; ++b) inv_start[b + 1] += inv_start[b];
+  inv_idx.assign(ctx->plan->desc.size(), 0);
+  {
+    std::vector<int> fillp(inv_start.begin(), inv_start.end() - 1);
+    for (size_t k = 0; k < ctx->plan->desc.size(); ++k) inv_idx[fillp[ctx->plan->desc[k].src]++] = (int)k;
+  }
   hipError_t e;
-  if ((e = upload(&ctx->d_boxes, db)) != hipSuccess ||
+  if ((e = upload(&ctx->d_inv_start, inv_start)) != hipSuccess ||
+      (e = upload(&ctx->d_inv_idx, inv_idx)) != hipSuccess ||
+      (e = upload(&ctx->d_boxes, db)) != hipSuccess ||
       (e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess ||
       (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess ||
       (e = upload(&ctx->d_desc, ctx->plan->desc)) != hipSuccess ||
@@ -473,6 +490,8 @@ int ppm_ctx_destroy(ppm_ctx* ctx) {
   (void)hipFree(ctx->d_start);
   (void)hipFree(ctx->d_consts);
   (void)hipFree(ctx->d_flags);
+  (void)hipFree(ctx->d_inv_start);
+  (void)hipFree(ctx->d_inv_idx);
   delete ctx;
   return PPM_OK;
 }
@@ -582,6 +601,57 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
     if (rc) return rc;
   }
   return PPM_OK;
+}
+
+size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx) {
+  if (!ctx) return 0;
+  return sizeof(double) * adjoint_workspace_doubles(ctx->LS, ctx->LE);
+}
+
+int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return PPM_EINVAL;
+  if (((uintptr_t)dev_ptr) % 256 != 0) return ctx->fail(PPM_EINVAL, "adjoint workspace must be 256-byte aligned");
+  ctx->awork = dev_ptr;
+  ctx->awork_bytes = dev_ptr ? bytes : 0;
+  return PPM_OK;
+}
+
+int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
+                           const double* dt_dev, const double dx[3], const ppm_params* params, void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  std::string m = validate_params(params);
+  if (m.empty()) m = validate_dx(dx);
+  if (m.empty() && (!U || !Unew_bar || !U_bar)) m = "adjoint: null pointer";
+  if (m.empty() && params->precision != 0) m = "adjoint: only the FP64 step (precision 0) has an adjoint";
+  if (m.empty() && !dt_dev && !(dt > 0.0 && std::isfinite(dt))) m = "adjoint: dt must be positive and finite";
+  const size_t alen = (size_t)ctx->off.back() * sizeof(double);
+  if (m.empty()) {
+    const char* a = (const char*)U_bar;
+    const char* b = (const char*)U;
+    const char* c = (const char*)Unew_bar;
+    if ((a < b + alen && b < a + alen) || (a < c + alen && c < a + alen)) m = "adjoint: U_bar overlaps an input";
+  }
+  if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, 0)))
+    m = "adjoint: workspace missing or too small (ppm_set_workspace)";
+  if (m.empty() && (!ctx->awork || ctx->awork_bytes < ppm_adjoint_workspace_bytes(ctx)))
+    m = "adjoint: adjoint workspace missing or too small (ppm_set_adjoint_workspace)";
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  hipStream_t s = (hipStream_t)stream;
+  const DevLevel L = ctx->level();
+  int rc = ctx->hip(launch_step_consts(L, dt, dt_dev, dx, params->grav, s), "adjoint consts");
+  if (rc) return rc;
+  const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
+  const int nS = (int)ctx->tilesS.size(), nE = (int)ctx->tilesE.size();
+  // recompute the forward intermediates through stage 2 (U is not written)
+  rc = ctx->hip(launch_step(L, 0, 0, nS, 0, nE, U, nullptr, nullptr, ctx->work, params->gamma, params->small_dens,
+                            params->small_pres, params->limiter, params->flattening, params->riemann_iters, grav,
+                            params->grav, s, nullptr, 5),
+                "adjoint recompute");
+  if (rc) return rc;
+  return ctx->hip(launch_adjoint(L, nS, nE, U, Unew_bar, U_bar, ctx->work, ctx->awork, params->gamma,
+                                 params->small_dens, params->small_pres, params->limiter, params->flattening,
+                                 params->riemann_iters, grav, params->grav, (long long)ctx->off.back(), s),
+                  "adjoint");
 }
 
 int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], const ppm_params* params,

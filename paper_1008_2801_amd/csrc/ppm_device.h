@@ -1,0 +1,73 @@
+// Device-side helpers shared by the forward and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ppm_internal.h"
+
+namespace ppm {
+
+template <class S> struct SC;
+template <> struct SC<double> {
+  __device__ static const double* dtdx(const StepConsts* c) { return c->d_dtdx; }
+  __device__ static const double* dt2h(const StepConsts* c) { return c->d_dt2h; }
+  __device__ static const double* dt3h(const StepConsts* c) { return c->d_dt3h; }
+  __device__ static const double* hdtg(const StepConsts* c) { return c->d_hdtg; }
+};
+template <> struct SC<float> {
+  __device__ static const float* dtdx(const StepConsts* c) { return c->f_dtdx; }
+  __device__ static const float* dt2h(const StepConsts* c) { return c->f_dt2h; }
+  __device__ static const float* dt3h(const StepConsts* c) { return c->f_dt3h; }
+  __device__ static const float* hdtg(const StepConsts* c) { return c->f_hdtg; }
+};
+
+// Tile index of this workgroup.  Consecutive workgroups are dealt round-robin
+// to the 8 XCDs; remapping gives each XCD a contiguous run of tiles so that
+// the stencil neighbours of a tile sit in the same XCD's L2.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int per = (ntiles + NXCD - 1) / NXCD;
+  const int b = blockIdx.x;
+  const int t = (b % NXCD) * per + b / NXCD;
+  return (t < ntiles) ? t : -1;
+}
+__host__ inline int xcd_grid(int ntiles) { return ((ntiles + NXCD - 1) / NXCD) * NXCD; }
+
+__device__ __forceinline__ void raise_flags(int* flags, int fl) {
+  if (fl) atomicOr(flags, fl);
+}
+
+// Zone geometry of a tile lane on the traced grid of a box: E = n + 2 per
+// axis, slot s <-> zone s - 1.
+struct EZone {
+  int x[3];     // zone coordinates, -1..n
+  int E[3];
+  long long e;  // linear index in the box's traced grid
+};
+
+__device__ __forceinline__ bool ezone(const Tile& tl, const DevBox& B, EZone& z) {
+  z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
+  const long long tot = (long long)z.E[0] * z.E[1] * z.E[2];
+  const long long idx = (long long)tl.start + threadIdx.x;
+  if (idx >= tot) return false;
+  z.e = idx;
+  const int i = (int)(idx % z.E[0]);
+  const long long r = idx / z.E[0];
+  z.x[0] = i - 1;
+  z.x[1] = (int)(r % z.E[1]) - 1;
+  z.x[2] = (int)(r / z.E[1]) - 1;
+  return true;
+}
+
+// Linear stride along axis d of a grid with extents E.
+__device__ __forceinline__ long long stride(const int E[3], int d) {
+  return d == 0 ? 1 : (d == 1 ? (long long)E[0] : (long long)E[0] * E[1]);
+}
+
+// Primitive-plane index of zone (x, y, z) of box B (stored grid).
+__device__ __forceinline__ long long pidx(const DevBox& B, int x, int y, int z) {
+  return B.poff + ((long long)(z + NG) * (B.n[1] + 2 * NG) + (y + NG)) * (B.n[0] + 2 * NG) + (x + NG);
+}
+
+__host__ __device__ constexpr int pair_index(int d, int t) { return 2 * d + (t > d ? t - 1 : t); }
+
+}  // namespace ppm

@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "ppm.h"
+#include "ppm_math.h"
 
 namespace ppm {
 
@@ -48,13 +49,6 @@ struct StepConsts {
   float f_dtdx[3], f_dt2h[3], f_dt3h[3], f_hdtg[3];
 };
 
-// Gas and scheme constants in the reconstruction scalar, formed on the host
-// in FP64 from gamma and the floors, rounded once to S.
-template <class S> struct Gas {
-  S gamma, gm1, gm1inv, beta, small_dens, small_pres;
-  int limiter, flattening, iters, grav;
-};
-
 // Number of planes in the traced-grid (E) arena: flattening 1, traces 30,
 // stage-1 fluxes 15, stage-2 fluxes 30, final fluxes 15.
 constexpr int E_FLAT = 0;
@@ -74,6 +68,8 @@ struct DevLevel {
   const long long* desc_start;  // exclusive prefix of zone counts, ndesc+1
   StepConsts* consts;
   int* flags;
+  const int* inv_start;  // nbox + 1: descriptors whose source is each box
+  const int* inv_idx;
   long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
 };
 
@@ -93,7 +89,14 @@ hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int t
                        const double* U, double* Unew, double* const* flux, void* work,
                        const double gamma, const double small_dens, const double small_pres,
                        int limiter, int flattening, int iters, int grav, const double g[3],
-                       hipStream_t s, hipEvent_t* ev);
+                       hipStream_t s, hipEvent_t* ev, int nstages = 7);
+// Adjoint of one FP64 step (ppm_adjoint.hip); the forward workspace must hold
+// the recomputed prim..riemann2 intermediates of the same step.
+size_t adjoint_workspace_doubles(long long LS, long long LE);
+hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
+                          const void* work, void* awork, double gamma, double small_dens, double small_pres,
+                          int limiter, int flattening, int iters, int grav, const double g[3], long long ULEN,
+                          hipStream_t s);
 // Events recorded by launch_step when ev is non-null: before each of the 7
 // stage kernels and after the last (STEP_EVENTS in all).
 constexpr int STEP_EVENTS = 8;

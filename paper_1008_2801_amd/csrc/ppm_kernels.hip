@@ -19,340 +19,12 @@
 // the same definition to the last bit.
 #include <hip/hip_runtime.h>
 
+#include "ppm_device.h"
 #include "ppm_internal.h"
+#include "ppm_math.h"
 
 namespace ppm {
 namespace {
-
-// ------------------------------------------------------------ helpers ------
-template <class S> __device__ __forceinline__ S smax(S a, S b) { return (a < b) ? b : a; }
-template <class S> __device__ __forceinline__ S smin(S a, S b) { return (b < a) ? b : a; }
-template <class S> __device__ __forceinline__ S sabs(S a) { return (a < S(0)) ? -a : a; }
-__device__ __forceinline__ double ssqrt(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float ssqrt(float x) { return __builtin_sqrtf(x); }
-template <class S> __device__ __forceinline__ S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
-
-#define HALF S(0.5)
-#define ONE S(1.0)
-#define TWO S(2.0)
-#define THREE S(3.0)
-#define SIX S(6.0)
-#define SIXTH S(1.0 / 6.0)
-#define TWO3 S(2.0 / 3.0)
-#define C033 S(0.33)
-#define TEN S(10.0)
-#define C075 S(0.75)
-
-template <class S> struct SC;
-template <> struct SC<double> {
-  __device__ static const double* dtdx(const StepConsts* c) { return c->d_dtdx; }
-  __device__ static const double* dt2h(const StepConsts* c) { return c->d_dt2h; }
-  __device__ static const double* dt3h(const StepConsts* c) { return c->d_dt3h; }
-  __device__ static const double* hdtg(const StepConsts* c) { return c->d_hdtg; }
-};
-template <> struct SC<float> {
-  __device__ static const float* dtdx(const StepConsts* c) { return c->f_dtdx; }
-  __device__ static const float* dt2h(const StepConsts* c) { return c->f_dt2h; }
-  __device__ static const float* dt3h(const StepConsts* c) { return c->f_dt3h; }
-  __device__ static const float* hdtg(const StepConsts* c) { return c->f_hdtg; }
-};
-
-// Tile index of this workgroup.  Consecutive workgroups are dealt round-robin
-// to the 8 XCDs; remapping gives each XCD a contiguous run of tiles so that
-// the stencil neighbours of a tile sit in the same XCD's L2.
-__device__ __forceinline__ int xcd_tile(int ntiles) {
-  const int per = (ntiles + NXCD - 1) / NXCD;
-  const int b = blockIdx.x;
-  const int t = (b % NXCD) * per + b / NXCD;
-  return (t < ntiles) ? t : -1;
-}
-__host__ inline int xcd_grid(int ntiles) { return ((ntiles + NXCD - 1) / NXCD) * NXCD; }
-
-__device__ __forceinline__ void raise_flags(int* flags, int fl) {
-  if (fl) atomicOr(flags, fl);
-}
-
-// ------------------------------------------------------- O6: Riemann -------
-// Fan sampling on the left side of the contact for (rho, u, p) with the
-// normal velocity oriented so that the side is the left one.  The right
-// side is the mirror image: the caller negates u, u* on entry and u on exit
-// (exact in IEEE arithmetic).
-template <class S>
-__device__ __forceinline__ void sample_side(S ro, S uo, S po, S C, S W, S iW, S us, S p, const Gas<S>& G,
-                                            S& r_, S& u_, S& p_, int& fl) {
-  const S irho = ONE / ro;
-  const S vstar = irho - (p - po) * (iW * iW);
-  S rs = ONE / vstar;
-  if (!(vstar > S(0)) || rs < G.small_dens) { fl |= PPM_FLAG_FLOOR; rs = G.small_dens; }
-  const S cst = ssqrt(G.gamma * p / rs);
-  const S co = C * irho;
-  r_ = ro; u_ = uo; p_ = po;
-  if (p > po) {
-    const S sh = uo - W * irho;
-    if (!(sh >= S(0))) { r_ = rs; u_ = us; p_ = p; }
-  } else {
-    const S hd = uo - co, tl = us - cst;
-    if (hd >= S(0)) {
-    } else if (tl <= S(0)) {
-      r_ = rs; u_ = us; p_ = p;
-    } else {
-      const S w = -hd / (tl - hd);
-      r_ = (ONE - w) * ro + w * rs;
-      u_ = (ONE - w) * uo + w * us;
-      p_ = (ONE - w) * po + w * p;
-    }
-  }
-}
-
-// Two-shock Riemann solver: flux F (xyz component order) at a face normal
-// to d from primitive states L and R (rho, u, v, w, p).
-template <int d, class S>
-__device__ __forceinline__ void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl) {
-  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-  const S rl = L[0], ul = L[1 + d], pl = L[4];
-  const S rr = R[0], ur = R[1 + d], pr = R[4];
-  const S cl = ssqrt(G.gamma * pl * rl);
-  const S cr = ssqrt(G.gamma * pr * rr);
-  S p = ((cr * pl + cl * pr) + (cl * cr) * (ul - ur)) / (cl + cr);
-  if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
-  p = smax(p, G.small_pres);
-  const S ipl = ONE / pl, ipr = ONE / pr;
-  for (int it = 0; it < G.iters; ++it) {
-    const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
-    const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-    const S iwl = ONE / wl, iwr = ONE / wr;
-    const S xl = cl * iwl, xr = cr * iwr;
-    const S izl = HALF * iwl * (ONE + xl * xl);
-    const S izr = HALF * iwr * (ONE + xr * xr);
-    const S usl = ul - (p - pl) * iwl;
-    const S usr = ur + (p - pr) * iwr;
-    p = p - (usr - usl) / (izl + izr);
-    if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
-    p = smax(p, G.small_pres);
-  }
-  const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
-  const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-  const S iwl = ONE / wl, iwr = ONE / wr;
-  const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
-
-  S g0, g1, g2, g3, g4;
-  if (us != S(0)) {
-    const bool left = us > S(0);
-    const S ro = left ? rl : rr;
-    const S uo = left ? ul : -ur;
-    const S po = left ? pl : pr;
-    const S C = left ? cl : cr;
-    const S W = left ? wl : wr;
-    const S iW = left ? iwl : iwr;
-    const S uss = left ? us : -us;
-    S r_, u_, p_;
-    sample_side(ro, uo, po, C, W, iW, uss, p, G, r_, u_, p_, fl);
-    g0 = r_;
-    g1 = left ? u_ : -u_;
-    g2 = p_;
-    g3 = left ? L[1 + t1] : R[1 + t1];
-    g4 = left ? L[1 + t2] : R[1 + t2];
-  } else {  // u* == 0: both sides averaged
-    S ra, ua, pa, rb, ub, pb;
-    sample_side(rl, ul, pl, cl, wl, iwl, us, p, G, ra, ua, pa, fl);
-    sample_side(rr, -ur, pr, cr, wr, iwr, -us, p, G, rb, ub, pb, fl);
-    ub = -ub;
-    g0 = HALF * (ra + rb);
-    g1 = HALF * (ua + ub);
-    g2 = HALF * (pa + pb);
-    g3 = HALF * (L[1 + t1] + R[1 + t1]);
-    g4 = HALF * (L[1 + t2] + R[1 + t2]);
-  }
-  const S m = g0 * g1;
-  const S e = g2 * G.gm1inv + HALF * g0 * ((g1 * g1 + g3 * g3) + g4 * g4);
-  F[0] = m;
-  F[1 + d] = m * g1 + g2;
-  F[1 + t1] = m * g3;
-  F[1 + t2] = m * g4;
-  F[4] = g1 * (e + g2);
-}
-
-// ------------------------------------------------------------ O4: PPM ------
-template <class S>
-__device__ __forceinline__ S ppm_slope(S am, S a0, S ap, int limiter) {
-  const S dc = HALF * (ap - am);
-  if (!limiter) return dc;
-  const S dl = a0 - am, dr = ap - a0;
-  if (dl * dr > S(0)) return scopysign(smin(smin(sabs(dc), TWO * sabs(dl)), TWO * sabs(dr)), dc);
-  return S(0);
-}
-
-template <class S>
-__device__ __forceinline__ void ppm_parabola(S am2, S am1, S a0, S ap1, S ap2, S phi, const Gas<S>& G,
-                                             S& aL, S& aR, S& a6) {
-  const S sm = ppm_slope(am2, am1, a0, G.limiter);
-  const S s0 = ppm_slope(am1, a0, ap1, G.limiter);
-  const S sp = ppm_slope(a0, ap1, ap2, G.limiter);
-  aL = HALF * (am1 + a0) - (s0 - sm) * SIXTH;
-  aR = HALF * (a0 + ap1) - (sp - s0) * SIXTH;
-  if (G.limiter) {
-    if (G.flattening) {
-      const S omp = ONE - phi;
-      aL = phi * aL + omp * a0;
-      aR = phi * aR + omp * a0;
-    }
-    if ((aR - a0) * (a0 - aL) <= S(0)) {
-      aL = a0;
-      aR = a0;
-    } else {
-      const S dq = aR - aL;
-      const S t = dq * (a0 - HALF * (aL + aR));
-      const S d2 = dq * dq * SIXTH;
-      if (t > d2) {
-        aL = THREE * a0 - TWO * aR;
-      } else if (-d2 > t) {
-        aR = THREE * a0 - TWO * aL;
-      }
-    }
-  }
-  a6 = SIX * a0 - THREE * (aL + aR);
-}
-
-template <class S> __device__ __forceinline__ S ppm_ip(S aR, S da, S a6, S sg) {
-  return aR - HALF * sg * (da - (ONE - TWO3 * sg) * a6);
-}
-template <class S> __device__ __forceinline__ S ppm_im(S aL, S da, S a6, S sg) {
-  return aL + HALF * sg * (da + (ONE - TWO3 * sg) * a6);
-}
-
-// ---------------------------------------------------------- O5: tracing ----
-template <class S>
-__device__ __forceinline__ void trace_edge(const S ref[5], S a1, S a2, S a3, S at1, S at2, S cor, S c2,
-                                           int mn, int m1, int m2, const Gas<S>& G, const S* hdtg,
-                                           S q[5], int& fl) {
-  q[0] = ref[0] - ((a1 + a3) + a2);
-  q[mn] = ref[mn] + cor * (a1 - a3);
-  q[4] = ref[4] - c2 * (a1 + a3);
-  q[m1] = ref[m1] - at1;
-  q[m2] = ref[m2] - at2;
-  if (G.grav) {
-    q[1] = q[1] + hdtg[0];
-    q[2] = q[2] + hdtg[1];
-    q[3] = q[3] + hdtg[2];
-  }
-  if (q[0] < G.small_dens) fl |= PPM_FLAG_FLOOR;
-  if (q[4] < G.small_pres) fl |= PPM_FLAG_FLOOR;
-  q[0] = smax(q[0], G.small_dens);
-  q[4] = smax(q[4], G.small_pres);
-}
-
-template <int d, class S>
-__device__ __forceinline__ void trace_zone(const S aL[5], const S aR[5], const S a6[5], S r, S un, S c,
-                                           S dtdx, const Gas<S>& G, const S* hdtg, S qp[5],
-                                           S qm[5], int& fl) {
-  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-  constexpr int mn = 1 + d, m1 = 1 + t1, m2 = 1 + t2;
-  S da[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) da[m] = aR[m] - aL[m];
-  const S rc = r * c, c2 = c * c, ic2 = ONE / c2, hic2 = HALF * ic2, cor = c / r;
-  const S l1 = un - c, l2 = un, l3 = un + c;
-  const S zero = S(0);
-  {
-    const S s1 = smax(l1, zero) * dtdx, s2 = smax(l2, zero) * dtdx, s3 = smax(l3, zero) * dtdx;
-    S ref[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) ref[m] = ppm_ip(aR[m], da[m], a6[m], s3);
-    S a1 = zero, a2 = zero, a3 = zero, at1 = zero, at2 = zero;
-    if (l1 > zero) {
-      const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], s1);
-      const S du = ref[mn] - ppm_ip(aR[mn], da[mn], a6[mn], s1);
-      a1 = (dp - rc * du) * hic2;
-    }
-    if (l2 > zero) {
-      const S dr = ref[0] - ppm_ip(aR[0], da[0], a6[0], s2);
-      const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], s2);
-      a2 = dr - dp * ic2;
-      at1 = ref[m1] - ppm_ip(aR[m1], da[m1], a6[m1], s2);
-      at2 = ref[m2] - ppm_ip(aR[m2], da[m2], a6[m2], s2);
-    }
-    if (l3 > zero) {
-      const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], s3);
-      const S du = ref[mn] - ppm_ip(aR[mn], da[mn], a6[mn], s3);
-      a3 = (dp + rc * du) * hic2;
-    }
-    trace_edge(ref, a1, a2, a3, at1, at2, cor, c2, mn, m1, m2, G, hdtg, qp, fl);
-  }
-  {
-    const S s1 = smax(-l1, zero) * dtdx, s2 = smax(-l2, zero) * dtdx, s3 = smax(-l3, zero) * dtdx;
-    S ref[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) ref[m] = ppm_im(aL[m], da[m], a6[m], s1);
-    S a1 = zero, a2 = zero, a3 = zero, at1 = zero, at2 = zero;
-    if (l1 < zero) {
-      const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], s1);
-      const S du = ref[mn] - ppm_im(aL[mn], da[mn], a6[mn], s1);
-      a1 = (dp - rc * du) * hic2;
-    }
-    if (l2 < zero) {
-      const S dr = ref[0] - ppm_im(aL[0], da[0], a6[0], s2);
-      const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], s2);
-      a2 = dr - dp * ic2;
-      at1 = ref[m1] - ppm_im(aL[m1], da[m1], a6[m1], s2);
-      at2 = ref[m2] - ppm_im(aL[m2], da[m2], a6[m2], s2);
-    }
-    if (l3 < zero) {
-      const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], s3);
-      const S du = ref[mn] - ppm_im(aL[mn], da[mn], a6[mn], s3);
-      a3 = (dp + rc * du) * hic2;
-    }
-    trace_edge(ref, a1, a2, a3, at1, at2, cor, c2, mn, m1, m2, G, hdtg, qm, fl);
-  }
-}
-
-// ------------------------------------------------ conversions (O2, O8) -----
-template <class S>
-__device__ __forceinline__ void prim_to_cons(const S q[5], const Gas<S>& G, S U[5]) {
-  U[0] = q[0];
-  U[1] = q[0] * q[1];
-  U[2] = q[0] * q[2];
-  U[3] = q[0] * q[3];
-  U[4] = q[4] * G.gm1inv + HALF * q[0] * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
-}
-
-template <class S>
-__device__ __forceinline__ void cons_to_prim_floor(const S U[5], const Gas<S>& G, S q[5], int& fl) {
-  if (U[0] < G.small_dens) fl |= PPM_FLAG_FLOOR;
-  const S r = smax(U[0], G.small_dens);
-  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
-  const S ke = HALF * r * ((u * u + v * v) + w * w);
-  S p = G.gm1 * (U[4] - ke);
-  if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
-  p = smax(p, G.small_pres);
-  q[0] = r; q[1] = u; q[2] = v; q[3] = w; q[4] = p;
-}
-
-// Zone geometry of a tile lane on the traced grid of a box: E = n + 2 per
-// axis, slot s <-> zone s - 1.
-struct EZone {
-  int x[3];     // zone coordinates, -1..n
-  int E[3];
-  long long e;  // linear index in the box's traced grid
-};
-
-__device__ __forceinline__ bool ezone(const Tile& tl, const DevBox& B, EZone& z) {
-  z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
-  const long long tot = (long long)z.E[0] * z.E[1] * z.E[2];
-  const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= tot) return false;
-  z.e = idx;
-  const int i = (int)(idx % z.E[0]);
-  const long long r = idx / z.E[0];
-  z.x[0] = i - 1;
-  z.x[1] = (int)(r % z.E[1]) - 1;
-  z.x[2] = (int)(r / z.E[1]) - 1;
-  return true;
-}
-
-// Linear stride along axis d of a grid with extents E.
-__device__ __forceinline__ long long stride(const int E[3], int d) {
-  return d == 0 ? 1 : (d == 1 ? (long long)E[0] : (long long)E[0] * E[1]);
-}
 
 // ------------------------------------------------------------- kernels -----
 __global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, const double* dt_dev,
@@ -414,10 +86,6 @@ __global__ void __launch_bounds__(TILE) k_prim(const Tile* __restrict__ tiles, i
   raise_flags(flags, fl);
 }
 
-// Primitive-plane index of zone x of box B (stored grid).
-__device__ __forceinline__ long long pidx(const DevBox& B, int x, int y, int z) {
-  return B.poff + ((long long)(z + NG) * (B.n[1] + 2 * NG) + (y + NG)) * (B.n[0] + 2 * NG) + (x + NG);
-}
 
 // O3 on the traced zones.
 template <class S>
@@ -554,7 +222,6 @@ __global__ void __launch_bounds__(TILE) k_riemann1(const Tile* __restrict__ tile
   }
 }
 
-__host__ __device__ constexpr int pair_index(int d, int t) { return 2 * d + (t > d ? t - 1 : t); }
 
 // O8: for the pair (d, t) = blockIdx.y: states of axis d corrected by the
 // stage-1 t-flux difference (dt/3h_t), then F^{d|t} at d-face slots x_d in
@@ -858,7 +525,7 @@ Gas<S> make_gas(double gamma, double small_dens, double small_pres, int limiter,
 template <class S>
 hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, const double* U, double* Unew,
                      double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
-                     hipEvent_t* ev) {
+                     hipEvent_t* ev, int nstages) {
   S* prim = (S*)work;
   S* ework = prim + P_PLANES * L.LS;
   const int nS = tS1 - tS0, nE = tE1 - tE0;
@@ -879,6 +546,7 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, cons
   if (ev) (void)hipEventRecord(ev[4], s);
   hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 6), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
                      L.consts, L.flags);
+  if (nstages <= 5) return hipGetLastError();
   double* fx = flux ? flux[0] : nullptr;
   double* fy = flux ? flux[1] : nullptr;
   double* fz = flux ? flux[2] : nullptr;
@@ -927,14 +595,14 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, const double* U,
                        double* Unew, double* const* flux, void* work, const double gamma,
                        const double small_dens, const double small_pres, int limiter, int flattening,
-                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev) {
+                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev, int nstages) {
   if (precision == 1)
     return step_impl<float>(L, tS0, tS1, tE0, tE1, U, Unew, flux, work,
                             make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
-                            g, s, ev);
+                            g, s, ev, nstages);
   return step_impl<double>(L, tS0, tS1, tE0, tE1, U, Unew, flux, work,
                            make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
-                           g, s, ev);
+                           g, s, ev, nstages);
 }
 
 }  // namespace ppm

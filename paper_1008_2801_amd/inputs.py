@@ -230,17 +230,20 @@ def cfg3(seed=3, sizes=(16, 24, 32, 48, 64), nper=8, h=1.0 / 256):
     return Workload("cfg3", lay, _fill_state(lay, hh, 1.4, prim), hh, 1.4, 20)
 
 
-def cfg4(n=128, seed=4, amp=0.05):
-    """rho = 1 + amp S_rho, p = 1 + amp S_p, u_d = amp S_d (8 modes each,
-    |k| <= 4); gamma 1.4, periodic.  RNG draws: modes of rho, p, u, v, w."""
+def cfg4(n=128, seed=4, amp=0.05, bulk=(0.0, 0.0, 0.0)):
+    """rho = 1 + amp S_rho, p = 1 + amp S_p, u_d = bulk_d + amp S_d (8 modes
+    each, |k| <= 4); gamma 1.4, periodic.  RNG draws: modes of rho, p, u, v, w.
+    A bulk velocity keeps every characteristic speed away from zero (the
+    tracing and the Riemann fan sampling switch branches where a speed
+    changes sign, which finite differences straddle)."""
     rng = np.random.default_rng(seed)
     lay = single_box(n)
     h = (1.0 / n,) * 3
     Sr, Sp, Su, Sv, Sw = [ModeSum(rng, 8, 4, (1.0, 1.0, 1.0)) for _ in range(5)]
 
     def prim(x, y, z):
-        return (1.0 + amp * Sr(x, y, z), amp * Su(x, y, z), amp * Sv(x, y, z), amp * Sw(x, y, z),
-                1.0 + amp * Sp(x, y, z))
+        return (1.0 + amp * Sr(x, y, z), bulk[0] + amp * Su(x, y, z), bulk[1] + amp * Sv(x, y, z),
+                bulk[2] + amp * Sw(x, y, z), 1.0 + amp * Sp(x, y, z))
     return Workload("cfg4", lay, _fill_state(lay, h, 1.4, prim), h, 1.4, 20)
 
 

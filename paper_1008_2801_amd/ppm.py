@@ -25,7 +25,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_flux_offsets", "ppm_workspace_bytes", "ppm_set_workspace", "ppm_fill_boundary",
            "ppm_compute_dt", "ppm_hydro_step", "ppm_graph_create", "ppm_graph_launch",
            "ppm_graph_destroy", "ppm_check_status", "ppm_plan_build", "ppm_fill_boundary_host",
-           "ppm_plan_cache_stats", "ppm_profile_enable", "ppm_profile_read")
+           "ppm_plan_cache_stats", "ppm_profile_enable", "ppm_profile_read",
+           "ppm_adjoint_workspace_bytes", "ppm_set_adjoint_workspace", "ppm_hydro_step_adjoint")
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
 
@@ -96,10 +97,15 @@ def lib():
         L.ppm_fill_boundary_host.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
         L.ppm_plan_cache_stats.argtypes = [_i64p, _i64p, _i32p]
         L.ppm_profile_enable.argtypes = [_vp, ctypes.c_int32]
+        L.ppm_adjoint_workspace_bytes.argtypes = [_vp]
+        L.ppm_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        L.ppm_set_adjoint_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
+                                             ctypes.POINTER(Params), _vp]
         L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
         for name in SYMBOLS:
             f = getattr(L, name)
-            if name not in ("ppm_last_error", "ppm_workspace_bytes"):
+            if name not in ("ppm_last_error", "ppm_workspace_bytes", "ppm_adjoint_workspace_bytes"):
                 f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -268,6 +274,26 @@ class Level:
         self._check(lib().ppm_profile_read(self.ctx, ms, cnt), "ppm_profile_read")
         return {PROF_TAGS[k]: (ms[k], cnt[k]) for k in range(n)}
 
+    def ensure_adjoint_workspace(self):
+        import torch
+        need = int(lib().ppm_adjoint_workspace_bytes(self.ctx))
+        if getattr(self, "_awork", None) is None or self._awork.numel() < need + 256:
+            self._awork = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self._awork.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(lib().ppm_set_adjoint_workspace(self.ctx, ctypes.c_void_p(aligned), need),
+                    "ppm_set_adjoint_workspace")
+
+    def hydro_step_adjoint(self, U, Unew_bar, U_bar, dx, p, dt=0.0, dt_dev=None, stream=None):
+        """U_bar = J^T Unew_bar for the step from U (ghosts filled), dt frozen."""
+        if self._work is None or self._work_prec != 0 or self._work.numel() < self.workspace_bytes(0):
+            self.ensure_workspace(0)
+        if getattr(self, "_awork", None) is None:
+            self.ensure_adjoint_workspace()
+        self._check(lib().ppm_hydro_step_adjoint(self.ctx, _ptr(U), _ptr(Unew_bar), _ptr(U_bar), float(dt),
+                                                 _ptr(dt_dev), _dp3(*dx), ctypes.byref(p), _stream(stream)),
+                    "ppm_hydro_step_adjoint")
+
     def check_status(self, stream=None):
         f = ctypes.c_int32(0)
         rc = lib().ppm_check_status(self.ctx, _stream(stream), ctypes.byref(f))
@@ -353,3 +379,98 @@ def hydro_step(boxes, U, dt, dx, gamma, bc=(0, 0, 0, 0, 0, 0), domain=None, flux
     F = lev.new_fluxes() if fluxes else None
     lev.hydro_step(Uf, Un, dx, p, dt=dt, fluxes=F)
     return Un, F
+
+
+def _autograd():
+    import torch
+
+    class HydroStep(torch.autograd.Function):
+        """One step U -> U' of a level as an autograd function (FP64).
+
+        Input: a state arena (valid zones used; ghosts ignored).  Output: the
+        new state arena with zero ghosts.  dt: a float or a device tensor
+        whose element 0 is dt; it is not differentiated (frozen).  The
+        backward applies the hand-written adjoint kernels."""
+
+        @staticmethod
+        def forward(ctx, U, level, dt, dx, p):
+            Uf = U.detach().clone()
+            level.fill_boundary(Uf)
+            Un = torch.zeros_like(Uf)
+            if torch.is_tensor(dt):
+                level.hydro_step(Uf, Un, dx, p, dt_dev=dt)
+            else:
+                level.hydro_step(Uf, Un, dx, p, dt=dt)
+            ctx.level, ctx.dt, ctx.dx, ctx.p = level, dt, dx, p
+            ctx.save_for_backward(Uf)
+            return Un
+
+        @staticmethod
+        def backward(ctx, g):
+            (Uf,) = ctx.saved_tensors
+            Ub = torch.empty_like(Uf)
+            lev = ctx.level
+            if torch.is_tensor(ctx.dt):
+                lev.hydro_step_adjoint(Uf, g.contiguous(), Ub, ctx.dx, ctx.p, dt_dev=ctx.dt)
+            else:
+                lev.hydro_step_adjoint(Uf, g.contiguous(), Ub, ctx.dx, ctx.p, dt=ctx.dt)
+            return Ub, None, None, None, None
+
+    class Rollout(torch.autograd.Function):
+        """nsteps steps with the CFL dt of each step computed in the forward
+        pass and frozen; the backward recomputes each segment of
+        `every` steps from its checkpoint and runs the step adjoints in
+        reverse (memory: the checkpoints plus one segment of states)."""
+
+        @staticmethod
+        def forward(ctx, U0, level, nsteps, dx, p, every, dts_in):
+            U = U0.detach().clone()
+            dts = torch.zeros(nsteps, 2, dtype=torch.float64, device=U.device) if dts_in is None else dts_in
+            ckpts = {}
+            V = torch.zeros_like(U)
+            for k in range(nsteps):
+                if k % every == 0:
+                    ckpts[k] = U.clone()
+                level.fill_boundary(U)
+                if dts_in is None:
+                    level.compute_dt(U, dx, p, out=dts[k])
+                level.hydro_step(U, V, dx, p, dt_dev=dts[k])
+                U, V = V, U
+            ctx.level, ctx.nsteps, ctx.dx, ctx.p, ctx.every = level, nsteps, dx, p, every
+            ctx.ckpts, ctx.dts = ckpts, dts
+            out = U.clone()
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            lev, n, every = ctx.level, ctx.nsteps, ctx.every
+            g = g.contiguous().clone()
+            Ub = torch.empty_like(g)
+            for s0 in reversed(range(0, n, every)):
+                s1 = min(n, s0 + every)
+                filled = []
+                U = ctx.ckpts[s0].clone()
+                for k in range(s0, s1):
+                    lev.fill_boundary(U)
+                    filled.append(U.clone())
+                    V = torch.zeros_like(U)
+                    lev.hydro_step(U, V, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
+                    U = V
+                for k in reversed(range(s0, s1)):
+                    lev.hydro_step_adjoint(filled[k - s0], g, Ub, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
+                    g, Ub = Ub, g
+            return g, None, None, None, None, None, None
+
+    return HydroStep, Rollout
+
+
+def hydro_step_autograd(U, level, dt, dx, p):
+    HydroStep, _ = _autograd()
+    return HydroStep.apply(U, level, dt, dx, p)
+
+
+def rollout(U0, level, nsteps, dx, p, checkpoint_every=5, dts=None):
+    """Differentiable roll-out of nsteps (dt per step from the CFL rule,
+    frozen; or the given (nsteps, 2) device tensor of [dt, s])."""
+    _, Rollout = _autograd()
+    return Rollout.apply(U0, level, nsteps, dx, p, checkpoint_every, dts)

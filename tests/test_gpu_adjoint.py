@@ -1,0 +1,242 @@
+"""GPU adjoint of the step (hand-written reverse kernels through the C ABI)
+against the oracle's exact forward-mode tangent: the dot-product identity
+<J^T w, v> = <w, J v> with dt and branch decisions frozen, central
+differences of the GPU forward for the smooth (unlimited) step, and the
+checkpointed roll-out gradient."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1008_2801_amd import inputs as I  # noqa: E402
+from paper_1008_2801_amd import ppm as P  # noqa: E402
+from tests.helpers import interior  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _valid_random(lay, rng):
+    a = np.zeros(lay.arena_len())
+    for b in range(lay.nbox):
+        v = lay.view(a, b)
+        interior(v)[:] = rng.normal(size=interior(v).shape)
+    return a
+
+
+def _dot_valid(lay, a, b):
+    return sum(float(np.sum(interior(lay.view(a, k)) * interior(lay.view(b, k)))) for k in range(lay.nbox))
+
+
+def oracle_jvp(wl, v, dt, **pk):
+    """J v of one step of the level (fill included) by the oracle's dual numbers."""
+    lay = wl.layout
+    p = O.params(gamma=wl.gamma, grav=wl.grav, **pk)
+    U = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    V = [lay.view(v, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, U)
+    O.fill(lay.boxes(), lay.domain(), lay.bc, V)
+    out = np.zeros(lay.arena_len())
+    for b in range(lay.nbox):
+        _, dU, _ = O.step_jvp(U[b], V[b], dt, wl.dx, p)
+        lay.view(out, b)[:] = dU
+    return out
+
+
+def gpu_vjp(wl, w, dt, allow_floor=False, **pk):
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, **pk)
+    U = torch.from_numpy(wl.arena).cuda()
+    lev.fill_boundary(U)
+    Ub = torch.full_like(U, float("nan"))
+    lev.hydro_step_adjoint(U, torch.from_numpy(w).cuda(), Ub, wl.dx, p, dt=dt)
+    out = Ub.cpu().numpy()
+    fl = lev.check_status()
+    assert fl == 0 or (allow_floor and fl == P.FLAG_FLOOR), fl
+    return out, lev
+
+
+def _dt(wl, frac=0.8, **pk):
+    lay = wl.layout
+    p = O.params(gamma=wl.gamma, **pk)
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    s = max(O.max_wavespeed(u, wl.dx, p)[0] for u in st)
+    return frac * p.cfl / s
+
+
+def _uneven(seed, bc=(0, 0, 0, 0, 0, 0)):
+    rng = np.random.default_rng(seed)
+    lay = I.tensor_tiling(rng.choice((6, 8, 10), 2), rng.choice((6, 8), 2), rng.choice((6, 9), 2), bc=bc)
+    L = tuple((np.array(lay.domain_hi) + 1) / 32.0)
+    S = [I.ModeSum(rng, 5, 3, L) for _ in range(5)]
+
+    def prim(x, y, z):
+        return (1.2 + 0.4 * S[0](x, y, z), 0.4 * S[1](x, y, z), 0.4 * S[2](x, y, z), 0.4 * S[3](x, y, z),
+                1.2 + 0.4 * S[4](x, y, z))
+    h = (1.0 / 32,) * 3
+    return I.Workload("uneven", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 1)
+
+
+CASES = {
+    "smooth_box": lambda: I.cfg4(10, amp=0.05),
+    "sod_box": lambda: I.cfg2(12),
+    "multibox": lambda: _uneven(3),
+    "walls_gravity": lambda: _uneven(4, bc=(0, 0, 0, 0, 2, 2)),
+    "outflow": lambda: _uneven(5, bc=(1, 1, 0, 0, 0, 0)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("opts", [dict(), dict(limiter=0), dict(riemann_iters=5)])
+def test_dot_product_identity_against_oracle_jvp(case, opts):
+    wl = CASES[case]()
+    if case == "walls_gravity":
+        wl.grav = (0.0, 0.0, -1.0)
+    lay = wl.layout
+    dt = _dt(wl, **opts)
+    rng = np.random.default_rng(17)
+    for _ in range(2):
+        v = _valid_random(lay, rng)
+        w = _valid_random(lay, rng)
+        jv = oracle_jvp(wl, v, dt, **opts)
+        # the unlimited scheme overshoots at the Sod jump and binds the
+        # pressure floor; both derivatives freeze the floor the same way
+        jtw, _ = gpu_vjp(wl, w, dt, allow_floor=(case == "sod_box"), **opts)
+        lhs = _dot_valid(lay, jtw, v)
+        rhs = _dot_valid(lay, w, jv)
+        assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+        for b in range(lay.nbox):  # ghost entries of the adjoint are zero
+            g = lay.view(jtw, b)
+            assert np.all(g[:, :4] == 0) and np.all(g[:, -4:] == 0)
+
+
+def test_vjp_matches_central_differences_of_gpu_forward():
+    """Unlimited step on a smooth state with a bulk flow (no characteristic
+    speed near zero, so no branch is crossed): <J^T w, v> against central
+    differences of the GPU forward, eps = 1e-6."""
+    wl = I.cfg4(12, amp=0.05, bulk=(0.3, 0.2, 0.25))
+    lay = wl.layout
+    dt = _dt(wl, limiter=0)
+    rng = np.random.default_rng(3)
+    v = _valid_random(lay, rng)
+    w = _valid_random(lay, rng)
+    jtw, lev = gpu_vjp(wl, w, dt, limiter=0)
+    p = P.params(gamma=wl.gamma, limiter=0)
+    eps = 1e-6
+
+    def fwd(a):
+        U = torch.from_numpy(a).cuda()
+        lev.fill_boundary(U)
+        V = torch.zeros_like(U)
+        lev.hydro_step(U, V, wl.dx, p, dt=dt)
+        return V.cpu().numpy()
+    fd = (_dot_valid(lay, w, fwd(wl.arena + eps * v)) - _dot_valid(lay, w, fwd(wl.arena - eps * v))) / (2 * eps)
+    ad = _dot_valid(lay, jtw, v)
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+
+
+def test_adjoint_is_deterministic():
+    wl = _uneven(6)
+    dt = _dt(wl)
+    w = _valid_random(wl.layout, np.random.default_rng(1))
+    a, _ = gpu_vjp(wl, w, dt)
+    b, _ = gpu_vjp(wl, w, dt)
+    assert np.array_equal(a, b)
+
+
+def _loss_and_grad(wl, nsteps, every, lo, hi, dts=None, **pk):
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, **pk)
+    U0 = torch.from_numpy(wl.arena).cuda().requires_grad_(True)
+    UT = P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=every, dts=dts)
+    rho = UT[: lay.box_size(0)].view(lay.stored_shape(0))[0]
+    sub = rho[4 + lo:4 + hi, 4 + lo:4 + hi, 4 + lo:4 + hi]
+    loss = (sub * sub).sum()
+    loss.backward()
+    return float(loss.item()), U0.grad.cpu().numpy(), lev
+
+
+def test_rollout_gradient_against_oracle_jvp_chain():
+    """loss = sum rho^2 over a sub-block after 4 steps (checkpoints every 2);
+    <grad, v> equals the oracle's forward-mode tangent chained through the
+    same frozen dt sequence."""
+    wl = I.cfg4(12, amp=0.05)
+    lay = wl.layout
+    nsteps, lo, hi = 4, 4, 8
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma)
+    dts = torch.zeros(nsteps, 2, dtype=torch.float64, device="cuda")
+    U0 = torch.from_numpy(wl.arena).cuda().requires_grad_(True)
+    UT = P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=2, dts=None)
+    rho = UT[: lay.box_size(0)].view(lay.stored_shape(0))[0]
+    loss = (rho[4 + lo:4 + hi, 4 + lo:4 + hi, 4 + lo:4 + hi] ** 2).sum()
+    loss.backward()
+    g = U0.grad.cpu().numpy()
+    # the dt sequence the forward used
+    U = torch.from_numpy(wl.arena).cuda()
+    V = torch.zeros_like(U)
+    dt_list = []
+    for k in range(nsteps):
+        lev.fill_boundary(U)
+        lev.compute_dt(U, wl.dx, p, out=dts[k])
+        dt_list.append(float(dts[k, 0].item()))
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dts[k])
+        U, V = V, U
+    rng = np.random.default_rng(5)
+    op = O.params(gamma=wl.gamma)
+    for _ in range(2):
+        v = _valid_random(lay, rng)
+        st = [lay.view(wl.arena, 0).copy()]
+        dv = [lay.view(v, 0).copy()]
+        for k in range(nsteps):
+            O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+            O.fill(lay.boxes(), lay.domain(), lay.bc, dv)
+            a, b, _ = O.step_jvp(st[0], dv[0], dt_list[k], wl.dx, op)
+            st, dv = [a], [b]
+        r = interior(st[0])[0][lo:hi, lo:hi, lo:hi]
+        dr = interior(dv[0])[0][lo:hi, lo:hi, lo:hi]
+        rhs = float(np.sum(2 * r * dr))
+        lhs = _dot_valid(lay, g, v)
+        assert abs(lhs - rhs) <= 1e-10 * abs(rhs), (lhs, rhs)
+
+
+def test_rollout_gradient_against_central_differences():
+    """Unlimited step on a smooth state with a bulk flow, 6 steps,
+    checkpoints every 5 (a partial last segment): <grad, v> vs central
+    differences with the dt sequence frozen.  (Without the bulk flow the
+    velocity crosses zero, where tracing switches waves discontinuously,
+    and central differences straddle those switches.)"""
+    wl = I.cfg4(12, amp=0.05, bulk=(0.3, 0.2, 0.25))
+    nsteps = 6
+    loss, g, lev = _loss_and_grad(wl, nsteps, 5, 3, 9, limiter=0)
+    lay = wl.layout
+    p = P.params(gamma=wl.gamma, limiter=0)
+    dts = torch.zeros(nsteps, 2, dtype=torch.float64, device="cuda")
+    U = torch.from_numpy(wl.arena).cuda()
+    V = torch.zeros_like(U)
+    for k in range(nsteps):
+        lev.fill_boundary(U)
+        lev.compute_dt(U, wl.dx, p, out=dts[k])
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dts[k])
+        U, V = V, U
+    rng = np.random.default_rng(11)
+    eps = 1e-6
+    for _ in range(3):
+        v = _valid_random(lay, rng)
+        lp = _loss_and_grad(I.Workload("p", lay, wl.arena + eps * v, wl.dx, wl.gamma, 1), nsteps, 5, 3, 9,
+                            dts=dts, limiter=0)[0]
+        lm = _loss_and_grad(I.Workload("m", lay, wl.arena - eps * v, wl.dx, wl.gamma, 1), nsteps, 5, 3, 9,
+                            dts=dts, limiter=0)[0]
+        fd = (lp - lm) / (2 * eps)
+        ad = _dot_valid(lay, g, v)
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)

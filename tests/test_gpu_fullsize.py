@@ -1,0 +1,122 @@
+"""Full-size GPU checks of the batched multi-box workloads against the
+oracle on sampled windows (the oracle recomputes each window from the same
+input), conservation over the whole level, the FP32-reconstruction error
+per field against FP64, and the Rayleigh-Taylor set-up (reflecting walls,
+gravity, FP32 reconstruction) on a reduced instance against the oracle's
+FP32 mode."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1008_2801_amd import inputs as I  # noqa: E402
+from paper_1008_2801_amd import ppm as P  # noqa: E402
+from tests.helpers import interior, field_errors  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _one_step(wl, precision=0, mode=P.BATCHED):
+    lev = P.Level(wl.layout)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+    U = torch.from_numpy(wl.arena).cuda()
+    lev.fill_boundary(U, mode)
+    dtv = lev.compute_dt(U, wl.dx, p)
+    V = lev.new_state()
+    lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, mode=mode)
+    out = V.cpu().numpy()
+    flags = lev.check_status()
+    dt = float(dtv[0].item())
+    lev.close()
+    return out, dt, flags
+
+
+@pytest.fixture(scope="module")
+def cfg3_state():
+    return I.cfg3()
+
+
+def test_cfg3_full_level_sampled_windows_and_conservation(cfg3_state):
+    wl = cfg3_state
+    lay = wl.layout
+    out, dt, flags = _one_step(wl)
+    assert flags == 0
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    p = O.params(gamma=wl.gamma)
+    s = max(O.max_wavespeed(u, wl.dx, p)[0] for u in st)
+    assert dt == p.cfl / s
+    rng = np.random.default_rng(2)
+    for b in rng.choice(lay.nbox, 24, replace=False):
+        n = lay.n(b)
+        for _ in range(2):
+            lo = tuple(int(rng.integers(0, n[d] - 1)) for d in range(3))
+            hi = tuple(v + 1 for v in lo)
+            ref, _, _ = O.step(st[b], dt, wl.dx, p, window=(lo, hi))
+            sl = (slice(None),) + tuple(slice(lo[d] + 4, hi[d] + 5) for d in (2, 1, 0))
+            got = lay.view(out, b)
+            err = np.abs(got[sl] - ref[sl]).max() / np.abs(ref[sl]).max()
+            assert err <= 1e-12, (b, lo, err)
+    for c in range(5):
+        s0 = math.fsum(np.concatenate([interior(lay.view(wl.arena, b))[c].ravel() for b in range(lay.nbox)]))
+        s1 = math.fsum(np.concatenate([interior(lay.view(out, b))[c].ravel() for b in range(lay.nbox)]))
+        sc = math.fsum(np.abs(np.concatenate([interior(lay.view(wl.arena, b))[c].ravel()
+                                              for b in range(lay.nbox)])))
+        assert abs(s1 - s0) <= 1e-13 * sc
+
+
+def test_cfg3_fp32_reconstruction_error_per_field(cfg3_state):
+    """One step in FP32-reconstruction mode against the FP64 step: per field,
+    the max error normalised by the field's max and the L1 error normalised
+    by its L1 norm; conservation still holds to FP64 round-off."""
+    wl = cfg3_state
+    lay = wl.layout
+    o64, dt64, _ = _one_step(wl, 0)
+    o32, dt32, flags = _one_step(wl, 1)
+    assert flags == 0 and dt32 == dt64
+    a = np.concatenate([interior(lay.view(o32, b)).reshape(5, -1) for b in range(lay.nbox)], axis=1)
+    r = np.concatenate([interior(lay.view(o64, b)).reshape(5, -1) for b in range(lay.nbox)], axis=1)
+    u0 = np.concatenate([interior(lay.view(wl.arena, b)).reshape(5, -1) for b in range(lay.nbox)], axis=1)
+    linf = np.abs(a - r).max(axis=1) / np.abs(r).max(axis=1)
+    l1 = np.abs(a - r).sum(axis=1) / np.abs(r).sum(axis=1)
+    print("fp32-reconstruction vs fp64, one step, per field (rho, mx, my, mz, E): Linf",
+          np.array2string(linf, precision=3), "L1", np.array2string(l1, precision=3))
+    assert linf.max() < 2e-5 and l1.max() < 2e-6
+    for c in range(5):
+        assert abs(math.fsum(a[c]) - math.fsum(u0[c])) <= 1e-13 * math.fsum(np.abs(u0[c]))
+
+
+def test_rayleigh_taylor_reduced_instance_matches_oracle_fp32_mode():
+    """2x2x2 boxes of 16^3 of the Rayleigh-Taylor set-up (walls in z,
+    g = -1 in z, FP32 reconstruction), 3 steps, against the oracle in the same
+    mode."""
+    wl = I.cfg5(2, 16)
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=1)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        lev.fill_boundary(U)
+        lev.compute_dt(U, wl.dx, p, out=dtv)
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv)
+        U, V = V, U
+    got = U.cpu().numpy()
+    assert lev.check_status() == 0
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    op = O.params(gamma=wl.gamma, grav=wl.grav, precision=1)
+    ost, _, ofl, _ = O.advance(lay.boxes(), lay.domain(), lay.bc, st, 3, wl.dx, op)
+    assert ofl == 0
+    worst = max(field_errors(interior(lay.view(got, b)), interior(ost[b])).max() for b in range(lay.nbox))
+    assert worst <= 1e-12, worst
