@@ -73,7 +73,11 @@ def level_rates(wl, steps, warmup, precision, per_box=True):
     U0 = torch.from_numpy(wl.arena).to("cuda")
     dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
     zones = lay.valid_zones()
-    out = {}
+    Uf = U0.clone()
+    lev.fill_boundary(Uf)
+    tile, strip, _ = lev.autotune(Uf, wl.dx, p, reps=2)
+    del Uf
+    out = {"tiling": {"tile": tile, "strip_rows": strip}}
     forms = (("batched", P.BATCHED), ("per_box", P.PER_BOX)) if per_box else (("batched", P.BATCHED),)
     for name, mode in forms:
         U = U0.clone()
@@ -181,6 +185,7 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--cpu-window", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tiling")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 512-box batched / per-box / graph measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -215,6 +220,13 @@ def main():
     p = P.params(gamma=wl.gamma, precision=wl.precision)
     lev.ensure_workspace(p.precision)
     dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    if not args.no_autotune:
+        Uf = U.clone()
+        lev.fill_boundary(Uf)
+        tiling = lev.autotune(Uf, wl.dx, p, reps=2)[:2]
+        del Uf
+    else:
+        tiling = lev.get_tiling()
 
     def step(a, b):
         lev.fill_boundary(a)
@@ -261,7 +273,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {lay.n(0)[0]}^3 single box, FP64, gamma {wl.gamma:.4g}, "
                                "random-mode density x planar Sod jump, periodic, CFL 0.5, plain step",
-                   "valid_zones": zones, "boxes": lay.nbox},
+                   "valid_zones": zones, "boxes": lay.nbox,
+                   "tiling": {"tile": tiling[0], "strip_rows": tiling[1]}},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops},

@@ -162,6 +162,25 @@ int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3],
 int ppm_graph_launch(ppm_graph* g, void* stream);
 int ppm_graph_destroy(ppm_graph* g);
 
+/* Tiling of the stage launches: `tile` zones per tile / threads per
+ * workgroup (64, 128, 256 or 512) and the strip height (rows) of the tile
+ * order (each strip of the planes is swept through all planes before the
+ * next; 0: plane by plane).  Rebuilds and uploads the tile lists;
+ * synchronises the device first.  Results do not depend on the tiling. */
+int ppm_set_tiling(ppm_ctx* ctx, int32_t tile, int32_t strip_rows);
+int ppm_get_tiling(const ppm_ctx* ctx, int32_t* tile, int32_t* strip_rows);
+
+/* Autotuner: times the batched step (reps steps after one warm-up, HIP
+ * events on the stream) from the filled state U into Unew for every
+ * candidate tile size x strip height, keeps the fastest, and appends it to
+ * the JSON-lines file cache_path (may be null) keyed by device
+ * architecture, precision and the histogram of box extents; a matching
+ * entry in the file is applied without timing (*from_cache = 1).
+ * Synchronises.  Writes the chosen tiling to *tile, *strip_rows. */
+int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3], const ppm_params* params,
+                 int32_t reps, const char* cache_path, void* stream, int32_t* tile, int32_t* strip_rows,
+                 int32_t* from_cache);
+
 /* Stage timing with HIP events recorded on the caller's stream around each
  * batched fill, dt and step stage launch while enabled (per-box launches are
  * not timed).  ppm_profile_read waits for the recorded events, writes the

@@ -48,13 +48,15 @@ __device__ __forceinline__ long long eidx(const DevBox& B, int x, int y, int z) 
   return ((long long)(z + 1) * (B.n[1] + 2) + (y + 1)) * (B.n[0] + 2) + (x + 1);
 }
 
-__global__ void __launch_bounds__(TILE) k_zero(double* __restrict__ p, long long n) {
-  for (long long i = (long long)blockIdx.x * TILE + threadIdx.x; i < n; i += (long long)gridDim.x * TILE)
+constexpr int ZERO_THREADS = 256;
+__global__ void __launch_bounds__(ZERO_THREADS) k_zero(double* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * ZERO_THREADS + threadIdx.x; i < n;
+       i += (long long)gridDim.x * ZERO_THREADS)
     p[i] = 0.0;
 }
 
 // Adjoint of the update and of the Heun source.
-__global__ void __launch_bounds__(TILE) k_adj_update(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_update(const Tile* __restrict__ tiles, int ntiles,
                                                      const DevBox* __restrict__ boxes,
                                                      const double* __restrict__ Ubn, double* __restrict__ aw,
                                                      long long LE, double* __restrict__ as, long long LS,
@@ -169,7 +171,7 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   }
 }
 
-__global__ void __launch_bounds__(TILE) k_adj_r3(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const double* __restrict__ work,
                                                  long long LE, double* __restrict__ aw, Gas<double> G,
                                                  const StepConsts* __restrict__ sc) {
@@ -247,7 +249,7 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
 // Two launches: phase 0 runs pairs (0,1), (1,0), (2,0); phase 1 runs (0,2),
 // (1,2), (2,1) -- within a launch every pair has its own axis d, so the
 // traced-state accumulations never meet.
-__global__ void __launch_bounds__(TILE) k_adj_r2(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_r2(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const double* __restrict__ work,
                                                  long long LE, double* __restrict__ aw, Gas<double> G,
                                                  const StepConsts* __restrict__ sc, int phase) {
@@ -308,7 +310,7 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
   }
 }
 
-__global__ void __launch_bounds__(TILE) k_adj_r1(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const double* __restrict__ work,
                                                  long long LE, double* __restrict__ aw, Gas<double> G,
                                                  const StepConsts* __restrict__ sc) {
@@ -323,7 +325,7 @@ __global__ void __launch_bounds__(TILE) k_adj_r1(const Tile* __restrict__ tiles,
 // primitives of its 5-zone stencil along d (A_GT), the sound speed (A_CB)
 // and the flattening coefficient (A_PHB, accumulated over the axes).
 template <int d>
-__global__ void __launch_bounds__(TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
                                                     const DevBox* __restrict__ boxes,
                                                     const double* __restrict__ prim, long long LS,
                                                     const double* __restrict__ work, long long LE,
@@ -375,7 +377,7 @@ __global__ void __launch_bounds__(TILE) k_adj_trace(const Tile* __restrict__ til
 // Gather of the trace contributions of axis d into the primitive adjoints of
 // every stored zone: qb_m(j) += sum over o of GT[m][o](j - o e_d).
 template <int d>
-__global__ void __launch_bounds__(TILE) k_adj_gather_trace(const Tile* __restrict__ tilesS, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_gather_trace(const Tile* __restrict__ tilesS, int ntiles,
                                                            const DevBox* __restrict__ boxes,
                                                            const double* __restrict__ aw, long long LE,
                                                            double* __restrict__ as, long long LS) {
@@ -384,9 +386,8 @@ __global__ void __launch_bounds__(TILE) k_adj_gather_trace(const Tile* __restric
   const Tile tl = tilesS[tt];
   const DevBox B = boxes[tl.box];
   const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
-  const long long tot = (long long)NS[0] * NS[1] * NS[2];
   const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= tot) return;
+  if (idx >= tl.end) return;
   int j[3];
   j[0] = (int)(idx % NS[0]) - NG;
   j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
@@ -410,7 +411,7 @@ __global__ void __launch_bounds__(TILE) k_adj_gather_trace(const Tile* __restric
 // Flattening adjoint: the derivative of phi = min_d (1 - chi_d) through the
 // selected axis, the selected shock-detector coefficient and its clamp,
 // into the pressures at offsets -3..3 along that axis (A_GF, A_SEL).
-__global__ void __launch_bounds__(TILE) k_adj_flatten(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict__ tiles, int ntiles,
                                                       const DevBox* __restrict__ boxes,
                                                       const double* __restrict__ prim, long long LS,
                                                       double* __restrict__ aw, long long LE, Gas<double> G) {
@@ -500,7 +501,7 @@ __global__ void __launch_bounds__(TILE) k_adj_flatten(const Tile* __restrict__ t
   a[A_SEL * LE] = (double)sel;
 }
 
-__global__ void __launch_bounds__(TILE) k_adj_gather_flatten(const Tile* __restrict__ tilesS, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_gather_flatten(const Tile* __restrict__ tilesS, int ntiles,
                                                              const DevBox* __restrict__ boxes,
                                                              const double* __restrict__ aw, long long LE,
                                                              double* __restrict__ as, long long LS) {
@@ -509,9 +510,8 @@ __global__ void __launch_bounds__(TILE) k_adj_gather_flatten(const Tile* __restr
   const Tile tl = tilesS[tt];
   const DevBox B = boxes[tl.box];
   const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
-  const long long tot = (long long)NS[0] * NS[1] * NS[2];
   const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= tot) return;
+  if (idx >= tl.end) return;
   int j[3];
   j[0] = (int)(idx % NS[0]) - NG;
   j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(TILE) k_adj_gather_flatten(const Tile* __restr
 }
 
 // Primitive adjoints -> conserved adjoints on every stored zone.
-__global__ void __launch_bounds__(TILE) k_adj_prim(const Tile* __restrict__ tilesS, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_prim(const Tile* __restrict__ tilesS, int ntiles,
                                                    const DevBox* __restrict__ boxes, const double* __restrict__ U,
                                                    double* __restrict__ as, long long LS, Gas<double> G) {
   const int tt = xcd_tile(ntiles);
@@ -538,7 +538,7 @@ __global__ void __launch_bounds__(TILE) k_adj_prim(const Tile* __restrict__ tile
   const DevBox B = boxes[tl.box];
   const long long NS = (long long)(B.n[0] + 2 * NG) * (B.n[1] + 2 * NG) * (B.n[2] + 2 * NG);
   const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= NS) return;
+  if (idx >= tl.end) return;
   double uc[5], qb[6], ub[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int c = 0; c < 5; ++c) uc[c] = U[B.soff + idx + c * NS];
@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(TILE) k_adj_prim(const Tile* __restrict__ tile
 // Transpose of the ghost fill: every valid zone of a source box sums the
 // adjoints of the ghost zones that copied it (signs of reflections applied),
 // in the fixed order of the plan; writes the result to Ub (valid zones).
-__global__ void __launch_bounds__(TILE) k_adj_fill(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    const FillDesc* __restrict__ desc,
                                                    const int* __restrict__ inv_start, const int* __restrict__ inv_idx,
@@ -629,14 +629,14 @@ hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, co
   G.flattening = flattening && limiter;
   G.iters = iters;
   G.grav = grav;
-  const dim3 blk(TILE);
+  const dim3 blk(L.tile);
   const unsigned zg = 4096;
   // zero: all stored-grid planes, and the traced-grid planes that are
   // accumulated or read where not written
-  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, as, (long long)A_SPLANES * L.LS);
-  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, aw + A_TB * L.LE, (long long)(30 + 30 + 60) * L.LE);
-  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, aw + A_PHB * L.LE, (long long)L.LE);
-  hipLaunchKernelGGL(k_zero, dim3(zg), blk, 0, s, Ub, ULEN);
+  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, as, (long long)A_SPLANES * L.LS);
+  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, aw + A_TB * L.LE, (long long)(30 + 30 + 60) * L.LE);
+  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, aw + A_PHB * L.LE, (long long)L.LE);
+  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, Ub, ULEN);
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
   hipLaunchKernelGGL(k_adj_update, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS, L.consts,
                      grav, g[0], g[1], g[2]);

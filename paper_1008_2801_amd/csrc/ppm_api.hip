@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <list>
+#include <map>
+#include <sstream>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -286,6 +289,28 @@ PlanCache& plan_cache() {
 
 long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 
+// Tiles of `tile` consecutive linear zones of one box's grid (extents
+// e0 x e1 x e2, x fastest), appended in strip order: the planes are cut into
+// strips of `strip_rows` rows and each strip is walked through all planes
+// before the next, so the z-neighbours of a tile were visited a few tiles
+// earlier and are still in the XCD's L2 (strip_rows = 0: plane by plane).
+constexpr int STRIP_ROWS = 32;
+void add_tiles(std::vector<Tile>& out, int b, int e0, int e1, int e2, int tile, int strip_rows) {
+  const long long plane = (long long)e0 * e1, tot = plane * e2;
+  const long long strip = strip_rows > 0 ? (long long)strip_rows * e0 : plane;
+  std::vector<std::pair<std::pair<long long, long long>, long long>> keyed;
+  for (long long s = 0; s < tot; s += tile) {
+    const long long k = s / plane, off = s % plane;
+    keyed.push_back({{off / strip, k}, s});
+  }
+  std::stable_sort(keyed.begin(), keyed.end(),
+                   [](const auto& a, const auto& c) { return a.first < c.first; });
+  for (const auto& kv : keyed) {
+    const long long s = kv.second;
+    out.push_back(Tile{b, (int)s, (int)std::min(s + tile, tot)});
+  }
+}
+
 }  // namespace
 
 // ============================================================ context =====
@@ -297,6 +322,7 @@ struct ppm_ctx {
   bool plan_hit = false;
   std::vector<Tile> tilesS, tilesE;
   std::vector<int> tS_begin, tE_begin;  // nbox + 1
+  int tile = TILE, strip_rows = STRIP_ROWS;
   long long LS = 0, LE = 0;
   // device copies
   DevBox* d_boxes = nullptr;
@@ -349,6 +375,7 @@ struct ppm_ctx {
     L.inv_idx = d_inv_idx;
     L.LS = LS;
     L.LE = LE;
+    L.tile = tile;
     return L;
   }
   int fail(int code, const std::string& msg) {
@@ -370,6 +397,21 @@ struct ppm_graph {
 };
 
 namespace {
+void build_tiles(ppm_ctx& c) {
+  c.tilesS.clear();
+  c.tilesE.clear();
+  c.tS_begin.assign(1, 0);
+  c.tE_begin.assign(1, 0);
+  for (int b = 0; b < c.layout.nbox; ++b) {
+    int n[3];
+    for (int d = 0; d < 3; ++d) n[d] = c.boxes[b].hi[d] - c.boxes[b].lo[d] + 1;
+    add_tiles(c.tilesS, b, n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG, c.tile, c.strip_rows);
+    add_tiles(c.tilesE, b, n[0] + 2, n[1] + 2, n[2] + 2, c.tile, c.strip_rows);
+    c.tS_begin.push_back((int)c.tilesS.size());
+    c.tE_begin.push_back((int)c.tilesE.size());
+  }
+}
+
 template <class T> hipError_t upload(T** dst, const std::vector<T>& v) {
   const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
   hipError_t e = hipMalloc((void**)dst, bytes);
@@ -420,8 +462,6 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
   ctx->off.assign(nb + 1, 0);
   for (int d = 0; d < 3; ++d) ctx->foff[d].assign(nb + 1, 0);
   long long ps = 0, pe = 0;
-  ctx->tS_begin.push_back(0);
-  ctx->tE_begin.push_back(0);
   for (int b = 0; b < nb; ++b) {
     int n[3];
     for (int d = 0; d < 3; ++d) n[d] = layout->boxes[b].hi[d] - layout->boxes[b].lo[d] + 1;
@@ -439,10 +479,6 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
       db[b].foff[d] = ctx->foff[d][b];
       ctx->foff[d][b + 1] = ctx->foff[d][b] + fe;
     }
-    for (long long s = 0; s < NS; s += TILE) ctx->tilesS.push_back(Tile{b, (int)s});
-    for (long long s = 0; s < NE; s += TILE) ctx->tilesE.push_back(Tile{b, (int)s});
-    ctx->tS_begin.push_back((int)ctx->tilesS.size());
-    ctx->tE_begin.push_back((int)ctx->tilesE.size());
     ps += NS;
     pe += NE;
   }
@@ -458,6 +494,7 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
     std::vector<int> fillp(inv_start.begin(), inv_start.end() - 1);
     for (size_t k = 0; k < ctx->plan->desc.size(); ++k) inv_idx[fillp[ctx->plan->desc[k].src]++] = (int)k;
   }
+  build_tiles(*ctx);
   hipError_t e;
   if ((e = upload(&ctx->d_inv_start, inv_start)) != hipSuccess ||
       (e = upload(&ctx->d_inv_idx, inv_idx)) != hipSuccess ||
@@ -710,6 +747,116 @@ int ppm_graph_destroy(ppm_graph* g) {
   if (g->graph) (void)hipGraphDestroy(g->graph);
   (void)hipFree(g->dtv);
   delete g;
+  return PPM_OK;
+}
+
+int ppm_set_tiling(ppm_ctx* ctx, int32_t tile, int32_t strip_rows) {
+  if (!ctx) return PPM_EINVAL;
+  if (!(tile == 64 || tile == 128 || tile == 256 || tile == 512) || strip_rows < 0)
+    return ctx->fail(PPM_EINVAL, "tiling: tile must be 64, 128, 256 or 512 and strip_rows >= 0");
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return ctx->hip(e, "tiling");
+  ctx->tile = tile;
+  ctx->strip_rows = strip_rows;
+  build_tiles(*ctx);
+  (void)hipFree(ctx->d_tilesS);
+  (void)hipFree(ctx->d_tilesE);
+  ctx->d_tilesS = nullptr;
+  ctx->d_tilesE = nullptr;
+  if ((e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess || (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess)
+    return ctx->hip(e, "tiling upload");
+  return PPM_OK;
+}
+
+int ppm_get_tiling(const ppm_ctx* ctx, int32_t* tile, int32_t* strip_rows) {
+  if (!ctx || !tile || !strip_rows) return PPM_EINVAL;
+  *tile = ctx->tile;
+  *strip_rows = ctx->strip_rows;
+  return PPM_OK;
+}
+
+int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3], const ppm_params* params,
+                 int32_t reps, const char* cache_path, void* stream, int32_t* tile, int32_t* strip_rows,
+                 int32_t* from_cache) {
+  if (!ctx) return PPM_EINVAL;
+  std::string m = validate_params(params);
+  if (m.empty()) m = validate_dx(dx);
+  if (m.empty() && (!U || !Unew || reps < 1)) m = "autotune: need U, Unew and reps >= 1";
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  // key: device architecture, precision and the histogram of box extents
+  hipDeviceProp_t prop;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipError_t e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return ctx->hip(e, "autotune");
+  std::map<std::array<int, 3>, int> hist;
+  for (const ppm_box& B : ctx->boxes)
+    hist[{B.hi[0] - B.lo[0] + 1, B.hi[1] - B.lo[1] + 1, B.hi[2] - B.lo[2] + 1}]++;
+  std::ostringstream ks;
+  ks << prop.gcnArchName << "|p" << params->precision << "|";
+  for (const auto& kv : hist) ks << kv.first[0] << "x" << kv.first[1] << "x" << kv.first[2] << ":" << kv.second << ";";
+  const std::string key = ks.str();
+  if (from_cache) *from_cache = 0;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (std::getline(in, line)) {
+      if (line.find(pat) == std::string::npos) continue;
+      int t = 0, sr = -1;
+      const size_t a = line.find("\"tile\": "), b = line.find("\"strip_rows\": ");
+      if (a != std::string::npos) t = std::atoi(line.c_str() + a + 8);
+      if (b != std::string::npos) sr = std::atoi(line.c_str() + b + 14);
+      if (ppm_set_tiling(ctx, t, sr) == PPM_OK) {
+        if (tile) *tile = t;
+        if (strip_rows) *strip_rows = sr;
+        if (from_cache) *from_cache = 1;
+        return PPM_OK;
+      }
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double* dtv = nullptr;
+  if ((e = hipMalloc((void**)&dtv, 2 * sizeof(double))) != hipSuccess) return ctx->hip(e, "autotune");
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int tiles[] = {128, 256, 512};
+  const int strips[] = {8, 16, 32, 64, 0};
+  float best = 1e30f;
+  int bt = ctx->tile, bs = ctx->strip_rows;
+  int rc = PPM_OK;
+  for (int t : tiles) {
+    for (int sr : strips) {
+      if ((rc = ppm_set_tiling(ctx, t, sr)) != PPM_OK) break;
+      if ((rc = ppm_compute_dt(ctx, U, dx, params, dtv, stream)) != PPM_OK) break;
+      if ((rc = ppm_hydro_step(ctx, U, Unew, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, stream)) != PPM_OK)
+        break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && rc == PPM_OK; ++r)
+        rc = ppm_hydro_step(ctx, U, Unew, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, stream);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (ms < best) { best = ms; bt = t; bs = sr; }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(dtv);
+  if (rc) return rc;
+  rc = ppm_set_tiling(ctx, bt, bs);
+  if (rc) return rc;
+  if (tile) *tile = bt;
+  if (strip_rows) *strip_rows = bs;
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << "{\"key\": \"" << key << "\", \"tile\": " << bt << ", \"strip_rows\": " << bs
+        << ", \"ms_per_step\": " << best << "}\n";
+  }
   return PPM_OK;
 }
 

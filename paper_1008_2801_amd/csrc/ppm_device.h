@@ -46,9 +46,8 @@ struct EZone {
 
 __device__ __forceinline__ bool ezone(const Tile& tl, const DevBox& B, EZone& z) {
   z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
-  const long long tot = (long long)z.E[0] * z.E[1] * z.E[2];
   const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= tot) return false;
+  if (idx >= tl.end) return false;
   z.e = idx;
   const int i = (int)(idx % z.E[0]);
   const long long r = idx / z.E[0];

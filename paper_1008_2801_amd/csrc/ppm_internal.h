@@ -10,7 +10,8 @@
 namespace ppm {
 
 constexpr int NG = 4;        // ghost zones per side
-constexpr int TILE = 256;    // zones per tile == threads per workgroup
+constexpr int TILE = 256;    // default zones per tile (== threads per workgroup)
+constexpr int MAX_TILE = 512;  // largest tile the kernels are built for
 constexpr int NXCD = 8;      // MI355X: 8 accelerator complex dies, 32 CUs each
 
 // Per-box metadata on the device.
@@ -23,10 +24,12 @@ struct DevBox {
   long long foff[3];  // element offsets in the three flux arenas
 };
 
-// A tile: TILE consecutive linear zones of one box's grid.
+// A tile: TILE (or fewer, at the end of a box) consecutive linear zones
+// [start, end) of one box's grid.
 struct Tile {
   int box;
   int start;
+  int end;
 };
 
 // One copy of the ghost-fill plan: the dst-box-local region [lo, hi] takes
@@ -71,6 +74,7 @@ struct DevLevel {
   const int* inv_start;  // nbox + 1: descriptors whose source is each box
   const int* inv_idx;
   long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
+  int tile;            // zones per tile of the tile lists (threads per workgroup)
 };
 
 }  // namespace ppm

@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, co
 
 // O2 on every stored zone: (rho, u, v, w, p, c) planes.
 template <class S>
-__global__ void __launch_bounds__(TILE) k_prim(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_prim(const Tile* __restrict__ tiles, int ntiles,
                                                const DevBox* __restrict__ boxes,
                                                const double* __restrict__ U, S* __restrict__ prim,
                                                long long LS, Gas<S> G, int* flags) {
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(TILE) k_prim(const Tile* __restrict__ tiles, i
   const DevBox B = boxes[tl.box];
   const long long NS = (long long)(B.n[0] + 2 * NG) * (B.n[1] + 2 * NG) * (B.n[2] + 2 * NG);
   const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= NS) return;
+  if (idx >= tl.end) return;
   const double* u = U + B.soff + idx;
   S uc[5];
 #pragma unroll
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(TILE) k_prim(const Tile* __restrict__ tiles, i
 
 // O3 on the traced zones.
 template <class S>
-__global__ void __launch_bounds__(TILE) k_flatten(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ tiles, int ntiles,
                                                   const DevBox* __restrict__ boxes,
                                                   const S* __restrict__ prim, long long LS,
                                                   S* __restrict__ work, long long LE, Gas<S> G) {
@@ -170,7 +170,7 @@ __device__ __forceinline__ void trace_body(const Tile* __restrict__ tiles, int n
 }
 
 template <class S>
-__global__ void __launch_bounds__(TILE) k_trace(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_trace(const Tile* __restrict__ tiles, int ntiles,
                                                 const DevBox* __restrict__ boxes,
                                                 const S* __restrict__ prim, long long LS,
                                                 S* __restrict__ work, long long LE, Gas<S> G,
@@ -211,7 +211,7 @@ __device__ __forceinline__ void riemann1_body(const Tile* __restrict__ tiles, in
 }
 
 template <class S>
-__global__ void __launch_bounds__(TILE) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    int* flags) {
@@ -223,71 +223,74 @@ __global__ void __launch_bounds__(TILE) k_riemann1(const Tile* __restrict__ tile
 }
 
 
-// O8: for the pair (d, t) = blockIdx.y: states of axis d corrected by the
-// stage-1 t-flux difference (dt/3h_t), then F^{d|t} at d-face slots x_d in
-// [0, n], x_t in [0, n-1], the remaining axis in [-1, n].
+// O8: for axis d = blockIdx.y, both pairs (d, t1) and (d, t2) in one lane:
+// the traced states of axis d are loaded once, corrected by the stage-1
+// flux difference along t1 (dt/3h_t1) and along t2 (dt/3h_t2), and the
+// fluxes F^{d|t} computed at d-face slots x_d in [0, n] with x_t in
+// [0, n-1] and the remaining axis in [-1, n] (each pair under its own mask).
 template <int d, int t, class S>
+__device__ __forceinline__ void riemann2_pair(const S* __restrict__ w, S* __restrict__ o, long long LE,
+                                              long long sd, long long stt, const S qeL[5], const S qeR[5],
+                                              const Gas<S>& G, S c3, int& fl) {
+  constexpr int pr = pair_index(d, t);
+  S ueL[5], ueR[5], L[5], R[5];
+  prim_to_cons(qeL, G, ueL);
+  prim_to_cons(qeR, G, ueR);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* fL = w + (E_F1 + t * 5 + m) * LE - sd;
+    const S* fR = w + (E_F1 + t * 5 + m) * LE;
+    ueL[m] = ueL[m] - c3 * (fL[stt] - fL[0]);
+    ueR[m] = ueR[m] - c3 * (fR[stt] - fR[0]);
+  }
+  cons_to_prim_floor(ueL, G, L, fl);
+  cons_to_prim_floor(ueR, G, R, fl);
+  S F[5];
+  riemann<d>(L, R, G, F, fl);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) o[(E_F2 + pr * 5 + m) * LE] = F[m];
+}
+
+template <int d, class S>
 __device__ __forceinline__ void riemann2_body(const Tile* __restrict__ tiles, int ntiles,
                                               const DevBox* __restrict__ boxes, S* __restrict__ work,
                                               long long LE, const Gas<S>& G,
                                               const StepConsts* __restrict__ sc, int* flags) {
-  constexpr int pr = pair_index(d, t);
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tiles[tt];
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  if (z.x[d] < 0 || z.x[t] < 0 || z.x[t] >= B.n[t]) return;
-  const long long sd = stride(z.E, d), stt = stride(z.E, t);
-  const S c3 = SC<S>::dt3h(sc)[t];
+  if (z.x[d] < 0) return;
+  const bool va = z.x[t1] >= 0 && z.x[t1] < B.n[t1];  // pair (d, t1)
+  const bool vb = z.x[t2] >= 0 && z.x[t2] < B.n[t2];  // pair (d, t2)
+  if (!va && !vb) return;
+  const long long sd = stride(z.E, d);
   const S* w = work + B.eoff + z.e;
-  int fl = 0;
-  S L[5], R[5];
-  {  // high-face state of zone x - e_d
-    S qe[5], ue[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) qe[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
-    prim_to_cons(qe, G, ue);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const S* f = w + (E_F1 + t * 5 + m) * LE - sd;
-      ue[m] = ue[m] - c3 * (f[stt] - f[0]);
-    }
-    cons_to_prim_floor(ue, G, L, fl);
-  }
-  {  // low-face state of zone x
-    S qe[5], ue[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) qe[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
-    prim_to_cons(qe, G, ue);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const S* f = w + (E_F1 + t * 5 + m) * LE;
-      ue[m] = ue[m] - c3 * (f[stt] - f[0]);
-    }
-    cons_to_prim_floor(ue, G, R, fl);
-  }
-  S F[5];
-  riemann<d>(L, R, G, F, fl);
   S* o = work + B.eoff + z.e;
+  S qeL[5], qeR[5];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) o[(E_F2 + pr * 5 + m) * LE] = F[m];
+  for (int m = 0; m < 5; ++m) {
+    qeL[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
+    qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
+  }
+  int fl = 0;
+  if (va) riemann2_pair<d, t1>(w, o, LE, sd, stride(z.E, t1), qeL, qeR, G, SC<S>::dt3h(sc)[t1], fl);
+  if (vb) riemann2_pair<d, t2>(w, o, LE, sd, stride(z.E, t2), qeL, qeR, G, SC<S>::dt3h(sc)[t2], fl);
   raise_flags(flags, fl);
 }
 
 template <class S>
-__global__ void __launch_bounds__(TILE) k_riemann2(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_riemann2(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    const StepConsts* __restrict__ sc, int* flags) {
   switch (blockIdx.y) {
-    case 0: riemann2_body<0, 1>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    case 1: riemann2_body<0, 2>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    case 2: riemann2_body<1, 0>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    case 3: riemann2_body<1, 2>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    case 4: riemann2_body<2, 0>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    default: riemann2_body<2, 1>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 0: riemann2_body<0>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 1: riemann2_body<1>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    default: riemann2_body<2>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
   }
 }
 
@@ -347,7 +350,7 @@ __device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, in
 }
 
 template <class S>
-__global__ void __launch_bounds__(TILE) k_riemann3(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_riemann3(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    const StepConsts* __restrict__ sc,
@@ -361,7 +364,7 @@ __global__ void __launch_bounds__(TILE) k_riemann3(const Tile* __restrict__ tile
 
 // O10: conservative update in FP64 (+ Heun source) on the valid zones.
 template <class S>
-__global__ void __launch_bounds__(TILE) k_update(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes,
                                                  const double* __restrict__ U, double* __restrict__ Unew,
                                                  const S* __restrict__ work, long long LE,
@@ -420,7 +423,7 @@ __global__ void __launch_bounds__(TILE) k_update(const Tile* __restrict__ tiles,
 // (on the bit pattern: non-negative doubles order like their unsigned bit
 // patterns) combines the workgroups.  max is exact, so the result does not
 // depend on the order.
-__global__ void __launch_bounds__(TILE) k_wavespeed(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) k_wavespeed(const Tile* __restrict__ tiles, int ntiles,
                                                     const DevBox* __restrict__ boxes,
                                                     const double* __restrict__ U, double h0, double h1,
                                                     double h2, double gamma, double gm1,
@@ -449,12 +452,12 @@ __global__ void __launch_bounds__(TILE) k_wavespeed(const Tile* __restrict__ til
     }
   }
   for (int off = 32; off > 0; off >>= 1) s = smax(s, __shfl_xor(s, off, 64));
-  __shared__ double wmax[TILE / 64];
+  __shared__ double wmax[MAX_TILE / 64];
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = wmax[0];
-    for (int w = 1; w < TILE / 64; ++w) m = smax(m, wmax[w]);
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = smax(m, wmax[w]);
     atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
   }
 }
@@ -473,11 +476,12 @@ __global__ void __launch_bounds__(64) k_finish_dt(double* dt_dev, double cfl) {
 
 // O1: ghost fill over the plan.  One lane per destination ghost zone; the
 // descriptor of a lane is found by binary search in the zone-count prefix.
-__global__ void __launch_bounds__(TILE) k_fill(const FillDesc* __restrict__ desc,
+constexpr int FILL_THREADS = 256;
+__global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restrict__ desc,
                                                const long long* __restrict__ start, int d0, int d1,
                                                long long z0, long long z1,
                                                const DevBox* __restrict__ boxes, double* U) {
-  const long long gidx = z0 + (long long)blockIdx.x * TILE + threadIdx.x;
+  const long long gidx = z0 + (long long)blockIdx.x * FILL_THREADS + threadIdx.x;
   if (gidx >= z1) return;
   int lo = d0, hi = d1 - 1;
   while (lo < hi) {
@@ -532,7 +536,7 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, cons
   const Tile* TS = L.tilesS + tS0;
   const Tile* TE = L.tilesE + tE0;
   if (nS <= 0 || nE <= 0) return hipSuccess;
-  const dim3 blk(TILE);
+  const dim3 blk(L.tile);
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_prim<S>, dim3(xcd_grid(nS)), blk, 0, s, TS, nS, L.boxes, U, prim, L.LS, G, L.flags);
   if (ev) (void)hipEventRecord(ev[1], s);
@@ -544,7 +548,7 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, cons
   hipLaunchKernelGGL(k_riemann1<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
                      L.flags);
   if (ev) (void)hipEventRecord(ev[4], s);
-  hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 6), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
+  hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
                      L.consts, L.flags);
   if (nstages <= 5) return hipGetLastError();
   double* fx = flux ? flux[0] : nullptr;
@@ -573,8 +577,8 @@ hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_en
                        long long zone_end, hipStream_t s) {
   if (desc_end <= desc_begin || zone_end <= zone_begin) return hipSuccess;
   const long long nz = zone_end - zone_begin;
-  const unsigned grid = (unsigned)((nz + TILE - 1) / TILE);
-  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(TILE), 0, s, L.desc, L.desc_start, desc_begin, desc_end,
+  const unsigned grid = (unsigned)((nz + FILL_THREADS - 1) / FILL_THREADS);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(FILL_THREADS), 0, s, L.desc, L.desc_start, desc_begin, desc_end,
                      zone_begin, zone_end, L.boxes, U);
   return hipGetLastError();
 }
@@ -586,7 +590,7 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, bits);
   const int n = tile_end - tile_begin;
   if (n > 0)
-    hipLaunchKernelGGL(k_wavespeed, dim3(n < 2048 ? n : 2048), dim3(TILE), 0, s, L.tilesE + tile_begin, n, L.boxes, U,
+    hipLaunchKernelGGL(k_wavespeed, dim3(n < 2048 ? n : 2048), dim3(L.tile), 0, s, L.tilesE + tile_begin, n, L.boxes, U,
                        h[0], h[1], h[2], gamma, gamma - 1.0, small_pres, bits);
   hipLaunchKernelGGL(k_finish_dt, dim3(1), dim3(64), 0, s, dt_dev, cfl);
   return hipGetLastError();

@@ -26,7 +26,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_compute_dt", "ppm_hydro_step", "ppm_graph_create", "ppm_graph_launch",
            "ppm_graph_destroy", "ppm_check_status", "ppm_plan_build", "ppm_fill_boundary_host",
            "ppm_plan_cache_stats", "ppm_profile_enable", "ppm_profile_read",
-           "ppm_adjoint_workspace_bytes", "ppm_set_adjoint_workspace", "ppm_hydro_step_adjoint")
+           "ppm_adjoint_workspace_bytes", "ppm_set_adjoint_workspace", "ppm_hydro_step_adjoint",
+           "ppm_set_tiling", "ppm_get_tiling", "ppm_autotune")
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
 
@@ -97,6 +98,10 @@ def lib():
         L.ppm_fill_boundary_host.argtypes = [ctypes.POINTER(LayoutC), ctypes.POINTER(ctypes.c_double)]
         L.ppm_plan_cache_stats.argtypes = [_i64p, _i64p, _i32p]
         L.ppm_profile_enable.argtypes = [_vp, ctypes.c_int32]
+        L.ppm_set_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+        L.ppm_get_tiling.argtypes = [_vp, _i32p, _i32p]
+        L.ppm_autotune.argtypes = [_vp, _vp, _vp, _dp3, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_char_p,
+                                   _vp, _i32p, _i32p, _i32p]
         L.ppm_adjoint_workspace_bytes.argtypes = [_vp]
         L.ppm_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.ppm_set_adjoint_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
@@ -273,6 +278,27 @@ class Level:
         cnt = (ctypes.c_int64 * n)()
         self._check(lib().ppm_profile_read(self.ctx, ms, cnt), "ppm_profile_read")
         return {PROF_TAGS[k]: (ms[k], cnt[k]) for k in range(n)}
+
+    def set_tiling(self, tile, strip_rows):
+        self._check(lib().ppm_set_tiling(self.ctx, int(tile), int(strip_rows)), "ppm_set_tiling")
+
+    def get_tiling(self):
+        t, s = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().ppm_get_tiling(self.ctx, ctypes.byref(t), ctypes.byref(s)), "ppm_get_tiling")
+        return t.value, s.value
+
+    def autotune(self, U, dx, p, reps=3, cache_path=None, stream=None):
+        """Pick the tiling by timing the batched step from U (ghosts filled);
+        returns (tile, strip_rows, from_cache)."""
+        if self._work is None or self._work_prec != p.precision or self._work.numel() < self.workspace_bytes(p.precision):
+            self.ensure_workspace(p.precision)
+        scratch = self.new_state()
+        t, s, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        path = None if cache_path is None else str(cache_path).encode()
+        self._check(lib().ppm_autotune(self.ctx, _ptr(U), _ptr(scratch), _dp3(*dx), ctypes.byref(p), int(reps),
+                                       path, _stream(stream), ctypes.byref(t), ctypes.byref(s), ctypes.byref(c)),
+                    "ppm_autotune")
+        return t.value, s.value, bool(c.value)
 
     def ensure_adjoint_workspace(self):
         import torch

@@ -25,9 +25,11 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-def gpu_run(wl, nsteps, mode=P.BATCHED, fluxes=False, dt=None, **pk):
+def gpu_run(wl, nsteps, mode=P.BATCHED, fluxes=False, dt=None, tiling=None, **pk):
     """nsteps of [fill, dt, step] on the GPU; returns (level, host arena, dts, flags, last fluxes)."""
     lev = P.Level(wl.layout)
+    if tiling is not None:
+        lev.set_tiling(*tiling)
     U = torch.from_numpy(wl.arena).cuda()
     V = lev.new_state()
     p = P.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision, **pk)
@@ -291,3 +293,23 @@ def test_cfg2_full_size_sampled_windows():
         s1 = math.fsum(interior(got)[c].ravel())
         sc = math.fsum(np.abs(interior(lay.view(wl.arena, 0))[c]).ravel())
         assert abs(s1 - s0) <= 1e-13 * sc
+
+
+def test_tiling_does_not_change_results_and_autotuner_caches(tmp_path):
+    """Every tile size / strip order gives the same bits; the autotuner
+    picks one of them and a second call takes it from its cache file."""
+    wl = _uneven_level(seed=13)
+    ref = gpu_run(wl, 2)[1]
+    for tiling in [(128, 8), (512, 0), (64, 16), (256, 64)]:
+        got = gpu_run(wl, 2, tiling=tiling)[1]
+        assert np.array_equal(np.nan_to_num(got), np.nan_to_num(ref)), tiling
+    lev = P.Level(wl.layout)
+    p = P.params(gamma=wl.gamma)
+    U = torch.from_numpy(wl.arena).cuda()
+    lev.fill_boundary(U)
+    cache = tmp_path / "tune.jsonl"
+    t, s, hit = lev.autotune(U, wl.dx, p, reps=1, cache_path=cache)
+    assert not hit and t in (128, 256, 512) and s in (0, 8, 16, 32, 64)
+    lev2 = P.Level(wl.layout)
+    t2, s2, hit2 = lev2.autotune(U, wl.dx, p, reps=1, cache_path=cache)
+    assert hit2 and (t2, s2) == (t, s) and lev2.get_tiling() == (t, s)
