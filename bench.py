@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiling")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 512-box batched / per-box / graph measurements")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only measure the adjoint/forward cost on the 128^3 differentiation workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -208,6 +210,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
                           "copies": 3}))
+        return
+
+    if args.adjoint_only:
+        from paper_1008_2801_amd import inputs as I
+        a = adjoint_costs(I.cfg4(), 20, 5)
+        print(json.dumps({"adjoint": a}))
         return
 
     wl = make_workload(args.workload)

@@ -126,6 +126,11 @@ __device__ __forceinline__ void r3_state(const S* w, long long LE, long long off
   }
 }
 
+// Face slot x along d is a stage-3 face when x_d >= 0 and both transverse
+// indices are valid.  The lane of slot x writes the adjoints of the two
+// states of its face (zone x - e_d, high side; zone x, low side); every zone
+// side not on a face is written as zero by the zone's own lane, so each
+// entry of the U3 and traced-state planes is written exactly once here.
 template <int d>
 __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int ntiles,
                                             const DevBox* __restrict__ boxes, const double* __restrict__ work,
@@ -139,11 +144,28 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  if (z.x[d] < 0 || z.x[t1] < 0 || z.x[t1] >= B.n[t1] || z.x[t2] < 0 || z.x[t2] >= B.n[t2]) return;
+  double* a = aw + B.eoff + z.e;
+  const bool tv = z.x[t1] >= 0 && z.x[t1] < B.n[t1] && z.x[t2] >= 0 && z.x[t2] < B.n[t2];
+  const bool face = tv && z.x[d] >= 0;
+  const bool hi_face = tv && z.x[d] + 1 <= B.n[d];  // slot x + e_d is a face
+  if (!hi_face) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      a[(A_U3 + (d * 2 + 0) * 5 + m) * LE] = 0.0;
+      a[(A_TB + (d * 2 + 0) * 5 + m) * LE] = 0.0;
+    }
+  }
+  if (!face) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      a[(A_U3 + (d * 2 + 1) * 5 + m) * LE] = 0.0;
+      a[(A_TB + (d * 2 + 1) * 5 + m) * LE] = 0.0;
+    }
+    return;
+  }
   const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
   const S c1 = sc->d_dt2h[t1], c2 = sc->d_dt2h[t2];
   const S* w = work + B.eoff + z.e;
-  double* a = aw + B.eoff + z.e;
   S Fb[5];
   const double dtdx = sc->dtdx[d];
 #pragma unroll
@@ -166,8 +188,8 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   for (int m = 0; m < 5; ++m) {
     a[(A_U3 + (d * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
     a[(A_U3 + (d * 2 + 1) * 5 + m) * LE] = uRb[m];
-    a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
-    a[(A_TB + (d * 2 + 1) * 5 + m) * LE] += tRb[m];
+    a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] = tLb[m];
+    a[(A_TB + (d * 2 + 1) * 5 + m) * LE] = tRb[m];
   }
 }
 
@@ -182,27 +204,19 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ ti
   }
 }
 
-// Stage-2 pair (d, t).
+// Stage-2 pair (d, t) of the face at the lane's slot: F2^{d|t} adjoint from
+// the stage-3 states of the third axis r (difference along d), reverse of the
+// corrected states, adjoints of the two traced states (returned) and of the
+// corrected states (written to U2).
 template <int d, int t>
-__device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int ntiles,
-                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
-                                            const StepConsts* __restrict__ sc) {
+__device__ __forceinline__ void adj_r2_pair(const double* __restrict__ w, double* __restrict__ a, long long LE,
+                                            long long sd, long long stt, const double qeL[5],
+                                            const double qeR[5], const Gas<double>& G,
+                                            const StepConsts* __restrict__ sc, double tLb[5], double tRb[5]) {
   using S = double;
   constexpr int pr = pair_index(d, t);
   constexpr int r = 3 - d - t;
-  const int tt = xcd_tile(ntiles);
-  if (tt < 0) return;
-  const Tile tl = tiles[tt];
-  const DevBox B = boxes[tl.box];
-  EZone z;
-  if (!ezone(tl, B, z)) return;
-  if (z.x[d] < 0 || z.x[t] < 0 || z.x[t] >= B.n[t]) return;
-  const long long sd = stride(z.E, d), stt = stride(z.E, t);
   const S c3 = sc->d_dt3h[t];
-  const S* w = work + B.eoff + z.e;
-  double* a = aw + B.eoff + z.e;
-  // F2^{d|t} adjoint from the stage-3 states of axis r (difference along d)
   S Fb[5];
   const double c2d = sc->d_dt2h[d];
 #pragma unroll
@@ -211,13 +225,8 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
     const double* um = a + (A_U3 + (r * 2 + 1) * 5 + m) * LE;
     Fb[m] = c2d * ((up[0] + um[0]) - (up[-sd] + um[-sd]));
   }
-  S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
+  S ueL[5], ueR[5], L[5], R[5];
   int fl = 0;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    qeL[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
-    qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
-  }
   prim_to_cons(qeL, G, ueL);
   prim_to_cons(qeR, G, ueR);
 #pragma unroll
@@ -234,34 +243,81 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
   cons_to_prim_floor_vjp(ueL, G, Lb, uLb);
   cons_to_prim_floor_vjp(ueR, G, Rb, uRb);
-  S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
   prim_to_cons_vjp(qeL, G, uLb, tLb);
   prim_to_cons_vjp(qeR, G, uRb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_U2 + (pr * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
     a[(A_U2 + (pr * 2 + 1) * 5 + m) * LE] = uRb[m];
+  }
+}
+
+// Both stage-2 pairs of axis d in one lane (traced states loaded once); the
+// traced-state adjoints of the face's two zones receive both pairs' parts.
+// Zone sides that are not on a pair's face get zero U2 entries from their
+// own lane.
+template <int d>
+__device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int ntiles,
+                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
+                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const StepConsts* __restrict__ sc) {
+  using S = double;
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  constexpr int pa = pair_index(d, t1), pb = pair_index(d, t2);
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  double* a = aw + B.eoff + z.e;
+  const bool ta = z.x[t1] >= 0 && z.x[t1] < B.n[t1];
+  const bool tb = z.x[t2] >= 0 && z.x[t2] < B.n[t2];
+  const bool up = z.x[d] + 1 <= B.n[d];
+  const bool va = ta && z.x[d] >= 0, vb = tb && z.x[d] >= 0;
+  if (!(ta && up)) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pa * 2 + 0) * 5 + m) * LE] = 0.0;
+  }
+  if (!(tb && up)) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pb * 2 + 0) * 5 + m) * LE] = 0.0;
+  }
+  if (!va) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pa * 2 + 1) * 5 + m) * LE] = 0.0;
+  }
+  if (!vb) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pb * 2 + 1) * 5 + m) * LE] = 0.0;
+  }
+  if (!va && !vb) return;
+  const long long sd = stride(z.E, d);
+  const S* w = work + B.eoff + z.e;
+  S qeL[5], qeR[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    qeL[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
+    qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
+  }
+  S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
+  if (va) adj_r2_pair<d, t1>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, G, sc, tLb, tRb);
+  if (vb) adj_r2_pair<d, t2>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, G, sc, tLb, tRb);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
     a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
     a[(A_TB + (d * 2 + 1) * 5 + m) * LE] += tRb[m];
   }
 }
 
-// Two launches: phase 0 runs pairs (0,1), (1,0), (2,0); phase 1 runs (0,2),
-// (1,2), (2,1) -- within a launch every pair has its own axis d, so the
-// traced-state accumulations never meet.
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r2(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const double* __restrict__ work,
                                                  long long LE, double* __restrict__ aw, Gas<double> G,
-                                                 const StepConsts* __restrict__ sc, int phase) {
-  const int k = blockIdx.y;
-  if (phase == 0) {
-    if (k == 0) adj_r2_body<0, 1>(tiles, ntiles, boxes, work, LE, aw, G, sc);
-    else if (k == 1) adj_r2_body<1, 0>(tiles, ntiles, boxes, work, LE, aw, G, sc);
-    else adj_r2_body<2, 0>(tiles, ntiles, boxes, work, LE, aw, G, sc);
-  } else {
-    if (k == 0) adj_r2_body<0, 2>(tiles, ntiles, boxes, work, LE, aw, G, sc);
-    else if (k == 1) adj_r2_body<1, 2>(tiles, ntiles, boxes, work, LE, aw, G, sc);
-    else adj_r2_body<2, 1>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+                                                 const StepConsts* __restrict__ sc) {
+  switch (blockIdx.y) {
+    case 0: adj_r2_body<0>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 1: adj_r2_body<1>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    default: adj_r2_body<2>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
   }
 }
 
@@ -343,13 +399,11 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
   const long long st = stride(NS, d);
   const S phi = work[E_FLAT * LE + B.eoff + z.e];
   double* a = aw + B.eoff + z.e;
-  S as5[5][5], aL[5], aR[5], a6[5];
+  S aL[5], aR[5], a6[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const S* p = prim + m * LS + base;
-#pragma unroll
-    for (int o = 0; o < 5; ++o) as5[m][o] = p[(o - 2) * st];
-    ppm_parabola(as5[m][0], as5[m][1], as5[m][2], as5[m][3], as5[m][4], phi, G, aL[m], aR[m], a6[m]);
+    ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL[m], aR[m], a6[m]);
   }
   const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
   S qpb[5], qmb[5];
@@ -363,15 +417,18 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
   S phib = 0;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
+    const S* p = prim + m * LS + base;
+    const S as5[5] = {p[-2 * st], p[-st], p[0], p[st], p[2 * st]};
     S ab[5] = {0, 0, 0, 0, 0};
-    ppm_parabola_vjp(as5[m], phi, G, aLb[m], aRb[m], a6b[m], ab, phib);
+    ppm_parabola_vjp(as5, phi, G, aLb[m], aRb[m], a6b[m], ab, phib);
     if (m == 0) ab[2] += rb;
     if (m == 1 + d) ab[2] += unb;
 #pragma unroll
     for (int o = 0; o < 5; ++o) a[(A_GT + m * 5 + o) * LE] = ab[o];
   }
   a[A_CB * LE] = cb;
-  a[A_PHB * LE] += phib;
+  if (d == 0) a[A_PHB * LE] = phib;
+  else a[A_PHB * LE] += phib;
 }
 
 // Gather of the trace contributions of axis d into the primitive adjoints of
@@ -403,9 +460,16 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather_trace(const Tile* __res
     for (int m = 0; m < 5; ++m) acc[m] += g[(A_GT + m * 5 + (o + 2)) * LE];
   }
   double* q = as + AS_QB * LS + B.poff + idx;
+  const double cb = in_e(j, B) ? aw[A_CB * LE + B.eoff + eidx(B, j[0], j[1], j[2])] : 0.0;
+  if (d == 0) {  // the first axis initialises the primitive adjoints
 #pragma unroll
-  for (int m = 0; m < 5; ++m) q[m * LS] += acc[m];
-  if (in_e(j, B)) q[5 * LS] += aw[A_CB * LE + B.eoff + eidx(B, j[0], j[1], j[2])];
+    for (int m = 0; m < 5; ++m) q[m * LS] = acc[m];
+    q[5 * LS] = cb;
+  } else {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) q[m * LS] += acc[m];
+    q[5 * LS] += cb;
+  }
 }
 
 // Flattening adjoint: the derivative of phi = min_d (1 - chi_d) through the
@@ -546,9 +610,14 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_prim(const Tile* __restrict__ 
 #pragma unroll
   for (int m = 0; m < 6; ++m) qb[m] = q[m * LS];
   prim_cell_vjp(uc, G, qb, ub);
+  // valid zones add the update's direct part (written by adj_update); ghost
+  // zones start from zero
+  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG;
+  const int x = (int)(idx % N0) - NG, y = (int)((idx / N0) % N1) - NG, zz = (int)(idx / ((long long)N0 * N1)) - NG;
+  const bool valid = x >= 0 && x < B.n[0] && y >= 0 && y < B.n[1] && zz >= 0 && zz < B.n[2];
   double* u = as + AS_UB * LS + B.poff + idx;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) u[c * LS] += ub[c];
+  for (int c = 0; c < 5; ++c) u[c * LS] = (valid ? u[c * LS] : 0.0) + ub[c];
 }
 
 // Transpose of the ghost fill: every valid zone of a source box sums the
@@ -573,7 +642,11 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ 
   double acc[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) acc[c] = as[(AS_UB + c) * LS + B.poff + li];
-  for (int k = inv_start[tl.box]; k < inv_start[tl.box + 1]; ++k) {
+  // every ghost copy reads a zone within NG of a face of its box
+  bool shell = false;
+  for (int d = 0; d < 3; ++d) shell = shell || z.x[d] < NG || z.x[d] >= B.n[d] - NG;
+  const int k0 = shell ? inv_start[tl.box] : 0, k1 = shell ? inv_start[tl.box + 1] : 0;
+  for (int k = k0; k < k1; ++k) {
     const FillDesc D = desc[inv_idx[k]];
     int lo[3], hi[3];
     bool hit = true;
@@ -631,18 +704,15 @@ hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, co
   G.grav = grav;
   const dim3 blk(L.tile);
   const unsigned zg = 4096;
-  // zero: all stored-grid planes, and the traced-grid planes that are
-  // accumulated or read where not written
-  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, as, (long long)A_SPLANES * L.LS);
-  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, aw + A_TB * L.LE, (long long)(30 + 30 + 60) * L.LE);
-  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, aw + A_PHB * L.LE, (long long)L.LE);
+  // every workspace entry is written before it is read (each reverse stage
+  // writes all entries it owns, zeros included); only the output's ghost
+  // zones need clearing
   hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, Ub, ULEN);
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
   hipLaunchKernelGGL(k_adj_update, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS, L.consts,
                      grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_r3, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL(k_adj_r2, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts, 0);
-  hipLaunchKernelGGL(k_adj_r2, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts, 1);
+  hipLaunchKernelGGL(k_adj_r2, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_trace<0>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
                      L.consts);
