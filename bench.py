@@ -141,6 +141,8 @@ def adjoint_costs(wl, nsteps, every, reps=3):
     t_fwd = timed(lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
     t_adj = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv))
     U0 = torch.from_numpy(wl.arena).to("cuda").requires_grad_(True)
+    P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=every).sum().backward()  # warm-up
+    U0.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     UT = P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=every)

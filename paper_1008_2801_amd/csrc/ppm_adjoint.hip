@@ -48,13 +48,6 @@ __device__ __forceinline__ long long eidx(const DevBox& B, int x, int y, int z) 
   return ((long long)(z + 1) * (B.n[1] + 2) + (y + 1)) * (B.n[0] + 2) + (x + 1);
 }
 
-constexpr int ZERO_THREADS = 256;
-__global__ void __launch_bounds__(ZERO_THREADS) k_zero(double* __restrict__ p, long long n) {
-  for (long long i = (long long)blockIdx.x * ZERO_THREADS + threadIdx.x; i < n;
-       i += (long long)gridDim.x * ZERO_THREADS)
-    p[i] = 0.0;
-}
-
 // Adjoint of the update and of the Heun source.
 __global__ void __launch_bounds__(MAX_TILE) k_adj_update(const Tile* __restrict__ tiles, int ntiles,
                                                      const DevBox* __restrict__ boxes,
@@ -592,10 +585,13 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather_flatten(const Tile* __r
   as[(AS_QB + 4) * LS + B.poff + idx] += acc;
 }
 
-// Primitive adjoints -> conserved adjoints on every stored zone.
+// Primitive adjoints -> conserved adjoints on every stored zone; the output's
+// ghost zones are cleared here (its valid zones are written by the fill
+// transpose).
 __global__ void __launch_bounds__(MAX_TILE) k_adj_prim(const Tile* __restrict__ tilesS, int ntiles,
                                                    const DevBox* __restrict__ boxes, const double* __restrict__ U,
-                                                   double* __restrict__ as, long long LS, Gas<double> G) {
+                                                   double* __restrict__ as, long long LS, Gas<double> G,
+                                                   double* __restrict__ Ub) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tilesS[tt];
@@ -618,11 +614,17 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_prim(const Tile* __restrict__ 
   double* u = as + AS_UB * LS + B.poff + idx;
 #pragma unroll
   for (int c = 0; c < 5; ++c) u[c * LS] = (valid ? u[c * LS] : 0.0) + ub[c];
+  if (!valid) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Ub[B.soff + idx + c * NS] = 0.0;
+  }
 }
 
 // Transpose of the ghost fill: every valid zone of a source box sums the
 // adjoints of the ghost zones that copied it (signs of reflections applied),
 // in the fixed order of the plan; writes the result to Ub (valid zones).
+// Only the descriptors listed for the zone's class are visited; zones more
+// than NG from every face have none.
 __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    const FillDesc* __restrict__ desc,
@@ -642,20 +644,20 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ 
   double acc[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) acc[c] = as[(AS_UB + c) * LS + B.poff + li];
-  // every ghost copy reads a zone within NG of a face of its box
-  bool shell = false;
-  for (int d = 0; d < 3; ++d) shell = shell || z.x[d] < NG || z.x[d] >= B.n[d] - NG;
-  const int k0 = shell ? inv_start[tl.box] : 0, k1 = shell ? inv_start[tl.box + 1] : 0;
+  const int cls = inv_axis_class(z.x[0], B.n[0]) + 4 * inv_axis_class(z.x[1], B.n[1]) +
+                  16 * inv_axis_class(z.x[2], B.n[2]);
+  const int k0 = inv_start[tl.box * INV_CLASSES + cls], k1 = inv_start[tl.box * INV_CLASSES + cls + 1];
   for (int k = k0; k < k1; ++k) {
     const FillDesc D = desc[inv_idx[k]];
     int lo[3], hi[3];
     bool hit = true;
-    for (int d = 0; d < 3 && hit; ++d) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
       const int y = z.x[d];
       if (D.a[d] == 1) { lo[d] = hi[d] = y - D.c[d]; }
       else if (D.a[d] == -1) { lo[d] = hi[d] = D.c[d] - y; }
-      else { if (y != D.c[d]) hit = false; lo[d] = D.lo[d]; hi[d] = D.hi[d]; }
-      if (hit && (lo[d] < D.lo[d] || hi[d] > D.hi[d])) hit = false;
+      else { hit = hit && y == D.c[d]; lo[d] = D.lo[d]; hi[d] = D.hi[d]; }
+      hit = hit && lo[d] >= D.lo[d] && hi[d] <= D.hi[d];
     }
     if (!hit) continue;
     const DevBox Bd = boxes[D.dst];
@@ -684,7 +686,7 @@ size_t adjoint_workspace_doubles(long long LS, long long LE) {
 
 hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
                           const void* work, void* awork, double gamma, double small_dens, double small_pres,
-                          int limiter, int flattening, int iters, int grav, const double g[3], long long ULEN,
+                          int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s) {
   const double* w = (const double*)work;
   const double* prim = w;
@@ -703,11 +705,8 @@ hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, co
   G.iters = iters;
   G.grav = grav;
   const dim3 blk(L.tile);
-  const unsigned zg = 4096;
-  // every workspace entry is written before it is read (each reverse stage
-  // writes all entries it owns, zeros included); only the output's ghost
-  // zones need clearing
-  hipLaunchKernelGGL(k_zero, dim3(zg), dim3(ZERO_THREADS), 0, s, Ub, ULEN);
+  // every workspace entry is written before it is read: each reverse stage
+  // writes all entries it owns, zeros included
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
   hipLaunchKernelGGL(k_adj_update, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS, L.consts,
                      grav, g[0], g[1], g[2]);
@@ -725,7 +724,7 @@ hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, co
   hipLaunchKernelGGL(k_adj_gather_trace<2>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
   hipLaunchKernelGGL(k_adj_flatten, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
   hipLaunchKernelGGL(k_adj_gather_flatten, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
-  hipLaunchKernelGGL(k_adj_prim, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, U, as, L.LS, G);
+  hipLaunchKernelGGL(k_adj_prim, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, U, as, L.LS, G, Ub);
   hipLaunchKernelGGL(k_adj_fill, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, L.desc, L.inv_start, L.inv_idx, as,
                      L.LS, Ub);
   return hipGetLastError();

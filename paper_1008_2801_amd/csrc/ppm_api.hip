@@ -485,14 +485,39 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
   ctx->LS = round_up(ps, 64);
   ctx->LE = round_up(pe, 64);
 
-  // inverse of the fill plan: descriptors grouped by source box
-  std::vector<int> inv_start(nb + 1, 0), inv_idx;
-  for (const FillDesc& D : ctx->plan->desc) inv_start[D.src + 1]++;
-  for (int b = 0; b < nb; ++b) inv_start[b + 1] += inv_start[b];
-  inv_idx.assign(ctx->plan->desc.size(), 0);
+  // inverse of the fill plan: for every source box and zone class (per axis:
+  // within NG of the low face, of the high face, of both or of neither) the
+  // descriptors that can copy a zone of that class, in plan order
+  std::vector<int> inv_start((size_t)nb * INV_CLASSES + 1, 0), inv_idx;
   {
+    const std::vector<FillDesc>& desc = ctx->plan->desc;
+    std::vector<unsigned long long> cmask(desc.size(), 0);  // bit per class
+    for (size_t k = 0; k < desc.size(); ++k) {
+      const FillDesc& D = desc[k];
+      const int* ns = layout->boxes[D.src].lo;
+      unsigned axm[3];
+      for (int d = 0; d < 3; ++d) {
+        const int n = layout->boxes[D.src].hi[d] - ns[d] + 1;
+        int y0, y1;
+        if (D.a[d] == 1) { y0 = D.lo[d] + D.c[d]; y1 = D.hi[d] + D.c[d]; }
+        else if (D.a[d] == -1) { y0 = D.c[d] - D.hi[d]; y1 = D.c[d] - D.lo[d]; }
+        else { y0 = y1 = D.c[d]; }
+        axm[d] = 0;
+        for (int y = std::max(y0, 0); y <= std::min(y1, n - 1); ++y) axm[d] |= 1u << inv_axis_class(y, n);
+      }
+      for (int c = 0; c < INV_CLASSES; ++c)
+        if ((axm[0] >> (c & 3) & 1) && (axm[1] >> ((c >> 2) & 3) & 1) && (axm[2] >> (c >> 4) & 1))
+          cmask[k] |= 1ull << c;
+    }
+    for (size_t k = 0; k < desc.size(); ++k)
+      for (int c = 0; c < INV_CLASSES; ++c)
+        if (cmask[k] >> c & 1) inv_start[(size_t)desc[k].src * INV_CLASSES + c + 1]++;
+    for (size_t i = 0; i + 1 < inv_start.size(); ++i) inv_start[i + 1] += inv_start[i];
+    inv_idx.assign(inv_start.back(), 0);
     std::vector<int> fillp(inv_start.begin(), inv_start.end() - 1);
-    for (size_t k = 0; k < ctx->plan->desc.size(); ++k) inv_idx[fillp[ctx->plan->desc[k].src]++] = (int)k;
+    for (size_t k = 0; k < desc.size(); ++k)
+      for (int c = 0; c < INV_CLASSES; ++c)
+        if (cmask[k] >> c & 1) inv_idx[fillp[(size_t)desc[k].src * INV_CLASSES + c]++] = (int)k;
   }
   build_tiles(*ctx);
   hipError_t e;
@@ -687,7 +712,7 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
   if (rc) return rc;
   return ctx->hip(launch_adjoint(L, nS, nE, U, Unew_bar, U_bar, ctx->work, ctx->awork, params->gamma,
                                  params->small_dens, params->small_pres, params->limiter, params->flattening,
-                                 params->riemann_iters, grav, params->grav, (long long)ctx->off.back(), s),
+                                 params->riemann_iters, grav, params->grav, s),
                   "adjoint");
 }
 

@@ -43,6 +43,11 @@ struct FillDesc {
   int count;
 };
 
+// Zone classes of the fill transpose: per axis, bit 0 = within NG of the low
+// face, bit 1 = within NG of the high face; class = c0 + 4 c1 + 16 c2.
+constexpr int INV_CLASSES = 64;
+inline __host__ __device__ int inv_axis_class(int y, int n) { return (y < NG ? 1 : 0) | (y >= n - NG ? 2 : 0); }
+
 // Per-step constants formed on the device from dt (so that a graph can take
 // dt from device memory).  The reconstruction copies exist in FP64 and FP32.
 struct StepConsts {
@@ -71,7 +76,7 @@ struct DevLevel {
   const long long* desc_start;  // exclusive prefix of zone counts, ndesc+1
   StepConsts* consts;
   int* flags;
-  const int* inv_start;  // nbox + 1: descriptors whose source is each box
+  const int* inv_start;  // nbox * INV_CLASSES + 1: descriptors per (source box, zone class)
   const int* inv_idx;
   long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
   int tile;            // zones per tile of the tile lists (threads per workgroup)
@@ -99,7 +104,7 @@ hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int t
 size_t adjoint_workspace_doubles(long long LS, long long LE);
 hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
                           const void* work, void* awork, double gamma, double small_dens, double small_pres,
-                          int limiter, int flattening, int iters, int grav, const double g[3], long long ULEN,
+                          int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s);
 // Events recorded by launch_step when ev is non-null: before each of the 7
 // stage kernels and after the last (STEP_EVENTS in all).

@@ -63,7 +63,8 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
       rsb += rb_; usb += ub_; pb += pb_;
     } else {
       const S D = tl - hd;
-      const S w = -hd / D;
+      const S iD = ONE / D;
+      const S w = -hd * iD;
       const S wb = rb_ * (rs - ro) + ub_ * (us - uo) + pb_ * (p - po);
       rob += (ONE - w) * rb_;
       rsb += w * rb_;
@@ -71,8 +72,8 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
       usb += w * ub_;
       pob += (ONE - w) * pb_;
       pb += w * pb_;
-      const S hdb = -wb * tl / (D * D);
-      const S tlb = wb * hd / (D * D);
+      const S hdb = -wb * tl * iD * iD;
+      const S tlb = wb * hd * iD * iD;
       uob += hdb;
       cob -= hdb;
       usb += tlb;
@@ -80,8 +81,11 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
     }
   }
   // cst = sqrt(gamma p / rs), co = C / rho
-  pb += cstb * G.gamma / (TWO * rs * cst);
-  rsb -= cstb * cst / (TWO * rs);
+  if (cstb != S(0)) {
+    const S h = cstb * HALF / (rs * cst);
+    pb += h * G.gamma;
+    rsb -= h * cst * cst;
+  }
   Cb += cob * irho;
   irhob += cob * C;
   // rs = 1 / vstar (floor frozen)
@@ -92,6 +96,9 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
   iWb -= vstarb * (p - po) * TWO * iW;
   rob -= irhob * irho * irho;
 }
+
+// Newton steps whose inputs the Riemann reverse keeps in registers.
+constexpr int RIEM_KEEP = 3;
 
 // One Newton step of the two-shock iteration, forward (returns the new p).
 template <class S>
@@ -126,8 +133,9 @@ PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   const S pn = p - dU / Q;
   if (pn < G.small_pres) return S(0);  // floor bound: the output does not depend on p
   S pb = pnb;
-  const S dUb = -pnb / Q;
-  const S Qb = pnb * dU / (Q * Q);
+  const S iQ = ONE / Q;
+  const S dUb = -pnb * iQ;
+  const S Qb = pnb * dU * iQ * iQ;
   const S usrb = dUb, uslb = -dUb;
   ulb += uslb;
   pb -= uslb * iwl;
@@ -148,7 +156,8 @@ PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   const S wlb = -iwlb * iwl * iwl, wrb = -iwrb * iwr * iwr;
   clb += wlb * sl;
   crb += wrb * sr;
-  const S alb = wlb * cl / (TWO * sl), arb = wrb * cr / (TWO * sr);
+  // cl / (2 sl) = cl^2 / (2 wl)
+  const S alb = wlb * HALF * cl * cl * iwl, arb = wrb * HALF * cr * cr * iwr;
   pb += alb * G.beta * ipl + arb * G.beta * ipr;
   iplb += alb * G.beta * p;
   iprb += arb * G.beta * p;
@@ -169,8 +178,17 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   const bool fl0 = p0r < G.small_pres;
   const S p0 = smax(p0r, G.small_pres);
   const S ipl = ONE / pl, ipr = ONE / pr;
+  // the inputs of the first RIEM_KEEP Newton steps are kept for the reverse
+  // sweep (fully unrolled, so they stay in registers); later ones are
+  // recomputed from the last kept one
+  S pit[RIEM_KEEP];
   S pst = p0;
-  for (int it = 0; it < G.iters; ++it) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
+#pragma unroll
+  for (int it = 0; it < RIEM_KEEP; ++it) {
+    pit[it] = pst;
+    if (it < G.iters) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
+  }
+  for (int it = RIEM_KEEP; it < G.iters; ++it) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
   const S all = ONE + G.beta * (pst * ipl - ONE), alr = ONE + G.beta * (pst * ipr - ONE);
   const S sl = ssqrt(all), sr = ssqrt(alr);
   const S wl = cl * sl, wr = cr * sr;
@@ -230,7 +248,8 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
     Rb[1 + t2] += HALF * gb[4];
   }
   // us = NU / DU
-  const S NUb = usb / DU, DUb = -usb * us / DU;
+  const S iDU = ONE / DU;
+  const S NUb = usb * iDU, DUb = -usb * us * iDU;
   S wlb = NUb * ul + DUb, wrb = NUb * ur + DUb;
   ulb += NUb * wl;
   urb += NUb * wr;
@@ -242,21 +261,26 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   crb += wrb * sr;
   S iplb = S(0), iprb = S(0);
   {
-    const S alb = wlb * cl / (TWO * sl), arb = wrb * cr / (TWO * sr);
+    const S alb = wlb * HALF * cl * cl * iwl, arb = wrb * HALF * cr * cr * iwr;
     pstb += alb * G.beta * ipl + arb * G.beta * ipr;
     iplb += alb * G.beta * pst;
     iprb += arb * G.beta * pst;
   }
-  // Newton iterations in reverse, each input recomputed from p0
+  // Newton iterations in reverse
   S pb = pstb;
-  for (int k = G.iters - 1; k >= 0; --k) {
-    S pk = p0;
-    for (int j = 0; j < k; ++j) pk = riem_iter(pk, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
+  for (int k = G.iters - 1; k >= RIEM_KEEP; --k) {
+    S pk = pit[RIEM_KEEP - 1];
+    for (int j = RIEM_KEEP - 1; j < k; ++j) pk = riem_iter(pk, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
     pb = riem_iter_vjp(pk, cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb, iprb);
   }
+#pragma unroll
+  for (int k = RIEM_KEEP - 1; k >= 0; --k)
+    if (k < G.iters)
+      pb = riem_iter_vjp(pit[k], cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb, iprb);
   // acoustic guess (floor frozen)
   if (!fl0) {
-    const S N0b = pb / D0, D0b = -pb * p0r / D0;
+    const S iD0 = ONE / D0;
+    const S N0b = pb * iD0, D0b = -pb * p0r * iD0;
     crb += N0b * (pl + cl * (ul - ur));
     plb += N0b * cr;
     clb += N0b * (pr + cr * (ul - ur));
@@ -268,10 +292,12 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   }
   plb -= iplb * ipl * ipl;
   prb -= iprb * ipr * ipr;
-  plb += clb * G.gamma * rl / (TWO * cl);
-  rlb += clb * G.gamma * pl / (TWO * cl);
-  prb += crb * G.gamma * rr / (TWO * cr);
-  rrb += crb * G.gamma * pr / (TWO * cr);
+  // cl^2 = gamma pl rl: d cl = gamma (rl d pl + pl d rl) / (2 cl)
+  const S hl = clb * HALF * G.gamma / cl, hr = crb * HALF * G.gamma / cr;
+  plb += hl * rl;
+  rlb += hl * pl;
+  prb += hr * rr;
+  rrb += hr * pr;
   Lb[0] += rlb; Lb[1 + d] += ulb; Lb[4] += plb;
   Rb[0] += rrb; Rb[1 + d] += urb; Rb[4] += prb;
 }
@@ -300,10 +326,11 @@ PPM_HD void prim_tail_vjp(S r, S u, S v, S w, const Gas<S>& G, S rb, S ub, S vb,
   ub += keb * r * u;
   vb += keb * r * v;
   wb += keb * r * w;
-  Ub[1] += ub / r;
-  Ub[2] += vb / r;
-  Ub[3] += wb / r;
-  rb -= (ub * u + vb * v + wb * w) / r;
+  const S ir = ONE / r;
+  Ub[1] += ub * ir;
+  Ub[2] += vb * ir;
+  Ub[3] += wb * ir;
+  rb -= (ub * u + vb * v + wb * w) * ir;
   if (!rfloor) Ub[0] += rb;
 }
 
@@ -329,8 +356,9 @@ PPM_HD void prim_cell_vjp(const S U[5], const Gas<S>& G, const S qb[6], S Ub[5])
   const bool pfl = praw < G.small_pres;
   const S p = smax(praw, G.small_pres);
   const S c = ssqrt(G.gamma * p / r);
-  S pb = qb[4] + qb[5] * G.gamma / (TWO * r * c);
-  const S rb = qb[0] - qb[5] * c / (TWO * r);
+  const S h = qb[5] * HALF / (r * c);
+  S pb = qb[4] + h * G.gamma;
+  const S rb = qb[0] - h * c * c;
   if (pfl) pb = S(0);
   prim_tail_vjp(r, u, v, w, G, rb, qb[1], qb[2], qb[3], pb, Ub, false);
 }
@@ -543,8 +571,9 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
   cb += TWO * c * c2b;
   rb += rcb * c;
   cb += rcb * r;
-  cb += corb / r;
-  rb -= corb * cor / r;
+  const S ir = ONE / r;
+  cb += corb * ir;
+  rb -= corb * cor * ir;
   for (int m = 0; m < 5; ++m) { aRb[m] += dab[m]; aLb[m] -= dab[m]; }
 }
 

@@ -472,18 +472,18 @@ def _autograd():
             lev, n, every = ctx.level, ctx.nsteps, ctx.every
             g = g.contiguous().clone()
             Ub = torch.empty_like(g)
+            # the filled input states of one segment; the segment's last
+            # step is not replayed (its output is not needed)
+            slots = [torch.empty_like(g) for _ in range(min(every, n))]
             for s0 in reversed(range(0, n, every)):
                 s1 = min(n, s0 + every)
-                filled = []
-                U = ctx.ckpts[s0].clone()
+                slots[0].copy_(ctx.ckpts[s0])
                 for k in range(s0, s1):
-                    lev.fill_boundary(U)
-                    filled.append(U.clone())
-                    V = torch.zeros_like(U)
-                    lev.hydro_step(U, V, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
-                    U = V
+                    lev.fill_boundary(slots[k - s0])
+                    if k + 1 < s1:
+                        lev.hydro_step(slots[k - s0], slots[k + 1 - s0], ctx.dx, ctx.p, dt_dev=ctx.dts[k])
                 for k in reversed(range(s0, s1)):
-                    lev.hydro_step_adjoint(filled[k - s0], g, Ub, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
+                    lev.hydro_step_adjoint(slots[k - s0], g, Ub, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
                     g, Ub = Ub, g
             return g, None, None, None, None, None, None
 
