@@ -9,10 +9,11 @@
 //                 and traced-state adjoints
 //   adj_riemann2  stage-2 fluxes' adjoint (from U3b) -> U2b, traced states
 //   adj_riemann1  stage-1 fluxes' adjoint (from U2b) -> traced states
-//   adj_trace     per axis: traced-state adjoints -> per-zone contributions
-//                 to the primitives of the 5-zone stencil, then a gather
-//   adj_flatten   flattening adjoint -> pressure stencil, then a gather
-//   adj_prim      primitive adjoints -> conserved adjoints (all stored zones)
+//   adj_trace     traced-state adjoints -> per-zone contributions to the
+//                 primitives of the 5-zone stencil of each axis
+//   adj_flatten   flattening adjoint -> contributions to the pressure stencil
+//   adj_gather    per stored zone: the contributions that reach it, then the
+//                 primitive conversion's adjoint -> conserved adjoints
 //   adj_fill      ghost adjoints gathered into their owning valid zones
 // Every reverse stage writes only the entries it owns or accumulates through
 // a gather in a fixed order: no atomics, results reproducible bit for bit.
@@ -26,20 +27,22 @@
 namespace ppm {
 namespace {
 
-// Adjoint workspace planes: traced grid (A_*) and stored grid (AS_*).
+// Adjoint workspace planes: traced grid (A_*) and stored grid (AS_*).  The
+// trace reverse's outputs (GT, CB, PHB) reuse the corrected-state planes,
+// which are dead once the stage-1 reverse has run.
 constexpr int A_UF = 0;              // 5: adjoint of the pre-source state (valid zones, else 0)
 constexpr int A_TB = A_UF + 5;       // 30: traced-state adjoints [d][side][m]
 constexpr int A_U3 = A_TB + 30;      // 30: stage-3 corrected-state adjoints [d][side][m]
 constexpr int A_U2 = A_U3 + 30;      // 60: stage-2 corrected-state adjoints [pair][side][m]
-constexpr int A_GT = A_U2 + 60;      // 25: trace contributions [m][offset + 2]
-constexpr int A_CB = A_GT + 25;      // 1: sound-speed adjoint of the current axis
-constexpr int A_PHB = A_CB + 1;      // 1: flattening-coefficient adjoint
-constexpr int A_GF = A_PHB + 1;      // 7: flattening contributions to p [offset + 3]
+constexpr int A_GT = A_U3;           // 75: trace contributions [d][m][offset + 2]
+constexpr int A_CB = A_GT + 75;      // 3: sound-speed adjoint per axis
+constexpr int A_PHB = A_CB + 3;      // 3: flattening-coefficient adjoint per axis
+constexpr int A_GF = A_U2 + 60;      // 7: flattening contributions to p [offset + 3]
 constexpr int A_SEL = A_GF + 7;      // 1: axis selected by the flattening minimum (-1: none)
 constexpr int A_EPLANES = A_SEL + 1;
-constexpr int AS_QB = 0;             // 6: primitive adjoints (rho, u, v, w, p, c)
-constexpr int AS_UB = 6;             // 5: conserved adjoints
-constexpr int A_SPLANES = 11;
+static_assert(A_PHB + 3 <= A_U2 + 60, "trace reverse outputs must fit in the corrected-state planes");
+constexpr int AS_UB = 0;             // 5: conserved adjoints
+constexpr int A_SPLANES = 5;
 
 __device__ __forceinline__ bool in_e(const int x[3], const DevBox& B) {
   return x[0] >= -1 && x[0] <= B.n[0] && x[1] >= -1 && x[1] <= B.n[1] && x[2] >= -1 && x[2] <= B.n[2];
@@ -371,8 +374,10 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ ti
 }
 
 // Trace adjoint of axis d: per traced zone, the contributions to the
-// primitives of its 5-zone stencil along d (A_GT), the sound speed (A_CB)
-// and the flattening coefficient (A_PHB, accumulated over the axes).
+// primitives of its 5-zone stencil along d (GT of axis d), the sound speed
+// (CB of axis d) and the flattening coefficient (PHB of axis d).
+// One launch per axis (the three bodies in one kernel would share the
+// register budget of the largest and spill).
 template <int d>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
                                                     const DevBox* __restrict__ boxes,
@@ -417,52 +422,10 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
     if (m == 0) ab[2] += rb;
     if (m == 1 + d) ab[2] += unb;
 #pragma unroll
-    for (int o = 0; o < 5; ++o) a[(A_GT + m * 5 + o) * LE] = ab[o];
+    for (int o = 0; o < 5; ++o) a[(A_GT + (d * 5 + m) * 5 + o) * LE] = ab[o];
   }
-  a[A_CB * LE] = cb;
-  if (d == 0) a[A_PHB * LE] = phib;
-  else a[A_PHB * LE] += phib;
-}
-
-// Gather of the trace contributions of axis d into the primitive adjoints of
-// every stored zone: qb_m(j) += sum over o of GT[m][o](j - o e_d).
-template <int d>
-__global__ void __launch_bounds__(MAX_TILE) k_adj_gather_trace(const Tile* __restrict__ tilesS, int ntiles,
-                                                           const DevBox* __restrict__ boxes,
-                                                           const double* __restrict__ aw, long long LE,
-                                                           double* __restrict__ as, long long LS) {
-  const int tt = xcd_tile(ntiles);
-  if (tt < 0) return;
-  const Tile tl = tilesS[tt];
-  const DevBox B = boxes[tl.box];
-  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
-  const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= tl.end) return;
-  int j[3];
-  j[0] = (int)(idx % NS[0]) - NG;
-  j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
-  j[2] = (int)(idx / ((long long)NS[0] * NS[1])) - NG;
-  double acc[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-  for (int o = -2; o <= 2; ++o) {
-    int y[3] = {j[0], j[1], j[2]};
-    y[d] -= o;
-    if (!in_e(y, B)) continue;
-    const double* g = aw + B.eoff + eidx(B, y[0], y[1], y[2]);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) acc[m] += g[(A_GT + m * 5 + (o + 2)) * LE];
-  }
-  double* q = as + AS_QB * LS + B.poff + idx;
-  const double cb = in_e(j, B) ? aw[A_CB * LE + B.eoff + eidx(B, j[0], j[1], j[2])] : 0.0;
-  if (d == 0) {  // the first axis initialises the primitive adjoints
-#pragma unroll
-    for (int m = 0; m < 5; ++m) q[m * LS] = acc[m];
-    q[5 * LS] = cb;
-  } else {
-#pragma unroll
-    for (int m = 0; m < 5; ++m) q[m * LS] += acc[m];
-    q[5 * LS] += cb;
-  }
+  a[(A_CB + d) * LE] = cb;
+  a[(A_PHB + d) * LE] = phib;
 }
 
 // Flattening adjoint: the derivative of phi = min_d (1 - chi_d) through the
@@ -488,17 +451,17 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
     S phi = ONE;
     int dsel = 0, osel = 0;
     bool live = false;
-    S pd[3][7];
-    int osl[3];
-    bool lv[3];
+    S ps[7];  // pressures along the selected axis
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
       const long long st = stride(NS, d);
       const S* pp = prim + 4 * LS + base;
       const S* uu = prim + (1 + d) * LS + base;
       S p[7], u[5];
+#pragma unroll
       for (int o = -3; o <= 3; ++o) p[o + 3] = pp[o * st];
+#pragma unroll
       for (int o = -2; o <= 2; ++o) u[o + 2] = uu[o * st];
-      for (int o = 0; o < 7; ++o) pd[d][o] = p[o];
       // chit(o): value and whether its derivative is live
       auto chit = [&](int o, bool& alive) -> S {
         const S dp1 = p[o + 4] - p[o + 2];
@@ -524,19 +487,27 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
         chi = smax(m1, cp);
         o = (m1 < cp) ? 1 : o1;
       }
-      osl[d] = o;
-      lv[d] = (o == -1) ? am : (o == 0 ? a0 : ap);
+      const bool lv = (o == -1) ? am : (o == 0 ? a0 : ap);
       const S val = ONE - chi;
-      if (d == 0 || val < phi) { phi = val; dsel = d; }
+      if (d == 0 || val < phi) {
+        phi = val;
+        dsel = d;
+        osel = o;
+        live = lv;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) ps[k] = p[k];
+      }
     }
-    osel = osl[dsel];
-    live = lv[dsel];
-    const double phib = a[A_PHB * LE];
+    const double phib = (a[A_PHB * LE] + a[(A_PHB + 1) * LE]) + a[(A_PHB + 2) * LE];
     if (live && phib != 0.0) {
-      const S* p = pd[dsel];
       const int o = osel;
-      const S dp1 = p[o + 4] - p[o + 2];
-      const S dp2 = p[o + 5] - p[o + 1];
+      // p index k <-> offset k - 3; the detector at o uses k = o+1, o+2, o+4, o+5
+      const S p1 = (o < 0) ? ps[0] : (o == 0 ? ps[1] : ps[2]);
+      const S p2 = (o < 0) ? ps[1] : (o == 0 ? ps[2] : ps[3]);
+      const S p4 = (o < 0) ? ps[3] : (o == 0 ? ps[4] : ps[5]);
+      const S p5 = (o < 0) ? ps[4] : (o == 0 ? ps[5] : ps[6]);
+      const S dp1 = p4 - p2;
+      const S dp2 = p5 - p1;
       const S a2 = sabs(dp2);
       const bool use2 = !(a2 < G.small_pres);
       const S D = smax(a2, G.small_pres);
@@ -545,11 +516,15 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
       const S dp1b = zetab * ((dp1 < S(0)) ? -ONE : ONE) / D;
       const S Db = -zetab * zeta / D;
       const S dp2b = use2 ? Db * ((dp2 < S(0)) ? -ONE : ONE) : S(0);
-      // offsets relative to the zone: p index k <-> offset k - 3
-      gf[o + 4] += dp1b;
-      gf[o + 2] -= dp1b;
-      gf[o + 5] += dp2b;
-      gf[o + 1] -= dp2b;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        S v = S(0);
+        if (k == o + 4) v += dp1b;
+        if (k == o + 2) v -= dp1b;
+        if (k == o + 5) v += dp2b;
+        if (k == o + 1) v -= dp2b;
+        gf[k] = v;
+      }
       sel = dsel;
     }
   }
@@ -558,65 +533,70 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
   a[A_SEL * LE] = (double)sel;
 }
 
-__global__ void __launch_bounds__(MAX_TILE) k_adj_gather_flatten(const Tile* __restrict__ tilesS, int ntiles,
-                                                             const DevBox* __restrict__ boxes,
-                                                             const double* __restrict__ aw, long long LE,
-                                                             double* __restrict__ as, long long LS) {
+// Gather of all primitive adjoints of a stored zone (the trace contributions
+// of the zones whose stencils cover it, its sound-speed adjoints, the
+// flattening contributions), then the reverse of its primitive conversion:
+// UB = (valid ? update part : 0) + J^T qb.  Clears the output's ghost zones
+// (its valid zones are written by the fill transpose).
+__global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict__ tilesS, int ntiles,
+                                                     const DevBox* __restrict__ boxes,
+                                                     const double* __restrict__ aw, long long LE,
+                                                     const double* __restrict__ U, double* __restrict__ as,
+                                                     long long LS, Gas<double> G, double* __restrict__ Ub) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tilesS[tt];
   const DevBox B = boxes[tl.box];
   const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+  const long long NSS = (long long)NS[0] * NS[1] * NS[2];
   const long long idx = (long long)tl.start + threadIdx.x;
   if (idx >= tl.end) return;
   int j[3];
   j[0] = (int)(idx % NS[0]) - NG;
   j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
   j[2] = (int)(idx / ((long long)NS[0] * NS[1])) - NG;
-  double acc = 0.0;
-  for (int d = 0; d < 3; ++d)
-    for (int o = -3; o <= 3; ++o) {
+  double qb[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
       int y[3] = {j[0], j[1], j[2]};
       y[d] -= o;
       if (!in_e(y, B)) continue;
-      const long long e = B.eoff + eidx(B, y[0], y[1], y[2]);
-      if (aw[A_SEL * LE + e] == (double)d) acc += aw[(A_GF + o + 3) * LE + e];
+      const double* g = aw + B.eoff + eidx(B, y[0], y[1], y[2]);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) qb[m] += g[(A_GT + (d * 5 + m) * 5 + (o + 2)) * LE];
     }
-  as[(AS_QB + 4) * LS + B.poff + idx] += acc;
-}
-
-// Primitive adjoints -> conserved adjoints on every stored zone; the output's
-// ghost zones are cleared here (its valid zones are written by the fill
-// transpose).
-__global__ void __launch_bounds__(MAX_TILE) k_adj_prim(const Tile* __restrict__ tilesS, int ntiles,
-                                                   const DevBox* __restrict__ boxes, const double* __restrict__ U,
-                                                   double* __restrict__ as, long long LS, Gas<double> G,
-                                                   double* __restrict__ Ub) {
-  const int tt = xcd_tile(ntiles);
-  if (tt < 0) return;
-  const Tile tl = tilesS[tt];
-  const DevBox B = boxes[tl.box];
-  const long long NS = (long long)(B.n[0] + 2 * NG) * (B.n[1] + 2 * NG) * (B.n[2] + 2 * NG);
-  const long long idx = (long long)tl.start + threadIdx.x;
-  if (idx >= tl.end) return;
-  double uc[5], qb[6], ub[5] = {0, 0, 0, 0, 0};
+  }
+  if (in_e(j, B)) {
+    const double* g = aw + B.eoff + eidx(B, j[0], j[1], j[2]);
+    qb[5] = (g[A_CB * LE] + g[(A_CB + 1) * LE]) + g[(A_CB + 2) * LE];
+  }
+  if (G.flattening) {
+    double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) uc[c] = U[B.soff + idx + c * NS];
-  const double* q = as + AS_QB * LS + B.poff + idx;
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-  for (int m = 0; m < 6; ++m) qb[m] = q[m * LS];
+      for (int o = -3; o <= 3; ++o) {
+        int y[3] = {j[0], j[1], j[2]};
+        y[d] -= o;
+        if (!in_e(y, B)) continue;
+        const long long e = B.eoff + eidx(B, y[0], y[1], y[2]);
+        if (aw[A_SEL * LE + e] == (double)d) acc += aw[(A_GF + o + 3) * LE + e];
+      }
+    qb[4] += acc;
+  }
+  double uc[5], ub[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) uc[c] = U[B.soff + idx + c * NSS];
   prim_cell_vjp(uc, G, qb, ub);
-  // valid zones add the update's direct part (written by adj_update); ghost
-  // zones start from zero
-  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG;
-  const int x = (int)(idx % N0) - NG, y = (int)((idx / N0) % N1) - NG, zz = (int)(idx / ((long long)N0 * N1)) - NG;
-  const bool valid = x >= 0 && x < B.n[0] && y >= 0 && y < B.n[1] && zz >= 0 && zz < B.n[2];
+  const bool valid = j[0] >= 0 && j[0] < B.n[0] && j[1] >= 0 && j[1] < B.n[1] && j[2] >= 0 && j[2] < B.n[2];
   double* u = as + AS_UB * LS + B.poff + idx;
 #pragma unroll
   for (int c = 0; c < 5; ++c) u[c * LS] = (valid ? u[c * LS] : 0.0) + ub[c];
   if (!valid) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Ub[B.soff + idx + c * NS] = 0.0;
+    for (int c = 0; c < 5; ++c) Ub[B.soff + idx + c * NSS] = 0.0;
   }
 }
 
@@ -715,16 +695,13 @@ hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, co
   hipLaunchKernelGGL(k_adj_r1, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_trace<0>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
                      L.consts);
-  hipLaunchKernelGGL(k_adj_gather_trace<0>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
   hipLaunchKernelGGL(k_adj_trace<1>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
                      L.consts);
-  hipLaunchKernelGGL(k_adj_gather_trace<1>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
   hipLaunchKernelGGL(k_adj_trace<2>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
                      L.consts);
-  hipLaunchKernelGGL(k_adj_gather_trace<2>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
-  hipLaunchKernelGGL(k_adj_flatten, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
-  hipLaunchKernelGGL(k_adj_gather_flatten, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, as, L.LS);
-  hipLaunchKernelGGL(k_adj_prim, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, U, as, L.LS, G, Ub);
+  if (G.flattening)
+    hipLaunchKernelGGL(k_adj_flatten, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
+  hipLaunchKernelGGL(k_adj_gather, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, U, as, L.LS, G, Ub);
   hipLaunchKernelGGL(k_adj_fill, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, L.desc, L.inv_start, L.inv_idx, as,
                      L.LS, Ub);
   return hipGetLastError();
