@@ -39,6 +39,65 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
+# Sources whose change invalidates recorded counter traffic (kernels, their
+# arithmetic and the tile lists that shape the launches).
+TRAFFIC_SOURCES = ("paper_1008_2801_amd/csrc/ppm_kernels.hip", "paper_1008_2801_amd/csrc/ppm_math.h",
+                   "paper_1008_2801_amd/csrc/ppm_device.h", "paper_1008_2801_amd/csrc/ppm_internal.h",
+                   "paper_1008_2801_amd/csrc/ppm_api.hip")
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record_path(kernel, workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+
+
+def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor, write_factor):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernel from two
+    rocprofv3 --pmc runs, times the factors a plain copy of known size gives,
+    stored with the digest of the kernel sources and the tiling."""
+    import csv
+
+    def mean_kib(path, counter):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                if r["Counter_Name"] == counter and f"k_{kernel}<double>" in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit(f"no {counter} records of k_{kernel}<double> in {path}")
+        return sum(vals) / len(vals), len(vals)
+    f_kib, nf = mean_kib(fetch_csv, "FETCH_SIZE")
+    w_kib, nw = mean_kib(write_csv, "WRITE_SIZE")
+    rec = {"kernel": f"k_{kernel}<double>", "workload": workload, "tiling": list(tiling),
+           "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib, "dispatches": [nf, nw],
+           "fetch_factor": fetch_factor, "write_factor": write_factor,
+           "read_bytes_per_launch": f_kib * 1024 * fetch_factor,
+           "write_bytes_per_launch": w_kib * 1024 * write_factor,
+           "sources_sha256": sources_digest()}
+    rec["traffic_bytes_per_launch"] = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    with open(traffic_record_path(kernel, workload), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def recorded_traffic(kernel, workload, tiling):
+    """HBM bytes per launch from the recorded counters, or None when there is
+    no record or the kernels or tiling changed since it was taken."""
+    try:
+        with open(traffic_record_path(kernel, workload)) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != sources_digest() or list(rec.get("tiling", [])) != list(tiling):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def stage_units(n):
     """Units each stage kernel processes on one box of valid extents n."""
     import numpy as np
@@ -191,10 +250,17 @@ def main():
     ap.add_argument("--cpu-window", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiling")
+    ap.add_argument("--tiling", default=None, help="'tile,strip_rows': use this tiling instead of autotuning")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 512-box batched / per-box / graph measurements")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only measure the adjoint/forward cost on the 128^3 differentiation workload")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record of the dominant kernel from two rocprofv3 --pmc "
+                         "counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--record-kernel", default="riemann2")
+    ap.add_argument("--counter-factors", default="2.0,1.0",
+                    help="FETCH_SIZE and WRITE_SIZE scale factors from the copy calibration")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -202,6 +268,13 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU box distribution is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
+
+    if args.record_traffic:
+        ff, wf = (float(v) for v in args.counter_factors.split(","))
+        t_, s_ = (int(v) for v in args.tiling.split(","))
+        record_traffic(args.record_traffic[0], args.record_traffic[1], args.record_kernel, args.workload,
+                       (t_, s_), ff, wf)
+        return
 
     import torch
     from paper_1008_2801_amd import ppm as P
@@ -233,7 +306,11 @@ def main():
     p = P.params(gamma=wl.gamma, precision=wl.precision)
     lev.ensure_workspace(p.precision)
     dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
-    if not args.no_autotune:
+    if args.tiling:
+        t_, s_ = (int(v) for v in args.tiling.split(","))
+        lev.set_tiling(t_, s_)
+        tiling = lev.get_tiling()
+    elif not args.no_autotune:
         Uf = U.clone()
         lev.fill_boundary(Uf)
         tiling = lev.autotune(Uf, wl.dx, p, reps=2)[:2]
@@ -289,7 +366,9 @@ def main():
                    "valid_zones": zones, "boxes": lay.nbox,
                    "tiling": {"tile": tiling[0], "strip_rows": tiling[1]}},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": recorded_traffic(dom, args.workload, tiling) if p.precision == 0 else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops},
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
         "step_flop_rate_tflops": step_flops * args.steps / (ms / 1e3) / 1e12,
@@ -315,6 +394,12 @@ def main():
         a["workload"] = "cfg4: 128^3 single box, FP64, gamma 1.4, smooth modes of amplitude 0.05, periodic"
         out["adjoint"] = a
         del w4
+        print("bench: adjoint cost on a 2x2x2-box instance of the Rayleigh-Taylor set-up", file=sys.stderr,
+              flush=True)
+        a5 = adjoint_costs(I.cfg5(nb=2, m=64, precision=0), 10, 5)
+        a5["workload"] = ("cfg5 instance: 8 boxes of 64^3 (128^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "
+                          "FP64, 10 steps")
+        out["adjoint_rayleigh_taylor"] = a5
         print("bench: 512^3 Rayleigh-Taylor level (512 boxes of 64^3)", file=sys.stderr, flush=True)
         w5 = I.cfg5()
         rt = {"workload": "cfg5: 512 boxes of 64^3 (512^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "

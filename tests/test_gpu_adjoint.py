@@ -92,6 +92,7 @@ CASES = {
     "multibox": lambda: _uneven(3),
     "walls_gravity": lambda: _uneven(4, bc=(0, 0, 0, 0, 2, 2)),
     "outflow": lambda: _uneven(5, bc=(1, 1, 0, 0, 0, 0)),
+    "rayleigh_taylor_boxes": lambda: I.cfg5(nb=2, m=8, precision=0),
 }
 
 
