@@ -169,7 +169,7 @@ def level_rates(wl, steps, warmup, precision, per_box=True):
     return out
 
 
-def adjoint_costs(wl, nsteps, every, reps=3):
+def adjoint_costs(wl, nsteps, every, reps=3, precision=0, rollout=True):
     """Per-step forward and adjoint times (the adjoint includes its own
     recompute of the forward intermediates) and the whole checkpointed
     roll-out, forward vs backward."""
@@ -177,15 +177,15 @@ def adjoint_costs(wl, nsteps, every, reps=3):
     from paper_1008_2801_amd import ppm as P
     lay = wl.layout
     lev = P.Level(lay)
-    p = P.params(gamma=wl.gamma, grav=wl.grav)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
     U = torch.from_numpy(wl.arena).to("cuda")
     lev.fill_boundary(U)
     V = lev.new_state()
     dtv = lev.compute_dt(U, wl.dx, p)
     W = torch.randn_like(U)
     Ub = torch.empty_like(U)
-    lev.ensure_workspace(0)
-    lev.ensure_adjoint_workspace()
+    lev.ensure_workspace(precision)
+    lev.ensure_adjoint_workspace(precision)
 
     def timed(fn):
         fn()
@@ -199,6 +199,13 @@ def adjoint_costs(wl, nsteps, every, reps=3):
         return e0.elapsed_time(e1) / reps
     t_fwd = timed(lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
     t_adj = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv))
+    res = {"precision": "f64" if precision == 0 else "f32 reconstruction + f64 update",
+           "forward_step_ms": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd}
+    if not rollout:
+        res["flags"] = lev.check_status()
+        lev.close()
+        return res
+    del W, Ub, V
     t_f, t_b = [], []
     for _ in range(3):  # the first backward also starts autograd's device thread
         U0 = torch.from_numpy(wl.arena).to("cuda").requires_grad_(True)
@@ -213,11 +220,11 @@ def adjoint_costs(wl, nsteps, every, reps=3):
         t_f.append(t1 - t0)
         t_b.append(t2 - t1)
         del UT, U0
-    flags = lev.check_status()
+    res.update({"rollout_steps": nsteps, "checkpoint_every": every, "rollout_forward_s": min(t_f),
+                "rollout_backward_s": min(t_b), "backward_over_forward": min(t_b) / min(t_f),
+                "flags": lev.check_status()})
     lev.close()
-    return {"forward_step_ms": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
-            "rollout_steps": nsteps, "checkpoint_every": every, "rollout_forward_s": min(t_f),
-            "rollout_backward_s": min(t_b), "backward_over_forward": min(t_b) / min(t_f), "flags": flags}
+    return res
 
 
 def cpu_baseline(wl, window_edge, gamma):
@@ -293,7 +300,8 @@ def main():
     if args.adjoint_only:
         from paper_1008_2801_amd import inputs as I
         a = adjoint_costs(I.cfg4(), 20, 5)
-        print(json.dumps({"adjoint": a}))
+        a32 = adjoint_costs(I.cfg4(), 20, 5, precision=1)
+        print(json.dumps({"adjoint": a, "adjoint_fp32_reconstruction": a32}))
         return
 
     wl = make_workload(args.workload)
@@ -393,6 +401,9 @@ def main():
         a = adjoint_costs(w4, 20, 5)
         a["workload"] = "cfg4: 128^3 single box, FP64, gamma 1.4, smooth modes of amplitude 0.05, periodic"
         out["adjoint"] = a
+        a = adjoint_costs(w4, 20, 5, precision=1)
+        a["workload"] = "cfg4 with the FP32-reconstruction step and its FP32 reverse"
+        out["adjoint_fp32_reconstruction"] = a
         del w4
         print("bench: adjoint cost on a 2x2x2-box instance of the Rayleigh-Taylor set-up", file=sys.stderr,
               flush=True)
@@ -400,6 +411,9 @@ def main():
         a5["workload"] = ("cfg5 instance: 8 boxes of 64^3 (128^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "
                           "FP64, 10 steps")
         out["adjoint_rayleigh_taylor"] = a5
+        a5 = adjoint_costs(I.cfg5(nb=2, m=64, precision=1), 10, 5, precision=1)
+        a5["workload"] = "the same instance with the FP32-reconstruction step and its FP32 reverse"
+        out["adjoint_rayleigh_taylor_fp32_reconstruction"] = a5
         print("bench: 512^3 Rayleigh-Taylor level (512 boxes of 64^3)", file=sys.stderr, flush=True)
         w5 = I.cfg5()
         rt = {"workload": "cfg5: 512 boxes of 64^3 (512^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "
@@ -407,6 +421,12 @@ def main():
         for prec, tag in ((1, "fp32_reconstruction"), (0, "fp64")):
             r = level_rates(w5, 10, 1, prec, per_box=False)
             rt[tag] = r
+        print("bench: adjoint step of the 512^3 Rayleigh-Taylor level (FP32 reconstruction)", file=sys.stderr,
+              flush=True)
+        torch.cuda.empty_cache()
+        a5 = adjoint_costs(w5, 0, 1, precision=1, rollout=False)
+        a5["workload"] = "cfg5: 512 boxes of 64^3, FP32 reconstruction, one forward step vs one adjoint step"
+        rt["adjoint"] = a5
         out["rayleigh_taylor"] = rt
         del w5
     if not args.no_cpu_baseline:

@@ -138,17 +138,23 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
                    const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
                    void* stream);
 
-/* Adjoint of one FP64 step (precision 0), dt and every branch decision of
- * the forward step frozen: given the step's input U (ghosts filled, as for
- * ppm_hydro_step) and the adjoint Unew_bar of the new state's valid zones,
- * writes to U_bar the adjoint of U's valid zones -- the transpose of the
- * step's Jacobian applied to Unew_bar, the ghost-fill transpose included
- * (ghost adjoints are added into the zones they were copied from) -- and
- * zeros U_bar's ghost zones.  The forward intermediates are recomputed
- * into the step workspace (ppm_set_workspace); the reverse stages use a
- * second caller-owned workspace (ppm_adjoint_workspace_bytes).  U_bar must
- * not overlap U or Unew_bar.  Deterministic: no atomics. */
-size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx);
+/* Adjoint of one step, dt and every branch decision of the forward step
+ * frozen: given the step's input U (ghosts filled, as for ppm_hydro_step)
+ * and the adjoint Unew_bar of the new state's valid zones, writes to U_bar
+ * the adjoint of U's valid zones -- the transpose of the step's Jacobian
+ * applied to Unew_bar, the ghost-fill transpose included (ghost adjoints are
+ * added into the zones they were copied from) -- and zeros U_bar's ghost
+ * zones.  The reverse stages run in the precision of the forward step they
+ * differentiate (params->precision: 0 all FP64; 1 the reconstruction,
+ * tracing and Riemann reverses in FP32, the update's reverse, the
+ * conversion's output and U_bar in FP64).  The forward intermediates are
+ * recomputed into the step workspace (ppm_set_workspace, sized for the same
+ * precision); the reverse stages use a second caller-owned workspace of
+ * ppm_adjoint_workspace_bytes(ctx, precision) bytes, 256-byte aligned.
+ * U_bar must not overlap U or Unew_bar.  Deterministic: no atomics.
+ * Returns PPM_EINVAL (message in ppm_last_error) for a null pointer,
+ * overlapping buffers, invalid parameters or a missing/small workspace. */
+size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx, int32_t precision);
 int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
 int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
                            const double* dt_dev, const double dx[3], const ppm_params* params, void* stream);

@@ -5,9 +5,9 @@
  *
  * Plain, serial CPU reference of one explicit unsplit Godunov step of the 3-D
  * gamma-law Euler equations on the rectangular boxes (FABs) of one level:
- * the "fully explicit advance of a hyperbolic system of conservation laws"
- * of the compressible code (paper Sec. 1), on the MultiFAB / FAB data model
- * with ghost cells filled from intersecting grids (paper Sec. 2).
+ * the compressible code's explicit update of a hyperbolic system of
+ * conservation laws (paper Sec. 1), on the MultiFAB / FAB data model with
+ * ghost cells filled from intersecting grids (paper Sec. 2).
  *
  * The paper names the advance but not its discretisation.  The reading used
  * here (stated step by step next to each function) is the classical one:
@@ -30,6 +30,8 @@
  *   float    - the FP32-reconstruction mode: O2..O9 in float, O10/O11 double
  *   Dual     - forward-mode tangent (exact Jacobian-vector product with the
  *              branch decisions taken on the primal values)
+ *   DualF    - the same for the FP32-reconstruction mode: float primal
+ *              (rounded exactly as the float mode), FP64 tangent
  *   Counted  - a double that counts its own floating-point operations
  */
 #include <cmath>
@@ -75,10 +77,29 @@ inline Dual operator/(Dual a, Dual b) {
 }
 inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
 
+// Primal in float, tangent in double: the derivative of the FP32 mode's
+// piecewise-smooth step with its own (float) branch decisions.
+struct DualF {
+  float v;
+  double d;
+  DualF() : v(0), d(0) {}
+  DualF(double x) : v((float)x), d(0) {}
+  DualF(float x, double t) : v(x), d(t) {}
+};
+inline DualF operator+(DualF a, DualF b) { return DualF(a.v + b.v, a.d + b.d); }
+inline DualF operator-(DualF a, DualF b) { return DualF(a.v - b.v, a.d - b.d); }
+inline DualF operator*(DualF a, DualF b) { return DualF(a.v * b.v, a.d * (double)b.v + (double)a.v * b.d); }
+inline DualF operator/(DualF a, DualF b) {
+  const float q = a.v / b.v;
+  return DualF(q, (a.d - (double)q * b.d) / (double)b.v);
+}
+inline DualF operator-(DualF a) { return DualF(-a.v, -a.d); }
+
 inline double V(double x) { return x; }
 inline double V(float x) { return x; }
 inline double V(const Counted& x) { return x.v; }
 inline double V(const Dual& x) { return x.v; }
+inline double V(const DualF& x) { return (double)x.v; }
 
 // max/min select an operand by value; the derivative follows the selection.
 template <class S> inline S smax(S a, S b) {
@@ -100,6 +121,10 @@ inline Dual ssqrt(Dual x) {
   double r = std::sqrt(x.v);
   return Dual(r, x.d / (2.0 * r));
 }
+inline DualF ssqrt(DualF x) {
+  const float r = std::sqrt(x.v);
+  return DualF(r, x.d / (2.0 * (double)r));
+}
 
 // Conversion of the FP64 state into the reconstruction scalar and back.
 template <class S, class A> inline S to_s(const A& a);
@@ -107,11 +132,13 @@ template <> inline double to_s<double, double>(const double& a) { return a; }
 template <> inline float to_s<float, double>(const double& a) { return (float)a; }
 template <> inline Counted to_s<Counted, Counted>(const Counted& a) { return a; }
 template <> inline Dual to_s<Dual, Dual>(const Dual& a) { return a; }
+template <> inline DualF to_s<DualF, Dual>(const Dual& a) { return DualF((float)a.v, a.d); }
 template <class A, class S> inline A to_a(const S& s);
 template <> inline double to_a<double, double>(const double& s) { return s; }
 template <> inline double to_a<double, float>(const float& s) { return (double)s; }
 template <> inline Counted to_a<Counted, Counted>(const Counted& s) { return s; }
 template <> inline Dual to_a<Dual, Dual>(const Dual& s) { return s; }
+template <> inline Dual to_a<Dual, DualF>(const DualF& s) { return Dual((double)s.v, s.d); }
 
 // ------------------------------------------------------------- parameters --
 struct OParams {
@@ -782,7 +809,8 @@ int oracle_step_count(const double* U, const int n[3], const int wlo[3], const i
 }
 
 // Jacobian-vector product of the step: (Unew, dUnew) = (step(U), J(U) dU)
-// with dt frozen and every branch decided on the primal values.  FP64.
+// with dt frozen and every branch decided on the primal values.  precision
+// 0: FP64; 1: the FP32-reconstruction step (float primal, double tangent).
 int oracle_step_jvp(const double* U, const double* dU, const int n[3], const int wlo[3],
                     const int whi[3], double dt, const double h[3], const OParams* P,
                     double* Unew, double* dUnew) {
@@ -792,7 +820,9 @@ int oracle_step_jvp(const double* U, const double* dU, const int n[3], const int
   std::vector<Dual> ud(tot), un(tot);
   for (size_t i = 0; i < tot; ++i) { ud[i] = Dual(U[i], dU[i]); un[i] = Dual(Unew[i], dUnew[i]); }
   Dual* none[3] = {nullptr, nullptr, nullptr};
-  int fl = run_step<Dual, Dual>(ud.data(), n, wlo, whi, dt, h, P, un.data(), none, false);
+  const int fl = (P->precision == 1)
+                     ? run_step<DualF, Dual>(ud.data(), n, wlo, whi, dt, h, P, un.data(), none, false)
+                     : run_step<Dual, Dual>(ud.data(), n, wlo, whi, dt, h, P, un.data(), none, false);
   for (size_t i = 0; i < tot; ++i) { Unew[i] = un[i].v; dUnew[i] = un[i].d; }
   return fl;
 }

@@ -51,10 +51,11 @@ __device__ __forceinline__ long long eidx(const DevBox& B, int x, int y, int z) 
   return ((long long)(z + 1) * (B.n[1] + 2) + (y + 1)) * (B.n[0] + 2) + (x + 1);
 }
 
-// Adjoint of the update and of the Heun source.
+// Adjoint of the update and of the Heun source (FP64, as the update).
+template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_update(const Tile* __restrict__ tiles, int ntiles,
                                                      const DevBox* __restrict__ boxes,
-                                                     const double* __restrict__ Ubn, double* __restrict__ aw,
+                                                     const double* __restrict__ Ubn, S* __restrict__ aw,
                                                      long long LE, double* __restrict__ as, long long LS,
                                                      const StepConsts* __restrict__ sc, int grav, double g0,
                                                      double g1, double g2) {
@@ -64,12 +65,12 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_update(const Tile* __restrict_
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  double* uf = aw + A_UF * LE + B.eoff + z.e;
+  S* uf = aw + A_UF * LE + B.eoff + z.e;
   const bool valid = z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] && z.x[2] >= 0 &&
                      z.x[2] < B.n[2];
   if (!valid) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) uf[m * LE] = 0.0;
+    for (int m = 0; m < 5; ++m) uf[m * LE] = S(0);
     return;
   }
   const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_update(const Tile* __restrict_
   double* ubs = as + AS_UB * LS + B.poff + li;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    uf[m * LE] = u1b[m];
+    uf[m * LE] = (S)u1b[m];
     ubs[m * LS] = u1b[m] + ud[m];
   }
 }
@@ -127,12 +128,11 @@ __device__ __forceinline__ void r3_state(const S* w, long long LE, long long off
 // states of its face (zone x - e_d, high side; zone x, low side); every zone
 // side not on a face is written as zero by the zone's own lane, so each
 // entry of the U3 and traced-state planes is written exactly once here.
-template <int d>
+template <int d, class S>
 __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int ntiles,
-                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                            long long LE, S* __restrict__ aw, const Gas<S>& G,
                                             const StepConsts* __restrict__ sc) {
-  using S = double;
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
@@ -140,32 +140,33 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  double* a = aw + B.eoff + z.e;
+  S* a = aw + B.eoff + z.e;
   const bool tv = z.x[t1] >= 0 && z.x[t1] < B.n[t1] && z.x[t2] >= 0 && z.x[t2] < B.n[t2];
   const bool face = tv && z.x[d] >= 0;
   const bool hi_face = tv && z.x[d] + 1 <= B.n[d];  // slot x + e_d is a face
   if (!hi_face) {
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      a[(A_U3 + (d * 2 + 0) * 5 + m) * LE] = 0.0;
-      a[(A_TB + (d * 2 + 0) * 5 + m) * LE] = 0.0;
+      a[(A_U3 + (d * 2 + 0) * 5 + m) * LE] = S(0);
+      a[(A_TB + (d * 2 + 0) * 5 + m) * LE] = S(0);
     }
   }
   if (!face) {
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      a[(A_U3 + (d * 2 + 1) * 5 + m) * LE] = 0.0;
-      a[(A_TB + (d * 2 + 1) * 5 + m) * LE] = 0.0;
+      a[(A_U3 + (d * 2 + 1) * 5 + m) * LE] = S(0);
+      a[(A_TB + (d * 2 + 1) * 5 + m) * LE] = S(0);
     }
     return;
   }
   const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
-  const S c1 = sc->d_dt2h[t1], c2 = sc->d_dt2h[t2];
+  const S c1 = SC<S>::dt2h(sc)[t1], c2 = SC<S>::dt2h(sc)[t2];
   const S* w = work + B.eoff + z.e;
   S Fb[5];
-  const double dtdx = sc->dtdx[d];
+  const double dtdx = sc->dtdx[d];  // the update is FP64
 #pragma unroll
-  for (int m = 0; m < 5; ++m) Fb[m] = dtdx * (a[(A_UF + m) * LE] - a[(A_UF + m) * LE - sd]);
+  for (int m = 0; m < 5; ++m)
+    Fb[m] = (S)(dtdx * ((double)a[(A_UF + m) * LE] - (double)a[(A_UF + m) * LE - sd]));
   S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
   int fl = 0;
   r3_state<d>(w, LE, -sd, 0, s1, s2, c1, c2, G, qeL, ueL);
@@ -189,14 +190,15 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   }
 }
 
+template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ tiles, int ntiles,
-                                                 const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                                 long long LE, double* __restrict__ aw, Gas<double> G,
+                                                 const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                                 long long LE, S* __restrict__ aw, Gas<S> G,
                                                  const StepConsts* __restrict__ sc) {
   switch (blockIdx.y) {
-    case 0: adj_r3_body<0>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    case 1: adj_r3_body<1>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    default: adj_r3_body<2>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
   }
 }
 
@@ -204,21 +206,20 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ ti
 // the stage-3 states of the third axis r (difference along d), reverse of the
 // corrected states, adjoints of the two traced states (returned) and of the
 // corrected states (written to U2).
-template <int d, int t>
-__device__ __forceinline__ void adj_r2_pair(const double* __restrict__ w, double* __restrict__ a, long long LE,
-                                            long long sd, long long stt, const double qeL[5],
-                                            const double qeR[5], const Gas<double>& G,
-                                            const StepConsts* __restrict__ sc, double tLb[5], double tRb[5]) {
-  using S = double;
+template <int d, int t, class S>
+__device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restrict__ a, long long LE,
+                                            long long sd, long long stt, const S qeL[5], const S qeR[5],
+                                            const Gas<S>& G, const StepConsts* __restrict__ sc, S tLb[5],
+                                            S tRb[5]) {
   constexpr int pr = pair_index(d, t);
   constexpr int r = 3 - d - t;
-  const S c3 = sc->d_dt3h[t];
+  const S c3 = SC<S>::dt3h(sc)[t];
   S Fb[5];
-  const double c2d = sc->d_dt2h[d];
+  const S c2d = SC<S>::dt2h(sc)[d];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    const double* up = a + (A_U3 + (r * 2 + 0) * 5 + m) * LE;
-    const double* um = a + (A_U3 + (r * 2 + 1) * 5 + m) * LE;
+    const S* up = a + (A_U3 + (r * 2 + 0) * 5 + m) * LE;
+    const S* um = a + (A_U3 + (r * 2 + 1) * 5 + m) * LE;
     Fb[m] = c2d * ((up[0] + um[0]) - (up[-sd] + um[-sd]));
   }
   S ueL[5], ueR[5], L[5], R[5];
@@ -252,12 +253,11 @@ __device__ __forceinline__ void adj_r2_pair(const double* __restrict__ w, double
 // traced-state adjoints of the face's two zones receive both pairs' parts.
 // Zone sides that are not on a pair's face get zero U2 entries from their
 // own lane.
-template <int d>
+template <int d, class S>
 __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int ntiles,
-                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                            long long LE, S* __restrict__ aw, const Gas<S>& G,
                                             const StepConsts* __restrict__ sc) {
-  using S = double;
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
   constexpr int pa = pair_index(d, t1), pb = pair_index(d, t2);
   const int tt = xcd_tile(ntiles);
@@ -266,26 +266,26 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  double* a = aw + B.eoff + z.e;
+  S* a = aw + B.eoff + z.e;
   const bool ta = z.x[t1] >= 0 && z.x[t1] < B.n[t1];
   const bool tb = z.x[t2] >= 0 && z.x[t2] < B.n[t2];
   const bool up = z.x[d] + 1 <= B.n[d];
   const bool va = ta && z.x[d] >= 0, vb = tb && z.x[d] >= 0;
   if (!(ta && up)) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) a[(A_U2 + (pa * 2 + 0) * 5 + m) * LE] = 0.0;
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pa * 2 + 0) * 5 + m) * LE] = S(0);
   }
   if (!(tb && up)) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) a[(A_U2 + (pb * 2 + 0) * 5 + m) * LE] = 0.0;
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pb * 2 + 0) * 5 + m) * LE] = S(0);
   }
   if (!va) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) a[(A_U2 + (pa * 2 + 1) * 5 + m) * LE] = 0.0;
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pa * 2 + 1) * 5 + m) * LE] = S(0);
   }
   if (!vb) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) a[(A_U2 + (pb * 2 + 1) * 5 + m) * LE] = 0.0;
+    for (int m = 0; m < 5; ++m) a[(A_U2 + (pb * 2 + 1) * 5 + m) * LE] = S(0);
   }
   if (!va && !vb) return;
   const long long sd = stride(z.E, d);
@@ -297,8 +297,8 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
     qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
   }
   S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
-  if (va) adj_r2_pair<d, t1>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, G, sc, tLb, tRb);
-  if (vb) adj_r2_pair<d, t2>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, G, sc, tLb, tRb);
+  if (va) adj_r2_pair<d, t1, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, G, sc, tLb, tRb);
+  if (vb) adj_r2_pair<d, t2, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, G, sc, tLb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
@@ -306,23 +306,23 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
   }
 }
 
+template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r2(const Tile* __restrict__ tiles, int ntiles,
-                                                 const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                                 long long LE, double* __restrict__ aw, Gas<double> G,
+                                                 const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                                 long long LE, S* __restrict__ aw, Gas<S> G,
                                                  const StepConsts* __restrict__ sc) {
   switch (blockIdx.y) {
-    case 0: adj_r2_body<0>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    case 1: adj_r2_body<1>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    default: adj_r2_body<2>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 0: adj_r2_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 1: adj_r2_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    default: adj_r2_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
   }
 }
 
-template <int d>
+template <int d, class S>
 __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int ntiles,
-                                            const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                            long long LE, double* __restrict__ aw, const Gas<double>& G,
+                                            const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                            long long LE, S* __restrict__ aw, const Gas<S>& G,
                                             const StepConsts* __restrict__ sc) {
-  using S = double;
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   constexpr int da = (d == 0) ? 1 : 0, db = (d == 2) ? 1 : 2;  // the two axes whose pairs use F1^d
@@ -334,17 +334,17 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
   if (z.x[d] < 0) return;
   const long long sd = stride(z.E, d);
   const S* w = work + B.eoff + z.e;
-  double* a = aw + B.eoff + z.e;
-  const double c3 = sc->d_dt3h[d];
+  S* a = aw + B.eoff + z.e;
+  const S c3 = SC<S>::dt3h(sc)[d];
   S Fb[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    const double* ap = a + (A_U2 + (pa * 2 + 0) * 5 + m) * LE;
-    const double* am = a + (A_U2 + (pa * 2 + 1) * 5 + m) * LE;
-    const double* bp = a + (A_U2 + (pb * 2 + 0) * 5 + m) * LE;
-    const double* bm = a + (A_U2 + (pb * 2 + 1) * 5 + m) * LE;
-    const double sa = (ap[0] + am[0]) - (ap[-sd] + am[-sd]);
-    const double sb = (bp[0] + bm[0]) - (bp[-sd] + bm[-sd]);
+    const S* ap = a + (A_U2 + (pa * 2 + 0) * 5 + m) * LE;
+    const S* am = a + (A_U2 + (pa * 2 + 1) * 5 + m) * LE;
+    const S* bp = a + (A_U2 + (pb * 2 + 0) * 5 + m) * LE;
+    const S* bm = a + (A_U2 + (pb * 2 + 1) * 5 + m) * LE;
+    const S sa = (ap[0] + am[0]) - (ap[-sd] + am[-sd]);
+    const S sb = (bp[0] + bm[0]) - (bp[-sd] + bm[-sd]);
     Fb[m] = c3 * sa + c3 * sb;
   }
   S L[5], R[5];
@@ -362,14 +362,15 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
   }
 }
 
+template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ tiles, int ntiles,
-                                                 const DevBox* __restrict__ boxes, const double* __restrict__ work,
-                                                 long long LE, double* __restrict__ aw, Gas<double> G,
+                                                 const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                                 long long LE, S* __restrict__ aw, Gas<S> G,
                                                  const StepConsts* __restrict__ sc) {
   switch (blockIdx.y) {
-    case 0: adj_r1_body<0>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    case 1: adj_r1_body<1>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    default: adj_r1_body<2>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 0: adj_r1_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 1: adj_r1_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    default: adj_r1_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
   }
 }
 
@@ -378,14 +379,13 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ ti
 // (CB of axis d) and the flattening coefficient (PHB of axis d).
 // One launch per axis (the three bodies in one kernel would share the
 // register budget of the largest and spill).
-template <int d>
+template <int d, class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
                                                     const DevBox* __restrict__ boxes,
-                                                    const double* __restrict__ prim, long long LS,
-                                                    const double* __restrict__ work, long long LE,
-                                                    double* __restrict__ aw, Gas<double> G,
+                                                    const S* __restrict__ prim, long long LS,
+                                                    const S* __restrict__ work, long long LE,
+                                                    S* __restrict__ aw, Gas<S> G,
                                                     const StepConsts* __restrict__ sc) {
-  using S = double;
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tiles[tt];
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
   const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
   const long long st = stride(NS, d);
   const S phi = work[E_FLAT * LE + B.eoff + z.e];
-  double* a = aw + B.eoff + z.e;
+  S* a = aw + B.eoff + z.e;
   S aL[5], aR[5], a6[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -411,7 +411,8 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
     qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
   }
   S aLb[5] = {0, 0, 0, 0, 0}, aRb[5] = {0, 0, 0, 0, 0}, a6b[5] = {0, 0, 0, 0, 0}, rb = 0, unb = 0, cb = 0;
-  trace_zone_vjp<d>(aL, aR, a6, r, un, c, sc->d_dtdx[d], G, sc->d_hdtg, qpb, qmb, aLb, aRb, a6b, rb, unb, cb);
+  trace_zone_vjp<d>(aL, aR, a6, r, un, c, SC<S>::dtdx(sc)[d], G, SC<S>::hdtg(sc), qpb, qmb, aLb, aRb, a6b, rb,
+                    unb, cb);
   S phib = 0;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
@@ -431,19 +432,19 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
 // Flattening adjoint: the derivative of phi = min_d (1 - chi_d) through the
 // selected axis, the selected shock-detector coefficient and its clamp,
 // into the pressures at offsets -3..3 along that axis (A_GF, A_SEL).
+template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict__ tiles, int ntiles,
                                                       const DevBox* __restrict__ boxes,
-                                                      const double* __restrict__ prim, long long LS,
-                                                      double* __restrict__ aw, long long LE, Gas<double> G) {
-  using S = double;
+                                                      const S* __restrict__ prim, long long LS,
+                                                      S* __restrict__ aw, long long LE, Gas<S> G) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tiles[tt];
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  double* a = aw + B.eoff + z.e;
-  double gf[7] = {0, 0, 0, 0, 0, 0, 0};
+  S* a = aw + B.eoff + z.e;
+  S gf[7] = {0, 0, 0, 0, 0, 0, 0};
   int sel = -1;
   if (G.flattening) {
     const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
@@ -498,8 +499,8 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
         for (int k = 0; k < 7; ++k) ps[k] = p[k];
       }
     }
-    const double phib = (a[A_PHB * LE] + a[(A_PHB + 1) * LE]) + a[(A_PHB + 2) * LE];
-    if (live && phib != 0.0) {
+    const S phib = (a[A_PHB * LE] + a[(A_PHB + 1) * LE]) + a[(A_PHB + 2) * LE];
+    if (live && phib != S(0)) {
       const int o = osel;
       // p index k <-> offset k - 3; the detector at o uses k = o+1, o+2, o+4, o+5
       const S p1 = (o < 0) ? ps[0] : (o == 0 ? ps[1] : ps[2]);
@@ -530,7 +531,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k) a[(A_GF + k) * LE] = gf[k];
-  a[A_SEL * LE] = (double)sel;
+  a[A_SEL * LE] = (S)sel;
 }
 
 // Gather of all primitive adjoints of a stored zone (the trace contributions
@@ -538,11 +539,12 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_flatten(const Tile* __restrict
 // flattening contributions), then the reverse of its primitive conversion:
 // UB = (valid ? update part : 0) + J^T qb.  Clears the output's ghost zones
 // (its valid zones are written by the fill transpose).
+template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict__ tilesS, int ntiles,
                                                      const DevBox* __restrict__ boxes,
-                                                     const double* __restrict__ aw, long long LE,
+                                                     const S* __restrict__ aw, long long LE,
                                                      const double* __restrict__ U, double* __restrict__ as,
-                                                     long long LS, Gas<double> G, double* __restrict__ Ub) {
+                                                     long long LS, Gas<S> G, double* __restrict__ Ub) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tilesS[tt];
@@ -555,7 +557,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
   j[0] = (int)(idx % NS[0]) - NG;
   j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
   j[2] = (int)(idx / ((long long)NS[0] * NS[1])) - NG;
-  double qb[6] = {0, 0, 0, 0, 0, 0};
+  S qb[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
 #pragma unroll
@@ -563,17 +565,17 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
       int y[3] = {j[0], j[1], j[2]};
       y[d] -= o;
       if (!in_e(y, B)) continue;
-      const double* g = aw + B.eoff + eidx(B, y[0], y[1], y[2]);
+      const S* g = aw + B.eoff + eidx(B, y[0], y[1], y[2]);
 #pragma unroll
       for (int m = 0; m < 5; ++m) qb[m] += g[(A_GT + (d * 5 + m) * 5 + (o + 2)) * LE];
     }
   }
   if (in_e(j, B)) {
-    const double* g = aw + B.eoff + eidx(B, j[0], j[1], j[2]);
+    const S* g = aw + B.eoff + eidx(B, j[0], j[1], j[2]);
     qb[5] = (g[A_CB * LE] + g[(A_CB + 1) * LE]) + g[(A_CB + 2) * LE];
   }
   if (G.flattening) {
-    double acc = 0.0;
+    S acc = S(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -582,18 +584,18 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
         y[d] -= o;
         if (!in_e(y, B)) continue;
         const long long e = B.eoff + eidx(B, y[0], y[1], y[2]);
-        if (aw[A_SEL * LE + e] == (double)d) acc += aw[(A_GF + o + 3) * LE + e];
+        if (aw[A_SEL * LE + e] == (S)d) acc += aw[(A_GF + o + 3) * LE + e];
       }
     qb[4] += acc;
   }
-  double uc[5], ub[5] = {0, 0, 0, 0, 0};
+  S uc[5], ub[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-  for (int c = 0; c < 5; ++c) uc[c] = U[B.soff + idx + c * NSS];
+  for (int c = 0; c < 5; ++c) uc[c] = (S)U[B.soff + idx + c * NSS];
   prim_cell_vjp(uc, G, qb, ub);
   const bool valid = j[0] >= 0 && j[0] < B.n[0] && j[1] >= 0 && j[1] < B.n[1] && j[2] >= 0 && j[2] < B.n[2];
   double* u = as + AS_UB * LS + B.poff + idx;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) u[c * LS] = (valid ? u[c * LS] : 0.0) + ub[c];
+  for (int c = 0; c < 5; ++c) u[c * LS] = (valid ? u[c * LS] : 0.0) + (double)ub[c];
   if (!valid) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) Ub[B.soff + idx + c * NSS] = 0.0;
@@ -658,53 +660,55 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ 
   for (int c = 0; c < 5; ++c) Ub[B.soff + li + c * NS] = acc[c];
 }
 
-}  // namespace
-
-size_t adjoint_workspace_doubles(long long LS, long long LE) {
-  return (size_t)(A_SPLANES * LS + A_EPLANES * LE);
-}
-
-hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
-                          const void* work, void* awork, double gamma, double small_dens, double small_pres,
-                          int limiter, int flattening, int iters, int grav, const double g[3],
-                          hipStream_t s) {
-  const double* w = (const double*)work;
-  const double* prim = w;
-  const double* ework = w + P_PLANES * L.LS;
+template <class S>
+hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
+                        const void* work, void* awork, const Gas<S>& G, int grav, const double g[3],
+                        hipStream_t s) {
+  const S* prim = (const S*)work;
+  const S* ework = prim + P_PLANES * L.LS;
   double* as = (double*)awork;
-  double* aw = as + A_SPLANES * L.LS;
-  Gas<double> G;
-  G.gamma = gamma;
-  G.gm1 = gamma - 1.0;
-  G.gm1inv = 1.0 / (gamma - 1.0);
-  G.beta = (gamma + 1.0) / (2.0 * gamma);
-  G.small_dens = small_dens;
-  G.small_pres = small_pres;
-  G.limiter = limiter;
-  G.flattening = flattening && limiter;
-  G.iters = iters;
-  G.grav = grav;
+  S* aw = (S*)(as + A_SPLANES * L.LS);
   const dim3 blk(L.tile);
   // every workspace entry is written before it is read: each reverse stage
   // writes all entries it owns, zeros included
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
-  hipLaunchKernelGGL(k_adj_update, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS, L.consts,
-                     grav, g[0], g[1], g[2]);
-  hipLaunchKernelGGL(k_adj_r3, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL(k_adj_r2, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL(k_adj_r1, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL(k_adj_trace<0>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
-                     L.consts);
-  hipLaunchKernelGGL(k_adj_trace<1>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
-                     L.consts);
-  hipLaunchKernelGGL(k_adj_trace<2>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE, aw, G,
-                     L.consts);
+  hipLaunchKernelGGL(k_adj_update<S>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS,
+                     L.consts, grav, g[0], g[1], g[2]);
+  hipLaunchKernelGGL(k_adj_r3<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL((k_adj_trace<0, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
+                     aw, G, L.consts);
+  hipLaunchKernelGGL((k_adj_trace<1, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
+                     aw, G, L.consts);
+  hipLaunchKernelGGL((k_adj_trace<2, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
+                     aw, G, L.consts);
   if (G.flattening)
-    hipLaunchKernelGGL(k_adj_flatten, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
-  hipLaunchKernelGGL(k_adj_gather, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, U, as, L.LS, G, Ub);
+    hipLaunchKernelGGL(k_adj_flatten<S>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
+  hipLaunchKernelGGL(k_adj_gather<S>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, U, as, L.LS, G, Ub);
   hipLaunchKernelGGL(k_adj_fill, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, L.desc, L.inv_start, L.inv_idx, as,
                      L.LS, Ub);
   return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adjoint_workspace_bytes(long long LS, long long LE, int precision) {
+  const size_t se = precision == 1 ? sizeof(float) : sizeof(double);
+  return sizeof(double) * (size_t)(A_SPLANES * LS) + se * (size_t)(A_EPLANES * LE);
+}
+
+hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, const double* U, const double* Ubn,
+                          double* Ub, const void* work, void* awork, double gamma, double small_dens,
+                          double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
+                          hipStream_t s) {
+  if (precision == 1)
+    return adjoint_impl<float>(L, nS, nE, U, Ubn, Ub, work, awork,
+                               make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
+                               grav, g, s);
+  return adjoint_impl<double>(L, nS, nE, U, Ubn, Ub, work, awork,
+                              make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
+                              grav, g, s);
 }
 
 }  // namespace ppm

@@ -665,9 +665,9 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
   return PPM_OK;
 }
 
-size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx) {
-  if (!ctx) return 0;
-  return sizeof(double) * adjoint_workspace_doubles(ctx->LS, ctx->LE);
+size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx, int32_t precision) {
+  if (!ctx || precision < 0 || precision > 1) return 0;
+  return adjoint_workspace_bytes(ctx->LS, ctx->LE, precision);
 }
 
 int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
@@ -684,7 +684,6 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
   std::string m = validate_params(params);
   if (m.empty()) m = validate_dx(dx);
   if (m.empty() && (!U || !Unew_bar || !U_bar)) m = "adjoint: null pointer";
-  if (m.empty() && params->precision != 0) m = "adjoint: only the FP64 step (precision 0) has an adjoint";
   if (m.empty() && !dt_dev && !(dt > 0.0 && std::isfinite(dt))) m = "adjoint: dt must be positive and finite";
   const size_t alen = (size_t)ctx->off.back() * sizeof(double);
   if (m.empty()) {
@@ -693,9 +692,9 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
     const char* c = (const char*)Unew_bar;
     if ((a < b + alen && b < a + alen) || (a < c + alen && c < a + alen)) m = "adjoint: U_bar overlaps an input";
   }
-  if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, 0)))
+  if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, params->precision)))
     m = "adjoint: workspace missing or too small (ppm_set_workspace)";
-  if (m.empty() && (!ctx->awork || ctx->awork_bytes < ppm_adjoint_workspace_bytes(ctx)))
+  if (m.empty() && (!ctx->awork || ctx->awork_bytes < ppm_adjoint_workspace_bytes(ctx, params->precision)))
     m = "adjoint: adjoint workspace missing or too small (ppm_set_adjoint_workspace)";
   if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
   hipStream_t s = (hipStream_t)stream;
@@ -705,14 +704,14 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
   const int nS = (int)ctx->tilesS.size(), nE = (int)ctx->tilesE.size();
   // recompute the forward intermediates through stage 2 (U is not written)
-  rc = ctx->hip(launch_step(L, 0, 0, nS, 0, nE, U, nullptr, nullptr, ctx->work, params->gamma, params->small_dens,
-                            params->small_pres, params->limiter, params->flattening, params->riemann_iters, grav,
-                            params->grav, s, nullptr, 5),
+  rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, U, nullptr, nullptr, ctx->work, params->gamma,
+                            params->small_dens, params->small_pres, params->limiter, params->flattening,
+                            params->riemann_iters, grav, params->grav, s, nullptr, 5),
                 "adjoint recompute");
   if (rc) return rc;
-  return ctx->hip(launch_adjoint(L, nS, nE, U, Unew_bar, U_bar, ctx->work, ctx->awork, params->gamma,
-                                 params->small_dens, params->small_pres, params->limiter, params->flattening,
-                                 params->riemann_iters, grav, params->grav, s),
+  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, U, Unew_bar, U_bar, ctx->work, ctx->awork,
+                                 params->gamma, params->small_dens, params->small_pres, params->limiter,
+                                 params->flattening, params->riemann_iters, grav, params->grav, s),
                   "adjoint");
 }
 

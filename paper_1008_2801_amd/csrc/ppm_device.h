@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ppm_internal.h"
+#include "ppm_math.h"
 
 namespace ppm {
 
@@ -65,6 +66,25 @@ __device__ __forceinline__ long long stride(const int E[3], int d) {
 // Primitive-plane index of zone (x, y, z) of box B (stored grid).
 __device__ __forceinline__ long long pidx(const DevBox& B, int x, int y, int z) {
   return B.poff + ((long long)(z + NG) * (B.n[1] + 2 * NG) + (y + NG)) * (B.n[0] + 2 * NG) + (x + NG);
+}
+
+// Gas and scheme constants in the reconstruction scalar, formed on the host
+// in FP64 and rounded once to S.
+template <class S>
+inline Gas<S> make_gas(double gamma, double small_dens, double small_pres, int limiter, int flattening, int iters,
+                int grav) {
+  Gas<S> G;
+  G.gamma = S(gamma);
+  G.gm1 = S(gamma - 1.0);
+  G.gm1inv = S(1.0 / (gamma - 1.0));
+  G.beta = S((gamma + 1.0) / (2.0 * gamma));
+  G.small_dens = S(small_dens);
+  G.small_pres = S(small_pres);
+  G.limiter = limiter;
+  G.flattening = flattening && limiter;
+  G.iters = iters;
+  G.grav = grav;
+  return G;
 }
 
 __host__ __device__ constexpr int pair_index(int d, int t) { return 2 * d + (t > d ? t - 1 : t); }

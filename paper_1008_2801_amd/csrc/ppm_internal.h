@@ -101,10 +101,10 @@ hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int t
                        hipStream_t s, hipEvent_t* ev, int nstages = 7);
 // Adjoint of one FP64 step (ppm_adjoint.hip); the forward workspace must hold
 // the recomputed prim..riemann2 intermediates of the same step.
-size_t adjoint_workspace_doubles(long long LS, long long LE);
-hipError_t launch_adjoint(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
-                          const void* work, void* awork, double gamma, double small_dens, double small_pres,
-                          int limiter, int flattening, int iters, int grav, const double g[3],
+size_t adjoint_workspace_bytes(long long LS, long long LE, int precision);
+hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, const double* U, const double* Ubn,
+                          double* Ub, const void* work, void* awork, double gamma, double small_dens,
+                          double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s);
 // Events recorded by launch_step when ev is non-null: before each of the 7
 // stage kernels and after the last (STEP_EVENTS in all).

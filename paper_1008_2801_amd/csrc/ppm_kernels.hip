@@ -509,22 +509,6 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restric
   }
 }
 
-template <class S>
-Gas<S> make_gas(double gamma, double small_dens, double small_pres, int limiter, int flattening, int iters,
-                int grav) {
-  Gas<S> G;
-  G.gamma = S(gamma);
-  G.gm1 = S(gamma - 1.0);
-  G.gm1inv = S(1.0 / (gamma - 1.0));
-  G.beta = S((gamma + 1.0) / (2.0 * gamma));
-  G.small_dens = S(small_dens);
-  G.small_pres = S(small_pres);
-  G.limiter = limiter;
-  G.flattening = flattening && limiter;
-  G.iters = iters;
-  G.grav = grav;
-  return G;
-}
 
 template <class S>
 hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, const double* U, double* Unew,

@@ -102,7 +102,7 @@ def lib():
         L.ppm_get_tiling.argtypes = [_vp, _i32p, _i32p]
         L.ppm_autotune.argtypes = [_vp, _vp, _vp, _dp3, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_char_p,
                                    _vp, _i32p, _i32p, _i32p]
-        L.ppm_adjoint_workspace_bytes.argtypes = [_vp]
+        L.ppm_adjoint_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
         L.ppm_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.ppm_set_adjoint_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
         L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
@@ -300,9 +300,9 @@ class Level:
                     "ppm_autotune")
         return t.value, s.value, bool(c.value)
 
-    def ensure_adjoint_workspace(self):
+    def ensure_adjoint_workspace(self, precision=0):
         import torch
-        need = int(lib().ppm_adjoint_workspace_bytes(self.ctx))
+        need = int(lib().ppm_adjoint_workspace_bytes(self.ctx, int(precision)))
         if getattr(self, "_awork", None) is None or self._awork.numel() < need + 256:
             self._awork = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
         base = self._awork.data_ptr()
@@ -311,11 +311,14 @@ class Level:
                     "ppm_set_adjoint_workspace")
 
     def hydro_step_adjoint(self, U, Unew_bar, U_bar, dx, p, dt=0.0, dt_dev=None, stream=None):
-        """U_bar = J^T Unew_bar for the step from U (ghosts filled), dt frozen."""
-        if self._work is None or self._work_prec != 0 or self._work.numel() < self.workspace_bytes(0):
-            self.ensure_workspace(0)
-        if getattr(self, "_awork", None) is None:
-            self.ensure_adjoint_workspace()
+        """U_bar = J^T Unew_bar for the step from U (ghosts filled), dt frozen;
+        the reverse runs in the step's precision (p.precision)."""
+        prec = int(p.precision)
+        if self._work is None or self._work_prec != prec or self._work.numel() < self.workspace_bytes(prec) + 256:
+            self.ensure_workspace(prec)
+        if getattr(self, "_awork", None) is None or getattr(self, "_awork_prec", None) != prec:
+            self.ensure_adjoint_workspace(prec)
+            self._awork_prec = prec
         self._check(lib().ppm_hydro_step_adjoint(self.ctx, _ptr(U), _ptr(Unew_bar), _ptr(U_bar), float(dt),
                                                  _ptr(dt_dev), _dp3(*dx), ctypes.byref(p), _stream(stream)),
                     "ppm_hydro_step_adjoint")

@@ -364,3 +364,35 @@ def test_jvp_matches_central_differences(limiter):
     fd = (interior(Up) - interior(Um)) / (2 * eps)
     err = np.abs(fd - interior(J)).max() / np.abs(interior(J)).max()
     assert err < 1e-6, err
+
+
+def test_fp32_jvp_primal_is_the_fp32_step_and_tangent_its_derivative():
+    """FP32-reconstruction tangent (float primal, double tangent): its primal
+    is the FP32 step bit for bit (so every branch is the FP32 step's own), and
+    its tangent is that step's derivative: central differences of the FP32
+    step on the smooth unlimited step with a bulk flow (no characteristic
+    speed near zero), eps = 3e-3 (float rounding of the quotient and the
+    truncation error both near 1e-5); it also equals the FP64 tangent to
+    float accuracy there (observed 1.1e-7)."""
+    wl = I.cfg4(8, amp=0.05, bulk=(0.3, 0.2, 0.25))
+    U = _filled(wl)[0]
+    p32 = O.params(gamma=1.4, limiter=0, precision=1)
+    p64 = O.params(gamma=1.4, limiter=0)
+    rng = np.random.default_rng(19)
+    v = np.zeros_like(U)
+    interior(v)[:] = rng.normal(size=interior(v).shape)
+    lay = wl.layout
+    vv = [v]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, vv)
+    dt = 0.02
+    A, J, _ = O.step_jvp(U, vv[0], dt, wl.dx, p32)
+    A0, _, _ = O.step(U, dt, wl.dx, p32)
+    assert np.array_equal(interior(A), interior(A0))
+    eps = 3e-3
+    Up, _, _ = O.step(U + eps * vv[0], dt, wl.dx, p32)
+    Um, _, _ = O.step(U - eps * vv[0], dt, wl.dx, p32)
+    fd = (interior(Up) - interior(Um)) / (2 * eps)
+    scale = np.abs(interior(J)).max()
+    assert np.abs(fd - interior(J)).max() / scale < 1e-4
+    _, J64, _ = O.step_jvp(U, vv[0], dt, wl.dx, p64)
+    assert np.abs(interior(J64) - interior(J)).max() / scale < 1e-6
