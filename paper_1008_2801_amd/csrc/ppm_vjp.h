@@ -97,7 +97,7 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
   rob -= irhob * irho * irho;
 }
 
-// Newton steps whose inputs the Riemann reverse keeps in registers.
+// Newton steps whose records the Riemann reverse keeps in registers.
 constexpr int RIEM_KEEP = 3;
 
 // One Newton step of the two-shock iteration, forward (returns the new p).
@@ -115,13 +115,18 @@ PPM_HD S riem_iter(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const 
   return smax(pn, G.small_pres);
 }
 
-// Reverse of one Newton step: pnb = adjoint of the output p; returns the
-// adjoint of the input p and accumulates the others.
+// What the reverse of one Newton step needs from its forward evaluation.
+template <class S> struct RiemIt {
+  S p, sl, sr, iwl, iwr;  // input p, sqrt(a_s), 1/W_s
+  bool floored;           // the output was bound by the pressure floor
+};
+
+// One Newton step, forward (the same arithmetic as riem_iter), recording
+// what its reverse needs.
 template <class S>
-PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G, S pnb, S& clb,
-                       S& crb, S& plb, S& prb, S& ulb, S& urb, S& iplb, S& iprb) {
-  const S al = ONE + G.beta * (p * ipl - ONE), ar = ONE + G.beta * (p * ipr - ONE);
-  const S sl = ssqrt(al), sr = ssqrt(ar);
+PPM_HD S riem_iter_rec(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G, RiemIt<S>& r) {
+  const S sl = ssqrt(ONE + G.beta * (p * ipl - ONE));
+  const S sr = ssqrt(ONE + G.beta * (p * ipr - ONE));
   const S wl = cl * sl, wr = cr * sr;
   const S iwl = ONE / wl, iwr = ONE / wr;
   const S xl = cl * iwl, xr = cr * iwr;
@@ -129,9 +134,29 @@ PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   const S izr = HALF * iwr * (ONE + xr * xr);
   const S usl = ul - (p - pl) * iwl;
   const S usr = ur + (p - pr) * iwr;
+  const S pn = p - (usr - usl) / (izl + izr);
+  r.p = p;
+  r.sl = sl;
+  r.sr = sr;
+  r.iwl = iwl;
+  r.iwr = iwr;
+  r.floored = pn < G.small_pres;
+  return smax(pn, G.small_pres);
+}
+
+// Reverse of one Newton step from its record: pnb = adjoint of the output
+// p; returns the adjoint of the input p and accumulates the others.
+template <class S>
+PPM_HD S riem_iter_vjp_rec(const RiemIt<S>& r, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G,
+                           S pnb, S& clb, S& crb, S& plb, S& prb, S& ulb, S& urb, S& iplb, S& iprb) {
+  if (r.floored) return S(0);  // floor bound: the output does not depend on p
+  const S p = r.p, sl = r.sl, sr = r.sr, iwl = r.iwl, iwr = r.iwr;
+  const S xl = cl * iwl, xr = cr * iwr;
+  const S izl = HALF * iwl * (ONE + xl * xl);
+  const S izr = HALF * iwr * (ONE + xr * xr);
+  const S usl = ul - (p - pl) * iwl;
+  const S usr = ur + (p - pr) * iwr;
   const S dU = usr - usl, Q = izl + izr;
-  const S pn = p - dU / Q;
-  if (pn < G.small_pres) return S(0);  // floor bound: the output does not depend on p
   S pb = pnb;
   const S iQ = ONE / Q;
   const S dUb = -pnb * iQ;
@@ -164,6 +189,15 @@ PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   return pb;
 }
 
+// Reverse of one Newton step with its forward recomputed from the input p.
+template <class S>
+PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G, S pnb, S& clb,
+                       S& crb, S& plb, S& prb, S& ulb, S& urb, S& iplb, S& iprb) {
+  RiemIt<S> r;
+  (void)riem_iter_rec(p, cl, cr, pl, pr, ul, ur, ipl, ipr, G, r);
+  return riem_iter_vjp_rec(r, cl, cr, pl, pr, ul, ur, ipl, ipr, G, pnb, clb, crb, plb, prb, ulb, urb, iplb, iprb);
+}
+
 // Reverse of riemann<d>: Fb = adjoint of the flux; accumulates Lb, Rb.
 template <int d, class S>
 PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[5], S Lb[5], S Rb[5]) {
@@ -178,16 +212,15 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   const bool fl0 = p0r < G.small_pres;
   const S p0 = smax(p0r, G.small_pres);
   const S ipl = ONE / pl, ipr = ONE / pr;
-  // the inputs of the first RIEM_KEEP Newton steps are kept for the reverse
-  // sweep (fully unrolled, so they stay in registers); later ones are
-  // recomputed from the last kept one
-  S pit[RIEM_KEEP];
+  // the first RIEM_KEEP Newton steps are recorded for the reverse sweep
+  // (fully unrolled, so the records stay in registers); later ones are
+  // recomputed from the output of the last recorded one
+  RiemIt<S> rec[RIEM_KEEP];
   S pst = p0;
 #pragma unroll
-  for (int it = 0; it < RIEM_KEEP; ++it) {
-    pit[it] = pst;
-    if (it < G.iters) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
-  }
+  for (int it = 0; it < RIEM_KEEP; ++it)
+    if (it < G.iters) pst = riem_iter_rec(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G, rec[it]);
+  const S pkeep = pst;
   for (int it = RIEM_KEEP; it < G.iters; ++it) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
   const S all = ONE + G.beta * (pst * ipl - ONE), alr = ONE + G.beta * (pst * ipr - ONE);
   const S sl = ssqrt(all), sr = ssqrt(alr);
@@ -269,14 +302,15 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   // Newton iterations in reverse
   S pb = pstb;
   for (int k = G.iters - 1; k >= RIEM_KEEP; --k) {
-    S pk = pit[RIEM_KEEP - 1];
-    for (int j = RIEM_KEEP - 1; j < k; ++j) pk = riem_iter(pk, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
+    S pk = pkeep;
+    for (int j = RIEM_KEEP; j < k; ++j) pk = riem_iter(pk, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
     pb = riem_iter_vjp(pk, cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb, iprb);
   }
 #pragma unroll
   for (int k = RIEM_KEEP - 1; k >= 0; --k)
     if (k < G.iters)
-      pb = riem_iter_vjp(pit[k], cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb, iprb);
+      pb = riem_iter_vjp_rec(rec[k], cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb,
+                             iprb);
   // acoustic guess (floor frozen)
   if (!fl0) {
     const S iD0 = ONE / D0;

@@ -313,3 +313,47 @@ def test_tiling_does_not_change_results_and_autotuner_caches(tmp_path):
     lev2 = P.Level(wl.layout)
     t2, s2, hit2 = lev2.autotune(U, wl.dx, p, reps=1, cache_path=cache)
     assert hit2 and (t2, s2) == (t, s) and lev2.get_tiling() == (t, s)
+
+
+def _smooth_on(lay, seed, gamma=1.4):
+    rng = np.random.default_rng(seed)
+    L = tuple((np.array(lay.domain_hi) + 1) / 16.0)
+    S = [I.ModeSum(rng, 4, 2, L) for _ in range(5)]
+
+    def prim(x, y, z):
+        return (1.0 + 0.3 * S[0](x, y, z), 0.5 * S[1](x, y, z), 0.5 * S[2](x, y, z), 0.5 * S[3](x, y, z),
+                1.0 + 0.3 * S[4](x, y, z))
+    h = (1.0 / 16,) * 3
+    return I.Workload("tiny", lay, I._fill_state(lay, h, gamma, prim), h, gamma, 1)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (1, 1, 0, 0, 2, 2)])
+def test_boxes_thinner_than_the_ghost_width_match_oracle(bc):
+    """Boxes of 1, 2 and 3 zones along an axis: a ghost shell then spans
+    several boxes (and periodic images) per face, edge and corner."""
+    lay = I.tensor_tiling((1, 3, 4), (2, 2), (1, 5), bc=bc)
+    wl = _smooth_on(lay, 41)
+    _, arena, dts, flags, _ = gpu_run(wl, 2)
+    ost, odts, ofl, _ = oracle_run(wl, 2)
+    assert dts == odts and flags == ofl == 0
+    compare_level(wl, arena, ost)
+
+
+def test_state_at_rest_preserved_bitwise():
+    """u = 0 everywhere: every Riemann solve lands on u* = 0 exactly (the
+    two-sided average) and the state must not change at all."""
+    wl = I.uniform(10, rho=0.8, vel=(0.0, 0.0, 0.0), p=1.9)
+    _, arena, _, flags, _ = gpu_run(wl, 2)
+    assert flags == 0
+    assert np.array_equal(interior(wl.layout.view(arena, 0)), interior(wl.layout.view(wl.arena, 0)))
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_strong_shock_tube_matches_oracle(axis):
+    """Pressure ratio 1e5 and density ratio 10 (a strong blast): flattening,
+    the limiter and the two-shock iteration far from the acoustic guess."""
+    wl = I.shock_tube(48, axis=axis, left=(10.0, 0.0, 1000.0), right=(1.0, 0.0, 0.01))
+    _, arena, dts, flags, _ = gpu_run(wl, 6)
+    ost, odts, ofl, _ = oracle_run(wl, 6)
+    assert dts == odts and flags == ofl
+    compare_level(wl, arena, ost)
