@@ -376,9 +376,9 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ ti
 
 // Trace adjoint of axis d: per traced zone, the contributions to the
 // primitives of its 5-zone stencil along d (GT of axis d), the sound speed
-// (CB of axis d) and the flattening coefficient (PHB of axis d).
-// One launch per axis (the three bodies in one kernel would share the
-// register budget of the largest and spill).
+// (CB of axis d) and the flattening coefficient (PHB of axis d).  One launch
+// per axis: the bodies of several axes in one kernel would share the
+// register budget of the largest and spill.
 template <int d, class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
                                                     const DevBox* __restrict__ boxes,
