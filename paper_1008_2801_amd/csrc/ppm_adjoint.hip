@@ -4,16 +4,17 @@
 // Given the step's input state U (ghosts filled) and the adjoint Ub' of the
 // new state's valid zones, the adjoint of U's valid zones is formed as
 //   recompute: prim, flatten, trace, riemann1, riemann2   (forward kernels)
-//   adj_update    Ub' -> adjoint of the pre-source state (Ufb) + direct part
-//   adj_riemann3  final fluxes' adjoint -> corrected-state adjoints (U3b)
-//                 and traced-state adjoints
+//   adj_riemann3  final fluxes' adjoint (from Ub' through the update and its
+//                 Heun source) -> corrected-state adjoints (U3b) and
+//                 traced-state adjoints
 //   adj_riemann2  stage-2 fluxes' adjoint (from U3b) -> U2b, traced states
 //   adj_riemann1  stage-1 fluxes' adjoint (from U2b) -> traced states
 //   adj_trace     traced-state adjoints -> per-zone contributions to the
 //                 primitives of the 5-zone stencil of each axis
 //   adj_flatten   flattening adjoint -> contributions to the pressure stencil
 //   adj_gather    per stored zone: the contributions that reach it, then the
-//                 primitive conversion's adjoint -> conserved adjoints
+//                 primitive conversion's adjoint -> conserved adjoints (plus,
+//                 on valid zones, Ub' through the update)
 //   adj_fill      ghost adjoints gathered into their owning valid zones
 // Every reverse stage writes only the entries it owns or accumulates through
 // a gather in a fixed order: no atomics, results reproducible bit for bit.
@@ -30,8 +31,7 @@ namespace {
 // Adjoint workspace planes: traced grid (A_*) and stored grid (AS_*).  The
 // trace reverse's outputs (GT, CB, PHB) reuse the corrected-state planes,
 // which are dead once the stage-1 reverse has run.
-constexpr int A_UF = 0;              // 5: adjoint of the pre-source state (valid zones, else 0)
-constexpr int A_TB = A_UF + 5;       // 30: traced-state adjoints [d][side][m]
+constexpr int A_TB = 0;              // 30: traced-state adjoints [d][side][m]
 constexpr int A_U3 = A_TB + 30;      // 30: stage-3 corrected-state adjoints [d][side][m]
 constexpr int A_U2 = A_U3 + 30;      // 60: stage-2 corrected-state adjoints [pair][side][m]
 constexpr int A_GT = A_U3;           // 75: trace contributions [d][m][offset + 2]
@@ -51,58 +51,49 @@ __device__ __forceinline__ long long eidx(const DevBox& B, int x, int y, int z) 
   return ((long long)(z + 1) * (B.n[1] + 2) + (y + 1)) * (B.n[0] + 2) + (x + 1);
 }
 
-// Adjoint of the update and of the Heun source (FP64, as the update).
-template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_adj_update(const Tile* __restrict__ tiles, int ntiles,
-                                                     const DevBox* __restrict__ boxes,
-                                                     const double* __restrict__ Ubn, S* __restrict__ aw,
-                                                     long long LE, double* __restrict__ as, long long LS,
-                                                     const StepConsts* __restrict__ sc, int grav, double g0,
-                                                     double g1, double g2) {
-  const int tt = xcd_tile(ntiles);
-  if (tt < 0) return;
-  const Tile tl = tiles[tt];
-  const DevBox B = boxes[tl.box];
-  EZone z;
-  if (!ezone(tl, B, z)) return;
-  S* uf = aw + A_UF * LE + B.eoff + z.e;
-  const bool valid = z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] && z.x[2] >= 0 &&
-                     z.x[2] < B.n[2];
-  if (!valid) {
+// Reverse of the update's Heun source at one valid zone (FP64, as the
+// update).  ub: the new state's adjoint there.  uf: the adjoint of the
+// pre-source state (what the flux divergence receives); direct: the part
+// that reaches the zone's own old state through the source.  The source is
+// S(U) = (0, rho g, (rho u).g), so S^T V = ((g.V_mom), g V_E, 0).
+__device__ __forceinline__ void heun_reverse(const double ub[5], int grav, double dt, double hdt, double g0,
+                                             double g1, double g2, double uf[5], double direct[5]) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) uf[m * LE] = S(0);
+  for (int m = 0; m < 5; ++m) { uf[m] = ub[m]; direct[m] = ub[m]; }
+  if (!grav) return;
+  auto st = [&](const double v[5], double o[5]) {
+    o[0] = (g0 * v[1] + g1 * v[2]) + g2 * v[3];
+    o[1] = g0 * v[4];
+    o[2] = g1 * v[4];
+    o[3] = g2 * v[4];
+    o[4] = 0.0;
+  };
+  double s[5], s1[5];
+  st(ub, s);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) uf[m] = ub[m] + hdt * s[m];
+  st(uf, s1);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) direct[m] = uf[m] + (dt * s1[m] - hdt * s[m]);
+}
+
+// Pre-source adjoint of zone (x, y, z) of box B from the new state's adjoint
+// (zero outside the valid zones).
+__device__ __forceinline__ void pre_source_adjoint(const double* __restrict__ Ubn, const DevBox& B, int x, int y,
+                                                   int z, int grav, const StepConsts* __restrict__ sc,
+                                                   double g0, double g1, double g2, double uf[5]) {
+  if (x < 0 || x >= B.n[0] || y < 0 || y >= B.n[1] || z < 0 || z >= B.n[2]) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) uf[m] = 0.0;
     return;
   }
   const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
   const long long NS = (long long)N0 * N1 * N2;
-  const long long li = ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
-  double ub[5], u1b[5], ud[5];
+  const long long li = ((long long)(z + NG) * N1 + (y + NG)) * N0 + (x + NG);
+  double ub[5], direct[5];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) { ub[m] = Ubn[B.soff + li + m * NS]; u1b[m] = ub[m]; ud[m] = 0.0; }
-  if (grav) {
-    const double dt = sc->dt, hdt = sc->hdt;
-    // S^T V for the constant-gravity source S(U) = (0, rho g, (rho u).g)
-    auto st = [&](const double v[5], double o[5]) {
-      o[0] = (g0 * v[1] + g1 * v[2]) + g2 * v[3];
-      o[1] = g0 * v[4];
-      o[2] = g1 * v[4];
-      o[3] = g2 * v[4];
-      o[4] = 0.0;
-    };
-    double s[5], s1[5];
-    st(ub, s);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) u1b[m] = ub[m] + hdt * s[m];
-    st(u1b, s1);
-#pragma unroll
-    for (int m = 0; m < 5; ++m) ud[m] = dt * s1[m] - hdt * s[m];
-  }
-  double* ubs = as + AS_UB * LS + B.poff + li;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    uf[m * LE] = (S)u1b[m];
-    ubs[m * LS] = u1b[m] + ud[m];
-  }
+  for (int m = 0; m < 5; ++m) ub[m] = Ubn[B.soff + li + m * NS];
+  heun_reverse(ub, grav, sc->dt, sc->hdt, g0, g1, g2, uf, direct);
 }
 
 // Corrected state of axis d at zone offset `off` from the lane's zone,
@@ -132,7 +123,8 @@ template <int d, class S>
 __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int ntiles,
                                             const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                             long long LE, S* __restrict__ aw, const Gas<S>& G,
-                                            const StepConsts* __restrict__ sc) {
+                                            const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
+                                            int grav, double g0, double g1, double g2) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
@@ -162,22 +154,26 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
   const S c1 = SC<S>::dt2h(sc)[t1], c2 = SC<S>::dt2h(sc)[t2];
   const S* w = work + B.eoff + z.e;
+  // the final flux's adjoint from the pre-source adjoints of the face's two
+  // zones (the update is FP64)
+  double ufR[5], ufL[5];
+  pre_source_adjoint(Ubn, B, z.x[0], z.x[1], z.x[2], grav, sc, g0, g1, g2, ufR);
+  pre_source_adjoint(Ubn, B, z.x[0] - (d == 0), z.x[1] - (d == 1), z.x[2] - (d == 2), grav, sc, g0, g1, g2, ufL);
   S Fb[5];
-  const double dtdx = sc->dtdx[d];  // the update is FP64
+  const double dtdx = sc->dtdx[d];
 #pragma unroll
-  for (int m = 0; m < 5; ++m)
-    Fb[m] = (S)(dtdx * ((double)a[(A_UF + m) * LE] - (double)a[(A_UF + m) * LE - sd]));
+  for (int m = 0; m < 5; ++m) Fb[m] = (S)(dtdx * (ufR[m] - ufL[m]));
   S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
-  int fl = 0;
+  bool rfL, pfL, rfR, pfR;
   r3_state<d>(w, LE, -sd, 0, s1, s2, c1, c2, G, qeL, ueL);
   r3_state<d>(w, LE, 0, 1, s1, s2, c1, c2, G, qeR, ueR);
-  cons_to_prim_floor(ueL, G, L, fl);
-  cons_to_prim_floor(ueR, G, R, fl);
+  cons_to_prim_dec(ueL, G, L, rfL, pfL);
+  cons_to_prim_dec(ueR, G, R, rfR, pfR);
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
   riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
-  cons_to_prim_floor_vjp(ueL, G, Lb, uLb);
-  cons_to_prim_floor_vjp(ueR, G, Rb, uRb);
+  cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
+  cons_to_prim_vjp_q(R, rfR, pfR, G, Rb, uRb);
   S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
   prim_to_cons_vjp(qeL, G, uLb, tLb);
   prim_to_cons_vjp(qeR, G, uRb, tRb);
@@ -194,11 +190,12 @@ template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                                  long long LE, S* __restrict__ aw, Gas<S> G,
-                                                 const StepConsts* __restrict__ sc) {
+                                                 const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
+                                                 int grav, double g0, double g1, double g2) {
   switch (blockIdx.y) {
-    case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+    case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
+    case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
+    default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
   }
 }
 
@@ -209,8 +206,8 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ ti
 template <int d, int t, class S>
 __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restrict__ a, long long LE,
                                             long long sd, long long stt, const S qeL[5], const S qeR[5],
-                                            const Gas<S>& G, const StepConsts* __restrict__ sc, S tLb[5],
-                                            S tRb[5]) {
+                                            const S ue0L[5], const S ue0R[5], const Gas<S>& G,
+                                            const StepConsts* __restrict__ sc, S tLb[5], S tRb[5]) {
   constexpr int pr = pair_index(d, t);
   constexpr int r = 3 - d - t;
   const S c3 = SC<S>::dt3h(sc)[t];
@@ -223,23 +220,21 @@ __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restri
     Fb[m] = c2d * ((up[0] + um[0]) - (up[-sd] + um[-sd]));
   }
   S ueL[5], ueR[5], L[5], R[5];
-  int fl = 0;
-  prim_to_cons(qeL, G, ueL);
-  prim_to_cons(qeR, G, ueR);
+  bool rfL, pfL, rfR, pfR;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const S* fL = w + (E_F1 + t * 5 + m) * LE - sd;
     const S* fR = w + (E_F1 + t * 5 + m) * LE;
-    ueL[m] = ueL[m] - c3 * (fL[stt] - fL[0]);
-    ueR[m] = ueR[m] - c3 * (fR[stt] - fR[0]);
+    ueL[m] = ue0L[m] - c3 * (fL[stt] - fL[0]);
+    ueR[m] = ue0R[m] - c3 * (fR[stt] - fR[0]);
   }
-  cons_to_prim_floor(ueL, G, L, fl);
-  cons_to_prim_floor(ueR, G, R, fl);
+  cons_to_prim_dec(ueL, G, L, rfL, pfL);
+  cons_to_prim_dec(ueR, G, R, rfR, pfR);
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
   riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
-  cons_to_prim_floor_vjp(ueL, G, Lb, uLb);
-  cons_to_prim_floor_vjp(ueR, G, Rb, uRb);
+  cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
+  cons_to_prim_vjp_q(R, rfR, pfR, G, Rb, uRb);
   prim_to_cons_vjp(qeL, G, uLb, tLb);
   prim_to_cons_vjp(qeR, G, uRb, tRb);
 #pragma unroll
@@ -296,9 +291,12 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
     qeL[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
     qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
   }
+  S ue0L[5], ue0R[5];
+  prim_to_cons(qeL, G, ue0L);
+  prim_to_cons(qeR, G, ue0R);
   S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
-  if (va) adj_r2_pair<d, t1, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, G, sc, tLb, tRb);
-  if (vb) adj_r2_pair<d, t2, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, G, sc, tLb, tRb);
+  if (va) adj_r2_pair<d, t1, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, ue0L, ue0R, G, sc, tLb, tRb);
+  if (vb) adj_r2_pair<d, t2, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, ue0L, ue0R, G, sc, tLb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
@@ -544,7 +542,10 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
                                                      const DevBox* __restrict__ boxes,
                                                      const S* __restrict__ aw, long long LE,
                                                      const double* __restrict__ U, double* __restrict__ as,
-                                                     long long LS, Gas<S> G, double* __restrict__ Ub) {
+                                                     long long LS, Gas<S> G, double* __restrict__ Ub,
+                                                     const double* __restrict__ Ubn,
+                                                     const StepConsts* __restrict__ sc, int grav, double g0,
+                                                     double g1, double g2) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tilesS[tt];
@@ -593,9 +594,18 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
   for (int c = 0; c < 5; ++c) uc[c] = (S)U[B.soff + idx + c * NSS];
   prim_cell_vjp(uc, G, qb, ub);
   const bool valid = j[0] >= 0 && j[0] < B.n[0] && j[1] >= 0 && j[1] < B.n[1] && j[2] >= 0 && j[2] < B.n[2];
+  // valid zones: plus the new state's adjoint through the update (identity
+  // and Heun source); ghost zones: only what the stencils gave them
+  double direct[5] = {0, 0, 0, 0, 0};
+  if (valid) {
+    double ubn[5], uf[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ubn[c] = Ubn[B.soff + idx + c * NSS];
+    heun_reverse(ubn, grav, sc->dt, sc->hdt, g0, g1, g2, uf, direct);
+  }
   double* u = as + AS_UB * LS + B.poff + idx;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) u[c * LS] = (valid ? u[c * LS] : 0.0) + (double)ub[c];
+  for (int c = 0; c < 5; ++c) u[c * LS] = direct[c] + (double)ub[c];
   if (!valid) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) Ub[B.soff + idx + c * NSS] = 0.0;
@@ -672,9 +682,8 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, cons
   // every workspace entry is written before it is read: each reverse stage
   // writes all entries it owns, zeros included
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
-  hipLaunchKernelGGL(k_adj_update<S>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, Ubn, aw, L.LE, as, L.LS,
-                     L.consts, grav, g[0], g[1], g[2]);
-  hipLaunchKernelGGL(k_adj_r3<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r3<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts, Ubn,
+                     grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<0, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
@@ -685,7 +694,8 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, cons
                      aw, G, L.consts);
   if (G.flattening)
     hipLaunchKernelGGL(k_adj_flatten<S>, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, aw, L.LE, G);
-  hipLaunchKernelGGL(k_adj_gather<S>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, U, as, L.LS, G, Ub);
+  hipLaunchKernelGGL(k_adj_gather<S>, dim3(gS), blk, 0, s, L.tilesS, nS, L.boxes, aw, L.LE, U, as, L.LS, G, Ub,
+                     Ubn, L.consts, grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_fill, dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, L.desc, L.inv_start, L.inv_idx, as,
                      L.LS, Ub);
   return hipGetLastError();

@@ -380,6 +380,25 @@ PPM_HD void cons_to_prim_floor_vjp(const S U[5], const Gas<S>& G, const S qb[5],
   prim_tail_vjp(r, u, v, w, G, qb[0], qb[1], qb[2], qb[3], pb, Ub, rfl);
 }
 
+// cons_to_prim_floor (same arithmetic), also returning its two floor
+// decisions for the reverse.
+template <class S>
+PPM_HD void cons_to_prim_dec(const S U[5], const Gas<S>& G, S q[5], bool& rfl, bool& pfl) {
+  rfl = U[0] < G.small_dens;
+  const S r = smax(U[0], G.small_dens);
+  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
+  const S ke = HALF * r * ((u * u + v * v) + w * w);
+  const S p = G.gm1 * (U[4] - ke);
+  pfl = p < G.small_pres;
+  q[0] = r; q[1] = u; q[2] = v; q[3] = w; q[4] = smax(p, G.small_pres);
+}
+
+// Reverse of cons_to_prim_floor from its outputs q and floor decisions.
+template <class S>
+PPM_HD void cons_to_prim_vjp_q(const S q[5], bool rfl, bool pfl, const Gas<S>& G, const S qb[5], S Ub[5]) {
+  prim_tail_vjp(q[0], q[1], q[2], q[3], G, qb[0], qb[1], qb[2], qb[3], pfl ? S(0) : qb[4], Ub, rfl);
+}
+
 // Cell conversion of a stored zone (rho, u, v, w, p, c): Ub += J^T qb.
 template <class S>
 PPM_HD void prim_cell_vjp(const S U[5], const Gas<S>& G, const S qb[6], S Ub[5]) {
