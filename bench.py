@@ -227,6 +227,27 @@ def adjoint_costs(wl, nsteps, every, reps=3, precision=0, rollout=True):
     return res
 
 
+def copy_bandwidth(gib=2, reps=5):
+    """Measured HBM bandwidth of a plain device-to-device copy (bytes read +
+    written per second), the practical ceiling next to the 8 TB/s spec."""
+    import torch
+    n = gib * (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / sec / 1e9
+
+
 def cpu_baseline(wl, window_edge, gamma):
     """Serial oracle on one step of a cubic window of the workload."""
     import numpy as np
@@ -380,6 +401,7 @@ def main():
                      "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops},
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
         "step_flop_rate_tflops": step_flops * args.steps / (ms / 1e3) / 1e12,
+        "hbm_copy_GBps": copy_bandwidth(),
         "status_flags": flags,
     }
     if not args.no_extras:

@@ -70,14 +70,14 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.oracle_step.restype = ctypes.c_int
         L.oracle_step.argtypes = [_dp, _ip, _ip, _ip, ctypes.c_double, _dp,
-                                  ctypes.POINTER(OParams), _dp, ctypes.POINTER(_dp)]
+                                  ctypes.POINTER(OParams), _ip, _dp, ctypes.POINTER(_dp)]
         L.oracle_step_count.restype = ctypes.c_int
         L.oracle_step_count.argtypes = [_dp, _ip, _ip, _ip, ctypes.c_double, _dp,
-                                        ctypes.POINTER(OParams), _dp,
+                                        ctypes.POINTER(OParams), _ip, _dp,
                                         ctypes.POINTER(ctypes.c_ulonglong)]
         L.oracle_step_jvp.restype = ctypes.c_int
         L.oracle_step_jvp.argtypes = [_dp, _dp, _ip, _ip, _ip, ctypes.c_double, _dp,
-                                      ctypes.POINTER(OParams), _dp, _dp]
+                                      ctypes.POINTER(OParams), _ip, _dp, _dp]
         L.oracle_max_wavespeed.restype = ctypes.c_double
         L.oracle_max_wavespeed.argtypes = [_dp, _ip, _dp, ctypes.POINTER(OParams), _ip]
         L.oracle_riemann.restype = ctypes.c_int
@@ -113,13 +113,33 @@ def _box_n(U):
     return (U.shape[3] - 2 * NG, U.shape[2] - 2 * NG, U.shape[1] - 2 * NG)
 
 
-def step(U, dt, dx, p, window=None, fluxes=False, out=None):
+def _walls(walls):
+    """Six wall flags (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi) as a C array, or None."""
+    if walls is None:
+        return None
+    return (ctypes.c_int * 6)(*[int(bool(w)) for w in walls])
+
+
+def box_walls(boxes, domain, bc, b):
+    """The faces of box b that lie on a reflecting domain boundary, as six
+    flags (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi)."""
+    lo, hi = boxes[b]
+    dlo, dhi = domain
+    out = []
+    for d in range(3):
+        out.append(int(lo[d] == dlo[d] and bc[2 * d] == BC_REFLECT))
+        out.append(int(hi[d] == dhi[d] and bc[2 * d + 1] == BC_REFLECT))
+    return tuple(out)
+
+
+def step(U, dt, dx, p, window=None, fluxes=False, out=None, walls=None):
     """One step of one box (ghosts of U already filled).
 
     Returns (Unew, F, flags).  Unew has U's shape; only the window's valid
     zones are written (others copy U).  F is None or a list of three
     face-centred arrays, F[d] of shape (5, nz', ny', nx') with n_d + 1 faces
     along d.  window: ((x0, y0, z0), (x1, y1, z1)) inclusive valid indices.
+    walls: the box's faces on a reflecting domain boundary (box_walls).
     """
     n = _box_n(U)
     wlo, whi = ((0, 0, 0), tuple(x - 1 for x in n)) if window is None else window
@@ -134,27 +154,27 @@ def step(U, dt, dx, p, window=None, fluxes=False, out=None):
             F.append(np.zeros((5, e[2], e[1], e[0])))
         Fp = (_dp * 3)(*[_d(f) for f in F])
     fl = lib().oracle_step(_d(U), _i3(n), _i3(wlo), _i3(whi), float(dt), _d3(dx),
-                           ctypes.byref(p), _d(Unew), Fp)
+                           ctypes.byref(p), _walls(walls), _d(Unew), Fp)
     if fl < 0:
         raise ValueError("oracle_step: invalid arguments")
     return Unew, F, fl
 
 
-def step_count(U, dt, dx, p, window=None):
+def step_count(U, dt, dx, p, window=None, walls=None):
     """Step with operation counting.  Returns (Unew, counts[stage][kind], flags)."""
     n = _box_n(U)
     wlo, whi = ((0, 0, 0), tuple(x - 1 for x in n)) if window is None else window
     Unew = U.copy()
     cnt = (ctypes.c_ulonglong * (len(STAGES) * len(OPKINDS)))()
     fl = lib().oracle_step_count(_d(U), _i3(n), _i3(wlo), _i3(whi), float(dt), _d3(dx),
-                                 ctypes.byref(p), _d(Unew), cnt)
+                                 ctypes.byref(p), _walls(walls), _d(Unew), cnt)
     if fl < 0:
         raise ValueError("oracle_step_count: invalid arguments")
     counts = np.array(list(cnt), dtype=np.int64).reshape(len(STAGES), len(OPKINDS))
     return Unew, counts, fl
 
 
-def step_jvp(U, dU, dt, dx, p, window=None):
+def step_jvp(U, dU, dt, dx, p, window=None, walls=None):
     """(step(U), J dU) with frozen dt and branches.  Ghosts of U and dU must be filled."""
     n = _box_n(U)
     assert dU.shape == U.shape and dU.dtype == np.float64 and dU.flags.c_contiguous
@@ -162,7 +182,7 @@ def step_jvp(U, dU, dt, dx, p, window=None):
     Unew = U.copy()
     dUnew = np.zeros_like(U)
     fl = lib().oracle_step_jvp(_d(U), _d(dU), _i3(n), _i3(wlo), _i3(whi), float(dt), _d3(dx),
-                               ctypes.byref(p), _d(Unew), _d(dUnew))
+                               ctypes.byref(p), _walls(walls), _d(Unew), _d(dUnew))
     if fl < 0:
         raise ValueError("oracle_step_jvp: invalid arguments")
     return Unew, dUnew, fl
@@ -249,8 +269,8 @@ def advance(boxes, domain, bc, states, nsteps, dx, p, dt=None, fluxes=False):
             dtn = dt
         dts.append(dtn)
         new, F = [], []
-        for U in states:
-            Un, Fb, fl = step(U, dtn, dx, p, fluxes=fluxes)
+        for b, U in enumerate(states):
+            Un, Fb, fl = step(U, dtn, dx, p, fluxes=fluxes, walls=box_walls(boxes, domain, bc, b))
             flags |= fl
             new.append(Un)
             F.append(Fb)

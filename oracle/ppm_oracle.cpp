@@ -525,6 +525,23 @@ struct Step {
   double dt, h[3];
   Consts<S> K;
   int flags = 0;
+  // faces of the box on a reflecting domain boundary: wall[2d] low, [2d+1] high
+  int wall[6] = {0, 0, 0, 0, 0, 0};
+
+  // Riemann problem on a reflecting wall (R14): the state outside the wall
+  // is the mirror image of the state inside it (normal velocity negated), so
+  // the solve gives u* = 0 — no mass or energy crosses the wall, only the
+  // pressure acts on it — whatever the traced ghost states hold (the gravity
+  // shift of the traced velocities is not mirror-symmetric).
+  void wall_states(int d, const int x[3], S L[5], S R[5]) const {
+    if (wall[2 * d] && x[d] == 0) {
+      for (int m = 0; m < 5; ++m) L[m] = R[m];
+      L[1 + d] = -R[1 + d];
+    } else if (wall[2 * d + 1] && x[d] == n[d]) {
+      for (int m = 0; m < 5; ++m) R[m] = L[m];
+      R[1 + d] = -L[1 + d];
+    }
+  }
 
   const A& u_at(int c, const int x[3]) const {
     return U[(((size_t)c * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)];
@@ -627,6 +644,7 @@ struct Step {
         shifted(x, d, -1, y);
         S L[5], R[5], F[5];
         for (int m = 0; m < 5; ++m) { L[m] = tp[d][m].at(y); R[m] = tm[d][m].at(x); }
+        wall_states(d, x, L, R);
         riemann(L, R, d, K, F, flags);
         for (int m = 0; m < 5; ++m) f1[d][m].at(x) = F[m];
       });
@@ -661,6 +679,7 @@ struct Step {
           stage(ST_TRANS1);
           corrected(tp[d], y, L);
           corrected(tm[d], x, R);
+          wall_states(d, x, L, R);
           stage(ST_RIEM2);
           riemann(L, R, d, K, F, flags);
           for (int m = 0; m < 5; ++m) f2[d][t][m].at(x) = F[m];
@@ -694,6 +713,7 @@ struct Step {
         stage(ST_TRANS2);
         corrected(tp[d], y, L);
         corrected(tm[d], x, R);
+        wall_states(d, x, L, R);
         stage(ST_RIEM3);
         riemann(L, R, d, K, F, flags);
         for (int m = 0; m < 5; ++m) f3[d][m].at(x) = F[m];
@@ -753,9 +773,11 @@ struct Step {
 
 template <class S, class A>
 int run_step(const A* U, const int n[3], const int wlo[3], const int whi[3], double dt,
-             const double h[3], const OParams* P, A* Unew, A* F[3], bool counting) {
+             const double h[3], const OParams* P, const int* walls, A* Unew, A* F[3], bool counting) {
   Step<S, A> st;
   st.U = U;
+  if (walls)
+    for (int f = 0; f < 6; ++f) st.wall[f] = walls[f] != 0;
   for (int d = 0; d < 3; ++d) { st.n[d] = n[d]; st.N[d] = n[d] + 2 * NG; st.h[d] = h[d]; }
   st.P = P;
   st.dt = dt;
@@ -775,23 +797,25 @@ bool window_ok(const int n[3], const int wlo[3], const int whi[3]) {
 extern "C" {
 
 // One step of one box on a window of valid zones (see Step).  precision 0:
-// FP64; 1: FP32 reconstruction with FP64 update.  F may be null (no flux
-// output) or point to three face-centred arrays, any of which may be null.
-// Returns the status flags (1: non-physical input, 2: a floor bound) or -1
-// for invalid arguments.
+// FP64; 1: FP32 reconstruction with FP64 update.  walls: null or six flags
+// (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi) marking the box faces that lie on a
+// reflecting domain boundary.  F may be null (no flux output) or point to
+// three face-centred arrays, any of which may be null.  Returns the status
+// flags (1: non-physical input, 2: a floor bound) or -1 for invalid
+// arguments.
 int oracle_step(const double* U, const int n[3], const int wlo[3], const int whi[3], double dt,
-                const double h[3], const OParams* P, double* Unew, double** F) {
+                const double h[3], const OParams* P, const int* walls, double* Unew, double** F) {
   if (!U || !Unew || !P || !window_ok(n, wlo, whi) || !(dt > 0) || !(P->gamma > 1.0)) return -1;
   if (P->precision == 1)
-    return run_step<float, double>(U, n, wlo, whi, dt, h, P, Unew, F, false);
-  return run_step<double, double>(U, n, wlo, whi, dt, h, P, Unew, F, false);
+    return run_step<float, double>(U, n, wlo, whi, dt, h, P, walls, Unew, F, false);
+  return run_step<double, double>(U, n, wlo, whi, dt, h, P, walls, Unew, F, false);
 }
 
 // Same step with the Counted scalar; counts[stage][kind] receives the number
 // of floating-point operations per stage (kinds: add/sub, mul, div, sqrt,
 // min/max).  FP64 mode only.
 int oracle_step_count(const double* U, const int n[3], const int wlo[3], const int whi[3],
-                      double dt, const double h[3], const OParams* P, double* Unew,
+                      double dt, const double h[3], const OParams* P, const int* walls, double* Unew,
                       unsigned long long* counts) {
   if (!U || !Unew || !P || !window_ok(n, wlo, whi)) return -1;
   const int N[3] = {n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG};
@@ -800,7 +824,7 @@ int oracle_step_count(const double* U, const int n[3], const int wlo[3], const i
   for (size_t i = 0; i < tot; ++i) { uc[i] = Counted(U[i]); un[i] = Counted(Unew[i]); }
   std::memset(g_ops, 0, sizeof(g_ops));
   Counted* none[3] = {nullptr, nullptr, nullptr};
-  int fl = run_step<Counted, Counted>(uc.data(), n, wlo, whi, dt, h, P, un.data(), none, true);
+  int fl = run_step<Counted, Counted>(uc.data(), n, wlo, whi, dt, h, P, walls, un.data(), none, true);
   g_stage = 0;
   for (size_t i = 0; i < tot; ++i) Unew[i] = un[i].v;
   for (int s = 0; s < ST_NSTAGE; ++s)
@@ -812,7 +836,7 @@ int oracle_step_count(const double* U, const int n[3], const int wlo[3], const i
 // with dt frozen and every branch decided on the primal values.  precision
 // 0: FP64; 1: the FP32-reconstruction step (float primal, double tangent).
 int oracle_step_jvp(const double* U, const double* dU, const int n[3], const int wlo[3],
-                    const int whi[3], double dt, const double h[3], const OParams* P,
+                    const int whi[3], double dt, const double h[3], const OParams* P, const int* walls,
                     double* Unew, double* dUnew) {
   if (!U || !dU || !Unew || !dUnew || !P || !window_ok(n, wlo, whi)) return -1;
   const int N[3] = {n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG};
@@ -821,8 +845,8 @@ int oracle_step_jvp(const double* U, const double* dU, const int n[3], const int
   for (size_t i = 0; i < tot; ++i) { ud[i] = Dual(U[i], dU[i]); un[i] = Dual(Unew[i], dUnew[i]); }
   Dual* none[3] = {nullptr, nullptr, nullptr};
   const int fl = (P->precision == 1)
-                     ? run_step<DualF, Dual>(ud.data(), n, wlo, whi, dt, h, P, un.data(), none, false)
-                     : run_step<Dual, Dual>(ud.data(), n, wlo, whi, dt, h, P, un.data(), none, false);
+                     ? run_step<DualF, Dual>(ud.data(), n, wlo, whi, dt, h, P, walls, un.data(), none, false)
+                     : run_step<Dual, Dual>(ud.data(), n, wlo, whi, dt, h, P, walls, un.data(), none, false);
   for (size_t i = 0; i < tot; ++i) { Unew[i] = un[i].v; dUnew[i] = un[i].d; }
   return fl;
 }

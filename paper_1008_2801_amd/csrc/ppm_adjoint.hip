@@ -169,8 +169,13 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   r3_state<d>(w, LE, 0, 1, s1, s2, c1, c2, G, qeR, ueR);
   cons_to_prim_dec(ueL, G, L, rfL, pfL);
   cons_to_prim_dec(ueR, G, R, rfR, pfR);
+  S Lw[5], Rw[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) { Lw[m] = L[m]; Rw[m] = R[m]; }
+  const int ws = wall_states<d>(B, z.x[d], Lw, Rw);
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
-  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  riemann_vjp<d>(Lw, Rw, G, Fb, Lb, Rb);
+  wall_states_vjp<d>(ws, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
   cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
   cons_to_prim_vjp_q(R, rfR, pfR, G, Rb, uRb);
@@ -207,7 +212,8 @@ template <int d, int t, class S>
 __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restrict__ a, long long LE,
                                             long long sd, long long stt, const S qeL[5], const S qeR[5],
                                             const S ue0L[5], const S ue0R[5], const Gas<S>& G,
-                                            const StepConsts* __restrict__ sc, S tLb[5], S tRb[5]) {
+                                            const StepConsts* __restrict__ sc, const DevBox& B, int xd,
+                                            S tLb[5], S tRb[5]) {
   constexpr int pr = pair_index(d, t);
   constexpr int r = 3 - d - t;
   const S c3 = SC<S>::dt3h(sc)[t];
@@ -230,8 +236,13 @@ __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restri
   }
   cons_to_prim_dec(ueL, G, L, rfL, pfL);
   cons_to_prim_dec(ueR, G, R, rfR, pfR);
+  S Lw[5], Rw[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) { Lw[m] = L[m]; Rw[m] = R[m]; }
+  const int ws = wall_states<d>(B, xd, Lw, Rw);
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
-  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  riemann_vjp<d>(Lw, Rw, G, Fb, Lb, Rb);
+  wall_states_vjp<d>(ws, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
   cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
   cons_to_prim_vjp_q(R, rfR, pfR, G, Rb, uRb);
@@ -295,8 +306,8 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
   prim_to_cons(qeL, G, ue0L);
   prim_to_cons(qeR, G, ue0R);
   S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
-  if (va) adj_r2_pair<d, t1, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, ue0L, ue0R, G, sc, tLb, tRb);
-  if (vb) adj_r2_pair<d, t2, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, ue0L, ue0R, G, sc, tLb, tRb);
+  if (va) adj_r2_pair<d, t1, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, ue0L, ue0R, G, sc, B, z.x[d], tLb, tRb);
+  if (vb) adj_r2_pair<d, t2, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, ue0L, ue0R, G, sc, B, z.x[d], tLb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
@@ -351,8 +362,10 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
     L[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - sd];
     R[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
   }
+  const int ws = wall_states<d>(B, z.x[d], L, R);
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
   riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  wall_states_vjp<d>(ws, Lb, Rb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += Lb[m];

@@ -468,7 +468,13 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
     const long long NS = (long long)(n[0] + 2 * NG) * (n[1] + 2 * NG) * (n[2] + 2 * NG);
     const long long NE = (long long)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
     for (int d = 0; d < 3; ++d) db[b].n[d] = n[d];
-    db[b].pad = 0;
+    db[b].wall = 0;
+    for (int d = 0; d < 3; ++d) {
+      if (layout->boxes[b].lo[d] == layout->domain.lo[d] && layout->bc[2 * d] == PPM_BC_REFLECT)
+        db[b].wall |= 1 << (2 * d);
+      if (layout->boxes[b].hi[d] == layout->domain.hi[d] && layout->bc[2 * d + 1] == PPM_BC_REFLECT)
+        db[b].wall |= 1 << (2 * d + 1);
+    }
     db[b].soff = ctx->off[b];
     db[b].poff = ps;
     db[b].eoff = pe;

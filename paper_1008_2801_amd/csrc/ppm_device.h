@@ -87,6 +87,40 @@ inline Gas<S> make_gas(double gamma, double small_dens, double small_pres, int l
   return G;
 }
 
+// Riemann problem on a reflecting wall: the state outside the wall is the
+// mirror image of the state inside it (normal velocity negated), so the solve
+// gives u* = 0 and only the pressure acts on the wall.  xd: the face slot
+// along d.  Returns which state was replaced: 1 the low side (the box's low
+// face is on a wall), 2 the high side, 0 none.
+template <int d, class S>
+__device__ __forceinline__ int wall_states(const DevBox& B, int xd, S L[5], S R[5]) {
+  if (((B.wall >> (2 * d)) & 3) == 0) return 0;  // uniform over the tile: most boxes skip here
+  const bool lo = xd == 0 && ((B.wall >> (2 * d)) & 1);
+  const bool hi = !lo && xd == B.n[d] && ((B.wall >> (2 * d + 1)) & 1);
+  if (!lo && !hi) return 0;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S l = L[m], r = R[m];
+    L[m] = lo ? ((m == 1 + d) ? -r : r) : l;
+    R[m] = hi ? ((m == 1 + d) ? -l : l) : r;
+  }
+  return lo ? 1 : (hi ? 2 : 0);
+}
+
+// Reverse of wall_states: the replaced state's adjoint goes to the state it
+// mirrors; the replaced state itself receives none.
+template <int d, class S>
+__device__ __forceinline__ void wall_states_vjp(int side, S Lb[5], S Rb[5]) {
+  if (side == 0) return;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S lb = Lb[m], rb = Rb[m];
+    const S ml = (m == 1 + d) ? -lb : lb, mr = (m == 1 + d) ? -rb : rb;
+    Lb[m] = side == 1 ? S(0) : (side == 2 ? lb + mr : lb);
+    Rb[m] = side == 2 ? S(0) : (side == 1 ? rb + ml : rb);
+  }
+}
+
 __host__ __device__ constexpr int pair_index(int d, int t) { return 2 * d + (t > d ? t - 1 : t); }
 
 }  // namespace ppm

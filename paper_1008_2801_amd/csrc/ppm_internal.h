@@ -17,7 +17,7 @@ constexpr int NXCD = 8;      // MI355X: 8 accelerator complex dies, 32 CUs each
 // Per-box metadata on the device.
 struct DevBox {
   int n[3];           // valid extents
-  int pad;
+  int wall;           // faces on a reflecting domain boundary: bit 2d low, bit 2d+1 high
   long long soff;     // element offset of the box in the state arena
   long long poff;     // offset in each plane of the primitive arena (stored grid, (n+8)^3)
   long long eoff;     // offset in each plane of the traced-grid arenas ((n+2)^3)

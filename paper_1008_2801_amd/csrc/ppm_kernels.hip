@@ -203,6 +203,7 @@ __device__ __forceinline__ void riemann1_body(const Tile* __restrict__ tiles, in
     R[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
   }
   int fl = 0;
+  wall_states<d>(B, z.x[d], L, R);
   riemann<d>(L, R, G, F, fl);
   S* f = work + B.eoff + z.e;
 #pragma unroll
@@ -231,7 +232,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_riemann1(const Tile* __restrict__ 
 template <int d, int t, class S>
 __device__ __forceinline__ void riemann2_pair(const S* __restrict__ w, S* __restrict__ o, long long LE,
                                               long long sd, long long stt, const S qeL[5], const S qeR[5],
-                                              const Gas<S>& G, S c3, int& fl) {
+                                              const Gas<S>& G, S c3, const DevBox& B, int xd, int& fl) {
   constexpr int pr = pair_index(d, t);
   S ueL[5], ueR[5], L[5], R[5];
   prim_to_cons(qeL, G, ueL);
@@ -245,6 +246,7 @@ __device__ __forceinline__ void riemann2_pair(const S* __restrict__ w, S* __rest
   }
   cons_to_prim_floor(ueL, G, L, fl);
   cons_to_prim_floor(ueR, G, R, fl);
+  wall_states<d>(B, xd, L, R);
   S F[5];
   riemann<d>(L, R, G, F, fl);
 #pragma unroll
@@ -277,8 +279,8 @@ __device__ __forceinline__ void riemann2_body(const Tile* __restrict__ tiles, in
     qeR[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
   }
   int fl = 0;
-  if (va) riemann2_pair<d, t1>(w, o, LE, sd, stride(z.E, t1), qeL, qeR, G, SC<S>::dt3h(sc)[t1], fl);
-  if (vb) riemann2_pair<d, t2>(w, o, LE, sd, stride(z.E, t2), qeL, qeR, G, SC<S>::dt3h(sc)[t2], fl);
+  if (va) riemann2_pair<d, t1>(w, o, LE, sd, stride(z.E, t1), qeL, qeR, G, SC<S>::dt3h(sc)[t1], B, z.x[d], fl);
+  if (vb) riemann2_pair<d, t2>(w, o, LE, sd, stride(z.E, t2), qeL, qeR, G, SC<S>::dt3h(sc)[t2], B, z.x[d], fl);
   raise_flags(flags, fl);
 }
 
@@ -331,6 +333,7 @@ __device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, in
     }
     cons_to_prim_floor(ue, G, side == 0 ? L : R, fl);
   }
+  wall_states<d>(B, z.x[d], L, R);
   S F[5];
   riemann<d>(L, R, G, F, fl);
   S* o = work + B.eoff + z.e;

@@ -47,7 +47,7 @@ def oracle_jvp(wl, v, dt, **pk):
     O.fill(lay.boxes(), lay.domain(), lay.bc, V)
     out = np.zeros(lay.arena_len())
     for b in range(lay.nbox):
-        _, dU, _ = O.step_jvp(U[b], V[b], dt, wl.dx, p)
+        _, dU, _ = O.step_jvp(U[b], V[b], dt, wl.dx, p, walls=O.box_walls(lay.boxes(), lay.domain(), lay.bc, b))
         lay.view(out, b)[:] = dU
     return out
 

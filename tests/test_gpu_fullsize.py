@@ -120,3 +120,53 @@ def test_rayleigh_taylor_reduced_instance_matches_oracle_fp32_mode():
     assert ofl == 0
     worst = max(field_errors(interior(lay.view(got, b)), interior(ost[b])).max() for b in range(lay.nbox))
     assert worst <= 1e-12, worst
+
+
+@pytest.fixture(scope="module")
+def cfg5_state():
+    wl = I.cfg5()
+    lay = wl.layout
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    return wl, st
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_rayleigh_taylor_full_level_sampled_windows(cfg5_state, precision):
+    """The 512^3 Rayleigh-Taylor level as timed (512 boxes of 64^3, walls in
+    z, g = (0, 0, -1)), one step in FP32-reconstruction and FP64 mode: the dt,
+    sampled 2^3 windows against the oracle in the same mode (boxes at both
+    walls and inside; windows at box corners and inside), conservation of
+    mass and of the x and y momenta (gravity and the walls act along z)."""
+    wl, st = cfg5_state
+    lay = wl.layout
+    out, dt, flags = _one_step(wl, precision)
+    assert flags == 0
+    p = O.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+    s = max(O.max_wavespeed(u, wl.dx, p)[0] for u in st)
+    assert dt == p.cfl / s
+    rng = np.random.default_rng(50 + precision)
+    zlo = [b for b in range(lay.nbox) if lay.lo[b, 2] == 0]
+    zhi = [b for b in range(lay.nbox) if lay.hi[b, 2] == lay.domain_hi[2]]
+    mid = [b for b in range(lay.nbox) if b not in zlo and b not in zhi]
+    boxes = list(rng.choice(zlo, 3, replace=False)) + list(rng.choice(zhi, 3, replace=False)) + \
+        list(rng.choice(mid, 4, replace=False))
+    for b in boxes:
+        n = lay.n(b)
+        corners = [(0, 0, 0), tuple(n[d] - 2 for d in range(3))]
+        inner = [tuple(int(rng.integers(1, n[d] - 2)) for d in range(3))]
+        for lo in corners + inner:
+            hi = tuple(v + 1 for v in lo)
+            ref, _, _ = O.step(st[b], dt, wl.dx, p, window=(lo, hi),
+                               walls=O.box_walls(lay.boxes(), lay.domain(), lay.bc, b))
+            sl = (slice(None),) + tuple(slice(lo[d] + 4, hi[d] + 5) for d in (2, 1, 0))
+            got = lay.view(out, b)
+            err = np.abs(got[sl] - ref[sl]).max() / np.abs(ref[sl]).max()
+            assert err <= 1e-12, (int(b), lo, err)
+    # pairwise sums per box, exact sum over boxes (rounding ~1e-15 of the
+    # scale: the total mass times the sound speed, about 1)
+    mass = math.fsum(float(np.sum(interior(lay.view(wl.arena, b))[0])) for b in range(lay.nbox))
+    for c in range(3):
+        s0 = math.fsum(float(np.sum(interior(lay.view(wl.arena, b))[c])) for b in range(lay.nbox))
+        s1 = math.fsum(float(np.sum(interior(lay.view(out, b))[c])) for b in range(lay.nbox))
+        assert abs(s1 - s0) <= 1e-13 * mass, (c, s1 - s0, mass)
