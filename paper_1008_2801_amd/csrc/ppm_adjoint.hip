@@ -169,12 +169,11 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   r3_state<d>(w, LE, 0, 1, s1, s2, c1, c2, G, qeR, ueR);
   cons_to_prim_dec(ueL, G, L, rfL, pfL);
   cons_to_prim_dec(ueR, G, R, rfR, pfR);
-  S Lw[5], Rw[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) { Lw[m] = L[m]; Rw[m] = R[m]; }
-  const int ws = wall_states<d>(B, z.x[d], Lw, Rw);
+  // a state replaced by a wall mirror gets no adjoint below, so L and R can
+  // be overwritten in place
+  const int ws = wall_states<d>(B, z.x[d], L, R);
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
-  riemann_vjp<d>(Lw, Rw, G, Fb, Lb, Rb);
+  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
   wall_states_vjp<d>(ws, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
   cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
@@ -192,16 +191,33 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
 }
 
 template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_adj_r3(const Tile* __restrict__ tiles, int ntiles,
-                                                 const DevBox* __restrict__ boxes, const S* __restrict__ work,
-                                                 long long LE, S* __restrict__ aw, Gas<S> G,
-                                                 const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
-                                                 int grav, double g0, double g1, double g2) {
+__device__ __forceinline__ void adj_r3_axes(const Tile* __restrict__ tiles, int ntiles,
+                                            const DevBox* __restrict__ boxes, const S* __restrict__ work,
+                                            long long LE, S* __restrict__ aw, const Gas<S> G,
+                                            const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
+                                            int grav, double g0, double g1, double g2) {
   switch (blockIdx.y) {
     case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
     case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
     default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
   }
+}
+
+// FP64: asking for 3 waves per SIMD (a few spilled values) beats the 2 the
+// compiler's own register choice allows; FP32 already fits 5.
+__global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3)))
+k_adj_r3_f64(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+             const double* __restrict__ work, long long LE, double* __restrict__ aw, Gas<double> G,
+             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, int grav, double g0, double g1,
+             double g2) {
+  adj_r3_axes<double>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2);
+}
+__global__ void __launch_bounds__(MAX_TILE)
+k_adj_r3_f32(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+             const float* __restrict__ work, long long LE, float* __restrict__ aw, Gas<float> G,
+             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, int grav, double g0, double g1,
+             double g2) {
+  adj_r3_axes<float>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2);
 }
 
 // Stage-2 pair (d, t) of the face at the lane's slot: F2^{d|t} adjoint from
@@ -236,12 +252,9 @@ __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restri
   }
   cons_to_prim_dec(ueL, G, L, rfL, pfL);
   cons_to_prim_dec(ueR, G, R, rfR, pfR);
-  S Lw[5], Rw[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) { Lw[m] = L[m]; Rw[m] = R[m]; }
-  const int ws = wall_states<d>(B, xd, Lw, Rw);
+  const int ws = wall_states<d>(B, xd, L, R);  // a replaced state gets no adjoint
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
-  riemann_vjp<d>(Lw, Rw, G, Fb, Lb, Rb);
+  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
   wall_states_vjp<d>(ws, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
   cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
@@ -695,8 +708,12 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, cons
   // every workspace entry is written before it is read: each reverse stage
   // writes all entries it owns, zeros included
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
-  hipLaunchKernelGGL(k_adj_r3<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts, Ubn,
-                     grav, g[0], g[1], g[2]);
+  if constexpr (sizeof(S) == sizeof(double))
+    hipLaunchKernelGGL(k_adj_r3_f64, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
+                       Ubn, grav, g[0], g[1], g[2]);
+  else
+    hipLaunchKernelGGL(k_adj_r3_f32, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
+                       Ubn, grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<0, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,

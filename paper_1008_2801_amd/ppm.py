@@ -232,7 +232,7 @@ class Level:
     def ensure_workspace(self, precision=0):
         import torch
         need = self.workspace_bytes(precision)
-        if self._work is None or self._work.numel() < need:
+        if self._work is None or self._work.numel() < need + 256:  # room for the 256-byte alignment
             self._work = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
         base = self._work.data_ptr()
         aligned = (base + 255) // 256 * 256
