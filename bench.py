@@ -39,6 +39,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
+# Tilings picked by the autotuner on this device, keyed by architecture,
+# precision and box-size histogram (see ppm_autotune); a level whose key is
+# present is set up without timing, so the timed configuration is stable.
+AUTOTUNE_CACHE = os.path.join(ROOT, "paper_1008_2801_amd", "autotune_cache.jsonl")
+
 # Sources whose change invalidates recorded counter traffic (kernels, their
 # arithmetic and the tile lists that shape the launches).
 TRAFFIC_SOURCES = ("paper_1008_2801_amd/csrc/ppm_kernels.hip", "paper_1008_2801_amd/csrc/ppm_math.h",
@@ -134,7 +139,7 @@ def level_rates(wl, steps, warmup, precision, per_box=True):
     zones = lay.valid_zones()
     Uf = U0.clone()
     lev.fill_boundary(Uf)
-    tile, strip, _ = lev.autotune(Uf, wl.dx, p, reps=2)
+    tile, strip, _ = lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)
     del Uf
     out = {"tiling": {"tile": tile, "strip_rows": strip}}
     forms = (("batched", P.BATCHED), ("per_box", P.PER_BOX)) if per_box else (("batched", P.BATCHED),)
@@ -278,6 +283,8 @@ def main():
     ap.add_argument("--cpu-window", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiling")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="autotuner cache file (default: the package's autotune_cache.jsonl)")
     ap.add_argument("--tiling", default=None, help="'tile,strip_rows': use this tiling instead of autotuning")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 512-box batched / per-box / graph measurements")
@@ -297,6 +304,9 @@ def main():
               "(the multi-GPU box distribution is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
+    if args.autotune_cache:
+        global AUTOTUNE_CACHE
+        AUTOTUNE_CACHE = args.autotune_cache
     if args.record_traffic:
         ff, wf = (float(v) for v in args.counter_factors.split(","))
         t_, s_ = (int(v) for v in args.tiling.split(","))
@@ -342,7 +352,7 @@ def main():
     elif not args.no_autotune:
         Uf = U.clone()
         lev.fill_boundary(Uf)
-        tiling = lev.autotune(Uf, wl.dx, p, reps=2)[:2]
+        tiling = lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)[:2]
         del Uf
     else:
         tiling = lev.get_tiling()
