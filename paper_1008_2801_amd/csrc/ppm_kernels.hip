@@ -211,8 +211,11 @@ __device__ __forceinline__ void riemann1_body(const Tile* __restrict__ tiles, in
   raise_flags(flags, fl);
 }
 
+// Occupancy requests (measured): riemann1 at 8 waves per SIMD and riemann2
+// at 5 fit without spills and run 2-3% faster than the compiler's own
+// register choice; riemann3 at 7 and trace at 6 are slower.
 template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(8))) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    int* flags) {
@@ -285,7 +288,7 @@ __device__ __forceinline__ void riemann2_body(const Tile* __restrict__ tiles, in
 }
 
 template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_riemann2(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(5))) k_riemann2(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    const StepConsts* __restrict__ sc, int* flags) {
