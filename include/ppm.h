@@ -3,10 +3,10 @@
  *
  * The library advances the 3-D gamma-law Euler equations by one explicit
  * unsplit Godunov step on the rectangular boxes (FABs) of one refinement
- * level: the "fully explicit advance of a hyperbolic system of conservation
- * laws" of the paper's compressible code (Sec. 1), on its MultiFAB / FAB data
- * model with ghost cells filled from intersecting grids, the intersections
- * found by a hash sort of the boxes and cached (Sec. 2).
+ * level: the compressible code's explicit update of a system of hyperbolic
+ * conservation laws (paper Sec. 1), on its MultiFAB / FAB data model with
+ * ghost cells filled from intersecting grids, the intersections found by a
+ * hash sort of the boxes and cached (Sec. 2).
  *
  * The discretisation (PPM with the Colella-Woodward limiter and flattening,
  * characteristic tracing, a two-shock Riemann solver with a fixed Newton
@@ -89,8 +89,9 @@ typedef struct ppm_ctx ppm_ctx;
 typedef struct ppm_graph ppm_graph;
 
 /* Context for one level layout (paper Sec. 2: replicated box metadata).
- * Validates the layout (disjoint boxes tiling the domain, ngrow == 4, box
- * and domain extents >= 4 along reflecting/outflow axes), builds or reuses
+ * Validates the layout (disjoint non-empty boxes tiling the domain,
+ * ngrow == 4, domain extents >= 4, periodic axes periodic on both faces;
+ * boxes may be thinner than the ghost width), builds or reuses
  * the ghost-fill plan (hash-sorted intersections, cached across contexts)
  * and the tile lists, and uploads them.  Allocates device memory for them.
  * Returns PPM_EINVAL for an invalid layout, PPM_EHIP on allocation failure. */
@@ -132,8 +133,13 @@ int ppm_compute_dt(ppm_ctx* ctx, const double* U, const double dx[3], const ppm_
  * Unew untouched).  dt: the time step, or, if dt_dev is non-null, read on
  * the device from dt_dev[0] (dt is then ignored).  flux: null, or three
  * flux-arena pointers (any may be null) that receive F^{n+1/2}.  U and Unew
- * must not overlap.  Needs a workspace (ppm_set_workspace).  Raises
- * PPM_FLAG_* on the device (ppm_check_status). */
+ * must not overlap.  On a face in the plane of a reflecting domain
+ * boundary every Riemann problem takes the mirror image of the state inside
+ * the wall as the outside state (normal velocity negated): no mass or
+ * energy crosses a wall.  Needs a workspace (ppm_set_workspace).  Raises
+ * PPM_FLAG_* on the device (ppm_check_status).  PPM_EINVAL for null or
+ * overlapping state pointers, invalid parameters, a non-positive dt
+ * without dt_dev, or a missing/small workspace. */
 int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
                    const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
                    void* stream);
