@@ -75,6 +75,12 @@ def lib():
         L.oracle_step_count.argtypes = [_dp, _ip, _ip, _ip, ctypes.c_double, _dp,
                                         ctypes.POINTER(OParams), _ip, _dp,
                                         ctypes.POINTER(ctypes.c_ulonglong)]
+        L.oracle_step_species.restype = ctypes.c_int
+        L.oracle_step_species.argtypes = [_dp, _dp, ctypes.c_int, _ip, _ip, _ip, ctypes.c_double, _dp,
+                                          ctypes.POINTER(OParams), _ip, _dp, _dp]
+        L.oracle_fill_scalars.restype = ctypes.c_int
+        L.oracle_fill_scalars.argtypes = [ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _dp,
+                                          ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
         L.oracle_step_jvp.restype = ctypes.c_int
         L.oracle_step_jvp.argtypes = [_dp, _dp, _ip, _ip, _ip, ctypes.c_double, _dp,
                                       ctypes.POINTER(OParams), _ip, _dp, _dp]
@@ -158,6 +164,22 @@ def step(U, dt, dx, p, window=None, fluxes=False, out=None, walls=None):
     if fl < 0:
         raise ValueError("oracle_step: invalid arguments")
     return Unew, F, fl
+
+
+def step_species(U, RX, dt, dx, p, window=None, walls=None):
+    """One step of one box with passive species (ghosts of U and RX filled).
+    RX: (ns, nz+8, ny+8, nx+8) partial densities rho X_s.  Returns
+    (Unew, RXnew, flags); only the window's valid zones are written."""
+    n = _box_n(U)
+    assert RX.dtype == np.float64 and RX.flags.c_contiguous and RX.shape[1:] == U.shape[1:]
+    wlo, whi = ((0, 0, 0), tuple(x - 1 for x in n)) if window is None else window
+    Unew = U.copy()
+    RXnew = RX.copy()
+    fl = lib().oracle_step_species(_d(U), _d(RX), int(RX.shape[0]), _i3(n), _i3(wlo), _i3(whi), float(dt),
+                                   _d3(dx), ctypes.byref(p), _walls(walls), _d(Unew), _d(RXnew))
+    if fl < 0:
+        raise ValueError("oracle_step_species: invalid arguments")
+    return Unew, RXnew, fl
 
 
 def step_count(U, dt, dx, p, window=None, walls=None):
@@ -248,6 +270,54 @@ def fill(boxes, domain, bc, states):
     for s, o, z in zip(states, off, sizes):
         s.ravel()[:] = arena[o:o + z]
     return states
+
+
+def fill_scalars(boxes, domain, bc, states):
+    """Ghost fill of per-box scalar arrays (ncomp, nz+8, ny+8, nx+8) (passive
+    species): like fill, with no sign change at reflecting walls."""
+    nb = len(boxes)
+    ncomp = int(states[0].shape[0])
+    lo = (ctypes.c_int * (3 * nb))(*[int(v) for b in boxes for v in b[0]])
+    hi = (ctypes.c_int * (3 * nb))(*[int(v) for b in boxes for v in b[1]])
+    sizes = [s.size for s in states]
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    arena = np.concatenate([s.ravel() for s in states])
+    rc = lib().oracle_fill_scalars(nb, lo, hi, _i3(domain[0]), _i3(domain[1]), (ctypes.c_int * 6)(*bc),
+                                   _d(arena), off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), ncomp)
+    if rc != 0:
+        raise ValueError("oracle_fill_scalars: ghost image without an owning box")
+    for s, o, z in zip(states, off, sizes):
+        s.ravel()[:] = arena[o:o + z]
+    return states
+
+
+def advance_species(boxes, domain, bc, states, rx, nsteps, dx, p, dt=None):
+    """advance with passive species: rx is a list of per-box (ns, ...) arrays
+    of partial densities.  Returns (states, rx, dts, flags)."""
+    states = [s.copy() for s in states]
+    rx = [r.copy() for r in rx]
+    dts, flags = [], 0
+    for _ in range(nsteps):
+        fill(boxes, domain, bc, states)
+        fill_scalars(boxes, domain, bc, rx)
+        if dt is None:
+            s = 0.0
+            for U in states:
+                sb, fl = max_wavespeed(U, dx, p)
+                flags |= fl
+                s = max(s, sb)
+            dtn = p.cfl / s
+        else:
+            dtn = dt
+        dts.append(dtn)
+        new, newx = [], []
+        for b, (U, R) in enumerate(zip(states, rx)):
+            Un, Rn, fl = step_species(U, R, dtn, dx, p, walls=box_walls(boxes, domain, bc, b))
+            flags |= fl
+            new.append(Un)
+            newx.append(Rn)
+        states, rx = new, newx
+    return states, rx, dts, flags
 
 
 def advance(boxes, domain, bc, states, nsteps, dx, p, dt=None, fluxes=False):

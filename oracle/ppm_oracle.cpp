@@ -21,6 +21,13 @@
  *       6 single-transverse corrections (dt/3h), 3 double corrections (dt/2h)
  *   O10 conservative flux-divergence update (+ Heun constant-gravity source)
  *   O11 CFL time step from the per-axis maximum signal speed
+ *   S1-S3 passive species (optional): each mass fraction X = (rho X)/rho is
+ *       reconstructed like a primitive variable, traced across the entropy
+ *       wave only (as a transverse velocity), carried through the three
+ *       stages by the stage's mass flux from the side the mass comes from,
+ *       corrected transversely like the density, and rho X updated
+ *       conservatively in FP64.  The paper does not describe species; this
+ *       is the usual passive-scalar extension of the same advance.
  * Every formula is written as a C expression; the order of evaluation is the
  * one C defines (left to right, no contraction, IEEE division and sqrt), and
  * that order is part of the definition.
@@ -527,6 +534,21 @@ struct Step {
   int flags = 0;
   // faces of the box on a reflecting domain boundary: wall[2d] low, [2d+1] high
   int wall[6] = {0, 0, 0, 0, 0, 0};
+  // passive species: ns partial densities rho X_s, layout [s][k][j][i] over
+  // the stored grid like U; null / 0: none
+  const A* RX = nullptr;
+  int ns = 0;
+  A* RXnew = nullptr;
+
+  const A& rx_at(int s, const int x[3]) const {
+    return RX[(((size_t)s * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)];
+  }
+
+  // S2: passive scalar carried by a face's mass flux: it takes the mass
+  // fraction of the side the mass comes from (a zero flux carries nothing,
+  // whichever side is taken; on a wall face the mirror states make the mass
+  // flux exactly zero, so no species crosses a wall).
+  static S carried(S frho, S xl, S xr) { return (V(frho) > 0) ? frho * xl : frho * xr; }
 
   // Riemann problem on a reflecting wall (R14): the state outside the wall
   // is the mirror image of the state inside it (normal velocity negated), so
@@ -730,6 +752,142 @@ struct Step {
       }
     }
 
+    // S1-S3, passive species (ns > 0): the same CTU sequence for each mass
+    // fraction X = rho X / rho, carried by the mass fluxes of the three
+    // stages.
+    if (ns > 0) {
+      // mass fractions on the primitive zones
+      std::vector<Grid<S>> xq(ns);
+      for (int sp = 0; sp < ns; ++sp) {
+        xq[sp].init(plo, phi_);
+        for_region(plo, phi_, [&](const int x[3]) { xq[sp].at(x) = to_s<S, A>(rx_at(sp, x)) / q[0].at(x); });
+      }
+      // traced mass fractions: PPM parabola (same limiter and flattening),
+      // reference state of the fastest wave toward the face, corrected by
+      // the entropy wave when it moves toward the face (as the transverse
+      // velocities)
+      std::vector<Grid<S>> xp(3 * ns), xm(3 * ns);
+      for (int i = 0; i < 3 * ns; ++i) { xp[i].init(glo, ghi); xm[i].init(glo, ghi); }
+      for_region(glo, ghi, [&](const int x[3]) {
+        const S c = q[5].at(x);
+        for (int d = 0; d < 3; ++d) {
+          const S un = q[1 + d].at(x);
+          const S lam[3] = {un - c, un, un + c};
+          const S zero(0.0);
+          S sgp[3], sgm[3];
+          for (int k = 0; k < 3; ++k) {
+            sgp[k] = smax(lam[k], zero) * K.dtdx[d];
+            sgm[k] = smax(-lam[k], zero) * K.dtdx[d];
+          }
+          for (int sp = 0; sp < ns; ++sp) {
+            S st[5], aL, aR, a6;
+            for (int o = -2; o <= 2; ++o) {
+              int y[3] = {x[0], x[1], x[2]};
+              y[d] += o;
+              st[o + 2] = xq[sp].at(y);
+            }
+            ppm_parabola(st, flat.at(x), K, aL, aR, a6);
+            const S da = aR - aL;
+            {
+              const S ref = ppm_ip(aR, da, a6, sgp[2], K);
+              const S at = (V(lam[1]) > 0) ? ref - ppm_ip(aR, da, a6, sgp[1], K) : zero;
+              xp[d * ns + sp].at(x) = ref - at;
+            }
+            {
+              const S ref = ppm_im(aL, da, a6, sgm[0], K);
+              const S at = (V(lam[1]) < 0) ? ref - ppm_im(aL, da, a6, sgm[1], K) : zero;
+              xm[d * ns + sp].at(x) = ref - at;
+            }
+          }
+        }
+      });
+      // S2, stage 1: species fluxes of the normal predictor
+      std::vector<Grid<S>> g1(3 * ns);
+      for (int d = 0; d < 3; ++d) {
+        int lo[3] = {glo[0], glo[1], glo[2]}, hi[3] = {ghi[0], ghi[1], ghi[2]};
+        lo[d] = wlo[d]; hi[d] = whi[d] + 1;
+        for (int sp = 0; sp < ns; ++sp) {
+          g1[d * ns + sp].init(glo, ghi);
+          for_region(lo, hi, [&](const int x[3]) {
+            int y[3];
+            shifted(x, d, -1, y);
+            const S xl = xp[d * ns + sp].at(y), xr = xm[d * ns + sp].at(x);
+            g1[d * ns + sp].at(x) = carried(f1[d][0].at(x), xl, xr);
+          });
+        }
+      }
+      // S2, stage 2: pair (d, t); corrected X = (rho X)/rho of the corrected
+      // conserved pair, the density floored as in O8
+      std::vector<Grid<S>> g2(9 * ns);
+      for (int d = 0; d < 3; ++d)
+        for (int t = 0; t < 3; ++t) {
+          if (t == d) continue;
+          const int r = 3 - d - t;
+          int lo[3], hi[3];
+          lo[d] = wlo[d]; hi[d] = whi[d] + 1;
+          lo[t] = wlo[t]; hi[t] = whi[t];
+          lo[r] = glo[r]; hi[r] = ghi[r];
+          for (int sp = 0; sp < ns; ++sp) {
+            Grid<S>& G2 = g2[(d * 3 + t) * ns + sp];
+            G2.init(glo, ghi);
+            auto corrected = [&](Grid<S>& rt, Grid<S>& xt, const int z[3]) {
+              int zp[3];
+              shifted(z, t, 1, zp);
+              const S rho = smax(rt.at(z) - K.dt3h[t] * (f1[t][0].at(zp) - f1[t][0].at(z)), K.small_dens);
+              const S rx = rt.at(z) * xt.at(z) - K.dt3h[t] * (g1[t * ns + sp].at(zp) - g1[t * ns + sp].at(z));
+              return rx / rho;
+            };
+            for_region(lo, hi, [&](const int x[3]) {
+              int y[3];
+              shifted(x, d, -1, y);
+              const S xl = corrected(tp[d][0], xp[d * ns + sp], y), xr = corrected(tm[d][0], xm[d * ns + sp], x);
+                G2.at(x) = carried(f2[d][t][0].at(x), xl, xr);
+            });
+          }
+        }
+      // S2, stage 3, and S3: the update of rho X (FP64, x + y + z in that order)
+      std::vector<Grid<S>> g3(3 * ns);
+      for (int d = 0; d < 3; ++d) {
+        const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+        int lo[3] = {wlo[0], wlo[1], wlo[2]}, hi[3] = {whi[0], whi[1], whi[2]};
+        hi[d] = whi[d] + 1;
+        for (int sp = 0; sp < ns; ++sp) {
+          g3[d * ns + sp].init(glo, ghi);
+          auto corrected = [&](Grid<S>& rt, Grid<S>& xt, const int z[3]) {
+            int z1[3], z2[3];
+            shifted(z, t1, 1, z1);
+            shifted(z, t2, 1, z2);
+            const S rho = smax(rt.at(z) - K.dt2h[t1] * (f2[t1][t2][0].at(z1) - f2[t1][t2][0].at(z))
+                                        - K.dt2h[t2] * (f2[t2][t1][0].at(z2) - f2[t2][t1][0].at(z)),
+                               K.small_dens);
+            Grid<S>& a = g2[(t1 * 3 + t2) * ns + sp];
+            Grid<S>& b = g2[(t2 * 3 + t1) * ns + sp];
+            const S rx = rt.at(z) * xt.at(z) - K.dt2h[t1] * (a.at(z1) - a.at(z)) - K.dt2h[t2] * (b.at(z2) - b.at(z));
+            return rx / rho;
+          };
+          for_region(lo, hi, [&](const int x[3]) {
+            int y[3];
+            shifted(x, d, -1, y);
+            const S xl = corrected(tp[d][0], xp[d * ns + sp], y), xr = corrected(tm[d][0], xm[d * ns + sp], x);
+            g3[d * ns + sp].at(x) = carried(f3[d][0].at(x), xl, xr);
+          });
+        }
+      }
+      const A dtdxs[3] = {A(dt / h[0]), A(dt / h[1]), A(dt / h[2])};
+      for (int sp = 0; sp < ns; ++sp)
+        for_region(wlo, whi, [&](const int x[3]) {
+          int xp1[3], yp1[3], zp1[3];
+          shifted(x, 0, 1, xp1);
+          shifted(x, 1, 1, yp1);
+          shifted(x, 2, 1, zp1);
+          const A fx = to_a<A, S>(g3[0 * ns + sp].at(xp1)) - to_a<A, S>(g3[0 * ns + sp].at(x));
+          const A fy = to_a<A, S>(g3[1 * ns + sp].at(yp1)) - to_a<A, S>(g3[1 * ns + sp].at(x));
+          const A fz = to_a<A, S>(g3[2 * ns + sp].at(zp1)) - to_a<A, S>(g3[2 * ns + sp].at(x));
+          RXnew[(((size_t)sp * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)] =
+              rx_at(sp, x) - ((dtdxs[0] * fx + dtdxs[1] * fy) + dtdxs[2] * fz);
+        });
+    }
+
     // O10: conservative update, FP64, x + y + z in that order; then the
     // Heun constant-gravity source S(U) = (0, rho g, (rho u).g).
     stage(ST_UPDATE);
@@ -773,9 +931,13 @@ struct Step {
 
 template <class S, class A>
 int run_step(const A* U, const int n[3], const int wlo[3], const int whi[3], double dt,
-             const double h[3], const OParams* P, const int* walls, A* Unew, A* F[3], bool counting) {
+             const double h[3], const OParams* P, const int* walls, A* Unew, A* F[3], bool counting,
+             const A* RX = nullptr, int ns = 0, A* RXnew = nullptr) {
   Step<S, A> st;
   st.U = U;
+  st.RX = RX;
+  st.ns = ns;
+  st.RXnew = RXnew;
   if (walls)
     for (int f = 0; f < 6; ++f) st.wall[f] = walls[f] != 0;
   for (int d = 0; d < 3; ++d) { st.n[d] = n[d]; st.N[d] = n[d] + 2 * NG; st.h[d] = h[d]; }
@@ -809,6 +971,21 @@ int oracle_step(const double* U, const int n[3], const int wlo[3], const int whi
   if (P->precision == 1)
     return run_step<float, double>(U, n, wlo, whi, dt, h, P, walls, Unew, F, false);
   return run_step<double, double>(U, n, wlo, whi, dt, h, P, walls, Unew, F, false);
+}
+
+// The step with ns passive species: RX holds the partial densities rho X_s
+// of the box (layout [s][k][j][i] over the stored grid, ghosts filled like
+// U); RXnew receives the window's new values (other entries untouched).
+// Returns the status flags or -1.
+int oracle_step_species(const double* U, const double* RX, int ns, const int n[3], const int wlo[3],
+                        const int whi[3], double dt, const double h[3], const OParams* P, const int* walls,
+                        double* Unew, double* RXnew) {
+  if (!U || !Unew || !P || !RX || !RXnew || ns < 1 || !window_ok(n, wlo, whi) || !(dt > 0) ||
+      !(P->gamma > 1.0))
+    return -1;
+  if (P->precision == 1)
+    return run_step<float, double>(U, n, wlo, whi, dt, h, P, walls, Unew, nullptr, false, RX, ns, RXnew);
+  return run_step<double, double>(U, n, wlo, whi, dt, h, P, walls, Unew, nullptr, false, RX, ns, RXnew);
 }
 
 // Same step with the Counted scalar; counts[stage][kind] receives the number
@@ -927,8 +1104,24 @@ int oracle_trace(const double aL[5], const double aR[5], const double a6[5], con
 // its image: periodic axes wrap, outflow axes clamp to the nearest valid
 // zone, reflecting axes mirror about the wall with the normal momentum
 // negated.  Returns 0, or -1 if an image has no owner.
+static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
+                      const int bc[6], double* arena, const long long* off, int ncomp, bool momentum);
+
 int oracle_fill(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
                 const int bc[6], double* arena, const long long* off) {
+  return fill_level(nbox, lo, hi, dlo, dhi, bc, arena, off, 5, true);
+}
+
+// The same fill for ncomp scalar fields per box (passive species): no
+// component changes sign at a reflecting wall.
+int oracle_fill_scalars(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
+                        const int bc[6], double* arena, const long long* off, int ncomp) {
+  if (ncomp < 1) return -1;
+  return fill_level(nbox, lo, hi, dlo, dhi, bc, arena, off, ncomp, false);
+}
+
+static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
+                      const int bc[6], double* arena, const long long* off, int ncomp, bool momentum) {
   int L[3];
   for (int d = 0; d < 3; ++d) L[d] = dhi[d] - dlo[d] + 1;
   // owner of every valid zone of the domain, painted box by box
@@ -949,7 +1142,7 @@ int oracle_fill(int nbox, const int* lo, const int* hi, const int dlo[3], const 
     for_region(gl, gh, [&](const int x[3]) {
       if (x[0] >= 0 && x[0] < n[0] && x[1] >= 0 && x[1] < n[1] && x[2] >= 0 && x[2] < n[2]) return;
       int g[3];
-      double sgn[5] = {1, 1, 1, 1, 1};
+      double sgn[3] = {1, 1, 1};  // momentum components 1..3
       for (int d = 0; d < 3; ++d) {
         int v = lo[3 * b + d] + x[d] - dlo[d];  // domain-relative index
         if (v < 0 || v >= L[d]) {
@@ -960,7 +1153,7 @@ int oracle_fill(int nbox, const int* lo, const int* hi, const int dlo[3], const 
             v = (v < 0) ? 0 : L[d] - 1;
           } else {
             v = (v < 0) ? (-1 - v) : (2 * L[d] - 1 - v);
-            sgn[1 + d] = -sgn[1 + d];
+            sgn[d] = -sgn[d];
           }
         }
         g[d] = v;
@@ -974,9 +1167,10 @@ int oracle_fill(int nbox, const int* lo, const int* hi, const int dlo[3], const 
         ol[d] = g[d] + dlo[d] - lo[3 * ob + d];
       }
       const double* src = arena + off[ob];
-      for (int c = 0; c < 5; ++c) {
+      for (int c = 0; c < ncomp; ++c) {
         const double v = src[(((size_t)c * ON[2] + (ol[2] + NG)) * ON[1] + (ol[1] + NG)) * ON[0] + (ol[0] + NG)];
-        dst[(((size_t)c * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)] = sgn[c] * v;
+        const double sg = (momentum && c >= 1 && c <= 3) ? sgn[c - 1] : 1.0;
+        dst[(((size_t)c * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)] = sg * v;
       }
     });
     if (bad) return -1;

@@ -307,3 +307,66 @@ def shock_tube(n, axis=0, ntrans=4, gamma=1.4, left=(1.0, 0.0, 1.0), right=(0.12
         vel[axis] = un
         return (rho, vel[0], vel[1], vel[2], p)
     return Workload("shock_tube", lay, _fill_state(lay, h, gamma, prim), h, gamma, 1)
+
+
+# ------------------------------------------------------- passive species ----
+# A species arena holds the partial densities rho X_s of ns passive species
+# for a whole level, box by box: box b holds ns planes over its stored
+# extents, order [s][k][j][i], ghosts NaN until filled.
+def species_offsets(layout, ns):
+    """off[0..nbox]: element offsets of each box in a species arena of ns
+    components; off[nbox] is the arena length."""
+    sz = [ns * int(np.prod(layout.stored_shape(b)[1:])) for b in range(layout.nbox)]
+    return np.concatenate([[0], np.cumsum(sz)]).astype(np.int64)
+
+
+def species_view(layout, arena, ns, b):
+    o = species_offsets(layout, ns)
+    return arena[o[b]:o[b + 1]].reshape((ns,) + layout.stored_shape(b)[1:])
+
+
+def species(wl, ns, seed=11, kind="modes", amp=0.9, nmodes=4, K=3):
+    """Partial densities of ns species for workload wl (its state gives rho).
+
+    kind "modes": mass fractions X_s = w_s / sum_r w_r with
+      w_s = 1 + amp S_s(x) (independent mode sums over the domain), so each
+      lies in (0, 1) and they sum to one.
+    kind "density": two species marking the heavy and the light fluid,
+      X_0 = (rho - min rho) / (max rho - min rho), X_1 = 1 - X_0 (the
+      Rayleigh-Taylor interface tracer).
+    kind "const": X_s = (s + 1) / (ns + 1) for ns > 1, X = 1 for ns = 1.
+    Returns the arena (ghosts NaN)."""
+    lay = wl.layout
+    g = lay.ngrow
+    arena = np.full(int(species_offsets(lay, ns)[-1]), np.nan)
+    rng = np.random.default_rng(seed)
+    Ld = [(lay.domain_hi[d] - lay.domain_lo[d] + 1) * wl.dx[d] for d in range(3)]
+    S = [ModeSum(rng, nmodes, K, Ld) for _ in range(ns)] if kind == "modes" else None
+    if kind == "density":
+        if ns != 2:
+            raise ValueError("kind 'density' makes two species")
+        rhos = [lay.view(wl.arena, b)[0, g:-g, g:-g, g:-g] for b in range(lay.nbox)]
+        rmin = min(float(r.min()) for r in rhos)
+        rmax = max(float(r.max()) for r in rhos)
+    for b in range(lay.nbox):
+        nx, ny, nz = lay.n(b)
+        lo = lay.lo[b]
+        rho = lay.view(wl.arena, b)[0, g:g + nz, g:g + ny, g:g + nx]
+        if kind == "modes":
+            x = ((lo[0] + np.arange(nx)) + 0.5)[None, None, :] * wl.dx[0]
+            y = ((lo[1] + np.arange(ny)) + 0.5)[None, :, None] * wl.dx[1]
+            z = ((lo[2] + np.arange(nz)) + 0.5)[:, None, None] * wl.dx[2]
+            w = [np.broadcast_to(1.0 + amp * S[s](x, y, z), (nz, ny, nx)) for s in range(ns)]
+            tot = sum(w)
+            X = [ws / tot for ws in w]
+        elif kind == "density":
+            X0 = (rho - rmin) / (rmax - rmin)
+            X = [X0, 1.0 - X0]
+        elif kind == "const":
+            X = [np.full((nz, ny, nx), 1.0 if ns == 1 else (s + 1.0) / (ns + 1.0)) for s in range(ns)]
+        else:
+            raise ValueError(kind)
+        V = species_view(lay, arena, ns, b)
+        for s in range(ns):
+            V[s, g:g + nz, g:g + ny, g:g + nx] = rho * X[s]
+    return arena
