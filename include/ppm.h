@@ -64,6 +64,8 @@ enum { PPM_FLAG_NONPHYS = 1, /* rho <= 0, p <= 0 or a non-finite value in an inp
 enum { PPM_LAUNCH_BATCHED = 0, /* each stage: one launch over the tile list of all boxes */
        PPM_LAUNCH_PER_BOX = 1  /* each stage: one launch per box (the plain baseline) */ };
 
+enum { PPM_MAX_SPECIES = 64 }; /* passive species per species arena */
+
 typedef struct { int32_t lo[3], hi[3]; } ppm_box; /* inclusive valid zones, global index space */
 
 typedef struct {
@@ -164,6 +166,45 @@ size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx, int32_t precision);
 int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
 int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
                            const double* dt_dev, const double dx[3], const ppm_params* params, void* stream);
+
+/* Passive species: mass fractions X_s carried with the flow (partial
+ * densities rho X_s obey the continuity equation with the mass flux times
+ * X_s).  The paper's code advances conserved variables generically (Sec. 1);
+ * species are the usual passive-scalar extension of the same advance, not a
+ * part the paper spells out.
+ *
+ * Species arena: one contiguous float64 buffer of ns components for the
+ * level; box b starts at element soff[b] (ppm_species_offsets) and holds
+ * ns planes rho X_s over the stored extents, order [s][k][j][i], like the
+ * state arena (same ghost width, same zone order).  ns in
+ * [1, PPM_MAX_SPECIES]. */
+int ppm_species_offsets(const ppm_ctx* ctx, int32_t ns, int64_t* off);
+
+/* Device scratch of the species stages (caller-owned, 256-byte aligned):
+ * bytes for ns species in the given precision; 0 for invalid arguments. */
+size_t ppm_species_workspace_bytes(const ppm_ctx* ctx, int32_t ns, int32_t precision);
+int ppm_set_species_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Ghost fill of a species arena: the copies of ppm_fill_boundary (periodic
+ * images, outflow copies, wall mirrors) with no sign change.  In place. */
+int ppm_fill_species(ppm_ctx* ctx, double* RX, int32_t ns, int32_t mode, void* stream);
+
+/* The hydro step (exactly ppm_hydro_step, batched launch form) followed by
+ * the species update of the same step: each X = (rho X)/rho gets the
+ * step's PPM parabola (same limiter and flattening), is traced across the
+ * entropy wave only, and is carried through the three corner-transport
+ * stages by that stage's mass flux from the side the mass comes from, with
+ * the transverse corrections applied to rho X against the corrected
+ * density; rho X is updated conservatively in FP64.  Species cross no
+ * wall (the wall rule makes the mass flux there exactly zero).  RX:
+ * species arena with ghosts filled (ppm_fill_species); RXnew receives the
+ * new valid zones (ghosts untouched).  Needs the step workspace and a
+ * species workspace for ns.  PPM_EINVAL, nothing enqueued, for the errors
+ * of ppm_hydro_step and for a bad ns, null or overlapping species arenas,
+ * RXnew overlapping a state arena, or a missing/small species workspace. */
+int ppm_hydro_step_species(ppm_ctx* ctx, const double* U, double* Unew, const double* RX, double* RXnew,
+                           int32_t ns, double* const* flux, double dt, const double* dt_dev, const double dx[3],
+                           const ppm_params* params, void* stream);
 
 /* Batched form captured in a HIP graph: nsteps steps alternating
  * A -> B -> A ..., each step = [fill, CFL dt on the device, step].  After

@@ -334,6 +334,8 @@ struct ppm_ctx {
   int* d_inv_idx = nullptr;
   void* awork = nullptr;
   size_t awork_bytes = 0;
+  void* swork = nullptr;
+  size_t swork_bytes = 0;
   StepConsts* d_consts = nullptr;
   int* d_flags = nullptr;
   void* work = nullptr;
@@ -719,6 +721,77 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
                                  params->gamma, params->small_dens, params->small_pres, params->limiter,
                                  params->flattening, params->riemann_iters, grav, params->grav, s),
                   "adjoint");
+}
+
+int ppm_species_offsets(const ppm_ctx* ctx, int32_t ns, int64_t* off) {
+  if (!ctx || !off || ns < 1 || ns > PPM_MAX_SPECIES) return PPM_EINVAL;
+  for (size_t b = 0; b < ctx->off.size(); ++b) off[b] = (int64_t)ns * (ctx->off[b] / 5);
+  return PPM_OK;
+}
+
+size_t ppm_species_workspace_bytes(const ppm_ctx* ctx, int32_t ns, int32_t precision) {
+  if (!ctx || ns < 1 || ns > PPM_MAX_SPECIES || precision < 0 || precision > 1) return 0;
+  return species_workspace_bytes(ctx->LS, ctx->LE, ns, precision);
+}
+
+int ppm_set_species_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return PPM_EINVAL;
+  if (((uintptr_t)dev_ptr) % 256 != 0) return ctx->fail(PPM_EINVAL, "species workspace must be 256-byte aligned");
+  ctx->swork = dev_ptr;
+  ctx->swork_bytes = dev_ptr ? bytes : 0;
+  return PPM_OK;
+}
+
+int ppm_fill_species(ppm_ctx* ctx, double* RX, int32_t ns, int32_t mode, void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  if (!RX) return ctx->fail(PPM_EINVAL, "fill_species: null arena");
+  if (ns < 1 || ns > PPM_MAX_SPECIES) return ctx->fail(PPM_EINVAL, "fill_species: ns must be in [1, PPM_MAX_SPECIES]");
+  if (mode != PPM_LAUNCH_BATCHED && mode != PPM_LAUNCH_PER_BOX) return ctx->fail(PPM_EINVAL, "fill_species: bad mode");
+  hipStream_t s = (hipStream_t)stream;
+  const DevLevel L = ctx->level();
+  const Plan& P = *ctx->plan;
+  if (mode == PPM_LAUNCH_BATCHED)
+    return ctx->hip(launch_fill_scalars(L, RX, ns, 0, (int)P.desc.size(), 0, P.start.back(), s), "fill_species");
+  for (int b = 0; b < ctx->layout.nbox; ++b) {
+    const int d0 = P.box_desc[b], d1 = P.box_desc[b + 1];
+    const int rc = ctx->hip(launch_fill_scalars(L, RX, ns, d0, d1, P.start[d0], P.start[d1], s), "fill_species");
+    if (rc) return rc;
+  }
+  return PPM_OK;
+}
+
+int ppm_hydro_step_species(ppm_ctx* ctx, const double* U, double* Unew, const double* RX, double* RXnew,
+                           int32_t ns, double* const* flux, double dt, const double* dt_dev, const double dx[3],
+                           const ppm_params* params, void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  std::string m;
+  if (ns < 1 || ns > PPM_MAX_SPECIES) m = "species step: ns must be in [1, PPM_MAX_SPECIES]";
+  if (m.empty() && (!RX || !RXnew)) m = "species step: null species arena";
+  if (m.empty() && params && (params->precision == 0 || params->precision == 1) &&
+      (!ctx->swork || ctx->swork_bytes < ppm_species_workspace_bytes(ctx, ns, params->precision)))
+    m = "species step: species workspace missing or too small (ppm_set_species_workspace)";
+  if (m.empty()) {
+    const size_t slen = (size_t)ns * (size_t)(ctx->off.back() / 5) * sizeof(double);
+    const size_t alen = (size_t)ctx->off.back() * sizeof(double);
+    const char* a = (const char*)RX;
+    const char* b = (const char*)RXnew;
+    const char* u = (const char*)U;
+    const char* v = (const char*)Unew;
+    if (a < b + slen && b < a + slen) m = "species step: RX and RXnew overlap (the step is out of place)";
+    else if (u && v && ((b < u + alen && u < b + slen) || (b < v + alen && v < b + slen)))
+      m = "species step: RXnew overlaps a state arena";
+  }
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  // the hydro step validates the rest and leaves its intermediates in the
+  // step workspace for the species stages
+  int rc = ppm_hydro_step(ctx, U, Unew, flux, dt, dt_dev, dx, params, PPM_LAUNCH_BATCHED, stream);
+  if (rc) return rc;
+  const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
+  return ctx->hip(launch_species(ctx->level(), params->precision, (int)ctx->tilesS.size(), (int)ctx->tilesE.size(),
+                                 RX, RXnew, ns, ctx->work, ctx->swork, params->gamma, params->small_dens,
+                                 params->small_pres, params->limiter, params->flattening, params->riemann_iters,
+                                 grav, (hipStream_t)stream),
+                  "species step");
 }
 
 int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], const ppm_params* params,

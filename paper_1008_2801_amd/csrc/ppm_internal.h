@@ -13,6 +13,7 @@ constexpr int NG = 4;        // ghost zones per side
 constexpr int TILE = 256;    // default zones per tile (== threads per workgroup)
 constexpr int MAX_TILE = 512;  // largest tile the kernels are built for
 constexpr int NXCD = 8;      // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr int FILL_THREADS = 256;  // threads per workgroup of the ghost-fill kernels
 
 // Per-box metadata on the device.
 struct DevBox {
@@ -106,6 +107,14 @@ hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, cons
                           double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s);
+// Passive species (ppm_species.hip), run after a full step whose
+// intermediates are still in the step workspace `work`.
+size_t species_workspace_bytes(long long LS, long long LE, int ns, int precision);
+hipError_t launch_species(const DevLevel& L, int precision, int nS, int nE, const double* RX, double* RXnew,
+                          int ns, const void* work, void* swork, double gamma, double small_dens,
+                          double small_pres, int limiter, int flattening, int iters, int grav, hipStream_t s);
+hipError_t launch_fill_scalars(const DevLevel& L, double* RX, int ns, int desc_begin, int desc_end,
+                               long long zone_begin, long long zone_end, hipStream_t s);
 // Events recorded by launch_step when ev is non-null: before each of the 7
 // stage kernels and after the last (STEP_EVENTS in all).
 constexpr int STEP_EVENTS = 8;

@@ -482,7 +482,6 @@ __global__ void __launch_bounds__(64) k_finish_dt(double* dt_dev, double cfl) {
 
 // O1: ghost fill over the plan.  One lane per destination ghost zone; the
 // descriptor of a lane is found by binary search in the zone-count prefix.
-constexpr int FILL_THREADS = 256;
 __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restrict__ desc,
                                                const long long* __restrict__ start, int d0, int d1,
                                                long long z0, long long z1,

@@ -27,7 +27,10 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_graph_destroy", "ppm_check_status", "ppm_plan_build", "ppm_fill_boundary_host",
            "ppm_plan_cache_stats", "ppm_profile_enable", "ppm_profile_read",
            "ppm_adjoint_workspace_bytes", "ppm_set_adjoint_workspace", "ppm_hydro_step_adjoint",
-           "ppm_set_tiling", "ppm_get_tiling", "ppm_autotune")
+           "ppm_set_tiling", "ppm_get_tiling", "ppm_autotune", "ppm_species_offsets",
+           "ppm_species_workspace_bytes", "ppm_set_species_workspace", "ppm_fill_species",
+           "ppm_hydro_step_species")
+MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
 
@@ -108,9 +111,17 @@ def lib():
         L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
                                              ctypes.POINTER(Params), _vp]
         L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.ppm_species_offsets.argtypes = [_vp, ctypes.c_int32, _i64p]
+        L.ppm_species_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+        L.ppm_species_workspace_bytes.restype = ctypes.c_size_t
+        L.ppm_set_species_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.ppm_fill_species.argtypes = [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp]
+        L.ppm_hydro_step_species.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.POINTER(_vp),
+                                             ctypes.c_double, _vp, _dp3, ctypes.POINTER(Params), _vp]
         for name in SYMBOLS:
             f = getattr(L, name)
-            if name not in ("ppm_last_error", "ppm_workspace_bytes", "ppm_adjoint_workspace_bytes"):
+            if name not in ("ppm_last_error", "ppm_workspace_bytes", "ppm_adjoint_workspace_bytes",
+                            "ppm_species_workspace_bytes"):
                 f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -322,6 +333,57 @@ class Level:
         self._check(lib().ppm_hydro_step_adjoint(self.ctx, _ptr(U), _ptr(Unew_bar), _ptr(U_bar), float(dt),
                                                  _ptr(dt_dev), _dp3(*dx), ctypes.byref(p), _stream(stream)),
                     "ppm_hydro_step_adjoint")
+
+    # ------------------------------------------------ passive species ----
+    def species_offsets(self, ns):
+        """Element offsets (nbox + 1) of each box in a species arena of ns
+        components."""
+        off = np.zeros(self.layout.nbox + 1, dtype=np.int64)
+        self._check(lib().ppm_species_offsets(self.ctx, int(ns), off.ctypes.data_as(_i64p)), "ppm_species_offsets")
+        return off
+
+    def new_species(self, ns):
+        import torch
+        return torch.full((int(self.species_offsets(ns)[-1]),), float("nan"), dtype=torch.float64,
+                          device=self.device)
+
+    def species_view(self, RX, ns, b):
+        """Box b of a species arena as (ns, Nz, Ny, Nx)."""
+        o = self.species_offsets(ns)
+        return RX[int(o[b]):int(o[b + 1])].view((int(ns),) + tuple(self.layout.stored_shape(b)[1:]))
+
+    def ensure_species_workspace(self, ns, precision=0):
+        import torch
+        need = int(lib().ppm_species_workspace_bytes(self.ctx, int(ns), int(precision)))
+        if need == 0:
+            raise PPMError(f"species workspace: invalid ns={ns} or precision={precision}")
+        if getattr(self, "_swork", None) is None or self._swork.numel() < need + 256:
+            self._swork = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = self._swork.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(lib().ppm_set_species_workspace(self.ctx, ctypes.c_void_p(aligned), need),
+                    "ppm_set_species_workspace")
+        self._swork_key = (int(ns), int(precision))
+
+    def fill_species(self, RX, ns, mode=BATCHED, stream=None):
+        self._check(lib().ppm_fill_species(self.ctx, _ptr(RX), int(ns), int(mode), _stream(stream)),
+                    "ppm_fill_species")
+
+    def hydro_step_species(self, U, Unew, RX, RXnew, ns, dx, p, dt=0.0, dt_dev=None, fluxes=None, stream=None):
+        """The batched step from U to Unew and the species update from RX to
+        RXnew (ghosts of U and RX filled)."""
+        prec = int(p.precision)
+        if self._work is None or self._work_prec != prec or self._work.numel() < self.workspace_bytes(prec) + 256:
+            self.ensure_workspace(prec)
+        if getattr(self, "_swork_key", None) != (int(ns), prec):
+            self.ensure_species_workspace(ns, prec)
+        fl = None
+        if fluxes is not None:
+            fl = (_vp * 3)(*[f.data_ptr() if f is not None else None for f in fluxes])
+        self._check(lib().ppm_hydro_step_species(self.ctx, _ptr(U), _ptr(Unew), _ptr(RX), _ptr(RXnew), int(ns), fl,
+                                                 float(dt), _ptr(dt_dev), _dp3(*dx), ctypes.byref(p),
+                                                 _stream(stream)),
+                    "ppm_hydro_step_species")
 
     def check_status(self, stream=None):
         f = ctypes.c_int32(0)

@@ -1,0 +1,222 @@
+"""GPU parity of the passive-species step: ppm_hydro_step_species and
+ppm_fill_species through the C ABI against the oracle's species step on the
+same seeded inputs.  FP64 bar: max |gpu - oracle| / max |oracle| <= 1e-12
+per species (the kernels evaluate the oracle's formulas in the same order,
+so the values are expected to agree bit for bit); FP32 reconstruction:
+1e-6 against the oracle's FP32 mode."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1008_2801_amd import inputs as I  # noqa: E402
+from paper_1008_2801_amd import ppm as P  # noqa: E402
+from tests.helpers import interior, field_errors  # noqa: E402
+from tests.test_gpu_parity import _uneven_level, _sample_windows  # noqa: E402
+from tests.test_oracle_step import _random_state  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def gpu_run_species(wl, rx, ns, nsteps, dt=None, mode=P.BATCHED, **pk):
+    """nsteps of [fill state and species, dt, step with species] on the GPU."""
+    lev = P.Level(wl.layout)
+    assert np.array_equal(lev.species_offsets(ns), I.species_offsets(wl.layout, ns))
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    R = torch.from_numpy(rx).cuda()
+    Rn = lev.new_species(ns)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision, **pk)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    dts = []
+    for _ in range(nsteps):
+        lev.fill_boundary(U, mode)
+        lev.fill_species(R, ns, mode)
+        if dt is None:
+            lev.compute_dt(U, wl.dx, p, out=dtv)
+        else:
+            dtv[0] = dt
+        lev.hydro_step_species(U, V, R, Rn, ns, wl.dx, p, dt_dev=dtv)
+        dts.append(float(dtv[0].item()))
+        U, V = V, U
+        R, Rn = Rn, R
+    flags = lev.check_status()
+    return lev, U.cpu().numpy(), R.cpu().numpy(), dts, flags
+
+
+def oracle_run_species(wl, rx, ns, nsteps, dt=None, **pk):
+    lay = wl.layout
+    st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    sp = [I.species_view(lay, rx, ns, b).copy() for b in range(lay.nbox)]
+    p = O.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision, **pk)
+    return O.advance_species(lay.boxes(), lay.domain(), lay.bc, st, sp, nsteps, wl.dx, p, dt=dt)
+
+
+def compare_species(wl, ns, garena, gspecies, ost, osp, tol=TOL):
+    """Per-field (state) and per-species errors over the valid zones."""
+    lay = wl.layout
+    worst_u = max(field_errors(interior(lay.view(garena, b)), interior(ost[b])).max() for b in range(lay.nbox))
+    worst_x, nbits = 0.0, 0
+    for s in range(ns):
+        g = np.concatenate([interior(I.species_view(lay, gspecies, ns, b))[s].ravel() for b in range(lay.nbox)])
+        o = np.concatenate([interior(osp[b])[s].ravel() for b in range(lay.nbox)])
+        worst_x = max(worst_x, np.abs(g - o).max() / np.abs(o).max())
+        nbits += int(np.count_nonzero(g != o))
+    assert worst_u <= tol and worst_x <= tol, (worst_u, worst_x, nbits)
+    return worst_u, worst_x, nbits
+
+
+def _case(name):
+    if name == "box_ragged":
+        wl = _random_state((20, 18, 22), 61, jump=True)
+        return wl, I.species(wl, 3, seed=62), 3, 3
+    if name == "multibox":
+        wl = _uneven_level(seed=63)
+        return wl, I.species(wl, 2, seed=64), 2, 2
+    if name == "walls_gravity":
+        wl = _uneven_level(seed=65, bc=(0, 0, 0, 0, 2, 2))
+        wl.grav = (0.0, 0.0, -1.0)
+        return wl, I.species(wl, 2, seed=66), 2, 2
+    if name == "rayleigh_taylor":
+        wl = I.cfg5(2, 8, precision=0)
+        return wl, I.species(wl, 2, kind="density"), 2, 3
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name", ["box_ragged", "multibox", "walls_gravity", "rayleigh_taylor"])
+def test_species_step_matches_oracle(name):
+    wl, rx, ns, nsteps = _case(name)
+    print(f"species parity case {name}: ns={ns} nsteps={nsteps} boxes={wl.layout.nbox}", flush=True)
+    _, ga, gx, dts, flags = gpu_run_species(wl, rx, ns, nsteps)
+    ost, osp, odts, ofl = oracle_run_species(wl, rx, ns, nsteps)
+    assert flags == 0 and ofl == 0
+    assert dts == odts
+    wu, wx, nbits = compare_species(wl, ns, ga, gx, ost, osp)
+    print(f"{name}: state {wu:.3e}, species {wx:.3e}, differing species values {nbits}")
+
+
+def test_species_fp32_reconstruction_matches_oracle_fp32_mode():
+    wl = I.cfg1(16)
+    wl.precision = 1
+    rx = I.species(wl, 2, seed=67)
+    _, ga, gx, dts, flags = gpu_run_species(wl, rx, 2, 3)
+    ost, osp, odts, ofl = oracle_run_species(wl, rx, 2, 3)
+    assert flags == 0 and ofl == 0
+    wu, wx, nbits = compare_species(wl, 2, ga, gx, ost, osp, tol=1e-6)
+    print(f"fp32 species: state {wu:.3e}, species {wx:.3e}")
+
+
+def test_unit_fraction_reproduces_the_density_bitwise_on_gpu():
+    wl = I.cfg5(2, 8, precision=0)
+    rx = I.species(wl, 1, kind="const")
+    _, ga, gx, _, flags = gpu_run_species(wl, rx, 1, 3)
+    assert flags == 0
+    for b in range(wl.layout.nbox):
+        assert np.array_equal(interior(I.species_view(wl.layout, gx, 1, b))[0],
+                              interior(wl.layout.view(ga, b))[0])
+
+
+def test_species_state_equals_the_plain_step_bitwise():
+    """The species ride along: Unew of the species step is the plain step's."""
+    wl = _uneven_level(seed=68)
+    rx = I.species(wl, 2, seed=69)
+    lev, ga, _, dts, _ = gpu_run_species(wl, rx, 2, 2)
+    lev2 = P.Level(wl.layout)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev2.new_state()
+    p = P.params(gamma=wl.gamma)
+    for dt in dts:
+        lev2.fill_boundary(U)
+        lev2.hydro_step(U, V, wl.dx, p, dt=dt)
+        U, V = V, U
+    ref = U.cpu().numpy()
+    for b in range(wl.layout.nbox):
+        assert np.array_equal(interior(wl.layout.view(ga, b)), interior(wl.layout.view(ref, b)))
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (1, 1, 0, 0, 2, 2), (2, 2, 1, 1, 0, 0)])
+def test_species_fill_matches_oracle_bitwise(bc):
+    wl = _uneven_level(seed=70, bc=bc)
+    ns = 3
+    rx = I.species(wl, ns, seed=71)
+    lay = wl.layout
+    lev = P.Level(lay)
+    R = torch.from_numpy(rx).cuda()
+    lev.fill_species(R, ns)
+    got = R.cpu().numpy()
+    R2 = torch.from_numpy(rx).cuda()
+    lev.fill_species(R2, ns, mode=P.PER_BOX)
+    assert np.array_equal(got, R2.cpu().numpy())
+    sp = [I.species_view(lay, rx, ns, b).copy() for b in range(lay.nbox)]
+    O.fill_scalars(lay.boxes(), lay.domain(), lay.bc, sp)
+    for b in range(lay.nbox):
+        assert np.array_equal(I.species_view(lay, got, ns, b), sp[b])
+
+
+def test_species_full_size_sampled_windows():
+    """The 256^3 workload with two species, one step as bench.py times it:
+    sampled windows of the new partial densities against the oracle one by
+    one, and conservation of each species over the whole box."""
+    wl = I.cfg2()
+    ns = 2
+    rx = I.species(wl, ns, seed=72)
+    lev, ga, gx, dts, flags = gpu_run_species(wl, rx, ns, 1)
+    assert flags == 0
+    lay = wl.layout
+    st = [lay.view(wl.arena, 0).copy()]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    sp = [I.species_view(lay, rx, ns, 0).copy()]
+    O.fill_scalars(lay.boxes(), lay.domain(), lay.bc, sp)
+    p = O.params(gamma=wl.gamma)
+    got = I.species_view(lay, gx, ns, 0)
+    rng = np.random.default_rng(73)
+    for lo, hi in _sample_windows(lay.n(0), rng, 8):
+        _, ref, _ = O.step_species(st[0], sp[0], dts[0], wl.dx, p, window=(lo, hi))
+        sl = (slice(None),) + tuple(slice(lo[d] + 4, hi[d] + 5) for d in (2, 1, 0))
+        err = np.abs(got[sl] - ref[sl]).max() / np.abs(ref[sl]).max()
+        assert err <= TOL, (lo, hi, err)
+    for s in range(ns):
+        s0 = math.fsum(interior(I.species_view(lay, rx, ns, 0))[s].ravel())
+        s1 = math.fsum(interior(got)[s].ravel())
+        assert abs(s1 - s0) <= 1e-13 * abs(s0)
+
+
+def test_species_invalid_arguments_are_rejected():
+    wl = _uneven_level(seed=74)
+    lev = P.Level(wl.layout)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    R = lev.new_species(2)
+    Rn = lev.new_species(2)
+    p = P.params(gamma=wl.gamma)
+    lev.fill_boundary(U)
+    R.zero_()
+    lev.fill_species(R, 2)
+    for bad_ns in (0, P.MAX_SPECIES + 1):
+        with pytest.raises(P.PPMError):
+            lev.fill_species(R, bad_ns)
+        assert int(P.lib().ppm_species_workspace_bytes(lev.ctx, bad_ns, 0)) == 0
+    with pytest.raises(P.PPMError, match="overlap"):
+        lev.hydro_step_species(U, V, R, R, 2, wl.dx, p, dt=1e-3)
+    with pytest.raises(P.PPMError, match="overlap"):
+        lev.hydro_step_species(U, V, R, V, 2, wl.dx, p, dt=1e-3)
+    # a species workspace sized for fewer species is refused
+    lev.ensure_species_workspace(1, 0)
+    rc = P.lib().ppm_hydro_step_species(lev.ctx, P._ptr(U), P._ptr(V), P._ptr(R), P._ptr(Rn), 2, None,
+                                        1e-3, None, P._dp3(*wl.dx), P.ctypes.byref(p), None)
+    assert rc == P.PPM_EINVAL
+    assert b"species workspace" in P.lib().ppm_last_error(lev.ctx)
+    # and a valid call still works afterwards
+    lev.hydro_step_species(U, V, R, Rn, 2, wl.dx, p, dt=1e-3)
+    torch.cuda.synchronize()
