@@ -232,6 +232,80 @@ def adjoint_costs(wl, nsteps, every, reps=3, precision=0, rollout=True):
     return res
 
 
+# Per species and traced zone, the bytes each staged species kernel must move
+# at least (every plane it reads or writes touched once, FP64): fractions
+# 8 + 8, trace 3 x 8 read + 6 x 8 written, stage 1 6 x 8 + 3 x 8, stage 2
+# (6 + 3) x 8 + 6 x 8, stage 3 (6 + 6) x 8 + 3 x 8, update 3 x 8 + 8 + 8;
+# plus the hydro planes the stages read once per zone for all species
+# (density for the fractions; flattening, normal velocity and sound speed
+# per axis; stage mass fluxes and traced densities).
+SPECIES_BYTES_PER_ZONE_SPECIES = 16 + 72 + 72 + 120 + 120 + 40
+SPECIES_SHARED_BYTES_PER_ZONE = 8 + 72 + 24 + 120 + 120
+
+
+def species_costs(wl, ns, steps, warmup, precision=0):
+    """Time of the step with ns passive species against the plain step on
+    the same level (HIP events on the launch stream), and the species part's
+    rate against the HBM roofline of its staged kernels' minimum traffic."""
+    import numpy as np
+    import torch
+    from paper_1008_2801_amd import inputs as I
+    from paper_1008_2801_amd import ppm as P
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+    lev.ensure_workspace(precision)
+    lev.ensure_species_workspace(ns, precision)
+    U0 = torch.from_numpy(wl.arena).to("cuda")
+    R0 = torch.from_numpy(I.species(wl, ns, seed=80)).to("cuda")
+    Uf = U0.clone()
+    lev.fill_boundary(Uf)
+    lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)
+    del Uf
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def run(with_species):
+        U, V = U0.clone(), lev.new_state()
+        R, Rn = R0.clone(), lev.new_species(ns)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for k in range(warmup + steps):
+            if k == warmup:
+                e0.record()
+            lev.fill_boundary(U)
+            lev.compute_dt(U, wl.dx, p, out=dtv)
+            if with_species:
+                lev.fill_species(R, ns)
+                lev.hydro_step_species(U, V, R, Rn, ns, wl.dx, p, dt_dev=dtv)
+                R, Rn = Rn, R
+            else:
+                lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv)
+            U, V = V, U
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    plain = min(run(False) for _ in range(2))
+    with_sp = min(run(True) for _ in range(2))
+    zones = lay.valid_zones()
+    ezones = sum(int(np.prod(np.asarray(lay.n(b)) + 2)) for b in range(lay.nbox))
+    sp_ms = with_sp - plain
+    size = 8 if precision == 0 else 4
+    # the fractions, fluxes and traces are in the reconstruction precision;
+    # rho X and its update stay FP64
+    nbytes = ezones * (ns * SPECIES_BYTES_PER_ZONE_SPECIES * size / 8 + SPECIES_SHARED_BYTES_PER_ZONE * size / 8)
+    out = {"species": ns, "ms_per_step_plain": plain, "ms_per_step_with_species": with_sp,
+           "species_ms_per_step": sp_ms, "species_ms_per_species": sp_ms / ns,
+           "zone_species_updates_per_s": zones * ns / (sp_ms / 1e3) if sp_ms > 0 else None,
+           "species_min_traffic_GB": nbytes / 1e9,
+           "species_hbm_GBps": nbytes / (sp_ms / 1e3) / 1e9 if sp_ms > 0 else None,
+           "flags": lev.check_status()}
+    lev.close()
+    del U0, R0, lev
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(gib=2, reps=5):
     """Measured HBM bandwidth of a plain device-to-device copy (bytes read +
     written per second), the practical ceiling next to the 8 TB/s spec."""
@@ -290,6 +364,8 @@ def main():
                     help="skip the 512-box batched / per-box / graph measurements")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only measure the adjoint/forward cost on the 128^3 differentiation workload")
+    ap.add_argument("--species-only", action="store_true",
+                    help="with --no-extras: still measure the passive-species step")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record of the dominant kernel from two rocprofv3 --pmc "
                          "counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) and exit")
@@ -461,6 +537,18 @@ def main():
         rt["adjoint"] = a5
         out["rayleigh_taylor"] = rt
         del w5
+    if not args.no_extras or args.species_only:
+        from paper_1008_2801_amd import inputs as I
+        print("bench: passive species on the 256^3 workload", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        w2 = make_workload(args.workload)
+        sp = {"workload": f"{w2.name} with passive species (mode-sum mass fractions summing to one), "
+                          "fill + dt + step, 10 steps"}
+        for ns in (1, 4):
+            sp[f"fp64_ns{ns}"] = species_costs(w2, ns, 10, 2, precision=0)
+        sp["fp32_reconstruction_ns4"] = species_costs(w2, 4, 10, 2, precision=1)
+        out["species"] = sp
+        del w2
     if not args.no_cpu_baseline:
         print("bench: timing the CPU reference on a window", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_window, wl.gamma)
