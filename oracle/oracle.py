@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "ppm_oracle.cpp")
 _LIBDIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_LIBDIR, "liboracle.so")
 NG = 4
-BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_COARSE_FINE = 0, 1, 2, 3
 FLAG_NONPHYS, FLAG_FLOOR = 1, 2
 STAGES = ("prim", "flatten", "trace", "riemann1", "transverse1", "riemann2",
           "transverse2", "riemann3", "update")

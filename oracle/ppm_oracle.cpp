@@ -158,7 +158,9 @@ struct OParams {
 };
 
 enum { FLAG_NONPHYS = 1, FLAG_FLOOR = 2 };
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
+// BC_COARSE_FINE: the face borders a coarser level; ghost zones beyond it
+// are filled by interpolation from that level, not by the level's own fill.
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_COARSE_FINE = 3 };
 const int NG = 4;  // ghost width: flattening reaches 3 zones past a traced zone
 
 // Per-step constants in the reconstruction scalar.  They are formed in FP64
@@ -1099,11 +1101,13 @@ int oracle_trace(const double aL[5], const double aR[5], const double a6[5], con
 // O1: ghost fill of every box of a level.  Boxes are inclusive [lo, hi]
 // triples in a global index space and tile the domain [dlo, dhi] exactly.
 // bc[2d], bc[2d+1]: low/high face of axis d (0 periodic, 1 outflow, 2
-// reflect).  Box b's data start at arena + off[b], layout [comp][k][j][i]
-// over (n+8)^3.  A ghost zone takes the value of the valid zone that owns
-// its image: periodic axes wrap, outflow axes clamp to the nearest valid
-// zone, reflecting axes mirror about the wall with the normal momentum
-// negated.  Returns 0, or -1 if an image has no owner.
+// reflect, 3 coarse-fine).  Box b's data start at arena + off[b], layout
+// [comp][k][j][i] over (n+8)^3.  A ghost zone takes the value of the valid
+// zone that owns its image: periodic axes wrap, outflow axes clamp to the
+// nearest valid zone, reflecting axes mirror about the wall with the normal
+// momentum negated.  Ghost zones beyond a coarse-fine face are left as they
+// are (the two-level advance interpolates them).  Returns 0, or -1 if an
+// image has no owner.
 static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
                       const int bc[6], double* arena, const long long* off, int ncomp, bool momentum);
 
@@ -1143,6 +1147,10 @@ static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], 
       if (x[0] >= 0 && x[0] < n[0] && x[1] >= 0 && x[1] < n[1] && x[2] >= 0 && x[2] < n[2]) return;
       int g[3];
       double sgn[3] = {1, 1, 1};  // momentum components 1..3
+      for (int d = 0; d < 3; ++d) {
+        const int v = lo[3 * b + d] + x[d] - dlo[d];
+        if ((v < 0 && bc[2 * d] == BC_COARSE_FINE) || (v >= L[d] && bc[2 * d + 1] == BC_COARSE_FINE)) return;
+      }
       for (int d = 0; d < 3; ++d) {
         int v = lo[3 * b + d] + x[d] - dlo[d];  // domain-relative index
         if (v < 0 || v >= L[d]) {

@@ -31,7 +31,7 @@ import math
 import numpy as np
 
 NG = 4
-BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_COARSE_FINE = 0, 1, 2, 3
 
 
 @dataclass
@@ -94,11 +94,12 @@ def single_box(n, bc=(0, 0, 0, 0, 0, 0)):
     return Layout(lo, hi, (0, 0, 0), tuple(int(v) for v in hi[0]), tuple(bc))
 
 
-def tensor_tiling(sx, sy, sz, bc=(0, 0, 0, 0, 0, 0)):
-    """Box (a, b, c) spans sizes sx[a] x sy[b] x sz[c]; box index a fastest."""
-    ex = np.concatenate([[0], np.cumsum(sx)])
-    ey = np.concatenate([[0], np.cumsum(sy)])
-    ez = np.concatenate([[0], np.cumsum(sz)])
+def tensor_tiling(sx, sy, sz, bc=(0, 0, 0, 0, 0, 0), origin=(0, 0, 0)):
+    """Box (a, b, c) spans sizes sx[a] x sy[b] x sz[c]; box index a fastest;
+    the first box starts at `origin`."""
+    ex = origin[0] + np.concatenate([[0], np.cumsum(sx)])
+    ey = origin[1] + np.concatenate([[0], np.cumsum(sy)])
+    ez = origin[2] + np.concatenate([[0], np.cumsum(sz)])
     lo, hi = [], []
     for c in range(len(sz)):
         for b in range(len(sy)):
@@ -107,7 +108,8 @@ def tensor_tiling(sx, sy, sz, bc=(0, 0, 0, 0, 0, 0)):
                 hi.append((ex[a + 1] - 1, ey[b + 1] - 1, ez[c + 1] - 1))
     lo = np.array(lo, dtype=np.int64)
     hi = np.array(hi, dtype=np.int64)
-    return Layout(lo, hi, (0, 0, 0), (int(ex[-1] - 1), int(ey[-1] - 1), int(ez[-1] - 1)), tuple(bc))
+    return Layout(lo, hi, tuple(int(v) for v in origin), (int(ex[-1] - 1), int(ey[-1] - 1), int(ez[-1] - 1)),
+                  tuple(bc))
 
 
 class ModeSum:
@@ -185,14 +187,8 @@ def cfg1(n=32):
     return Workload("cfg1", lay, _fill_state(lay, h, 1.4, prim), h, 1.4, 10)
 
 
-def cfg2(n=256, seed=2):
-    """rho = rho_J(x) (1 + 0.1 S), S: 16 modes with |k| <= 8; p = p_J(x);
-    rho_J, p_J = (1, 1) for x < 1/2 and (0.125, 0.1) beyond; constant velocity
-    with each component ~ U[-0.5, 0.5]; gamma 5/3, periodic.  RNG draws:
-    the density modes, then the three velocity components."""
+def _cfg2_prim(seed):
     rng = np.random.default_rng(seed)
-    lay = single_box(n)
-    h = (1.0 / n,) * 3
     S = ModeSum(rng, 16, 8, (1.0, 1.0, 1.0))
     vel = rng.uniform(-0.5, 0.5, size=3)
 
@@ -201,6 +197,17 @@ def cfg2(n=256, seed=2):
         rj = np.where(left, 1.0, 0.125)
         pj = np.where(left, 1.0, 0.1)
         return (rj * (1.0 + 0.1 * S(x, y, z)), vel[0], vel[1], vel[2], pj)
+    return prim, vel
+
+
+def cfg2(n=256, seed=2):
+    """rho = rho_J(x) (1 + 0.1 S), S: 16 modes with |k| <= 8; p = p_J(x);
+    rho_J, p_J = (1, 1) for x < 1/2 and (0.125, 0.1) beyond; constant velocity
+    with each component ~ U[-0.5, 0.5]; gamma 5/3, periodic.  RNG draws:
+    the density modes, then the three velocity components."""
+    lay = single_box(n)
+    h = (1.0 / n,) * 3
+    prim, vel = _cfg2_prim(seed)
     return Workload("cfg2", lay, _fill_state(lay, h, 5.0 / 3.0, prim), h, 5.0 / 3.0, 20,
                     meta={"velocity": vel.tolist()})
 
@@ -370,3 +377,73 @@ def species(wl, ns, seed=11, kind="modes", amp=0.9, nmodes=4, K=3):
         for s in range(ns):
             V[s, g:g + nz, g:g + ny, g:g + nx] = rho * X[s]
     return arena
+
+
+# ----------------------------------------------------- two-level AMR -------
+@dataclass
+class TwoLevel:
+    """A coarse level tiling the periodic unit cube and a fine level (ratio
+    2) tiling the refinement of the coarse-index rectangle `region`; the
+    fine layout's domain is that refinement, all its faces coarse-fine."""
+    name: str
+    coarse: Workload
+    fine: Workload
+    region: tuple
+
+
+def _split(total, size):
+    sizes = [size] * (total // size)
+    if total % size:
+        sizes.append(total % size)
+    return sizes
+
+
+def two_level(n, cbox, fbox, prim, gamma, name, grav=(0.0, 0.0, 0.0), region=None):
+    """Coarse n^3 zones on the unit cube (periodic) cut into boxes of at
+    most cbox per edge; by default the inner half of every axis refined (the
+    inner 12.5% of the volume), its n^3 fine zones cut into boxes of at most
+    fbox per edge (fbox even).  Both levels sample prim at their own cell
+    centres (h_f = h_c / 2)."""
+    nc = (n, n, n) if np.isscalar(n) else tuple(n)
+    if region is None:
+        region = (tuple(v // 4 for v in nc), tuple(3 * v // 4 - 1 for v in nc))
+    clay = tensor_tiling(_split(nc[0], cbox), _split(nc[1], cbox), _split(nc[2], cbox))
+    hc = tuple(1.0 / v for v in nc)
+    rlo, rhi = region
+    fe = [2 * (rhi[d] - rlo[d] + 1) for d in range(3)]
+    flay = tensor_tiling(_split(fe[0], fbox), _split(fe[1], fbox), _split(fe[2], fbox),
+                         bc=(BC_COARSE_FINE,) * 6, origin=tuple(2 * v for v in rlo))
+    hf = tuple(v / 2.0 for v in hc)
+    cw = Workload(name + "_coarse", clay, _fill_state(clay, hc, gamma, prim), hc, gamma, 1, grav=tuple(grav))
+    fw = Workload(name + "_fine", flay, _fill_state(flay, hf, gamma, prim), hf, gamma, 1, grav=tuple(grav))
+    return TwoLevel(name, cw, fw, (tuple(rlo), tuple(rhi)))
+
+
+def amr_wave(n=16, cbox=None, fbox=None):
+    """cfg1's advected density wave on a two-level hierarchy."""
+    def prim(x, y, z):
+        return (1.0 + 0.2 * np.sin(2.0 * math.pi * (x + y + z)), 1.0, 0.5, 0.25, 1.0)
+    return two_level(n, cbox or n, fbox or n, prim, 1.4, "amr_wave")
+
+
+def amr_cfg2(n=256, cbox=None, fbox=None, seed=2):
+    """cfg2's state (random-mode density times a Sod jump in x, constant
+    velocity, gamma 5/3) with the inner 12.5% refined: n^3 coarse and n^3
+    fine zones, so one coarse step (one coarse and two fine steps) costs
+    three single-level steps of the coarse level plus the level operations."""
+    prim, _ = _cfg2_prim(seed)
+    return two_level(n, cbox or n, fbox or n, prim, 5.0 / 3.0, "amr_cfg2")
+
+
+def amr_random(n=16, cbox=8, fbox=8, seed=21, grav=(0.0, 0.0, 0.0)):
+    """Smooth random fields with a density/pressure jump in x, several boxes
+    per level: the parity workload of the two-level advance."""
+    rng = np.random.default_rng(seed)
+    S = [ModeSum(rng, 6, 3, (1.0, 1.0, 1.0)) for _ in range(5)]
+
+    def prim(x, y, z):
+        rj = np.where(x < 0.45, 1.0, 0.4)
+        pj = np.where(x < 0.45, 1.0, 0.3)
+        return (rj * (1.0 + 0.3 * S[0](x, y, z)), 0.5 * S[1](x, y, z), 0.5 * S[2](x, y, z),
+                0.5 * S[3](x, y, z), pj * (1.0 + 0.3 * S[4](x, y, z)))
+    return two_level(n, cbox, fbox, prim, 1.4, "amr_random", grav=grav)
