@@ -54,7 +54,9 @@ enum {
   PPM_ENONPHYS = 3   /* status flags raised (ppm_check_status only) */
 };
 
-enum { PPM_BC_PERIODIC = 0, PPM_BC_OUTFLOW = 1, PPM_BC_REFLECT = 2 };
+enum { PPM_BC_PERIODIC = 0, PPM_BC_OUTFLOW = 1, PPM_BC_REFLECT = 2,
+       PPM_BC_COARSE_FINE = 3 /* the face borders a coarser level: ghost zones beyond it are left to
+                                 the two-level interpolation (ppm_amr_fill_fine), not filled */ };
 
 /* status flags accumulated on the device */
 enum { PPM_FLAG_NONPHYS = 1, /* rho <= 0, p <= 0 or a non-finite value in an input state */
@@ -205,6 +207,63 @@ int ppm_fill_species(ppm_ctx* ctx, double* RX, int32_t ns, int32_t mode, void* s
 int ppm_hydro_step_species(ppm_ctx* ctx, const double* U, double* Unew, const double* RX, double* RXnew,
                            int32_t ns, double* const* flux, double dt, const double* dt_dev, const double dx[3],
                            const ppm_params* params, void* stream);
+
+/* Two-level hierarchy with subcycling in time, refinement ratio 2 (paper
+ * Sec. 1: adaptive mesh refinement; Sec. 2: ghost cells from intersecting
+ * grids and synchronisation of the levels; Sec. 3: a coarse time step is
+ * one coarse and two fine steps; the multilevel runs refine the inner 12.5%
+ * of the domain).  The formulas are the standard Berger-Colella ones:
+ *  - dt: one coarse dt = cfl / max(S_c, S_f / 2) (S: the level's maximum of
+ *    (|u_d| + c)/h_d over valid zones), two fine steps of dt / 2;
+ *  - fine ghost zones beyond the refined region: conservative linear
+ *    interpolation of the coarse state at the fine step's start time,
+ *    U(th) = (1 - th) U_old + th U_new with th = 0, then 1/2: per component
+ *    and axis the MC-limited slope s = copysign(min(|dc|, 2|dl|, 2|dr|), dc)
+ *    if dl dr > 0, else 0, and the fine value U + ((s_x o_x + s_y o_y) +
+ *    s_z o_z), o = -1/4 / +1/4 for the lower / upper half of the parent;
+ *  - flux register: per coarse face of the refined region's surface the
+ *    four fine sub-face fluxes summed pairwise, (f00 + f10) + (f01 + f11),
+ *    both fine steps added;
+ *  - reflux: the uncovered coarse zone next to the face gets
+ *    -+ dt/h_d (register / 8 - its coarse flux) (minus where the face is
+ *    the zone's high face);
+ *  - average down: each covered coarse zone = ((f000 + f100) + (f010 +
+ *    f110)) + ((f001 + f101) + (f011 + f111)), times 1/8.
+ * The coarse context is any level; the fine context's layout has as its
+ * domain the refinement of one rectangle of whole coarse zones at least 3
+ * coarse zones from every coarse domain face, PPM_BC_COARSE_FINE on all six
+ * faces, and boxes that start and end on coarse-zone boundaries (even lower,
+ * odd upper fine indices).  ppm_amr_create checks this (PPM_EINVAL, message
+ * in ppm_last_error of the coarse context) and keeps device copies of the
+ * interpolation, register and average-down lists and a register of 5
+ * doubles per register face (library-owned, freed by ppm_amr_destroy).  The
+ * contexts must outlive the hierarchy; each keeps its own step workspace. */
+typedef struct ppm_amr ppm_amr;
+int ppm_amr_create(ppm_ctx* coarse, ppm_ctx* fine, ppm_amr** out);
+int ppm_amr_destroy(ppm_amr* a);
+const char* ppm_amr_last_error(const ppm_amr* a);
+/* Zones the interpolation writes, faces of the flux register, covered
+ * coarse zones (any pointer may be null). */
+int ppm_amr_sizes(const ppm_amr* a, int64_t* interp_zones, int64_t* register_faces, int64_t* covered_zones);
+
+/* Fine ghost zones: the fine level's own fill (copies between fine boxes),
+ * then the interpolation from the coarse states Uc_old and Uc_new (ghosts
+ * filled) at th = half / 2 (half 0 or 1).  Writes Uf's ghost zones only. */
+int ppm_amr_fill_fine(ppm_amr* a, const double* Uc_old, const double* Uc_new, int32_t half, double* Uf,
+                      void* stream);
+
+/* One coarse step of the hierarchy.  Reads the valid zones of Uc (its ghost
+ * zones are filled in place) and Uf; writes the new coarse level to Uc_new
+ * (synchronised: refluxed and averaged down) and the new fine level to Uf
+ * (Uf_tmp holds the intermediate fine state).  Fc, Ff: three flux arenas
+ * per level (ppm_flux_offsets of each context), overwritten.  dt > 0: fixed
+ * coarse dt; dt = 0: the rule above.  dt_out (device, 2 doubles, may be
+ * null) receives the coarse and the fine dt.  Needs both contexts' step
+ * workspaces.  PPM_EINVAL for null or overlapping arenas, cfl outside
+ * (0, 1), dt < 0, and the errors of the underlying steps. */
+int ppm_amr_step(ppm_amr* a, const double* Uc, double* Uc_new, double* Uf, double* Uf_tmp, double* const* Fc,
+                 double* const* Ff, const double dxc[3], const ppm_params* params, double dt, double* dt_out,
+                 void* stream);
 
 /* Batched form captured in a HIP graph: nsteps steps alternating
  * A -> B -> A ..., each step = [fill, CFL dt on the device, step].  After

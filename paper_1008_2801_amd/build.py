@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("ppm_api.hip", "ppm_kernels.hip", "ppm_adjoint.hip", "ppm_species.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("ppm_api.hip", "ppm_kernels.hip", "ppm_adjoint.hip", "ppm_species.hip", "ppm_amr.hip")]
 OUT = os.path.join(HERE, "libppm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "ppm_internal.h"
+#include "ppm_ctx.h"
 
 using namespace ppm;
 
@@ -26,13 +26,6 @@ struct IBox {
   int lo[3], hi[3];
 };
 
-// The ghost-fill plan of a layout: copy descriptors grouped by destination
-// box, with the exclusive prefix of their zone counts.
-struct Plan {
-  std::vector<FillDesc> desc;
-  std::vector<long long> start;   // ndesc + 1
-  std::vector<int> box_desc;      // nbox + 1: descriptor range of each destination box
-};
 
 struct LayoutKey {
   std::vector<int> v;  // nbox, boxes, domain, bc, ngrow
@@ -67,7 +60,7 @@ std::string validate_layout(const ppm_layout& L) {
     const bool pl = L.bc[2 * d] == PPM_BC_PERIODIC, ph = L.bc[2 * d + 1] == PPM_BC_PERIODIC;
     if (pl != ph) return "layout: a periodic axis needs both faces periodic";
     for (int s = 0; s < 2; ++s)
-      if (L.bc[2 * d + s] < 0 || L.bc[2 * d + s] > 2) return "layout: unknown boundary code";
+      if (L.bc[2 * d + s] < 0 || L.bc[2 * d + s] > PPM_BC_COARSE_FINE) return "layout: unknown boundary code";
   }
   long long vol = 0;
   for (int b = 0; b < L.nbox; ++b) {
@@ -190,8 +183,9 @@ Plan build_plan(const ppm_layout& L, bool brute) {
             l += B.lo[d];
             h += B.lo[d];
             const int cuts[4] = {l, std::max(l, dlo[d]), std::min(h, dhi[d]) + 1, h + 1};
-            // below the domain
-            if (cuts[0] < cuts[1]) {
+            // below the domain (nothing beyond a coarse-fine face: the
+            // two-level advance interpolates those ghost zones)
+            if (cuts[0] < cuts[1] && L.bc[2 * d] != PPM_BC_COARSE_FINE) {
               const int bc = L.bc[2 * d];
               Piece pc{cuts[0], std::min(cuts[1] - 1, h), 1, 0, 0};
               if (bc == PPM_BC_PERIODIC) { pc.a = 1; pc.c = ext[d]; }
@@ -200,7 +194,7 @@ Plan build_plan(const ppm_layout& L, bool brute) {
               pcs[d].push_back(pc);
             }
             if (cuts[1] < cuts[2]) pcs[d].push_back(Piece{cuts[1], cuts[2] - 1, 1, 0, 0});
-            if (cuts[2] < cuts[3]) {
+            if (cuts[2] < cuts[3] && L.bc[2 * d + 1] != PPM_BC_COARSE_FINE) {
               const int bc = L.bc[2 * d + 1];
               Piece pc{std::max(cuts[2], l), cuts[3] - 1, 1, 0, 0};
               if (bc == PPM_BC_PERIODIC) { pc.a = 1; pc.c = -ext[d]; }
@@ -294,7 +288,6 @@ long long round_up(long long x, long long m) { return (x + m - 1) / m * m; }
 // strips of `strip_rows` rows and each strip is walked through all planes
 // before the next, so the z-neighbours of a tile were visited a few tiles
 // earlier and are still in the XCD's L2 (strip_rows = 0: plane by plane).
-constexpr int STRIP_ROWS = 32;
 void add_tiles(std::vector<Tile>& out, int b, int e0, int e1, int e2, int tile, int strip_rows) {
   const long long plane = (long long)e0 * e1, tot = plane * e2;
   const long long strip = strip_rows > 0 ? (long long)strip_rows * e0 : plane;
@@ -312,84 +305,6 @@ void add_tiles(std::vector<Tile>& out, int b, int e0, int e1, int e2, int tile, 
 }
 
 }  // namespace
-
-// ============================================================ context =====
-struct ppm_ctx {
-  std::vector<ppm_box> boxes;
-  ppm_layout layout{};
-  std::vector<int64_t> off, foff[3];
-  std::shared_ptr<const Plan> plan;
-  bool plan_hit = false;
-  std::vector<Tile> tilesS, tilesE;
-  std::vector<int> tS_begin, tE_begin;  // nbox + 1
-  int tile = TILE, strip_rows = STRIP_ROWS;
-  long long LS = 0, LE = 0;
-  // device copies
-  DevBox* d_boxes = nullptr;
-  Tile* d_tilesS = nullptr;
-  Tile* d_tilesE = nullptr;
-  FillDesc* d_desc = nullptr;
-  long long* d_start = nullptr;
-  int* d_inv_start = nullptr;
-  int* d_inv_idx = nullptr;
-  void* awork = nullptr;
-  size_t awork_bytes = 0;
-  void* swork = nullptr;
-  size_t swork_bytes = 0;
-  StepConsts* d_consts = nullptr;
-  int* d_flags = nullptr;
-  void* work = nullptr;
-  size_t work_bytes = 0;
-  std::string err;
-  // stage timing with HIP events (ppm_profile_enable / ppm_profile_read)
-  struct ProfRec {
-    int tag0, n;
-    std::array<hipEvent_t, STEP_EVENTS> ev;
-  };
-  bool prof = false;
-  std::vector<ProfRec> recs;
-  std::vector<std::array<hipEvent_t, STEP_EVENTS>> pool;
-
-  // An event set for a record of n events starting at stage tag tag0.
-  ProfRec* begin_rec(int tag0, int n) {
-    std::array<hipEvent_t, STEP_EVENTS> ev{};
-    if (!pool.empty()) {
-      ev = pool.back();
-      pool.pop_back();
-    } else {
-      for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    }
-    recs.push_back(ProfRec{tag0, n, ev});
-    return &recs.back();
-  }
-
-  DevLevel level() const {
-    DevLevel L;
-    L.boxes = d_boxes;
-    L.tilesS = d_tilesS;
-    L.tilesE = d_tilesE;
-    L.desc = d_desc;
-    L.desc_start = d_start;
-    L.consts = d_consts;
-    L.flags = d_flags;
-    L.inv_start = d_inv_start;
-    L.inv_idx = d_inv_idx;
-    L.LS = LS;
-    L.LE = LE;
-    L.tile = tile;
-    return L;
-  }
-  int fail(int code, const std::string& msg) {
-    err = msg;
-    return code;
-  }
-  int hip(hipError_t e, const char* what) {
-    if (e == hipSuccess) return PPM_OK;
-    err = std::string(what) + ": " + hipGetErrorString(e);
-    return PPM_EHIP;
-  }
-};
 
 struct ppm_graph {
   ppm_ctx* ctx = nullptr;

@@ -1,0 +1,106 @@
+// Host-side context of a level, shared by the library's host sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ppm.h"
+#include "ppm_internal.h"
+
+namespace ppm {
+// The ghost-fill plan of a layout: copy descriptors grouped by destination
+// box, with the exclusive prefix of their zone counts.
+struct Plan {
+  std::vector<FillDesc> desc;
+  std::vector<long long> start;   // ndesc + 1
+  std::vector<int> box_desc;      // nbox + 1: descriptor range of each destination box
+};
+// Rows per strip of the default tile order.
+constexpr int STRIP_ROWS = 32;
+}  // namespace ppm
+
+using namespace ppm;
+
+// ============================================================ context =====
+// A level: box metadata, fill plan, tile lists and their device copies.
+struct ppm_ctx {
+  std::vector<ppm_box> boxes;
+  ppm_layout layout{};
+  std::vector<int64_t> off, foff[3];
+  std::shared_ptr<const Plan> plan;
+  bool plan_hit = false;
+  std::vector<Tile> tilesS, tilesE;
+  std::vector<int> tS_begin, tE_begin;  // nbox + 1
+  int tile = TILE, strip_rows = STRIP_ROWS;
+  long long LS = 0, LE = 0;
+  // device copies
+  DevBox* d_boxes = nullptr;
+  Tile* d_tilesS = nullptr;
+  Tile* d_tilesE = nullptr;
+  FillDesc* d_desc = nullptr;
+  long long* d_start = nullptr;
+  int* d_inv_start = nullptr;
+  int* d_inv_idx = nullptr;
+  void* awork = nullptr;
+  size_t awork_bytes = 0;
+  void* swork = nullptr;
+  size_t swork_bytes = 0;
+  StepConsts* d_consts = nullptr;
+  int* d_flags = nullptr;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  std::string err;
+  // stage timing with HIP events (ppm_profile_enable / ppm_profile_read)
+  struct ProfRec {
+    int tag0, n;
+    std::array<hipEvent_t, STEP_EVENTS> ev;
+  };
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<std::array<hipEvent_t, STEP_EVENTS>> pool;
+
+  // An event set for a record of n events starting at stage tag tag0.
+  ProfRec* begin_rec(int tag0, int n) {
+    std::array<hipEvent_t, STEP_EVENTS> ev{};
+    if (!pool.empty()) {
+      ev = pool.back();
+      pool.pop_back();
+    } else {
+      for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    }
+    recs.push_back(ProfRec{tag0, n, ev});
+    return &recs.back();
+  }
+
+  DevLevel level() const {
+    DevLevel L;
+    L.boxes = d_boxes;
+    L.tilesS = d_tilesS;
+    L.tilesE = d_tilesE;
+    L.desc = d_desc;
+    L.desc_start = d_start;
+    L.consts = d_consts;
+    L.flags = d_flags;
+    L.inv_start = d_inv_start;
+    L.inv_idx = d_inv_idx;
+    L.LS = LS;
+    L.LE = LE;
+    L.tile = tile;
+    return L;
+  }
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PPM_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return PPM_EHIP;
+  }
+};
+

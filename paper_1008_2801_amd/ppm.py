@@ -29,7 +29,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_adjoint_workspace_bytes", "ppm_set_adjoint_workspace", "ppm_hydro_step_adjoint",
            "ppm_set_tiling", "ppm_get_tiling", "ppm_autotune", "ppm_species_offsets",
            "ppm_species_workspace_bytes", "ppm_set_species_workspace", "ppm_fill_species",
-           "ppm_hydro_step_species")
+           "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
+           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -111,6 +112,14 @@ def lib():
         L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
                                              ctypes.POINTER(Params), _vp]
         L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
+        L.ppm_amr_destroy.argtypes = [_vp]
+        L.ppm_amr_last_error.argtypes = [_vp]
+        L.ppm_amr_last_error.restype = ctypes.c_char_p
+        L.ppm_amr_sizes.argtypes = [_vp, _i64p, _i64p, _i64p]
+        L.ppm_amr_fill_fine.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp]
+        L.ppm_amr_step.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp3,
+                                   ctypes.POINTER(Params), ctypes.c_double, _vp, _vp]
         L.ppm_species_offsets.argtypes = [_vp, ctypes.c_int32, _i64p]
         L.ppm_species_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
         L.ppm_species_workspace_bytes.restype = ctypes.c_size_t
@@ -121,7 +130,7 @@ def lib():
         for name in SYMBOLS:
             f = getattr(L, name)
             if name not in ("ppm_last_error", "ppm_workspace_bytes", "ppm_adjoint_workspace_bytes",
-                            "ppm_species_workspace_bytes"):
+                            "ppm_species_workspace_bytes", "ppm_amr_last_error"):
                 f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -383,7 +392,8 @@ class Level:
         self._check(lib().ppm_hydro_step_species(self.ctx, _ptr(U), _ptr(Unew), _ptr(RX), _ptr(RXnew), int(ns), fl,
                                                  float(dt), _ptr(dt_dev), _dp3(*dx), ctypes.byref(p),
                                                  _stream(stream)),
-                    "ppm_hydro_step_species")
+                    "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
+           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step")
 
     def check_status(self, stream=None):
         f = ctypes.c_int32(0)
@@ -406,6 +416,67 @@ class Level:
         e[d] += 1
         o = self.flux_offsets[d]
         return F[int(o[b]):int(o[b + 1])].view(5, e[2], e[1], e[0])
+
+
+class TwoLevel:
+    """Two-level hierarchy (ratio 2, subcycling) on the GPU: a coarse Level,
+    a fine Level whose layout is the refinement of a rectangle of coarse
+    zones with coarse-fine faces, the library's hierarchy object and the
+    six flux arenas the coarse step needs."""
+
+    def __init__(self, coarse_layout, fine_layout):
+        self.coarse = Level(coarse_layout)
+        self.fine = Level(fine_layout)
+        h = ctypes.c_void_p()
+        rc = lib().ppm_amr_create(self.coarse.ctx, self.fine.ctx, ctypes.byref(h))
+        if rc != PPM_OK:
+            msg = lib().ppm_last_error(self.coarse.ctx)
+            raise PPMError(f"ppm_amr_create failed ({rc}): {msg.decode() if msg else ''}")
+        self.amr = h
+        self.Fc = self.coarse.new_fluxes()
+        self.Ff = self.fine.new_fluxes()
+
+    def close(self):
+        if getattr(self, "amr", None):
+            lib().ppm_amr_destroy(self.amr)
+            self.amr = None
+        for lev in (getattr(self, "fine", None), getattr(self, "coarse", None)):
+            if lev is not None:
+                lev.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != PPM_OK:
+            msg = lib().ppm_amr_last_error(self.amr)
+            raise PPMError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def sizes(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().ppm_amr_sizes(self.amr, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+                    "ppm_amr_sizes")
+        return {"interp_zones": a.value, "register_faces": b.value, "covered_zones": c.value}
+
+    def fill_fine(self, Uc_old, Uc_new, half, Uf, stream=None):
+        self._check(lib().ppm_amr_fill_fine(self.amr, _ptr(Uc_old), _ptr(Uc_new), int(half), _ptr(Uf),
+                                            _stream(stream)), "ppm_amr_fill_fine")
+
+    def step(self, Uc, Uc_new, Uf, Uf_tmp, dxc, p, dt=0.0, dt_out=None, stream=None):
+        """One coarse step: Uc -> Uc_new (synchronised), Uf -> Uf (two fine
+        steps through Uf_tmp).  dt = 0: the CFL rule of both levels."""
+        for lev in (self.coarse, self.fine):
+            if lev._work is None or lev._work_prec != p.precision or \
+                    lev._work.numel() < lev.workspace_bytes(p.precision) + 256:
+                lev.ensure_workspace(p.precision)
+        fc = (_vp * 3)(*[f.data_ptr() for f in self.Fc])
+        ff = (_vp * 3)(*[f.data_ptr() for f in self.Ff])
+        self._check(lib().ppm_amr_step(self.amr, _ptr(Uc), _ptr(Uc_new), _ptr(Uf), _ptr(Uf_tmp), fc, ff,
+                                       _dp3(*dxc), ctypes.byref(p), float(dt), _ptr(dt_out), _stream(stream)),
+                    "ppm_amr_step")
 
 
 class Graph:
