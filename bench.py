@@ -306,6 +306,90 @@ def species_costs(wl, ns, steps, warmup, precision=0):
     return out
 
 
+def amr_costs(n, cbox, fbox, steps, warmup, precision=0):
+    """One coarse step of the two-level hierarchy (inner 12.5% refined by 2,
+    so the fine level has as many zones as the coarse one) against the
+    single-level steps it contains.  The paper's overhead measure compares
+    it with three single-level coarse steps; the second measure compares it
+    with the level steps actually run (one coarse and two fine)."""
+    import torch
+    from paper_1008_2801_amd import inputs as I
+    from paper_1008_2801_amd import ppm as P
+    t = I.amr_cfg2(n, cbox=cbox, fbox=fbox)
+    H = P.TwoLevel(t.coarse.layout, t.fine.layout)
+    p = P.params(gamma=t.coarse.gamma, precision=precision)
+    for lev in (H.coarse, H.fine):
+        lev.ensure_workspace(precision)
+    Uc0 = torch.from_numpy(t.coarse.arena).to("cuda")
+    Uf0 = torch.from_numpy(t.fine.arena).to("cuda")
+    for lev, U in ((H.coarse, Uc0), (H.fine, Uf0)):
+        Ut = U.clone()
+        if lev is H.coarse:
+            lev.fill_boundary(Ut)
+        else:
+            Uc = Uc0.clone()
+            H.coarse.fill_boundary(Uc)
+            H.fill_fine(Uc, Uc, 0, Ut)
+            del Uc
+        lev.autotune(Ut, t.coarse.dx if lev is H.coarse else t.fine.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)
+        del Ut
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def timed(fn, nst, nwarm):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for k in range(nwarm + nst):
+            if k == nwarm:
+                e0.record()
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / nst
+
+    # single-level steps: the coarse level alone (periodic) and the fine
+    # level alone (its coarse-fine ghosts filled once, then left as they are)
+    st = {"Uc": Uc0.clone(), "Vc": H.coarse.new_state()}
+
+    def coarse_single():
+        H.coarse.fill_boundary(st["Uc"])
+        H.coarse.compute_dt(st["Uc"], t.coarse.dx, p, out=dtv)
+        H.coarse.hydro_step(st["Uc"], st["Vc"], t.coarse.dx, p, dt_dev=dtv)
+        st["Uc"], st["Vc"] = st["Vc"], st["Uc"]
+    t_c = min(timed(coarse_single, steps, warmup) for _ in range(2))
+    Uc = Uc0.clone()
+    H.coarse.fill_boundary(Uc)
+    fs = {"Uf": Uf0.clone(), "Vf": H.fine.new_state()}
+    H.fill_fine(Uc, Uc, 0, fs["Uf"])
+    H.fill_fine(Uc, Uc, 0, fs["Vf"])
+
+    def fine_single():
+        H.fine.fill_boundary(fs["Uf"])
+        H.fine.compute_dt(fs["Uf"], t.fine.dx, p, out=dtv)
+        H.fine.hydro_step(fs["Uf"], fs["Vf"], t.fine.dx, p, dt_dev=dtv)
+        fs["Uf"], fs["Vf"] = fs["Vf"], fs["Uf"]
+    t_f = min(timed(fine_single, steps, warmup) for _ in range(2))
+    del Uc, fs, st
+    # the hierarchy
+    am = {"Uc": Uc0.clone(), "Vc": H.coarse.new_state(), "Uf": Uf0.clone(), "Tf": H.fine.new_state()}
+
+    def amr_step():
+        H.step(am["Uc"], am["Vc"], am["Uf"], am["Tf"], t.coarse.dx, p)
+        am["Uc"], am["Vc"] = am["Vc"], am["Uc"]
+    t_a = min(timed(amr_step, steps, warmup) for _ in range(2))
+    flags = H.coarse.check_status() | H.fine.check_status()
+    sizes = H.sizes()
+    zc, zf = t.coarse.layout.valid_zones(), t.fine.layout.valid_zones()
+    H.close()
+    del am, Uc0, Uf0, H
+    torch.cuda.empty_cache()
+    return {"coarse_zones": zc, "fine_zones": zf, "coarse_boxes": t.coarse.layout.nbox,
+            "fine_boxes": t.fine.layout.nbox, "ms_single_level_coarse_step": t_c,
+            "ms_single_level_fine_step": t_f, "ms_two_level_coarse_step": t_a,
+            "overhead_vs_3_coarse_steps": t_a / (3.0 * t_c) - 1.0,
+            "overhead_vs_level_steps": t_a / (t_c + 2.0 * t_f) - 1.0,
+            "zone_updates_per_s": (zc + 2 * zf) / (t_a / 1e3), "sizes": sizes, "flags": flags}
+
+
 def copy_bandwidth(gib=2, reps=5):
     """Measured HBM bandwidth of a plain device-to-device copy (bytes read +
     written per second), the practical ceiling next to the 8 TB/s spec."""
@@ -364,6 +448,8 @@ def main():
                     help="skip the 512-box batched / per-box / graph measurements")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only measure the adjoint/forward cost on the 128^3 differentiation workload")
+    ap.add_argument("--amr-only", action="store_true",
+                    help="with --no-extras: still measure the two-level hierarchy")
     ap.add_argument("--species-only", action="store_true",
                     help="with --no-extras: still measure the passive-species step")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -537,6 +623,15 @@ def main():
         rt["adjoint"] = a5
         out["rayleigh_taylor"] = rt
         del w5
+    if not args.no_extras or args.amr_only:
+        print("bench: two-level hierarchy (256^3 coarse, inner 12.5% refined)", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        am = {"workload": "cfg2's state on 256^3 coarse zones with the inner 12.5% of the domain refined by 2 "
+                          "(256^3 fine zones); one coarse step = coarse step + two fine steps + fill, "
+                          "interpolation, flux register, reflux, average down; 5 timed steps",
+              "one_box_per_level": amr_costs(256, 256, 256, 5, 1),
+              "boxes_of_64": amr_costs(256, 64, 64, 5, 1)}
+        out["amr"] = am
     if not args.no_extras or args.species_only:
         from paper_1008_2801_amd import inputs as I
         print("bench: passive species on the 256^3 workload", file=sys.stderr, flush=True)
