@@ -20,7 +20,7 @@ _SRC = os.path.join(_HERE, "ppm_oracle.cpp")
 _LIBDIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_LIBDIR, "liboracle.so")
 NG = 4
-BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_COARSE_FINE = 0, 1, 2, 3
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_COARSE_FINE, BC_INFLOW = 0, 1, 2, 3, 4
 FLAG_NONPHYS, FLAG_FLOOR = 1, 2
 STAGES = ("prim", "flatten", "trace", "riemann1", "transverse1", "riemann2",
           "transverse2", "riemann3", "update")
@@ -78,6 +78,9 @@ def lib():
         L.oracle_step_species.restype = ctypes.c_int
         L.oracle_step_species.argtypes = [_dp, _dp, ctypes.c_int, _ip, _ip, _ip, ctypes.c_double, _dp,
                                           ctypes.POINTER(OParams), _ip, _dp, _dp]
+        L.oracle_fill_inflow.restype = ctypes.c_int
+        L.oracle_fill_inflow.argtypes = [ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _dp,
+                                         ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_dp)]
         L.oracle_fill_scalars.restype = ctypes.c_int
         L.oracle_fill_scalars.argtypes = [ctypes.c_int, _ip, _ip, _ip, _ip, _ip, _dp,
                                           ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
@@ -250,12 +253,15 @@ def trace(aL, aR, a6, cell, d, dtdx, p):
     return qp, qm, fl
 
 
-def fill(boxes, domain, bc, states):
+def fill(boxes, domain, bc, states, inflow=None):
     """Ghost fill (O1) of a level, in place.
 
     boxes: list of (lo, hi) inclusive global index triples; domain: (lo, hi);
     bc: six face codes (x-lo, x-hi, y-lo, y-hi, z-lo, z-hi); states: list of
-    per-box arrays (5, nz+8, ny+8, nx+8), modified in place.
+    per-box arrays (5, nz+8, ny+8, nx+8), modified in place.  inflow: for a
+    layout with an inflow face, {face: array (5, E_t2, E_t1)} of the
+    prescribed conserved state over the domain's extents of the two other
+    axes (t1 < t2).
     """
     nb = len(boxes)
     lo = (ctypes.c_int * (3 * nb))(*[int(v) for b in boxes for v in b[0]])
@@ -263,8 +269,14 @@ def fill(boxes, domain, bc, states):
     sizes = [s.size for s in states]
     off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
     arena = np.concatenate([s.ravel() for s in states])
-    rc = lib().oracle_fill(nb, lo, hi, _i3(domain[0]), _i3(domain[1]), (ctypes.c_int * 6)(*bc),
-                           _d(arena), off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+    if inflow:
+        keep = {f: np.ascontiguousarray(a, dtype=np.float64) for f, a in inflow.items()}
+        ptrs = (_dp * 6)(*[_d(keep[f]) if f in keep else None for f in range(6)])
+        rc = lib().oracle_fill_inflow(nb, lo, hi, _i3(domain[0]), _i3(domain[1]), (ctypes.c_int * 6)(*bc),
+                                      _d(arena), off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)), ptrs)
+    else:
+        rc = lib().oracle_fill(nb, lo, hi, _i3(domain[0]), _i3(domain[1]), (ctypes.c_int * 6)(*bc),
+                               _d(arena), off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
     if rc != 0:
         raise ValueError("oracle_fill: ghost image without an owning box")
     for s, o, z in zip(states, off, sizes):
@@ -320,14 +332,15 @@ def advance_species(boxes, domain, bc, states, rx, nsteps, dx, p, dt=None):
     return states, rx, dts, flags
 
 
-def advance(boxes, domain, bc, states, nsteps, dx, p, dt=None, fluxes=False):
+def advance(boxes, domain, bc, states, nsteps, dx, p, dt=None, fluxes=False, inflow=None):
     """Run nsteps full steps of a level: fill, dt = cfl / max signal speed
     (unless dt is given), step every box.  Returns (states, dts, flags, F)
-    where F holds the last step's per-box fluxes if requested."""
+    where F holds the last step's per-box fluxes if requested.  inflow: the
+    inflow-face data of fill()."""
     states = [s.copy() for s in states]
     dts, flags, F = [], 0, None
     for _ in range(nsteps):
-        fill(boxes, domain, bc, states)
+        fill(boxes, domain, bc, states, inflow=inflow)
         if dt is None:
             s = 0.0
             for U in states:

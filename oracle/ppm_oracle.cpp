@@ -160,7 +160,8 @@ struct OParams {
 enum { FLAG_NONPHYS = 1, FLAG_FLOOR = 2 };
 // BC_COARSE_FINE: the face borders a coarser level; ghost zones beyond it
 // are filled by interpolation from that level, not by the level's own fill.
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_COARSE_FINE = 3 };
+// BC_INFLOW: ghost zones beyond the face hold a prescribed state (inflow).
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_COARSE_FINE = 3, BC_INFLOW = 4 };
 const int NG = 4;  // ghost width: flattening reaches 3 zones past a traced zone
 
 // Per-step constants in the reconstruction scalar.  They are formed in FP64
@@ -1106,14 +1107,27 @@ int oracle_trace(const double aL[5], const double aR[5], const double a6[5], con
 // zone that owns its image: periodic axes wrap, outflow axes clamp to the
 // nearest valid zone, reflecting axes mirror about the wall with the normal
 // momentum negated.  Ghost zones beyond a coarse-fine face are left as they
-// are (the two-level advance interpolates them).  Returns 0, or -1 if an
-// image has no owner.
+// are (the two-level advance interpolates them).  Ghost zones beyond an
+// inflow face (bc 4, at most one per layout) take the prescribed state of
+// that face, inflow[face]: 5 components over the domain's extents of the two
+// other axes t1 < t2, order [c][t2][t1], at the image of the zone's
+// transverse coordinates under those axes' rules (momentum signs as for a
+// copy).  Returns 0, or -1 if an image has no owner or inflow data are
+// missing.
 static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
-                      const int bc[6], double* arena, const long long* off, int ncomp, bool momentum);
+                      const int bc[6], double* arena, const long long* off, int ncomp, bool momentum,
+                      const double* const* inflow = nullptr);
 
 int oracle_fill(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
                 const int bc[6], double* arena, const long long* off) {
   return fill_level(nbox, lo, hi, dlo, dhi, bc, arena, off, 5, true);
+}
+
+// The state fill with inflow faces: inflow[6] (null entries for the faces
+// that are not inflow faces).
+int oracle_fill_inflow(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
+                       const int bc[6], double* arena, const long long* off, const double* const* inflow) {
+  return fill_level(nbox, lo, hi, dlo, dhi, bc, arena, off, 5, true, inflow);
 }
 
 // The same fill for ncomp scalar fields per box (passive species): no
@@ -1125,7 +1139,15 @@ int oracle_fill_scalars(int nbox, const int* lo, const int* hi, const int dlo[3]
 }
 
 static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], const int dhi[3],
-                      const int bc[6], double* arena, const long long* off, int ncomp, bool momentum) {
+                      const int bc[6], double* arena, const long long* off, int ncomp, bool momentum,
+                      const double* const* inflow) {
+  int ninflow = 0;
+  for (int f = 0; f < 6; ++f)
+    if (bc[f] == BC_INFLOW) {
+      ++ninflow;
+      if (!inflow || !inflow[f] || ncomp != 5) return -1;
+    }
+  if (ninflow > 1) return -1;
   int L[3];
   for (int d = 0; d < 3; ++d) L[d] = dhi[d] - dlo[d] + 1;
   // owner of every valid zone of the domain, painted box by box
@@ -1147,6 +1169,7 @@ static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], 
       if (x[0] >= 0 && x[0] < n[0] && x[1] >= 0 && x[1] < n[1] && x[2] >= 0 && x[2] < n[2]) return;
       int g[3];
       double sgn[3] = {1, 1, 1};  // momentum components 1..3
+      int inface = -1;
       for (int d = 0; d < 3; ++d) {
         const int v = lo[3 * b + d] + x[d] - dlo[d];
         if ((v < 0 && bc[2 * d] == BC_COARSE_FINE) || (v >= L[d] && bc[2 * d + 1] == BC_COARSE_FINE)) return;
@@ -1155,7 +1178,10 @@ static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], 
         int v = lo[3 * b + d] + x[d] - dlo[d];  // domain-relative index
         if (v < 0 || v >= L[d]) {
           const int face = (v < 0) ? 2 * d : 2 * d + 1;
-          if (bc[face] == BC_PERIODIC) {
+          if (bc[face] == BC_INFLOW) {
+            inface = face;
+            v = 0;
+          } else if (bc[face] == BC_PERIODIC) {
             v = ((v % L[d]) + L[d]) % L[d];
           } else if (bc[face] == BC_OUTFLOW) {
             v = (v < 0) ? 0 : L[d] - 1;
@@ -1165,6 +1191,16 @@ static int fill_level(int nbox, const int* lo, const int* hi, const int dlo[3], 
           }
         }
         g[d] = v;
+      }
+      if (inface >= 0) {
+        const int d = inface / 2, t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+        const double* src = inflow[inface];
+        for (int c = 0; c < 5; ++c) {
+          const double v = src[((size_t)c * L[t2] + g[t2]) * L[t1] + g[t1]];
+          const double sg = (c >= 1 && c <= 3) ? sgn[c - 1] : 1.0;
+          dst[(((size_t)c * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)] = sg * v;
+        }
+        return;
       }
       const int ob = owner[((size_t)g[2] * L[1] + g[1]) * L[0] + g[0]];
       if (ob < 0) { bad = true; return; }

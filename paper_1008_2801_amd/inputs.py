@@ -447,3 +447,41 @@ def amr_random(n=16, cbox=8, fbox=8, seed=21, grav=(0.0, 0.0, 0.0)):
         return (rj * (1.0 + 0.3 * S[0](x, y, z)), 0.5 * S[1](x, y, z), 0.5 * S[2](x, y, z),
                 0.5 * S[3](x, y, z), pj * (1.0 + 0.3 * S[4](x, y, z)))
     return two_level(n, cbox, fbox, prim, 1.4, "amr_random", grav=grav)
+
+
+# --------------------------------------------------------- inflow jet ------
+BC_INFLOW = 4
+
+
+def jet_inflow_velocity(x, cs):
+    """Normal velocity of the jet at the inflow face (x in cm): the paper's
+    tanh profile, peak Mach number 0.1 of the gas at rest."""
+    return cs * (0.01 + 0.045 * (np.tanh(100.0 * (x - 0.4)) + np.tanh(100.0 * (0.6 - x))))
+
+
+def jet(n=128, nz=4, rho0=1.225e-3, p0=1.01325e6, gamma=1.4):
+    """The inflowing jet (compressible side of the paper's end-to-end
+    test): a 1 cm x 1 cm domain of n^2 zones, nz zones thick and periodic in
+    z (a planar problem); air at rest, rho0 g/cm^3 and p0 dyn/cm^2 (sea-level
+    values: the paper says only 'terrestrial'); the face y = 0 is an inflow
+    face with density rho0/2, pressure p0 and normal velocity
+    jet_inflow_velocity(x, c_s), c_s = sqrt(gamma p0 / rho0) of the gas at
+    rest; outflow at the other x and y faces; run to t = 300 us.
+    meta['inflow'] = {2: (5, nz, n) conserved inflow state over the y-lo
+    face, order [c][z][x]}."""
+    lay = single_box((n, n, nz), bc=(BC_OUTFLOW, BC_OUTFLOW, BC_INFLOW, BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC))
+    h = (1.0 / n,) * 3
+    cs = math.sqrt(gamma * p0 / rho0)
+
+    def prim(x, y, z):
+        return (rho0, 0.0, 0.0, 0.0, p0)
+    arena = _fill_state(lay, h, gamma, prim)
+    x = (np.arange(n) + 0.5) * h[0]
+    v = jet_inflow_velocity(x, cs)
+    rin = 0.5 * rho0
+    face = np.zeros((5, nz, n))
+    face[0] = rin
+    face[2] = rin * v[None, :]
+    face[4] = p0 / (gamma - 1.0) + 0.5 * rin * (v * v)[None, :]
+    return Workload("jet", lay, arena, h, gamma, 0,
+                    meta={"inflow": {2: face}, "t_end": 3.0e-4, "sound_speed": cs, "rho0": rho0, "p0": p0})

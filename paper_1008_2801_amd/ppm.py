@@ -392,8 +392,7 @@ class Level:
         self._check(lib().ppm_hydro_step_species(self.ctx, _ptr(U), _ptr(Unew), _ptr(RX), _ptr(RXnew), int(ns), fl,
                                                  float(dt), _ptr(dt_dev), _dp3(*dx), ctypes.byref(p),
                                                  _stream(stream)),
-                    "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
-           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step")
+                    "ppm_hydro_step_species")
 
     def check_status(self, stream=None):
         f = ctypes.c_int32(0)
