@@ -55,8 +55,10 @@ enum {
 };
 
 enum { PPM_BC_PERIODIC = 0, PPM_BC_OUTFLOW = 1, PPM_BC_REFLECT = 2,
-       PPM_BC_COARSE_FINE = 3 /* the face borders a coarser level: ghost zones beyond it are left to
-                                 the two-level interpolation (ppm_amr_fill_fine), not filled */ };
+       PPM_BC_COARSE_FINE = 3, /* the face borders a coarser level: ghost zones beyond it are left to
+                                  the two-level interpolation (ppm_amr_fill_fine), not filled */
+       PPM_BC_INFLOW = 4 /* ghost zones beyond the face take a prescribed state (ppm_set_inflow);
+                            at most one inflow face per layout */ };
 
 /* status flags accumulated on the device */
 enum { PPM_FLAG_NONPHYS = 1, /* rho <= 0, p <= 0 or a non-finite value in an input state */
@@ -124,6 +126,18 @@ int ppm_set_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
  * read, ghost zones written.  mode: PPM_LAUNCH_BATCHED (one launch) or
  * PPM_LAUNCH_PER_BOX (one launch per destination box). */
 int ppm_fill_boundary(ppm_ctx* ctx, double* U, int32_t mode, void* stream);
+
+/* Prescribed state of an inflow face (the inflowing jet of the paper's
+ * Sec. 4 enters through such a face): `state` is a device array of 5
+ * conserved components over the domain's extents of the two axes t1 < t2
+ * other than the face normal, order [c][t2][t1], owned by the caller and
+ * read by every later fill.  A ghost zone beyond the face takes the state
+ * at the image of its transverse coordinates under those axes' own rules
+ * (periodic wrap, outflow clamp, reflecting mirror with the momentum sign).
+ * ppm_fill_boundary returns PPM_EINVAL while an inflow face has no state;
+ * species fills reject layouts with an inflow face.  PPM_EINVAL if `face`
+ * is not an inflow face of the layout. */
+int ppm_set_inflow(ppm_ctx* ctx, int32_t face, const double* state);
 
 /* O11 -- CFL rule.  Writes to dt_dev[0] the time step
  *   dt = cfl / max over valid zones and axes of (|u_d| + c) / h_d

@@ -60,8 +60,11 @@ std::string validate_layout(const ppm_layout& L) {
     const bool pl = L.bc[2 * d] == PPM_BC_PERIODIC, ph = L.bc[2 * d + 1] == PPM_BC_PERIODIC;
     if (pl != ph) return "layout: a periodic axis needs both faces periodic";
     for (int s = 0; s < 2; ++s)
-      if (L.bc[2 * d + s] < 0 || L.bc[2 * d + s] > PPM_BC_COARSE_FINE) return "layout: unknown boundary code";
+      if (L.bc[2 * d + s] < 0 || L.bc[2 * d + s] > PPM_BC_INFLOW) return "layout: unknown boundary code";
   }
+  int ninflow = 0;
+  for (int f = 0; f < 6; ++f) ninflow += L.bc[f] == PPM_BC_INFLOW;
+  if (ninflow > 1) return "layout: at most one inflow face";
   long long vol = 0;
   for (int b = 0; b < L.nbox; ++b) {
     long long v = 1;
@@ -173,7 +176,7 @@ Plan build_plan(const ppm_layout& L, bool brute) {
           if (sx == 0 && sy == 0 && sz == 0) continue;
           const int s[3] = {sx, sy, sz};
           // per axis: up to 3 pieces [a, b] in global coordinates + their map
-          struct Piece { int lo, hi, a, c, refl; };
+          struct Piece { int lo, hi, a, c, refl, inflow; };  // inflow: face index or -1
           std::vector<Piece> pcs[3];
           for (int d = 0; d < 3; ++d) {
             int l, h;
@@ -187,18 +190,20 @@ Plan build_plan(const ppm_layout& L, bool brute) {
             // two-level advance interpolates those ghost zones)
             if (cuts[0] < cuts[1] && L.bc[2 * d] != PPM_BC_COARSE_FINE) {
               const int bc = L.bc[2 * d];
-              Piece pc{cuts[0], std::min(cuts[1] - 1, h), 1, 0, 0};
+              Piece pc{cuts[0], std::min(cuts[1] - 1, h), 1, 0, 0, -1};
               if (bc == PPM_BC_PERIODIC) { pc.a = 1; pc.c = ext[d]; }
               else if (bc == PPM_BC_OUTFLOW) { pc.a = 0; pc.c = dlo[d]; }
+              else if (bc == PPM_BC_INFLOW) { pc.a = 0; pc.c = dlo[d]; pc.inflow = 2 * d; }
               else { pc.a = -1; pc.c = 2 * dlo[d] - 1; pc.refl = 1; }
               pcs[d].push_back(pc);
             }
-            if (cuts[1] < cuts[2]) pcs[d].push_back(Piece{cuts[1], cuts[2] - 1, 1, 0, 0});
+            if (cuts[1] < cuts[2]) pcs[d].push_back(Piece{cuts[1], cuts[2] - 1, 1, 0, 0, -1});
             if (cuts[2] < cuts[3] && L.bc[2 * d + 1] != PPM_BC_COARSE_FINE) {
               const int bc = L.bc[2 * d + 1];
-              Piece pc{std::max(cuts[2], l), cuts[3] - 1, 1, 0, 0};
+              Piece pc{std::max(cuts[2], l), cuts[3] - 1, 1, 0, 0, -1};
               if (bc == PPM_BC_PERIODIC) { pc.a = 1; pc.c = -ext[d]; }
               else if (bc == PPM_BC_OUTFLOW) { pc.a = 0; pc.c = dhi[d]; }
+              else if (bc == PPM_BC_INFLOW) { pc.a = 0; pc.c = dhi[d]; pc.inflow = 2 * d + 1; }
               else { pc.a = -1; pc.c = 2 * dhi[d] + 1; pc.refl = 1; }
               pcs[d].push_back(pc);
             }
@@ -207,6 +212,35 @@ Plan build_plan(const ppm_layout& L, bool brute) {
             for (const Piece& py : pcs[1])
               for (const Piece& pz : pcs[2]) {
                 const Piece* pp[3] = {&px, &py, &pz};
+                int inface = -1;
+                for (int d = 0; d < 3; ++d)
+                  if (pp[d]->inflow >= 0) inface = pp[d]->inflow;
+                if (inface >= 0) {
+                  // beyond the inflow face: the face's prescribed state at the
+                  // domain-relative image of the transverse coordinates
+                  FillDesc D;
+                  D.dst = b;
+                  D.src = -1 - inface;
+                  D.sign = 0;
+                  long long cnt = 1;
+                  for (int d = 0; d < 3; ++d) {
+                    const Piece& q = *pp[d];
+                    D.lo[d] = q.lo - B.lo[d];
+                    D.hi[d] = q.hi - B.lo[d];
+                    if (d == inface / 2) {
+                      D.a[d] = 0;
+                      D.c[d] = 0;
+                    } else {
+                      D.a[d] = q.a;
+                      D.c[d] = q.a * B.lo[d] + q.c - dlo[d];
+                      if (q.refl) D.sign |= 1 << d;
+                    }
+                    cnt *= (q.hi - q.lo + 1);
+                  }
+                  D.count = (int)cnt;
+                  P.desc.push_back(D);
+                  continue;
+                }
                 IBox img;
                 for (int d = 0; d < 3; ++d) {
                   const Piece& q = *pp[d];
@@ -417,6 +451,7 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
     std::vector<unsigned long long> cmask(desc.size(), 0);  // bit per class
     for (size_t k = 0; k < desc.size(); ++k) {
       const FillDesc& D = desc[k];
+      if (D.src < 0) continue;  // prescribed inflow state: no adjoint flows back
       const int* ns = layout->boxes[D.src].lo;
       unsigned axm[3];
       for (int d = 0; d < 3; ++d) {
@@ -509,9 +544,20 @@ int ppm_set_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
   return PPM_OK;
 }
 
+int ppm_set_inflow(ppm_ctx* ctx, int32_t face, const double* state) {
+  if (!ctx) return PPM_EINVAL;
+  if (face < 0 || face > 5 || ctx->layout.bc[face] != PPM_BC_INFLOW)
+    return ctx->fail(PPM_EINVAL, "set_inflow: the face is not an inflow face of the layout");
+  ctx->inflow[face] = state;
+  return PPM_OK;
+}
+
 int ppm_fill_boundary(ppm_ctx* ctx, double* U, int32_t mode, void* stream) {
   if (!ctx) return PPM_EINVAL;
   if (!U) return ctx->fail(PPM_EINVAL, "fill: null state");
+  for (int f = 0; f < 6; ++f)
+    if (ctx->layout.bc[f] == PPM_BC_INFLOW && !ctx->inflow[f])
+      return ctx->fail(PPM_EINVAL, "fill: inflow face without its state (ppm_set_inflow)");
   if (mode != PPM_LAUNCH_BATCHED && mode != PPM_LAUNCH_PER_BOX) return ctx->fail(PPM_EINVAL, "fill: bad mode");
   hipStream_t s = (hipStream_t)stream;
   const DevLevel L = ctx->level();
@@ -659,6 +705,9 @@ int ppm_set_species_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
 
 int ppm_fill_species(ppm_ctx* ctx, double* RX, int32_t ns, int32_t mode, void* stream) {
   if (!ctx) return PPM_EINVAL;
+  for (int f = 0; f < 6; ++f)
+    if (ctx->layout.bc[f] == PPM_BC_INFLOW)
+      return ctx->fail(PPM_EINVAL, "fill_species: species on a layout with an inflow face are not supported");
   if (!RX) return ctx->fail(PPM_EINVAL, "fill_species: null arena");
   if (ns < 1 || ns > PPM_MAX_SPECIES) return ctx->fail(PPM_EINVAL, "fill_species: ns must be in [1, PPM_MAX_SPECIES]");
   if (mode != PPM_LAUNCH_BATCHED && mode != PPM_LAUNCH_PER_BOX) return ctx->fail(PPM_EINVAL, "fill_species: bad mode");
@@ -942,7 +991,9 @@ int ppm_plan_build(const ppm_layout* layout, int32_t brute, int32_t max, int32_t
 
 int ppm_fill_boundary_host(const ppm_layout* layout, double* U) {
   if (!layout || !U) return PPM_EINVAL;
-  const std::string m = validate_layout(*layout);
+  std::string m = validate_layout(*layout);
+  for (int f = 0; m.empty() && f < 6; ++f)
+    if (layout->bc[f] == PPM_BC_INFLOW) m = "inflow faces need device state (ppm_set_inflow)";
   if (!m.empty()) {
     std::fprintf(stderr, "ppm_fill_boundary_host: %s\n", m.c_str());
     return PPM_EINVAL;

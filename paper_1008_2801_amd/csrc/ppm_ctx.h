@@ -49,6 +49,7 @@ struct ppm_ctx {
   size_t awork_bytes = 0;
   void* swork = nullptr;
   size_t swork_bytes = 0;
+  const double* inflow[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // ppm_set_inflow
   StepConsts* d_consts = nullptr;
   int* d_flags = nullptr;
   void* work = nullptr;
@@ -91,6 +92,8 @@ struct ppm_ctx {
     L.LS = LS;
     L.LE = LE;
     L.tile = tile;
+    for (int f = 0; f < 6; ++f) L.inflow.p[f] = inflow[f];
+    for (int d = 0; d < 3; ++d) L.inflow.ext[d] = layout.domain.hi[d] - layout.domain.lo[d] + 1;
     return L;
   }
   int fail(int code, const std::string& msg) {

@@ -35,7 +35,9 @@ struct Tile {
 
 // One copy of the ghost-fill plan: the dst-box-local region [lo, hi] takes
 // its values from src-box-local zone a*x + c (per axis, a in {1, -1, 0}),
-// negating the momentum components flagged in sign.
+// negating the momentum components flagged in sign.  src < 0: the region
+// lies beyond inflow face -1 - src and takes the face's prescribed state at
+// domain-relative transverse index a*x + c (a = 0 along the face normal).
 struct FillDesc {
   int dst, src;
   int lo[3], hi[3];
@@ -68,6 +70,14 @@ constexpr int E_F3 = E_F2 + 30;     // + d*5 + m
 constexpr int E_PLANES = E_F3 + 15;
 constexpr int P_PLANES = 6;         // rho, u, v, w, p, c
 
+// Prescribed ghost states of inflow faces: p[face] (null if the face is not
+// an inflow face) holds 5 conserved components over the domain's extents of
+// the two other axes t1 < t2, order [c][t2][t1]; ext: the domain extents.
+struct InflowView {
+  const double* p[6];
+  int ext[3];
+};
+
 // Launch-side views of the context's device data.
 struct DevLevel {
   const DevBox* boxes;
@@ -81,6 +91,7 @@ struct DevLevel {
   const int* inv_idx;
   long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
   int tile;            // zones per tile of the tile lists (threads per workgroup)
+  InflowView inflow;
 };
 
 }  // namespace ppm

@@ -485,7 +485,7 @@ __global__ void __launch_bounds__(64) k_finish_dt(double* dt_dev, double cfl) {
 __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restrict__ desc,
                                                const long long* __restrict__ start, int d0, int d1,
                                                long long z0, long long z1,
-                                               const DevBox* __restrict__ boxes, double* U) {
+                                               const DevBox* __restrict__ boxes, double* U, InflowView inf) {
   const long long gidx = z0 + (long long)blockIdx.x * FILL_THREADS + threadIdx.x;
   if (gidx >= z1) return;
   int lo = d0, hi = d1 - 1;
@@ -500,15 +500,29 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restric
   const int y = D.lo[1] + (int)((l / ex) % ey);
   const int zz = D.lo[2] + (int)(l / ((long long)ex * ey));
   const int sx = D.a[0] * x + D.c[0], sy = D.a[1] * y + D.c[1], sz = D.a[2] * zz + D.c[2];
-  const DevBox Bd = boxes[D.dst], Bs = boxes[D.src];
+  const DevBox Bd = boxes[D.dst];
   const int dN0 = Bd.n[0] + 2 * NG, dN1 = Bd.n[1] + 2 * NG, dN2 = Bd.n[2] + 2 * NG;
-  const int sN0 = Bs.n[0] + 2 * NG, sN1 = Bs.n[1] + 2 * NG, sN2 = Bs.n[2] + 2 * NG;
-  const long long dNS = (long long)dN0 * dN1 * dN2, sNS = (long long)sN0 * sN1 * sN2;
+  const long long dNS = (long long)dN0 * dN1 * dN2;
   const long long di = Bd.soff + ((long long)(zz + NG) * dN1 + (y + NG)) * dN0 + (x + NG);
-  const long long si = Bs.soff + ((long long)(sz + NG) * sN1 + (sy + NG)) * sN0 + (sx + NG);
+  const double* src;
+  long long si, sNS;
+  if (D.src < 0) {  // prescribed state of an inflow face
+    const int f = -1 - D.src, d = f >> 1;
+    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int s3[3] = {sx, sy, sz};
+    src = inf.p[f];
+    sNS = (long long)inf.ext[t1] * inf.ext[t2];
+    si = (long long)s3[t2] * inf.ext[t1] + s3[t1];
+  } else {
+    const DevBox Bs = boxes[D.src];
+    const int sN0 = Bs.n[0] + 2 * NG, sN1 = Bs.n[1] + 2 * NG, sN2 = Bs.n[2] + 2 * NG;
+    src = U;
+    sNS = (long long)sN0 * sN1 * sN2;
+    si = Bs.soff + ((long long)(sz + NG) * sN1 + (sy + NG)) * sN0 + (sx + NG);
+  }
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const double v = U[si + c * sNS];
+    const double v = src[si + c * sNS];
     const bool neg = c >= 1 && c <= 3 && ((D.sign >> (c - 1)) & 1);
     U[di + c * dNS] = neg ? -v : v;
   }
@@ -568,7 +582,7 @@ hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_en
   const long long nz = zone_end - zone_begin;
   const unsigned grid = (unsigned)((nz + FILL_THREADS - 1) / FILL_THREADS);
   hipLaunchKernelGGL(k_fill, dim3(grid), dim3(FILL_THREADS), 0, s, L.desc, L.desc_start, desc_begin, desc_end,
-                     zone_begin, zone_end, L.boxes, U);
+                     zone_begin, zone_end, L.boxes, U, L.inflow);
   return hipGetLastError();
 }
 

@@ -324,6 +324,7 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill_scalars(const FillDesc* _
     if (start[mid] <= gidx) lo = mid; else hi = mid - 1;
   }
   const FillDesc D = desc[lo];
+  if (D.src < 0) return;  // inflow faces carry no species (rejected on the host)
   const long long l = gidx - start[lo];
   const int ex = D.hi[0] - D.lo[0] + 1, ey = D.hi[1] - D.lo[1] + 1;
   const int x = D.lo[0] + (int)(l % ex);

@@ -30,7 +30,7 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_set_tiling", "ppm_get_tiling", "ppm_autotune", "ppm_species_offsets",
            "ppm_species_workspace_bytes", "ppm_set_species_workspace", "ppm_fill_species",
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
-           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step")
+           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -112,6 +112,7 @@ def lib():
         L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
                                              ctypes.POINTER(Params), _vp]
         L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.ppm_amr_destroy.argtypes = [_vp]
         L.ppm_amr_last_error.argtypes = [_vp]
@@ -267,6 +268,15 @@ class Level:
         import torch
         return [torch.zeros(int(self.flux_offsets[d][-1]), dtype=torch.float64, device=self.device)
                 for d in range(3)]
+
+    def set_inflow(self, face, state):
+        """Prescribed conserved state of an inflow face: a float64 CUDA
+        tensor (5, E_t2, E_t1) over the domain's transverse extents (kept
+        alive by the level)."""
+        if not hasattr(self, "_inflow"):
+            self._inflow = {}
+        self._inflow[int(face)] = state
+        self._check(lib().ppm_set_inflow(self.ctx, int(face), _ptr(state)), "ppm_set_inflow")
 
     def fill_boundary(self, U, mode=BATCHED, stream=None):
         self._check(lib().ppm_fill_boundary(self.ctx, _ptr(U), int(mode), _stream(stream)), "ppm_fill_boundary")
