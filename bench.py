@@ -390,6 +390,58 @@ def amr_costs(n, cbox, fbox, steps, warmup, precision=0):
             "zone_updates_per_s": (zc + 2 * zf) / (t_a / 1e3), "sizes": sizes, "flags": flags}
 
 
+def jet_costs(n=256, nz=4, graph_steps=250):
+    """The inflowing jet on n^2 x nz zones to t = 300 us: the eager loop
+    (fill, CFL dt read back every step, step) timed over the whole run, and
+    HIP graphs of graph_steps steps (dt from the CFL rule on the device)."""
+    import numpy as np
+    import torch
+    from paper_1008_2801_amd import inputs as I
+    from paper_1008_2801_amd import ppm as P
+    wl = I.jet(n, nz=nz)
+    lev = P.Level(wl.layout)
+    lev.set_inflow(2, torch.from_numpy(np.ascontiguousarray(wl.meta["inflow"][2])).to("cuda"))
+    p = P.params(gamma=wl.gamma)
+    lev.ensure_workspace(0)
+    U = torch.from_numpy(wl.arena).to("cuda")
+    V = lev.new_state()
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t, t_end, nsteps = 0.0, wl.meta["t_end"], 0
+    while t < t_end * (1 - 1e-12):
+        lev.fill_boundary(U)
+        lev.compute_dt(U, wl.dx, p, out=dtv)
+        dt = min(float(dtv[0].item()), t_end - t)
+        lev.hydro_step(U, V, wl.dx, p, dt=dt)
+        U, V = V, U
+        t += dt
+        nsteps += 1
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+    A = U.clone()
+    B = lev.new_state()
+    g = lev.graph(A, B, wl.dx, p, graph_steps)
+    g.launch()
+    torch.cuda.synchronize()
+    reps = 4
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.launch()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / (reps * graph_steps)
+    flags = lev.check_status()
+    g.close()
+    lev.close()
+    zones = wl.layout.valid_zones()
+    del U, V, A, B, lev
+    torch.cuda.empty_cache()
+    return {"zones": zones, "steps_to_300us": nsteps, "eager_run_s": eager_s,
+            "eager_ms_per_step": eager_s / nsteps * 1e3, "graph_ms_per_step": graph_s * 1e3,
+            "graph_zone_updates_per_s": zones / graph_s, "graph_run_s_estimate": graph_s * nsteps,
+            "flags": flags}
+
+
 def copy_bandwidth(gib=2, reps=5):
     """Measured HBM bandwidth of a plain device-to-device copy (bytes read +
     written per second), the practical ceiling next to the 8 TB/s spec."""
@@ -450,6 +502,8 @@ def main():
                     help="only measure the adjoint/forward cost on the 128^3 differentiation workload")
     ap.add_argument("--amr-only", action="store_true",
                     help="with --no-extras: still measure the two-level hierarchy")
+    ap.add_argument("--jet-only", action="store_true",
+                    help="with --no-extras: still run the inflowing jet to 300 us")
     ap.add_argument("--species-only", action="store_true",
                     help="with --no-extras: still measure the passive-species step")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -632,6 +686,13 @@ def main():
               "one_box_per_level": amr_costs(256, 256, 256, 5, 1),
               "boxes_of_64": amr_costs(256, 64, 64, 5, 1)}
         out["amr"] = am
+    if not args.no_extras or args.jet_only:
+        print("bench: inflowing jet to 300 us", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["jet"] = {"workload": "inflowing jet: 1 cm square of sea-level air, tanh inflow of peak Mach 0.1 "
+                                  "and half density at y = 0, outflow elsewhere, 4 zones periodic in z, "
+                                  "FP64, to t = 300 us",
+                      "n256": jet_costs(256), "n512": jet_costs(512)}
     if not args.no_extras or args.species_only:
         from paper_1008_2801_amd import inputs as I
         print("bench: passive species on the 256^3 workload", file=sys.stderr, flush=True)
