@@ -204,30 +204,46 @@ def adjoint_costs(wl, nsteps, every, reps=3, precision=0, rollout=True):
         return e0.elapsed_time(e1) / reps
     t_fwd = timed(lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
     t_adj = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv))
+    # the adjoint on the intermediates the forward step left in its workspace
+    acc = 0.0
+    for r in range(reps + 1):
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv, saved=True)
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            acc += e0.elapsed_time(e1)
+    t_sav = acc / reps
     res = {"precision": "f64" if precision == 0 else "f32 reconstruction + f64 update",
-           "forward_step_ms": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd}
+           "forward_step_ms": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
+           "adjoint_step_saved_ms": t_sav, "adjoint_saved_over_forward": t_sav / t_fwd}
     if not rollout:
         res["flags"] = lev.check_status()
         lev.close()
         return res
     del W, Ub, V
-    t_f, t_b = [], []
-    for _ in range(3):  # the first backward also starts autograd's device thread
-        U0 = torch.from_numpy(wl.arena).to("cuda").requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        UT = P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=every)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        UT.backward(torch.ones_like(UT))
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        t_f.append(t1 - t0)
-        t_b.append(t2 - t1)
-        del UT, U0
-    res.update({"rollout_steps": nsteps, "checkpoint_every": every, "rollout_forward_s": min(t_f),
-                "rollout_backward_s": min(t_b), "backward_over_forward": min(t_b) / min(t_f),
-                "flags": lev.check_status()})
+    res.update({"rollout_steps": nsteps, "checkpoint_every": every})
+    for saved, tag in ((False, ""), (True, "_saved_segments")):
+        t_f, t_b = [], []
+        for _ in range(3):  # the first backward also starts autograd's device thread
+            U0 = torch.from_numpy(wl.arena).to("cuda").requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            UT = P.rollout(U0, lev, nsteps, wl.dx, p, checkpoint_every=every, saved=saved)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            UT.backward(torch.ones_like(UT))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t_f.append(t1 - t0)
+            t_b.append(t2 - t1)
+            del UT, U0
+        res.update({"rollout_forward_s" + tag: min(t_f), "rollout_backward_s" + tag: min(t_b),
+                    "backward_over_forward" + tag: min(t_b) / min(t_f)})
+    lev.release_workspace_slots()
+    res["flags"] = lev.check_status()
     lev.close()
     return res
 

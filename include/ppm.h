@@ -183,6 +183,17 @@ int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
 int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
                            const double* dt_dev, const double dx[3], const ppm_params* params, void* stream);
 
+/* The same adjoint without the recompute: the step workspace must still
+ * hold the intermediates of the forward step from this U with the same dt
+ * and params (ppm_hydro_step ran with this workspace and nothing has
+ * written to it since).  Results are bitwise those of
+ * ppm_hydro_step_adjoint.  For callers that keep one workspace per step of
+ * a checkpoint segment (memory for compute); the library cannot check the
+ * precondition. */
+int ppm_hydro_step_adjoint_saved(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar,
+                                 double dt, const double* dt_dev, const double dx[3], const ppm_params* params,
+                                 void* stream);
+
 /* Passive species: mass fractions X_s carried with the flow (partial
  * densities rho X_s obey the continuity equation with the mass flux times
  * X_s).  The paper's code advances conserved variables generically (Sec. 1);

@@ -647,8 +647,9 @@ int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
   return PPM_OK;
 }
 
-int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
-                           const double* dt_dev, const double dx[3], const ppm_params* params, void* stream) {
+static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
+                        const double* dt_dev, const double dx[3], const ppm_params* params, void* stream,
+                        bool recompute) {
   if (!ctx) return PPM_EINVAL;
   std::string m = validate_params(params);
   if (m.empty()) m = validate_dx(dx);
@@ -672,12 +673,15 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
   if (rc) return rc;
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
   const int nS = (int)ctx->tilesS.size(), nE = (int)ctx->tilesE.size();
-  // recompute the forward intermediates through stage 2 (U is not written)
-  rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, U, nullptr, nullptr, ctx->work, params->gamma,
-                            params->small_dens, params->small_pres, params->limiter, params->flattening,
-                            params->riemann_iters, grav, params->grav, s, nullptr, 5),
-                "adjoint recompute");
-  if (rc) return rc;
+  // recompute the forward intermediates through stage 2 (U is not written),
+  // unless the workspace holds them from the forward step
+  if (recompute) {
+    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, U, nullptr, nullptr, ctx->work, params->gamma,
+                              params->small_dens, params->small_pres, params->limiter, params->flattening,
+                              params->riemann_iters, grav, params->grav, s, nullptr, 5),
+                  "adjoint recompute");
+    if (rc) return rc;
+  }
   return ctx->hip(launch_adjoint(L, params->precision, nS, nE, U, Unew_bar, U_bar, ctx->work, ctx->awork,
                                  params->gamma, params->small_dens, params->small_pres, params->limiter,
                                  params->flattening, params->riemann_iters, grav, params->grav, s),
@@ -756,6 +760,17 @@ int ppm_hydro_step_species(ppm_ctx* ctx, const double* U, double* Unew, const do
                                  params->small_pres, params->limiter, params->flattening, params->riemann_iters,
                                  grav, (hipStream_t)stream),
                   "species step");
+}
+
+int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
+                           const double* dt_dev, const double dx[3], const ppm_params* params, void* stream) {
+  return adjoint_step(ctx, U, Unew_bar, U_bar, dt, dt_dev, dx, params, stream, true);
+}
+
+int ppm_hydro_step_adjoint_saved(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar,
+                                 double dt, const double* dt_dev, const double dx[3], const ppm_params* params,
+                                 void* stream) {
+  return adjoint_step(ctx, U, Unew_bar, U_bar, dt, dt_dev, dx, params, stream, false);
 }
 
 int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], const ppm_params* params,

@@ -30,7 +30,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_set_tiling", "ppm_get_tiling", "ppm_autotune", "ppm_species_offsets",
            "ppm_species_workspace_bytes", "ppm_set_species_workspace", "ppm_fill_species",
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
-           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow")
+           "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
+           "ppm_hydro_step_adjoint_saved")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -112,6 +113,8 @@ def lib():
         L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
                                              ctypes.POINTER(Params), _vp]
         L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.ppm_hydro_step_adjoint_saved.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
+                                                   ctypes.POINTER(Params), _vp]
         L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.ppm_amr_destroy.argtypes = [_vp]
@@ -225,6 +228,8 @@ class Level:
         assert np.array_equal(off, layout.offsets()), "arena offsets differ from the layout's"
         self._work = None
         self._work_prec = None
+        self._slot = None
+        self._slots = {}
         self.device = torch.device("cuda")
 
     def close(self):
@@ -259,6 +264,7 @@ class Level:
         aligned = (base + 255) // 256 * 256
         self._check(lib().ppm_set_workspace(self.ctx, ctypes.c_void_p(aligned), need), "ppm_set_workspace")
         self._work_prec = precision
+        self._slot = None
 
     def new_state(self):
         import torch
@@ -289,7 +295,8 @@ class Level:
         return out
 
     def hydro_step(self, U, Unew, dx, p, dt=0.0, dt_dev=None, fluxes=None, mode=BATCHED, stream=None):
-        if self._work is None or self._work_prec != p.precision or self._work.numel() < self.workspace_bytes(p.precision):
+        if self._slot is None and (self._work is None or self._work_prec != p.precision or
+                                   self._work.numel() < self.workspace_bytes(p.precision)):
             self.ensure_workspace(p.precision)
         fl = None
         if fluxes is not None:
@@ -340,18 +347,45 @@ class Level:
         self._check(lib().ppm_set_adjoint_workspace(self.ctx, ctypes.c_void_p(aligned), need),
                     "ppm_set_adjoint_workspace")
 
-    def hydro_step_adjoint(self, U, Unew_bar, U_bar, dx, p, dt=0.0, dt_dev=None, stream=None):
+    def hydro_step_adjoint(self, U, Unew_bar, U_bar, dx, p, dt=0.0, dt_dev=None, stream=None, saved=False):
         """U_bar = J^T Unew_bar for the step from U (ghosts filled), dt frozen;
-        the reverse runs in the step's precision (p.precision)."""
+        the reverse runs in the step's precision (p.precision).  saved=True:
+        the selected workspace still holds this step's forward
+        intermediates (no recompute)."""
         prec = int(p.precision)
-        if self._work is None or self._work_prec != prec or self._work.numel() < self.workspace_bytes(prec) + 256:
+        if self._slot is None and (self._work is None or self._work_prec != prec or
+                                   self._work.numel() < self.workspace_bytes(prec) + 256):
             self.ensure_workspace(prec)
         if getattr(self, "_awork", None) is None or getattr(self, "_awork_prec", None) != prec:
             self.ensure_adjoint_workspace(prec)
             self._awork_prec = prec
-        self._check(lib().ppm_hydro_step_adjoint(self.ctx, _ptr(U), _ptr(Unew_bar), _ptr(U_bar), float(dt),
-                                                 _ptr(dt_dev), _dp3(*dx), ctypes.byref(p), _stream(stream)),
-                    "ppm_hydro_step_adjoint")
+        fn = lib().ppm_hydro_step_adjoint_saved if saved else lib().ppm_hydro_step_adjoint
+        self._check(fn(self.ctx, _ptr(U), _ptr(Unew_bar), _ptr(U_bar), float(dt), _ptr(dt_dev), _dp3(*dx),
+                       ctypes.byref(p), _stream(stream)), "ppm_hydro_step_adjoint")
+
+    def select_workspace(self, slot, precision=0):
+        """Make workspace slot `slot` (allocated on first use) the step
+        workspace, or the default one for slot None.  A checkpoint segment
+        keeps one slot per step so that its adjoints need no recompute."""
+        import torch
+        if slot is None:
+            self._slot = None
+            self.ensure_workspace(precision)
+            return
+        need = self.workspace_bytes(precision)
+        t = self._slots.get(slot)
+        if t is None or t.numel() < need + 256:
+            t = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            self._slots[slot] = t
+        aligned = (t.data_ptr() + 255) // 256 * 256
+        self._check(lib().ppm_set_workspace(self.ctx, ctypes.c_void_p(aligned), need), "ppm_set_workspace")
+        self._slot = slot
+
+    def release_workspace_slots(self):
+        self._slots = {}
+        if self._slot is not None:
+            self._slot = None
+            self.ensure_workspace(self._work_prec or 0)
 
     # ------------------------------------------------ passive species ----
     def species_offsets(self, ns):
@@ -594,7 +628,7 @@ def _autograd():
         reverse (memory: the checkpoints plus one segment of states)."""
 
         @staticmethod
-        def forward(ctx, U0, level, nsteps, dx, p, every, dts_in):
+        def forward(ctx, U0, level, nsteps, dx, p, every, dts_in, saved):
             U = U0.detach().clone()
             dts = torch.zeros(nsteps, 2, dtype=torch.float64, device=U.device) if dts_in is None else dts_in
             ckpts = {}
@@ -608,7 +642,7 @@ def _autograd():
                 level.hydro_step(U, V, dx, p, dt_dev=dts[k])
                 U, V = V, U
             ctx.level, ctx.nsteps, ctx.dx, ctx.p, ctx.every = level, nsteps, dx, p, every
-            ctx.ckpts, ctx.dts = ckpts, dts
+            ctx.ckpts, ctx.dts, ctx.saved = ckpts, dts, saved
             out = U.clone()
             return out
 
@@ -617,20 +651,38 @@ def _autograd():
             lev, n, every = ctx.level, ctx.nsteps, ctx.every
             g = g.contiguous().clone()
             Ub = torch.empty_like(g)
-            # the filled input states of one segment; the segment's last
-            # step is not replayed (its output is not needed)
-            slots = [torch.empty_like(g) for _ in range(min(every, n))]
-            for s0 in reversed(range(0, n, every)):
-                s1 = min(n, s0 + every)
-                slots[0].copy_(ctx.ckpts[s0])
-                for k in range(s0, s1):
-                    lev.fill_boundary(slots[k - s0])
-                    if k + 1 < s1:
-                        lev.hydro_step(slots[k - s0], slots[k + 1 - s0], ctx.dx, ctx.p, dt_dev=ctx.dts[k])
-                for k in reversed(range(s0, s1)):
-                    lev.hydro_step_adjoint(slots[k - s0], g, Ub, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
-                    g, Ub = Ub, g
-            return g, None, None, None, None, None, None
+            m = min(every, n)
+            prec = int(ctx.p.precision)
+            saved = ctx.saved
+            if saved is None:  # keep one workspace per segment step if it fits in half the free memory
+                free, _ = torch.cuda.mem_get_info(g.device)
+                saved = m * (lev.workspace_bytes(prec) + 256) <= free // 2
+            # the filled input states of one segment; without saved
+            # workspaces the segment's last step is not replayed (its output
+            # is not needed), with them every step runs on its own workspace
+            slots = [torch.empty_like(g) for _ in range(m)]
+            scratch = torch.empty_like(g) if saved else None
+            try:
+                for s0 in reversed(range(0, n, every)):
+                    s1 = min(n, s0 + every)
+                    slots[0].copy_(ctx.ckpts[s0])
+                    for k in range(s0, s1):
+                        lev.fill_boundary(slots[k - s0])
+                        if saved:
+                            lev.select_workspace(k - s0, prec)
+                            out = slots[k + 1 - s0] if k + 1 < s1 else scratch
+                            lev.hydro_step(slots[k - s0], out, ctx.dx, ctx.p, dt_dev=ctx.dts[k])
+                        elif k + 1 < s1:
+                            lev.hydro_step(slots[k - s0], slots[k + 1 - s0], ctx.dx, ctx.p, dt_dev=ctx.dts[k])
+                    for k in reversed(range(s0, s1)):
+                        if saved:
+                            lev.select_workspace(k - s0, prec)
+                        lev.hydro_step_adjoint(slots[k - s0], g, Ub, ctx.dx, ctx.p, dt_dev=ctx.dts[k], saved=saved)
+                        g, Ub = Ub, g
+            finally:
+                if saved:
+                    lev.select_workspace(None, prec)
+            return g, None, None, None, None, None, None, None
 
     return HydroStep, Rollout
 
@@ -640,8 +692,11 @@ def hydro_step_autograd(U, level, dt, dx, p):
     return HydroStep.apply(U, level, dt, dx, p)
 
 
-def rollout(U0, level, nsteps, dx, p, checkpoint_every=5, dts=None):
+def rollout(U0, level, nsteps, dx, p, checkpoint_every=5, dts=None, saved=None):
     """Differentiable roll-out of nsteps (dt per step from the CFL rule,
-    frozen; or the given (nsteps, 2) device tensor of [dt, s])."""
+    frozen; or the given (nsteps, 2) device tensor of [dt, s]).  saved: the
+    backward replays each segment with one workspace per step and runs the
+    adjoints on the kept intermediates (True), recomputes them in every
+    adjoint (False), or chooses by free memory (None)."""
     _, Rollout = _autograd()
-    return Rollout.apply(U0, level, nsteps, dx, p, checkpoint_every, dts)
+    return Rollout.apply(U0, level, nsteps, dx, p, checkpoint_every, dts, saved)
