@@ -167,7 +167,7 @@ const int NG = 4;  // ghost width: flattening reaches 3 zones past a traced zone
 // Per-step constants in the reconstruction scalar.  They are formed in FP64
 // from gamma, dt and h, then rounded to S once.
 template <class S> struct Consts {
-  S gamma, gm1, gm1inv, beta, small_dens, small_pres;
+  S gamma, gm1, gm1inv, beta, small_dens, small_pres, ismall_dens;
   S dtdx[3], dt2h[3], dt3h[3], hdtg[3];
   S half, one, two, three, six, sixth, two3, c033, ten, c075;
   bool grav;
@@ -182,6 +182,7 @@ Consts<S> make_consts(const OParams& P, double dt, const double h[3]) {
   K.beta = S((P.gamma + 1.0) / (2.0 * P.gamma));
   K.small_dens = S(P.small_dens);
   K.small_pres = S(P.small_pres);
+  K.ismall_dens = S(1.0 / P.small_dens);
   for (int d = 0; d < 3; ++d) {
     K.dtdx[d] = S(dt / h[d]);
     K.dt2h[d] = S(dt / (2.0 * h[d]));
@@ -224,7 +225,8 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   for (int it = 0; it < K.iters; ++it) {
     const S wl = cl * ssqrt(K.one + K.beta * (p * ipl - K.one));
     const S wr = cr * ssqrt(K.one + K.beta * (p * ipr - K.one));
-    const S iwl = K.one / wl, iwr = K.one / wr;
+    const S iww = K.one / (wl * wr);  // one division for both 1/W_s
+    const S iwl = wr * iww, iwr = wl * iww;
     const S xl = cl * iwl, xr = cr * iwr;
     const S izl = K.half * iwl * (K.one + xl * xl);
     const S izr = K.half * iwr * (K.one + xr * xr);
@@ -236,7 +238,8 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   }
   const S wl = cl * ssqrt(K.one + K.beta * (p * ipl - K.one));
   const S wr = cr * ssqrt(K.one + K.beta * (p * ipr - K.one));
-  const S iwl = K.one / wl, iwr = K.one / wr;
+  const S iww = K.one / (wl * wr);
+  const S iwl = wr * iww, iwr = wl * iww;
   const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
 
   // Sample the wave fan at x/t = 0 on one side of the contact.  Outer state:
@@ -247,9 +250,9 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   auto sample_left = [&](S st[5]) {
     const S irho = K.one / rl;
     const S vstar = irho - (p - pl) * (iwl * iwl);
-    S rs = K.one / vstar;
-    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; }
-    const S cst = ssqrt(K.gamma * p / rs);
+    S rs = K.one / vstar, ivs = vstar;  // ivs = 1/rho* (floored with it)
+    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; ivs = K.ismall_dens; }
+    const S cst = ssqrt(K.gamma * p * ivs);
     const S co = cl * irho;
     S r_ = rl, u_ = ul, p_ = pl;  // outer
     if (V(p) > V(pl)) {
@@ -272,9 +275,9 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   auto sample_right = [&](S st[5]) {
     const S irho = K.one / rr;
     const S vstar = irho - (p - pr) * (iwr * iwr);
-    S rs = K.one / vstar;
-    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; }
-    const S cst = ssqrt(K.gamma * p / rs);
+    S rs = K.one / vstar, ivs = vstar;  // ivs = 1/rho* (floored with it)
+    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; ivs = K.ismall_dens; }
+    const S cst = ssqrt(K.gamma * p * ivs);
     const S co = cr * irho;
     S r_ = rr, u_ = ur, p_ = pr;
     if (V(p) > V(pr)) {
@@ -481,7 +484,8 @@ template <class S>
 void cons_to_prim_floor(const S U[5], const Consts<S>& K, S q[5], int& flags) {
   if (V(U[0]) < V(K.small_dens)) flags |= FLAG_FLOOR;
   const S r = smax(U[0], K.small_dens);
-  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
+  const S ir = K.one / r;  // one division for the three velocities
+  const S u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
   const S ke = K.half * r * ((u * u + v * v) + w * w);
   S p = K.gm1 * (U[4] - ke);
   if (V(p) < V(K.small_pres)) flags |= FLAG_FLOOR;

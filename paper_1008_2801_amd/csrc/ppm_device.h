@@ -80,6 +80,7 @@ inline Gas<S> make_gas(double gamma, double small_dens, double small_pres, int l
   G.beta = S((gamma + 1.0) / (2.0 * gamma));
   G.small_dens = S(small_dens);
   G.small_pres = S(small_pres);
+  G.ismall_dens = S(1.0 / small_dens);
   G.limiter = limiter;
   G.flattening = flattening && limiter;
   G.iters = iters;

@@ -18,7 +18,7 @@ namespace ppm {
 // Gas and scheme constants in the reconstruction scalar, formed on the host
 // in FP64 from gamma and the floors, rounded once to S.
 template <class S> struct Gas {
-  S gamma, gm1, gm1inv, beta, small_dens, small_pres;
+  S gamma, gm1, gm1inv, beta, small_dens, small_pres, ismall_dens;
   int limiter, flattening, iters, grav;
 };
 
@@ -52,9 +52,9 @@ PPM_HD void sample_side(S ro, S uo, S po, S C, S W, S iW, S us, S p, const Gas<S
                                             S& r_, S& u_, S& p_, int& fl) {
   const S irho = ONE / ro;
   const S vstar = irho - (p - po) * (iW * iW);
-  S rs = ONE / vstar;
-  if (!(vstar > S(0)) || rs < G.small_dens) { fl |= PPM_FLAG_FLOOR; rs = G.small_dens; }
-  const S cst = ssqrt(G.gamma * p / rs);
+  S rs = ONE / vstar, ivs = vstar;  // ivs = 1/rho* (floored with it)
+  if (!(vstar > S(0)) || rs < G.small_dens) { fl |= PPM_FLAG_FLOOR; rs = G.small_dens; ivs = G.ismall_dens; }
+  const S cst = ssqrt(G.gamma * p * ivs);
   const S co = C * irho;
   r_ = ro; u_ = uo; p_ = po;
   if (p > po) {
@@ -90,7 +90,8 @@ PPM_HD void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl
   for (int it = 0; it < G.iters; ++it) {
     const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
     const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-    const S iwl = ONE / wl, iwr = ONE / wr;
+    const S iww = ONE / (wl * wr);  // one division for both 1/W_s
+    const S iwl = wr * iww, iwr = wl * iww;
     const S xl = cl * iwl, xr = cr * iwr;
     const S izl = HALF * iwl * (ONE + xl * xl);
     const S izr = HALF * iwr * (ONE + xr * xr);
@@ -102,7 +103,8 @@ PPM_HD void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl
   }
   const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
   const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-  const S iwl = ONE / wl, iwr = ONE / wr;
+  const S iww = ONE / (wl * wr);
+  const S iwl = wr * iww, iwr = wl * iww;
   const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
 
   S g0, g1, g2, g3, g4;
@@ -289,7 +291,8 @@ template <class S>
 PPM_HD void cons_to_prim_floor(const S U[5], const Gas<S>& G, S q[5], int& fl) {
   if (U[0] < G.small_dens) fl |= PPM_FLAG_FLOOR;
   const S r = smax(U[0], G.small_dens);
-  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
+  const S ir = ONE / r;  // one division for the three velocities
+  const S u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
   const S ke = HALF * r * ((u * u + v * v) + w * w);
   S p = G.gm1 * (U[4] - ke);
   if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;

@@ -45,12 +45,12 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
                             S pb_, S& rob, S& uob, S& pob, S& Cb, S& iWb, S& usb, S& pb) {
   const S irho = ONE / ro;
   const S vstar = irho - (p - po) * (iW * iW);
-  S rs = ONE / vstar;
+  S rs = ONE / vstar, ivs = vstar;
   bool fl = false;
-  if (!(vstar > S(0)) || rs < G.small_dens) { fl = true; rs = G.small_dens; }
-  const S cst = ssqrt(G.gamma * p / rs);
+  if (!(vstar > S(0)) || rs < G.small_dens) { fl = true; rs = G.small_dens; ivs = G.ismall_dens; }
+  const S cst = ssqrt(G.gamma * p * ivs);
   const S co = C * irho;
-  S rsb = S(0), cstb = S(0), cob = S(0), irhob = S(0);
+  S rsb = S(0), cstb = S(0), cob = S(0), irhob = S(0), ivsb = S(0);
   if (p > po) {
     const S sh = uo - W * irho;
     if (!(sh >= S(0))) { rsb += rb_; usb += ub_; pb += pb_; }
@@ -80,16 +80,16 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
       cstb -= tlb;
     }
   }
-  // cst = sqrt(gamma p / rs), co = C / rho
+  // cst = sqrt(gamma p ivs), co = C / rho
   if (cstb != S(0)) {
-    const S h = cstb * HALF / (rs * cst);
-    pb += h * G.gamma;
-    rsb -= h * cst * cst;
+    const S h = cstb * HALF / cst;
+    pb += h * G.gamma * ivs;
+    ivsb += h * G.gamma * p;
   }
   Cb += cob * irho;
   irhob += cob * C;
-  // rs = 1 / vstar (floor frozen)
-  const S vstarb = fl ? S(0) : -rsb * rs * rs;
+  // rs = 1 / vstar and ivs = vstar (floor frozen)
+  const S vstarb = fl ? S(0) : -rsb * rs * rs + ivsb;
   irhob += vstarb;
   pb -= vstarb * (iW * iW);
   pob += vstarb * (iW * iW);
@@ -105,7 +105,8 @@ template <class S>
 PPM_HD S riem_iter(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G) {
   const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
   const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-  const S iwl = ONE / wl, iwr = ONE / wr;
+  const S iww = ONE / (wl * wr);
+  const S iwl = wr * iww, iwr = wl * iww;
   const S xl = cl * iwl, xr = cr * iwr;
   const S izl = HALF * iwl * (ONE + xl * xl);
   const S izr = HALF * iwr * (ONE + xr * xr);
@@ -128,7 +129,8 @@ PPM_HD S riem_iter_rec(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   const S sl = ssqrt(ONE + G.beta * (p * ipl - ONE));
   const S sr = ssqrt(ONE + G.beta * (p * ipr - ONE));
   const S wl = cl * sl, wr = cr * sr;
-  const S iwl = ONE / wl, iwr = ONE / wr;
+  const S iww = ONE / (wl * wr);
+  const S iwl = wr * iww, iwr = wl * iww;
   const S xl = cl * iwl, xr = cr * iwr;
   const S izl = HALF * iwl * (ONE + xl * xl);
   const S izr = HALF * iwr * (ONE + xr * xr);
@@ -225,7 +227,8 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   const S all = ONE + G.beta * (pst * ipl - ONE), alr = ONE + G.beta * (pst * ipr - ONE);
   const S sl = ssqrt(all), sr = ssqrt(alr);
   const S wl = cl * sl, wr = cr * sr;
-  const S iwl = ONE / wl, iwr = ONE / wr;
+  const S iww = ONE / (wl * wr);
+  const S iwl = wr * iww, iwr = wl * iww;
   const S NU = (wl * ul + wr * ur) + (pl - pr), DU = wl + wr;
   const S us = NU / DU;
 
@@ -373,7 +376,8 @@ template <class S>
 PPM_HD void cons_to_prim_floor_vjp(const S U[5], const Gas<S>& G, const S qb[5], S Ub[5]) {
   const bool rfl = U[0] < G.small_dens;
   const S r = smax(U[0], G.small_dens);
-  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
+  const S ir0 = ONE / r;
+  const S u = U[1] * ir0, v = U[2] * ir0, w = U[3] * ir0;
   const S ke = HALF * r * ((u * u + v * v) + w * w);
   const S p = G.gm1 * (U[4] - ke);
   const S pb = (p < G.small_pres) ? S(0) : qb[4];
@@ -386,7 +390,8 @@ template <class S>
 PPM_HD void cons_to_prim_dec(const S U[5], const Gas<S>& G, S q[5], bool& rfl, bool& pfl) {
   rfl = U[0] < G.small_dens;
   const S r = smax(U[0], G.small_dens);
-  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
+  const S ir = ONE / r;
+  const S u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
   const S ke = HALF * r * ((u * u + v * v) + w * w);
   const S p = G.gm1 * (U[4] - ke);
   pfl = p < G.small_pres;
