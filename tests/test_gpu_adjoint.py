@@ -321,3 +321,50 @@ def test_rollout_with_saved_segments_equals_recompute_bitwise():
         assert lev._slot is None  # the default workspace is selected again
         lev.close()
     assert torch.equal(grads[0], grads[1])
+
+
+def test_differentiation_workload_full_size_against_central_differences():
+    """The differentiation workload as specified: 128^3, 20 steps with
+    checkpoints every 5, loss = sum of rho^2 over an 8^3 sub-block; the
+    checkpointed roll-out gradient against central differences (eps 1e-6)
+    of the GPU forward along 64 random directions, the dt sequence frozen.
+    Unlimited reconstruction and a bulk flow keep every branch of the step
+    (limiter cases, wave sides) away from the perturbation, as the
+    workload's small amplitude intends."""
+    wl = I.cfg4(128, amp=0.05, bulk=(0.3, 0.2, 0.25))
+    lay = wl.layout
+    nsteps, every, lo, hi = 20, 5, 60, 68
+    loss, g, lev = _loss_and_grad(wl, nsteps, every, lo, hi, limiter=0)
+    p = P.params(gamma=wl.gamma, limiter=0)
+    dts = torch.zeros(nsteps, 2, dtype=torch.float64, device="cuda")
+    U = torch.from_numpy(wl.arena).cuda()
+    V = torch.zeros_like(U)
+    for k in range(nsteps):
+        lev.fill_boundary(U)
+        lev.compute_dt(U, wl.dx, p, out=dts[k])
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dts[k])
+        U, V = V, U
+    U0 = torch.from_numpy(wl.arena).cuda()
+    gt = torch.from_numpy(g).cuda()
+    mask = torch.zeros_like(U0)
+    lay.view(mask, 0)[:, 4:-4, 4:-4, 4:-4] = 1.0  # valid zones of the box
+
+    def loss_of(Uin):
+        A, B = Uin.clone(), torch.zeros_like(Uin)
+        for k in range(nsteps):
+            lev.fill_boundary(A)
+            lev.hydro_step(A, B, wl.dx, p, dt_dev=dts[k])
+            A, B = B, A
+        rho = A[: lay.box_size(0)].view(lay.stored_shape(0))[0]
+        sub = rho[4 + lo:4 + hi, 4 + lo:4 + hi, 4 + lo:4 + hi]
+        return float((sub * sub).sum().item())
+    gen = torch.Generator(device="cuda").manual_seed(64)
+    eps = 1e-6
+    worst = 0.0
+    for i in range(64):
+        v = torch.randn(U0.shape, generator=gen, device="cuda", dtype=torch.float64) * mask
+        fd = (loss_of(U0 + eps * v) - loss_of(U0 - eps * v)) / (2 * eps)
+        ad = float((gt * v).sum().item())
+        worst = max(worst, abs(fd - ad) / abs(ad))
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (i, fd, ad)
+    print(f"128^3, 20 steps, 64 directions: worst relative gradient error {worst:.2e} (loss {loss:.6e})")
