@@ -512,6 +512,8 @@ def main():
     ap.add_argument("--autotune-cache", default=None,
                     help="autotuner cache file (default: the package's autotune_cache.jsonl)")
     ap.add_argument("--tiling", default=None, help="'tile,strip_rows': use this tiling instead of autotuning")
+    ap.add_argument("--fused", action="store_true",
+                    help="run the final fluxes and the update in the brick kernel (fluxes in LDS)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 512-box batched / per-box / graph measurements")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -572,6 +574,7 @@ def main():
     print(f"bench: workload {wl.name} {lay.n(0)} x {lay.nbox} box(es), building state", file=sys.stderr,
           flush=True)
     lev = P.Level(lay)
+    lev.set_step_form(args.fused)
     U = torch.from_numpy(wl.arena).to("cuda")
     V = lev.new_state()
     p = P.params(gamma=wl.gamma, precision=wl.precision)

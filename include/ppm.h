@@ -307,6 +307,18 @@ int ppm_graph_destroy(ppm_graph* g);
 int ppm_set_tiling(ppm_ctx* ctx, int32_t tile, int32_t strip_rows);
 int ppm_get_tiling(const ppm_ctx* ctx, int32_t* tile, int32_t* strip_rows);
 
+/* Form of the step's last stage.  fused = 0 (the default): the final
+ * fluxes go to the workspace and a separate kernel updates the zones.
+ * fused = 1: the final fluxes of each brick of 32 x 4 x 4 valid zones are
+ * computed into LDS and the brick is updated from them in the same kernel
+ * (the fluxes on a brick's faces are computed by both bricks that share
+ * them; nothing is written to the workspace's final-flux planes).  Results
+ * are identical bit for bit; on gfx950 the staged form is the faster one.
+ * The species step always runs the staged form (it reads the final mass
+ * fluxes from the workspace). */
+int ppm_set_step_form(ppm_ctx* ctx, int32_t fused);
+int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused);
+
 /* Autotuner: times the batched step (reps steps after one warm-up, HIP
  * events on the stream) from the filled state U into Unew for every
  * candidate tile size x strip height, keeps the fastest, and appends it to

@@ -348,6 +348,29 @@ struct ppm_graph {
 };
 
 namespace {
+// Bricks of at most BRICK_E valid zones per box, x fastest then y then z.
+void build_bricks(ppm_ctx& c) {
+  c.bricks.clear();
+  c.tB_begin.assign(1, 0);
+  for (int b = 0; b < c.layout.nbox; ++b) {
+    int n[3];
+    for (int d = 0; d < 3; ++d) n[d] = c.boxes[b].hi[d] - c.boxes[b].lo[d] + 1;
+    for (int z = 0; z < n[2]; z += BRICK_E[2])
+      for (int y = 0; y < n[1]; y += BRICK_E[1])
+        for (int x = 0; x < n[0]; x += BRICK_E[0]) {
+          Brick K;
+          K.box = b;
+          const int o[3] = {x, y, z};
+          for (int d = 0; d < 3; ++d) {
+            K.o[d] = o[d];
+            K.e[d] = std::min(BRICK_E[d], n[d] - o[d]);
+          }
+          c.bricks.push_back(K);
+        }
+    c.tB_begin.push_back((int)c.bricks.size());
+  }
+}
+
 void build_tiles(ppm_ctx& c) {
   c.tilesS.clear();
   c.tilesE.clear();
@@ -478,8 +501,10 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
         if (cmask[k] >> c & 1) inv_idx[fillp[(size_t)desc[k].src * INV_CLASSES + c]++] = (int)k;
   }
   build_tiles(*ctx);
+  build_bricks(*ctx);
   hipError_t e;
-  if ((e = upload(&ctx->d_inv_start, inv_start)) != hipSuccess ||
+  if ((e = upload(&ctx->d_bricks, ctx->bricks)) != hipSuccess ||
+      (e = upload(&ctx->d_inv_start, inv_start)) != hipSuccess ||
       (e = upload(&ctx->d_inv_idx, inv_idx)) != hipSuccess ||
       (e = upload(&ctx->d_boxes, db)) != hipSuccess ||
       (e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess ||
@@ -506,6 +531,7 @@ int ppm_ctx_destroy(ppm_ctx* ctx) {
   (void)hipFree(ctx->d_boxes);
   (void)hipFree(ctx->d_tilesS);
   (void)hipFree(ctx->d_tilesE);
+  (void)hipFree(ctx->d_bricks);
   (void)hipFree(ctx->d_desc);
   (void)hipFree(ctx->d_start);
   (void)hipFree(ctx->d_consts);
@@ -594,9 +620,9 @@ int ppm_compute_dt(ppm_ctx* ctx, const double* U, const double dx[3], const ppm_
   return rc;
 }
 
-int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
-                   const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
-                   void* stream) {
+static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                           const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                           void* stream, int upto) {
   if (!ctx) return PPM_EINVAL;
   std::string m = validate_params(params);
   if (m.empty()) m = validate_dx(dx);
@@ -617,20 +643,41 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
   int rc = ctx->hip(launch_step_consts(L, dt, dt_dev, dx, params->grav, s), "step consts");
   if (rc) return rc;
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
-  auto run = [&](int tS0, int tS1, int tE0, int tE1, hipEvent_t* ev) {
-    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, U, Unew, flux, ctx->work,
+  auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, hipEvent_t* ev) {
+    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, ctx->work,
                                 params->gamma, params->small_dens, params->small_pres, params->limiter,
-                                params->flattening, params->riemann_iters, grav, params->grav, s, ev),
+                                params->flattening, params->riemann_iters, grav, params->grav, s, ev, upto),
                     "step");
   };
   if (mode == PPM_LAUNCH_BATCHED) {
     ppm_ctx::ProfRec* r = ctx->prof ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
-    return run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), r ? r->ev.data() : nullptr);
+    return run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(),
+               r ? r->ev.data() : nullptr);
   }
   for (int b = 0; b < ctx->layout.nbox; ++b) {
-    rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], nullptr);
+    rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], ctx->tB_begin[b],
+             ctx->tB_begin[b + 1], nullptr);
     if (rc) return rc;
   }
+  return PPM_OK;
+}
+
+int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                   const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                   void* stream) {
+  return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL);
+}
+
+int ppm_set_step_form(ppm_ctx* ctx, int32_t fused) {
+  if (!ctx) return PPM_EINVAL;
+  if (fused != 0 && fused != 1) return ctx->fail(PPM_EINVAL, "set_step_form: fused must be 0 or 1");
+  ctx->fused = fused;
+  return PPM_OK;
+}
+
+int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused) {
+  if (!ctx || !fused) return PPM_EINVAL;
+  *fused = ctx->fused;
   return PPM_OK;
 }
 
@@ -676,9 +723,10 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, d
   // recompute the forward intermediates through stage 2 (U is not written),
   // unless the workspace holds them from the forward step
   if (recompute) {
-    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, U, nullptr, nullptr, ctx->work, params->gamma,
-                              params->small_dens, params->small_pres, params->limiter, params->flattening,
-                              params->riemann_iters, grav, params->grav, s, nullptr, 5),
+    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, 0, 0, U, nullptr, nullptr, ctx->work,
+                              params->gamma, params->small_dens, params->small_pres, params->limiter,
+                              params->flattening, params->riemann_iters, grav, params->grav, s, nullptr,
+                              STEP_TO_STAGE2),
                   "adjoint recompute");
     if (rc) return rc;
   }
@@ -752,7 +800,8 @@ int ppm_hydro_step_species(ppm_ctx* ctx, const double* U, double* Unew, const do
   if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
   // the hydro step validates the rest and leaves its intermediates in the
   // step workspace for the species stages
-  int rc = ppm_hydro_step(ctx, U, Unew, flux, dt, dt_dev, dx, params, PPM_LAUNCH_BATCHED, stream);
+  int rc = hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, PPM_LAUNCH_BATCHED, stream,
+                           STEP_FULL_STAGED);
   if (rc) return rc;
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
   return ctx->hip(launch_species(ctx->level(), params->precision, (int)ctx->tilesS.size(), (int)ctx->tilesE.size(),

@@ -35,12 +35,16 @@ struct ppm_ctx {
   bool plan_hit = false;
   std::vector<Tile> tilesS, tilesE;
   std::vector<int> tS_begin, tE_begin;  // nbox + 1
+  std::vector<Brick> bricks;
+  std::vector<int> tB_begin;            // nbox + 1
+  int fused = 0;                        // 1: final fluxes + update in one brick kernel
   int tile = TILE, strip_rows = STRIP_ROWS;
   long long LS = 0, LE = 0;
   // device copies
   DevBox* d_boxes = nullptr;
   Tile* d_tilesS = nullptr;
   Tile* d_tilesE = nullptr;
+  Brick* d_bricks = nullptr;
   FillDesc* d_desc = nullptr;
   long long* d_start = nullptr;
   int* d_inv_start = nullptr;
@@ -94,6 +98,8 @@ struct ppm_ctx {
     L.tile = tile;
     for (int f = 0; f < 6; ++f) L.inflow.p[f] = inflow[f];
     for (int d = 0; d < 3; ++d) L.inflow.ext[d] = layout.domain.hi[d] - layout.domain.lo[d] + 1;
+    L.bricks = d_bricks;
+    L.fused = fused;
     return L;
   }
   int fail(int code, const std::string& msg) {

@@ -33,6 +33,23 @@ struct Tile {
   int end;
 };
 
+// A brick: valid zones [o, o + e) of one box (e_d <= BRICK_E[d]), the
+// work unit of the fused final-flux-and-update kernel.  Long in x, so that
+// the lanes of a wavefront read runs of consecutive zones.
+constexpr int BRICK_E[3] = {32, 4, 4};
+constexpr int BRICK_THREADS = 512;
+// faces of the largest axis of a full brick (LDS slots per axis and component)
+constexpr int BRICK_FACES_D(int d) {
+  return (BRICK_E[0] + (d == 0)) * (BRICK_E[1] + (d == 1)) * (BRICK_E[2] + (d == 2));
+}
+constexpr int BRICK_FACES = BRICK_FACES_D(0) > BRICK_FACES_D(1)
+                                ? (BRICK_FACES_D(0) > BRICK_FACES_D(2) ? BRICK_FACES_D(0) : BRICK_FACES_D(2))
+                                : (BRICK_FACES_D(1) > BRICK_FACES_D(2) ? BRICK_FACES_D(1) : BRICK_FACES_D(2));
+struct Brick {
+  int box;
+  int o[3], e[3];
+};
+
 // One copy of the ghost-fill plan: the dst-box-local region [lo, hi] takes
 // its values from src-box-local zone a*x + c (per axis, a in {1, -1, 0}),
 // negating the momentum components flagged in sign.  src < 0: the region
@@ -92,6 +109,8 @@ struct DevLevel {
   long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
   int tile;            // zones per tile of the tile lists (threads per workgroup)
   InflowView inflow;
+  const Brick* bricks;  // valid-zone bricks of every box (fused final stage)
+  int fused;            // 1: final fluxes and update in one brick kernel (fluxes kept in LDS)
 };
 
 }  // namespace ppm
@@ -105,12 +124,17 @@ hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_en
 hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, const double* U,
                              const double h[3], double gamma, double small_pres, double cfl,
                              double* dt_dev, hipStream_t s);
-// The step stages over E-tiles [tE0, tE1) and S-tiles [tS0, tS1).
-hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1,
+// The step stages over E-tiles [tE0, tE1), S-tiles [tS0, tS1) and bricks
+// [tB0, tB1).  upto: STEP_TO_STAGE2 (prim..riemann2, for the adjoint's
+// recompute), STEP_FULL (the whole step; the fused final stage when the
+// level asks for it), STEP_FULL_STAGED (the whole step with the final
+// fluxes left in the workspace, as the species stages need).
+enum { STEP_TO_STAGE2 = 5, STEP_FULL = 7, STEP_FULL_STAGED = 8 };
+hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
                        const double* U, double* Unew, double* const* flux, void* work,
                        const double gamma, const double small_dens, const double small_pres,
                        int limiter, int flattening, int iters, int grav, const double g[3],
-                       hipStream_t s, hipEvent_t* ev, int nstages = 7);
+                       hipStream_t s, hipEvent_t* ev, int upto = STEP_FULL);
 // Adjoint of one FP64 step (ppm_adjoint.hip); the forward workspace must hold
 // the recomputed prim..riemann2 intermediates of the same step.
 size_t adjoint_workspace_bytes(long long LS, long long LE, int precision);

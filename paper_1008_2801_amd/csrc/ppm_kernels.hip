@@ -300,26 +300,18 @@ __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(5
 }
 
 // O9: states of axis d corrected by F^{t1|t2} and F^{t2|t1} (dt/2h), then
-// the final fluxes at d-face slots x_d in [0, n], transverse valid.
+// the final flux at the d-face slot x (x_d in [0, n], transverse valid).
 template <int d, class S>
-__device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, int ntiles,
-                                              const DevBox* __restrict__ boxes, S* __restrict__ work,
-                                              long long LE, const Gas<S>& G,
-                                              const StepConsts* __restrict__ sc, double* fx, double* fy,
-                                              double* fz, int* flags) {
-  const int tt = xcd_tile(ntiles);
-  if (tt < 0) return;
+__device__ __forceinline__ void riemann3_face(const DevBox& B, const int x[3], const S* __restrict__ work,
+                                              long long LE, const Gas<S>& G, const StepConsts* __restrict__ sc,
+                                              S F[5], int& fl) {
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-  const Tile tl = tiles[tt];
-  const DevBox B = boxes[tl.box];
-  EZone z;
-  if (!ezone(tl, B, z)) return;
-  if (z.x[d] < 0 || z.x[t1] < 0 || z.x[t1] >= B.n[t1] || z.x[t2] < 0 || z.x[t2] >= B.n[t2]) return;
-  const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
+  const int E[3] = {B.n[0] + 2, B.n[1] + 2, B.n[2] + 2};
+  const long long e = ((long long)(x[2] + 1) * E[1] + (x[1] + 1)) * E[0] + (x[0] + 1);
+  const long long sd = stride(E, d), s1 = stride(E, t1), s2 = stride(E, t2);
   const S c1 = SC<S>::dt2h(sc)[t1], c2 = SC<S>::dt2h(sc)[t2];
   constexpr int p12 = pair_index(t1, t2), p21 = pair_index(t2, t1);
-  const S* w = work + B.eoff + z.e;
-  int fl = 0;
+  const S* w = work + B.eoff + e;
   S L[5], R[5];
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -336,22 +328,44 @@ __device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, in
     }
     cons_to_prim_floor(ue, G, side == 0 ? L : R, fl);
   }
-  wall_states<d>(B, z.x[d], L, R);
-  S F[5];
+  wall_states<d>(B, x[d], L, R);
   riemann<d>(L, R, G, F, fl);
+}
+
+// Face-centred flux output of face slot x along d (FP64, extents n + e_d).
+template <int d, class S>
+__device__ __forceinline__ void write_flux(const DevBox& B, const int x[3], const S F[5], double* fo) {
+  int fe[3] = {B.n[0], B.n[1], B.n[2]};
+  fe[d] += 1;
+  const long long FN = (long long)fe[0] * fe[1] * fe[2];
+  const long long li = ((long long)x[2] * fe[1] + x[1]) * fe[0] + x[0];
+  double* q = fo + B.foff[d] + li;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) q[m * FN] = (double)F[m];
+}
+
+template <int d, class S>
+__device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, int ntiles,
+                                              const DevBox* __restrict__ boxes, S* __restrict__ work,
+                                              long long LE, const Gas<S>& G,
+                                              const StepConsts* __restrict__ sc, double* fx, double* fy,
+                                              double* fz, int* flags) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  if (!ezone(tl, B, z)) return;
+  if (z.x[d] < 0 || z.x[t1] < 0 || z.x[t1] >= B.n[t1] || z.x[t2] < 0 || z.x[t2] >= B.n[t2]) return;
+  int fl = 0;
+  S F[5];
+  riemann3_face<d>(B, z.x, work, LE, G, sc, F, fl);
   S* o = work + B.eoff + z.e;
 #pragma unroll
   for (int m = 0; m < 5; ++m) o[(E_F3 + d * 5 + m) * LE] = F[m];
   double* fo = d == 0 ? fx : (d == 1 ? fy : fz);
-  if (fo) {
-    int fe[3] = {B.n[0], B.n[1], B.n[2]};
-    fe[d] += 1;
-    const long long FN = (long long)fe[0] * fe[1] * fe[2];
-    const long long li = ((long long)z.x[2] * fe[1] + z.x[1]) * fe[0] + z.x[0];
-    double* q = fo + B.foff[d] + li;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) q[m * FN] = (double)F[m];
-  }
+  if (fo) write_flux<d>(B, z.x, F, fo);
   raise_flags(flags, fl);
 }
 
@@ -365,6 +379,32 @@ __global__ void __launch_bounds__(MAX_TILE) k_riemann3(const Tile* __restrict__ 
     case 0: riemann3_body<0>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
     case 1: riemann3_body<1>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
     default: riemann3_body<2>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+  }
+}
+
+// O10 for one zone: U' = U - ((dt/h_x dFx + dt/h_y dFy) + dt/h_z dFz), then
+// the Heun constant-gravity source.
+__device__ __forceinline__ void update_zone(const double uo[5], const double fxd[5], const double fyd[5],
+                                            const double fzd[5], double dtdx0, double dtdx1, double dtdx2,
+                                            const StepConsts* __restrict__ sc, int grav, double g0, double g1,
+                                            double g2, double un[5]) {
+#pragma unroll
+  for (int m = 0; m < 5; ++m) un[m] = uo[m] - ((dtdx0 * fxd[m] + dtdx1 * fyd[m]) + dtdx2 * fzd[m]);
+  if (grav) {
+    const double adt = sc->dt, hdt = sc->hdt;
+    double s0[5], s1[5];
+    s0[1] = uo[0] * g0;
+    s0[2] = uo[0] * g1;
+    s0[3] = uo[0] * g2;
+    s0[4] = (uo[1] * g0 + uo[2] * g1) + uo[3] * g2;
+#pragma unroll
+    for (int m = 1; m < 5; ++m) un[m] = un[m] + adt * s0[m];
+    s1[1] = un[0] * g0;
+    s1[2] = un[0] * g1;
+    s1[3] = un[0] * g2;
+    s1[4] = (un[1] * g0 + un[2] * g1) + un[3] * g2;
+#pragma unroll
+    for (int m = 1; m < 5; ++m) un[m] = un[m] + hdt * (s1[m] - s0[m]);
   }
 }
 
@@ -391,36 +431,90 @@ __global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ ti
   const long long NS = (long long)N0 * N1 * N2;
   const long long ui = B.soff + ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
   const S* w = work + B.eoff + z.e;
-  double un[5], uo[5];
+  double fxd[5], fyd[5], fzd[5], uo[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const S* f0 = w + (E_F3 + 0 * 5 + m) * LE;
     const S* f1 = w + (E_F3 + 1 * 5 + m) * LE;
     const S* f2 = w + (E_F3 + 2 * 5 + m) * LE;
-    const double fxd = (double)f0[1] - (double)f0[0];
-    const double fyd = (double)f1[sy] - (double)f1[0];
-    const double fzd = (double)f2[sz] - (double)f2[0];
+    fxd[m] = (double)f0[1] - (double)f0[0];
+    fyd[m] = (double)f1[sy] - (double)f1[0];
+    fzd[m] = (double)f2[sz] - (double)f2[0];
     uo[m] = U[ui + m * NS];
-    un[m] = uo[m] - ((dtdx0 * fxd + dtdx1 * fyd) + dtdx2 * fzd);
   }
-  if (grav) {
-    const double adt = sc->dt, hdt = sc->hdt;
-    double s0[5], s1[5];
-    s0[1] = uo[0] * g0;
-    s0[2] = uo[0] * g1;
-    s0[3] = uo[0] * g2;
-    s0[4] = (uo[1] * g0 + uo[2] * g1) + uo[3] * g2;
-#pragma unroll
-    for (int m = 1; m < 5; ++m) un[m] = un[m] + adt * s0[m];
-    s1[1] = un[0] * g0;
-    s1[2] = un[0] * g1;
-    s1[3] = un[0] * g2;
-    s1[4] = (un[1] * g0 + un[2] * g1) + un[3] * g2;
-#pragma unroll
-    for (int m = 1; m < 5; ++m) un[m] = un[m] + hdt * (s1[m] - s0[m]);
-  }
+  double un[5];
+  update_zone(uo, fxd, fyd, fzd, dtdx0, dtdx1, dtdx2, sc, grav, g0, g1, g2, un);
 #pragma unroll
   for (int m = 0; m < 5; ++m) Unew[ui + m * NS] = un[m];
+}
+
+// O9 + O10 fused on a brick of valid zones: the final fluxes of every face
+// of the brick (its boundary faces are computed by both bricks that share
+// them) go to LDS instead of HBM, then each zone of the brick is updated
+// from them.  The arithmetic is riemann3_face and update_zone, so the
+// results are those of the staged kernels bit for bit.
+template <int d, class S>
+__device__ __forceinline__ void brick_faces(const Brick& K, const DevBox& B, const S* __restrict__ work,
+                                            long long LE, const Gas<S>& G, const StepConsts* __restrict__ sc,
+                                            S* __restrict__ Fs, double* fo, int& fl) {
+  int ex[3] = {K.e[0], K.e[1], K.e[2]};
+  ex[d] += 1;
+  const int nf = ex[0] * ex[1] * ex[2];
+  for (int f = threadIdx.x; f < nf; f += BRICK_THREADS) {
+    const int x[3] = {K.o[0] + f % ex[0], K.o[1] + (f / ex[0]) % ex[1], K.o[2] + f / (ex[0] * ex[1])};
+    S F[5];
+    riemann3_face<d>(B, x, work, LE, G, sc, F, fl);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Fs[m * BRICK_FACES + f] = F[m];
+    if (fo) write_flux<d>(B, x, F, fo);
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(BRICK_THREADS) k_final_update(const Brick* __restrict__ bricks, int nbricks,
+                                                            const DevBox* __restrict__ boxes,
+                                                            const S* __restrict__ work, long long LE, Gas<S> G,
+                                                            const StepConsts* __restrict__ sc,
+                                                            const double* __restrict__ U, double* __restrict__ Unew,
+                                                            double* fx, double* fy, double* fz, int grav, double g0,
+                                                            double g1, double g2, int* flags) {
+  __shared__ S Fs[3 * 5 * BRICK_FACES];
+  const int k = xcd_tile(nbricks);
+  if (k < 0) return;
+  const Brick K = bricks[k];
+  const DevBox B = boxes[K.box];
+  int fl = 0;
+  brick_faces<0>(K, B, work, LE, G, sc, Fs, fx, fl);
+  brick_faces<1>(K, B, work, LE, G, sc, Fs + 5 * BRICK_FACES, fy, fl);
+  brick_faces<2>(K, B, work, LE, G, sc, Fs + 10 * BRICK_FACES, fz, fl);
+  raise_flags(flags, fl);
+  __syncthreads();
+  const int e0 = K.e[0], e1 = K.e[1], e2 = K.e[2];
+  const double dtdx0 = sc->dtdx[0], dtdx1 = sc->dtdx[1], dtdx2 = sc->dtdx[2];
+  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
+  const long long NS = (long long)N0 * N1 * N2;
+  for (int z = threadIdx.x; z < e0 * e1 * e2; z += BRICK_THREADS) {
+    const int l0 = z % e0, l1 = (z / e0) % e1, l2 = z / (e0 * e1);
+    const int ix = (l2 * e1 + l1) * (e0 + 1) + l0;        // x-face below the zone
+    const int iy = (l2 * (e1 + 1) + l1) * e0 + l0;        // y-face below
+    const int iz = (l2 * e1 + l1) * e0 + l0;              // z-face below
+    const long long ui = B.soff + ((long long)(K.o[2] + l2 + NG) * N1 + (K.o[1] + l1 + NG)) * N0 +
+                         (K.o[0] + l0 + NG);
+    double fxd[5], fyd[5], fzd[5], uo[5], un[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const S* F0 = Fs + m * BRICK_FACES;
+      const S* F1 = Fs + (5 + m) * BRICK_FACES;
+      const S* F2 = Fs + (10 + m) * BRICK_FACES;
+      fxd[m] = (double)F0[ix + 1] - (double)F0[ix];
+      fyd[m] = (double)F1[iy + e0] - (double)F1[iy];
+      fzd[m] = (double)F2[iz + e0 * e1] - (double)F2[iz];
+      uo[m] = U[ui + m * NS];
+    }
+    update_zone(uo, fxd, fyd, fzd, dtdx0, dtdx1, dtdx2, sc, grav, g0, g1, g2, un);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Unew[ui + m * NS] = un[m];
+  }
 }
 
 // O11: max over valid zones and axes of (|u_d| + c)/h_d, FP64.  A fixed grid
@@ -530,9 +624,9 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restric
 
 
 template <class S>
-hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, const double* U, double* Unew,
-                     double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
-                     hipEvent_t* ev, int nstages) {
+hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, const double* U,
+                     double* Unew, double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
+                     hipEvent_t* ev, int upto) {
   S* prim = (S*)work;
   S* ework = prim + P_PLANES * L.LS;
   const int nS = tS1 - tS0, nE = tE1 - tE0;
@@ -553,11 +647,20 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, cons
   if (ev) (void)hipEventRecord(ev[4], s);
   hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
                      L.consts, L.flags);
-  if (nstages <= 5) return hipGetLastError();
+  if (upto <= STEP_TO_STAGE2) return hipGetLastError();
   double* fx = flux ? flux[0] : nullptr;
   double* fy = flux ? flux[1] : nullptr;
   double* fz = flux ? flux[2] : nullptr;
   if (ev) (void)hipEventRecord(ev[5], s);
+  const int nB = tB1 - tB0;
+  if (L.fused && upto == STEP_FULL && nB > 0) {
+    hipLaunchKernelGGL(k_final_update<S>, dim3(xcd_grid(nB)), dim3(BRICK_THREADS), 0, s, L.bricks + tB0, nB,
+                       L.boxes, (const S*)ework, L.LE, G, L.consts, U, Unew, fx, fy, fz, G.grav, g[0], g[1], g[2],
+                       L.flags);
+    if (ev) (void)hipEventRecord(ev[6], s);
+    if (ev) (void)hipEventRecord(ev[7], s);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_riemann3<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
                      L.consts, fx, fy, fz, L.flags);
   if (ev) (void)hipEventRecord(ev[6], s);
@@ -599,17 +702,17 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
   return hipGetLastError();
 }
 
-hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, const double* U,
-                       double* Unew, double* const* flux, void* work, const double gamma,
+hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
+                       const double* U, double* Unew, double* const* flux, void* work, const double gamma,
                        const double small_dens, const double small_pres, int limiter, int flattening,
-                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev, int nstages) {
+                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev, int upto) {
   if (precision == 1)
-    return step_impl<float>(L, tS0, tS1, tE0, tE1, U, Unew, flux, work,
+    return step_impl<float>(L, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
                             make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
-                            g, s, ev, nstages);
-  return step_impl<double>(L, tS0, tS1, tE0, tE1, U, Unew, flux, work,
+                            g, s, ev, upto);
+  return step_impl<double>(L, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
                            make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
-                           g, s, ev, nstages);
+                           g, s, ev, upto);
 }
 
 }  // namespace ppm

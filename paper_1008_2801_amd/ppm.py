@@ -31,7 +31,7 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_species_workspace_bytes", "ppm_set_species_workspace", "ppm_fill_species",
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
-           "ppm_hydro_step_adjoint_saved")
+           "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -116,6 +116,8 @@ def lib():
         L.ppm_hydro_step_adjoint_saved.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
                                                    ctypes.POINTER(Params), _vp]
         L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
+        L.ppm_set_step_form.argtypes = [_vp, ctypes.c_int32]
+        L.ppm_get_step_form.argtypes = [_vp, _i32p]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.ppm_amr_destroy.argtypes = [_vp]
         L.ppm_amr_last_error.argtypes = [_vp]
@@ -318,6 +320,16 @@ class Level:
 
     def set_tiling(self, tile, strip_rows):
         self._check(lib().ppm_set_tiling(self.ctx, int(tile), int(strip_rows)), "ppm_set_tiling")
+
+    def set_step_form(self, fused):
+        """fused=True: final fluxes and update in one brick kernel (LDS);
+        False: the staged pair of kernels.  Same results."""
+        self._check(lib().ppm_set_step_form(self.ctx, int(bool(fused))), "ppm_set_step_form")
+
+    def get_step_form(self):
+        f = ctypes.c_int32()
+        self._check(lib().ppm_get_step_form(self.ctx, ctypes.byref(f)), "ppm_get_step_form")
+        return bool(f.value)
 
     def get_tiling(self):
         t, s = ctypes.c_int32(), ctypes.c_int32()
