@@ -121,6 +121,7 @@ template <class S> inline S sabs(S a) { return (V(a) < 0) ? -a : a; }
 // |m| carrying the sign of s (m >= 0 on every call site).
 template <class S> inline S scopysign(S m, S s) { return std::signbit(V(s)) ? -m : m; }
 
+
 inline double ssqrt(double x) { return std::sqrt(x); }
 inline float ssqrt(float x) { return std::sqrt(x); }
 inline Counted ssqrt(Counted x) { g_ops[g_stage][OP_SQRT]++; return Counted(std::sqrt(x.v)); }
@@ -166,6 +167,35 @@ const int NG = 4;  // ghost width: flattening reaches 3 zones past a traced zone
 
 // Per-step constants in the reconstruction scalar.  They are formed in FP64
 // from gamma, dt and h, then rounded to S once.
+// Scalars whose primal is FP32 (the FP32-reconstruction mode).  The product
+// of two wave speeds W = rho c can leave the FP32 range (W reaches 1e19 in
+// white-dwarf matter in cgs units), so these take 1/W_L and 1/W_R by two
+// divisions; the FP64 scalars take both from one division, 1/(W_L W_R), as
+// 1/W_L = W_R/(W_L W_R).
+template <class S> struct F32Primal { static constexpr bool value = false; };
+template <> struct F32Primal<float> { static constexpr bool value = true; };
+template <> struct F32Primal<DualF> { static constexpr bool value = true; };
+
+// a b > 0.  The CW84 tests compare products of two differences of one
+// field, which for the pressure or energy of stellar matter in cgs units
+// (1e22 and up) leave the FP32 range: FP32 scalars decide from the signs of
+// a and b, FP64 scalars from the product.
+template <class S> inline bool same_sign(S a, S b) {
+  if constexpr (F32Primal<S>::value) return (V(a) > 0 && V(b) > 0) || (V(a) < 0 && V(b) < 0);
+  else return V(a * b) > 0;
+}
+
+template <class S> void pair_reciprocals(S a, S b, S one, S& ia, S& ib) {
+  if constexpr (F32Primal<S>::value) {
+    ia = one / a;
+    ib = one / b;
+  } else {
+    const S iab = one / (a * b);
+    ia = b * iab;
+    ib = a * iab;
+  }
+}
+
 template <class S> struct Consts {
   S gamma, gm1, gm1inv, beta, small_dens, small_pres, ismall_dens;
   S dtdx[3], dt2h[3], dt3h[3], hdtg[3];
@@ -225,8 +255,8 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   for (int it = 0; it < K.iters; ++it) {
     const S wl = cl * ssqrt(K.one + K.beta * (p * ipl - K.one));
     const S wr = cr * ssqrt(K.one + K.beta * (p * ipr - K.one));
-    const S iww = K.one / (wl * wr);  // one division for both 1/W_s
-    const S iwl = wr * iww, iwr = wl * iww;
+    S iwl, iwr;
+    pair_reciprocals(wl, wr, K.one, iwl, iwr);
     const S xl = cl * iwl, xr = cr * iwr;
     const S izl = K.half * iwl * (K.one + xl * xl);
     const S izr = K.half * iwr * (K.one + xr * xr);
@@ -238,8 +268,8 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   }
   const S wl = cl * ssqrt(K.one + K.beta * (p * ipl - K.one));
   const S wr = cr * ssqrt(K.one + K.beta * (p * ipr - K.one));
-  const S iww = K.one / (wl * wr);
-  const S iwl = wr * iww, iwr = wl * iww;
+  S iwl, iwr;
+  pair_reciprocals(wl, wr, K.one, iwl, iwr);
   const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
 
   // Sample the wave fan at x/t = 0 on one side of the contact.  Outer state:
@@ -328,7 +358,7 @@ S ppm_slope(S am, S a0, S ap, const Consts<S>& K) {
   const S dc = K.half * (ap - am);
   if (!K.limiter) return dc;
   const S dl = a0 - am, dr = ap - a0;
-  if (V(dl * dr) > 0) return scopysign(smin(smin(sabs(dc), K.two * sabs(dl)), K.two * sabs(dr)), dc);
+  if (same_sign(dl, dr)) return scopysign(smin(smin(sabs(dc), K.two * sabs(dl)), K.two * sabs(dr)), dc);
   return S(0.0);
 }
 
@@ -350,16 +380,30 @@ void ppm_parabola(const S a[5], S phi, const Consts<S>& K, S& aL, S& aR, S& a6) 
       aL = phi * aL + omp * a0;
       aR = phi * aR + omp * a0;
     }
-    if (V((aR - a0) * (a0 - aL)) <= 0) {
+    // a0 is an extremum when (aR - a0)(a0 - aL) <= 0; otherwise the
+    // parabola overshoots an edge when dq (a0 - mid) > dq^2/6 (or
+    // < -dq^2/6).  In FP32 these are decided from signs: dq and
+    // a0 - mid -/+ dq/6 have the same (opposite) sign.
+    if (!same_sign(aR - a0, a0 - aL)) {
       aL = a0;
       aR = a0;
     } else {
       const S dq = aR - aL;
-      const S t = dq * (a0 - K.half * (aL + aR));
-      const S d2 = dq * dq * K.sixth;
-      if (V(t) > V(d2)) {
+      const S m = a0 - K.half * (aL + aR);
+      bool hi, lo;
+      if constexpr (F32Primal<S>::value) {
+        const S q = dq * K.sixth;
+        hi = same_sign(dq, m - q);
+        lo = same_sign(dq, -(m + q));
+      } else {
+        const S t = dq * m;
+        const S d2 = dq * dq * K.sixth;
+        hi = V(t) > V(d2);
+        lo = V(-d2) > V(t);
+      }
+      if (hi) {
         aL = K.three * a0 - K.two * aR;
-      } else if (V(-d2) > V(t)) {
+      } else if (lo) {
         aR = K.three * a0 - K.two * aL;
       }
     }

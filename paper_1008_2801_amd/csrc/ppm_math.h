@@ -30,6 +30,28 @@ template <class S> PPM_HD S sabs(S a) { return (a < S(0)) ? -a : a; }
 PPM_HD double ssqrt(double x) { return __builtin_sqrt(x); }
 PPM_HD float ssqrt(float x) { return __builtin_sqrtf(x); }
 template <class S> PPM_HD S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
+// a b > 0.  The CW84 tests compare products of two differences of one
+// field, which for the pressure or energy of stellar matter in cgs units
+// (1e22 and up) leave the FP32 range: FP32 decides from the signs of a and
+// b, FP64 from the product.
+template <class S> PPM_HD bool same_sign(S a, S b) {
+  if constexpr (sizeof(S) == 4) return (a > S(0) && b > S(0)) || (a < S(0) && b < S(0));
+  else return a * b > S(0);
+}
+
+// 1/a and 1/b of the two wave speeds W_L, W_R.  FP64: from one division,
+// 1/a = b/(a b).  FP32: two divisions, since the product of two wave speeds
+// of stellar matter in cgs units can leave the FP32 range.
+template <class S> PPM_HD void pair_recip(S a, S b, S& ia, S& ib) {
+  if constexpr (sizeof(S) == 4) {
+    ia = S(1) / a;
+    ib = S(1) / b;
+  } else {
+    const S iab = S(1) / (a * b);
+    ia = b * iab;
+    ib = a * iab;
+  }
+}
 
 #define HALF S(0.5)
 #define ONE S(1.0)
@@ -41,6 +63,21 @@ template <class S> PPM_HD S scopysign(S m, S s) { return __builtin_signbit(s) ? 
 #define C033 S(0.33)
 #define TEN S(10.0)
 #define C075 S(0.75)
+
+// The CW84 overshoot tests dq m > dq^2/6 (hi) and dq m < -dq^2/6 (lo),
+// m = a0 - (aL + aR)/2; in FP32 from the signs of dq and m -/+ dq/6.
+template <class S> PPM_HD void cw_overshoot(S dq, S m, bool& hi, bool& lo) {
+  if constexpr (sizeof(S) == 4) {
+    const S q = dq * SIXTH;
+    hi = same_sign(dq, m - q);
+    lo = same_sign(dq, -(m + q));
+  } else {
+    const S t = dq * m;
+    const S d2 = dq * dq * SIXTH;
+    hi = t > d2;
+    lo = -d2 > t;
+  }
+}
 
 // ------------------------------------------------------- O6: Riemann -------
 // Fan sampling on the left side of the contact for (rho, u, p) with the
@@ -90,8 +127,8 @@ PPM_HD void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl
   for (int it = 0; it < G.iters; ++it) {
     const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
     const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-    const S iww = ONE / (wl * wr);  // one division for both 1/W_s
-    const S iwl = wr * iww, iwr = wl * iww;
+    S iwl, iwr;
+    pair_recip(wl, wr, iwl, iwr);
     const S xl = cl * iwl, xr = cr * iwr;
     const S izl = HALF * iwl * (ONE + xl * xl);
     const S izr = HALF * iwr * (ONE + xr * xr);
@@ -103,8 +140,8 @@ PPM_HD void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl
   }
   const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
   const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-  const S iww = ONE / (wl * wr);
-  const S iwl = wr * iww, iwr = wl * iww;
+  S iwl, iwr;
+  pair_recip(wl, wr, iwl, iwr);
   const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
 
   S g0, g1, g2, g3, g4;
@@ -150,7 +187,7 @@ PPM_HD S ppm_slope(S am, S a0, S ap, int limiter) {
   const S dc = HALF * (ap - am);
   if (!limiter) return dc;
   const S dl = a0 - am, dr = ap - a0;
-  if (dl * dr > S(0)) return scopysign(smin(smin(sabs(dc), TWO * sabs(dl)), TWO * sabs(dr)), dc);
+  if (same_sign(dl, dr)) return scopysign(smin(smin(sabs(dc), TWO * sabs(dl)), TWO * sabs(dr)), dc);
   return S(0);
 }
 
@@ -168,16 +205,15 @@ PPM_HD void ppm_parabola(S am2, S am1, S a0, S ap1, S ap2, S phi, const Gas<S>& 
       aL = phi * aL + omp * a0;
       aR = phi * aR + omp * a0;
     }
-    if ((aR - a0) * (a0 - aL) <= S(0)) {
+    if (!same_sign(aR - a0, a0 - aL)) {  // a0 is an extremum
       aL = a0;
       aR = a0;
     } else {
-      const S dq = aR - aL;
-      const S t = dq * (a0 - HALF * (aL + aR));
-      const S d2 = dq * dq * SIXTH;
-      if (t > d2) {
+      bool hi, lo;
+      cw_overshoot(aR - aL, a0 - HALF * (aL + aR), hi, lo);
+      if (hi) {
         aL = THREE * a0 - TWO * aR;
-      } else if (-d2 > t) {
+      } else if (lo) {
         aR = THREE * a0 - TWO * aL;
       }
     }

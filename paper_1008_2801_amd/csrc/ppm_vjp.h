@@ -105,8 +105,8 @@ template <class S>
 PPM_HD S riem_iter(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G) {
   const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
   const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
-  const S iww = ONE / (wl * wr);
-  const S iwl = wr * iww, iwr = wl * iww;
+  S iwl, iwr;
+  pair_recip(wl, wr, iwl, iwr);
   const S xl = cl * iwl, xr = cr * iwr;
   const S izl = HALF * iwl * (ONE + xl * xl);
   const S izr = HALF * iwr * (ONE + xr * xr);
@@ -129,8 +129,8 @@ PPM_HD S riem_iter_rec(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   const S sl = ssqrt(ONE + G.beta * (p * ipl - ONE));
   const S sr = ssqrt(ONE + G.beta * (p * ipr - ONE));
   const S wl = cl * sl, wr = cr * sr;
-  const S iww = ONE / (wl * wr);
-  const S iwl = wr * iww, iwr = wl * iww;
+  S iwl, iwr;
+  pair_recip(wl, wr, iwl, iwr);
   const S xl = cl * iwl, xr = cr * iwr;
   const S izl = HALF * iwl * (ONE + xl * xl);
   const S izr = HALF * iwr * (ONE + xr * xr);
@@ -227,8 +227,8 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   const S all = ONE + G.beta * (pst * ipl - ONE), alr = ONE + G.beta * (pst * ipr - ONE);
   const S sl = ssqrt(all), sr = ssqrt(alr);
   const S wl = cl * sl, wr = cr * sr;
-  const S iww = ONE / (wl * wr);
-  const S iwl = wr * iww, iwr = wl * iww;
+  S iwl, iwr;
+  pair_recip(wl, wr, iwl, iwr);
   const S NU = (wl * ul + wr * ur) + (pl - pr), DU = wl + wr;
   const S us = NU / DU;
 
@@ -430,7 +430,7 @@ PPM_HD void ppm_slope_vjp(S am, S a0, S ap, int limiter, S sb, S& amb, S& a0b, S
     dcb = sb;
   } else {
     const S dl = a0 - am, dr = ap - a0;
-    if (!(dl * dr > S(0))) return;
+    if (!same_sign(dl, dr)) return;
     const S A = sabs(dc), B = TWO * sabs(dl), C = TWO * sabs(dr);
     const S m1 = smin(A, B);
     const bool selA = !(B < A);
@@ -473,19 +473,18 @@ PPM_HD void ppm_parabola_vjp(const S a[5], S phi, const Gas<S>& G, S aLb, S aRb,
   ab[2] += SIX * a6b;
   S aL1b = aL2b, aR1b = aR2b;
   if (G.limiter) {
-    if ((aR1 - a0) * (a0 - aL1) <= S(0)) {
+    if (!same_sign(aR1 - a0, a0 - aL1)) {
       ab[2] += aL2b + aR2b;
       aL1b = S(0);
       aR1b = S(0);
     } else {
-      const S dq = aR1 - aL1;
-      const S t = dq * (a0 - HALF * (aL1 + aR1));
-      const S d2 = dq * dq * SIXTH;
-      if (t > d2) {
+      bool hi, lo;
+      cw_overshoot(aR1 - aL1, a0 - HALF * (aL1 + aR1), hi, lo);
+      if (hi) {
         ab[2] += THREE * aL2b;
         aR1b = aR2b - TWO * aL2b;
         aL1b = S(0);
-      } else if (-d2 > t) {
+      } else if (lo) {
         ab[2] += THREE * aR2b;
         aL1b = aL2b - TWO * aR2b;
         aR1b = S(0);

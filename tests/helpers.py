@@ -1,4 +1,7 @@
 """Shared helpers of the test suite (inputs and comparisons only)."""
+import copy
+import math
+
 import numpy as np
 
 NG = 4
@@ -26,3 +29,24 @@ def field_errors(A, B):
         s = np.abs(B[c]).max()
         e.append(np.abs(A[c] - B[c]).max() / (s if s > 0 else scale4))
     return np.array(e)
+
+
+# Density and pressure factors of a change of units (velocity: their ratio's
+# square root, 2^26; lengths unchanged).  Powers of two, so that every
+# floating-point operation of a dimensionally consistent step scales exactly.
+# They take unit-scale states to rho ~ 1e6 and p ~ 5e21, the magnitudes of a
+# white dwarf's outer layers in cgs units.
+UNIT_R, UNIT_P = 2.0 ** 20, 2.0 ** 72
+
+
+def rescaled(wl, R=UNIT_R, P=UNIT_P):
+    """A copy of a Workload in units where density is R times and pressure P
+    times larger: momentum scales by R V, energy by P, gravity by V^2 (V =
+    sqrt(P / R)).  Returns (workload, per-field factors, V)."""
+    V = math.sqrt(P / R)
+    w = copy.deepcopy(wl)
+    sc = np.array([R, R * V, R * V, R * V, P])
+    for b in range(w.layout.nbox):
+        w.layout.view(w.arena, b)[...] *= sc[:, None, None, None]
+    w.grav = tuple(g * V * V for g in wl.grav)
+    return w, sc[:, None, None, None], V

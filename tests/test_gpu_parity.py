@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O  # noqa: E402
 from paper_1008_2801_amd import inputs as I  # noqa: E402
 from paper_1008_2801_amd import ppm as P  # noqa: E402
-from tests.helpers import interior, field_errors  # noqa: E402
+from tests.helpers import interior, field_errors, rescaled  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -395,3 +395,29 @@ def test_fused_and_staged_final_stage_agree_bitwise(precision):
             assert np.array_equal(interior(lay.view(u, b)), interior(lay.view(ref_u, b)))
         for d in range(3):
             assert np.array_equal(f[d], ref_f[d])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_power_of_two_change_of_units_on_gpu(precision):
+    """Density x 2^20 and pressure x 2^72 (a white dwarf's outer layers in
+    cgs units), gravity on: the GPU run in the new units is the scaled GPU
+    run in the old ones bit for bit, dt included, and matches the oracle at
+    these magnitudes (FP64: the bitwise bar; FP32 mode: 1e-6)."""
+    wl = I.cfg2(16)
+    wl.grav = (0.3, -0.2, 0.1)
+    wl.precision = precision
+    ws, sc, V = rescaled(wl)
+    print(f"change of units, precision {precision}", flush=True)
+    _, a, dts, fl, _ = gpu_run(wl, 3)
+    _, b, dtss, fls, _ = gpu_run(ws, 3)
+    assert fl == fls == 0
+    assert dtss == [d / V for d in dts]
+    lay = wl.layout
+    for bx in range(lay.nbox):
+        assert np.array_equal(lay.view(b, bx)[:, 4:-4, 4:-4, 4:-4], lay.view(a, bx)[:, 4:-4, 4:-4, 4:-4] * sc)
+    ost, odts, ofl, _ = oracle_run(ws, 3)
+    assert ofl == 0
+    if precision == 0:
+        assert odts == dtss
+    worst, nbits = compare_level(ws, b, ost, tol=TOL if precision == 0 else 1e-6)
+    print(f"max field error vs oracle {worst:.3e}, differing values {nbits}")
