@@ -90,6 +90,15 @@ def test_invalid_layouts_rejected(lo, hi, dom, bc):
         P.plan_build(lay)
 
 
+def test_empty_layout_rejected():
+    """A level without boxes has nothing to advance: the library refuses it
+    (PPM_EINVAL, "no boxes") rather than building an empty plan."""
+    none = np.zeros((0, 3), dtype=np.int64)
+    lay = I.Layout(none, none, (0, 0, 0), (3, 3, 3), (0,) * 6)
+    with pytest.raises(P.PPMError):
+        P.plan_build(lay)
+
+
 def _apply_plan(lay, desc, arena, inflow):
     """Execute fill descriptors (ndesc, 20) in numpy: copies between boxes,
     and for src < 0 the prescribed state of the inflow face -1 - src."""
