@@ -319,6 +319,16 @@ int ppm_get_tiling(const ppm_ctx* ctx, int32_t* tile, int32_t* strip_rows);
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused);
 int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused);
 
+/* Diagnostic: out[i] = the FP64 square root the Riemann solver takes of its
+ * wave-speed factor 1 + beta (p/p_s - 1) (>= 1 - beta > 0; the Lagrangian
+ * shock speed of Colella-Glaz 1985 is C_s times it), computed on the device
+ * for n arguments x[i].  x and out are device pointers of n doubles, owned
+ * by the caller; asynchronous on the stream.  The kernels use a shortened
+ * form of the compiler's correctly rounded square root; for every finite
+ * x >= 2^-767 it returns the IEEE square root, which a test checks against
+ * the host's.  PPM_EINVAL for n < 0 or null pointers with n > 0. */
+int ppm_sqrt_wave_values(const double* x, double* out, int64_t n, void* stream);
+
 /* Autotuner: times the batched step (reps steps after one warm-up, HIP
  * events on the stream) from the filled state U into Unew for every
  * candidate tile size x strip height, keeps the fastest, and appends it to

@@ -668,6 +668,11 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
   return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL);
 }
 
+int ppm_sqrt_wave_values(const double* x, double* out, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !out))) return PPM_EINVAL;
+  return ppm::launch_sqrt_wave(x, out, n, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
+}
+
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused) {
   if (!ctx) return PPM_EINVAL;
   if (fused != 0 && fused != 1) return ctx->fail(PPM_EINVAL, "set_step_form: fused must be 0 or 1");

@@ -670,6 +670,13 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
   return hipGetLastError();
 }
 
+// Values of the FP64 wave-speed root for a list of arguments (grid-stride).
+__global__ void __launch_bounds__(256) k_sqrt_wave(const double* __restrict__ x, double* __restrict__ out,
+                                                   long long n) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    out[i] = sqrt_wave(x[i]);
+}
+
 }  // namespace
 
 hipError_t launch_step_consts(const DevLevel& L, double dt, const double* dt_dev, const double h[3],
@@ -699,6 +706,13 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
     hipLaunchKernelGGL(k_wavespeed, dim3(n < 2048 ? n : 2048), dim3(L.tile), 0, s, L.tilesE + tile_begin, n, L.boxes, U,
                        h[0], h[1], h[2], gamma, gamma - 1.0, small_pres, bits);
   hipLaunchKernelGGL(k_finish_dt, dim3(1), dim3(64), 0, s, dt_dev, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_wave(const double* x, double* out, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_sqrt_wave, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, s, x, out, n);
   return hipGetLastError();
 }
 

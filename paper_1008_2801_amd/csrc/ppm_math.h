@@ -29,6 +29,31 @@ template <class S> PPM_HD S smin(S a, S b) { return (b < a) ? b : a; }
 template <class S> PPM_HD S sabs(S a) { return (a < S(0)) ? -a : a; }
 PPM_HD double ssqrt(double x) { return __builtin_sqrt(x); }
 PPM_HD float ssqrt(float x) { return __builtin_sqrtf(x); }
+// Square root of the two-shock wave-speed factor 1 + beta (p/p_s - 1),
+// which is at least 1 - beta > 0.  FP64 on the device: the core of the
+// correctly rounded square root hipcc emits (hardware reciprocal square
+// root, one Newton-Raphson step on the root and the half reciprocal, two
+// residual corrections of the root), without the rescaling of arguments
+// below 2^-767 and the fix-up of 0 and +inf that surround it.  For every
+// finite argument >= 2^-767 the two are the same instructions and give the
+// same bits: 10 instructions instead of 18.  Elsewhere the library root.
+PPM_HD double sqrt_wave(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r;
+  double h = r * 0.5;
+  const double e = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, e, g);
+  h = __builtin_fma(h, e, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  return __builtin_fma(d, h, g);
+#else
+  return __builtin_sqrt(x);
+#endif
+}
+PPM_HD float sqrt_wave(float x) { return __builtin_sqrtf(x); }
 template <class S> PPM_HD S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
 // a b > 0.  The CW84 tests compare products of two differences of one
 // field, which for the pressure or energy of stellar matter in cgs units
@@ -125,8 +150,8 @@ PPM_HD void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl
   p = smax(p, G.small_pres);
   const S ipl = ONE / pl, ipr = ONE / pr;
   for (int it = 0; it < G.iters; ++it) {
-    const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
-    const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
+    const S wl = cl * sqrt_wave(ONE + G.beta * (p * ipl - ONE));
+    const S wr = cr * sqrt_wave(ONE + G.beta * (p * ipr - ONE));
     S iwl, iwr;
     pair_recip(wl, wr, iwl, iwr);
     const S xl = cl * iwl, xr = cr * iwr;
@@ -138,8 +163,8 @@ PPM_HD void riemann(const S L[5], const S R[5], const Gas<S>& G, S F[5], int& fl
     if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
     p = smax(p, G.small_pres);
   }
-  const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
-  const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
+  const S wl = cl * sqrt_wave(ONE + G.beta * (p * ipl - ONE));
+  const S wr = cr * sqrt_wave(ONE + G.beta * (p * ipr - ONE));
   S iwl, iwr;
   pair_recip(wl, wr, iwl, iwr);
   const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);

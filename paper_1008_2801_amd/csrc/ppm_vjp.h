@@ -103,8 +103,8 @@ constexpr int RIEM_KEEP = 3;
 // One Newton step of the two-shock iteration, forward (returns the new p).
 template <class S>
 PPM_HD S riem_iter(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G) {
-  const S wl = cl * ssqrt(ONE + G.beta * (p * ipl - ONE));
-  const S wr = cr * ssqrt(ONE + G.beta * (p * ipr - ONE));
+  const S wl = cl * sqrt_wave(ONE + G.beta * (p * ipl - ONE));
+  const S wr = cr * sqrt_wave(ONE + G.beta * (p * ipr - ONE));
   S iwl, iwr;
   pair_recip(wl, wr, iwl, iwr);
   const S xl = cl * iwl, xr = cr * iwr;
@@ -126,8 +126,8 @@ template <class S> struct RiemIt {
 // what its reverse needs.
 template <class S>
 PPM_HD S riem_iter_rec(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const Gas<S>& G, RiemIt<S>& r) {
-  const S sl = ssqrt(ONE + G.beta * (p * ipl - ONE));
-  const S sr = ssqrt(ONE + G.beta * (p * ipr - ONE));
+  const S sl = sqrt_wave(ONE + G.beta * (p * ipl - ONE));
+  const S sr = sqrt_wave(ONE + G.beta * (p * ipr - ONE));
   const S wl = cl * sl, wr = cr * sr;
   S iwl, iwr;
   pair_recip(wl, wr, iwl, iwr);
@@ -225,7 +225,7 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   const S pkeep = pst;
   for (int it = RIEM_KEEP; it < G.iters; ++it) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
   const S all = ONE + G.beta * (pst * ipl - ONE), alr = ONE + G.beta * (pst * ipr - ONE);
-  const S sl = ssqrt(all), sr = ssqrt(alr);
+  const S sl = sqrt_wave(all), sr = sqrt_wave(alr);
   const S wl = cl * sl, wr = cr * sr;
   S iwl, iwr;
   pair_recip(wl, wr, iwl, iwr);

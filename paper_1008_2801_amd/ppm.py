@@ -31,7 +31,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_species_workspace_bytes", "ppm_set_species_workspace", "ppm_fill_species",
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
-           "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form")
+           "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
+           "ppm_sqrt_wave_values")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -118,6 +119,7 @@ def lib():
         L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
         L.ppm_set_step_form.argtypes = [_vp, ctypes.c_int32]
         L.ppm_get_step_form.argtypes = [_vp, _i32p]
+        L.ppm_sqrt_wave_values.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.ppm_amr_destroy.argtypes = [_vp]
         L.ppm_amr_last_error.argtypes = [_vp]
@@ -192,6 +194,19 @@ def plan_cache_stats():
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
     lib().ppm_plan_cache_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return a.value, b.value, c.value
+
+
+def sqrt_wave_values(x, stream=None):
+    """Device values of the Riemann solver's FP64 wave-speed root for the
+    float64 CUDA tensor x (diagnostic; ppm_sqrt_wave_values)."""
+    import torch
+    if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
+        raise PPMError("sqrt_wave_values: x must be a contiguous float64 CUDA tensor")
+    out = torch.empty_like(x)
+    rc = lib().ppm_sqrt_wave_values(_ptr(x), _ptr(out), x.numel(), _stream(stream))
+    if rc != 0:
+        raise PPMError(f"ppm_sqrt_wave_values failed ({rc})")
+    return out
 
 
 def _stream(stream=None):

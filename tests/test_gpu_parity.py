@@ -421,3 +421,27 @@ def test_power_of_two_change_of_units_on_gpu(precision):
         assert odts == dtss
     worst, nbits = compare_level(ws, b, ost, tol=TOL if precision == 0 else 1e-6)
     print(f"max field error vs oracle {worst:.3e}, differing values {nbits}")
+
+
+def test_wave_speed_root_is_the_ieee_root():
+    """The Riemann solver takes the root of its wave-speed factor with a
+    shortened form of the compiler's correctly rounded FP64 square root
+    (no rescaling of arguments below 2^-767, no fix-up of 0 and inf).  It
+    must return the IEEE root, bit for bit, for every finite argument from
+    2^-767 up: 2^20 random arguments with exponents uniform over that range,
+    the factor's own range near 1 - beta, and the end points."""
+    rng = np.random.default_rng(12)
+    n = 1 << 20
+    mant = rng.integers(0, 1 << 52, size=n, dtype=np.uint64)
+    expo = rng.integers(-767, 1024, size=n).astype(np.int64)
+    bits = ((expo + 1023).astype(np.uint64) << np.uint64(52)) | mant
+    x = bits.view(np.float64)
+    beta = (1.4 + 1.0) / 2.8
+    near = 1.0 - beta + rng.uniform(0.0, 4.0, size=4096) ** 3
+    ends = np.array([2.0 ** -767, np.nextafter(2.0 ** -767, 1.0), 1.0 - beta, 1.0, 2.0, 4.0,
+                     np.finfo(np.float64).max, np.nextafter(np.finfo(np.float64).max, 0.0)])
+    x = np.concatenate([x, near, ends])
+    got = P.sqrt_wave_values(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = np.sqrt(x)
+    bad = np.flatnonzero(got.view(np.uint64) != ref.view(np.uint64))
+    assert bad.size == 0, (bad.size, x[bad[:5]], got[bad[:5]], ref[bad[:5]])
