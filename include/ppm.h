@@ -319,15 +319,31 @@ int ppm_get_tiling(const ppm_ctx* ctx, int32_t* tile, int32_t* strip_rows);
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused);
 int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused);
 
-/* Diagnostic: out[i] = the FP64 square root the Riemann solver takes of its
- * wave-speed factor 1 + beta (p/p_s - 1) (>= 1 - beta > 0; the Lagrangian
- * shock speed of Colella-Glaz 1985 is C_s times it), computed on the device
- * for n arguments x[i].  x and out are device pointers of n doubles, owned
- * by the caller; asynchronous on the stream.  The kernels use a shortened
- * form of the compiler's correctly rounded square root; for every finite
- * x >= 2^-767 it returns the IEEE square root, which a test checks against
- * the host's.  PPM_EINVAL for n < 0 or null pointers with n > 0. */
-int ppm_sqrt_wave_values(const double* x, double* out, int64_t n, void* stream);
+/* Diagnostic: out[i] = one of the FP64 square roots the Riemann solver
+ * takes, computed on the device for n arguments x[i].  form 0: the root of
+ * the wave-speed factor 1 + beta (p/p_s - 1) (>= 1 - beta > 0; the
+ * Lagrangian shock speed of Colella-Glaz 1985 is C_s times it); form 1: the
+ * root of gamma p rho (the Lagrangian sound speed C_s) and of the star
+ * state's gamma p / rho.  x and out are device pointers of n doubles, owned
+ * by the caller; asynchronous on the stream.  The kernels use the core of
+ * the compiler's correctly rounded square root without its rescaling of
+ * arguments below 2^-767 (form 0 also without the fix-up of 0 and +inf):
+ * the IEEE root for every finite argument >= 2^-767 (form 1: also for 0,
+ * +inf, negative and NaN arguments), which a test checks against the
+ * host's.  PPM_EINVAL for n < 0, null pointers with n > 0, or another
+ * form. */
+int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream);
+
+/* Diagnostic: out[i] = a[i] / b[i] as the kernels divide in FP64 (the
+ * Riemann solver, the corrected states, tracing and flattening), computed
+ * on the device for n operand pairs.  a, b and out are device pointers of n
+ * doubles, owned by the caller; asynchronous on the stream.  The kernels use
+ * the compiler's correctly rounded division without its operand scaling;
+ * it returns the IEEE quotient when the exponents of a and b lie in
+ * [-900, 900] and differ by at most 700, and for zero, infinite and NaN
+ * operands, which a test checks against the host's.  PPM_EINVAL for n < 0
+ * or null pointers with n > 0. */
+int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n, void* stream);
 
 /* Autotuner: times the batched step (reps steps after one warm-up, HIP
  * events on the stream) from the filled state U into Unew for every

@@ -668,9 +668,14 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
   return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL);
 }
 
-int ppm_sqrt_wave_values(const double* x, double* out, int64_t n, void* stream) {
-  if (n < 0 || (n > 0 && (!x || !out))) return PPM_EINVAL;
-  return ppm::launch_sqrt_wave(x, out, n, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
+int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !out)) || (form != 0 && form != 1)) return PPM_EINVAL;
+  return ppm::launch_sqrt_form(x, out, n, form, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
+}
+
+int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!a || !b || !out))) return PPM_EINVAL;
+  return ppm::launch_quotient(a, b, out, n, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
 }
 
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused) {

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ t
       auto chit = [&](int o) -> S {
         const S dp1 = p[o + 4] - p[o + 2];
         const S dp2 = p[o + 5] - p[o + 1];
-        const S zeta = sabs(dp1) / smax(sabs(dp2), G.small_pres);
+        const S zeta = qdiv(sabs(dp1), smax(sabs(dp2), G.small_pres));
         const S zz = smin(smax(TEN * (zeta - C075), S(0)), ONE);
         const bool compress = (u[o + 1] - u[o + 3]) > S(0);
         const bool strong = sabs(dp1) > C033 * smin(p[o + 4], p[o + 2]);
@@ -670,11 +670,19 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
   return hipGetLastError();
 }
 
-// Values of the FP64 wave-speed root for a list of arguments (grid-stride).
-__global__ void __launch_bounds__(256) k_sqrt_wave(const double* __restrict__ x, double* __restrict__ out,
-                                                   long long n) {
+// Values of the kernels' FP64 quotient for a list of operand pairs (grid-stride).
+__global__ void __launch_bounds__(256) k_quotient(const double* __restrict__ a, const double* __restrict__ b,
+                                                  double* __restrict__ out, long long n) {
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-    out[i] = sqrt_wave(x[i]);
+    out[i] = qdiv(a[i], b[i]);
+}
+
+// Values of the kernels' FP64 roots for a list of arguments (grid-stride):
+// form 0 the wave-speed root, form 1 the sound-speed root.
+__global__ void __launch_bounds__(256) k_sqrt_form(const double* __restrict__ x, double* __restrict__ out,
+                                                   long long n, int form) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    out[i] = form == 0 ? sqrt_wave(x[i]) : sqrt_phys(x[i]);
 }
 
 }  // namespace
@@ -709,10 +717,18 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
   return hipGetLastError();
 }
 
-hipError_t launch_sqrt_wave(const double* x, double* out, long long n, hipStream_t s) {
+hipError_t launch_quotient(const double* a, const double* b, double* out, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const long long blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_sqrt_wave, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, s, x, out, n);
+  hipLaunchKernelGGL(k_quotient, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, s, a, b, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_form(const double* x, double* out, long long n, int form, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long long blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_sqrt_form, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, s, x, out, n,
+                     form);
   return hipGetLastError();
 }
 

@@ -43,12 +43,12 @@ PPM_HD void flux_vjp(const S g[5], const Gas<S>& G, const S Fb[5], S gb[5]) {
 template <class S>
 PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const Gas<S>& G, S rb_, S ub_,
                             S pb_, S& rob, S& uob, S& pob, S& Cb, S& iWb, S& usb, S& pb) {
-  const S irho = ONE / ro;
+  const S irho = qdiv(ONE, ro);
   const S vstar = irho - (p - po) * (iW * iW);
-  S rs = ONE / vstar, ivs = vstar;
+  S rs = qdiv(ONE, vstar), ivs = vstar;
   bool fl = false;
   if (!(vstar > S(0)) || rs < G.small_dens) { fl = true; rs = G.small_dens; ivs = G.ismall_dens; }
-  const S cst = ssqrt(G.gamma * p * ivs);
+  const S cst = sqrt_phys(G.gamma * p * ivs);
   const S co = C * irho;
   S rsb = S(0), cstb = S(0), cob = S(0), irhob = S(0), ivsb = S(0);
   if (p > po) {
@@ -63,7 +63,7 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
       rsb += rb_; usb += ub_; pb += pb_;
     } else {
       const S D = tl - hd;
-      const S iD = ONE / D;
+      const S iD = qdiv(ONE, D);
       const S w = -hd * iD;
       const S wb = rb_ * (rs - ro) + ub_ * (us - uo) + pb_ * (p - po);
       rob += (ONE - w) * rb_;
@@ -112,7 +112,7 @@ PPM_HD S riem_iter(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, const 
   const S izr = HALF * iwr * (ONE + xr * xr);
   const S usl = ul - (p - pl) * iwl;
   const S usr = ur + (p - pr) * iwr;
-  const S pn = p - (usr - usl) / (izl + izr);
+  const S pn = p - qdiv(usr - usl, izl + izr);
   return smax(pn, G.small_pres);
 }
 
@@ -136,7 +136,7 @@ PPM_HD S riem_iter_rec(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
   const S izr = HALF * iwr * (ONE + xr * xr);
   const S usl = ul - (p - pl) * iwl;
   const S usr = ur + (p - pr) * iwr;
-  const S pn = p - (usr - usl) / (izl + izr);
+  const S pn = p - qdiv(usr - usl, izl + izr);
   r.p = p;
   r.sl = sl;
   r.sr = sr;
@@ -160,7 +160,7 @@ PPM_HD S riem_iter_vjp_rec(const RiemIt<S>& r, S cl, S cr, S pl, S pr, S ul, S u
   const S usr = ur + (p - pr) * iwr;
   const S dU = usr - usl, Q = izl + izr;
   S pb = pnb;
-  const S iQ = ONE / Q;
+  const S iQ = qdiv(ONE, Q);
   const S dUb = -pnb * iQ;
   const S Qb = pnb * dU * iQ * iQ;
   const S usrb = dUb, uslb = -dUb;
@@ -206,14 +206,14 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
   const S rl = L[0], ul = L[1 + d], pl = L[4];
   const S rr = R[0], ur = R[1 + d], pr = R[4];
-  const S cl = ssqrt(G.gamma * pl * rl);
-  const S cr = ssqrt(G.gamma * pr * rr);
+  const S cl = sqrt_phys(G.gamma * pl * rl);
+  const S cr = sqrt_phys(G.gamma * pr * rr);
   const S N0 = (cr * pl + cl * pr) + (cl * cr) * (ul - ur);
   const S D0 = cl + cr;
-  const S p0r = N0 / D0;
+  const S p0r = qdiv(N0, D0);
   const bool fl0 = p0r < G.small_pres;
   const S p0 = smax(p0r, G.small_pres);
-  const S ipl = ONE / pl, ipr = ONE / pr;
+  const S ipl = qdiv(ONE, pl), ipr = qdiv(ONE, pr);
   // the first RIEM_KEEP Newton steps are recorded for the reverse sweep
   // (fully unrolled, so the records stay in registers); later ones are
   // recomputed from the output of the last recorded one
@@ -230,7 +230,7 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   S iwl, iwr;
   pair_recip(wl, wr, iwl, iwr);
   const S NU = (wl * ul + wr * ur) + (pl - pr), DU = wl + wr;
-  const S us = NU / DU;
+  const S us = qdiv(NU, DU);
 
   // forward sample -> Godunov state g, then the flux adjoint
   S g[5];
@@ -284,7 +284,7 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
     Rb[1 + t2] += HALF * gb[4];
   }
   // us = NU / DU
-  const S iDU = ONE / DU;
+  const S iDU = qdiv(ONE, DU);
   const S NUb = usb * iDU, DUb = -usb * us * iDU;
   S wlb = NUb * ul + DUb, wrb = NUb * ur + DUb;
   ulb += NUb * wl;
@@ -316,7 +316,7 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
                              iprb);
   // acoustic guess (floor frozen)
   if (!fl0) {
-    const S iD0 = ONE / D0;
+    const S iD0 = qdiv(ONE, D0);
     const S N0b = pb * iD0, D0b = -pb * p0r * iD0;
     crb += N0b * (pl + cl * (ul - ur));
     plb += N0b * cr;
@@ -363,7 +363,7 @@ PPM_HD void prim_tail_vjp(S r, S u, S v, S w, const Gas<S>& G, S rb, S ub, S vb,
   ub += keb * r * u;
   vb += keb * r * v;
   wb += keb * r * w;
-  const S ir = ONE / r;
+  const S ir = qdiv(ONE, r);
   Ub[1] += ub * ir;
   Ub[2] += vb * ir;
   Ub[3] += wb * ir;
@@ -376,7 +376,7 @@ template <class S>
 PPM_HD void cons_to_prim_floor_vjp(const S U[5], const Gas<S>& G, const S qb[5], S Ub[5]) {
   const bool rfl = U[0] < G.small_dens;
   const S r = smax(U[0], G.small_dens);
-  const S ir0 = ONE / r;
+  const S ir0 = qdiv(ONE, r);
   const S u = U[1] * ir0, v = U[2] * ir0, w = U[3] * ir0;
   const S ke = HALF * r * ((u * u + v * v) + w * w);
   const S p = G.gm1 * (U[4] - ke);
@@ -390,7 +390,7 @@ template <class S>
 PPM_HD void cons_to_prim_dec(const S U[5], const Gas<S>& G, S q[5], bool& rfl, bool& pfl) {
   rfl = U[0] < G.small_dens;
   const S r = smax(U[0], G.small_dens);
-  const S ir = ONE / r;
+  const S ir = qdiv(ONE, r);
   const S u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
   const S ke = HALF * r * ((u * u + v * v) + w * w);
   const S p = G.gm1 * (U[4] - ke);
@@ -547,7 +547,7 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
   constexpr int mn = 1 + d, m1 = 1 + t1, m2 = 1 + t2;
   S da[5], dab[5];
   for (int m = 0; m < 5; ++m) { da[m] = aR[m] - aL[m]; dab[m] = S(0); }
-  const S rc = r * c, c2 = c * c, ic2 = ONE / c2, hic2 = HALF * ic2, cor = c / r;
+  const S rc = r * c, c2 = c * c, ic2 = qdiv(ONE, c2), hic2 = HALF * ic2, cor = qdiv(c, r);
   const S lam[3] = {un - c, un, un + c};
   const S zero = S(0);
   S rcb = zero, c2b = zero, ic2b = zero, hic2b = zero, corb = zero;
@@ -628,7 +628,7 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
   cb += TWO * c * c2b;
   rb += rcb * c;
   cb += rcb * r;
-  const S ir = ONE / r;
+  const S ir = qdiv(ONE, r);
   cb += corb * ir;
   rb -= corb * cor * ir;
   for (int m = 0; m < 5; ++m) { aRb[m] += dab[m]; aLb[m] -= dab[m]; }

@@ -32,7 +32,7 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
            "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
-           "ppm_sqrt_wave_values")
+           "ppm_sqrt_values", "ppm_quotient_values")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -119,7 +119,8 @@ def lib():
         L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
         L.ppm_set_step_form.argtypes = [_vp, ctypes.c_int32]
         L.ppm_get_step_form.argtypes = [_vp, _i32p]
-        L.ppm_sqrt_wave_values.argtypes = [_vp, _vp, ctypes.c_int64, _vp]
+        L.ppm_sqrt_values.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
+        L.ppm_quotient_values.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.ppm_amr_destroy.argtypes = [_vp]
         L.ppm_amr_last_error.argtypes = [_vp]
@@ -196,16 +197,33 @@ def plan_cache_stats():
     return a.value, b.value, c.value
 
 
-def sqrt_wave_values(x, stream=None):
-    """Device values of the Riemann solver's FP64 wave-speed root for the
-    float64 CUDA tensor x (diagnostic; ppm_sqrt_wave_values)."""
+def sqrt_values(x, form=0, stream=None):
+    """Device values of one of the Riemann solver's FP64 square roots (form
+    0: the wave-speed factor's, form 1: the sound speeds') for the float64
+    CUDA tensor x (diagnostic; ppm_sqrt_values)."""
     import torch
     if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
-        raise PPMError("sqrt_wave_values: x must be a contiguous float64 CUDA tensor")
+        raise PPMError("sqrt_values: x must be a contiguous float64 CUDA tensor")
     out = torch.empty_like(x)
-    rc = lib().ppm_sqrt_wave_values(_ptr(x), _ptr(out), x.numel(), _stream(stream))
+    rc = lib().ppm_sqrt_values(_ptr(x), _ptr(out), x.numel(), int(form), _stream(stream))
     if rc != 0:
-        raise PPMError(f"ppm_sqrt_wave_values failed ({rc})")
+        raise PPMError(f"ppm_sqrt_values failed ({rc})")
+    return out
+
+
+def quotient_values(a, b, stream=None):
+    """Device values of the kernels' FP64 quotient a / b for float64 CUDA
+    tensors a, b of one shape (diagnostic; ppm_quotient_values)."""
+    import torch
+    for t in (a, b):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise PPMError("quotient_values: operands must be contiguous float64 CUDA tensors")
+    if a.shape != b.shape:
+        raise PPMError("quotient_values: operands differ in shape")
+    out = torch.empty_like(a)
+    rc = lib().ppm_quotient_values(_ptr(a), _ptr(b), _ptr(out), a.numel(), _stream(stream))
+    if rc != 0:
+        raise PPMError(f"ppm_quotient_values failed ({rc})")
     return out
 
 

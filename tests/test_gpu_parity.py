@@ -423,13 +423,17 @@ def test_power_of_two_change_of_units_on_gpu(precision):
     print(f"max field error vs oracle {worst:.3e}, differing values {nbits}")
 
 
-def test_wave_speed_root_is_the_ieee_root():
-    """The Riemann solver takes the root of its wave-speed factor with a
-    shortened form of the compiler's correctly rounded FP64 square root
-    (no rescaling of arguments below 2^-767, no fix-up of 0 and inf).  It
+@pytest.mark.parametrize("form", [0, 1])
+def test_kernel_roots_are_the_ieee_root(form):
+    """The Riemann solver takes its FP64 square roots with the core of the
+    compiler's correctly rounded root, without the rescaling of arguments
+    below 2^-767 (the wave-speed root, form 0, also without the fix-up of 0
+    and inf, which its argument 1 + beta (p/p_s - 1) never reaches).  Both
     must return the IEEE root, bit for bit, for every finite argument from
     2^-767 up: 2^20 random arguments with exponents uniform over that range,
-    the factor's own range near 1 - beta, and the end points."""
+    the wave-speed factor's own range near 1 - beta, the end points, and
+    for the sound-speed root (form 1) also 0, -0, +inf, negative and NaN
+    arguments."""
     rng = np.random.default_rng(12)
     n = 1 << 20
     mant = rng.integers(0, 1 << 52, size=n, dtype=np.uint64)
@@ -440,8 +444,48 @@ def test_wave_speed_root_is_the_ieee_root():
     near = 1.0 - beta + rng.uniform(0.0, 4.0, size=4096) ** 3
     ends = np.array([2.0 ** -767, np.nextafter(2.0 ** -767, 1.0), 1.0 - beta, 1.0, 2.0, 4.0,
                      np.finfo(np.float64).max, np.nextafter(np.finfo(np.float64).max, 0.0)])
-    x = np.concatenate([x, near, ends])
-    got = P.sqrt_wave_values(torch.from_numpy(x).cuda()).cpu().numpy()
-    ref = np.sqrt(x)
-    bad = np.flatnonzero(got.view(np.uint64) != ref.view(np.uint64))
+    special = np.array([0.0, -0.0, np.inf, -1.0, -np.inf, np.nan]) if form == 1 else np.array([])
+    x = np.concatenate([x, near, ends, special])
+    got = P.sqrt_values(torch.from_numpy(x).cuda(), form).cpu().numpy()
+    with np.errstate(invalid="ignore"):
+        ref = np.sqrt(x)
+    same = (got.view(np.uint64) == ref.view(np.uint64)) | (np.isnan(got) & np.isnan(ref))
+    bad = np.flatnonzero(~same)
     assert bad.size == 0, (bad.size, x[bad[:5]], got[bad[:5]], ref[bad[:5]])
+
+
+def test_kernel_quotient_is_the_ieee_quotient():
+    """The kernels divide with the compiler's correctly rounded FP64 division
+    without its operand scaling.  It must return the IEEE quotient, bit for
+    bit, whenever both exponents lie in [-900, 900] and differ by at most
+    700, and for zero, infinite and NaN operands: 2^20 random pairs of
+    either sign over that range (half of them with nearby exponents, as the
+    method's quotients have), signed zeros and infinities over either sign,
+    divisions by zero, and the range's corners."""
+    rng = np.random.default_rng(13)
+    n = 1 << 20
+
+    def make(expo):
+        mant = rng.integers(0, 1 << 52, size=expo.size, dtype=np.uint64)
+        bits = ((expo + 1023).astype(np.uint64) << np.uint64(52)) | mant
+        x = bits.view(np.float64)
+        return np.where(rng.integers(0, 2, size=expo.size) == 1, -x, x)
+    eb = rng.integers(-900, 901, size=n).astype(np.int64)
+    near = eb + rng.integers(-30, 31, size=n)
+    far = eb + rng.integers(-700, 701, size=n)
+    ea = np.clip(np.where(np.arange(n) % 2 == 0, near, far), -900, 900)
+    a, b = make(ea), make(eb)
+    inf = np.inf
+    zeros = np.array([0.0, -0.0] * 4 + [1.5, -1.5, 0.0, -0.0, inf, -inf, inf, 2.0, np.nan, 1.0])
+    zb = np.array([1.0, 1.0, -1.0, -1.0, 2.0 ** 900, 2.0 ** -900, -3.5, 7.25]
+                  + [0.0, 0.0, -0.0, 0.0, 3.0, 3.0, -inf, inf, 1.0, np.nan])
+    ca = np.array([2.0 ** 900, 2.0 ** -900, 2.0 ** 200, 2.0 ** -200, 1.0, 1.0 - 2.0 ** -52])
+    cb = np.array([2.0 ** 200, 2.0 ** -200, 2.0 ** 900, 2.0 ** -900, 3.0, 1.0 + 2.0 ** -52])
+    a = np.concatenate([a, zeros, ca])
+    b = np.concatenate([b, zb, cb])
+    got = P.quotient_values(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ref = a / b
+    same = (got.view(np.uint64) == ref.view(np.uint64)) | (np.isnan(got) & np.isnan(ref))
+    bad = np.flatnonzero(~same)
+    assert bad.size == 0, (bad.size, a[bad[:5]], b[bad[:5]], got[bad[:5]], ref[bad[:5]])
