@@ -52,11 +52,18 @@ TRAFFIC_SOURCES = ("paper_1008_2801_amd/csrc/ppm_kernels.hip", "paper_1008_2801_
 
 
 def sources_digest():
+    """SHA-256 of the traffic sources' code: comments and blank lines are
+    dropped first, so that only a change of the code itself invalidates a
+    record."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()
 
 

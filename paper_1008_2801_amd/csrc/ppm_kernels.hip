@@ -213,7 +213,8 @@ __device__ __forceinline__ void riemann1_body(const Tile* __restrict__ tiles, in
 
 // Occupancy requests (measured): riemann1 at 8 waves per SIMD and riemann2
 // at 5 fit without spills and run 2-3% faster than the compiler's own
-// register choice; riemann3 at 7 and trace at 6 are slower.
+// register choice.  riemann3 (7 waves on its own) at 8 and trace at 6
+// spill and are slower.
 template <class S>
 __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(8))) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
