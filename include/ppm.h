@@ -162,6 +162,19 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
                    const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
                    void* stream);
 
+/* ppm_hydro_step that also leaves the next step's time step: dt_next_dev
+ * (2 device doubles) receives what ppm_compute_dt(Unew) would write, bit
+ * for bit -- the CFL rule over the valid zones of Unew, which the staged
+ * update computes from the states it writes instead of a separate pass over
+ * Unew (the fused brick form, ppm_set_step_form(1), runs that pass).  The
+ * ghost fill before the next step does not change valid zones, so the next
+ * step can read its dt from dt_next_dev.  dt_next_dev may alias dt_dev (it
+ * is written after the step has read dt_dev[0]).  PPM_EINVAL as for
+ * ppm_hydro_step, and for a null dt_next_dev or a cfl outside (0, 1). */
+int ppm_hydro_step_dt(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                      const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                      double* dt_next_dev, void* stream);
+
 /* Adjoint of one step, dt and every branch decision of the forward step
  * frozen: given the step's input U (ghosts filled, as for ppm_hydro_step)
  * and the adjoint Unew_bar of the new state's valid zones, writes to U_bar

@@ -622,7 +622,7 @@ int ppm_compute_dt(ppm_ctx* ctx, const double* U, const double dx[3], const ppm_
 
 static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
                            const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
-                           void* stream, int upto) {
+                           void* stream, int upto, double* dt_next = nullptr) {
   if (!ctx) return PPM_EINVAL;
   std::string m = validate_params(params);
   if (m.empty()) m = validate_dx(dx);
@@ -637,28 +637,39 @@ static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* 
   }
   if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, params->precision)))
     m = "step: workspace missing or too small (ppm_set_workspace)";
+  if (m.empty() && dt_next && !(params->cfl > 0.0 && params->cfl < 1.0)) m = "params: cfl must be in (0, 1)";
   if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
   hipStream_t s = (hipStream_t)stream;
   const DevLevel L = ctx->level();
   int rc = ctx->hip(launch_step_consts(L, dt, dt_dev, dx, params->grav, s), "step consts");
   if (rc) return rc;
+  SpeedOut so{nullptr, {dx[0], dx[1], dx[2]}, params->gamma, params->gamma - 1.0, params->small_pres};
+  if (dt_next) {
+    // after the step constants have read dt_dev, which dt_next may alias
+    so.bits = (unsigned long long*)(dt_next + 1);
+    rc = ctx->hip(launch_speed_clear(so.bits, s), "next dt");
+    if (rc) return rc;
+  }
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
   auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, hipEvent_t* ev) {
     return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, ctx->work,
                                 params->gamma, params->small_dens, params->small_pres, params->limiter,
-                                params->flattening, params->riemann_iters, grav, params->grav, s, ev, upto),
+                                params->flattening, params->riemann_iters, grav, params->grav, s, ev, upto, so),
                     "step");
   };
   if (mode == PPM_LAUNCH_BATCHED) {
     ppm_ctx::ProfRec* r = ctx->prof ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
-    return run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(),
-               r ? r->ev.data() : nullptr);
-  }
-  for (int b = 0; b < ctx->layout.nbox; ++b) {
-    rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], ctx->tB_begin[b],
-             ctx->tB_begin[b + 1], nullptr);
+    rc = run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(),
+             r ? r->ev.data() : nullptr);
     if (rc) return rc;
+  } else {
+    for (int b = 0; b < ctx->layout.nbox; ++b) {
+      rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], ctx->tB_begin[b],
+               ctx->tB_begin[b + 1], nullptr);
+      if (rc) return rc;
+    }
   }
+  if (dt_next) return ctx->hip(launch_speed_finish(dt_next, params->cfl, s), "next dt");
   return PPM_OK;
 }
 
@@ -666,6 +677,14 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
                    const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
                    void* stream) {
   return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL);
+}
+
+int ppm_hydro_step_dt(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                      const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                      double* dt_next_dev, void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  if (!dt_next_dev) return ctx->fail(PPM_EINVAL, "step_dt: null dt_next_dev");
+  return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL, dt_next_dev);
 }
 
 int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream) {

@@ -132,11 +132,25 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
 // level asks for it), STEP_FULL_STAGED (the whole step with the final
 // fluxes left in the workspace, as the species stages need).
 enum { STEP_TO_STAGE2 = 5, STEP_FULL = 7, STEP_FULL_STAGED = 8 };
+// Optional output of the staged update: the maximum over the updated valid
+// zones of the signal speed max_d (|u_d| + c) / h_d, as the bits of a
+// non-negative double, max-accumulated into *bits (null: not computed).
+struct SpeedOut {
+  unsigned long long* bits;
+  double h[3];
+  double gamma, gm1, small_pres;
+};
+
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
                        const double* U, double* Unew, double* const* flux, void* work,
                        const double gamma, const double small_dens, const double small_pres,
                        int limiter, int flattening, int iters, int grav, const double g[3],
-                       hipStream_t s, hipEvent_t* ev, int upto = STEP_FULL);
+                       hipStream_t s, hipEvent_t* ev, int upto = STEP_FULL,
+                       SpeedOut so = SpeedOut{nullptr, {0.0, 0.0, 0.0}, 0.0, 0.0, 0.0});
+// The speed accumulator of a fused-dt step: cleared before the step's
+// launches, turned into dt = cfl / s after them (one lane each).
+hipError_t launch_speed_clear(unsigned long long* bits, hipStream_t s);
+hipError_t launch_speed_finish(double* dt_dev, double cfl, hipStream_t s);
 // Adjoint of one FP64 step (ppm_adjoint.hip); the forward workspace must hold
 // the recomputed prim..riemann2 intermediates of the same step.
 size_t adjoint_workspace_bytes(long long LS, long long LE, int precision);

@@ -410,22 +410,49 @@ __device__ __forceinline__ void update_zone(const double uo[5], const double fxd
 }
 
 // O10: conservative update in FP64 (+ Heun source) on the valid zones.
+// Fold of one valid zone's signal speeds (|u_d| + c) / h_d into the running
+// maximum s, from its conserved state (rho, rho u, rho v, rho w, rho E).
+// A NaN speed (a non-physical zone) never replaces s.  The dt kernel and the
+// update's fused form both use it, so their maxima agree bit for bit.
+__device__ __forceinline__ double fold_signal_speed(double s, double r, double mx, double my, double mz,
+                                                    double E, double h0, double h1, double h2, double gamma,
+                                                    double gm1, double small_pres) {
+  const double vx = mx / r, vy = my / r, vz = mz / r;
+  const double ke = 0.5 * r * ((vx * vx + vy * vy) + vz * vz);
+  double p = gm1 * (E - ke);
+  p = smax(p, small_pres);
+  const double c = __builtin_sqrt(gamma * p / r);
+  const double sx = (sabs(vx) + c) / h0;
+  const double sy = (sabs(vy) + c) / h1;
+  const double sz = (sabs(vz) + c) / h2;
+  return smax(smax(smax(s, sx), sy), sz);
+}
+
+// Maximum of s over the workgroup, max-accumulated into *bits (the bits of
+// a non-negative double order like the doubles).  One atomic per
+// workgroup, skipped when the running maximum is already as large.  Every
+// lane of the workgroup must call it.
+__device__ __forceinline__ void block_max_to(double s, unsigned long long* bits) {
+  for (int off = 32; off > 0; off >>= 1) s = smax(s, __shfl_xor(s, off, 64));
+  __shared__ double wmax[MAX_TILE / 64];
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = smax(m, wmax[w]);
+    const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+    if (mb > __hip_atomic_load(bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(bits, mb);
+  }
+}
+
+// The update of one valid zone; returns its signal speed folded into 0 when
+// so.bits is set (else 0).
 template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ tiles, int ntiles,
-                                                 const DevBox* __restrict__ boxes,
-                                                 const double* __restrict__ U, double* __restrict__ Unew,
-                                                 const S* __restrict__ work, long long LE,
-                                                 const StepConsts* __restrict__ sc, int grav,
-                                                 double g0, double g1, double g2) {
-  const int tt = xcd_tile(ntiles);
-  if (tt < 0) return;
-  const Tile tl = tiles[tt];
-  const DevBox B = boxes[tl.box];
-  EZone z;
-  if (!ezone(tl, B, z)) return;
-  if (z.x[0] < 0 || z.x[0] >= B.n[0] || z.x[1] < 0 || z.x[1] >= B.n[1] || z.x[2] < 0 ||
-      z.x[2] >= B.n[2])
-    return;
+__device__ __forceinline__ double update_body(const Tile& tl, const DevBox& B, const EZone& z,
+                                              const double* __restrict__ U, double* __restrict__ Unew,
+                                              const S* __restrict__ work, long long LE,
+                                              const StepConsts* __restrict__ sc, int grav, double g0, double g1,
+                                              double g2, const SpeedOut& so) {
   const long long sy = z.E[0], sz = (long long)z.E[0] * z.E[1];
   const double dtdx0 = sc->dtdx[0], dtdx1 = sc->dtdx[1], dtdx2 = sc->dtdx[2];
   const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
@@ -447,7 +474,30 @@ __global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ ti
   update_zone(uo, fxd, fyd, fzd, dtdx0, dtdx1, dtdx2, sc, grav, g0, g1, g2, un);
 #pragma unroll
   for (int m = 0; m < 5; ++m) Unew[ui + m * NS] = un[m];
+  if (!so.bits) return 0.0;
+  return fold_signal_speed(0.0, un[0], un[1], un[2], un[3], un[4], so.h[0], so.h[1], so.h[2], so.gamma, so.gm1,
+                           so.small_pres);
 }
+
+template <class S>
+__global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ tiles, int ntiles,
+                                                 const DevBox* __restrict__ boxes,
+                                                 const double* __restrict__ U, double* __restrict__ Unew,
+                                                 const S* __restrict__ work, long long LE,
+                                                 const StepConsts* __restrict__ sc, int grav,
+                                                 double g0, double g1, double g2, SpeedOut so) {
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;  // the whole workgroup
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  const bool valid = ezone(tl, B, z) && z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] &&
+                     z.x[2] >= 0 && z.x[2] < B.n[2];
+  double smax_lane = 0.0;
+  if (valid) smax_lane = update_body(tl, B, z, U, Unew, work, LE, sc, grav, g0, g1, g2, so);
+  if (so.bits) block_max_to(smax_lane, so.bits);
+}
+
 
 // O9 + O10 fused on a brick of valid zones: the final fluxes of every face
 // of the brick (its boundary faces are computed by both bricks that share
@@ -540,27 +590,10 @@ __global__ void __launch_bounds__(MAX_TILE) k_wavespeed(const Tile* __restrict__
       const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
       const long long NS = (long long)N0 * N1 * N2;
       const double* u = U + B.soff + ((long long)(z.x[2] + NG) * N1 + (z.x[1] + NG)) * N0 + (z.x[0] + NG);
-      const double r = u[0];
-      const double vx = u[NS] / r, vy = u[2 * NS] / r, vz = u[3 * NS] / r;
-      const double ke = 0.5 * r * ((vx * vx + vy * vy) + vz * vz);
-      double p = gm1 * (u[4 * NS] - ke);
-      p = smax(p, small_pres);
-      const double c = __builtin_sqrt(gamma * p / r);
-      const double sx = (sabs(vx) + c) / h0;
-      const double sy = (sabs(vy) + c) / h1;
-      const double sz = (sabs(vz) + c) / h2;
-      s = smax(smax(smax(s, sx), sy), sz);
+      s = fold_signal_speed(s, u[0], u[NS], u[2 * NS], u[3 * NS], u[4 * NS], h0, h1, h2, gamma, gm1, small_pres);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) s = smax(s, __shfl_xor(s, off, 64));
-  __shared__ double wmax[MAX_TILE / 64];
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = wmax[0];
-    for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = smax(m, wmax[w]);
-    atomicMax(smax_bits, (unsigned long long)__double_as_longlong(m));
-  }
+  block_max_to(s, smax_bits);
 }
 
 __global__ void __launch_bounds__(64) k_zero_u64(unsigned long long* p) {
@@ -627,7 +660,7 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restric
 template <class S>
 hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, const double* U,
                      double* Unew, double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
-                     hipEvent_t* ev, int upto) {
+                     hipEvent_t* ev, int upto, const SpeedOut& so) {
   S* prim = (S*)work;
   S* ework = prim + P_PLANES * L.LS;
   const int nS = tS1 - tS0, nE = tE1 - tE0;
@@ -658,6 +691,9 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
     hipLaunchKernelGGL(k_final_update<S>, dim3(xcd_grid(nB)), dim3(BRICK_THREADS), 0, s, L.bricks + tB0, nB,
                        L.boxes, (const S*)ework, L.LE, G, L.consts, U, Unew, fx, fy, fz, G.grav, g[0], g[1], g[2],
                        L.flags);
+    if (so.bits)  // the brick kernel has no fused speed maximum: a separate pass over Unew
+      hipLaunchKernelGGL(k_wavespeed, dim3(nE < 2048 ? nE : 2048), blk, 0, s, TE, nE, L.boxes, (const double*)Unew,
+                         so.h[0], so.h[1], so.h[2], so.gamma, so.gm1, so.small_pres, so.bits);
     if (ev) (void)hipEventRecord(ev[6], s);
     if (ev) (void)hipEventRecord(ev[7], s);
     return hipGetLastError();
@@ -666,7 +702,7 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
                      L.consts, fx, fy, fz, L.flags);
   if (ev) (void)hipEventRecord(ev[6], s);
   hipLaunchKernelGGL(k_update<S>, dim3(xcd_grid(nE)), blk, 0, s, TE, nE, L.boxes, U, Unew,
-                     (const S*)ework, L.LE, L.consts, G.grav, g[0], g[1], g[2]);
+                     (const S*)ework, L.LE, L.consts, G.grav, g[0], g[1], g[2], so);
   if (ev) (void)hipEventRecord(ev[7], s);
   return hipGetLastError();
 }
@@ -736,14 +772,25 @@ hipError_t launch_sqrt_form(const double* x, double* out, long long n, int form,
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
                        const double* U, double* Unew, double* const* flux, void* work, const double gamma,
                        const double small_dens, const double small_pres, int limiter, int flattening,
-                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev, int upto) {
+                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev, int upto,
+                       SpeedOut so) {
   if (precision == 1)
     return step_impl<float>(L, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
                             make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
-                            g, s, ev, upto);
+                            g, s, ev, upto, so);
   return step_impl<double>(L, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
                            make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
-                           g, s, ev, upto);
+                           g, s, ev, upto, so);
+}
+
+hipError_t launch_speed_clear(unsigned long long* bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_speed_finish(double* dt_dev, double cfl, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_dt, dim3(1), dim3(64), 0, s, dt_dev, cfl);
+  return hipGetLastError();
 }
 
 }  // namespace ppm

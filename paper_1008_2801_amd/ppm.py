@@ -32,7 +32,7 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
            "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
-           "ppm_sqrt_values", "ppm_quotient_values")
+           "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt")
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -95,6 +95,8 @@ def lib():
         L.ppm_compute_dt.argtypes = [_vp, _vp, _dp3, ctypes.POINTER(Params), _vp, _vp]
         L.ppm_hydro_step.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_double, _vp, _dp3,
                                      ctypes.POINTER(Params), ctypes.c_int32, _vp]
+        L.ppm_hydro_step_dt.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_double, _vp, _dp3,
+                                        ctypes.POINTER(Params), ctypes.c_int32, _vp, _vp]
         L.ppm_graph_create.argtypes = [_vp, _vp, _vp, _dp3, ctypes.POINTER(Params), ctypes.c_int32, _vp,
                                        ctypes.POINTER(_vp)]
         L.ppm_graph_launch.argtypes = [_vp, _vp]
@@ -227,6 +229,11 @@ def quotient_values(a, b, stream=None):
     return out
 
 
+def _torch():
+    import torch
+    return torch
+
+
 def _stream(stream=None):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -329,16 +336,28 @@ class Level:
                                          _stream(stream)), "ppm_compute_dt")
         return out
 
-    def hydro_step(self, U, Unew, dx, p, dt=0.0, dt_dev=None, fluxes=None, mode=BATCHED, stream=None):
+    def hydro_step(self, U, Unew, dx, p, dt=0.0, dt_dev=None, fluxes=None, mode=BATCHED, stream=None,
+                   dt_next=None):
+        """One step U -> Unew.  dt_next: a device float64 tensor of 2 that
+        receives the next step's dt from the valid zones of Unew, computed
+        by the update (ppm_hydro_step_dt); it may be dt_dev itself."""
         if self._slot is None and (self._work is None or self._work_prec != p.precision or
                                    self._work.numel() < self.workspace_bytes(p.precision)):
             self.ensure_workspace(p.precision)
         fl = None
         if fluxes is not None:
             fl = (_vp * 3)(*[f.data_ptr() if f is not None else None for f in fluxes])
-        self._check(lib().ppm_hydro_step(self.ctx, _ptr(U), _ptr(Unew), fl, float(dt), _ptr(dt_dev),
-                                         _dp3(*dx), ctypes.byref(p), int(mode), _stream(stream)),
-                    "ppm_hydro_step")
+        if dt_next is None:
+            self._check(lib().ppm_hydro_step(self.ctx, _ptr(U), _ptr(Unew), fl, float(dt), _ptr(dt_dev),
+                                             _dp3(*dx), ctypes.byref(p), int(mode), _stream(stream)),
+                        "ppm_hydro_step")
+            return
+        if dt_next.dtype != _torch().float64 or not dt_next.is_cuda or dt_next.numel() < 2:
+            raise PPMError("hydro_step: dt_next must be a float64 CUDA tensor of 2 elements")
+        self._check(lib().ppm_hydro_step_dt(self.ctx, _ptr(U), _ptr(Unew), fl, float(dt), _ptr(dt_dev),
+                                            _dp3(*dx), ctypes.byref(p), int(mode), _ptr(dt_next),
+                                            _stream(stream)),
+                    "ppm_hydro_step_dt")
 
     def profile_enable(self, on=True):
         self._check(lib().ppm_profile_enable(self.ctx, int(bool(on))), "ppm_profile_enable")

@@ -489,3 +489,63 @@ def test_kernel_quotient_is_the_ieee_quotient():
     same = (got.view(np.uint64) == ref.view(np.uint64)) | (np.isnan(got) & np.isnan(ref))
     bad = np.flatnonzero(~same)
     assert bad.size == 0, (bad.size, a[bad[:5]], b[bad[:5]], got[bad[:5]], ref[bad[:5]])
+
+
+@pytest.mark.parametrize("mode,precision,fused", [(P.BATCHED, 0, False), (P.PER_BOX, 0, False),
+                                                  (P.BATCHED, 1, False), (P.BATCHED, 0, True)])
+def test_fused_next_dt_is_compute_dt_of_the_new_state(mode, precision, fused):
+    """ppm_hydro_step_dt leaves the CFL dt of the state it writes: bit for
+    bit what a separate ppm_compute_dt pass over Unew gives (dt and the
+    maximum signal speed), on uneven boxes with walls and gravity, in the
+    per-box launch form, in FP32-reconstruction mode and in the brick form
+    (which runs that separate pass itself)."""
+    wl = _uneven_level(seed=17, bc=(0, 0, 1, 1, 2, 2), sizes=(6, 8, 12, 20))
+    wl.grav = (0.0, 0.0, -1.0)
+    wl.precision = precision
+    lev = P.Level(wl.layout)
+    lev.set_step_form(fused)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    nxt = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ref = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lev.fill_boundary(U, mode)
+    lev.compute_dt(U, wl.dx, p, out=dtv)
+    for _ in range(3):
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, mode=mode, dt_next=nxt)
+        lev.compute_dt(V, wl.dx, p, out=ref)
+        assert torch.equal(nxt.view(torch.int64), ref.view(torch.int64)), (nxt.tolist(), ref.tolist())
+        dtv.copy_(nxt)
+        U, V = V, U
+        lev.fill_boundary(U, mode)
+    assert lev.check_status() == 0
+    lev.close()
+
+
+def test_run_with_fused_dt_equals_the_plain_run():
+    """Steps that read their dt from the previous step's update (one dt
+    buffer, passed as both dt_dev and dt_next) reproduce the plain loop of
+    fill, compute_dt and step bit for bit: every dt and the final state."""
+    wl = _uneven_level(seed=18, bc=(0, 0, 0, 0, 1, 1), sizes=(8, 12, 16))
+    _, plain, dts, flags, _ = gpu_run(wl, 4)
+    assert flags == 0
+    lev = P.Level(wl.layout)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    p = P.params(gamma=wl.gamma, grav=wl.grav)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lev.fill_boundary(U)
+    lev.compute_dt(U, wl.dx, p, out=dtv)
+    got = []
+    for _ in range(4):
+        got.append(float(dtv[0].item()))
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, dt_next=dtv)
+        U, V = V, U
+        lev.fill_boundary(U)
+    assert got == dts
+    fused = U.cpu().numpy()
+    for b in range(wl.layout.nbox):
+        assert np.array_equal(interior(wl.layout.view(fused, b)), interior(wl.layout.view(plain, b)))
+    assert lev.check_status() == 0
+    lev.close()
