@@ -304,7 +304,9 @@ int ppm_amr_step(ppm_amr* a, const double* Uc, double* Uc_new, double* Uf, doubl
                  void* stream);
 
 /* Batched form captured in a HIP graph: nsteps steps alternating
- * A -> B -> A ..., each step = [fill, CFL dt on the device, step].  After
+ * A -> B -> A ..., each step = [fill, step] with the CFL dt on the device:
+ * the first step's from a dt pass over A, every later step's from the
+ * update of the step before it (ppm_hydro_step_dt; the same bits).  After
  * an even nsteps the result is in A, after an odd nsteps in B.  The graph
  * keeps the pointers; launches replay it on the stream. */
 int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3],

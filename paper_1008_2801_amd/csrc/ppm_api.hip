@@ -873,9 +873,11 @@ int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], c
   for (int k = 0; k < nsteps && rc == PPM_OK; ++k) {
     double* src = (k % 2 == 0) ? Ua : Ub;
     double* dst = (k % 2 == 0) ? Ub : Ua;
+    // the first step's dt from a dt pass, every later one from the update
+    // of the step before it (the same bits)
     rc = ppm_fill_boundary(ctx, src, PPM_LAUNCH_BATCHED, stream);
-    if (!rc) rc = ppm_compute_dt(ctx, src, dx, params, dtv, stream);
-    if (!rc) rc = ppm_hydro_step(ctx, src, dst, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, stream);
+    if (!rc && k == 0) rc = ppm_compute_dt(ctx, src, dx, params, dtv, stream);
+    if (!rc) rc = ppm_hydro_step_dt(ctx, src, dst, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, dtv, stream);
   }
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(s, &graph);
