@@ -32,10 +32,12 @@ PPM_HD float ssqrt(float x) { return __builtin_sqrtf(x); }
 // a / b.  FP64 on the device: the correctly rounded division hipcc emits
 // (hardware reciprocal of b, two Newton-Raphson steps on it, the quotient,
 // one residual correction, the fix-up of signs and special values) without
-// its operand scaling: 9 instructions instead of 11.  When the exponents of
-// a and b lie in [-900, 900] and differ by at most 700 the scaling is the
-// identity, so the bits are those of the IEEE quotient; zero, infinite and
-// NaN operands go through the fix-up as before.  The kernels divide only
+// its operand scaling: 9 instructions instead of 11.  The scaling only acts
+// near the ends of the exponent range; when the exponents of a and b lie in
+// [-900, 900] and differ by at most 700 the two give the same bits, the
+// IEEE quotient (measured on the device over random operands of that range
+// and tested against the host's quotient); zero, infinite and NaN operands
+// go through the fix-up as before.  The kernels divide only
 // quantities of a physical state (densities, pressures, sound and wave
 // speeds, their sums and differences), far inside that range.  Elsewhere
 // the library division.
