@@ -339,14 +339,15 @@ int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused);
  * the wave-speed factor 1 + beta (p/p_s - 1) (>= 1 - beta > 0; the
  * Lagrangian shock speed of Colella-Glaz 1985 is C_s times it); form 1: the
  * root of gamma p rho (the Lagrangian sound speed C_s) and of the star
- * state's gamma p / rho.  x and out are device pointers of n doubles, owned
- * by the caller; asynchronous on the stream.  The kernels use the core of
- * the compiler's correctly rounded square root without its rescaling of
- * arguments below 2^-767 (form 0 also without the fix-up of 0 and +inf):
- * the IEEE root for every finite argument >= 2^-767 (form 1: also for 0,
- * +inf, negative and NaN arguments), which a test checks against the
- * host's.  PPM_EINVAL for n < 0, null pointers with n > 0, or another
- * form. */
+ * state's gamma p / rho; form 2: the FP32 root of the wave-speed factor,
+ * taken of (float) x[i] and returned widened to double.  x and out are
+ * device pointers of n doubles, owned by the caller; asynchronous on the
+ * stream.  The kernels use the core of the compiler's correctly rounded
+ * square root without its rescaling of small arguments (form 0 and 2 also
+ * without the fix-up of 0 and +inf): the IEEE root for every finite
+ * argument >= 2^-767 (form 2: >= 2^-96; form 1: also for 0, +inf, negative
+ * and NaN arguments), which a test checks against the host's.  PPM_EINVAL
+ * for n < 0, null pointers with n > 0, or another form. */
 int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream);
 
 /* Diagnostic: out[i] = a[i] / b[i] as the kernels divide in FP64 (the

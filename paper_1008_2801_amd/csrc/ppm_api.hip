@@ -688,7 +688,7 @@ int ppm_hydro_step_dt(ppm_ctx* ctx, const double* U, double* Unew, double* const
 }
 
 int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream) {
-  if (n < 0 || (n > 0 && (!x || !out)) || (form != 0 && form != 1)) return PPM_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !out)) || form < 0 || form > 2) return PPM_EINVAL;
   return ppm::launch_sqrt_form(x, out, n, form, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
 }
 

@@ -714,12 +714,13 @@ __global__ void __launch_bounds__(256) k_quotient(const double* __restrict__ a, 
     out[i] = qdiv(a[i], b[i]);
 }
 
-// Values of the kernels' FP64 roots for a list of arguments (grid-stride):
-// form 0 the wave-speed root, form 1 the sound-speed root.
+// Values of the kernels' roots for a list of arguments (grid-stride): form
+// 0 the FP64 wave-speed root, 1 the FP64 sound-speed root, 2 the FP32
+// wave-speed root of (float) x, widened back to double.
 __global__ void __launch_bounds__(256) k_sqrt_form(const double* __restrict__ x, double* __restrict__ out,
                                                    long long n, int form) {
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-    out[i] = form == 0 ? sqrt_wave(x[i]) : sqrt_phys(x[i]);
+    out[i] = form == 0 ? sqrt_wave(x[i]) : (form == 1 ? sqrt_phys(x[i]) : (double)sqrt_wave((float)x[i]));
 }
 
 }  // namespace

@@ -81,7 +81,24 @@ PPM_HD double sqrt_wave(double x) {
   return __builtin_sqrt(x);
 #endif
 }
-PPM_HD float sqrt_wave(float x) { return __builtin_sqrtf(x); }
+// FP32 on the device: hipcc's correctly rounded FP32 root (hardware root,
+// then a one-ulp correction either way from two residuals) without its
+// rescaling of arguments below 2^-96 and its fix-up of 0 and +inf: 8
+// instructions instead of 17, the same bits for every finite argument
+// >= 2^-96.
+PPM_HD float sqrt_wave(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const int si = __float_as_int(s);
+  const float sm = __int_as_float(si - 1), sp = __int_as_float(si + 1);
+  const float rm = __builtin_fmaf(-sm, s, x);
+  const float rp = __builtin_fmaf(-sp, s, x);
+  const float t = (rm <= 0.0f) ? sm : s;
+  return (rp > 0.0f) ? sp : t;
+#else
+  return __builtin_sqrtf(x);
+#endif
+}
 // Square root of a product of a density, a pressure and gamma (a squared
 // Lagrangian sound speed or the star sound speed).  FP64 on the device: the
 // same core as sqrt_wave followed by hipcc's fix-up of 0 and +inf (the root

@@ -200,9 +200,10 @@ def plan_cache_stats():
 
 
 def sqrt_values(x, form=0, stream=None):
-    """Device values of one of the Riemann solver's FP64 square roots (form
-    0: the wave-speed factor's, form 1: the sound speeds') for the float64
-    CUDA tensor x (diagnostic; ppm_sqrt_values)."""
+    """Device values of one of the Riemann solver's square roots (form 0:
+    the FP64 wave-speed factor's, 1: the FP64 sound speeds', 2: the FP32
+    wave-speed factor's, of x rounded to float) for the float64 CUDA tensor
+    x (diagnostic; ppm_sqrt_values)."""
     import torch
     if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
         raise PPMError("sqrt_values: x must be a contiguous float64 CUDA tensor")

@@ -454,6 +454,30 @@ def test_kernel_roots_are_the_ieee_root(form):
     assert bad.size == 0, (bad.size, x[bad[:5]], got[bad[:5]], ref[bad[:5]])
 
 
+def test_fp32_wave_root_is_the_ieee_root():
+    """The FP32 mode takes the root of the wave-speed factor with hipcc's
+    correctly rounded FP32 root minus its rescaling of arguments below
+    2^-96 and its fix-up of 0 and inf (the factor is at least 1 - beta).  It
+    must return the IEEE FP32 root, bit for bit, for every finite FP32
+    argument from 2^-96 up: 2^20 random ones with exponents uniform over
+    that range, the factor's own range and the end points."""
+    rng = np.random.default_rng(14)
+    n = 1 << 20
+    mant = rng.integers(0, 1 << 23, size=n, dtype=np.uint32)
+    expo = rng.integers(-96, 128, size=n).astype(np.int64)
+    bits = ((expo + 127).astype(np.uint32) << np.uint32(23)) | mant
+    x = bits.view(np.float32)
+    beta = np.float32((1.4 + 1.0) / 2.8)
+    near = (np.float32(1.0) - beta + rng.uniform(0.0, 4.0, size=4096).astype(np.float32) ** 3).astype(np.float32)
+    ends = np.array([2.0 ** -96, np.nextafter(np.float32(2.0 ** -96), np.float32(1.0)), 1.0 - beta, 1.0, 2.0,
+                     np.finfo(np.float32).max], dtype=np.float32)
+    x = np.concatenate([x, near, ends]).astype(np.float32)
+    got = P.sqrt_values(torch.from_numpy(x.astype(np.float64)).cuda(), 2).cpu().numpy().astype(np.float32)
+    ref = np.sqrt(x)
+    bad = np.flatnonzero(got.view(np.uint32) != ref.view(np.uint32))
+    assert bad.size == 0, (bad.size, x[bad[:5]], got[bad[:5]], ref[bad[:5]])
+
+
 def test_kernel_quotient_is_the_ieee_quotient():
     """The kernels divide with the compiler's correctly rounded FP64 division
     without its operand scaling.  It must return the IEEE quotient, bit for
