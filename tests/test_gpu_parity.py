@@ -2,6 +2,7 @@
 seeded inputs.  FP64 bar: per-field max |gpu - oracle| / max |oracle| <= 1e-12
 (the path evaluates the same formulas in the same order, so the results are
 expected to agree bit for bit; the tolerance is the stated bar)."""
+import ctypes
 import math
 
 import numpy as np
@@ -239,6 +240,15 @@ def test_invalid_arguments_are_rejected():
         lev.hydro_step(U, V, wl.dx, P.params(gamma=1.0), dt=0.01)
     with pytest.raises(P.PPMError):
         lev.hydro_step(U, V, (0.1, 0.0, 0.1), p, dt=0.01)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PPMError):                       # the next dt needs a cfl in (0, 1)
+        lev.hydro_step(U, V, wl.dx, P.params(gamma=1.4, cfl=1.5), dt=0.01, dt_next=dtv)
+    with pytest.raises(P.PPMError):                       # two doubles for the next dt
+        lev.hydro_step(U, V, wl.dx, p, dt=0.01, dt_next=dtv[:1])
+    lev.ensure_workspace(0)
+    rc = P.lib().ppm_hydro_step_dt(lev.ctx, P._ptr(U), P._ptr(V), None, 0.01, None, P._dp3(*wl.dx),
+                                   ctypes.byref(p), P.BATCHED, None, None)
+    assert rc != 0                                        # null dt_next_dev
     bad = I.Layout(np.array([[0, 0, 0], [2, 0, 0]]), np.array([[3, 3, 3], [5, 3, 3]]), (0, 0, 0), (5, 3, 3))
     with pytest.raises(P.PPMError):
         P.Level(bad)

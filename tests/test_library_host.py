@@ -4,6 +4,7 @@ executed on the host, reproduces the oracle's ghost fill (inflow faces
 included); the plan cache is hit on repeated layouts; invalid layouts are
 rejected."""
 import ctypes
+import json
 import os
 import re
 
@@ -160,3 +161,31 @@ def test_inflow_plan_equals_oracle_fill(which):
     # the host executor of the library refuses a layout with an inflow face
     with pytest.raises(P.PPMError):
         P.fill_boundary_host(lay, arena.copy())
+
+
+def test_traffic_record_follows_the_code_not_the_comments(tmp_path, monkeypatch):
+    """bench.py reports recorded counter traffic only while the kernel
+    sources' code and the tiling are those it was taken with: a changed
+    comment keeps the record, a changed line of code or another tiling
+    drops it."""
+    import shutil
+    import bench
+    for f in bench.TRAFFIC_SOURCES:
+        (tmp_path / os.path.dirname(f)).mkdir(parents=True, exist_ok=True)
+        shutil.copy(os.path.join(bench.ROOT, f), tmp_path / f)
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    d0 = bench.sources_digest()
+    rec = {"tiling": [256, 32], "sources_sha256": d0, "traffic_bytes_per_launch": 123.0}
+    with open(bench.traffic_record_path("riemann2", "cfg2"), "w") as fh:
+        json.dump(rec, fh)
+    assert bench.recorded_traffic("riemann2", "cfg2", (256, 32)) == 123.0
+    assert bench.recorded_traffic("riemann2", "cfg2", (128, 0)) is None
+    src = tmp_path / bench.TRAFFIC_SOURCES[1]
+    text = src.read_text()
+    src.write_text("// a new comment line\n" + text.replace("\n", "\n/* block */\n", 1) + "\n\n")
+    assert bench.sources_digest() == d0
+    assert bench.recorded_traffic("riemann2", "cfg2", (256, 32)) == 123.0
+    src.write_text(text + "\nconstexpr int unused_value = 1;\n")
+    assert bench.sources_digest() != d0
+    assert bench.recorded_traffic("riemann2", "cfg2", (256, 32)) is None
