@@ -85,6 +85,16 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor,
         return sum(vals) / len(vals), len(vals)
     f_kib, nf = mean_kib(fetch_csv, "FETCH_SIZE")
     w_kib, nw = mean_kib(write_csv, "WRITE_SIZE")
+
+    def step_bytes(path, counter, factor):
+        # every stage kernel of the step (not the one dt pass before the
+        # first step), per step: the counted dispatches over the step count,
+        # which the kernel's own dispatches give
+        tot = sum(float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+                  if r["Counter_Name"] == counter and "ppm::" in r["Kernel_Name"]
+                  and "k_wavespeed" not in r["Kernel_Name"])
+        return tot * 1024 * factor
+    steps = nf  # one dispatch of the kernel per step
     rec = {"kernel": f"k_{kernel}<double>", "workload": workload, "tiling": list(tiling),
            "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib, "dispatches": [nf, nw],
            "fetch_factor": fetch_factor, "write_factor": write_factor,
@@ -92,14 +102,17 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor,
            "write_bytes_per_launch": w_kib * 1024 * write_factor,
            "sources_sha256": sources_digest()}
     rec["traffic_bytes_per_launch"] = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    rec["step_traffic_bytes"] = (step_bytes(fetch_csv, "FETCH_SIZE", fetch_factor) +
+                                 step_bytes(write_csv, "WRITE_SIZE", write_factor)) / steps
     with open(traffic_record_path(kernel, workload), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
 
-def recorded_traffic(kernel, workload, tiling):
-    """HBM bytes per launch from the recorded counters, or None when there is
-    no record or the kernels or tiling changed since it was taken."""
+def recorded_traffic(kernel, workload, tiling, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch of the kernel (key "step_traffic_bytes": of the
+    whole step) from the recorded counters, or None when there is no record
+    or the kernels or tiling changed since it was taken."""
     try:
         with open(traffic_record_path(kernel, workload)) as fh:
             rec = json.load(fh)
@@ -107,7 +120,7 @@ def recorded_traffic(kernel, workload, tiling):
         return None
     if rec.get("sources_sha256") != sources_digest() or list(rec.get("tiling", [])) != list(tiling):
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec.get(key)
 
 
 def stage_units(n):
@@ -642,6 +655,10 @@ def main():
     flops = FLOPS_PER_UNIT[dom] * units[dom]
     achieved = flops / mean_s / 1e12
     step_flops = sum(FLOPS_PER_UNIT[k] * units[k] for k in FLOPS_PER_UNIT)
+    # HBM bytes of a whole step from the same counter record (all its
+    # kernels), against the step's live time: the staged step's traffic rate
+    step_traffic = (recorded_traffic(dom, args.workload, tiling, "step_traffic_bytes")
+                    if p.precision == 0 else None)
     out = {
         "metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
@@ -656,7 +673,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": recorded_traffic(dom, args.workload, tiling) if p.precision == 0 else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops},
+                     "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops,
+                     "step_traffic": step_traffic,
+                     "step_traffic_GBps": (step_traffic / (ms / args.steps / 1e3) / 1e9
+                                           if step_traffic else None)},
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
         "step_flop_rate_tflops": step_flops * args.steps / (ms / 1e3) / 1e12,
         "hbm_copy_GBps": copy_bandwidth(),
