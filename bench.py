@@ -556,7 +556,7 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU box distribution is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
