@@ -70,7 +70,8 @@ def per_unit(U, dx, p, windows):
             {k: {O.OPKINDS[i]: kinds[k][i] / cnt[k] for i in range(len(O.OPKINDS))} for k in KERNELS})
 
 
-def main(name="cfg2"):
+def measure(name="cfg2"):
+    """(flops per unit, ops per unit by kind, windows) of a workload's step."""
     if name == "cfg2":
         wl = I.cfg2(64)  # same recipe (seed, modes, jump, velocity draws) on a 64^3 box
     elif name == "cfg3":
@@ -92,6 +93,11 @@ def main(name="cfg2"):
         windows.append((tuple(lo), tuple(v + w - 1 for v in lo)))
     p = O.params(gamma=wl.gamma, grav=wl.grav)
     flops, kinds = per_unit(U, wl.dx, p, windows)
+    return flops, kinds, windows
+
+
+def main(name="cfg2"):
+    flops, kinds, windows = measure(name)
     print(json.dumps({"workload": name, "windows": windows, "flops_per_unit": flops,
                       "ops_per_unit_by_kind": kinds}, indent=1))
 

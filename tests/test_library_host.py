@@ -189,3 +189,17 @@ def test_traffic_record_follows_the_code_not_the_comments(tmp_path, monkeypatch)
     src.write_text(text + "\nconstexpr int unused_value = 1;\n")
     assert bench.sources_digest() != d0
     assert bench.recorded_traffic("riemann2", "cfg2", (256, 32)) is None
+
+
+def test_roofline_flop_figures_are_the_op_counting_oracles():
+    """bench.py prices the stage kernels with per-unit flop counts; they
+    must be the op-counting oracle's on the 256^3 workload's recipe (to the
+    two decimals stored), and bench's units per stage must be the oracle's
+    definitions, so that the reported roofline rests on counted work."""
+    import bench
+    from oracle import opcount
+    flops, _, _ = opcount.measure("cfg2")
+    for k, v in bench.FLOPS_PER_UNIT.items():
+        assert abs(v - flops[k]) <= 0.006, (k, v, flops[k])
+    for n in ((256, 256, 256), (16, 24, 8), (1, 3, 5)):
+        assert bench.stage_units(n) == opcount.units(n), n
