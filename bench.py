@@ -36,6 +36,9 @@ FLOPS_PER_UNIT = {"prim": 15.0, "flatten": 64.99, "trace": 388.27, "riemann1": 1
                   "riemann2": 256.06, "riemann3": 286.06, "update": 45.0}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# MI355X FP32 vector peak (packed FP32 FMA), the peak of the FP32-reconstruction
+# mode's stage kernels.
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
@@ -141,6 +144,10 @@ def make_workload(name):
         return I.cfg2()
     if name == "cfg2-small":
         return I.cfg2(64)
+    if name == "cfg2-fp32":
+        wl = I.cfg2()  # the same level and state, FP32 reconstruction, FP64 update
+        wl.precision = 1
+        return wl
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -655,6 +662,9 @@ def main():
     flops = FLOPS_PER_UNIT[dom] * units[dom]
     achieved = flops / mean_s / 1e12
     step_flops = sum(FLOPS_PER_UNIT[k] * units[k] for k in FLOPS_PER_UNIT)
+    # the FP32 mode's stage kernels compute in FP32 (the counts are those of
+    # the same algorithm; the FP32 forms differ by a few operations per solve)
+    peak = FP64_VECTOR_PEAK_TFLOPS if p.precision == 0 else FP32_VECTOR_PEAK_TFLOPS
     # HBM bytes of a whole step from the same counter record (all its
     # kernels), against the step's live time: the staged step's traffic rate
     step_traffic = (recorded_traffic(dom, args.workload, tiling, "step_traffic_bytes")
@@ -664,13 +674,15 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if p.precision == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {lay.n(0)[0]}^3 single box, FP64, gamma {wl.gamma:.4g}, "
+        "config": {"workload": f"{wl.name}: {lay.n(0)[0]}^3 single box, "
+                               f"{'FP64' if p.precision == 0 else 'FP32 reconstruction + FP64 update'}, "
+                               f"gamma {wl.gamma:.4g}, "
                                "random-mode density x planar Sod jump, periodic, CFL 0.5, plain step "
                                "(fill + step; each step's CFL dt computed by the previous step's update)",
                    "valid_zones": zones, "boxes": lay.nbox,
                    "tiling": {"tile": tiling[0], "strip_rows": tiling[1]}},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": recorded_traffic(dom, args.workload, tiling) if p.precision == 0 else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops,
