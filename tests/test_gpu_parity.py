@@ -279,12 +279,30 @@ def _sample_windows(n, rng, k, w=2):
 
 
 def test_cfg2_full_size_sampled_windows():
-    """256^3 FP64, one step as bench.py runs it; the oracle recomputes sampled
-    windows of the output one by one; the whole output is checked for
-    conservation."""
+    """256^3 FP64, one step as bench.py runs it (its update also leaving the
+    next dt); the oracle recomputes sampled windows of the output one by
+    one and the next dt over the whole output; the whole output is checked
+    for conservation."""
     wl = I.cfg2()
     lev, arena, dts, flags, _ = gpu_run(wl, 1)
     assert flags == 0
+    lev.close()
+    # the same step with the next dt from the update: the same state, and
+    # the oracle's CFL dt of it, bit for bit
+    lev = P.Level(wl.layout)
+    U = torch.from_numpy(wl.arena).cuda()
+    V = lev.new_state()
+    pg = P.params(gamma=wl.gamma)
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    lev.fill_boundary(U)
+    lev.compute_dt(U, wl.dx, pg, out=dtv)
+    lev.hydro_step(U, V, wl.dx, pg, dt_dev=dtv, dt_next=dtv)
+    nxt = float(dtv[0].item())
+    assert lev.check_status() == 0
+    fused = V.cpu().numpy()
+    assert np.array_equal(interior(wl.layout.view(fused, 0)), interior(wl.layout.view(arena, 0)))
+    del U, V, fused
+    lev.close()
     lay = wl.layout
     st = [lay.view(wl.arena, 0).copy()]
     O.fill(lay.boxes(), lay.domain(), lay.bc, st)
@@ -292,6 +310,8 @@ def test_cfg2_full_size_sampled_windows():
     s, _ = O.max_wavespeed(st[0], wl.dx, p)
     assert dts[0] == p.cfl / s
     got = lay.view(arena, 0)
+    s1, _ = O.max_wavespeed(np.ascontiguousarray(got), wl.dx, p)
+    assert nxt == p.cfl / s1
     rng = np.random.default_rng(1)
     for lo, hi in _sample_windows(lay.n(0), rng, 12):
         ref, _, _ = O.step(st[0], dts[0], wl.dx, p, window=(lo, hi))
