@@ -32,7 +32,7 @@ METRIC = "zone-updates/s per PPM step: batched vs plain per-box; adjoint/forward
 # unit of work of each stage kernel, counted by the op-counting instantiation
 # of the reference evaluation on windows of this workload's state
 # (oracle/opcount.py cfg2).  Units: see stage_units().
-FLOPS_PER_UNIT = {"prim": 15.0, "flatten": 64.99, "trace": 388.27, "riemann1": 176.06,
+FLOPS_PER_UNIT = {"prim": 15.0, "flatten": 64.99, "trace": 389.27, "riemann1": 178.06,
                   "riemann2": 256.06, "riemann3": 286.06, "update": 45.0}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 FP64_VECTOR_PEAK_TFLOPS = 78.6

@@ -32,7 +32,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 from oracle import oracle as O  # noqa: E402
-from paper_1008_2801_amd import inputs as I  # noqa: E402
+
+
+def _load_inputs():
+    """The seeded input generators (paper_1008_2801_amd/inputs.py, which
+    imports only numpy and the standard library), loaded from their file
+    alone: the package's __init__, and with it the HIP binding, is never
+    imported."""
+    import importlib.util
+    path = os.path.join(ROOT, "paper_1008_2801_amd", "inputs.py")
+    spec = importlib.util.spec_from_file_location("ppm_workload_inputs", path)
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules[spec.name] = mod  # dataclasses look their module up by name
+    spec.loader.exec_module(mod)
+    return mod
+
+
+I = _load_inputs()
 
 KERNELS = {"prim": ["prim"], "flatten": ["flatten"], "trace": ["trace"], "riemann1": ["riemann1"],
            "riemann2": ["transverse1", "riemann2"], "riemann3": ["transverse2", "riemann3"],

@@ -91,6 +91,11 @@ def lib():
         L.oracle_max_wavespeed.argtypes = [_dp, _ip, _dp, ctypes.POINTER(OParams), _ip]
         L.oracle_riemann.restype = ctypes.c_int
         L.oracle_riemann.argtypes = [_dp, _dp, ctypes.c_int, ctypes.POINTER(OParams), _dp]
+        L.oracle_flatten.restype = ctypes.c_int
+        L.oracle_flatten.argtypes = [_dp, _ip, ctypes.POINTER(OParams), _dp]
+        L.oracle_count_ops.restype = ctypes.c_int
+        L.oracle_count_ops.argtypes = [ctypes.c_int, _dp, ctypes.POINTER(OParams), _dp,
+                                       ctypes.POINTER(ctypes.c_ulonglong)]
         L.oracle_ppm_line.restype = ctypes.c_int
         L.oracle_ppm_line.argtypes = [_dp, ctypes.c_int, _dp, ctypes.POINTER(OParams), _dp, _dp, _dp]
         L.oracle_ppm_integrals.restype = None
@@ -227,6 +232,33 @@ def riemann(L, R, d, p):
     F = np.zeros(5)
     fl = lib().oracle_riemann(_d(L), _d(R), int(d), ctypes.byref(p), _d(F))
     return F, fl
+
+
+def flatten(U, p):
+    """O3 alone: the flattening coefficient of every traced zone [-1, n]^3 of
+    one box (O2 on its stored zones first; ghosts as given).  Returns
+    (phi of shape (nz+2, ny+2, nx+2), flags)."""
+    n = _box_n(U)
+    phi = np.zeros((n[2] + 2, n[1] + 2, n[0] + 2))
+    fl = lib().oracle_flatten(_d(U), _i3(n), ctypes.byref(p), _d(phi))
+    if fl < 0:
+        raise ValueError("oracle_flatten: invalid arguments")
+    return phi, fl
+
+
+def count_ops(what, inp, p):
+    """Operation counts of one piece of the method: what = "riemann" (inp =
+    L[5] + R[5], a face normal to x) or "conversion" (inp = q[5]: primitive
+    -> conserved -> primitive with floors).  Returns (output, {kind: count},
+    flags)."""
+    code = {"riemann": 0, "conversion": 1}[what]
+    a = np.ascontiguousarray(inp, dtype=np.float64)
+    out = np.zeros(5)
+    cnt = (ctypes.c_ulonglong * len(OPKINDS))()
+    fl = lib().oracle_count_ops(code, _d(a), ctypes.byref(p), _d(out), cnt)
+    if fl < 0:
+        raise ValueError("oracle_count_ops: invalid arguments")
+    return out, dict(zip(OPKINDS, (int(c) for c in cnt))), fl
 
 
 def ppm_line(a, p, phi=None):

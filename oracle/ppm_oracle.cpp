@@ -28,9 +28,19 @@
  *       corrected transversely like the density, and rho X updated
  *       conservatively in FP64.  The paper does not describe species; this
  *       is the usual passive-scalar extension of the same advance.
- * Every formula is written as a C expression; the order of evaluation is the
- * one C defines (left to right, no contraction, IEEE division and sqrt), and
- * that order is part of the definition.
+ * Every formula is the method's definition written out as it stands: each
+ * quotient is a division, each root a square root, no reciprocal is shared
+ * between formulas.  The order of evaluation is the one C defines (left to
+ * right, no contraction, IEEE division and sqrt).  The GPU kernels evaluate
+ * algebraically equal forms with fewer divisions, so the two agree to
+ * rounding.
+ *
+ * Pins that tie this file to the method rather than to itself are in the
+ * test suite: exact solutions (Sod, two-shock collisions, uniform flow,
+ * uniform acceleration), invariants (conservation, mirror and axis
+ * symmetries, planar data), convergence rates, hand-computed flattening
+ * coefficients and CFL speeds, and hand counts of the operations of one
+ * Riemann solve and one state conversion.
  *
  * The arithmetic is templated on the scalar type:
  *   double   - the FP64 reference
@@ -165,41 +175,16 @@ enum { FLAG_NONPHYS = 1, FLAG_FLOOR = 2 };
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2, BC_COARSE_FINE = 3, BC_INFLOW = 4 };
 const int NG = 4;  // ghost width: flattening reaches 3 zones past a traced zone
 
+// a b > 0: the sign tests of the MC slope and the CW84 limiter compare a
+// product of two differences of one field with zero.
+template <class S> inline bool pos_product(S a, S b) { return V(a * b) > 0; }
+
 // Per-step constants in the reconstruction scalar.  They are formed in FP64
 // from gamma, dt and h, then rounded to S once.
-// Scalars whose primal is FP32 (the FP32-reconstruction mode).  The product
-// of two wave speeds W = rho c can leave the FP32 range (W reaches 1e19 in
-// white-dwarf matter in cgs units), so these take 1/W_L and 1/W_R by two
-// divisions; the FP64 scalars take both from one division, 1/(W_L W_R), as
-// 1/W_L = W_R/(W_L W_R).
-template <class S> struct F32Primal { static constexpr bool value = false; };
-template <> struct F32Primal<float> { static constexpr bool value = true; };
-template <> struct F32Primal<DualF> { static constexpr bool value = true; };
-
-// a b > 0.  The CW84 tests compare products of two differences of one
-// field, which for the pressure or energy of stellar matter in cgs units
-// (1e22 and up) leave the FP32 range: FP32 scalars decide from the signs of
-// a and b, FP64 scalars from the product.
-template <class S> inline bool same_sign(S a, S b) {
-  if constexpr (F32Primal<S>::value) return (V(a) > 0 && V(b) > 0) || (V(a) < 0 && V(b) < 0);
-  else return V(a * b) > 0;
-}
-
-template <class S> void pair_reciprocals(S a, S b, S one, S& ia, S& ib) {
-  if constexpr (F32Primal<S>::value) {
-    ia = one / a;
-    ib = one / b;
-  } else {
-    const S iab = one / (a * b);
-    ia = b * iab;
-    ib = a * iab;
-  }
-}
-
 template <class S> struct Consts {
-  S gamma, gm1, gm1inv, beta, small_dens, small_pres, ismall_dens;
+  S gamma, gm1, beta, small_dens, small_pres;
   S dtdx[3], dt2h[3], dt3h[3], hdtg[3];
-  S half, one, two, three, six, sixth, two3, c033, ten, c075;
+  S half, one, two, three, six, two3, c033, ten, c075;
   bool grav;
   int limiter, flattening, iters;
 };
@@ -208,11 +193,9 @@ Consts<S> make_consts(const OParams& P, double dt, const double h[3]) {
   Consts<S> K;
   K.gamma = S(P.gamma);
   K.gm1 = S(P.gamma - 1.0);
-  K.gm1inv = S(1.0 / (P.gamma - 1.0));
   K.beta = S((P.gamma + 1.0) / (2.0 * P.gamma));
   K.small_dens = S(P.small_dens);
   K.small_pres = S(P.small_pres);
-  K.ismall_dens = S(1.0 / P.small_dens);
   for (int d = 0; d < 3; ++d) {
     K.dtdx[d] = S(dt / h[d]);
     K.dt2h[d] = S(dt / (2.0 * h[d]));
@@ -220,7 +203,7 @@ Consts<S> make_consts(const OParams& P, double dt, const double h[3]) {
     K.hdtg[d] = S(0.5 * dt * P.grav[d]);
   }
   K.half = S(0.5); K.one = S(1.0); K.two = S(2.0); K.three = S(3.0); K.six = S(6.0);
-  K.sixth = S(1.0 / 6.0); K.two3 = S(2.0 / 3.0); K.c033 = S(0.33); K.ten = S(10.0);
+  K.two3 = S(2.0 / 3.0); K.c033 = S(0.33); K.ten = S(10.0);
   K.c075 = S(0.75);
   K.grav = (P.grav[0] != 0.0 || P.grav[1] != 0.0 || P.grav[2] != 0.0);
   K.limiter = P.limiter;
@@ -234,11 +217,15 @@ Consts<S> make_consts(const OParams& P, double dt, const double h[3]) {
 // state R (primitive, xyz order: rho, u, v, w, p).
 //
 // Two-shock approximation (Colella-Woodward 1984 Sec. 2, Colella-Glaz 1985):
-// both nonlinear waves follow the shock Hugoniot, with Lagrangian wave speed
-//   W_s(p) = C_s sqrt(1 + beta (p/p_s - 1)),  C_s = sqrt(gamma p_s rho_s),
-// and the star pressure solves u*_R(p) = u*_L(p) by a fixed number of Newton
-// steps from the acoustic guess.  The Newton slope of each branch is
-//   |dp/du*_s| = Z_s = 2 W_s^3 / (W_s^2 + C_s^2),  so  1/Z_s = (1 + (C_s/W_s)^2) / (2 W_s).
+// both nonlinear waves follow the shock Hugoniot.  With the Lagrangian sound
+// speed C_s = sqrt(gamma p_s rho_s) of side s, a wave of post-wave pressure p
+// moves with the Lagrangian speed
+//   W_s(p) = C_s sqrt(1 + beta (p/p_s - 1)),   beta = (gamma + 1)/(2 gamma),
+// and leaves the velocity u*_L = u_L - (p - p_L)/W_L behind it on the left,
+// u*_R = u_R + (p - p_R)/W_R on the right.  The star pressure makes the two
+// agree; it is found by a fixed number of Newton steps from the acoustic
+// guess, each branch's slope |dp/du*_s| taken as Z_s = 2 W_s^3/(W_s^2 + C_s^2).
+// Each quantity below is that formula written out as it stands.
 template <class S>
 void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int& flags) {
   const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
@@ -251,42 +238,42 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   S p = ((cr * pl + cl * pr) + (cl * cr) * (ul - ur)) / (cl + cr);
   if (V(p) < V(K.small_pres)) flags |= FLAG_FLOOR;
   p = smax(p, K.small_pres);
-  const S ipl = K.one / pl, ipr = K.one / pr;
+  auto wave_speed = [&](S c, S ps) { return c * ssqrt(K.one + K.beta * (p / ps - K.one)); };
   for (int it = 0; it < K.iters; ++it) {
-    const S wl = cl * ssqrt(K.one + K.beta * (p * ipl - K.one));
-    const S wr = cr * ssqrt(K.one + K.beta * (p * ipr - K.one));
-    S iwl, iwr;
-    pair_reciprocals(wl, wr, K.one, iwl, iwr);
-    const S xl = cl * iwl, xr = cr * iwr;
-    const S izl = K.half * iwl * (K.one + xl * xl);
-    const S izr = K.half * iwr * (K.one + xr * xr);
-    const S usl = ul - (p - pl) * iwl;
-    const S usr = ur + (p - pr) * iwr;
-    p = p - (usr - usl) / (izl + izr);
+    const S wl = wave_speed(cl, pl);
+    const S wr = wave_speed(cr, pr);
+    const S zl = K.two * wl * wl * wl / (wl * wl + cl * cl);
+    const S zr = K.two * wr * wr * wr / (wr * wr + cr * cr);
+    const S usl = ul - (p - pl) / wl;
+    const S usr = ur + (p - pr) / wr;
+    p = p - zl * zr * (usr - usl) / (zl + zr);
     if (V(p) < V(K.small_pres)) flags |= FLAG_FLOOR;
     p = smax(p, K.small_pres);
   }
-  const S wl = cl * ssqrt(K.one + K.beta * (p * ipl - K.one));
-  const S wr = cr * ssqrt(K.one + K.beta * (p * ipr - K.one));
-  S iwl, iwr;
-  pair_reciprocals(wl, wr, K.one, iwl, iwr);
+  const S wl = wave_speed(cl, pl);
+  const S wr = wave_speed(cr, pr);
   const S us = ((wl * ul + wr * ur) + (pl - pr)) / (wl + wr);
 
   // Sample the wave fan at x/t = 0 on one side of the contact.  Outer state:
   // the side's input; star state: (rho*_s, u*, p*) with rho* from the Hugoniot
-  // 1/rho* = 1/rho_s - (p* - p_s)/W_s^2.  A shock is a single jump at speed
+  // 1/rho* = 1/rho_s - (p* - p_s)/W_s^2 (floored at small_dens, also when the
+  // right-hand side is not positive).  A shock is a single jump at speed
   // u_s -/+ W_s/rho_s; a rarefaction is a linear fan between its head
-  // (u_s -/+ c_s) and tail (u* -/+ c*_s).
+  // (u_s -/+ c_s, c_s = sqrt(gamma p_s/rho_s)) and tail (u* -/+ c*_s,
+  // c*_s = sqrt(gamma p*/rho*_s)).
+  auto star_density = [&](S rs_, S ps, S ws) {
+    const S vstar = K.one / rs_ - (p - ps) / (ws * ws);
+    S rs = K.one / vstar;
+    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; }
+    return rs;
+  };
   auto sample_left = [&](S st[5]) {
-    const S irho = K.one / rl;
-    const S vstar = irho - (p - pl) * (iwl * iwl);
-    S rs = K.one / vstar, ivs = vstar;  // ivs = 1/rho* (floored with it)
-    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; ivs = K.ismall_dens; }
-    const S cst = ssqrt(K.gamma * p * ivs);
-    const S co = cl * irho;
+    const S rs = star_density(rl, pl, wl);
+    const S cst = ssqrt(K.gamma * p / rs);
+    const S co = ssqrt(K.gamma * pl / rl);
     S r_ = rl, u_ = ul, p_ = pl;  // outer
     if (V(p) > V(pl)) {
-      const S sh = ul - wl * irho;
+      const S sh = ul - wl / rl;
       if (!(V(sh) >= 0)) { r_ = rs; u_ = us; p_ = p; }
     } else {
       const S hd = ul - co, tl = us - cst;
@@ -303,15 +290,12 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
     st[0] = r_; st[1] = u_; st[2] = p_; st[3] = vl1; st[4] = vl2;
   };
   auto sample_right = [&](S st[5]) {
-    const S irho = K.one / rr;
-    const S vstar = irho - (p - pr) * (iwr * iwr);
-    S rs = K.one / vstar, ivs = vstar;  // ivs = 1/rho* (floored with it)
-    if (!(V(vstar) > 0) || V(rs) < V(K.small_dens)) { flags |= FLAG_FLOOR; rs = K.small_dens; ivs = K.ismall_dens; }
-    const S cst = ssqrt(K.gamma * p * ivs);
-    const S co = cr * irho;
+    const S rs = star_density(rr, pr, wr);
+    const S cst = ssqrt(K.gamma * p / rs);
+    const S co = ssqrt(K.gamma * pr / rr);
     S r_ = rr, u_ = ur, p_ = pr;
     if (V(p) > V(pr)) {
-      const S sh = ur + wr * irho;
+      const S sh = ur + wr / rr;
       if (!(V(sh) <= 0)) { r_ = rs; u_ = us; p_ = p; }
     } else {
       const S hd = ur + co, tl = us + cst;
@@ -327,7 +311,6 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
     }
     st[0] = r_; st[1] = u_; st[2] = p_; st[3] = vr1; st[4] = vr2;
   };
-
   S g[5];  // Godunov state in the rotated frame: rho, u_n, p, u_t1, u_t2
   if (V(us) > 0) {
     sample_left(g);
@@ -341,7 +324,7 @@ void riemann(const S L[5], const S R[5], int d, const Consts<S>& K, S F[5], int&
   }
   // Euler flux of the Godunov state, rotated back to xyz component order.
   const S m = g[0] * g[1];
-  const S e = g[2] * K.gm1inv + K.half * g[0] * ((g[1] * g[1] + g[3] * g[3]) + g[4] * g[4]);
+  const S e = g[2] / K.gm1 + K.half * g[0] * ((g[1] * g[1] + g[3] * g[3]) + g[4] * g[4]);
   F[0] = m;
   F[1 + d] = m * g[1] + g[2];
   F[1 + t1] = m * g[3];
@@ -358,7 +341,7 @@ S ppm_slope(S am, S a0, S ap, const Consts<S>& K) {
   const S dc = K.half * (ap - am);
   if (!K.limiter) return dc;
   const S dl = a0 - am, dr = ap - a0;
-  if (same_sign(dl, dr)) return scopysign(smin(smin(sabs(dc), K.two * sabs(dl)), K.two * sabs(dr)), dc);
+  if (pos_product(dl, dr)) return scopysign(smin(smin(sabs(dc), K.two * sabs(dl)), K.two * sabs(dr)), dc);
   return S(0.0);
 }
 
@@ -372,8 +355,8 @@ void ppm_parabola(const S a[5], S phi, const Consts<S>& K, S& aL, S& aR, S& a6) 
   const S s0 = ppm_slope(a[1], a[2], a[3], K);
   const S sp = ppm_slope(a[2], a[3], a[4], K);
   const S a0 = a[2];
-  aL = K.half * (a[1] + a0) - (s0 - sm) * K.sixth;
-  aR = K.half * (a0 + a[3]) - (sp - s0) * K.sixth;
+  aL = K.half * (a[1] + a0) - (s0 - sm) / K.six;
+  aR = K.half * (a0 + a[3]) - (sp - s0) / K.six;
   if (K.limiter) {
     if (K.flattening) {
       const S omp = K.one - phi;
@@ -382,28 +365,18 @@ void ppm_parabola(const S a[5], S phi, const Consts<S>& K, S& aL, S& aR, S& a6) 
     }
     // a0 is an extremum when (aR - a0)(a0 - aL) <= 0; otherwise the
     // parabola overshoots an edge when dq (a0 - mid) > dq^2/6 (or
-    // < -dq^2/6).  In FP32 these are decided from signs: dq and
-    // a0 - mid -/+ dq/6 have the same (opposite) sign.
-    if (!same_sign(aR - a0, a0 - aL)) {
+    // < -dq^2/6), dq = aR - aL, mid = (aL + aR)/2.
+    if (!pos_product(aR - a0, a0 - aL)) {
       aL = a0;
       aR = a0;
     } else {
       const S dq = aR - aL;
       const S m = a0 - K.half * (aL + aR);
-      bool hi, lo;
-      if constexpr (F32Primal<S>::value) {
-        const S q = dq * K.sixth;
-        hi = same_sign(dq, m - q);
-        lo = same_sign(dq, -(m + q));
-      } else {
-        const S t = dq * m;
-        const S d2 = dq * dq * K.sixth;
-        hi = V(t) > V(d2);
-        lo = V(-d2) > V(t);
-      }
-      if (hi) {
+      const S t = dq * m;
+      const S d2 = dq * dq / K.six;
+      if (V(t) > V(d2)) {
         aL = K.three * a0 - K.two * aR;
-      } else if (lo) {
+      } else if (V(-d2) > V(t)) {
         aR = K.three * a0 - K.two * aL;
       }
     }
@@ -434,13 +407,13 @@ void trace_zone(const S aL[5], const S aR[5], const S a6[5], const S cell[6], in
   S da[5];
   for (int m = 0; m < 5; ++m) da[m] = aR[m] - aL[m];
   const S r = cell[0], un = cell[1 + d], c = cell[5];
-  const S rc = r * c, c2 = c * c, ic2 = K.one / c2, hic2 = K.half * ic2, cor = c / r;
+  const S rc = r * c, c2 = c * c;
   const S lam[3] = {un - c, un, un + c};
   const S zero(0.0);
 
   auto edge = [&](const S ref[5], S a1, S a2, S a3, S at1, S at2, S q[5]) {
     q[0] = ref[0] - ((a1 + a3) + a2);
-    q[mn] = ref[mn] + cor * (a1 - a3);
+    q[mn] = ref[mn] + c / r * (a1 - a3);
     q[4] = ref[4] - c2 * (a1 + a3);
     q[m1] = ref[m1] - at1;
     q[m2] = ref[m2] - at2;
@@ -461,19 +434,19 @@ void trace_zone(const S aL[5], const S aR[5], const S a6[5], const S cell[6], in
     if (V(lam[0]) > 0) {
       const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], sg[0], K);
       const S du = ref[mn] - ppm_ip(aR[mn], da[mn], a6[mn], sg[0], K);
-      a1 = (dp - rc * du) * hic2;
+      a1 = (dp - rc * du) / (K.two * c2);
     }
     if (V(lam[1]) > 0) {
       const S dr = ref[0] - ppm_ip(aR[0], da[0], a6[0], sg[1], K);
       const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], sg[1], K);
-      a2 = dr - dp * ic2;
+      a2 = dr - dp / c2;
       at1 = ref[m1] - ppm_ip(aR[m1], da[m1], a6[m1], sg[1], K);
       at2 = ref[m2] - ppm_ip(aR[m2], da[m2], a6[m2], sg[1], K);
     }
     if (V(lam[2]) > 0) {
       const S dp = ref[4] - ppm_ip(aR[4], da[4], a6[4], sg[2], K);
       const S du = ref[mn] - ppm_ip(aR[mn], da[mn], a6[mn], sg[2], K);
-      a3 = (dp + rc * du) * hic2;
+      a3 = (dp + rc * du) / (K.two * c2);
     }
     edge(ref, a1, a2, a3, at1, at2, qp);
   }
@@ -486,19 +459,19 @@ void trace_zone(const S aL[5], const S aR[5], const S a6[5], const S cell[6], in
     if (V(lam[0]) < 0) {
       const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], sg[0], K);
       const S du = ref[mn] - ppm_im(aL[mn], da[mn], a6[mn], sg[0], K);
-      a1 = (dp - rc * du) * hic2;
+      a1 = (dp - rc * du) / (K.two * c2);
     }
     if (V(lam[1]) < 0) {
       const S dr = ref[0] - ppm_im(aL[0], da[0], a6[0], sg[1], K);
       const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], sg[1], K);
-      a2 = dr - dp * ic2;
+      a2 = dr - dp / c2;
       at1 = ref[m1] - ppm_im(aL[m1], da[m1], a6[m1], sg[1], K);
       at2 = ref[m2] - ppm_im(aL[m2], da[m2], a6[m2], sg[1], K);
     }
     if (V(lam[2]) < 0) {
       const S dp = ref[4] - ppm_im(aL[4], da[4], a6[4], sg[2], K);
       const S du = ref[mn] - ppm_im(aL[mn], da[mn], a6[mn], sg[2], K);
-      a3 = (dp + rc * du) * hic2;
+      a3 = (dp + rc * du) / (K.two * c2);
     }
     edge(ref, a1, a2, a3, at1, at2, qm);
   }
@@ -528,8 +501,7 @@ template <class S>
 void cons_to_prim_floor(const S U[5], const Consts<S>& K, S q[5], int& flags) {
   if (V(U[0]) < V(K.small_dens)) flags |= FLAG_FLOOR;
   const S r = smax(U[0], K.small_dens);
-  const S ir = K.one / r;  // one division for the three velocities
-  const S u = U[1] * ir, v = U[2] * ir, w = U[3] * ir;
+  const S u = U[1] / r, v = U[2] / r, w = U[3] / r;
   const S ke = K.half * r * ((u * u + v * v) + w * w);
   S p = K.gm1 * (U[4] - ke);
   if (V(p) < V(K.small_pres)) flags |= FLAG_FLOOR;
@@ -543,7 +515,7 @@ void prim_to_cons(const S q[5], const Consts<S>& K, S U[5]) {
   U[1] = q[0] * q[1];
   U[2] = q[0] * q[2];
   U[3] = q[0] * q[3];
-  U[4] = q[4] * K.gm1inv + K.half * q[0] * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
+  U[4] = q[4] / K.gm1 + K.half * q[0] * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]);
 }
 
 // ------------------------------------------------------------ 3-D arrays ---
@@ -590,6 +562,9 @@ struct Step {
   const A* RX = nullptr;
   int ns = 0;
   A* RXnew = nullptr;
+  // non-null: stop after O3 and write the flattening coefficient of the
+  // traced zones of the window here
+  double* phi_out = nullptr;
 
   const A& rx_at(int s, const int x[3]) const {
     return RX[(((size_t)s * N[2] + (x[2] + NG)) * N[1] + (x[1] + NG)) * N[0] + (x[0] + NG)];
@@ -671,6 +646,11 @@ struct Step {
       }
       flat.at(x) = phi;
     });
+    if (phi_out) {  // O3 alone: the coefficient over the traced zones, x fastest
+      size_t i = 0;
+      for_region(glo, ghi, [&](const int x[3]) { phi_out[i++] = V(flat.at(x)); });
+      return flags;
+    }
 
     // O4 + O5: parabolas and traced edge states on the traced zones
     stage(ST_TRACE);
@@ -1110,6 +1090,53 @@ int oracle_riemann(const double L[5], const double R[5], int d, const OParams* P
   Consts<double> K = make_consts<double>(*P, 1.0, h);
   int fl = 0;
   riemann(L, R, d, K, F, fl);
+  return fl;
+}
+
+// O3 alone, for tests: after O2 on the stored zones of one box (ghosts of U
+// as given), the flattening coefficient phi of every traced zone [-1, n]^3,
+// written to phi ((n+2)^3 values, x fastest).  Returns the status flags or -1.
+int oracle_flatten(const double* U, const int n[3], const OParams* P, double* phi) {
+  const int wlo[3] = {0, 0, 0}, whi[3] = {n[0] - 1, n[1] - 1, n[2] - 1};
+  if (!U || !phi || !P || !window_ok(n, wlo, whi)) return -1;
+  Step<double, double> st;
+  st.U = U;
+  for (int d = 0; d < 3; ++d) { st.n[d] = n[d]; st.N[d] = n[d] + 2 * NG; st.h[d] = 1.0; }
+  st.P = P;
+  st.dt = 1.0;
+  const double h[3] = {1.0, 1.0, 1.0};
+  st.K = make_consts<double>(*P, 1.0, h);
+  st.phi_out = phi;
+  return st.run(wlo, whi, nullptr, nullptr, false);
+}
+
+// Operation counts of single pieces of the method with the Counted scalar,
+// for the op-count pins.  what = 0: one Riemann solve (O6) of the face normal
+// to x, in = L[5] then R[5], out = the flux F[5].  what = 1: one conversion
+// of a corrected state as in O8/O9 without the correction, primitive ->
+// conserved -> primitive with floors, in = q[5], out = the primitive state.
+// counts[kind] (add/sub, mul, div, sqrt, min/max) receives the counts.
+// Returns the status flags or -1.
+int oracle_count_ops(int what, const double* in, const OParams* P, double* out, unsigned long long counts[5]) {
+  if (!in || !out || !P || !counts || what < 0 || what > 1) return -1;
+  const double h[3] = {1.0, 1.0, 1.0};
+  Consts<Counted> K = make_consts<Counted>(*P, 1.0, h);
+  std::memset(g_ops, 0, sizeof(g_ops));
+  g_stage = 0;
+  int fl = 0;
+  if (what == 0) {
+    Counted L[5], R[5], F[5];
+    for (int m = 0; m < 5; ++m) { L[m] = Counted(in[m]); R[m] = Counted(in[5 + m]); }
+    riemann(L, R, 0, K, F, fl);
+    for (int m = 0; m < 5; ++m) out[m] = F[m].v;
+  } else {
+    Counted q[5], u[5], qo[5];
+    for (int m = 0; m < 5; ++m) q[m] = Counted(in[m]);
+    prim_to_cons(q, K, u);
+    cons_to_prim_floor(u, K, qo, fl);
+    for (int m = 0; m < 5; ++m) out[m] = qo[m].v;
+  }
+  for (int k = 0; k < OP_NKIND; ++k) counts[k] = g_ops[0][k];
   return fl;
 }
 

@@ -13,10 +13,10 @@
 // quantity, every box's grid contiguous inside a plane), so each lane of a
 // wavefront touches consecutive addresses on every load and store.
 //
-// Every formula is evaluated in the same order as the definition of the
-// method (no contraction: built with -ffp-contract=off; IEEE division and
-// square root), so that the FP64 results agree with a serial evaluation of
-// the same definition to the last bit.
+// Every formula is a C expression evaluated as written (no contraction:
+// built with -ffp-contract=off).  The pointwise arithmetic (ppm_math.h)
+// uses reciprocal forms of the method's divisions, so the results agree
+// with a serial evaluation of the plain definition to rounding.
 #include <hip/hip_runtime.h>
 
 #include "ppm_device.h"

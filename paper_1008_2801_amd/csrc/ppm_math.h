@@ -2,6 +2,16 @@
 // kernels and compilable for the host (for CPU checks of the derivatives).
 // Every formula is a C expression evaluated left to right; built without
 // FP contraction, the results are those of IEEE double/float arithmetic.
+//
+// The formulas are algebraically those of the method, arranged to divide
+// less often: the Newton step of the two-shock solver works with 1/p_s,
+// 1/W_s and 1/Z_s = (1 + (C_s/W_s)^2)/(2 W_s) (in FP64 both 1/W_s of a step
+// from one division, 1/(W_L W_R)); the star sound speed uses 1/rho* from
+// the Hugoniot instead of dividing by rho*; the outer sound speed is
+// C_s/rho_s; a corrected state's three velocities share one 1/rho; the
+// tracing's wave amplitudes multiply by 1/c^2.  They round differently
+// from the plain definition (which the CPU reference evaluates), so the
+// two agree to rounding, not bit for bit.
 #pragma once
 
 #include "ppm.h"
@@ -115,18 +125,13 @@ PPM_HD double sqrt_phys(double x) {
 }
 PPM_HD float sqrt_phys(float x) { return __builtin_sqrtf(x); }
 template <class S> PPM_HD S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
-// a b > 0.  The CW84 tests compare products of two differences of one
-// field, which for the pressure or energy of stellar matter in cgs units
-// (1e22 and up) leave the FP32 range: FP32 decides from the signs of a and
-// b, FP64 from the product.
-template <class S> PPM_HD bool same_sign(S a, S b) {
-  if constexpr (sizeof(S) == 4) return (a > S(0) && b > S(0)) || (a < S(0) && b < S(0));
-  else return a * b > S(0);
-}
+// a b > 0: the MC slope and the CW84 limiter test the sign of a product of
+// two differences of one field.
+template <class S> PPM_HD bool same_sign(S a, S b) { return a * b > S(0); }
 
 // 1/a and 1/b of the two wave speeds W_L, W_R.  FP64: from one division,
-// 1/a = b/(a b).  FP32: two divisions, since the product of two wave speeds
-// of stellar matter in cgs units can leave the FP32 range.
+// 1/a = b/(a b).  FP32: two divisions, which keep the FP32 range of a
+// single wave speed.
 template <class S> PPM_HD void pair_recip(S a, S b, S& ia, S& ib) {
   if constexpr (sizeof(S) == 4) {
     ia = S(1) / a;
@@ -150,18 +155,12 @@ template <class S> PPM_HD void pair_recip(S a, S b, S& ia, S& ib) {
 #define C075 S(0.75)
 
 // The CW84 overshoot tests dq m > dq^2/6 (hi) and dq m < -dq^2/6 (lo),
-// m = a0 - (aL + aR)/2; in FP32 from the signs of dq and m -/+ dq/6.
+// m = a0 - (aL + aR)/2.
 template <class S> PPM_HD void cw_overshoot(S dq, S m, bool& hi, bool& lo) {
-  if constexpr (sizeof(S) == 4) {
-    const S q = dq * SIXTH;
-    hi = same_sign(dq, m - q);
-    lo = same_sign(dq, -(m + q));
-  } else {
-    const S t = dq * m;
-    const S d2 = dq * dq * SIXTH;
-    hi = t > d2;
-    lo = -d2 > t;
-  }
+  const S t = dq * m;
+  const S d2 = dq * dq * SIXTH;
+  hi = t > d2;
+  lo = -d2 > t;
 }
 
 // ------------------------------------------------------- O6: Riemann -------

@@ -50,3 +50,43 @@ def rescaled(wl, R=UNIT_R, P=UNIT_P):
         w.layout.view(w.arena, b)[...] *= sc[:, None, None, None]
     w.grav = tuple(g * V * V for g in wl.grav)
     return w, sc[:, None, None, None], V
+
+
+def dts_close(got, ref, rtol=1e-12):
+    """Time-step sequences equal to rtol (the first step's dt is computed
+    from the same state on both sides; later ones from states that agree
+    to rounding)."""
+    return len(got) == len(ref) and all(abs(a - b) <= rtol * abs(b) for a, b in zip(got, ref))
+
+
+def parity_report(tag, pairs, tol):
+    """Per-field parity of GPU arrays against reference arrays: pairs is a
+    list of (gpu, ref) arrays of shape (ncomp, ...).  Each field's error is
+    max |gpu - ref| / max |ref| over all pairs (a field identically zero in
+    the reference is normalised by the largest reference field).  Prints
+    the errors and how many values differ in their bits; asserts every
+    field error <= tol and names the worst value's pair and position if
+    not."""
+    ncomp = pairs[0][1].shape[0]
+    num = np.zeros(ncomp)
+    den = np.zeros(ncomp)
+    nbits = 0
+    total = 0
+    where = [None] * ncomp
+    for k, (g, r) in enumerate(pairs):
+        d = np.abs(g - r)
+        for c in range(ncomp):
+            m = float(np.nanmax(d[c])) if d[c].size else 0.0
+            if not (m <= num[c]):
+                num[c] = m
+                where[c] = (k, np.unravel_index(int(np.nanargmax(d[c])), d[c].shape))
+            den[c] = max(den[c], float(np.abs(r[c]).max()) if r[c].size else 0.0)
+        nbits += int(np.count_nonzero(g != r))
+        total += g.size
+    scale = np.where(den > 0, den, den.max() if den.max() > 0 else 1.0)
+    err = num / scale
+    print(f"{tag}: per-field error {np.array2string(err, precision=2)}, "
+          f"{nbits} of {total} values differ in their bits", flush=True)
+    bad = [c for c in range(ncomp) if not err[c] <= tol]
+    assert not bad, (tag, [(c, err[c], where[c]) for c in bad])
+    return err, nbits

@@ -14,7 +14,7 @@ from oracle import amr as A  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from paper_1008_2801_amd import inputs as I  # noqa: E402
 from paper_1008_2801_amd import ppm as P  # noqa: E402
-from tests.helpers import interior, field_errors  # noqa: E402
+from tests.helpers import dts_close, interior, parity_report  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -57,16 +57,14 @@ def gpu_run(t, nsteps, dt=0.0, **pk):
     return out
 
 
-def compare(t, gc, gf, oc, of, tol=TOL):
-    worst, nbits = 0.0, 0
+def compare(t, gc, gf, oc, of, tol=TOL, tag="two-level"):
+    """Per-field parity over both levels' valid zones."""
+    pairs = []
     for lay, arena, ref in ((t.coarse.layout, gc, oc), (t.fine.layout, gf, of)):
         for b in range(lay.nbox):
-            g = interior(lay.view(arena, b))
-            o = interior(ref[b])
-            worst = max(worst, field_errors(g, o).max())
-            nbits += int(np.count_nonzero(g != o))
-    assert worst <= tol, (worst, nbits)
-    return worst, nbits
+            pairs.append((interior(lay.view(arena, b)), interior(ref[b])))
+    err, nbits = parity_report(tag, pairs, tol)
+    return float(err.max()), nbits
 
 
 def _ragged_prim(x, y, z):
@@ -93,9 +91,8 @@ def test_two_level_step_matches_oracle(name):
     p = O.params(gamma=t.coarse.gamma, grav=t.coarse.grav)
     oc, of, odts, ofl = A.advance(hier(t), oc, of, nsteps, t.coarse.dx, p)
     assert flags == 0 and ofl == 0
-    assert dts == odts
-    worst, nbits = compare(t, gc, gf, oc, of)
-    print(f"{name}: max field error {worst:.3e}, differing values {nbits}")
+    assert dts_close(dts, odts)
+    compare(t, gc, gf, oc, of, tag=f"two-level {name}, {nsteps} coarse steps")
 
 
 def test_fill_fine_matches_oracle_bitwise():

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O  # noqa: E402
 from paper_1008_2801_amd import inputs as I  # noqa: E402
 from paper_1008_2801_amd import ppm as P  # noqa: E402
-from tests.helpers import interior, field_errors  # noqa: E402
+from tests.helpers import dts_close, interior, parity_report  # noqa: E402
 from tests.test_gpu_parity import _uneven_level, _sample_windows  # noqa: E402
 from tests.test_oracle_step import _random_state  # noqa: E402
 
@@ -63,18 +63,15 @@ def oracle_run_species(wl, rx, ns, nsteps, dt=None, **pk):
     return O.advance_species(lay.boxes(), lay.domain(), lay.bc, st, sp, nsteps, wl.dx, p, dt=dt)
 
 
-def compare_species(wl, ns, garena, gspecies, ost, osp, tol=TOL):
-    """Per-field (state) and per-species errors over the valid zones."""
+def compare_species(wl, ns, garena, gspecies, ost, osp, tol=TOL, tag="species"):
+    """Per-field (state) and per-species parity over the valid zones."""
     lay = wl.layout
-    worst_u = max(field_errors(interior(lay.view(garena, b)), interior(ost[b])).max() for b in range(lay.nbox))
-    worst_x, nbits = 0.0, 0
-    for s in range(ns):
-        g = np.concatenate([interior(I.species_view(lay, gspecies, ns, b))[s].ravel() for b in range(lay.nbox)])
-        o = np.concatenate([interior(osp[b])[s].ravel() for b in range(lay.nbox)])
-        worst_x = max(worst_x, np.abs(g - o).max() / np.abs(o).max())
-        nbits += int(np.count_nonzero(g != o))
-    assert worst_u <= tol and worst_x <= tol, (worst_u, worst_x, nbits)
-    return worst_u, worst_x, nbits
+    eu, _ = parity_report(f"{tag}: state", [(interior(lay.view(garena, b)), interior(ost[b]))
+                                            for b in range(lay.nbox)], tol)
+    ex, nbits = parity_report(f"{tag}: partial densities",
+                              [(interior(I.species_view(lay, gspecies, ns, b)), interior(osp[b]))
+                               for b in range(lay.nbox)], tol)
+    return float(eu.max()), float(ex.max()), nbits
 
 
 def _case(name):
@@ -101,9 +98,8 @@ def test_species_step_matches_oracle(name):
     _, ga, gx, dts, flags = gpu_run_species(wl, rx, ns, nsteps)
     ost, osp, odts, ofl = oracle_run_species(wl, rx, ns, nsteps)
     assert flags == 0 and ofl == 0
-    assert dts == odts
-    wu, wx, nbits = compare_species(wl, ns, ga, gx, ost, osp)
-    print(f"{name}: state {wu:.3e}, species {wx:.3e}, differing species values {nbits}")
+    assert dts_close(dts, odts)
+    compare_species(wl, ns, ga, gx, ost, osp, tag=f"species {name}, {nsteps} steps")
 
 
 def test_species_fp32_reconstruction_matches_oracle_fp32_mode():
@@ -113,8 +109,7 @@ def test_species_fp32_reconstruction_matches_oracle_fp32_mode():
     _, ga, gx, dts, flags = gpu_run_species(wl, rx, 2, 3)
     ost, osp, odts, ofl = oracle_run_species(wl, rx, 2, 3)
     assert flags == 0 and ofl == 0
-    wu, wx, nbits = compare_species(wl, 2, ga, gx, ost, osp, tol=1e-6)
-    print(f"fp32 species: state {wu:.3e}, species {wx:.3e}")
+    compare_species(wl, 2, ga, gx, ost, osp, tol=1e-6, tag="species, FP32 mode vs the oracle's FP32 mode")
 
 
 def test_unit_fraction_reproduces_the_density_bitwise_on_gpu():
@@ -181,11 +176,12 @@ def test_species_full_size_sampled_windows():
     p = O.params(gamma=wl.gamma)
     got = I.species_view(lay, gx, ns, 0)
     rng = np.random.default_rng(73)
+    pairs = []
     for lo, hi in _sample_windows(lay.n(0), rng, 8):
         _, ref, _ = O.step_species(st[0], sp[0], dts[0], wl.dx, p, window=(lo, hi))
         sl = (slice(None),) + tuple(slice(lo[d] + 4, hi[d] + 5) for d in (2, 1, 0))
-        err = np.abs(got[sl] - ref[sl]).max() / np.abs(ref[sl]).max()
-        assert err <= TOL, (lo, hi, err)
+        pairs.append((got[sl], ref[sl]))
+    parity_report("256^3 with two species, one step, windows", pairs, TOL)
     for s in range(ns):
         s0 = math.fsum(interior(I.species_view(lay, rx, ns, 0))[s].ravel())
         s1 = math.fsum(interior(got)[s].ravel())
