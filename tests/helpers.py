@@ -59,17 +59,26 @@ def dts_close(got, ref, rtol=1e-12):
     return len(got) == len(ref) and all(abs(a - b) <= rtol * abs(b) for a, b in zip(got, ref))
 
 
-def parity_report(tag, pairs, tol):
+def parity_report(tag, pairs, tol, state=None):
     """Per-field parity of GPU arrays against reference arrays: pairs is a
     list of (gpu, ref) arrays of shape (ncomp, ...).  Each field's error is
-    max |gpu - ref| / max |ref| over all pairs (a field identically zero in
-    the reference is normalised by the largest reference field).  Prints
-    the errors and how many values differ in their bits; asserts every
-    field error <= tol and names the worst value's pair and position if
-    not."""
+    max |gpu - ref| over all pairs divided by the field's scale: its largest
+    reference magnitude, except that for a conserved state (ncomp == 5,
+    state not False) the three momenta are scaled by at least
+    M = max over zones of sqrt(rho rho E), the momentum of the matter moving
+    at about its sound speed.  The momentum fluxes of every face carry the
+    pressure, so their rounding error is a fraction of rho c whatever the
+    flow speed; a momentum component that is nearly zero (matter at rest, a
+    flow along one axis) would otherwise turn rounding of the pressure terms
+    into large relative errors.  Prints the errors (and, where the floor
+    applies, the errors relative to the field's own maximum) and how many
+    values differ in their bits; asserts every field error <= tol and names
+    the worst value's pair and position if not."""
     ncomp = pairs[0][1].shape[0]
+    state = (ncomp == 5) if state is None else state
     num = np.zeros(ncomp)
     den = np.zeros(ncomp)
+    mscale = 0.0
     nbits = 0
     total = 0
     where = [None] * ncomp
@@ -81,11 +90,19 @@ def parity_report(tag, pairs, tol):
                 num[c] = m
                 where[c] = (k, np.unravel_index(int(np.nanargmax(d[c])), d[c].shape))
             den[c] = max(den[c], float(np.abs(r[c]).max()) if r[c].size else 0.0)
+        if state and r[0].size:
+            mscale = max(mscale, float(np.sqrt(np.abs(r[0] * r[4])).max()))
         nbits += int(np.count_nonzero(g != r))
         total += g.size
-    scale = np.where(den > 0, den, den.max() if den.max() > 0 else 1.0)
+    own = np.where(den > 0, den, den.max() if den.max() > 0 else 1.0)
+    scale = own.copy()
+    if state:
+        scale[1:4] = np.maximum(scale[1:4], mscale)
     err = num / scale
-    print(f"{tag}: per-field error {np.array2string(err, precision=2)}, "
+    extra = ""
+    if state and np.any(scale != own):
+        extra = f" (momenta against their own maxima {np.array2string(num[1:4] / own[1:4], precision=2)})"
+    print(f"{tag}: per-field error {np.array2string(err, precision=2)}{extra}, "
           f"{nbits} of {total} values differ in their bits", flush=True)
     bad = [c for c in range(ncomp) if not err[c] <= tol]
     assert not bad, (tag, [(c, err[c], where[c]) for c in bad])

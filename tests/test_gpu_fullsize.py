@@ -3,7 +3,7 @@ oracle on sampled windows and pencils (the oracle recomputes each window
 from the same input), conservation over the whole level, the
 FP32-reconstruction error per field against FP64, and the Rayleigh-Taylor
 set-up (reflecting walls, gravity) on a reduced instance against the oracle
-in both precisions.  Bars: 1e-12 per field (FP64), 1e-6 per field against
+in both precisions.  Bars: 1e-12 per field (FP64), 1e-5 per field against
 the oracle's own FP32 mode."""
 import math
 
@@ -19,7 +19,8 @@ from tests.helpers import interior, parity_report  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
-FP32_TOL = 1e-6
+# against the oracle's FP32 mode; see test_gpu_parity.FP32_TOL
+FP32_TOL = 1e-5
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -72,8 +72,12 @@ def test_inflow_on_a_multibox_level_with_walls_matches_oracle():
     rng = np.random.default_rng(11)
     S = I.ModeSum(rng, 4, 2, (1.0, 1.0, 1.0))
 
+    # every velocity component away from zero: where a component is zero up
+    # to rounding, the tracing switches the entropy-wave term on or off with
+    # the sign of that rounding (a discontinuity of the scheme at u_n = 0),
+    # and the kernels and the oracle round differently
     def prim(x, y, z):
-        return (1.0 + 0.2 * S(x, y, z), 0.0, 0.1, 0.0, 1.0)
+        return (1.0 + 0.2 * S(x, y, z), 0.05, 0.1, 0.05, 1.0)
     wl = I.Workload("inflow_boxes", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 1)
     face = np.zeros((5, 12, 24))
     x = (np.arange(24) + 0.5) * h[0]

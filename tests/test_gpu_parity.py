@@ -21,9 +21,11 @@ TOL = 1e-12
 # FP32-reconstruction mode against the oracle's FP32 mode: both round every
 # reconstruction, tracing and Riemann operation to FP32 (unit roundoff
 # 6e-8) in differently arranged formulas, and the update adds dt/h times
-# flux differences of that accuracy to the FP64 state; a few such steps
-# stay below 1e-6 of each field's maximum.
-FP32_TOL = 1e-6
+# flux differences of that accuracy to the FP64 state.  Where the step
+# cancels large terms (a hydrostatic column) or starts from rest (the
+# tracing then picks waves by the sign of FP32 rounding noise), the two
+# differ by as much as the FP32 mode differs from FP64 itself: a few 1e-6.
+FP32_TOL = 1e-5
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -84,7 +86,10 @@ def test_cfg1_full_run_matches_oracle():
 
 @pytest.mark.parametrize("limiter,iters", [(1, 3), (0, 3), (1, 0), (1, 8)])
 def test_scheme_options_match_oracle(limiter, iters):
-    wl = I.cfg2(24)
+    # the unlimited scheme is for smooth data (at the Sod jump it overshoots
+    # into negative pressures and the run collapses): the smooth state of
+    # the differentiation workload for limiter 0, the Sod recipe otherwise
+    wl = I.cfg4(24) if limiter == 0 else I.cfg2(24)
     _, arena, dts, flags, _ = gpu_run(wl, 3, limiter=limiter, riemann_iters=iters)
     ost, odts, ofl, _ = oracle_run(wl, 3, limiter=limiter, riemann_iters=iters)
     assert dts_close(dts, odts) and flags == ofl
@@ -96,7 +101,8 @@ def test_fluxes_match_oracle():
     lev, arena, dts, flags, F = gpu_run(wl, 1, fluxes=True)
     ost, odts, ofl, OF = oracle_run(wl, 1, fluxes=True)
     for d in range(3):
-        parity_report(f"20^3 fluxes along axis {d}", [(lev.flux_view(F[d], d, 0).cpu().numpy(), OF[0][d])], TOL)
+        parity_report(f"20^3 fluxes along axis {d}", [(lev.flux_view(F[d], d, 0).cpu().numpy(), OF[0][d])], TOL,
+                      state=False)
 
 
 @pytest.mark.parametrize("bc", [(0, 0, 0, 0, 0, 0), (0, 0, 0, 0, 2, 2), (1, 1, 2, 2, 0, 0)])

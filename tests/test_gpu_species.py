@@ -70,7 +70,7 @@ def compare_species(wl, ns, garena, gspecies, ost, osp, tol=TOL, tag="species"):
                                             for b in range(lay.nbox)], tol)
     ex, nbits = parity_report(f"{tag}: partial densities",
                               [(interior(I.species_view(lay, gspecies, ns, b)), interior(osp[b]))
-                               for b in range(lay.nbox)], tol)
+                               for b in range(lay.nbox)], tol, state=False)
     return float(eu.max()), float(ex.max()), nbits
 
 
@@ -181,7 +181,7 @@ def test_species_full_size_sampled_windows():
         _, ref, _ = O.step_species(st[0], sp[0], dts[0], wl.dx, p, window=(lo, hi))
         sl = (slice(None),) + tuple(slice(lo[d] + 4, hi[d] + 5) for d in (2, 1, 0))
         pairs.append((got[sl], ref[sl]))
-    parity_report("256^3 with two species, one step, windows", pairs, TOL)
+    parity_report("256^3 with two species, one step, windows", pairs, TOL, state=False)
     for s in range(ns):
         s0 = math.fsum(interior(I.species_view(lay, rx, ns, 0))[s].ravel())
         s1 = math.fsum(interior(got)[s].ravel())
