@@ -162,6 +162,29 @@ int ppm_hydro_step(ppm_ctx* ctx, const double* U, double* Unew, double* const* f
                    const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
                    void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of ppm_hydro_step, same arguments and results bit for bit, with the step
+ * workspace taken from a library-owned device array of
+ * PPM_NOALLOC_SCRATCH_BYTES instead of ppm_set_workspace.  The array is
+ * static device memory of the library, one copy per GPU, held until the
+ * process ends; its address on a device is looked up once, when the first
+ * context is created with that device current.  The call allocates and
+ * frees nothing (no hipMalloc, no event creation; profiling does not time
+ * it).  The caller still owns U, Unew, the fluxes and dt_dev.  Every call on
+ * a GPU uses that GPU's one array: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the
+ * caller.  The step writes every scratch entry it reads, so nothing is
+ * cleared between calls.  PPM_EINVAL for the errors of ppm_hydro_step and
+ * when ppm_workspace_bytes(ctx, params->precision) exceeds
+ * PPM_NOALLOC_SCRATCH_BYTES (a single box fits up to 53^3 zones in FP64,
+ * 67^3 in the FP32-reconstruction mode); PPM_EHIP if the array's address
+ * could not be found. */
+enum { PPM_NOALLOC_SCRATCH_BYTES = 134217728 /* 128 MiB */ };
+int ppm_hydro_step_noalloc(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                           const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                           void* stream);
+
 /* ppm_hydro_step that also leaves the next step's time step: dt_next_dev
  * (2 device doubles) receives what ppm_compute_dt(Unew) would write, bit
  * for bit -- the CFL rule over the valid zones of Unew, which the staged

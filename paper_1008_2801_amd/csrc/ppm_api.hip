@@ -10,6 +10,7 @@
 #include <fstream>
 #include <list>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <memory>
 #include <mutex>
@@ -413,6 +414,35 @@ std::string validate_dx(const double dx[3]) {
     if (!(dx[d] > 0.0) || !std::isfinite(dx[d])) return "dx: spacings must be positive and finite";
   return "";
 }
+// Step scratch of the allocation-free step (ppm_hydro_step_noalloc): a
+// file-scope device array of PPM_NOALLOC_SCRATCH_BYTES, one copy per GPU
+// for the life of the process.  In host code `scratch` only names the
+// symbol; its device address on each GPU comes from hipGetSymbolAddress,
+// taken once per device (with that device current) when the first context
+// is created there, and only that address is passed to kernels.
+__attribute__((used)) static __device__ __align__(256) unsigned char scratch[PPM_NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+
+// Records the scratch address of device `dev` (the current device).
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) g_scratch_ptr[dev] = ptr;
+  else g_scratch_err[dev] = (e == hipSuccess) ? hipErrorInvalidSymbol : e;
+}
+
+void* scratch_ptr(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= MAX_DEVICES) { *err = hipErrorInvalidDevice; return nullptr; }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
 }  // namespace
 
 extern "C" {
@@ -514,11 +544,13 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
       (e = hipMalloc((void**)&ctx->d_consts, sizeof(StepConsts))) != hipSuccess ||
       (e = hipMalloc((void**)&ctx->d_flags, 256)) != hipSuccess ||
       (e = hipMemset(ctx->d_flags, 0, 256)) != hipSuccess ||
-      (e = hipMemset(ctx->d_consts, 0, sizeof(StepConsts))) != hipSuccess) {
+      (e = hipMemset(ctx->d_consts, 0, sizeof(StepConsts))) != hipSuccess ||
+      (e = hipGetDevice(&ctx->device)) != hipSuccess) {
     std::fprintf(stderr, "ppm_ctx_create: %s\n", hipGetErrorString(e));
     ppm_ctx_destroy(ctx.release());
     return PPM_EHIP;
   }
+  scratch_setup(ctx->device);
   *out = ctx.release();
   return PPM_OK;
 }
@@ -620,9 +652,12 @@ int ppm_compute_dt(ppm_ctx* ctx, const double* U, const double dx[3], const ppm_
   return rc;
 }
 
+// work: the step workspace (null: the context's, ppm_set_workspace) and its
+// size; timed: record profiling events when profiling is on.
 static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
                            const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
-                           void* stream, int upto, double* dt_next = nullptr) {
+                           void* stream, int upto, double* dt_next = nullptr, void* work = nullptr,
+                           size_t work_bytes = 0, bool timed = true) {
   if (!ctx) return PPM_EINVAL;
   std::string m = validate_params(params);
   if (m.empty()) m = validate_dx(dx);
@@ -635,7 +670,11 @@ static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* 
     const char* b = (const char*)Unew;
     if (a < b + alen && b < a + alen) m = "step: U and Unew overlap (the step is out of place)";
   }
-  if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, params->precision)))
+  if (!work) {
+    work = ctx->work;
+    work_bytes = ctx->work_bytes;
+  }
+  if (m.empty() && (!work || work_bytes < ppm_workspace_bytes(ctx, params->precision)))
     m = "step: workspace missing or too small (ppm_set_workspace)";
   if (m.empty() && dt_next && !(params->cfl > 0.0 && params->cfl < 1.0)) m = "params: cfl must be in (0, 1)";
   if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
@@ -652,13 +691,13 @@ static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* 
   }
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
   auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, hipEvent_t* ev) {
-    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, ctx->work,
+    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
                                 params->gamma, params->small_dens, params->small_pres, params->limiter,
                                 params->flattening, params->riemann_iters, grav, params->grav, s, ev, upto, so),
                     "step");
   };
   if (mode == PPM_LAUNCH_BATCHED) {
-    ppm_ctx::ProfRec* r = ctx->prof ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
+    ppm_ctx::ProfRec* r = (timed && ctx->prof) ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
     rc = run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(),
              r ? r->ev.data() : nullptr);
     if (rc) return rc;
@@ -685,6 +724,27 @@ int ppm_hydro_step_dt(ppm_ctx* ctx, const double* U, double* Unew, double* const
   if (!ctx) return PPM_EINVAL;
   if (!dt_next_dev) return ctx->fail(PPM_EINVAL, "step_dt: null dt_next_dev");
   return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL, dt_next_dev);
+}
+
+int ppm_hydro_step_noalloc(ppm_ctx* ctx, const double* U, double* Unew, double* const* flux, double dt,
+                           const double* dt_dev, const double dx[3], const ppm_params* params, int32_t mode,
+                           void* stream) {
+  if (!ctx) return PPM_EINVAL;
+  const std::string m = validate_params(params);
+  if (!m.empty()) return ctx->fail(PPM_EINVAL, m);
+  const size_t need = ppm_workspace_bytes(ctx, params->precision);
+  if (need > (size_t)PPM_NOALLOC_SCRATCH_BYTES) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "step_noalloc: the level needs %zu bytes of step scratch, more than the library's %zu",
+                  need, (size_t)PPM_NOALLOC_SCRATCH_BYTES);
+    return ctx->fail(PPM_EINVAL, buf);
+  }
+  hipError_t e = hipSuccess;
+  void* ptr = scratch_ptr(ctx->device, &e);
+  if (!ptr) return ctx->hip(e == hipSuccess ? hipErrorInvalidSymbol : e, "step_noalloc: scratch address");
+  return hydro_step_impl(ctx, U, Unew, flux, dt, dt_dev, dx, params, mode, stream, STEP_FULL, nullptr, ptr,
+                         (size_t)PPM_NOALLOC_SCRATCH_BYTES, false);
 }
 
 int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream) {

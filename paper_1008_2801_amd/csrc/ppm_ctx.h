@@ -38,6 +38,7 @@ struct ppm_ctx {
   std::vector<Brick> bricks;
   std::vector<int> tB_begin;            // nbox + 1
   int fused = 0;                        // 1: final fluxes + update in one brick kernel
+  int device = -1;                      // HIP device current at ppm_ctx_create
   int tile = TILE, strip_rows = STRIP_ROWS;
   long long LS = 0, LE = 0;
   // device copies

@@ -32,7 +32,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
            "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
-           "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt")
+           "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt", "ppm_hydro_step_noalloc")
+NOALLOC_SCRATCH_BYTES = 128 << 20
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 
@@ -97,6 +98,8 @@ def lib():
                                      ctypes.POINTER(Params), ctypes.c_int32, _vp]
         L.ppm_hydro_step_dt.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_double, _vp, _dp3,
                                         ctypes.POINTER(Params), ctypes.c_int32, _vp, _vp]
+        L.ppm_hydro_step_noalloc.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), ctypes.c_double, _vp, _dp3,
+                                             ctypes.POINTER(Params), ctypes.c_int32, _vp]
         L.ppm_graph_create.argtypes = [_vp, _vp, _vp, _dp3, ctypes.POINTER(Params), ctypes.c_int32, _vp,
                                        ctypes.POINTER(_vp)]
         L.ppm_graph_launch.argtypes = [_vp, _vp]
