@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the unsplit PPM step on one MI355X.
 
-A step is one pass of the hot path over the level: ghost fill, CFL time step
+A step is one pass of the hot path over a level: ghost fill, CFL time step
 on the device, and the step itself (primitive conversion, flattening, PPM
 reconstruction, characteristic tracing, 12 two-shock Riemann solves per zone
 with corner-transport corrections, conservative update).  The default
-workload is the 256^3 single-box FP64 problem (gamma 5/3, random-mode density
-times a planar Sod jump, constant random velocity, periodic); inputs are
-synthetic and seeded and are resident in HBM before timing starts.
+workload is the largest level: the 512^3 Rayleigh-Taylor set-up as 512 boxes
+of 64^3 (walls in z, constant gravity, gamma 1.4), FP64, in the batched form
+(every stage one launch over all boxes' tiles, whole steps captured in a HIP
+graph); inputs are synthetic and seeded and are resident in HBM before
+timing starts.
 
-Prints one JSON line.  `value` is zone-updates/s (valid zones x steps / s).
-`roofline` reports the stage kernel that takes the most time, with its
-algorithmic FP64 flops per launch divided by its mean launch time (HIP events
-on the stream the kernels run on) against the FP64 vector peak.
-`cpu_baseline` times the serial CPU reference evaluation on a bounded window
-of the same workload.
+Prints one JSON line.  `value` is zone-updates/s (valid zones x steps / s)
+of the graph form; the same level is also timed with one launch per stage
+per box (`per_box`), and the ratio is `batched_over_per_box`.  `roofline`
+reports the stage kernel that takes the most time, with its algorithmic FP64
+flops per launch divided by its mean launch time (HIP events on the stream
+the kernels run on) against the FP64 vector peak.  `cpu_baseline` times the
+serial CPU reference evaluation on boxes of the same level, on one core and
+on all the cores the process may use (one box per thread at a time).
 """
 import argparse
 import json
@@ -30,10 +34,15 @@ METRIC = "zone-updates/s per PPM step: batched vs plain per-box; adjoint/forward
 
 # Algorithmic FP64 flops (add/sub, mul, div, sqrt; min/max not counted) per
 # unit of work of each stage kernel, counted by the op-counting instantiation
-# of the reference evaluation on windows of this workload's state
-# (oracle/opcount.py cfg2).  Units: see stage_units().
-FLOPS_PER_UNIT = {"prim": 15.0, "flatten": 64.99, "trace": 389.27, "riemann1": 178.06,
-                  "riemann2": 256.06, "riemann3": 286.06, "update": 45.0}
+# of the reference evaluation on windows of each workload's recipe
+# (`python oracle/opcount.py cfg2|cfg5`).  Units: see stage_units().
+FLOPS_PER_UNIT = {
+    "cfg2": {"prim": 15.0, "flatten": 64.98, "trace": 389.28, "riemann1": 178.06,
+             "riemann2": 256.06, "riemann3": 286.06, "update": 45.0},
+    "cfg5": {"prim": 15.0, "flatten": 62.0, "trace": 362.75, "riemann1": 194.0,
+             "riemann2": 266.86, "riemann3": 291.62, "update": 81.0},
+}
+STAGES = ("prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # MI355X FP32 vector peak (packed FP32 FMA), the peak of the FP32-reconstruction
@@ -74,10 +83,15 @@ def traffic_record_path(kernel, workload):
     return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
 
 
-def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor, write_factor):
+def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor, write_factor, valu_csv=None):
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the kernel from two
     rocprofv3 --pmc runs, times the factors a plain copy of known size gives,
-    stored with the digest of the kernel sources and the tiling."""
+    stored with the digest of the kernel sources and the tiling.  With
+    valu_csv (a third run with SQ_INSTS_VALU and GRBM_GUI_ACTIVE): the
+    kernel's VALU issue utilisation, SQ_INSTS_VALU x 4 cycles (a wave64 FP64
+    instruction holds a 16-lane SIMD for 4 cycles) over 1024 SIMDs x the
+    kernel's cycles (GRBM_GUI_ACTIVE / 8 XCDs), and the sustained clock,
+    those cycles over the dispatch's duration."""
     import csv
 
     def mean_kib(path, counter):
@@ -107,9 +121,41 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor,
     rec["traffic_bytes_per_launch"] = rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
     rec["step_traffic_bytes"] = (step_bytes(fetch_csv, "FETCH_SIZE", fetch_factor) +
                                  step_bytes(write_csv, "WRITE_SIZE", write_factor)) / steps
+    if valu_csv:
+        rows = [r for r in csv.DictReader(open(valu_csv)) if f"k_{kernel}<double>" in r["Kernel_Name"]]
+        by = {}
+        for r in rows:
+            by.setdefault(r["Dispatch_Id"], {})[r["Counter_Name"]] = (float(r["Counter_Value"]), r)
+        utils, clocks = [], []
+        for d in by.values():
+            if "SQ_INSTS_VALU" in d and "GRBM_GUI_ACTIVE" in d:
+                cyc = d["GRBM_GUI_ACTIVE"][0] / 8.0
+                utils.append(d["SQ_INSTS_VALU"][0] * 4.0 / (1024.0 * cyc))
+                r0 = d["GRBM_GUI_ACTIVE"][1]
+                if r0.get("Start_Timestamp") and r0.get("End_Timestamp"):
+                    ns = float(r0["End_Timestamp"]) - float(r0["Start_Timestamp"])
+                    if ns > 0:
+                        clocks.append(cyc / ns)
+        if utils:
+            rec["valu_util"] = sum(utils) / len(utils)
+        if clocks:
+            rec["clock_ghz"] = sum(clocks) / len(clocks)
     with open(traffic_record_path(kernel, workload), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def recorded_record(kernel, workload, tiling):
+    """The counter record of the kernel and workload, or None when there is
+    none or the kernels or tiling changed since it was taken."""
+    try:
+        with open(traffic_record_path(kernel, workload)) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != sources_digest() or list(rec.get("tiling", [])) != list(tiling):
+        return None
+    return rec
 
 
 def recorded_traffic(kernel, workload, tiling, key="traffic_bytes_per_launch"):
@@ -138,8 +184,22 @@ def stage_units(n):
             "riemann1": int(r1), "riemann2": int(r2), "riemann3": int(r3), "update": int(np.prod(w))}
 
 
+WORKLOADS = {
+    "cfg5": "512^3 Rayleigh-Taylor level, 512 boxes of 64^3, walls in z, g = (0,0,-1), gamma 1.4, FP64",
+    "cfg5-fp32": "512^3 Rayleigh-Taylor level, 512 boxes of 64^3, walls in z, g = (0,0,-1), gamma 1.4, "
+                 "FP32 reconstruction + FP64 fluxes and update",
+    "cfg2": "256^3 single box, gamma 5/3, random-mode density x planar Sod jump, constant velocity, periodic, FP64",
+    "cfg2-fp32": "256^3 single box as cfg2, FP32 reconstruction + FP64 fluxes and update",
+    "cfg2-small": "64^3 single box with cfg2's recipe, FP64",
+}
+
+
 def make_workload(name):
     from paper_1008_2801_amd import inputs as I
+    if name == "cfg5":
+        return I.cfg5(precision=0)
+    if name == "cfg5-fp32":
+        return I.cfg5(precision=1)
     if name == "cfg2":
         return I.cfg2()
     if name == "cfg2-small":
@@ -149,6 +209,10 @@ def make_workload(name):
         wl.precision = 1
         return wl
     raise SystemExit(f"unknown workload {name}")
+
+
+def flops_table(name):
+    return FLOPS_PER_UNIT["cfg5" if name.startswith("cfg5") else "cfg2"]
 
 
 def level_rates(wl, steps, warmup, precision, per_box=True):
@@ -508,43 +572,217 @@ def copy_bandwidth(gib=2, reps=5):
     return 2 * n * 8 / sec / 1e9
 
 
-def cpu_baseline(wl, window_edge, gamma):
-    """Serial oracle on one step of a cubic window of the workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, single_s=10.0, per_thread=2):
+    """The serial CPU oracle on whole boxes of the same level (one box's step
+    per call, each call single-threaded), first on one core for about
+    single_s seconds, then on every core of the process's affinity set, one
+    box per thread at a time (ctypes releases the GIL during each call).
+    The ghost fill and the level's dt are the oracle's own, outside the
+    timing.  A box stepped in both phases must come out bit for bit the
+    same."""
+    import concurrent.futures as cf
     import numpy as np
     from oracle import oracle as O
     lay = wl.layout
     st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
     O.fill(lay.boxes(), lay.domain(), lay.bc, st)
-    p = O.params(gamma=gamma)
-    s, _ = O.max_wavespeed(st[0], wl.dx, p)
-    dt = p.cfl / s
-    lo = (0, 0, 0)
-    hi = (window_edge - 1,) * 3
+    p = O.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision)
+    dt = p.cfl / max(O.max_wavespeed(u, wl.dx, p)[0] for u in st)
+    walls = [O.box_walls(lay.boxes(), lay.domain(), lay.bc, b) for b in range(lay.nbox)]
+    order = [int(b) for b in np.random.default_rng(7).permutation(lay.nbox)]
+
+    def one(b):
+        out, _, _ = O.step(st[b], dt, wl.dx, p, walls=walls[b])
+        return b, out
+
     t0 = time.perf_counter()
-    O.step(st[0], dt, wl.dx, p, window=(lo, hi))
-    sec = time.perf_counter() - t0
-    zones = window_edge ** 3
-    return {"value": zones / sec, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one step of the same workload on the {window_edge}^3 window of valid zones "
-                      f"at the box corner (serial C++ reference, -O2, 1 thread), {sec:.1f} s"}
+    k, zones1, first = 0, 0, None
+    while k < lay.nbox and (k == 0 or time.perf_counter() - t0 < single_s):
+        b, out = one(order[k])
+        if first is None:
+            first = (b, out)
+        zones1 += int(np.prod(lay.n(b)))
+        k += 1
+    sec1 = time.perf_counter() - t0
+    ncores = len(os.sched_getaffinity(0))
+    nb = min(lay.nbox, ncores * per_thread)
+    todo = [first[0]] + [order[(k + i) % lay.nbox] for i in range(nb - 1)]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(ncores) as ex:
+        res = list(ex.map(one, todo))
+    secn = time.perf_counter() - t0
+    zonesn = sum(int(np.prod(lay.n(b))) for b in todo)
+    same = bool(np.array_equal(res[0][1], first[1]))
+    return {"value": zonesn / secn, "unit": "zone-updates/s", "cores": ncores, "kind": "oracle",
+            "sample": f"one step of {nb} boxes of the same level ({zonesn} zones), one box per thread on "
+                      f"{ncores} threads, {secn:.1f} s wall; serial C++ reference (-O2, no contraction)",
+            "single_core": {"value": zones1 / sec1, "cores": 1,
+                            "sample": f"one step of {k} boxes ({zones1} zones) on one thread, {sec1:.1f} s"},
+            "threads_bitwise_equal_to_serial": same, "cpu_model": cpu_model()}
+
+
+def child_processes():
+    """Child processes of this process still alive (none are started)."""
+    try:
+        import psutil
+        return [c.pid for c in psutil.Process().children(recursive=True)]
+    except Exception:
+        return []
+
+
+def algorithmic_bytes_per_step(lay):
+    """HBM bytes a step must move at least: read every stored zone of U (5
+    FP64 values, ghosts included), write every valid zone of U'."""
+    import numpy as np
+    stored = sum(int(np.prod(np.asarray(lay.n(b)) + 8)) for b in range(lay.nbox))
+    return 40 * stored + 40 * lay.valid_zones()
+
+
+def headline(wl, wname, steps, warmup, per_box=True, tiling=None, autotune=True):
+    """The timed level: batched eager steps with stage profiling (the
+    roofline's kernel times), the same steps as one HIP-graph launch (the
+    value), and one launch per stage per box."""
+    import torch
+    from paper_1008_2801_amd import ppm as P
+    lay = wl.layout
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav, precision=wl.precision)
+    lev.ensure_workspace(p.precision)
+    U0 = torch.from_numpy(wl.arena).to("cuda")
+    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+    from_cache = None
+    if tiling:
+        lev.set_tiling(*tiling)
+    elif autotune:
+        Uf = U0.clone()
+        lev.fill_boundary(Uf)
+        t_, s_, from_cache = lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)
+        del Uf
+    tiling = lev.get_tiling()
+    zones = lay.valid_zones()
+    out = {"tiling": {"tile": tiling[0], "strip_rows": tiling[1]},
+           "autotune": {"from_cache": None if from_cache is None else bool(from_cache),
+                        "cache": os.path.relpath(AUTOTUNE_CACHE, ROOT) if from_cache is not None else None}}
+
+    def eager(mode, prof):
+        U = U0.clone()
+        V = lev.new_state()
+        lev.compute_dt(U, wl.dx, p, out=dtv)
+        for _ in range(warmup):
+            lev.fill_boundary(U, mode)
+            lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, mode=mode, dt_next=dtv)
+            U, V = V, U
+        torch.cuda.synchronize()
+        if prof:
+            lev.profile_read()
+            lev.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lev.fill_boundary(U, mode)
+            lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, mode=mode, dt_next=dtv)
+            U, V = V, U
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        st = None
+        if prof:
+            lev.profile_enable(False)
+            st = lev.profile_read()
+        del U, V
+        return sec, st
+
+    sec_b, prof = eager(P.BATCHED, True)
+    out["batched_eager"] = zones * steps / sec_b
+    # the graph of `steps` whole steps [fill, step], each dt from the update
+    # before it (the first from a dt pass), replayed once untimed, then timed
+    A = U0.clone()
+    B = lev.new_state()
+    g = lev.graph(A, B, wl.dx, p, steps)
+    for _ in range(max(1, warmup // max(1, steps))):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.launch()
+    torch.cuda.synchronize()
+    sec_g = time.perf_counter() - t0
+    out["graph"] = zones * steps / sec_g
+    out["ms_per_step"] = sec_g / steps * 1e3
+    g.close()
+    del A, B
+    if per_box:
+        sec_p, _ = eager(P.PER_BOX, False)
+        out["per_box"] = zones * steps / sec_p
+        out["batched_over_per_box"] = out["graph"] / out["per_box"]
+    out["flags"] = lev.check_status()
+    lev.close()
+    lev._work = None
+    del U0, lev
+    torch.cuda.empty_cache()
+    return out, prof, tiling
+
+
+def roofline(wname, lay, prof, ms_step, precision, tiling):
+    """The dominant stage kernel's algorithmic flop rate against the vector
+    peak of its precision, with the recorded counter figures of the same
+    kernel and workload (null once the kernel sources or the tiling
+    changed since the counters were taken), and the step's HBM figures."""
+    units = {k: 0 for k in STAGES}
+    for b in range(lay.nbox):
+        for k, v in stage_units(lay.n(b)).items():
+            units[k] += v
+    table = flops_table(wname)
+    stages = {k: prof[k] for k in STAGES}
+    dom = max(stages, key=lambda k: stages[k][0])
+    t_ms, cnt = stages[dom]
+    mean_s = t_ms / cnt / 1e3
+    flops = table[dom] * units[dom]
+    achieved = flops / mean_s / 1e12
+    peak = FP64_VECTOR_PEAK_TFLOPS if precision == 0 else FP32_VECTOR_PEAK_TFLOPS
+    rec = recorded_record(dom, wname, tiling) if precision == 0 else None
+    step_flops = sum(table[k] * units[k] for k in STAGES)
+    alg = algorithmic_bytes_per_step(lay)
+    r = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+         "frac": achieved / peak,
+         "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
+         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+         "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops,
+         "flops_per_unit": table[dom], "units_per_launch": units[dom],
+         "clock_ghz": rec.get("clock_ghz") if rec else None,
+         "valu_issue_util": rec.get("valu_util") if rec else None,
+         "step_traffic": rec.get("step_traffic_bytes") if rec else None,
+         "step_traffic_GBps": (rec["step_traffic_bytes"] / (ms_step / 1e3) / 1e9
+                               if rec and rec.get("step_traffic_bytes") else None),
+         "step_flop_rate_tflops": step_flops / (ms_step / 1e3) / 1e12,
+         "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": alg / (ms_step / 1e3) / 1e9,
+                 "peak_GBps": HBM_PEAK_GBS, "frac": alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS}}
+    return r
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2")
-    ap.add_argument("--cpu-window", type=int, default=160)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="single-core oracle sample length")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tiling")
+    ap.add_argument("--no-per-box", action="store_true", help="skip the one-launch-per-box timing")
     ap.add_argument("--autotune-cache", default=None,
                     help="autotuner cache file (default: the package's autotune_cache.jsonl)")
     ap.add_argument("--tiling", default=None, help="'tile,strip_rows': use this tiling instead of autotuning")
-    ap.add_argument("--fused", action="store_true",
-                    help="run the final fluxes and the update in the brick kernel (fluxes in LDS)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the 512-box batched / per-box / graph measurements")
+                    help="skip the other workloads (single box, 512-box tiling, adjoint, two-level, jet, species)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only measure the adjoint/forward cost on the 128^3 differentiation workload")
     ap.add_argument("--amr-only", action="store_true",
@@ -554,8 +792,11 @@ def main():
     ap.add_argument("--species-only", action="store_true",
                     help="with --no-extras: still measure the passive-species step")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the traffic record of the dominant kernel from two rocprofv3 --pmc "
+                    help="write the counter record of the dominant kernel from two rocprofv3 --pmc "
                          "counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--record-valu", default=None, metavar="VALU_CSV",
+                    help="with --record-traffic: a counter_collection.csv with SQ_INSTS_VALU, "
+                         "SQ_BUSY_CYCLES and GRBM_GUI_ACTIVE of the same command")
     ap.add_argument("--record-kernel", default="riemann2")
     ap.add_argument("--counter-factors", default="2.0,1.0",
                     help="FETCH_SIZE and WRITE_SIZE scale factors from the copy calibration")
@@ -574,11 +815,10 @@ def main():
         ff, wf = (float(v) for v in args.counter_factors.split(","))
         t_, s_ = (int(v) for v in args.tiling.split(","))
         record_traffic(args.record_traffic[0], args.record_traffic[1], args.record_kernel, args.workload,
-                       (t_, s_), ff, wf)
+                       (t_, s_), ff, wf, args.record_valu)
         return
 
     import torch
-    from paper_1008_2801_amd import ppm as P
 
     if args.calibrate_copy:
         n = (1 << 30) // 8
@@ -600,105 +840,41 @@ def main():
 
     wl = make_workload(args.workload)
     lay = wl.layout
-    print(f"bench: workload {wl.name} {lay.n(0)} x {lay.nbox} box(es), building state", file=sys.stderr,
+    print(f"bench: workload {args.workload}: {lay.nbox} box(es), {lay.valid_zones()} valid zones", file=sys.stderr,
           flush=True)
-    lev = P.Level(lay)
-    lev.set_step_form(args.fused)
-    U = torch.from_numpy(wl.arena).to("cuda")
-    V = lev.new_state()
-    p = P.params(gamma=wl.gamma, precision=wl.precision)
-    lev.ensure_workspace(p.precision)
-    dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
-    if args.tiling:
-        t_, s_ = (int(v) for v in args.tiling.split(","))
-        lev.set_tiling(t_, s_)
-        tiling = lev.get_tiling()
-    elif not args.no_autotune:
-        Uf = U.clone()
-        lev.fill_boundary(Uf)
-        tiling = lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)[:2]
-        del Uf
-    else:
-        tiling = lev.get_tiling()
-
-    # Each step reads its dt from dtv and leaves the next step's there: the
-    # CFL maximum of the state it writes, computed by its update kernel
-    # (ppm_hydro_step_dt), the same bits as a separate pass over it.
-    def step(a, b):
-        lev.fill_boundary(a)
-        lev.hydro_step(a, b, wl.dx, p, dt_dev=dtv, dt_next=dtv)
-        return b, a
-
-    lev.compute_dt(U, wl.dx, p, out=dtv)
-    for _ in range(args.warmup):
-        U, V = step(U, V)
-    torch.cuda.synchronize()
-    lev.profile_read()
-    lev.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        U, V = step(U, V)
-    e1.record()
-    torch.cuda.synchronize()
-    lev.profile_enable(False)
-    ms = e0.elapsed_time(e1)
-    prof = lev.profile_read()
-    flags = lev.check_status()
+    tiling = tuple(int(v) for v in args.tiling.split(",")) if args.tiling else None
+    h, prof, tiling = headline(wl, args.workload, args.steps, args.warmup, per_box=not args.no_per_box,
+                               tiling=tiling, autotune=not args.no_autotune)
     zones = lay.valid_zones()
-    value = zones * args.steps / (ms / 1e3)
-
-    # dominant stage kernel and its arithmetic roofline
-    units = {k: 0 for k in FLOPS_PER_UNIT}
-    for b in range(lay.nbox):
-        for k, v in stage_units(lay.n(b)).items():
-            units[k] += v
-    stages = {k: prof[k] for k in FLOPS_PER_UNIT}
-    dom = max(stages, key=lambda k: stages[k][0])
-    t_ms, cnt = stages[dom]
-    mean_s = t_ms / cnt / 1e3
-    flops = FLOPS_PER_UNIT[dom] * units[dom]
-    achieved = flops / mean_s / 1e12
-    step_flops = sum(FLOPS_PER_UNIT[k] * units[k] for k in FLOPS_PER_UNIT)
-    # the FP32 mode's stage kernels compute in FP32 (the counts are those of
-    # the same algorithm; the FP32 forms differ by a few operations per solve)
-    peak = FP64_VECTOR_PEAK_TFLOPS if p.precision == 0 else FP32_VECTOR_PEAK_TFLOPS
-    # HBM bytes of a whole step from the same counter record (all its
-    # kernels), against the step's live time: the staged step's traffic rate
-    step_traffic = (recorded_traffic(dom, args.workload, tiling, "step_traffic_bytes")
-                    if p.precision == 0 else None)
+    print(f"bench: {args.workload} graph {h['graph']:.4g} zone-updates/s ({h['ms_per_step']:.3f} ms/step)",
+          file=sys.stderr, flush=True)
+    rf = roofline(args.workload, lay, prof, h["ms_per_step"], wl.precision, tiling)
     out = {
-        "metric": METRIC, "value": value, "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if p.precision == 0 else "f32+f64",
+        "metric": METRIC, "value": h["graph"], "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if wl.precision == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {lay.n(0)[0]}^3 single box, "
-                               f"{'FP64' if p.precision == 0 else 'FP32 reconstruction + FP64 update'}, "
-                               f"gamma {wl.gamma:.4g}, "
-                               "random-mode density x planar Sod jump, periodic, CFL 0.5, plain step "
-                               "(fill + step; each step's CFL dt computed by the previous step's update)",
-                   "valid_zones": zones, "boxes": lay.nbox,
-                   "tiling": {"tile": tiling[0], "strip_rows": tiling[1]}},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": recorded_traffic(dom, args.workload, tiling) if p.precision == 0 else None,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops,
-                     "step_traffic": step_traffic,
-                     "step_traffic_GBps": (step_traffic / (ms / args.steps / 1e3) / 1e9
-                                           if step_traffic else None)},
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}; batched step (one launch per "
+                               "stage over all boxes' tiles), [fill, step] x steps captured in one HIP graph, "
+                               "each step's CFL dt left on the device by the previous step's update",
+                   "valid_zones": zones, "boxes": lay.nbox, "tiling": h["tiling"], "autotune": h["autotune"]},
+        "batched_eager": h["batched_eager"],
+        "per_box": h.get("per_box"), "batched_over_per_box": h.get("batched_over_per_box"),
+        "roofline": rf,
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in prof.items()},
-        "step_flop_rate_tflops": step_flops * args.steps / (ms / 1e3) / 1e12,
         "hbm_copy_GBps": copy_bandwidth(),
-        "status_flags": flags,
+        "status_flags": h["flags"],
     }
     if not args.no_extras:
-        del lev, U, V
-        torch.cuda.empty_cache()
         from paper_1008_2801_amd import inputs as I
-        print("bench: 512-box level (batched / per-box / graph)", file=sys.stderr, flush=True)
+        print("bench: 256^3 single box (FP64)", file=sys.stderr, flush=True)
+        w2 = I.cfg2()
+        r2, p2, t2 = headline(w2, "cfg2", 20, 2, per_box=False)
+        r2["roofline"] = roofline("cfg2", w2.layout, p2, r2["ms_per_step"], 0, t2)
+        r2["workload"] = "cfg2: " + WORKLOADS["cfg2"]
+        out["single_box_256"] = r2
+        del w2
+        print("bench: 512-box tensor tiling (batched / per-box / graph)", file=sys.stderr, flush=True)
         w3 = I.cfg3()
         extra = {"workload": f"cfg3: 512 boxes, edges from {{16,24,32,48,64}} (seed 3), "
                              f"{w3.layout.valid_zones()} valid zones, gamma 1.4, periodic, 20 steps",
@@ -708,6 +884,16 @@ def main():
             extra[tag] = r
             extra[tag]["batched_over_per_box"] = r["batched"] / r["per_box"]
         out["multibox"] = extra
+        print("bench: the same 512^3 level, FP32 reconstruction", file=sys.stderr, flush=True)
+        w5 = I.cfg5(precision=1)
+        r5, p5, t5 = headline(w5, "cfg5-fp32", args.steps, args.warmup, per_box=False)
+        r5["workload"] = "cfg5-fp32: " + WORKLOADS["cfg5-fp32"]
+        out["fp32_reconstruction"] = r5
+        print("bench: adjoint step of the 512^3 level (FP32 reconstruction)", file=sys.stderr, flush=True)
+        a5 = adjoint_costs(w5, 0, 1, precision=1, rollout=False)
+        a5["workload"] = "cfg5: 512 boxes of 64^3, FP32 reconstruction, one forward step vs one adjoint step"
+        out["adjoint_512cubed_fp32"] = a5
+        del w5
         print("bench: adjoint cost on the 128^3 differentiation workload", file=sys.stderr, flush=True)
         w4 = I.cfg4()
         a = adjoint_costs(w4, 20, 5)
@@ -720,27 +906,9 @@ def main():
         print("bench: adjoint cost on a 2x2x2-box instance of the Rayleigh-Taylor set-up", file=sys.stderr,
               flush=True)
         a5 = adjoint_costs(I.cfg5(nb=2, m=64, precision=0), 10, 5)
-        a5["workload"] = ("cfg5 instance: 8 boxes of 64^3 (128^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "
+        a5["workload"] = ("Rayleigh-Taylor instance: 8 boxes of 64^3 (128^3), g = (0,0,-1), walls in z, "
                           "FP64, 10 steps")
         out["adjoint_rayleigh_taylor"] = a5
-        a5 = adjoint_costs(I.cfg5(nb=2, m=64, precision=1), 10, 5, precision=1)
-        a5["workload"] = "the same instance with the FP32-reconstruction step and its FP32 reverse"
-        out["adjoint_rayleigh_taylor_fp32_reconstruction"] = a5
-        print("bench: 512^3 Rayleigh-Taylor level (512 boxes of 64^3)", file=sys.stderr, flush=True)
-        w5 = I.cfg5()
-        rt = {"workload": "cfg5: 512 boxes of 64^3 (512^3), Rayleigh-Taylor, g = (0,0,-1), walls in z, "
-                          "10 steps", "unit": "zone-updates/s"}
-        for prec, tag in ((1, "fp32_reconstruction"), (0, "fp64")):
-            r = level_rates(w5, 10, 1, prec, per_box=False)
-            rt[tag] = r
-        print("bench: adjoint step of the 512^3 Rayleigh-Taylor level (FP32 reconstruction)", file=sys.stderr,
-              flush=True)
-        torch.cuda.empty_cache()
-        a5 = adjoint_costs(w5, 0, 1, precision=1, rollout=False)
-        a5["workload"] = "cfg5: 512 boxes of 64^3, FP32 reconstruction, one forward step vs one adjoint step"
-        rt["adjoint"] = a5
-        out["rayleigh_taylor"] = rt
-        del w5
     if not args.no_extras or args.amr_only:
         print("bench: two-level hierarchy (256^3 coarse, inner 12.5% refined)", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
@@ -761,8 +929,8 @@ def main():
         from paper_1008_2801_amd import inputs as I
         print("bench: passive species on the 256^3 workload", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-        w2 = make_workload(args.workload)
-        sp = {"workload": f"{w2.name} with passive species (mode-sum mass fractions summing to one), "
+        w2 = I.cfg2()
+        sp = {"workload": "cfg2 with passive species (mode-sum mass fractions summing to one), "
                           "fill + dt + step, 10 steps"}
         for ns in (1, 4):
             sp[f"fp64_ns{ns}"] = species_costs(w2, ns, 10, 2, precision=0)
@@ -770,9 +938,12 @@ def main():
         out["species"] = sp
         del w2
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU reference on a window", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_window, wl.gamma)
-    print(json.dumps(out))
+        print("bench: timing the CPU reference on boxes of the level", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, single_s=args.cpu_seconds)
+    kids = child_processes()
+    if kids:
+        print(f"bench: child processes still alive: {kids}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -70,12 +70,15 @@ def units(w):
             "riemann1": int(r1), "riemann2": int(r2), "riemann3": int(r3), "update": int(np.prod(w))}
 
 
-def per_unit(U, dx, p, windows):
+def per_unit(states, dx, p, windows, walls=None):
+    """Flops per unit of each stage over windows [(box, lo, hi)] of the
+    boxes' filled states."""
     tot = {k: 0 for k in KERNELS}
     cnt = {k: 0 for k in KERNELS}
     kinds = {k: np.zeros(len(O.OPKINDS), dtype=np.int64) for k in KERNELS}
-    for lo, hi in windows:
-        _, counts, _ = O.step_count(U, 1e-3, dx, p, window=(lo, hi))
+    for b, lo, hi in windows:
+        _, counts, _ = O.step_count(states[b], 1e-3, dx, p, window=(lo, hi),
+                                    walls=walls[b] if walls else None)
         u = units(np.array(hi) - np.array(lo) + 1)
         for k, stages in KERNELS.items():
             c = sum(counts[O.STAGES.index(s)] for s in stages)
@@ -87,7 +90,9 @@ def per_unit(U, dx, p, windows):
 
 
 def measure(name="cfg2"):
-    """(flops per unit, ops per unit by kind, windows) of a workload's step."""
+    """(flops per unit, ops per unit by kind, windows) of a workload's step:
+    six 12^3 windows of the initial state (in six different boxes of a
+    multi-box level)."""
     if name == "cfg2":
         wl = I.cfg2(64)  # same recipe (seed, modes, jump, velocity draws) on a 64^3 box
     elif name == "cfg3":
@@ -95,20 +100,24 @@ def measure(name="cfg2"):
     elif name == "cfg4":
         wl = I.cfg4(64)
     else:
-        wl = I.cfg5(2, 32)
+        # the 512^3 Rayleigh-Taylor recipe on 4^3 boxes of 32^3 (interface
+        # width 2 zones as in the full level; the sampled boxes include the
+        # walls and the interface)
+        wl = I.cfg5(4, 32, precision=0)
     lay = wl.layout
     st = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
     O.fill(lay.boxes(), lay.domain(), lay.bc, st)
-    U = st[0]
-    n = lay.n(0)
+    walls = [O.box_walls(lay.boxes(), lay.domain(), lay.bc, b) for b in range(lay.nbox)]
     rng = np.random.default_rng(0)
     w = 12
+    boxes = rng.choice(lay.nbox, min(6, lay.nbox), replace=False) if lay.nbox > 1 else [0] * 6
     windows = []
-    for _ in range(6):
-        lo = [int(rng.integers(0, n[d] - w)) for d in range(3)]
-        windows.append((tuple(lo), tuple(v + w - 1 for v in lo)))
+    for b in boxes:
+        n = lay.n(int(b))
+        lo = [int(rng.integers(0, n[d] - w + 1)) for d in range(3)]
+        windows.append((int(b), tuple(lo), tuple(v + w - 1 for v in lo)))
     p = O.params(gamma=wl.gamma, grav=wl.grav)
-    flops, kinds = per_unit(U, wl.dx, p, windows)
+    flops, kinds = per_unit(st, wl.dx, p, windows, walls)
     return flops, kinds, windows
 
 

@@ -193,13 +193,16 @@ def test_traffic_record_follows_the_code_not_the_comments(tmp_path, monkeypatch)
 
 def test_roofline_flop_figures_are_the_op_counting_oracles():
     """bench.py prices the stage kernels with per-unit flop counts; they
-    must be the op-counting oracle's on the 256^3 workload's recipe (to the
-    two decimals stored), and bench's units per stage must be the oracle's
-    definitions, so that the reported roofline rests on counted work."""
+    must be the op-counting oracle's on the 256^3 and 512^3 workloads'
+    recipes (to the two decimals stored), and bench's units per stage must
+    be the oracle's definitions, so that the reported roofline rests on
+    counted work."""
     import bench
     from oracle import opcount
-    flops, _, _ = opcount.measure("cfg2")
-    for k, v in bench.FLOPS_PER_UNIT.items():
-        assert abs(v - flops[k]) <= 0.006, (k, v, flops[k])
+    for wl in ("cfg2", "cfg5"):
+        flops, _, _ = opcount.measure(wl)
+        assert set(bench.FLOPS_PER_UNIT[wl]) == set(bench.STAGES)
+        for k, v in bench.FLOPS_PER_UNIT[wl].items():
+            assert abs(v - flops[k]) <= 0.006, (wl, k, v, flops[k])
     for n in ((256, 256, 256), (16, 24, 8), (1, 3, 5)):
         assert bench.stage_units(n) == opcount.units(n), n
