@@ -62,7 +62,12 @@ enum { PPM_BC_PERIODIC = 0, PPM_BC_OUTFLOW = 1, PPM_BC_REFLECT = 2,
 
 /* status flags accumulated on the device */
 enum { PPM_FLAG_NONPHYS = 1, /* rho <= 0, p <= 0 or a non-finite value in an input state */
-       PPM_FLAG_FLOOR = 2 }; /* a density/pressure floor bound inside the step */
+       PPM_FLAG_FLOOR = 2,   /* a density/pressure floor bound inside the step */
+       PPM_FLAG_RANGE = 4 }; /* an input zone's density, pressure or sound speed lies outside
+                                [2^-120, 2^120], or a velocity component beyond 2^120 in magnitude:
+                                the FP64 divisions and square roots of the step drop the compiler's
+                                range scaling and are correctly rounded only for the magnitudes
+                                states within those bounds produce (the step is still computed) */
 
 /* launch forms of the step */
 enum { PPM_LAUNCH_BATCHED = 0, /* each stage: one launch over the tile list of all boxes */
@@ -83,7 +88,7 @@ typedef struct {
 typedef struct {
   double gamma;          /* > 1 */
   double cfl;            /* Courant number of the dt rule, in (0, 1) */
-  double small_dens, small_pres; /* floors (> 0) */
+  double small_dens, small_pres; /* floors, in [2^-120, 2^120] */
   double grav[3];        /* constant gravity, Heun source; zeros: none */
   int32_t limiter;       /* 1: MC slopes + CW84 limiter; 0: unlimited (smooth) */
   int32_t flattening;    /* 1: CW84 shock flattening (needs limiter = 1) */
@@ -199,25 +204,32 @@ int ppm_hydro_step_dt(ppm_ctx* ctx, const double* U, double* Unew, double* const
                       double* dt_next_dev, void* stream);
 
 /* Adjoint of one step, dt and every branch decision of the forward step
- * frozen: given the step's input U (ghosts filled, as for ppm_hydro_step)
- * and the adjoint Unew_bar of the new state's valid zones, writes to U_bar
- * the adjoint of U's valid zones -- the transpose of the step's Jacobian
- * applied to Unew_bar, the ghost-fill transpose included (ghost adjoints are
- * added into the zones they were copied from) -- and zeros U_bar's ghost
- * zones.  The reverse stages run in the precision of the forward step they
+ * frozen: given the step's input U (ghosts filled, as for ppm_hydro_step),
+ * the adjoint Unew_bar of the new state's valid zones and optionally the
+ * adjoints of the step's flux outputs, writes to U_bar the adjoint of U's
+ * valid zones -- the transpose of the step's Jacobian (new state and
+ * fluxes) applied to (Unew_bar, flux_bar), the ghost-fill transpose
+ * included (ghost adjoints are added into the zones they were copied from)
+ * -- and zeros U_bar's ghost zones.  flux_bar: null, or three flux-arena
+ * pointers (ppm_flux_offsets layout, any may be null) holding the adjoints
+ * of the F^{n+1/2} that ppm_hydro_step writes (the refluxing of a coarser
+ * level consumes those fluxes, paper Sec. 2-3); a null entry adds
+ * nothing.  The reverse stages run in the precision of the forward step they
  * differentiate (params->precision: 0 all FP64; 1 the reconstruction,
  * tracing and Riemann reverses in FP32, the update's reverse, the
  * conversion's output and U_bar in FP64).  The forward intermediates are
  * recomputed into the step workspace (ppm_set_workspace, sized for the same
  * precision); the reverse stages use a second caller-owned workspace of
  * ppm_adjoint_workspace_bytes(ctx, precision) bytes, 256-byte aligned.
- * U_bar must not overlap U or Unew_bar.  Deterministic: no atomics.
+ * U_bar must not overlap U, Unew_bar or a flux adjoint.  Deterministic:
+ * no atomics.
  * Returns PPM_EINVAL (message in ppm_last_error) for a null pointer,
  * overlapping buffers, invalid parameters or a missing/small workspace. */
 size_t ppm_adjoint_workspace_bytes(const ppm_ctx* ctx, int32_t precision);
 int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes);
-int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
-                           const double* dt_dev, const double dx[3], const ppm_params* params, void* stream);
+int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, const double* const* flux_bar,
+                           double* U_bar, double dt, const double* dt_dev, const double dx[3],
+                           const ppm_params* params, void* stream);
 
 /* The same adjoint without the recompute: the step workspace must still
  * hold the intermediates of the forward step from this U with the same dt
@@ -226,9 +238,9 @@ int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar
  * ppm_hydro_step_adjoint.  For callers that keep one workspace per step of
  * a checkpoint segment (memory for compute); the library cannot check the
  * precondition. */
-int ppm_hydro_step_adjoint_saved(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar,
-                                 double dt, const double* dt_dev, const double dx[3], const ppm_params* params,
-                                 void* stream);
+int ppm_hydro_step_adjoint_saved(ppm_ctx* ctx, const double* U, const double* Unew_bar,
+                                 const double* const* flux_bar, double* U_bar, double dt, const double* dt_dev,
+                                 const double dx[3], const ppm_params* params, void* stream);
 
 /* Passive species: mass fractions X_s carried with the flow (partial
  * densities rho X_s obey the continuity equation with the mass flux times
@@ -331,7 +343,12 @@ int ppm_amr_step(ppm_amr* a, const double* Uc, double* Uc_new, double* Uf, doubl
  * the first step's from a dt pass over A, every later step's from the
  * update of the step before it (ppm_hydro_step_dt; the same bits).  After
  * an even nsteps the result is in A, after an odd nsteps in B.  The graph
- * keeps the pointers; launches replay it on the stream. */
+ * keeps the pointers it was captured with (A, B, the workspace, the tile
+ * lists, inflow states); launches replay it on the stream.  A launch
+ * returns PPM_EINVAL, and replays nothing, once the context was destroyed
+ * or its workspace (another pointer or size), tiling, step form or an
+ * inflow state changed since the capture: capture again.  A and B must
+ * stay allocated while the graph is launched. */
 int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3],
                      const ppm_params* params, int32_t nsteps, void* stream, ppm_graph** out);
 int ppm_graph_launch(ppm_graph* g, void* stream);

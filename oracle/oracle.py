@@ -87,6 +87,10 @@ def lib():
         L.oracle_step_jvp.restype = ctypes.c_int
         L.oracle_step_jvp.argtypes = [_dp, _dp, _ip, _ip, _ip, ctypes.c_double, _dp,
                                       ctypes.POINTER(OParams), _ip, _dp, _dp]
+        L.oracle_step_jvp_flux.restype = ctypes.c_int
+        L.oracle_step_jvp_flux.argtypes = [_dp, _dp, _ip, _ip, _ip, ctypes.c_double, _dp,
+                                           ctypes.POINTER(OParams), _ip, _dp, _dp, ctypes.POINTER(_dp),
+                                           ctypes.POINTER(_dp)]
         L.oracle_max_wavespeed.restype = ctypes.c_double
         L.oracle_max_wavespeed.argtypes = [_dp, _ip, _dp, ctypes.POINTER(OParams), _ip]
         L.oracle_riemann.restype = ctypes.c_int
@@ -216,6 +220,29 @@ def step_jvp(U, dU, dt, dx, p, window=None, walls=None):
     if fl < 0:
         raise ValueError("oracle_step_jvp: invalid arguments")
     return Unew, dUnew, fl
+
+
+def step_jvp_flux(U, dU, dt, dx, p, walls=None):
+    """(step(U), J dU, F, J_F dU): the new state and the face-centred flux
+    outputs of one box with their tangents (FP64 mode; ghosts of U and dU
+    filled).  F[d], dF[d]: arrays (5, nz', ny', nx') with n_d + 1 faces
+    along d."""
+    n = _box_n(U)
+    assert dU.shape == U.shape and dU.dtype == np.float64 and dU.flags.c_contiguous
+    Unew = U.copy()
+    dUnew = np.zeros_like(U)
+    F, dF = [], []
+    for d in range(3):
+        e = list(n)
+        e[d] += 1
+        F.append(np.zeros((5, e[2], e[1], e[0])))
+        dF.append(np.zeros((5, e[2], e[1], e[0])))
+    fl = lib().oracle_step_jvp_flux(_d(U), _d(dU), _i3(n), _i3((0, 0, 0)), _i3(tuple(x - 1 for x in n)),
+                                    float(dt), _d3(dx), ctypes.byref(p), _walls(walls), _d(Unew), _d(dUnew),
+                                    (_dp * 3)(*[_d(f) for f in F]), (_dp * 3)(*[_d(f) for f in dF]))
+    if fl < 0:
+        raise ValueError("oracle_step_jvp_flux: invalid arguments")
+    return Unew, dUnew, F, dF, fl
 
 
 def max_wavespeed(U, dx, p):

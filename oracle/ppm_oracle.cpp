@@ -1059,6 +1059,35 @@ int oracle_step_jvp(const double* U, const double* dU, const int n[3], const int
   return fl;
 }
 
+// The same with the flux outputs and their tangents: F[d], dF[d] (any may be
+// null) receive the face-centred fluxes F^{n+1/2} of axis d (extents n + e_d,
+// order [c][k][j][i]) and their tangents along dU.
+int oracle_step_jvp_flux(const double* U, const double* dU, const int n[3], const int wlo[3], const int whi[3],
+                         double dt, const double h[3], const OParams* P, const int* walls, double* Unew,
+                         double* dUnew, double** F, double** dF) {
+  if (!U || !dU || !Unew || !dUnew || !P || !F || !dF || !window_ok(n, wlo, whi) || P->precision != 0) return -1;
+  const int N[3] = {n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG};
+  const size_t tot = (size_t)5 * N[0] * N[1] * N[2];
+  std::vector<Dual> ud(tot), un(tot);
+  for (size_t i = 0; i < tot; ++i) { ud[i] = Dual(U[i], dU[i]); un[i] = Dual(Unew[i], dUnew[i]); }
+  std::vector<Dual> fd[3];
+  Dual* fp[3] = {nullptr, nullptr, nullptr};
+  size_t fn[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    if (!F[d] || !dF[d]) continue;
+    size_t e = 5;
+    for (int a = 0; a < 3; ++a) e *= (size_t)(n[a] + (a == d ? 1 : 0));
+    fd[d].assign(e, Dual(0.0));
+    fp[d] = fd[d].data();
+    fn[d] = e;
+  }
+  const int fl = run_step<Dual, Dual>(ud.data(), n, wlo, whi, dt, h, P, walls, un.data(), fp, false);
+  for (size_t i = 0; i < tot; ++i) { Unew[i] = un[i].v; dUnew[i] = un[i].d; }
+  for (int d = 0; d < 3; ++d)
+    for (size_t i = 0; i < fn[d]; ++i) { F[d][i] = fd[d][i].v; dF[d][i] = fd[d][i].d; }
+  return fl;
+}
+
 // O11: largest signal speed over valid zones and axes, max_d (|u_d| + c)/h_d,
 // from the FP64 primitive state; dt = cfl / s.  Sets *flags like the step.
 double oracle_max_wavespeed(const double* U, const int n[3], const double h[3], const OParams* P,

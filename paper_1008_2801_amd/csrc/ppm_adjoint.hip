@@ -124,7 +124,7 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
                                             const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                             long long LE, S* __restrict__ aw, const Gas<S>& G,
                                             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
-                                            int grav, double g0, double g1, double g2) {
+                                            const FluxBar& fbar, int grav, double g0, double g1, double g2) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
@@ -161,8 +161,19 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   pre_source_adjoint(Ubn, B, z.x[0] - (d == 0), z.x[1] - (d == 1), z.x[2] - (d == 2), grav, sc, g0, g1, g2, ufL);
   S Fb[5];
   const double dtdx = sc->dtdx[d];
+  // plus the adjoint of the face's flux output, when given (face-centred
+  // arena of axis d: extents n + e_d, order [c][k][j][i])
+  double fo[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (fbar.p[d]) {
+    int fe[3] = {B.n[0], B.n[1], B.n[2]};
+    fe[d] += 1;
+    const long long FN = (long long)fe[0] * fe[1] * fe[2];
+    const double* q = fbar.p[d] + B.foff[d] + ((long long)z.x[2] * fe[1] + z.x[1]) * fe[0] + z.x[0];
 #pragma unroll
-  for (int m = 0; m < 5; ++m) Fb[m] = (S)(dtdx * (ufR[m] - ufL[m]));
+    for (int m = 0; m < 5; ++m) fo[m] = q[m * FN];
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Fb[m] = (S)(dtdx * (ufR[m] - ufL[m]) + fo[m]);
   S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
   bool rfL, pfL, rfR, pfR;
   r3_state<d>(w, LE, -sd, 0, s1, s2, c1, c2, G, qeL, ueL);
@@ -195,11 +206,11 @@ __device__ __forceinline__ void adj_r3_axes(const Tile* __restrict__ tiles, int 
                                             const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                             long long LE, S* __restrict__ aw, const Gas<S> G,
                                             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
-                                            int grav, double g0, double g1, double g2) {
+                                            const FluxBar& fbar, int grav, double g0, double g1, double g2) {
   switch (blockIdx.y) {
-    case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
-    case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
-    default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2); break;
+    case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2); break;
+    case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2); break;
+    default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2); break;
   }
 }
 
@@ -208,16 +219,16 @@ __device__ __forceinline__ void adj_r3_axes(const Tile* __restrict__ tiles, int 
 __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3)))
 k_adj_r3_f64(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
              const double* __restrict__ work, long long LE, double* __restrict__ aw, Gas<double> G,
-             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, int grav, double g0, double g1,
-             double g2) {
-  adj_r3_axes<double>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2);
+             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, FluxBar fbar, int grav,
+             double g0, double g1, double g2) {
+  adj_r3_axes<double>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2);
 }
 __global__ void __launch_bounds__(MAX_TILE)
 k_adj_r3_f32(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
              const float* __restrict__ work, long long LE, float* __restrict__ aw, Gas<float> G,
-             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, int grav, double g0, double g1,
-             double g2) {
-  adj_r3_axes<float>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, grav, g0, g1, g2);
+             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, FluxBar fbar, int grav,
+             double g0, double g1, double g2) {
+  adj_r3_axes<float>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2);
 }
 
 // Stage-2 pair (d, t) of the face at the lane's slot: F2^{d|t} adjoint from
@@ -697,8 +708,8 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ 
 }
 
 template <class S>
-hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, double* Ub,
-                        const void* work, void* awork, const Gas<S>& G, int grav, const double g[3],
+hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, FluxBar fb,
+                        double* Ub, const void* work, void* awork, const Gas<S>& G, int grav, const double g[3],
                         hipStream_t s) {
   const S* prim = (const S*)work;
   const S* ework = prim + P_PLANES * L.LS;
@@ -710,10 +721,10 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, cons
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
   if constexpr (sizeof(S) == sizeof(double))
     hipLaunchKernelGGL(k_adj_r3_f64, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
-                       Ubn, grav, g[0], g[1], g[2]);
+                       Ubn, fb, grav, g[0], g[1], g[2]);
   else
     hipLaunchKernelGGL(k_adj_r3_f32, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
-                       Ubn, grav, g[0], g[1], g[2]);
+                       Ubn, fb, grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<0, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
@@ -739,14 +750,14 @@ size_t adjoint_workspace_bytes(long long LS, long long LE, int precision) {
 }
 
 hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, const double* U, const double* Ubn,
-                          double* Ub, const void* work, void* awork, double gamma, double small_dens,
+                          FluxBar fb, double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s) {
   if (precision == 1)
-    return adjoint_impl<float>(L, nS, nE, U, Ubn, Ub, work, awork,
+    return adjoint_impl<float>(L, nS, nE, U, Ubn, fb, Ub, work, awork,
                                make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                                grav, g, s);
-  return adjoint_impl<double>(L, nS, nE, U, Ubn, Ub, work, awork,
+  return adjoint_impl<double>(L, nS, nE, U, Ubn, fb, Ub, work, awork,
                               make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                               grav, g, s);
 }

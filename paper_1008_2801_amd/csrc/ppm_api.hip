@@ -342,7 +342,8 @@ void add_tiles(std::vector<Tile>& out, int b, int e0, int e1, int e2, int tile, 
 }  // namespace
 
 struct ppm_graph {
-  ppm_ctx* ctx = nullptr;
+  ppm_ctx* ctx = nullptr;          // null once the context is destroyed
+  unsigned long long gen = 0;      // the context's generation at capture
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   double* dtv = nullptr;  // device [dt, max signal speed] of the step being replayed
@@ -398,7 +399,9 @@ template <class T> hipError_t upload(T** dst, const std::vector<T>& v) {
 std::string validate_params(const ppm_params* p) {
   if (!p) return "params: null";
   if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return "params: gamma must be > 1";
-  if (!(p->small_dens > 0.0) || !(p->small_pres > 0.0)) return "params: floors must be > 0";
+  if (!(p->small_dens >= 0x1p-120 && p->small_dens <= 0x1p120) ||
+      !(p->small_pres >= 0x1p-120 && p->small_pres <= 0x1p120))
+    return "params: floors must lie in [2^-120, 2^120]";
   if (p->riemann_iters < 0 || p->riemann_iters > 16) return "params: riemann_iters must be in [0, 16]";
   if (p->precision != 0 && p->precision != 1) return "params: precision must be 0 or 1";
   if ((p->limiter != 0 && p->limiter != 1) || (p->flattening != 0 && p->flattening != 1))
@@ -557,6 +560,7 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
 
 int ppm_ctx_destroy(ppm_ctx* ctx) {
   if (!ctx) return PPM_OK;
+  for (ppm_graph* g : ctx->graphs) g->ctx = nullptr;  // their launches are refused from now on
   for (auto& r : ctx->recs) ctx->pool.push_back(r.ev);
   for (auto& ev : ctx->pool)
     for (auto& e : ev) (void)hipEventDestroy(e);
@@ -597,6 +601,7 @@ size_t ppm_workspace_bytes(const ppm_ctx* ctx, int32_t precision) {
 int ppm_set_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
   if (!ctx) return PPM_EINVAL;
   if (((uintptr_t)dev_ptr) % 256 != 0) return ctx->fail(PPM_EINVAL, "workspace must be 256-byte aligned");
+  if (dev_ptr != ctx->work || (dev_ptr ? bytes : 0) != ctx->work_bytes) ++ctx->gen;
   ctx->work = dev_ptr;
   ctx->work_bytes = dev_ptr ? bytes : 0;
   return PPM_OK;
@@ -606,6 +611,7 @@ int ppm_set_inflow(ppm_ctx* ctx, int32_t face, const double* state) {
   if (!ctx) return PPM_EINVAL;
   if (face < 0 || face > 5 || ctx->layout.bc[face] != PPM_BC_INFLOW)
     return ctx->fail(PPM_EINVAL, "set_inflow: the face is not an inflow face of the layout");
+  if (ctx->inflow[face] != state) ++ctx->gen;
   ctx->inflow[face] = state;
   return PPM_OK;
 }
@@ -760,6 +766,7 @@ int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused) {
   if (!ctx) return PPM_EINVAL;
   if (fused != 0 && fused != 1) return ctx->fail(PPM_EINVAL, "set_step_form: fused must be 0 or 1");
+  if (fused != ctx->fused) ++ctx->gen;
   ctx->fused = fused;
   return PPM_OK;
 }
@@ -783,9 +790,9 @@ int ppm_set_adjoint_workspace(ppm_ctx* ctx, void* dev_ptr, size_t bytes) {
   return PPM_OK;
 }
 
-static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
-                        const double* dt_dev, const double dx[3], const ppm_params* params, void* stream,
-                        bool recompute) {
+static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, const double* const* flux_bar,
+                        double* U_bar, double dt, const double* dt_dev, const double dx[3],
+                        const ppm_params* params, void* stream, bool recompute) {
   if (!ctx) return PPM_EINVAL;
   std::string m = validate_params(params);
   if (m.empty()) m = validate_dx(dx);
@@ -797,6 +804,11 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, d
     const char* b = (const char*)U;
     const char* c = (const char*)Unew_bar;
     if ((a < b + alen && b < a + alen) || (a < c + alen && c < a + alen)) m = "adjoint: U_bar overlaps an input";
+    for (int d = 0; d < 3 && m.empty() && flux_bar; ++d) {
+      const char* f = (const char*)flux_bar[d];
+      const size_t flen = (size_t)ctx->foff[d].back() * sizeof(double);
+      if (f && a < f + flen && f < a + alen) m = "adjoint: U_bar overlaps a flux adjoint";
+    }
   }
   if (m.empty() && (!ctx->work || ctx->work_bytes < ppm_workspace_bytes(ctx, params->precision)))
     m = "adjoint: workspace missing or too small (ppm_set_workspace)";
@@ -819,7 +831,10 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, d
                   "adjoint recompute");
     if (rc) return rc;
   }
-  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, U, Unew_bar, U_bar, ctx->work, ctx->awork,
+  FluxBar fb{{nullptr, nullptr, nullptr}};
+  if (flux_bar)
+    for (int d = 0; d < 3; ++d) fb.p[d] = flux_bar[d];
+  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, U, Unew_bar, fb, U_bar, ctx->work, ctx->awork,
                                  params->gamma, params->small_dens, params->small_pres, params->limiter,
                                  params->flattening, params->riemann_iters, grav, params->grav, s),
                   "adjoint");
@@ -900,15 +915,16 @@ int ppm_hydro_step_species(ppm_ctx* ctx, const double* U, double* Unew, const do
                   "species step");
 }
 
-int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar, double dt,
-                           const double* dt_dev, const double dx[3], const ppm_params* params, void* stream) {
-  return adjoint_step(ctx, U, Unew_bar, U_bar, dt, dt_dev, dx, params, stream, true);
+int ppm_hydro_step_adjoint(ppm_ctx* ctx, const double* U, const double* Unew_bar, const double* const* flux_bar,
+                           double* U_bar, double dt, const double* dt_dev, const double dx[3],
+                           const ppm_params* params, void* stream) {
+  return adjoint_step(ctx, U, Unew_bar, flux_bar, U_bar, dt, dt_dev, dx, params, stream, true);
 }
 
-int ppm_hydro_step_adjoint_saved(ppm_ctx* ctx, const double* U, const double* Unew_bar, double* U_bar,
-                                 double dt, const double* dt_dev, const double dx[3], const ppm_params* params,
-                                 void* stream) {
-  return adjoint_step(ctx, U, Unew_bar, U_bar, dt, dt_dev, dx, params, stream, false);
+int ppm_hydro_step_adjoint_saved(ppm_ctx* ctx, const double* U, const double* Unew_bar,
+                                 const double* const* flux_bar, double* U_bar, double dt, const double* dt_dev,
+                                 const double dx[3], const ppm_params* params, void* stream) {
+  return adjoint_step(ctx, U, Unew_bar, flux_bar, U_bar, dt, dt_dev, dx, params, stream, false);
 }
 
 int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], const ppm_params* params,
@@ -954,17 +970,23 @@ int ppm_graph_create(ppm_ctx* ctx, double* Ua, double* Ub, const double dx[3], c
   }
   g->graph = graph;
   g->dtv = dtv;
+  g->gen = ctx->gen;
+  ctx->graphs.insert(g.get());
   *out = g.release();
   return PPM_OK;
 }
 
 int ppm_graph_launch(ppm_graph* g, void* stream) {
-  if (!g || !g->exec) return PPM_EINVAL;
+  if (!g || !g->exec || !g->ctx) return PPM_EINVAL;  // no graph, or its context was destroyed
+  if (g->gen != g->ctx->gen)
+    return g->ctx->fail(PPM_EINVAL, "graph launch: the context's workspace, tiling, step form or inflow "
+                                    "state changed since the graph was captured; capture it again");
   return g->ctx->hip(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
 }
 
 int ppm_graph_destroy(ppm_graph* g) {
   if (!g) return PPM_OK;
+  if (g->ctx) g->ctx->graphs.erase(g);
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
   (void)hipFree(g->dtv);
@@ -978,6 +1000,7 @@ int ppm_set_tiling(ppm_ctx* ctx, int32_t tile, int32_t strip_rows) {
     return ctx->fail(PPM_EINVAL, "tiling: tile must be 64, 128, 256 or 512 and strip_rows >= 0");
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return ctx->hip(e, "tiling");
+  ++ctx->gen;  // the tile lists are re-uploaded
   ctx->tile = tile;
   ctx->strip_rows = strip_rows;
   build_tiles(*ctx);

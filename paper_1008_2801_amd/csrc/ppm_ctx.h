@@ -5,6 +5,7 @@
 
 #include <array>
 #include <memory>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -39,6 +40,11 @@ struct ppm_ctx {
   std::vector<int> tB_begin;            // nbox + 1
   int fused = 0;                        // 1: final fluxes + update in one brick kernel
   int device = -1;                      // HIP device current at ppm_ctx_create
+  // Generation of the device state a captured graph bakes in (workspace,
+  // tile lists, step form, inflow states): bumped whenever one changes; a
+  // graph captured under another generation is refused at launch.
+  unsigned long long gen = 1;
+  std::set<ppm_graph*> graphs;          // live graphs captured on this context
   int tile = TILE, strip_rows = STRIP_ROWS;
   long long LS = 0, LE = 0;
   // device copies

@@ -154,8 +154,12 @@ hipError_t launch_speed_finish(double* dt_dev, double cfl, hipStream_t s);
 // Adjoint of one FP64 step (ppm_adjoint.hip); the forward workspace must hold
 // the recomputed prim..riemann2 intermediates of the same step.
 size_t adjoint_workspace_bytes(long long LS, long long LE, int precision);
+// Adjoints of the three flux outputs (flux arenas, FP64; null: none).
+struct FluxBar {
+  const double* p[3];
+};
 hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, const double* U, const double* Ubn,
-                          double* Ub, const void* work, void* awork, double gamma, double small_dens,
+                          FluxBar fb, double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s);
 // Passive species (ppm_species.hip), run after a full step whose

@@ -76,13 +76,19 @@ __global__ void __launch_bounds__(MAX_TILE) k_prim(const Tile* __restrict__ tile
   if (!fin || !(r > S(0)) || !(p > S(0))) fl |= PPM_FLAG_NONPHYS;
   if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
   p = smax(p, G.small_pres);
+  const S c = ssqrt(G.gamma * p / r);
+  // magnitudes for which the shortened FP64 divisions and roots of the
+  // later stages are the IEEE results (zero velocities included)
+  if (!(in_range(r) && in_range(p) && in_range(c) && speed_in_range(vx) && speed_in_range(vy) &&
+        speed_in_range(vz)))
+    fl |= PPM_FLAG_RANGE;
   S* q = prim + B.poff + idx;
   q[0] = r;
   q[LS] = vx;
   q[2 * LS] = vy;
   q[3 * LS] = vz;
   q[4 * LS] = p;
-  q[5 * LS] = ssqrt(G.gamma * p / r);
+  q[5 * LS] = c;
   raise_flags(flags, fl);
 }
 

@@ -125,6 +125,14 @@ PPM_HD double sqrt_phys(double x) {
 }
 PPM_HD float sqrt_phys(float x) { return __builtin_sqrtf(x); }
 template <class S> PPM_HD S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
+// 2^-120 <= x <= 2^120 for a state's density, pressure and sound speed,
+// |u| <= 2^120 for its velocity components (no quotient divides by a
+// velocity): the magnitudes for which every quotient and root the step
+// forms from them keeps the operand exponents where qdiv, sqrt_wave and
+// sqrt_phys are the IEEE results (products of up to five such quantities
+// and their differences stay within 2^-800 .. 2^600).
+template <class S> PPM_HD bool in_range(S x) { return x >= S(0x1p-120) && x <= S(0x1p120); }
+template <class S> PPM_HD bool speed_in_range(S u) { return sabs(u) <= S(0x1p120); }
 // a b > 0: the MC slope and the CW84 limiter test the sign of a product of
 // two differences of one field.
 template <class S> PPM_HD bool same_sign(S a, S b) { return a * b > S(0); }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libppm.so")
 
 PPM_OK, PPM_EINVAL, PPM_EHIP, PPM_ENONPHYS = 0, 1, 2, 3
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT = 0, 1, 2
-FLAG_NONPHYS, FLAG_FLOOR = 1, 2
+FLAG_NONPHYS, FLAG_FLOOR, FLAG_RANGE = 1, 2, 4
 BATCHED, PER_BOX = 0, 1
 
 # Every exported symbol of include/ppm.h.
@@ -116,11 +116,11 @@ def lib():
         L.ppm_adjoint_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
         L.ppm_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.ppm_set_adjoint_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
-        L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
+        L.ppm_hydro_step_adjoint.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), _vp, ctypes.c_double, _vp, _dp3,
                                              ctypes.POINTER(Params), _vp]
         L.ppm_profile_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
-        L.ppm_hydro_step_adjoint_saved.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _dp3,
-                                                   ctypes.POINTER(Params), _vp]
+        L.ppm_hydro_step_adjoint_saved.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_vp), _vp, ctypes.c_double, _vp,
+                                                   _dp3, ctypes.POINTER(Params), _vp]
         L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
         L.ppm_set_step_form.argtypes = [_vp, ctypes.c_int32]
         L.ppm_get_step_form.argtypes = [_vp, _i32p]
@@ -415,11 +415,14 @@ class Level:
         self._check(lib().ppm_set_adjoint_workspace(self.ctx, ctypes.c_void_p(aligned), need),
                     "ppm_set_adjoint_workspace")
 
-    def hydro_step_adjoint(self, U, Unew_bar, U_bar, dx, p, dt=0.0, dt_dev=None, stream=None, saved=False):
-        """U_bar = J^T Unew_bar for the step from U (ghosts filled), dt frozen;
-        the reverse runs in the step's precision (p.precision).  saved=True:
-        the selected workspace still holds this step's forward
-        intermediates (no recompute)."""
+    def hydro_step_adjoint(self, U, Unew_bar, U_bar, dx, p, dt=0.0, dt_dev=None, stream=None, saved=False,
+                           flux_bar=None):
+        """U_bar = J^T (Unew_bar, flux_bar) for the step from U (ghosts
+        filled), dt frozen; flux_bar: None or three flux-arena tensors (any
+        None) holding the adjoints of the step's flux outputs.  The reverse
+        runs in the step's precision (p.precision).  saved=True: the
+        selected workspace still holds this step's forward intermediates
+        (no recompute)."""
         prec = int(p.precision)
         if self._slot is None and (self._work is None or self._work_prec != prec or
                                    self._work.numel() < self.workspace_bytes(prec) + 256):
@@ -428,7 +431,10 @@ class Level:
             self.ensure_adjoint_workspace(prec)
             self._awork_prec = prec
         fn = lib().ppm_hydro_step_adjoint_saved if saved else lib().ppm_hydro_step_adjoint
-        self._check(fn(self.ctx, _ptr(U), _ptr(Unew_bar), _ptr(U_bar), float(dt), _ptr(dt_dev), _dp3(*dx),
+        fb = None
+        if flux_bar is not None:
+            fb = (_vp * 3)(*[f.data_ptr() if f is not None else None for f in flux_bar])
+        self._check(fn(self.ctx, _ptr(U), _ptr(Unew_bar), fb, _ptr(U_bar), float(dt), _ptr(dt_dev), _dp3(*dx),
                        ctypes.byref(p), _stream(stream)), "ppm_hydro_step_adjoint")
 
     def select_workspace(self, slot, precision=0):
@@ -597,7 +603,9 @@ class Graph:
         import torch
         level.ensure_workspace(p.precision)
         self.level = level
-        self._keep = (Ua, Ub)
+        # the buffers the graph replays from: the states and the workspace
+        # it was captured with stay alive while the graph does
+        self._keep = (Ua, Ub, level._work)
         g = ctypes.c_void_p()
         # capture needs a stream other than the legacy null stream
         cap = torch.cuda.Stream() if stream is None else stream

@@ -383,3 +383,46 @@ def test_differentiation_workload_full_size_against_central_differences():
         worst = max(worst, abs(fd - ad) / abs(ad))
         assert abs(fd - ad) <= 1e-6 * abs(ad), (i, fd, ad)
     print(f"128^3, 20 steps, 64 directions: worst relative gradient error {worst:.2e} (loss {loss:.6e})")
+
+
+@pytest.mark.parametrize("with_state", [False, True])
+def test_adjoint_through_the_flux_outputs(with_state):
+    """ppm_hydro_step_adjoint with flux adjoints: on a multi-box level with
+    reflecting walls in z and gravity, <J^T (w_U, w_F), v> equals
+    <w_U, J_U v> + sum_d <w_F[d], J_F[d] v> with the oracle's dual-number
+    tangents of the new state and of the three flux outputs (w_U = 0 tests
+    the flux part alone)."""
+    wl = _uneven(4, bc=(0, 0, 0, 0, 2, 2))
+    wl.grav = (0.0, 0.0, -1.0)
+    lay = wl.layout
+    dt = _dt(wl)
+    rng = np.random.default_rng(31)
+    lev = P.Level(lay)
+    p = P.params(gamma=wl.gamma, grav=wl.grav)
+    U = torch.from_numpy(wl.arena).cuda()
+    lev.fill_boundary(U)
+    wU = _valid_random(lay, rng) if with_state else np.zeros(lay.arena_len())
+    Fb = lev.new_fluxes()
+    for F in Fb:
+        F.copy_(torch.from_numpy(rng.normal(size=F.numel())))
+    Ub = torch.full_like(U, float("nan"))
+    lev.hydro_step_adjoint(U, torch.from_numpy(wU).cuda(), Ub, wl.dx, p, dt=dt, flux_bar=Fb)
+    assert lev.check_status() == 0
+    v = _valid_random(lay, rng)
+    lhs = _dot_valid(lay, Ub.cpu().numpy(), v)
+    op = O.params(gamma=wl.gamma, grav=wl.grav)
+    St = [lay.view(wl.arena, b).copy() for b in range(lay.nbox)]
+    Vt = [lay.view(v, b).copy() for b in range(lay.nbox)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, St)
+    O.fill(lay.boxes(), lay.domain(), lay.bc, Vt)
+    rhs = 0.0
+    for b in range(lay.nbox):
+        _, dU, _, dF, fl = O.step_jvp_flux(St[b], Vt[b], dt, wl.dx, op,
+                                           walls=O.box_walls(lay.boxes(), lay.domain(), lay.bc, b))
+        assert fl == 0
+        rhs += float(np.sum(interior(lay.view(wU, b)) * interior(dU)))
+        for d in range(3):
+            rhs += float(np.sum(lev.flux_view(Fb[d], d, b).cpu().numpy() * dF[d]))
+    print(f"flux adjoint (state part {'on' if with_state else 'off'}): {lhs:.15e} vs {rhs:.15e}")
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+    lev.close()

@@ -625,3 +625,66 @@ def test_run_with_fused_dt_equals_the_plain_run():
         assert np.array_equal(interior(wl.layout.view(fused, b)), interior(wl.layout.view(plain, b)))
     assert lev.check_status() == 0
     lev.close()
+
+
+def test_graph_launch_refused_after_the_context_changes():
+    """A captured graph replays the workspace, tile lists and step form it
+    was captured with: after set_tiling, a new workspace, a changed step
+    form or the context's destruction, its launch is refused (PPM_EINVAL)
+    and replays nothing; a graph captured afterwards runs."""
+    wl = I.cfg2(16)
+    lev = P.Level(wl.layout)
+    p = P.params(gamma=wl.gamma)
+    A = torch.from_numpy(wl.arena).cuda()
+    B = lev.new_state()
+    g = lev.graph(A, B, wl.dx, p, 2)
+    g.launch()
+    torch.cuda.synchronize()
+    before = A.clone()
+    lev.set_tiling(128, 8)
+    with pytest.raises(P.PPMError, match="changed since the graph was captured"):
+        g.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(A, before)                 # nothing was replayed
+    g.close()
+    g = lev.graph(A, B, wl.dx, p, 2)              # captured again: runs
+    g.launch()
+    torch.cuda.synchronize()
+    lev.set_step_form(True)
+    with pytest.raises(P.PPMError):
+        g.launch()
+    lev.set_step_form(False)
+    g.close()
+    g = lev.graph(A, B, wl.dx, p, 2)
+    lev._work = None
+    lev.ensure_workspace(0)                       # a new workspace buffer
+    with pytest.raises(P.PPMError):
+        g.launch()
+    g.close()
+    g = lev.graph(A, B, wl.dx, p, 2)
+    lev.close()                                   # the context is gone
+    rc = P.lib().ppm_graph_launch(g.g, None)
+    assert rc == P.PPM_EINVAL
+    g.close()
+
+
+def test_state_outside_the_exact_range_raises_the_range_flag():
+    """The shortened FP64 divisions and roots are the IEEE results for
+    states whose densities, pressures and sound speeds lie in
+    [2^-120, 2^120] (velocities up to 2^120): a zone outside raises
+    FLAG_RANGE (the step still runs); floors outside that range are
+    refused."""
+    wl = I.cfg1(8)
+    lay = wl.layout
+    U0 = wl.arena.copy()
+    v = lay.view(U0, 0)
+    v[:, 6, 6, 6] *= 2.0 ** -130          # density, momenta, energy: rho ~ 1e-39, p ~ 1e-39
+    wl2 = I.Workload("tiny", lay, U0, wl.dx, wl.gamma, 1)
+    _, out, _, flags, _ = gpu_run(wl2, 1, dt=1e-3)
+    assert flags & P.FLAG_RANGE and not flags & P.FLAG_NONPHYS
+    _, _, _, flags, _ = gpu_run(wl, 1, dt=1e-3)
+    assert flags == 0
+    lev = P.Level(lay)
+    U = torch.from_numpy(wl.arena).cuda()
+    with pytest.raises(P.PPMError, match="floors"):
+        lev.hydro_step(U, lev.new_state(), wl.dx, P.params(gamma=1.4, small_pres=1e-40), dt=1e-3)

@@ -263,3 +263,27 @@ def test_state_conversion_operation_count():
     assert fl == 0
     assert got == {"div": 4, "add": 6, "mul": 14, "sqrt": 0, "minmax": 2}
     assert np.allclose(out, q, rtol=1e-15, atol=0)
+
+
+def test_flux_output_tangent_matches_central_differences():
+    """The tangents of the step's flux outputs (the dual-number evaluation
+    with flux output) against central differences of the plain step's
+    fluxes on smooth data with the unlimited scheme (no kinks)."""
+    from paper_1008_2801_amd import inputs as I
+    wl = I.cfg4(10, amp=0.05, bulk=(0.3, 0.2, 0.25))
+    lay = wl.layout
+    st = [lay.view(wl.arena, 0).copy()]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+    dv = [np.random.default_rng(0).normal(size=st[0].shape)]
+    O.fill(lay.boxes(), lay.domain(), lay.bc, dv)
+    p = O.params(gamma=wl.gamma, limiter=0)
+    U1, _, F, dF, fl = O.step_jvp_flux(st[0], dv[0], 1e-3, wl.dx, p)
+    U2, F2, _ = O.step(st[0], 1e-3, wl.dx, p, fluxes=True)
+    assert fl == 0 and np.array_equal(U1, U2)
+    eps = 1e-6
+    _, Fp, _ = O.step(st[0] + eps * dv[0], 1e-3, wl.dx, p, fluxes=True)
+    _, Fm, _ = O.step(st[0] - eps * dv[0], 1e-3, wl.dx, p, fluxes=True)
+    for d in range(3):
+        assert np.array_equal(F[d], F2[d])
+        err = np.abs((Fp[d] - Fm[d]) / (2 * eps) - dF[d]).max() / np.abs(dF[d]).max()
+        assert err < 1e-8, (d, err)
