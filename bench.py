@@ -104,12 +104,19 @@ def record_traffic(fetch_csv, write_csv, kernel, workload, tiling, fetch_factor,
     w_kib, nw = mean_kib(write_csv, "WRITE_SIZE")
 
     def step_bytes(path, counter, factor):
-        # every stage kernel of the step (not the one dt pass before the
-        # first step), per step: the counted dispatches over the step count,
-        # which the kernel's own dispatches give
-        tot = sum(float(r["Counter_Value"]) for r in csv.DictReader(open(path))
-                  if r["Counter_Name"] == counter and "ppm::" in r["Kernel_Name"]
-                  and "k_wavespeed" not in r["Kernel_Name"])
+        # every kernel of the steps, per step: the counted dispatches over
+        # the step count, which the kernel's own dispatches give.  A
+        # stand-alone dt pass (k_zero_u64, k_wavespeed, k_finish_dt) is not
+        # part of a step; the speed pass that the brick form runs after its
+        # update is.
+        rows = sorted((r for r in csv.DictReader(open(path))
+                       if r["Counter_Name"] == counter and "ppm::" in r["Kernel_Name"]),
+                      key=lambda r: int(r["Dispatch_Id"]))
+        tot = 0.0
+        for i, r in enumerate(rows):
+            if "k_wavespeed" in r["Kernel_Name"] and i > 0 and "k_zero_u64" in rows[i - 1]["Kernel_Name"]:
+                continue
+            tot += float(r["Counter_Value"])
         return tot * 1024 * factor
     steps = nf  # one dispatch of the kernel per step
     rec = {"kernel": f"k_{kernel}<double>", "workload": workload, "tiling": list(tiling),
@@ -649,6 +656,19 @@ def algorithmic_bytes_per_step(lay):
     return 40 * stored + 40 * lay.valid_zones()
 
 
+# The final stage's launch forms (ppm_set_step_form): the staged riemann3 +
+# update kernels, the brick kernel, the streamed kernel.
+FINAL_FORMS = ("staged", "brick", "streamed")
+
+
+def launch_config(lev):
+    """[tile, strip_rows, final-stage form] and, for the streamed form, its
+    tile extents [x, y, z run]: what the counter records are tied to."""
+    t, s = lev.get_tiling()
+    form = lev.get_step_form()
+    return [t, s, form] + (list(lev.get_stream_tiling()) if form == 2 else [])
+
+
 def headline(wl, wname, steps, warmup, per_box=True, tiling=None, autotune=True):
     """The timed level: batched eager steps with stage profiling (the
     roofline's kernel times), the same steps as one HIP-graph launch (the
@@ -663,15 +683,20 @@ def headline(wl, wname, steps, warmup, per_box=True, tiling=None, autotune=True)
     dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
     from_cache = None
     if tiling:
-        lev.set_tiling(*tiling)
+        lev.set_tiling(*tiling[:2])
+        if len(tiling) > 2:
+            if len(tiling) > 3:
+                lev.set_stream_tiling(*tiling[3:6])
+            lev.set_step_form(tiling[2])
     elif autotune:
         Uf = U0.clone()
         lev.fill_boundary(Uf)
         t_, s_, from_cache = lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)
         del Uf
-    tiling = lev.get_tiling()
+    tiling = launch_config(lev)
     zones = lay.valid_zones()
-    out = {"tiling": {"tile": tiling[0], "strip_rows": tiling[1]},
+    out = {"tiling": {"tile": tiling[0], "strip_rows": tiling[1], "final_stage_form": FINAL_FORMS[tiling[2]],
+                      "stream_tile": tiling[3:] or None},
            "autotune": {"from_cache": None if from_cache is None else bool(from_cache),
                         "cache": os.path.relpath(AUTOTUNE_CACHE, ROOT) if from_cache is not None else None}}
 
@@ -741,22 +766,32 @@ def roofline(wname, lay, prof, ms_step, precision, tiling):
         for k, v in stage_units(lay.n(b)).items():
             units[k] += v
     table = flops_table(wname)
-    stages = {k: prof[k] for k in STAGES}
+    # with a fused final stage (brick or streamed form) one kernel does the
+    # riemann3 and update work, timed in the riemann3 slot
+    fused = len(tiling) > 2 and tiling[2] != 0
+    stages = {k: prof[k] for k in STAGES if not (fused and k == "update")}
+    flops_of = {k: table[k] * units[k] for k in stages}
+    if fused:
+        flops_of["riemann3"] += table["update"] * units["update"]
     dom = max(stages, key=lambda k: stages[k][0])
     t_ms, cnt = stages[dom]
     mean_s = t_ms / cnt / 1e3
-    flops = table[dom] * units[dom]
+    flops = flops_of[dom]
     achieved = flops / mean_s / 1e12
     peak = FP64_VECTOR_PEAK_TFLOPS if precision == 0 else FP32_VECTOR_PEAK_TFLOPS
     rec = recorded_record(dom, wname, tiling) if precision == 0 else None
     step_flops = sum(table[k] * units[k] for k in STAGES)
     alg = algorithmic_bytes_per_step(lay)
-    r = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+    name = dom if not (fused and dom == "riemann3") else \
+        ("final_update (riemann3 + update, brick form)" if tiling[2] == 1 else
+         "final_stream (riemann3 + update, streamed form)")
+    r = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
          "frac": achieved / peak,
          "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
          "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
          "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops,
-         "flops_per_unit": table[dom], "units_per_launch": units[dom],
+         "flops_per_unit": table[dom] if name == dom else None,
+         "units_per_launch": units[dom] if name == dom else None,
          "clock_ghz": rec.get("clock_ghz") if rec else None,
          "valu_issue_util": rec.get("valu_util") if rec else None,
          "step_traffic": rec.get("step_traffic_bytes") if rec else None,
@@ -780,7 +815,9 @@ def main():
     ap.add_argument("--no-per-box", action="store_true", help="skip the one-launch-per-box timing")
     ap.add_argument("--autotune-cache", default=None,
                     help="autotuner cache file (default: the package's autotune_cache.jsonl)")
-    ap.add_argument("--tiling", default=None, help="'tile,strip_rows': use this tiling instead of autotuning")
+    ap.add_argument("--tiling", default=None,
+                    help="'tile,strip_rows[,form[,x,y,z]]': use this launch configuration (tiling, final-stage "
+                         "form 0 staged / 1 brick / 2 streamed, streamed tile extents) instead of autotuning")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (single box, 512-box tiling, adjoint, two-level, jet, species)")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -813,9 +850,8 @@ def main():
         AUTOTUNE_CACHE = args.autotune_cache
     if args.record_traffic:
         ff, wf = (float(v) for v in args.counter_factors.split(","))
-        t_, s_ = (int(v) for v in args.tiling.split(","))
         record_traffic(args.record_traffic[0], args.record_traffic[1], args.record_kernel, args.workload,
-                       (t_, s_), ff, wf, args.record_valu)
+                       [int(v) for v in args.tiling.split(",")], ff, wf, args.record_valu)
         return
 
     import torch

@@ -367,12 +367,25 @@ int ppm_get_tiling(const ppm_ctx* ctx, int32_t* tile, int32_t* strip_rows);
  * fused = 1: the final fluxes of each brick of 32 x 4 x 4 valid zones are
  * computed into LDS and the brick is updated from them in the same kernel
  * (the fluxes on a brick's faces are computed by both bricks that share
- * them; nothing is written to the workspace's final-flux planes).  Results
- * are identical bit for bit; on gfx950 the staged form is the faster one.
- * The species step always runs the staged form (it reads the final mass
- * fluxes from the workspace). */
+ * them).  fused = 2: each workgroup owns an x-y tile of valid zones
+ * (ppm_set_stream_tiling) and walks it through a run of z planes: per plane
+ * its lanes solve every x and y face of the tile and each zone's high z
+ * face once into LDS (the high z faces serve as the next plane's low ones),
+ * then update the plane (only the faces shared with neighbouring tiles and
+ * runs are solved twice).  In forms 1 and 2 nothing is written to the
+ * workspace's final-flux planes.  Results are identical bit for bit in all
+ * forms.  The species step always runs the staged form (it reads the final
+ * mass fluxes from the workspace).  The autotuner picks among the forms and
+ * the tile shape. */
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused);
 int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused);
+/* Tile of the streamed final stage (form 2): sx x sy valid zones in x-y
+ * (sx, sy >= 2; sx * sy a multiple of 32 up to 256; the workgroup has twice
+ * as many lanes), runs of sz planes in z.  Default 16 x 8 x 32.
+ * Synchronises the device when form 2 is active (the tile list is
+ * rebuilt).  PPM_EINVAL otherwise. */
+int ppm_set_stream_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz);
+int ppm_get_stream_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz);
 
 /* Diagnostic: out[i] = one of the FP64 square roots the Riemann solver
  * takes, computed on the device for n arguments x[i].  form 0: the root of
@@ -403,11 +416,14 @@ int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n
 
 /* Autotuner: times the batched step (reps steps after one warm-up, HIP
  * events on the stream) from the filled state U into Unew for every
- * candidate tile size x strip height, keeps the fastest, and appends it to
- * the JSON-lines file cache_path (may be null) keyed by device
- * architecture, precision and the histogram of box extents; a matching
- * entry in the file is applied without timing (*from_cache = 1).
- * Synchronises.  Writes the chosen tiling to *tile, *strip_rows. */
+ * candidate tile size x strip height, keeps the fastest, then times the
+ * final stage staged (form 0) and streamed (form 2) with several tile
+ * shapes and keeps the fastest, and appends the choice to the JSON-lines
+ * file cache_path (may be null) keyed by device architecture, precision
+ * and the histogram of box extents; a matching entry in the file is
+ * applied without timing (*from_cache = 1).  Synchronises.  Writes the
+ * chosen tiling to *tile, *strip_rows (ppm_get_step_form and
+ * ppm_get_stream_tiling give the rest). */
 int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3], const ppm_params* params,
                  int32_t reps, const char* cache_path, void* stream, int32_t* tile, int32_t* strip_rows,
                  int32_t* from_cache);

@@ -350,28 +350,32 @@ struct ppm_graph {
 };
 
 namespace {
-// Bricks of at most BRICK_E valid zones per box, x fastest then y then z.
+// Blocks of valid zones per box for the fused final stage, x fastest then y
+// then z: bricks of at most BRICK_E zones (form 1) or the streamed form's
+// tiles of stream_e (form 2).
 void build_bricks(ppm_ctx& c) {
   c.bricks.clear();
   c.tB_begin.assign(1, 0);
+  const int* E = c.fused == 2 ? c.stream_e : BRICK_E;
   for (int b = 0; b < c.layout.nbox; ++b) {
     int n[3];
     for (int d = 0; d < 3; ++d) n[d] = c.boxes[b].hi[d] - c.boxes[b].lo[d] + 1;
-    for (int z = 0; z < n[2]; z += BRICK_E[2])
-      for (int y = 0; y < n[1]; y += BRICK_E[1])
-        for (int x = 0; x < n[0]; x += BRICK_E[0]) {
+    for (int z = 0; z < n[2]; z += E[2])
+      for (int y = 0; y < n[1]; y += E[1])
+        for (int x = 0; x < n[0]; x += E[0]) {
           Brick K;
           K.box = b;
           const int o[3] = {x, y, z};
           for (int d = 0; d < 3; ++d) {
             K.o[d] = o[d];
-            K.e[d] = std::min(BRICK_E[d], n[d] - o[d]);
+            K.e[d] = std::min(E[d], n[d] - o[d]);
           }
           c.bricks.push_back(K);
         }
     c.tB_begin.push_back((int)c.bricks.size());
   }
 }
+
 
 void build_tiles(ppm_ctx& c) {
   c.tilesS.clear();
@@ -394,6 +398,16 @@ template <class T> hipError_t upload(T** dst, const std::vector<T>& v) {
   if (e != hipSuccess) return e;
   if (!v.empty()) e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   return e;
+}
+
+// Rebuilds and uploads the block list of the current final-stage form.
+hipError_t upload_bricks(ppm_ctx& c) {
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return e;
+  build_bricks(c);
+  (void)hipFree(c.d_bricks);
+  c.d_bricks = nullptr;
+  return upload(&c.d_bricks, c.bricks);
 }
 
 std::string validate_params(const ppm_params* p) {
@@ -765,9 +779,33 @@ int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n
 
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused) {
   if (!ctx) return PPM_EINVAL;
-  if (fused != 0 && fused != 1) return ctx->fail(PPM_EINVAL, "set_step_form: fused must be 0 or 1");
-  if (fused != ctx->fused) ++ctx->gen;
+  if (fused < 0 || fused > 2) return ctx->fail(PPM_EINVAL, "set_step_form: fused must be 0, 1 or 2");
+  if (fused == ctx->fused) return PPM_OK;
+  ++ctx->gen;
+  const bool rebuild = (fused == 2) != (ctx->fused == 2);  // forms 0 and 1 share the brick list
   ctx->fused = fused;
+  if (rebuild) return ctx->hip(upload_bricks(*ctx), "set_step_form");
+  return PPM_OK;
+}
+
+int ppm_set_stream_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz) {
+  if (!ctx) return PPM_EINVAL;
+  if (sx < 2 || sy < 2 || sz < 1 || sx * sy > STREAM_MAX_THREADS / 2 || sx * sy % 32 != 0)
+    return ctx->fail(PPM_EINVAL, "set_stream_tiling: need sx, sy >= 2, sz >= 1 and sx * sy a multiple of 32 "
+                                 "up to 256");
+  ++ctx->gen;
+  ctx->stream_e[0] = sx;
+  ctx->stream_e[1] = sy;
+  ctx->stream_e[2] = sz;
+  if (ctx->fused == 2) return ctx->hip(upload_bricks(*ctx), "set_stream_tiling");
+  return PPM_OK;
+}
+
+int ppm_get_stream_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz) {
+  if (!ctx || !sx || !sy || !sz) return PPM_EINVAL;
+  *sx = ctx->stream_e[0];
+  *sy = ctx->stream_e[1];
+  *sz = ctx->stream_e[2];
   return PPM_OK;
 }
 
@@ -1038,7 +1076,7 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
   for (const ppm_box& B : ctx->boxes)
     hist[{B.hi[0] - B.lo[0] + 1, B.hi[1] - B.lo[1] + 1, B.hi[2] - B.lo[2] + 1}]++;
   std::ostringstream ks;
-  ks << prop.gcnArchName << "|p" << params->precision << "|";
+  ks << prop.gcnArchName << "|p" << params->precision << "|fs|";
   for (const auto& kv : hist) ks << kv.first[0] << "x" << kv.first[1] << "x" << kv.first[2] << ":" << kv.second << ";";
   const std::string key = ks.str();
   if (from_cache) *from_cache = 0;
@@ -1048,11 +1086,20 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
     const std::string pat = "\"key\": \"" + key + "\"";
     while (std::getline(in, line)) {
       if (line.find(pat) == std::string::npos) continue;
-      int t = 0, sr = -1;
-      const size_t a = line.find("\"tile\": "), b = line.find("\"strip_rows\": ");
-      if (a != std::string::npos) t = std::atoi(line.c_str() + a + 8);
-      if (b != std::string::npos) sr = std::atoi(line.c_str() + b + 14);
-      if (ppm_set_tiling(ctx, t, sr) == PPM_OK) {
+      int t = 0, sr = -1, form = 0, se[3] = {0, 0, 0};
+      auto field = [&](const char* name, int dflt) {
+        const std::string f = std::string("\"") + name + "\": ";
+        const size_t a = line.find(f);
+        return a == std::string::npos ? dflt : std::atoi(line.c_str() + a + f.size());
+      };
+      t = field("tile", 0);
+      sr = field("strip_rows", -1);
+      form = field("form", 0);
+      se[0] = field("sx", ctx->stream_e[0]);
+      se[1] = field("sy", ctx->stream_e[1]);
+      se[2] = field("sz", ctx->stream_e[2]);
+      if (ppm_set_tiling(ctx, t, sr) == PPM_OK && ppm_set_stream_tiling(ctx, se[0], se[1], se[2]) == PPM_OK &&
+          ppm_set_step_form(ctx, form) == PPM_OK) {
         if (tile) *tile = t;
         if (strip_rows) *strip_rows = sr;
         if (from_cache) *from_cache = 1;
@@ -1089,17 +1136,60 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
     }
     if (rc) break;
   }
+  if (!rc) rc = ppm_set_tiling(ctx, bt, bs);
+  // then the final stage's form: the staged pair of kernels, the brick
+  // kernel, or the streamed kernel with one of its tile shapes (x, y
+  // extents, z run)
+  static const int shapes[][3] = {{16, 8, 32}, {32, 8, 32}, {16, 16, 32}, {32, 4, 32}, {16, 8, 64}, {32, 8, 16},
+                                  {64, 4, 32}};
+  int bform = 0, bse[3] = {ctx->stream_e[0], ctx->stream_e[1], ctx->stream_e[2]};
+  const int form0 = ctx->fused;
+  auto timed = [&](float& ms) {
+    int r = ppm_compute_dt(ctx, U, dx, params, dtv, stream);
+    if (!r) r = ppm_hydro_step(ctx, U, Unew, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, stream);
+    (void)hipEventRecord(e0, s);
+    for (int q = 0; q < reps && !r; ++q)
+      r = ppm_hydro_step(ctx, U, Unew, nullptr, 0.0, dtv, dx, params, PPM_LAUNCH_BATCHED, stream);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    return r;
+  };
+  if (!rc) {
+    float ms = 0.f;
+    if (!(rc = ppm_set_step_form(ctx, 0)) && !(rc = timed(ms))) best = ms;
+    if (!rc && !(rc = ppm_set_step_form(ctx, 1)) && !(rc = timed(ms)) && ms < best) {
+      best = ms;
+      bform = 1;
+    }
+    for (const auto& sh : shapes) {
+      if (rc) break;
+      if (ppm_set_stream_tiling(ctx, sh[0], sh[1], sh[2]) != PPM_OK) continue;
+      if ((rc = ppm_set_step_form(ctx, 2)) || (rc = timed(ms))) break;
+      if (ms < best) {
+        best = ms;
+        bform = 2;
+        for (int d = 0; d < 3; ++d) bse[d] = sh[d];
+      }
+      if ((rc = ppm_set_step_form(ctx, 0))) break;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(dtv);
-  if (rc) return rc;
-  rc = ppm_set_tiling(ctx, bt, bs);
-  if (rc) return rc;
+  if (rc) {
+    (void)ppm_set_step_form(ctx, form0);
+    return rc;
+  }
+  if ((rc = ppm_set_stream_tiling(ctx, bse[0], bse[1], bse[2])) || (rc = ppm_set_step_form(ctx, bform))) return rc;
   if (tile) *tile = bt;
   if (strip_rows) *strip_rows = bs;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"tile\": " << bt << ", \"strip_rows\": " << bs
+        << ", \"form\": " << bform << ", \"sx\": " << bse[0] << ", \"sy\": " << bse[1] << ", \"sz\": " << bse[2]
         << ", \"ms_per_step\": " << best << "}\n";
   }
   return PPM_OK;

@@ -38,7 +38,8 @@ struct ppm_ctx {
   std::vector<int> tS_begin, tE_begin;  // nbox + 1
   std::vector<Brick> bricks;
   std::vector<int> tB_begin;            // nbox + 1
-  int fused = 0;                        // 1: final fluxes + update in one brick kernel
+  int fused = 0;                        // 1: final fluxes + update in one brick kernel; 2: streamed
+  int stream_e[3] = {16, 8, 32};        // tile extents of the streamed final stage
   int device = -1;                      // HIP device current at ppm_ctx_create
   // Generation of the device state a captured graph bakes in (workspace,
   // tile lists, step form, inflow states): bumped whenever one changes; a
@@ -107,6 +108,7 @@ struct ppm_ctx {
     for (int d = 0; d < 3; ++d) L.inflow.ext[d] = layout.domain.hi[d] - layout.domain.lo[d] + 1;
     L.bricks = d_bricks;
     L.fused = fused;
+    for (int d = 0; d < 3; ++d) L.stream_e[d] = stream_e[d];
     return L;
   }
   int fail(int code, const std::string& msg) {

@@ -38,6 +38,11 @@ struct Tile {
 // the lanes of a wavefront read runs of consecutive zones.
 constexpr int BRICK_E[3] = {32, 4, 4};
 constexpr int BRICK_THREADS = 512;
+// The streamed final stage: x-y tiles of sx x sy zones (a multiple of 32,
+// at most 256); a workgroup of twice as many lanes (at most 512) works
+// through the plane's 3 sx sy + sx + sy face solves.
+constexpr int STREAM_MAX_THREADS = 512;
+inline int stream_threads(int sx, int sy) { return 2 * sx * sy < STREAM_MAX_THREADS ? 2 * sx * sy : STREAM_MAX_THREADS; }
 // faces of the largest axis of a full brick (LDS slots per axis and component)
 constexpr int BRICK_FACES_D(int d) {
   return (BRICK_E[0] + (d == 0)) * (BRICK_E[1] + (d == 1)) * (BRICK_E[2] + (d == 2));
@@ -109,8 +114,10 @@ struct DevLevel {
   long long LS, LE;    // plane lengths (elements) of the primitive and traced arenas
   int tile;            // zones per tile of the tile lists (threads per workgroup)
   InflowView inflow;
-  const Brick* bricks;  // valid-zone bricks of every box (fused final stage)
-  int fused;            // 1: final fluxes and update in one brick kernel (fluxes kept in LDS)
+  const Brick* bricks;  // valid-zone blocks of every box (fused final stage)
+  int fused;            // 1: final fluxes and update in one brick kernel (fluxes kept in LDS);
+                        // 2: the same in x-y tiles streamed along z (ppm_kernels.hip, k_final_stream)
+  int stream_e[3];      // form 2: x, y extents of a tile (threads = product) and the z run
 };
 
 }  // namespace ppm

@@ -119,15 +119,17 @@ __global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ t
       for (int o = -3; o <= 3; ++o) p[o + 3] = pp[o * st];
 #pragma unroll
       for (int o = -2; o <= 2; ++o) u[o + 2] = uu[o * st];
-      // shock-detector coefficient at offset o (p index o+3, u index o+2)
+      // shock-detector coefficient at offset o (p index o+3, u index o+2);
+      // the pressure ratio (one division) only where the zone is a strong
+      // compression, which away from shocks no lane of a wave is
       auto chit = [&](int o) -> S {
         const S dp1 = p[o + 4] - p[o + 2];
-        const S dp2 = p[o + 5] - p[o + 1];
-        const S zeta = qdiv(sabs(dp1), smax(sabs(dp2), G.small_pres));
-        const S zz = smin(smax(TEN * (zeta - C075), S(0)), ONE);
         const bool compress = (u[o + 1] - u[o + 3]) > S(0);
         const bool strong = sabs(dp1) > C033 * smin(p[o + 4], p[o + 2]);
-        return (compress && strong) ? zz : S(0);
+        if (!(compress && strong)) return S(0);
+        const S dp2 = p[o + 5] - p[o + 1];
+        const S zeta = qdiv(sabs(dp1), smax(sabs(dp2), G.small_pres));
+        return smin(smax(TEN * (zeta - C075), S(0)), ONE);
       };
       const S dp1 = p[4] - p[2];
       S chi;
@@ -574,6 +576,122 @@ __global__ void __launch_bounds__(BRICK_THREADS) k_final_update(const Brick* __r
   }
 }
 
+// O9 + O10 fused, streamed along z: a workgroup owns an x-y tile of
+// ex x ey valid zones and walks it through a run of z planes.  Per plane the
+// stage-3 problems of the tile's faces are work items dealt round-robin to
+// the workgroup's lanes, x faces first, then y faces, then the zones' high
+// z faces (so a wave seldom mixes axes): (ex + 1) ey + ex (ey + 1) + ex ey
+// solves, the x and y fluxes into LDS, the z fluxes into one of two LDS
+// planes, the low z flux of a zone being the high one of the plane below
+// (the run's first plane solves its low faces once more).  Every face is
+// solved once, except the faces shared by neighbouring tiles and runs, and
+// the final fluxes never go to HBM.  Then the plane's zones are updated.
+// The arithmetic is riemann3_face and update_zone, so the results are the
+// staged kernels' bit for bit.
+template <class S>
+__device__ __forceinline__ void stream_face(int f, const Brick& K, const DevBox& B, const S* __restrict__ work,
+                                            long long LE, const Gas<S>& G, const StepConsts* __restrict__ sc,
+                                            int z, int sx, int sy, S* Fx, S* Fy, S* Fz, double* fx, double* fy,
+                                            double* fz, int& fl) {
+  const int ex = K.e[0], ey = K.e[1];
+  const int nfx = (ex + 1) * ey, nfy = ex * (ey + 1);
+  const int FXN = (sx + 1) * sy, FYN = sx * (sy + 1), FZN = sx * sy;
+  S F[5];
+  if (f < nfx) {  // x face i of row j (i in [0, ex])
+    const int j = f / (ex + 1), i = f - j * (ex + 1);
+    const int x[3] = {K.o[0] + i, K.o[1] + j, z};
+    riemann3_face<0>(B, x, work, LE, G, sc, F, fl);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Fx[m * FXN + j * (sx + 1) + i] = F[m];
+    if (fx) write_flux<0>(B, x, F, fx);
+  } else if ((f -= nfx) < nfy) {  // y face j of column i (j in [0, ey])
+    const int j = f / ex, i = f - j * ex;
+    const int x[3] = {K.o[0] + i, K.o[1] + j, z};
+    riemann3_face<1>(B, x, work, LE, G, sc, F, fl);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Fy[m * FYN + j * sx + i] = F[m];
+    if (fy) write_flux<1>(B, x, F, fy);
+  } else {  // z face z of zone (i, j)
+    f -= nfy;
+    const int j = f / ex, i = f - j * ex;
+    const int x[3] = {K.o[0] + i, K.o[1] + j, z};
+    riemann3_face<2>(B, x, work, LE, G, sc, F, fl);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) Fz[m * FZN + j * sx + i] = F[m];
+    if (fz) write_flux<2>(B, x, F, fz);
+  }
+}
+
+template <class S>
+__global__ void __launch_bounds__(STREAM_MAX_THREADS) k_final_stream(
+    const Brick* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes, const S* __restrict__ work,
+    long long LE, Gas<S> G, const StepConsts* __restrict__ sc, const double* __restrict__ U,
+    double* __restrict__ Unew, double* fx, double* fy, double* fz, int grav, double g0, double g1, double g2,
+    int sx, int sy, SpeedOut so, int* flags) {
+  extern __shared__ unsigned char smem_raw[];
+  const int k = xcd_tile(ntiles);
+  if (k < 0) return;  // the whole workgroup
+  const Brick K = tiles[k];
+  const DevBox B = boxes[K.box];
+  const int FXN = (sx + 1) * sy, FYN = sx * (sy + 1), FZN = sx * sy;
+  S* Fx = (S*)smem_raw;  // [m][j][i], i in [0, sx]: x faces of row j
+  S* Fy = Fx + 5 * FXN;  // [m][j][i], j in [0, sy]: y faces of column i
+  S* Fz0 = Fy + 5 * FYN;  // two planes [m][j][i] of z faces
+  S* Fz1 = Fz0 + 5 * FZN;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int ex = K.e[0], ey = K.e[1];
+  const int nfx = (ex + 1) * ey, nfy = ex * (ey + 1), nz = ex * ey;
+  const double dtdx0 = sc->dtdx[0], dtdx1 = sc->dtdx[1], dtdx2 = sc->dtdx[2];
+  const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
+  const long long NS = (long long)N0 * N1 * N2;
+  int fl = 0;
+  double smax_lane = 0.0;
+  // the run's first low z faces (the box's own low face is written once, here);
+  // the work-item loops are not unrolled: one face solve is live at a time
+#pragma nounroll
+  for (int f = t; f < nz; f += nt)
+    stream_face<S>(nfx + nfy + f, K, B, work, LE, G, sc, K.o[2], sx, sy, Fx, Fy, Fz0,
+                   nullptr, nullptr, K.o[2] == 0 ? fz : nullptr, fl);
+  S* Flo = Fz0;
+  S* Fhi = Fz1;
+  for (int kz = 0; kz < K.e[2]; ++kz) {
+    const int z = K.o[2] + kz;
+#pragma nounroll
+    for (int f = t; f < nfx + nfy; f += nt)
+      stream_face<S>(f, K, B, work, LE, G, sc, z, sx, sy, Fx, Fy, Fhi, fx, fy, fz, fl);
+#pragma nounroll
+    for (int f = t; f < nz; f += nt)  // high z faces: slot z + 1
+      stream_face<S>(nfx + nfy + f, K, B, work, LE, G, sc, z + 1, sx, sy, Fx, Fy, Fhi, fx, fy, fz, fl);
+    __syncthreads();
+#pragma nounroll
+    for (int q = t; q < nz; q += nt) {
+      const int j = q / ex, i = q - j * ex;
+      const int x0 = K.o[0] + i, y0 = K.o[1] + j;
+      double fxd[5], fyd[5], fzd[5], uo[5], un[5];
+      const long long ui = B.soff + ((long long)(z + NG) * N1 + (y0 + NG)) * N0 + (x0 + NG);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        fxd[m] = (double)Fx[m * FXN + j * (sx + 1) + i + 1] - (double)Fx[m * FXN + j * (sx + 1) + i];
+        fyd[m] = (double)Fy[m * FYN + (j + 1) * sx + i] - (double)Fy[m * FYN + j * sx + i];
+        fzd[m] = (double)Fhi[m * FZN + j * sx + i] - (double)Flo[m * FZN + j * sx + i];
+        uo[m] = U[ui + m * NS];
+      }
+      update_zone(uo, fxd, fyd, fzd, dtdx0, dtdx1, dtdx2, sc, grav, g0, g1, g2, un);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) Unew[ui + m * NS] = un[m];
+      if (so.bits)
+        smax_lane = smax(smax_lane, fold_signal_speed(0.0, un[0], un[1], un[2], un[3], un[4], so.h[0], so.h[1],
+                                                      so.h[2], so.gamma, so.gm1, so.small_pres));
+    }
+    S* tmp = Flo;
+    Flo = Fhi;
+    Fhi = tmp;
+    __syncthreads();  // before the next plane's faces overwrite the LDS
+  }
+  raise_flags(flags, fl);
+  if (so.bits) block_max_to(smax_lane, so.bits);
+}
+
 // O11: max over valid zones and axes of (|u_d| + c)/h_d, FP64.  A fixed grid
 // strides over the tiles; each lane keeps a running max, the workgroup
 // reduces it with wave64 shuffles and LDS, and one atomic max per workgroup
@@ -693,7 +811,18 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
   double* fz = flux ? flux[2] : nullptr;
   if (ev) (void)hipEventRecord(ev[5], s);
   const int nB = tB1 - tB0;
-  if (L.fused && upto == STEP_FULL && nB > 0) {
+  if (L.fused == 2 && upto == STEP_FULL && nB > 0) {
+    const int sx = L.stream_e[0], sy = L.stream_e[1];
+    const size_t lds = sizeof(S) * 5 * (size_t)((sx + 1) * sy + sx * (sy + 1) + 2 * sx * sy);
+    hipLaunchKernelGGL(k_final_stream<S>, dim3(xcd_grid(nB)), dim3(stream_threads(sx, sy)), lds, s, L.bricks + tB0,
+                       nB, L.boxes,
+                       (const S*)ework, L.LE, G, L.consts, U, Unew, fx, fy, fz, G.grav, g[0], g[1], g[2], sx, sy,
+                       so, L.flags);
+    if (ev) (void)hipEventRecord(ev[6], s);
+    if (ev) (void)hipEventRecord(ev[7], s);
+    return hipGetLastError();
+  }
+  if (L.fused == 1 && upto == STEP_FULL && nB > 0) {
     hipLaunchKernelGGL(k_final_update<S>, dim3(xcd_grid(nB)), dim3(BRICK_THREADS), 0, s, L.bricks + tB0, nB,
                        L.boxes, (const S*)ework, L.LE, G, L.consts, U, Unew, fx, fy, fz, G.grav, g[0], g[1], g[2],
                        L.flags);

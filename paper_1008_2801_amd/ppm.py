@@ -32,7 +32,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
            "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
-           "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt", "ppm_hydro_step_noalloc")
+           "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt", "ppm_hydro_step_noalloc",
+           "ppm_set_stream_tiling", "ppm_get_stream_tiling")
 NOALLOC_SCRATCH_BYTES = 128 << 20
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
@@ -124,6 +125,8 @@ def lib():
         L.ppm_set_inflow.argtypes = [_vp, ctypes.c_int32, _vp]
         L.ppm_set_step_form.argtypes = [_vp, ctypes.c_int32]
         L.ppm_get_step_form.argtypes = [_vp, _i32p]
+        L.ppm_set_stream_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.ppm_get_stream_tiling.argtypes = [_vp, _i32p, _i32p, _i32p]
         L.ppm_sqrt_values.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
         L.ppm_quotient_values.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
@@ -378,14 +381,23 @@ class Level:
         self._check(lib().ppm_set_tiling(self.ctx, int(tile), int(strip_rows)), "ppm_set_tiling")
 
     def set_step_form(self, fused):
-        """fused=True: final fluxes and update in one brick kernel (LDS);
-        False: the staged pair of kernels.  Same results."""
-        self._check(lib().ppm_set_step_form(self.ctx, int(bool(fused))), "ppm_set_step_form")
+        """0/False: the staged final-flux and update kernels; 1/True: one
+        brick kernel (fluxes in LDS); 2: the streamed kernel (x-y tiles
+        walked along z).  Same results."""
+        self._check(lib().ppm_set_step_form(self.ctx, int(fused)), "ppm_set_step_form")
 
     def get_step_form(self):
         f = ctypes.c_int32()
         self._check(lib().ppm_get_step_form(self.ctx, ctypes.byref(f)), "ppm_get_step_form")
-        return bool(f.value)
+        return f.value
+
+    def set_stream_tiling(self, sx, sy, sz):
+        self._check(lib().ppm_set_stream_tiling(self.ctx, int(sx), int(sy), int(sz)), "ppm_set_stream_tiling")
+
+    def get_stream_tiling(self):
+        v = [ctypes.c_int32() for _ in range(3)]
+        self._check(lib().ppm_get_stream_tiling(self.ctx, *[ctypes.byref(x) for x in v]), "ppm_get_stream_tiling")
+        return tuple(x.value for x in v)
 
     def get_tiling(self):
         t, s = ctypes.c_int32(), ctypes.c_int32()

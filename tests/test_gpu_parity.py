@@ -367,9 +367,12 @@ def test_tiling_does_not_change_results_and_autotuner_caches(tmp_path):
     cache = tmp_path / "tune.jsonl"
     t, s, hit = lev.autotune(U, wl.dx, p, reps=1, cache_path=cache)
     assert not hit and t in (128, 256, 512) and s in (0, 8, 16, 32, 64)
+    form, shape = lev.get_step_form(), lev.get_stream_tiling()
+    assert form in (0, 2)
     lev2 = P.Level(wl.layout)
     t2, s2, hit2 = lev2.autotune(U, wl.dx, p, reps=1, cache_path=cache)
     assert hit2 and (t2, s2) == (t, s) and lev2.get_tiling() == (t, s)
+    assert lev2.get_step_form() == form and lev2.get_stream_tiling() == shape
 
 
 def _smooth_on(lay, seed, gamma=1.4):
@@ -416,42 +419,53 @@ def test_strong_shock_tube_matches_oracle(axis):
     compare_level(wl, arena, ost, tag=f"1e5 pressure-ratio shock tube along axis {axis}, 6 steps")
 
 
+FINAL_FORMS = [(0, None), (1, None), (2, (16, 8, 32)), (2, (16, 4, 5)), (2, (8, 8, 3)), (2, (32, 8, 64)),
+               (2, (4, 8, 7))]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
-def test_fused_and_staged_final_stage_agree_bitwise(precision):
-    """The brick kernel (final fluxes in LDS, then the update) and the
-    staged pair give the same state and the same flux output bit for bit:
-    uneven boxes (several smaller than a brick), walls, gravity, both launch
-    forms."""
+def test_final_stage_forms_agree_bitwise(precision):
+    """The staged pair (final fluxes in the workspace, then the update), the
+    brick kernel and the streamed kernel with several tile shapes (tiles
+    larger and smaller than the boxes, runs that split the boxes' z extent
+    unevenly) give the same state, the same flux output and the same next
+    dt bit for bit: uneven boxes, walls, gravity, both launch forms."""
     wl = _uneven_level(seed=9, bc=(0, 0, 1, 1, 2, 2), sizes=(6, 8, 12, 20))
     wl.grav = (0.0, 0.0, -1.0)
     wl.precision = precision
     outs = []
-    for fused in (True, False):
+    for form, shape in FINAL_FORMS:
         for mode in (P.BATCHED, P.PER_BOX):
+            print(f"final-stage form {form}, tile {shape}, mode {mode}, precision {precision}", flush=True)
             lev = P.Level(wl.layout)
-            lev.set_step_form(fused)
-            assert lev.get_step_form() == fused
+            if shape:
+                lev.set_stream_tiling(*shape)
+            lev.set_step_form(form)
+            assert lev.get_step_form() == form
             U = torch.from_numpy(wl.arena).cuda()
             V = lev.new_state()
             p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
             dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
-            F = None
+            lev.compute_dt(U, wl.dx, p, out=dtv)
+            F, dts = None, []
             for _ in range(2):
                 lev.fill_boundary(U, mode)
-                lev.compute_dt(U, wl.dx, p, out=dtv)
                 F = lev.new_fluxes()
-                lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, fluxes=F, mode=mode)
+                lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, fluxes=F, mode=mode, dt_next=dtv)
+                dts.append(dtv.cpu().numpy().copy())
                 U, V = V, U
             assert lev.check_status() == 0
-            outs.append((U.cpu().numpy(), [f.cpu().numpy() for f in F]))
+            outs.append((U.cpu().numpy(), [f.cpu().numpy() for f in F], dts))
             lev.close()
-    ref_u, ref_f = outs[0]
+    ref_u, ref_f, ref_dt = outs[0]
     lay = wl.layout
-    for u, f in outs[1:]:
+    for k, (u, f, dts) in enumerate(outs[1:]):
         for b in range(lay.nbox):
-            assert np.array_equal(interior(lay.view(u, b)), interior(lay.view(ref_u, b)))
+            assert np.array_equal(interior(lay.view(u, b)), interior(lay.view(ref_u, b))), (k, b)
         for d in range(3):
-            assert np.array_equal(f[d], ref_f[d])
+            assert np.array_equal(f[d], ref_f[d]), (k, d)
+        for a, r in zip(dts, ref_dt):
+            assert np.array_equal(a, r), k
 
 
 def test_power_of_two_change_of_units_on_gpu():
@@ -567,14 +581,14 @@ def test_kernel_quotient_is_the_ieee_quotient():
     assert bad.size == 0, (bad.size, a[bad[:5]], b[bad[:5]], got[bad[:5]], ref[bad[:5]])
 
 
-@pytest.mark.parametrize("mode,precision,fused", [(P.BATCHED, 0, False), (P.PER_BOX, 0, False),
-                                                  (P.BATCHED, 1, False), (P.BATCHED, 0, True)])
+@pytest.mark.parametrize("mode,precision,fused", [(P.BATCHED, 0, 0), (P.PER_BOX, 0, 0), (P.BATCHED, 1, 0),
+                                                  (P.BATCHED, 0, 1), (P.BATCHED, 0, 2), (P.PER_BOX, 1, 2)])
 def test_fused_next_dt_is_compute_dt_of_the_new_state(mode, precision, fused):
     """ppm_hydro_step_dt leaves the CFL dt of the state it writes: bit for
     bit what a separate ppm_compute_dt pass over Unew gives (dt and the
     maximum signal speed), on uneven boxes with walls and gravity, in the
-    per-box launch form, in FP32-reconstruction mode and in the brick form
-    (which runs that separate pass itself)."""
+    per-box launch form, in FP32-reconstruction mode, in the brick form
+    (which runs that separate pass itself) and in the streamed form."""
     wl = _uneven_level(seed=17, bc=(0, 0, 1, 1, 2, 2), sizes=(6, 8, 12, 20))
     wl.grav = (0.0, 0.0, -1.0)
     wl.precision = precision
