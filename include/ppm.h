@@ -414,11 +414,13 @@ int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void*
  * or null pointers with n > 0. */
 int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n, void* stream);
 
-/* Autotuner: times the batched step (reps steps after one warm-up, HIP
- * events on the stream) from the filled state U into Unew for every
- * candidate tile size x strip height, keeps the fastest, then times the
- * final stage staged (form 0) and streamed (form 2) with several tile
- * shapes and keeps the fastest, and appends the choice to the JSON-lines
+/* Autotuner: times the batched step as graphs and steady loops run it
+ * (ppm_hydro_step_dt, the next dt left on the device; reps steps after one
+ * warm-up, HIP events on the stream) from the filled state U into Unew for
+ * every candidate tile size x strip height, keeps the fastest, then times
+ * the final stage staged (form 0), in bricks (form 1) and streamed (form 2)
+ * with several tile shapes and keeps the fastest, and appends the choice
+ * to the JSON-lines
  * file cache_path (may be null) keyed by device architecture, precision
  * and the histogram of box extents; a matching entry in the file is
  * applied without timing (*from_cache = 1).  Synchronises.  Writes the

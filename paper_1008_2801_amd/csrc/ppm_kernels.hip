@@ -27,10 +27,8 @@ namespace ppm {
 namespace {
 
 // ------------------------------------------------------------- kernels -----
-__global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, const double* dt_dev,
-                                                    double h0, double h1, double h2, double g0,
-                                                    double g1, double g2) {
-  if (threadIdx.x != 0) return;
+__device__ __forceinline__ void step_consts(StepConsts* c, double dt, const double* dt_dev, double h0, double h1,
+                                            double h2, double g0, double g1, double g2) {
   const double t = dt_dev ? dt_dev[0] : dt;
   const double h[3] = {h0, h1, h2}, g[3] = {g0, g1, g2};
   c->dt = t;
@@ -48,13 +46,18 @@ __global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, co
   }
 }
 
+__global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, const double* dt_dev,
+                                                    double h0, double h1, double h2, double g0,
+                                                    double g1, double g2) {
+  if (threadIdx.x == 0) step_consts(c, dt, dt_dev, h0, h1, h2, g0, g1, g2);
+}
+
 // O2 on every stored zone: (rho, u, v, w, p, c) planes.
+// t: the tile (-1: none), here and in the other stage bodies.
 template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_prim(const Tile* __restrict__ tiles, int ntiles,
-                                               const DevBox* __restrict__ boxes,
-                                               const double* __restrict__ U, S* __restrict__ prim,
-                                               long long LS, Gas<S> G, int* flags) {
-  const int t = xcd_tile(ntiles);
+__device__ __forceinline__ void prim_body(int t, const Tile* __restrict__ tiles, const DevBox* __restrict__ boxes,
+                                          const double* __restrict__ U, S* __restrict__ prim, long long LS,
+                                          const Gas<S>& G, int* flags) {
   if (t < 0) return;
   const Tile tl = tiles[t];
   const DevBox B = boxes[tl.box];
@@ -92,14 +95,20 @@ __global__ void __launch_bounds__(MAX_TILE) k_prim(const Tile* __restrict__ tile
   raise_flags(flags, fl);
 }
 
+template <class S>
+__global__ void __launch_bounds__(MAX_TILE) k_prim(const Tile* __restrict__ tiles, int ntiles,
+                                               const DevBox* __restrict__ boxes,
+                                               const double* __restrict__ U, S* __restrict__ prim,
+                                               long long LS, Gas<S> G, int* flags) {
+  prim_body(xcd_tile(ntiles), tiles, boxes, U, prim, LS, G, flags);
+}
+
 
 // O3 on the traced zones.
 template <class S>
-__global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ tiles, int ntiles,
-                                                  const DevBox* __restrict__ boxes,
-                                                  const S* __restrict__ prim, long long LS,
-                                                  S* __restrict__ work, long long LE, Gas<S> G) {
-  const int t = xcd_tile(ntiles);
+__device__ __forceinline__ void flatten_body(int t, const Tile* __restrict__ tiles,
+                                             const DevBox* __restrict__ boxes, const S* __restrict__ prim,
+                                             long long LS, S* __restrict__ work, long long LE, const Gas<S>& G) {
   if (t < 0) return;
   const Tile tl = tiles[t];
   const DevBox B = boxes[tl.box];
@@ -142,13 +151,20 @@ __global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ t
   work[E_FLAT * LE + B.eoff + z.e] = phi;
 }
 
+template <class S>
+__global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ tiles, int ntiles,
+                                                  const DevBox* __restrict__ boxes,
+                                                  const S* __restrict__ prim, long long LS,
+                                                  S* __restrict__ work, long long LE, Gas<S> G) {
+  flatten_body(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G);
+}
+
 // O4 + O5 for one axis (blockIdx.y) on the traced zones.
 template <int d, class S>
-__device__ __forceinline__ void trace_body(const Tile* __restrict__ tiles, int ntiles,
+__device__ __forceinline__ void trace_body(int t, const Tile* __restrict__ tiles,
                                            const DevBox* __restrict__ boxes, const S* __restrict__ prim,
                                            long long LS, S* __restrict__ work, long long LE, const Gas<S>& G,
                                            const StepConsts* __restrict__ sc, int* flags) {
-  const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const Tile tl = tiles[t];
   const DevBox B = boxes[tl.box];
@@ -184,18 +200,17 @@ __global__ void __launch_bounds__(MAX_TILE) k_trace(const Tile* __restrict__ til
                                                 S* __restrict__ work, long long LE, Gas<S> G,
                                                 const StepConsts* __restrict__ sc, int* flags) {
   switch (blockIdx.y) {
-    case 0: trace_body<0>(tiles, ntiles, boxes, prim, LS, work, LE, G, sc, flags); break;
-    case 1: trace_body<1>(tiles, ntiles, boxes, prim, LS, work, LE, G, sc, flags); break;
-    default: trace_body<2>(tiles, ntiles, boxes, prim, LS, work, LE, G, sc, flags); break;
+    case 0: trace_body<0>(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G, sc, flags); break;
+    case 1: trace_body<1>(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G, sc, flags); break;
+    default: trace_body<2>(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G, sc, flags); break;
   }
 }
 
 // O7: F^d at d-face slots x_d in [0, n], transverse in [-1, n].
 template <int d, class S>
-__device__ __forceinline__ void riemann1_body(const Tile* __restrict__ tiles, int ntiles,
+__device__ __forceinline__ void riemann1_body(int t, const Tile* __restrict__ tiles,
                                               const DevBox* __restrict__ boxes, S* __restrict__ work,
                                               long long LE, const Gas<S>& G, int* flags) {
-  const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const Tile tl = tiles[t];
   const DevBox B = boxes[tl.box];
@@ -229,9 +244,9 @@ __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(8
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    int* flags) {
   switch (blockIdx.y) {
-    case 0: riemann1_body<0>(tiles, ntiles, boxes, work, LE, G, flags); break;
-    case 1: riemann1_body<1>(tiles, ntiles, boxes, work, LE, G, flags); break;
-    default: riemann1_body<2>(tiles, ntiles, boxes, work, LE, G, flags); break;
+    case 0: riemann1_body<0>(xcd_tile(ntiles), tiles, boxes, work, LE, G, flags); break;
+    case 1: riemann1_body<1>(xcd_tile(ntiles), tiles, boxes, work, LE, G, flags); break;
+    default: riemann1_body<2>(xcd_tile(ntiles), tiles, boxes, work, LE, G, flags); break;
   }
 }
 
@@ -266,12 +281,11 @@ __device__ __forceinline__ void riemann2_pair(const S* __restrict__ w, S* __rest
 }
 
 template <int d, class S>
-__device__ __forceinline__ void riemann2_body(const Tile* __restrict__ tiles, int ntiles,
+__device__ __forceinline__ void riemann2_body(int tt, const Tile* __restrict__ tiles,
                                               const DevBox* __restrict__ boxes, S* __restrict__ work,
                                               long long LE, const Gas<S>& G,
                                               const StepConsts* __restrict__ sc, int* flags) {
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-  const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tiles[tt];
   const DevBox B = boxes[tl.box];
@@ -302,9 +316,9 @@ __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(5
                                                    S* __restrict__ work, long long LE, Gas<S> G,
                                                    const StepConsts* __restrict__ sc, int* flags) {
   switch (blockIdx.y) {
-    case 0: riemann2_body<0>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    case 1: riemann2_body<1>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
-    default: riemann2_body<2>(tiles, ntiles, boxes, work, LE, G, sc, flags); break;
+    case 0: riemann2_body<0>(xcd_tile(ntiles), tiles, boxes, work, LE, G, sc, flags); break;
+    case 1: riemann2_body<1>(xcd_tile(ntiles), tiles, boxes, work, LE, G, sc, flags); break;
+    default: riemann2_body<2>(xcd_tile(ntiles), tiles, boxes, work, LE, G, sc, flags); break;
   }
 }
 
@@ -354,12 +368,11 @@ __device__ __forceinline__ void write_flux(const DevBox& B, const int x[3], cons
 }
 
 template <int d, class S>
-__device__ __forceinline__ void riemann3_body(const Tile* __restrict__ tiles, int ntiles,
+__device__ __forceinline__ void riemann3_body(int tt, const Tile* __restrict__ tiles,
                                               const DevBox* __restrict__ boxes, S* __restrict__ work,
                                               long long LE, const Gas<S>& G,
                                               const StepConsts* __restrict__ sc, double* fx, double* fy,
                                               double* fz, int* flags) {
-  const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
   const Tile tl = tiles[tt];
@@ -385,9 +398,9 @@ __global__ void __launch_bounds__(MAX_TILE) k_riemann3(const Tile* __restrict__ 
                                                    const StepConsts* __restrict__ sc,
                                                    double* fx, double* fy, double* fz, int* flags) {
   switch (blockIdx.y) {
-    case 0: riemann3_body<0>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
-    case 1: riemann3_body<1>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
-    default: riemann3_body<2>(tiles, ntiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+    case 0: riemann3_body<0>(xcd_tile(ntiles), tiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+    case 1: riemann3_body<1>(xcd_tile(ntiles), tiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
+    default: riemann3_body<2>(xcd_tile(ntiles), tiles, boxes, work, LE, G, sc, fx, fy, fz, flags); break;
   }
 }
 
@@ -487,6 +500,22 @@ __device__ __forceinline__ double update_body(const Tile& tl, const DevBox& B, c
                            so.small_pres);
 }
 
+// The update of the valid zones of tile tt; returns the lane's signal speed
+// (0 without so.bits or off the valid zones).
+template <class S>
+__device__ __forceinline__ double update_tile(int tt, const Tile* __restrict__ tiles,
+                                              const DevBox* __restrict__ boxes, const double* __restrict__ U,
+                                              double* __restrict__ Unew, const S* __restrict__ work, long long LE,
+                                              const StepConsts* __restrict__ sc, int grav, double g0, double g1,
+                                              double g2, const SpeedOut& so) {
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  EZone z;
+  const bool valid = ezone(tl, B, z) && z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] &&
+                     z.x[2] >= 0 && z.x[2] < B.n[2];
+  return valid ? update_body(tl, B, z, U, Unew, work, LE, sc, grav, g0, g1, g2, so) : 0.0;
+}
+
 template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes,
@@ -496,13 +525,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ ti
                                                  double g0, double g1, double g2, SpeedOut so) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;  // the whole workgroup
-  const Tile tl = tiles[tt];
-  const DevBox B = boxes[tl.box];
-  EZone z;
-  const bool valid = ezone(tl, B, z) && z.x[0] >= 0 && z.x[0] < B.n[0] && z.x[1] >= 0 && z.x[1] < B.n[1] &&
-                     z.x[2] >= 0 && z.x[2] < B.n[2];
-  double smax_lane = 0.0;
-  if (valid) smax_lane = update_body(tl, B, z, U, Unew, work, LE, sc, grav, g0, g1, g2, so);
+  const double smax_lane = update_tile(tt, tiles, boxes, U, Unew, work, LE, sc, grav, g0, g1, g2, so);
   if (so.bits) block_max_to(smax_lane, so.bits);
 }
 

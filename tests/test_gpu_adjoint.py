@@ -385,6 +385,119 @@ def test_differentiation_workload_full_size_against_central_differences():
     print(f"128^3, 20 steps, 64 directions: worst relative gradient error {worst:.2e} (loss {loss:.6e})")
 
 
+def _oracle_tangent_chain(U0, v, dts, dx, gamma, m=32, threads=16):
+    """The oracle's dual-number tangent of len(dts) steps of a periodic
+    single-box level of extents n^3 (valid zones, (5, n, n, n) arrays),
+    evaluated on the same level cut into boxes of m^3 (the step is local, so
+    the cut changes no value) with one box per thread at a time."""
+    import concurrent.futures as cf
+    n = U0.shape[1]
+    k = n // m
+    lay = I.tensor_tiling([m] * k, [m] * k, [m] * k)
+    p = O.params(gamma=gamma)
+
+    def cut(A):
+        out = []
+        for b in range(lay.nbox):
+            lo = lay.lo[b]
+            a = np.zeros((5, m + 8, m + 8, m + 8))
+            a[:, 4:-4, 4:-4, 4:-4] = A[:, lo[2]:lo[2] + m, lo[1]:lo[1] + m, lo[0]:lo[0] + m]
+            out.append(a)
+        return out
+
+    def glue(bs):
+        A = np.zeros((5, n, n, n))
+        for b in range(lay.nbox):
+            lo = lay.lo[b]
+            A[:, lo[2]:lo[2] + m, lo[1]:lo[1] + m, lo[0]:lo[0] + m] = bs[b][:, 4:-4, 4:-4, 4:-4]
+        return A
+    st, dv = cut(U0), cut(v)
+    with cf.ThreadPoolExecutor(threads) as ex:
+        for dt in dts:
+            O.fill(lay.boxes(), lay.domain(), lay.bc, st)
+            O.fill(lay.boxes(), lay.domain(), lay.bc, dv)
+            res = list(ex.map(lambda b: O.step_jvp(st[b], dv[b], dt, dx, p)[:2], range(lay.nbox)))
+            st, dv = [r[0] for r in res], [r[1] for r in res]
+    return glue(st), glue(dv)
+
+
+def test_differentiation_workload_limited_full_size():
+    """The differentiation workload exactly as specified (128^3, amplitude
+    0.05, no bulk flow, limiter and flattening on, 20 steps with checkpoints
+    every 5, loss = sum of rho^2 over an 8^3 sub-block).  The checkpointed
+    roll-out gradient against the oracle's exact tangent of the same 20
+    steps (dt sequence and branch decisions frozen) along two random
+    directions, to 1e-10.  Then central differences of the GPU forward
+    along 16 directions (eps 1e-8), reported with the branch flips they
+    straddle: the limited scheme switches branches (the CW84 extremum and
+    overshoot cases, the MC slope, the tracing's wave selection where a
+    speed changes sign) everywhere in the level, so one-sided differences
+    u+ and u- disagree wherever a switch lies within eps; a direction counts
+    as flipped when they differ by more than 1e-5 of the gradient.  Bars on
+    the differences: the better one-sided difference within 5e-3 of the
+    adjoint in every direction (a one-sided difference that straddles no
+    switch converges to it), the central difference within 1e-2."""
+    wl = I.cfg4(128, amp=0.05)
+    lay = wl.layout
+    nsteps, every, lo, hi = 20, 5, 60, 68
+    loss, g, lev = _loss_and_grad(wl, nsteps, every, lo, hi)
+    p = P.params(gamma=wl.gamma)
+    dts = torch.zeros(nsteps, 2, dtype=torch.float64, device="cuda")
+    U = torch.from_numpy(wl.arena).cuda()
+    V = torch.zeros_like(U)
+    for k in range(nsteps):
+        lev.fill_boundary(U)
+        lev.compute_dt(U, wl.dx, p, out=dts[k])
+        lev.hydro_step(U, V, wl.dx, p, dt_dev=dts[k])
+        U, V = V, U
+    assert lev.check_status() == 0
+    dt_list = [float(x) for x in dts[:, 0].cpu().numpy()]
+    U0 = interior(lay.view(wl.arena, 0)).copy()
+    gi = interior(lay.view(g, 0))
+    rng = np.random.default_rng(128)
+    for i in range(2):
+        v = rng.normal(size=U0.shape)
+        print(f"oracle tangent chain, direction {i}", flush=True)
+        st, dv = _oracle_tangent_chain(U0, v, dt_list, wl.dx, wl.gamma)
+        r = st[0, lo:hi, lo:hi, lo:hi]
+        rhs = float(np.sum(2 * r * dv[0, lo:hi, lo:hi, lo:hi]))
+        lhs = float(np.sum(gi * v))
+        print(f"  <grad, v> = {lhs:.15e}, oracle tangent {rhs:.15e}, rel {abs(lhs - rhs) / abs(rhs):.2e}")
+        assert abs(lhs - rhs) <= 1e-10 * abs(rhs), (i, lhs, rhs)
+    base = torch.from_numpy(wl.arena).cuda()
+    gt = torch.from_numpy(g).cuda()
+    mask = torch.zeros_like(base)
+    lay.view(mask, 0)[:, 4:-4, 4:-4, 4:-4] = 1.0
+    A, B = torch.zeros_like(base), torch.zeros_like(base)
+
+    def loss_of(Uin):
+        nonlocal A, B
+        A.copy_(Uin)
+        for k in range(nsteps):
+            lev.fill_boundary(A)
+            lev.hydro_step(A, B, wl.dx, p, dt_dev=dts[k])
+            A, B = B, A
+        rho = A[: lay.box_size(0)].view(lay.stored_shape(0))[0]
+        sub = rho[4 + lo:4 + hi, 4 + lo:4 + hi, 4 + lo:4 + hi]
+        return float((sub * sub).sum().item())
+    L0 = loss_of(base)
+    gen = torch.Generator(device="cuda").manual_seed(1280)
+    eps = 1e-8
+    flips, worst_one, errs = 0, 0.0, []
+    for i in range(16):
+        v = torch.randn(base.shape, generator=gen, device="cuda", dtype=torch.float64) * mask
+        ad = float((gt * v).sum().item())
+        lp, lm = loss_of(base + eps * v), loss_of(base - eps * v)
+        fp, fm, fc = (lp - L0) / eps, (L0 - lm) / eps, (lp - lm) / (2 * eps)
+        flips += abs(fp - fm) > 1e-5 * abs(ad)
+        one = min(abs(fp - ad), abs(fm - ad)) / abs(ad)
+        worst_one = max(worst_one, one)
+        errs.append(abs(fc - ad) / abs(ad))
+        assert one <= 5e-3 and errs[-1] <= 1e-2, (i, fp, fm, fc, ad)
+    print(f"128^3 limited, 20 steps, 16 directions, eps {eps:g}: {flips} straddle a branch switch; central "
+          f"difference error median {np.median(errs):.2e}, max {max(errs):.2e}; best one-sided max {worst_one:.2e}")
+
+
 @pytest.mark.parametrize("with_state", [False, True])
 def test_adjoint_through_the_flux_outputs(with_state):
     """ppm_hydro_step_adjoint with flux adjoints: on a multi-box level with
