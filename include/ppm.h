@@ -387,6 +387,32 @@ int ppm_get_step_form(const ppm_ctx* ctx, int32_t* fused);
 int ppm_set_stream_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz);
 int ppm_get_stream_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz);
 
+/* Form of the step's front end, the PPM reconstruction with characteristic
+ * tracing (paper Sec. 1's explicit advance; O4, O5) and the normal-predictor
+ * Riemann solves (O7).  form 0 (default): two staged kernels, the tracing
+ * writing the traced face states to the workspace and the solves reading
+ * them back.  form 1: one kernel whose workgroups each own an x-y tile of a
+ * box's traced zones and walk it through a run of z planes; per plane each
+ * zone is traced along the three axes (a lane per zone and axis) and the
+ * stage-1 problems on its low faces solved after a barrier, the x and y
+ * neighbours' states exchanged through LDS and the z neighbour's kept in
+ * registers from the plane before, so the traced states are written (later
+ * stages read them) but not read back.
+ * Results are identical bit for bit in both forms (also for the adjoint's
+ * recompute and the species step, which run the same front end).  Tiles:
+ * ppm_set_front_tiling.  The autotuner picks the form and the tile. */
+int ppm_set_front_form(ppm_ctx* ctx, int32_t form);
+int ppm_get_front_form(const ppm_ctx* ctx, int32_t* form);
+/* Tile of the streamed front end: at most sx x sy traced zones in x-y and
+ * runs of at most sz planes in z, each box's traced grid cut as evenly as
+ * possible (sx, sy, sz >= 1, sx * sy <= 128, sx + sy <= 128: the workgroup
+ * has a group of lanes per axis, one per zone of the tile, and one group
+ * for the rows and columns of its low edges, each group whole wavefronts,
+ * up to 512 lanes).  Default 16 x 8 x 32.  Synchronises the device (the
+ * tile list is rebuilt).  PPM_EINVAL otherwise. */
+int ppm_set_front_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz);
+int ppm_get_front_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz);
+
 /* Diagnostic: out[i] = one of the FP64 square roots the Riemann solver
  * takes, computed on the device for n arguments x[i].  form 0: the root of
  * the wave-speed factor 1 + beta (p/p_s - 1) (>= 1 - beta > 0; the

@@ -377,6 +377,46 @@ void build_bricks(ppm_ctx& c) {
 }
 
 
+// Tiles of the streamed front end: per box, the traced grid (zones -1..n
+// per axis) cut into x-y tiles of at most front_e[0] x front_e[1] zones and
+// z runs of at most front_e[2] planes, the pieces along each axis as even
+// as possible (so no tile is a thin remainder).
+void build_front(ppm_ctx& c) {
+  c.fbricks.clear();
+  c.tF_begin.assign(1, 0);
+  c.front_m[0] = c.front_m[1] = 1;
+  for (int b = 0; b < c.layout.nbox; ++b) {
+    std::vector<int> org[3], ext[3];
+    for (int d = 0; d < 3; ++d) {
+      const int E = c.boxes[b].hi[d] - c.boxes[b].lo[d] + 3;
+      const int k = (E + c.front_e[d] - 1) / c.front_e[d];
+      int o = -1;
+      for (int p = 0; p < k; ++p) {
+        const int e = E / k + (p < E % k ? 1 : 0);
+        org[d].push_back(o);
+        ext[d].push_back(e);
+        o += e;
+      }
+    }
+    for (size_t z = 0; z < org[2].size(); ++z)
+      for (size_t y = 0; y < org[1].size(); ++y)
+        for (size_t x = 0; x < org[0].size(); ++x) {
+          Brick K;
+          K.box = b;
+          K.o[0] = org[0][x];
+          K.o[1] = org[1][y];
+          K.o[2] = org[2][z];
+          K.e[0] = ext[0][x];
+          K.e[1] = ext[1][y];
+          K.e[2] = ext[2][z];
+          c.front_m[0] = std::max(c.front_m[0], K.e[0]);
+          c.front_m[1] = std::max(c.front_m[1], K.e[1]);
+          c.fbricks.push_back(K);
+        }
+    c.tF_begin.push_back((int)c.fbricks.size());
+  }
+}
+
 void build_tiles(ppm_ctx& c) {
   c.tilesS.clear();
   c.tilesE.clear();
@@ -401,6 +441,13 @@ template <class T> hipError_t upload(T** dst, const std::vector<T>& v) {
 }
 
 // Rebuilds and uploads the block list of the current final-stage form.
+hipError_t upload_front(ppm_ctx& c) {
+  build_front(c);
+  (void)hipFree(c.d_fbricks);
+  c.d_fbricks = nullptr;
+  return upload(&c.d_fbricks, c.fbricks);
+}
+
 hipError_t upload_bricks(ppm_ctx& c) {
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return e;
@@ -549,8 +596,10 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
   }
   build_tiles(*ctx);
   build_bricks(*ctx);
+  build_front(*ctx);
   hipError_t e;
   if ((e = upload(&ctx->d_bricks, ctx->bricks)) != hipSuccess ||
+      (e = upload(&ctx->d_fbricks, ctx->fbricks)) != hipSuccess ||
       (e = upload(&ctx->d_inv_start, inv_start)) != hipSuccess ||
       (e = upload(&ctx->d_inv_idx, inv_idx)) != hipSuccess ||
       (e = upload(&ctx->d_boxes, db)) != hipSuccess ||
@@ -582,6 +631,7 @@ int ppm_ctx_destroy(ppm_ctx* ctx) {
   (void)hipFree(ctx->d_tilesS);
   (void)hipFree(ctx->d_tilesE);
   (void)hipFree(ctx->d_bricks);
+  (void)hipFree(ctx->d_fbricks);
   (void)hipFree(ctx->d_desc);
   (void)hipFree(ctx->d_start);
   (void)hipFree(ctx->d_consts);
@@ -710,21 +760,21 @@ static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* 
     if (rc) return rc;
   }
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
-  auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, hipEvent_t* ev) {
-    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
+  auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, int tF0, int tF1, hipEvent_t* ev) {
+    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, U, Unew, flux, work,
                                 params->gamma, params->small_dens, params->small_pres, params->limiter,
                                 params->flattening, params->riemann_iters, grav, params->grav, s, ev, upto, so),
                     "step");
   };
   if (mode == PPM_LAUNCH_BATCHED) {
     ppm_ctx::ProfRec* r = (timed && ctx->prof) ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
-    rc = run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(),
-             r ? r->ev.data() : nullptr);
+    rc = run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(), 0,
+             (int)ctx->fbricks.size(), r ? r->ev.data() : nullptr);
     if (rc) return rc;
   } else {
     for (int b = 0; b < ctx->layout.nbox; ++b) {
       rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], ctx->tB_begin[b],
-               ctx->tB_begin[b + 1], nullptr);
+               ctx->tB_begin[b + 1], ctx->tF_begin[b], ctx->tF_begin[b + 1], nullptr);
       if (rc) return rc;
     }
   }
@@ -801,6 +851,40 @@ int ppm_set_stream_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz) {
   return PPM_OK;
 }
 
+int ppm_set_front_form(ppm_ctx* ctx, int32_t form) {
+  if (!ctx) return PPM_EINVAL;
+  if (form != 0 && form != 1) return ctx->fail(PPM_EINVAL, "set_front_form: form must be 0 or 1");
+  if (form != ctx->front) ++ctx->gen;
+  ctx->front = form;
+  return PPM_OK;
+}
+
+int ppm_get_front_form(const ppm_ctx* ctx, int32_t* form) {
+  if (!ctx || !form) return PPM_EINVAL;
+  *form = ctx->front;
+  return PPM_OK;
+}
+
+int ppm_set_front_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz) {
+  if (!ctx) return PPM_EINVAL;
+  if (sx < 1 || sy < 1 || sz < 1 || sx > FRONT_MAX_THREADS || sy > FRONT_MAX_THREADS ||
+      front_threads(sx, sy) > FRONT_MAX_THREADS)
+    return ctx->fail(PPM_EINVAL, "set_front_tiling: need sx, sy, sz >= 1, sx * sy <= 128 and sx + sy <= 128");
+  ++ctx->gen;
+  ctx->front_e[0] = sx;
+  ctx->front_e[1] = sy;
+  ctx->front_e[2] = sz;
+  return ctx->hip(upload_front(*ctx), "set_front_tiling");
+}
+
+int ppm_get_front_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz) {
+  if (!ctx || !sx || !sy || !sz) return PPM_EINVAL;
+  *sx = ctx->front_e[0];
+  *sy = ctx->front_e[1];
+  *sz = ctx->front_e[2];
+  return PPM_OK;
+}
+
 int ppm_get_stream_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz) {
   if (!ctx || !sx || !sy || !sz) return PPM_EINVAL;
   *sx = ctx->stream_e[0];
@@ -862,7 +946,8 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, c
   // recompute the forward intermediates through stage 2 (U is not written),
   // unless the workspace holds them from the forward step
   if (recompute) {
-    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, 0, 0, U, nullptr, nullptr, ctx->work,
+    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, 0, 0, 0, (int)ctx->fbricks.size(), U, nullptr,
+                              nullptr, ctx->work,
                               params->gamma, params->small_dens, params->small_pres, params->limiter,
                               params->flattening, params->riemann_iters, grav, params->grav, s, nullptr,
                               STEP_TO_STAGE2),
@@ -1098,8 +1183,11 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
       se[0] = field("sx", ctx->stream_e[0]);
       se[1] = field("sy", ctx->stream_e[1]);
       se[2] = field("sz", ctx->stream_e[2]);
+      const int front = field("front", 0);
+      const int fe[3] = {field("fx", ctx->front_e[0]), field("fy", ctx->front_e[1]), field("fz", ctx->front_e[2])};
       if (ppm_set_tiling(ctx, t, sr) == PPM_OK && ppm_set_stream_tiling(ctx, se[0], se[1], se[2]) == PPM_OK &&
-          ppm_set_step_form(ctx, form) == PPM_OK) {
+          ppm_set_step_form(ctx, form) == PPM_OK && ppm_set_front_tiling(ctx, fe[0], fe[1], fe[2]) == PPM_OK &&
+          ppm_set_front_form(ctx, front) == PPM_OK) {
         if (tile) *tile = t;
         if (strip_rows) *strip_rows = sr;
         if (from_cache) *from_cache = 1;
@@ -1118,6 +1206,7 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
   (void)hipEventCreate(&e1);
   const int tiles[] = {128, 256, 512};
   const int strips[] = {8, 16, 32, 64, 0};
+  (void)ppm_set_front_form(ctx, 0);  // tiling and final stage timed with the staged front end
   float best = 1e30f;
   int bt = ctx->tile, bs = ctx->strip_rows;
   int rc = PPM_OK;
@@ -1180,20 +1269,43 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
       if ((rc = ppm_set_step_form(ctx, 0))) break;
     }
   }
+  // then the front end, with the final stage chosen: staged, or streamed
+  // with one of its tile shapes
+  static const int fshapes[][3] = {{11, 11, 32}, {16, 8, 32}};
+  int bfront = 0, bfe[3] = {ctx->front_e[0], ctx->front_e[1], ctx->front_e[2]};
+  const int front0 = ctx->front;
+  if (!rc && !(rc = ppm_set_stream_tiling(ctx, bse[0], bse[1], bse[2])) && !(rc = ppm_set_step_form(ctx, bform))) {
+    float ms = 0.f;
+    for (const auto& sh : fshapes) {
+      if ((rc = ppm_set_front_tiling(ctx, sh[0], sh[1], sh[2])) || (rc = ppm_set_front_form(ctx, 1)) ||
+          (rc = timed(ms)))
+        break;
+      if (ms < best) {
+        best = ms;
+        bfront = 1;
+        for (int d = 0; d < 3; ++d) bfe[d] = sh[d];
+      }
+    }
+    if (!rc) rc = ppm_set_front_form(ctx, 0);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(dtv);
   if (rc) {
     (void)ppm_set_step_form(ctx, form0);
+    (void)ppm_set_front_form(ctx, front0);
     return rc;
   }
-  if ((rc = ppm_set_stream_tiling(ctx, bse[0], bse[1], bse[2])) || (rc = ppm_set_step_form(ctx, bform))) return rc;
+  if ((rc = ppm_set_stream_tiling(ctx, bse[0], bse[1], bse[2])) || (rc = ppm_set_step_form(ctx, bform)) ||
+      (rc = ppm_set_front_tiling(ctx, bfe[0], bfe[1], bfe[2])) || (rc = ppm_set_front_form(ctx, bfront)))
+    return rc;
   if (tile) *tile = bt;
   if (strip_rows) *strip_rows = bs;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"tile\": " << bt << ", \"strip_rows\": " << bs
         << ", \"form\": " << bform << ", \"sx\": " << bse[0] << ", \"sy\": " << bse[1] << ", \"sz\": " << bse[2]
+        << ", \"front\": " << bfront << ", \"fx\": " << bfe[0] << ", \"fy\": " << bfe[1] << ", \"fz\": " << bfe[2]
         << ", \"ms_per_step\": " << best << "}\n";
   }
   return PPM_OK;

@@ -40,6 +40,14 @@ struct ppm_ctx {
   std::vector<int> tB_begin;            // nbox + 1
   int fused = 0;                        // 1: final fluxes + update in one brick kernel; 2: streamed
   int stream_e[3] = {16, 8, 32};        // tile extents of the streamed final stage
+  // front end: 0 trace and stage-1 solves as two staged kernels; 1 one
+  // kernel streamed along z over x-y tiles of the traced grids (fbricks,
+  // at most front_e zones per axis, balanced per box)
+  int front = 0;
+  int front_e[3] = {16, 8, 32};
+  std::vector<Brick> fbricks;
+  std::vector<int> tF_begin;            // nbox + 1
+  int front_m[2] = {1, 1};              // largest x, y extents of the front tiles
   int device = -1;                      // HIP device current at ppm_ctx_create
   // Generation of the device state a captured graph bakes in (workspace,
   // tile lists, step form, inflow states): bumped whenever one changes; a
@@ -53,6 +61,7 @@ struct ppm_ctx {
   Tile* d_tilesS = nullptr;
   Tile* d_tilesE = nullptr;
   Brick* d_bricks = nullptr;
+  Brick* d_fbricks = nullptr;
   FillDesc* d_desc = nullptr;
   long long* d_start = nullptr;
   int* d_inv_start = nullptr;
@@ -109,6 +118,10 @@ struct ppm_ctx {
     L.bricks = d_bricks;
     L.fused = fused;
     for (int d = 0; d < 3; ++d) L.stream_e[d] = stream_e[d];
+    L.fbricks = d_fbricks;
+    L.front = front;
+    L.front_m[0] = front_m[0];
+    L.front_m[1] = front_m[1];
     return L;
   }
   int fail(int code, const std::string& msg) {

@@ -42,6 +42,15 @@ constexpr int BRICK_THREADS = 512;
 // at most 256); a workgroup of twice as many lanes (at most 512) works
 // through the plane's 3 sx sy + sx + sy face solves.
 constexpr int STREAM_MAX_THREADS = 512;
+// streamed front end: a group of lanes per axis, one per zone of an x-y
+// tile, and a group for the rows and columns of its low edges, each group
+// in whole wavefronts
+constexpr int FRONT_MAX_THREADS = 512;
+__host__ __device__ inline int front_group(int mx, int my) {
+  const int a = mx * my > mx + my ? mx * my : mx + my;
+  return ((a + 63) / 64) * 64;
+}
+inline int front_threads(int mx, int my) { return 4 * front_group(mx, my); }
 inline int stream_threads(int sx, int sy) { return 2 * sx * sy < STREAM_MAX_THREADS ? 2 * sx * sy : STREAM_MAX_THREADS; }
 // faces of the largest axis of a full brick (LDS slots per axis and component)
 constexpr int BRICK_FACES_D(int d) {
@@ -118,6 +127,9 @@ struct DevLevel {
   int fused;            // 1: final fluxes and update in one brick kernel (fluxes kept in LDS);
                         // 2: the same in x-y tiles streamed along z (ppm_kernels.hip, k_final_stream)
   int stream_e[3];      // form 2: x, y extents of a tile (threads = product) and the z run
+  const Brick* fbricks; // traced-grid x-y tiles with z runs (streamed front end)
+  int front;            // 1: trace + stage-1 solves in one kernel streamed along z (k_front_stream)
+  int front_m[2];       // largest x, y extents of the front tiles (LDS layout, lanes)
 };
 
 }  // namespace ppm
@@ -133,8 +145,8 @@ hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_en
 hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, const double* U,
                              const double h[3], double gamma, double small_pres, double cfl,
                              double* dt_dev, hipStream_t s);
-// The step stages over E-tiles [tE0, tE1), S-tiles [tS0, tS1) and bricks
-// [tB0, tB1).  upto: STEP_TO_STAGE2 (prim..riemann2, for the adjoint's
+// The step stages over E-tiles [tE0, tE1), S-tiles [tS0, tS1), bricks
+// [tB0, tB1) and front tiles [tF0, tF1).  upto: STEP_TO_STAGE2 (prim..riemann2, for the adjoint's
 // recompute), STEP_FULL (the whole step; the fused final stage when the
 // level asks for it), STEP_FULL_STAGED (the whole step with the final
 // fluxes left in the workspace, as the species stages need).
@@ -149,6 +161,7 @@ struct SpeedOut {
 };
 
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
+                       int tF0, int tF1,
                        const double* U, double* Unew, double* const* flux, void* work,
                        const double gamma, const double small_dens, const double small_pres,
                        int limiter, int flattening, int iters, int grav, const double g[3],

@@ -159,6 +159,39 @@ __global__ void __launch_bounds__(MAX_TILE) k_flatten(const Tile* __restrict__ t
   flatten_body(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G);
 }
 
+// O4 + O5 along axis d for zone (x, y, z) of box B (e: its index in the
+// traced grid): the states at the zone's high (qp) and low (qm) d faces.
+template <int d, class S>
+__device__ __forceinline__ void trace_at(const DevBox& B, int x, int y, int z, long long e,
+                                         const S* __restrict__ prim, long long LS, const S* __restrict__ work,
+                                         long long LE, const Gas<S>& G, const StepConsts* __restrict__ sc, S qp[5],
+                                         S qm[5], int& fl) {
+  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
+  const long long base = pidx(B, x, y, z);
+  const long long st = stride(NS, d);
+  const S phi = work[E_FLAT * LE + B.eoff + e];
+  S aL[5], aR[5], a6[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const S* a = prim + m * LS + base;
+    ppm_parabola(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, G, aL[m], aR[m], a6[m]);
+  }
+  const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
+  trace_zone<d>(aL, aR, a6, r, un, c, SC<S>::dtdx(sc)[d], G, SC<S>::hdtg(sc), qp, qm, fl);
+}
+
+// Traced states of zone e along d into the workspace planes.
+template <int d, class S>
+__device__ __forceinline__ void store_traced(S* __restrict__ work, long long LE, const DevBox& B, long long e,
+                                             const S qp[5], const S qm[5]) {
+  S* w = work + B.eoff + e;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE] = qp[m];
+    w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE] = qm[m];
+  }
+}
+
 // O4 + O5 for one axis (blockIdx.y) on the traced zones.
 template <int d, class S>
 __device__ __forceinline__ void trace_body(int t, const Tile* __restrict__ tiles,
@@ -170,26 +203,10 @@ __device__ __forceinline__ void trace_body(int t, const Tile* __restrict__ tiles
   const DevBox B = boxes[tl.box];
   EZone z;
   if (!ezone(tl, B, z)) return;
-  const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
-  const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
-  const long long st = stride(NS, d);
-  const S phi = work[E_FLAT * LE + B.eoff + z.e];
-  S aL[5], aR[5], a6[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const S* a = prim + m * LS + base;
-    ppm_parabola(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, G, aL[m], aR[m], a6[m]);
-  }
-  const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
   S qp[5], qm[5];
   int fl = 0;
-  trace_zone<d>(aL, aR, a6, r, un, c, SC<S>::dtdx(sc)[d], G, SC<S>::hdtg(sc), qp, qm, fl);
-  S* w = work + B.eoff + z.e;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE] = qp[m];
-    w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE] = qm[m];
-  }
+  trace_at<d>(B, z.x[0], z.x[1], z.x[2], z.e, prim, LS, work, LE, G, sc, qp, qm, fl);
+  store_traced<d>(work, LE, B, z.e, qp, qm);
   raise_flags(flags, fl);
 }
 
@@ -206,6 +223,20 @@ __global__ void __launch_bounds__(MAX_TILE) k_trace(const Tile* __restrict__ til
   }
 }
 
+// O7 on the d face at slot xd (between zones xd - 1 and xd along d) whose
+// high-side zone has traced-grid index e: L, R the traced states on its two
+// sides (overwritten), the flux into the stage-1 plane.
+template <int d, class S>
+__device__ __forceinline__ void stage1_face(const DevBox& B, int xd, S L[5], S R[5], const Gas<S>& G,
+                                            S* __restrict__ work, long long LE, long long e, int& fl) {
+  S F[5];
+  wall_states<d>(B, xd, L, R);
+  riemann<d>(L, R, G, F, fl);
+  S* f = work + B.eoff + e;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) f[(E_F1 + d * 5 + m) * LE] = F[m];
+}
+
 // O7: F^d at d-face slots x_d in [0, n], transverse in [-1, n].
 template <int d, class S>
 __device__ __forceinline__ void riemann1_body(int t, const Tile* __restrict__ tiles,
@@ -219,18 +250,14 @@ __device__ __forceinline__ void riemann1_body(int t, const Tile* __restrict__ ti
   if (z.x[d] < 0) return;
   const long long st = stride(z.E, d);
   const S* w = work + B.eoff + z.e;
-  S L[5], R[5], F[5];
+  S L[5], R[5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     L[m] = w[(E_TRACE + (d * 2 + 0) * 5 + m) * LE - st];
     R[m] = w[(E_TRACE + (d * 2 + 1) * 5 + m) * LE];
   }
   int fl = 0;
-  wall_states<d>(B, z.x[d], L, R);
-  riemann<d>(L, R, G, F, fl);
-  S* f = work + B.eoff + z.e;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) f[(E_F1 + d * 5 + m) * LE] = F[m];
+  stage1_face<d>(B, z.x[d], L, R, G, work, LE, z.e, fl);
   raise_flags(flags, fl);
 }
 
@@ -250,6 +277,118 @@ __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(8
   }
 }
 
+
+// O4-O7 fused and streamed along z: a workgroup owns an x-y tile of
+// ex x ey zones of the traced grid and walks it through a run of z planes.
+// It has a group of lanes per axis (whole wavefronts; lane r of group d
+// owns zone r of the tile along d) and one group tracing the zones just
+// below the tile's low x and y edges.  Per plane each owner lane traces its
+// zone along its axis (the traced states still go to the workspace: the
+// later stages read them), the x and y lanes put the high-face state into
+// LDS, and after a barrier each owner lane solves the stage-1 problem on its
+// zone's low face: the x and y neighbours' states from LDS, the z
+// neighbour's from the lane's own registers (the plane below; the run's
+// first plane traces the plane below it once more).  This stage never reads
+// the traced states back.  The arithmetic is trace_at and stage1_face, so
+// the results are the staged trace and riemann1 kernels' bit for bit.
+// mx, my: the largest tile extents of the list (LDS layout and lane groups).
+template <int d, class S>
+__device__ __forceinline__ void front_plane_trace(const DevBox& B, int x, int y, int z, long long e,
+                                                  const S* __restrict__ prim, long long LS, S* __restrict__ work,
+                                                  long long LE, const Gas<S>& G, const StepConsts* __restrict__ sc,
+                                                  S qp[5], S qm[5], int& fl) {
+  trace_at<d>(B, x, y, z, e, prim, LS, work, LE, G, sc, qp, qm, fl);
+  store_traced<d>(work, LE, B, e, qp, qm);
+}
+
+template <class S>
+__global__ void __launch_bounds__(FRONT_MAX_THREADS) k_front_stream(
+    const Brick* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes, const S* __restrict__ prim,
+    long long LS, S* __restrict__ work, long long LE, Gas<S> G, const StepConsts* __restrict__ sc, int mx, int my,
+    int* flags) {
+  extern __shared__ unsigned char smem_raw[];
+  const int k = xcd_tile(ntiles);
+  if (k < 0) return;  // the whole workgroup
+  const Brick K = tiles[k];  // o: the tile's first zone (traced grid, from -1); e: extents
+  const DevBox B = boxes[K.box];
+  const int PXN = (mx + 1) * my, PYN = mx * (my + 1);
+  S* Px = (S*)smem_raw;  // [m][j][i + 1], i in [-1, ex): high x-face states of row j
+  S* Py = Px + 5 * PXN;  // [m][j + 1][i], j in [-1, ey): high y-face states of column i
+  const int ex = K.e[0], ey = K.e[1], nown = ex * ey;
+  const int E0 = B.n[0] + 2, E1 = B.n[1] + 2;
+  const int A = front_group(mx, my);
+  const int g = threadIdx.x / A, r = threadIdx.x - g * A;
+  // group 0-2: owner of zone (i, j) along axis g; group 3: the x halo of
+  // row j (zone i = -1) or the y halo of column i (zone j = -1)
+  bool act = false;
+  int i = 0, j = 0;
+  if (g < 3) {
+    act = r < nown;
+    j = act ? r / ex : 0;
+    i = act ? r - j * ex : 0;
+  } else if (r < ey) {
+    act = K.o[0] >= 0;
+    j = r;
+    i = -1;
+  } else if (r < ey + ex) {
+    act = K.o[1] >= 0;
+    i = r - ey;
+    j = -1;
+  }
+  const int x = K.o[0] + i, y = K.o[1] + j;
+  const bool hx = g == 3 && i < 0;
+  int fl = 0;
+  S qz[5];  // z lanes: high z-face state of the zone below
+  if (g == 2 && act && K.o[2] >= 0) {
+    const int z = K.o[2] - 1;
+    S qm[5];
+    trace_at<2>(B, x, y, z, ((long long)(z + 1) * E1 + (y + 1)) * E0 + (x + 1), prim, LS, work, LE, G, sc, qz, qm,
+                fl);
+  }
+  for (int kz = 0; kz < K.e[2]; ++kz) {
+    const int z = K.o[2] + kz;
+    const long long e = ((long long)(z + 1) * E1 + (y + 1)) * E0 + (x + 1);
+    S qp[5], qm[5];
+    if (act) {
+      if (g == 0 || hx) {
+        trace_at<0>(B, x, y, z, e, prim, LS, work, LE, G, sc, qp, qm, fl);
+        if (g == 0) store_traced<0>(work, LE, B, e, qp, qm);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) Px[m * PXN + j * (mx + 1) + i + 1] = qp[m];
+      } else if (g == 1 || g == 3) {
+        trace_at<1>(B, x, y, z, e, prim, LS, work, LE, G, sc, qp, qm, fl);
+        if (g == 1) store_traced<1>(work, LE, B, e, qp, qm);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) Py[m * PYN + (j + 1) * mx + i] = qp[m];
+      } else {
+        front_plane_trace<2>(B, x, y, z, e, prim, LS, work, LE, G, sc, qp, qm, fl);
+      }
+    }
+    __syncthreads();
+    if (act && g < 3) {
+      S L[5];
+      if (g == 0) {
+        if (x >= 0) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) L[m] = Px[m * PXN + j * (mx + 1) + i];
+          stage1_face<0>(B, x, L, qm, G, work, LE, e, fl);
+        }
+      } else if (g == 1) {
+        if (y >= 0) {
+#pragma unroll
+          for (int m = 0; m < 5; ++m) L[m] = Py[m * PYN + j * mx + i];
+          stage1_face<1>(B, y, L, qm, G, work, LE, e, fl);
+        }
+      } else {
+        if (z >= 0) stage1_face<2>(B, z, qz, qm, G, work, LE, e, fl);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) qz[m] = qp[m];
+      }
+    }
+    __syncthreads();  // before the next plane's states overwrite the LDS
+  }
+  raise_flags(flags, fl);
+}
 
 // O8: for axis d = blockIdx.y, both pairs (d, t1) and (d, t2) in one lane:
 // the traced states of axis d are loaded once, corrected by the stage-1
@@ -805,7 +944,8 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restric
 
 
 template <class S>
-hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, const double* U,
+hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, int tF0, int tF1,
+                     const double* U,
                      double* Unew, double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
                      hipEvent_t* ev, int upto, const SpeedOut& so) {
   S* prim = (S*)work;
@@ -820,12 +960,24 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
   if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_flatten<S>, dim3(xcd_grid(nE)), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework, L.LE, G);
   if (ev) (void)hipEventRecord(ev[2], s);
-  hipLaunchKernelGGL(k_trace<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework, L.LE,
-                     G, L.consts, L.flags);
-  if (ev) (void)hipEventRecord(ev[3], s);
-  hipLaunchKernelGGL(k_riemann1<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
-                     L.flags);
-  if (ev) (void)hipEventRecord(ev[4], s);
+  const int nF = tF1 - tF0;
+  if (L.front == 1 && nF > 0) {
+    // trace and stage-1 solves in one kernel (timed in the trace slot)
+    const int mx = L.front_m[0], my = L.front_m[1];
+    const size_t lds = sizeof(S) * 5 * (size_t)((mx + 1) * my + mx * (my + 1));
+    hipLaunchKernelGGL(k_front_stream<S>, dim3(xcd_grid(nF)), dim3(front_threads(mx, my)), lds, s,
+                       L.fbricks + tF0, nF, L.boxes, (const S*)prim, L.LS, ework, L.LE, G, L.consts, mx, my,
+                       L.flags);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    if (ev) (void)hipEventRecord(ev[4], s);
+  } else {
+    hipLaunchKernelGGL(k_trace<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework, L.LE,
+                       G, L.consts, L.flags);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    hipLaunchKernelGGL(k_riemann1<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
+                       L.flags);
+    if (ev) (void)hipEventRecord(ev[4], s);
+  }
   hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
                      L.consts, L.flags);
   if (upto <= STEP_TO_STAGE2) return hipGetLastError();
@@ -929,15 +1081,15 @@ hipError_t launch_sqrt_form(const double* x, double* out, long long n, int form,
 }
 
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
-                       const double* U, double* Unew, double* const* flux, void* work, const double gamma,
-                       const double small_dens, const double small_pres, int limiter, int flattening,
-                       int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev, int upto,
-                       SpeedOut so) {
+                       int tF0, int tF1, const double* U, double* Unew, double* const* flux, void* work,
+                       const double gamma, const double small_dens, const double small_pres, int limiter,
+                       int flattening, int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev,
+                       int upto, SpeedOut so) {
   if (precision == 1)
-    return step_impl<float>(L, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
+    return step_impl<float>(L, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, U, Unew, flux, work,
                             make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                             g, s, ev, upto, so);
-  return step_impl<double>(L, tS0, tS1, tE0, tE1, tB0, tB1, U, Unew, flux, work,
+  return step_impl<double>(L, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, U, Unew, flux, work,
                            make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                            g, s, ev, upto, so);
 }

@@ -33,7 +33,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
            "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
            "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt", "ppm_hydro_step_noalloc",
-           "ppm_set_stream_tiling", "ppm_get_stream_tiling")
+           "ppm_set_stream_tiling", "ppm_get_stream_tiling", "ppm_set_front_form", "ppm_get_front_form",
+           "ppm_set_front_tiling", "ppm_get_front_tiling")
 NOALLOC_SCRATCH_BYTES = 128 << 20
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
@@ -127,6 +128,10 @@ def lib():
         L.ppm_get_step_form.argtypes = [_vp, _i32p]
         L.ppm_set_stream_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.ppm_get_stream_tiling.argtypes = [_vp, _i32p, _i32p, _i32p]
+        L.ppm_set_front_form.argtypes = [_vp, ctypes.c_int32]
+        L.ppm_get_front_form.argtypes = [_vp, _i32p]
+        L.ppm_set_front_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.ppm_get_front_tiling.argtypes = [_vp, _i32p, _i32p, _i32p]
         L.ppm_sqrt_values.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
         L.ppm_quotient_values.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
@@ -393,6 +398,24 @@ class Level:
 
     def set_stream_tiling(self, sx, sy, sz):
         self._check(lib().ppm_set_stream_tiling(self.ctx, int(sx), int(sy), int(sz)), "ppm_set_stream_tiling")
+
+    def set_front_form(self, form):
+        """0: trace and stage-1 solves as two staged kernels; 1: one kernel
+        streamed along z (ppm_set_front_form)."""
+        self._check(lib().ppm_set_front_form(self.ctx, int(form)), "ppm_set_front_form")
+
+    def get_front_form(self):
+        v = ctypes.c_int32()
+        self._check(lib().ppm_get_front_form(self.ctx, ctypes.byref(v)), "ppm_get_front_form")
+        return v.value
+
+    def set_front_tiling(self, sx, sy, sz):
+        self._check(lib().ppm_set_front_tiling(self.ctx, int(sx), int(sy), int(sz)), "ppm_set_front_tiling")
+
+    def get_front_tiling(self):
+        v = [ctypes.c_int32() for _ in range(3)]
+        self._check(lib().ppm_get_front_tiling(self.ctx, *[ctypes.byref(x) for x in v]), "ppm_get_front_tiling")
+        return tuple(x.value for x in v)
 
     def get_stream_tiling(self):
         v = [ctypes.c_int32() for _ in range(3)]

@@ -318,6 +318,32 @@ def test_saved_intermediates_adjoint_equals_the_recomputing_one(precision):
     assert torch.equal(A, B)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adjoint_with_streamed_front_end_is_bitwise_the_same(precision):
+    """The adjoint's recompute of the forward intermediates runs the level's
+    front end: the streamed form gives the staged form's U_bar bit for bit
+    (walls, gravity, several boxes)."""
+    wl = CASES["walls_gravity"]()
+    w = _valid_random(wl.layout, np.random.default_rng(31))
+    dt = _dt(wl)
+    outs = []
+    for front in (0, 1):
+        lay = wl.layout
+        lev = P.Level(lay)
+        if front:
+            lev.set_front_tiling(8, 4, 5)
+            lev.set_front_form(1)
+        p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+        U = torch.from_numpy(wl.arena).cuda()
+        lev.fill_boundary(U)
+        Ub = torch.full_like(U, float("nan"))
+        lev.hydro_step_adjoint(U, torch.from_numpy(w).cuda(), Ub, wl.dx, p, dt=dt)
+        outs.append(Ub.cpu().numpy())
+        assert lev.check_status() == 0
+        lev.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_rollout_with_saved_segments_equals_recompute_bitwise():
     """The roll-out backward that keeps one workspace per segment step gives
     the recomputing backward's gradient bit for bit (5 steps, checkpoints

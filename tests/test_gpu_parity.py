@@ -468,6 +468,67 @@ def test_final_stage_forms_agree_bitwise(precision):
             assert np.array_equal(a, r), k
 
 
+FRONT_FORMS = [(16, 8, 32), (4, 4, 3), (11, 11, 5), (64, 2, 64), (7, 3, 7), (1, 1, 1), (1, 127, 2)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_front_forms_agree_bitwise(precision):
+    """The streamed front end (trace and stage-1 solves in one kernel, x-y
+    tiles walked along z) with tiles larger and smaller than the boxes,
+    single-zone tiles and runs that split the boxes' z extent unevenly, in
+    both launch forms and with the streamed final stage too, gives the
+    staged front end's state, flux output and next dt bit for bit: uneven
+    boxes, walls, gravity."""
+    wl = _uneven_level(seed=9, bc=(0, 0, 1, 1, 2, 2), sizes=(6, 8, 12, 20))
+    wl.grav = (0.0, 0.0, -1.0)
+    wl.precision = precision
+    cases = [(None, 0, P.BATCHED)] + [(sh, 0, P.BATCHED) for sh in FRONT_FORMS] + \
+        [(FRONT_FORMS[1], 0, P.PER_BOX), (FRONT_FORMS[0], 2, P.BATCHED), (FRONT_FORMS[3], 1, P.PER_BOX)]
+    outs = []
+    for shape, final, mode in cases:
+        print(f"front tile {shape}, final-stage form {final}, mode {mode}, precision {precision}", flush=True)
+        lev = P.Level(wl.layout)
+        if shape:
+            lev.set_front_tiling(*shape)
+            lev.set_front_form(1)
+            assert lev.get_front_form() == 1 and lev.get_front_tiling() == shape
+        lev.set_step_form(final)
+        U = torch.from_numpy(wl.arena).cuda()
+        V = lev.new_state()
+        p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
+        dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
+        lev.compute_dt(U, wl.dx, p, out=dtv)
+        F, dts = None, []
+        for _ in range(2):
+            lev.fill_boundary(U, mode)
+            F = lev.new_fluxes()
+            lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv, fluxes=F, mode=mode, dt_next=dtv)
+            dts.append(dtv.cpu().numpy().copy())
+            U, V = V, U
+        assert lev.check_status() == 0
+        outs.append((U.cpu().numpy(), [f.cpu().numpy() for f in F], dts))
+        lev.close()
+    ref_u, ref_f, ref_dt = outs[0]
+    lay = wl.layout
+    for k, (u, f, dts) in enumerate(outs[1:]):
+        for b in range(lay.nbox):
+            assert np.array_equal(interior(lay.view(u, b)), interior(lay.view(ref_u, b))), (k, b)
+        for d in range(3):
+            assert np.array_equal(f[d], ref_f[d]), (k, d)
+        for a, r in zip(dts, ref_dt):
+            assert np.array_equal(a, r), k
+
+
+def test_front_tiling_rejects_oversized_tiles():
+    wl = _uneven_level(seed=9)
+    lev = P.Level(wl.layout)
+    with pytest.raises(P.PPMError, match="front_tiling"):
+        lev.set_front_tiling(16, 16, 8)  # 256 zones per tile
+    with pytest.raises(P.PPMError, match="front_form"):
+        lev.set_front_form(2)
+    lev.close()
+
+
 def test_power_of_two_change_of_units_on_gpu():
     """Density x 2^20 and pressure x 2^72 (velocity x 2^26), gravity on: the
     GPU run in the new units is the scaled GPU run in the old ones bit for
