@@ -657,16 +657,37 @@ def algorithmic_bytes_per_step(lay):
 
 
 # The final stage's launch forms (ppm_set_step_form): the staged riemann3 +
-# update kernels, the brick kernel, the streamed kernel.
+# update kernels, the brick kernel, the streamed kernel; the front end's
+# (ppm_set_front_form): staged trace + riemann1, streamed along z, the x
+# axis fused, every axis fused.
 FINAL_FORMS = ("staged", "brick", "streamed")
+FRONT_FORMS = ("staged", "streamed", "x_fused", "xyz_fused")
 
 
 def launch_config(lev):
-    """[tile, strip_rows, final-stage form] and, for the streamed form, its
-    tile extents [x, y, z run]: what the counter records are tied to."""
+    """[tile, strip_rows, final-stage form, front-end form], then the
+    streamed final stage's tile extents [x, y, z run] when that form is on
+    and the streamed front end's when that one is: what the counter records
+    are tied to."""
     t, s = lev.get_tiling()
-    form = lev.get_step_form()
-    return [t, s, form] + (list(lev.get_stream_tiling()) if form == 2 else [])
+    form, front = lev.get_step_form(), lev.get_front_form()
+    return [t, s, form, front] + (list(lev.get_stream_tiling()) if form == 2 else []) + \
+        (list(lev.get_front_tiling()) if front == 1 else [])
+
+
+def apply_launch_config(lev, cfg):
+    """The inverse of launch_config (a prefix of it is enough)."""
+    lev.set_tiling(*cfg[:2])
+    k = 4
+    if len(cfg) > 2 and cfg[2] == 2 and len(cfg) >= k + 3:
+        lev.set_stream_tiling(*cfg[k:k + 3])
+        k += 3
+    if len(cfg) > 3 and cfg[3] == 1 and len(cfg) >= k + 3:
+        lev.set_front_tiling(*cfg[k:k + 3])
+    if len(cfg) > 2:
+        lev.set_step_form(cfg[2])
+    if len(cfg) > 3:
+        lev.set_front_form(cfg[3])
 
 
 def headline(wl, wname, steps, warmup, per_box=True, tiling=None, autotune=True):
@@ -683,11 +704,7 @@ def headline(wl, wname, steps, warmup, per_box=True, tiling=None, autotune=True)
     dtv = torch.zeros(2, dtype=torch.float64, device="cuda")
     from_cache = None
     if tiling:
-        lev.set_tiling(*tiling[:2])
-        if len(tiling) > 2:
-            if len(tiling) > 3:
-                lev.set_stream_tiling(*tiling[3:6])
-            lev.set_step_form(tiling[2])
+        apply_launch_config(lev, tiling)
     elif autotune:
         Uf = U0.clone()
         lev.fill_boundary(Uf)
@@ -696,7 +713,7 @@ def headline(wl, wname, steps, warmup, per_box=True, tiling=None, autotune=True)
     tiling = launch_config(lev)
     zones = lay.valid_zones()
     out = {"tiling": {"tile": tiling[0], "strip_rows": tiling[1], "final_stage_form": FINAL_FORMS[tiling[2]],
-                      "stream_tile": tiling[3:] or None},
+                      "front_end_form": FRONT_FORMS[tiling[3]], "extents": tiling[4:] or None},
            "autotune": {"from_cache": None if from_cache is None else bool(from_cache),
                         "cache": os.path.relpath(AUTOTUNE_CACHE, ROOT) if from_cache is not None else None}}
 
@@ -767,12 +784,18 @@ def roofline(wname, lay, prof, ms_step, precision, tiling):
             units[k] += v
     table = flops_table(wname)
     # with a fused final stage (brick or streamed form) one kernel does the
-    # riemann3 and update work, timed in the riemann3 slot
+    # riemann3 and update work, timed in the riemann3 slot; with a fused
+    # front end (any form but the staged one) the trace and riemann1 slots
+    # hold kernels that share the two stages' work, priced together
     fused = len(tiling) > 2 and tiling[2] != 0
-    stages = {k: prof[k] for k in STAGES if not (fused and k == "update")}
+    ffront = len(tiling) > 3 and tiling[3] != 0
+    stages = {k: prof[k] for k in STAGES if not (fused and k == "update") and not (ffront and k == "riemann1")}
     flops_of = {k: table[k] * units[k] for k in stages}
     if fused:
         flops_of["riemann3"] += table["update"] * units["update"]
+    if ffront:
+        stages["trace"] = (prof["trace"][0] + prof["riemann1"][0], prof["trace"][1])
+        flops_of["trace"] += table["riemann1"] * units["riemann1"]
     dom = max(stages, key=lambda k: stages[k][0])
     t_ms, cnt = stages[dom]
     mean_s = t_ms / cnt / 1e3
@@ -782,9 +805,12 @@ def roofline(wname, lay, prof, ms_step, precision, tiling):
     rec = recorded_record(dom, wname, tiling) if precision == 0 else None
     step_flops = sum(table[k] * units[k] for k in STAGES)
     alg = algorithmic_bytes_per_step(lay)
-    name = dom if not (fused and dom == "riemann3") else \
-        ("final_update (riemann3 + update, brick form)" if tiling[2] == 1 else
-         "final_stream (riemann3 + update, streamed form)")
+    name = dom
+    if fused and dom == "riemann3":
+        name = ("final_update (riemann3 + update, brick form)" if tiling[2] == 1 else
+                "final_stream (riemann3 + update, streamed form)")
+    elif ffront and dom == "trace":
+        name = f"front end (trace + riemann1, {FRONT_FORMS[tiling[3]]} form)"
     r = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
          "frac": achieved / peak,
          "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
@@ -816,8 +842,10 @@ def main():
     ap.add_argument("--autotune-cache", default=None,
                     help="autotuner cache file (default: the package's autotune_cache.jsonl)")
     ap.add_argument("--tiling", default=None,
-                    help="'tile,strip_rows[,form[,x,y,z]]': use this launch configuration (tiling, final-stage "
-                         "form 0 staged / 1 brick / 2 streamed, streamed tile extents) instead of autotuning")
+                    help="'tile,strip_rows[,final[,front[,x,y,z[,x,y,z]]]]': use this launch configuration "
+                         "(tiling; final-stage form 0 staged / 1 brick / 2 streamed; front-end form 0 staged / "
+                         "1 streamed / 2 x fused / 3 all fused; the streamed forms' tile extents) instead of "
+                         "autotuning")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (single box, 512-box tiling, adjoint, two-level, jet, species)")
     ap.add_argument("--adjoint-only", action="store_true",

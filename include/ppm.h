@@ -192,9 +192,9 @@ int ppm_hydro_step_noalloc(ppm_ctx* ctx, const double* U, double* Unew, double* 
 
 /* ppm_hydro_step that also leaves the next step's time step: dt_next_dev
  * (2 device doubles) receives what ppm_compute_dt(Unew) would write, bit
- * for bit -- the CFL rule over the valid zones of Unew, which the staged
- * update computes from the states it writes instead of a separate pass over
- * Unew (the fused brick form, ppm_set_step_form(1), runs that pass).  The
+ * for bit -- the CFL rule over the valid zones of Unew, which the update
+ * (in every form of the final stage) computes from the states it writes
+ * instead of a separate pass over Unew.  The
  * ghost fill before the next step does not change valid zones, so the next
  * step can read its dt from dt_next_dev.  dt_next_dev may alias dt_dev (it
  * is written after the step has read dt_dev[0]).  PPM_EINVAL as for
@@ -389,7 +389,7 @@ int ppm_get_stream_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t*
 
 /* Form of the step's front end, the PPM reconstruction with characteristic
  * tracing (paper Sec. 1's explicit advance; O4, O5) and the normal-predictor
- * Riemann solves (O7).  form 0 (default): two staged kernels, the tracing
+ * Riemann solves (O7).  form 0: two staged kernels, the tracing
  * writing the traced face states to the workspace and the solves reading
  * them back.  form 1: one kernel whose workgroups each own an x-y tile of a
  * box's traced zones and walk it through a run of z planes; per plane each
@@ -398,9 +398,18 @@ int ppm_get_stream_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t*
  * neighbours' states exchanged through LDS and the z neighbour's kept in
  * registers from the plane before, so the traced states are written (later
  * stages read them) but not read back.
- * Results are identical bit for bit in both forms (also for the adjoint's
- * recompute and the species step, which run the same front end).  Tiles:
- * ppm_set_front_tiling.  The autotuner picks the form and the tile. */
+ * form 2: the x axis's tracing and solves in one kernel whose wavefronts
+ * each trace 64 consecutive zones, the first of them the previous
+ * wavefront's last, so both states of every x face they solve meet in
+ * neighbouring lanes (a lane shuffle; no LDS, no barrier); y and z staged
+ * (the default).
+ * form 3: the same for every axis; along y and z each wavefront traces an
+ * 8 x 8 patch of the x-y or x-z plane whose first row along the axis is the
+ * previous patch's last (one zone in eight traced twice).
+ * Results are identical bit for bit in all forms (also for the adjoint's
+ * recompute and the species step, which run the same front end).  Tiles of
+ * form 1: ppm_set_front_tiling.  The autotuner picks the form and the
+ * tile. */
 int ppm_set_front_form(ppm_ctx* ctx, int32_t form);
 int ppm_get_front_form(const ppm_ctx* ctx, int32_t* form);
 /* Tile of the streamed front end: at most sx x sy traced zones in x-y and

@@ -417,18 +417,38 @@ void build_front(ppm_ctx& c) {
   }
 }
 
+// The whole level's ranges of the fused front end's work lists.
+FrontRanges front_all(const ppm_ctx& c) {
+  return FrontRanges{0, (int)c.tilesX.size(), 0, (int)c.tilesY.size(), 0, (int)c.tilesZ.size()};
+}
+
 void build_tiles(ppm_ctx& c) {
   c.tilesS.clear();
   c.tilesE.clear();
   c.tS_begin.assign(1, 0);
   c.tE_begin.assign(1, 0);
+  c.tilesX.clear();
+  c.tX_begin.assign(1, 0);
+  c.tilesY.clear();
+  c.tY_begin.assign(1, 0);
+  c.tilesZ.clear();
+  c.tZ_begin.assign(1, 0);
   for (int b = 0; b < c.layout.nbox; ++b) {
     int n[3];
     for (int d = 0; d < 3; ++d) n[d] = c.boxes[b].hi[d] - c.boxes[b].lo[d] + 1;
     add_tiles(c.tilesS, b, n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG, c.tile, c.strip_rows);
     add_tiles(c.tilesE, b, n[0] + 2, n[1] + 2, n[2] + 2, c.tile, c.strip_rows);
+    add_tiles(c.tilesX, b, n[0] + 2, n[1] + 2, n[2] + 2, XF_OWNED, c.strip_rows);
+    // front form 3: workgroup w of a box along y or z; the kernel decodes w
+    for (long long w = 0; w < front_yz_groups(n[0] + 2, n[1] + 2, n[2] + 2); ++w)
+      c.tilesY.push_back(Tile{b, (int)w, (int)w + 1});
+    for (long long w = 0; w < front_yz_groups(n[0] + 2, n[2] + 2, n[1] + 2); ++w)
+      c.tilesZ.push_back(Tile{b, (int)w, (int)w + 1});
     c.tS_begin.push_back((int)c.tilesS.size());
     c.tE_begin.push_back((int)c.tilesE.size());
+    c.tX_begin.push_back((int)c.tilesX.size());
+    c.tY_begin.push_back((int)c.tilesY.size());
+    c.tZ_begin.push_back((int)c.tilesZ.size());
   }
 }
 
@@ -605,6 +625,9 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
       (e = upload(&ctx->d_boxes, db)) != hipSuccess ||
       (e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess ||
       (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesX, ctx->tilesX)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesY, ctx->tilesY)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesZ, ctx->tilesZ)) != hipSuccess ||
       (e = upload(&ctx->d_desc, ctx->plan->desc)) != hipSuccess ||
       (e = upload(&ctx->d_start, ctx->plan->start)) != hipSuccess ||
       (e = hipMalloc((void**)&ctx->d_consts, sizeof(StepConsts))) != hipSuccess ||
@@ -630,6 +653,9 @@ int ppm_ctx_destroy(ppm_ctx* ctx) {
   (void)hipFree(ctx->d_boxes);
   (void)hipFree(ctx->d_tilesS);
   (void)hipFree(ctx->d_tilesE);
+  (void)hipFree(ctx->d_tilesX);
+  (void)hipFree(ctx->d_tilesY);
+  (void)hipFree(ctx->d_tilesZ);
   (void)hipFree(ctx->d_bricks);
   (void)hipFree(ctx->d_fbricks);
   (void)hipFree(ctx->d_desc);
@@ -760,8 +786,10 @@ static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* 
     if (rc) return rc;
   }
   const int grav = (params->grav[0] != 0.0 || params->grav[1] != 0.0 || params->grav[2] != 0.0) ? 1 : 0;
-  auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, int tF0, int tF1, hipEvent_t* ev) {
-    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, U, Unew, flux, work,
+  auto run = [&](int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, int tF0, int tF1, const FrontRanges& fr,
+                 hipEvent_t* ev) {
+    return ctx->hip(launch_step(L, params->precision, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, fr, U, Unew, flux,
+                                work,
                                 params->gamma, params->small_dens, params->small_pres, params->limiter,
                                 params->flattening, params->riemann_iters, grav, params->grav, s, ev, upto, so),
                     "step");
@@ -769,12 +797,14 @@ static int hydro_step_impl(ppm_ctx* ctx, const double* U, double* Unew, double* 
   if (mode == PPM_LAUNCH_BATCHED) {
     ppm_ctx::ProfRec* r = (timed && ctx->prof) ? ctx->begin_rec(PROF_PRIM, STEP_EVENTS) : nullptr;
     rc = run(0, (int)ctx->tilesS.size(), 0, (int)ctx->tilesE.size(), 0, (int)ctx->bricks.size(), 0,
-             (int)ctx->fbricks.size(), r ? r->ev.data() : nullptr);
+             (int)ctx->fbricks.size(), front_all(*ctx), r ? r->ev.data() : nullptr);
     if (rc) return rc;
   } else {
     for (int b = 0; b < ctx->layout.nbox; ++b) {
+      const FrontRanges fr{ctx->tX_begin[b], ctx->tX_begin[b + 1], ctx->tY_begin[b], ctx->tY_begin[b + 1],
+                           ctx->tZ_begin[b], ctx->tZ_begin[b + 1]};
       rc = run(ctx->tS_begin[b], ctx->tS_begin[b + 1], ctx->tE_begin[b], ctx->tE_begin[b + 1], ctx->tB_begin[b],
-               ctx->tB_begin[b + 1], ctx->tF_begin[b], ctx->tF_begin[b + 1], nullptr);
+               ctx->tB_begin[b + 1], ctx->tF_begin[b], ctx->tF_begin[b + 1], fr, nullptr);
       if (rc) return rc;
     }
   }
@@ -853,7 +883,7 @@ int ppm_set_stream_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz) {
 
 int ppm_set_front_form(ppm_ctx* ctx, int32_t form) {
   if (!ctx) return PPM_EINVAL;
-  if (form != 0 && form != 1) return ctx->fail(PPM_EINVAL, "set_front_form: form must be 0 or 1");
+  if (form < 0 || form > 3) return ctx->fail(PPM_EINVAL, "set_front_form: form must be 0, 1, 2 or 3");
   if (form != ctx->front) ++ctx->gen;
   ctx->front = form;
   return PPM_OK;
@@ -946,8 +976,8 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, c
   // recompute the forward intermediates through stage 2 (U is not written),
   // unless the workspace holds them from the forward step
   if (recompute) {
-    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, 0, 0, 0, (int)ctx->fbricks.size(), U, nullptr,
-                              nullptr, ctx->work,
+    rc = ctx->hip(launch_step(L, params->precision, 0, nS, 0, nE, 0, 0, 0, (int)ctx->fbricks.size(), front_all(*ctx),
+                              U, nullptr, nullptr, ctx->work,
                               params->gamma, params->small_dens, params->small_pres, params->limiter,
                               params->flattening, params->riemann_iters, grav, params->grav, s, nullptr,
                               STEP_TO_STAGE2),
@@ -1129,9 +1159,17 @@ int ppm_set_tiling(ppm_ctx* ctx, int32_t tile, int32_t strip_rows) {
   build_tiles(*ctx);
   (void)hipFree(ctx->d_tilesS);
   (void)hipFree(ctx->d_tilesE);
+  (void)hipFree(ctx->d_tilesX);
+  (void)hipFree(ctx->d_tilesY);
+  (void)hipFree(ctx->d_tilesZ);
   ctx->d_tilesS = nullptr;
   ctx->d_tilesE = nullptr;
-  if ((e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess || (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess)
+  ctx->d_tilesX = nullptr;
+  ctx->d_tilesY = nullptr;
+  ctx->d_tilesZ = nullptr;
+  if ((e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess || (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesX, ctx->tilesX)) != hipSuccess || (e = upload(&ctx->d_tilesY, ctx->tilesY)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesZ, ctx->tilesZ)) != hipSuccess)
     return ctx->hip(e, "tiling upload");
   return PPM_OK;
 }
@@ -1198,8 +1236,7 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
   hipStream_t s = (hipStream_t)stream;
   double* dtv = nullptr;
   // dtv[0..1]: the step's dt; dtv[2..3]: the next dt the timed steps leave,
-  // as the graph and the benchmark run them (the brick form pays a separate
-  // speed pass for it)
+  // as the graph and the benchmark run them
   if ((e = hipMalloc((void**)&dtv, 4 * sizeof(double))) != hipSuccess) return ctx->hip(e, "autotune");
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
@@ -1269,8 +1306,8 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
       if ((rc = ppm_set_step_form(ctx, 0))) break;
     }
   }
-  // then the front end, with the final stage chosen: staged, or streamed
-  // with one of its tile shapes
+  // then the front end, with the final stage chosen: staged, streamed with
+  // one of its tile shapes, or the x axis fused
   static const int fshapes[][3] = {{11, 11, 32}, {16, 8, 32}};
   int bfront = 0, bfe[3] = {ctx->front_e[0], ctx->front_e[1], ctx->front_e[2]};
   const int front0 = ctx->front;
@@ -1286,6 +1323,11 @@ int ppm_autotune(ppm_ctx* ctx, const double* U, double* Unew, const double dx[3]
         for (int d = 0; d < 3; ++d) bfe[d] = sh[d];
       }
     }
+    for (int f = 2; f <= 3 && !rc; ++f)
+      if (!(rc = ppm_set_front_form(ctx, f)) && !(rc = timed(ms)) && ms < best) {
+        best = ms;
+        bfront = f;
+      }
     if (!rc) rc = ppm_set_front_form(ctx, 0);
   }
   (void)hipEventDestroy(e0);

@@ -36,14 +36,20 @@ struct ppm_ctx {
   bool plan_hit = false;
   std::vector<Tile> tilesS, tilesE;
   std::vector<int> tS_begin, tE_begin;  // nbox + 1
+  std::vector<Tile> tilesX;             // front forms 2, 3: traced-grid runs of XF_OWNED zones
+  std::vector<int> tX_begin;            // nbox + 1
+  std::vector<Tile> tilesY, tilesZ;     // front form 3: 8 x 8 wavefront patches (x-d planes) along y, z
+  std::vector<int> tY_begin, tZ_begin;  // nbox + 1
   std::vector<Brick> bricks;
   std::vector<int> tB_begin;            // nbox + 1
   int fused = 0;                        // 1: final fluxes + update in one brick kernel; 2: streamed
   int stream_e[3] = {16, 8, 32};        // tile extents of the streamed final stage
   // front end: 0 trace and stage-1 solves as two staged kernels; 1 one
   // kernel streamed along z over x-y tiles of the traced grids (fbricks,
-  // at most front_e zones per axis, balanced per box)
-  int front = 0;
+  // at most front_e zones per axis, balanced per box); 2 the x axis's trace
+  // and solves in one kernel (tilesX), y and z staged; 3 each axis's trace
+  // and solves in one kernel (tilesX, tilesY, tilesZ)
+  int front = 2;
   int front_e[3] = {16, 8, 32};
   std::vector<Brick> fbricks;
   std::vector<int> tF_begin;            // nbox + 1
@@ -60,6 +66,9 @@ struct ppm_ctx {
   DevBox* d_boxes = nullptr;
   Tile* d_tilesS = nullptr;
   Tile* d_tilesE = nullptr;
+  Tile* d_tilesX = nullptr;
+  Tile* d_tilesY = nullptr;
+  Tile* d_tilesZ = nullptr;
   Brick* d_bricks = nullptr;
   Brick* d_fbricks = nullptr;
   FillDesc* d_desc = nullptr;
@@ -104,6 +113,9 @@ struct ppm_ctx {
     L.boxes = d_boxes;
     L.tilesS = d_tilesS;
     L.tilesE = d_tilesE;
+    L.tilesX = d_tilesX;
+    L.tilesY = d_tilesY;
+    L.tilesZ = d_tilesZ;
     L.desc = d_desc;
     L.desc_start = d_start;
     L.consts = d_consts;

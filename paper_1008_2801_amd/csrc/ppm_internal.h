@@ -46,6 +46,21 @@ constexpr int STREAM_MAX_THREADS = 512;
 // tile, and a group for the rows and columns of its low edges, each group
 // in whole wavefronts
 constexpr int FRONT_MAX_THREADS = 512;
+// front form 2: workgroups of XF_THREADS lanes, each wavefront tracing 64
+// consecutive traced zones of which the first is the previous wavefront's
+// last (so every x face's two states meet in one wavefront)
+constexpr int XF_THREADS = 256;
+constexpr int XF_OWNED = XF_THREADS / 64 * 63;
+// front form 3 along y and z: each wavefront an 8 x 8 patch (8 x slots, 8
+// slots along the axis, the first a halo), a workgroup 4 patches side by
+// side in x; workgroups per box: ceil(E0 / 32) x ceil(E_d / 7) x E_other
+inline long long front_yz_groups(int E0, int Ed, int Eo) {
+  return (long long)((E0 + 31) / 32) * ((Ed + 6) / 7) * Eo;
+}
+// ranges of the front forms' work lists of a launch
+struct FrontRanges {
+  int x0, x1, y0, y1, z0, z1;
+};
 __host__ __device__ inline int front_group(int mx, int my) {
   const int a = mx * my > mx + my ? mx * my : mx + my;
   return ((a + 63) / 64) * 64;
@@ -114,6 +129,9 @@ struct DevLevel {
   const DevBox* boxes;
   const Tile* tilesS;  // tiles over the stored grids
   const Tile* tilesE;  // tiles over the traced grids
+  const Tile* tilesX;  // runs of XF_OWNED traced zones (front forms 2, 3)
+  const Tile* tilesY;  // workgroups of 8 x 8 patches in x-y planes (front form 3)
+  const Tile* tilesZ;  // workgroups of 8 x 8 patches in x-z planes (front form 3)
   const FillDesc* desc;
   const long long* desc_start;  // exclusive prefix of zone counts, ndesc+1
   StepConsts* consts;
@@ -128,7 +146,9 @@ struct DevLevel {
                         // 2: the same in x-y tiles streamed along z (ppm_kernels.hip, k_final_stream)
   int stream_e[3];      // form 2: x, y extents of a tile (threads = product) and the z run
   const Brick* fbricks; // traced-grid x-y tiles with z runs (streamed front end)
-  int front;            // 1: trace + stage-1 solves in one kernel streamed along z (k_front_stream)
+  int front;            // 1: trace + stage-1 solves in one kernel streamed along z (k_front_stream);
+                        // 2: the x axis's trace + stage-1 solves in one kernel (k_front_x);
+                        // 3: every axis's (k_front_x, k_front_yz)
   int front_m[2];       // largest x, y extents of the front tiles (LDS layout, lanes)
 };
 
@@ -146,7 +166,7 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
                              const double h[3], double gamma, double small_pres, double cfl,
                              double* dt_dev, hipStream_t s);
 // The step stages over E-tiles [tE0, tE1), S-tiles [tS0, tS1), bricks
-// [tB0, tB1) and front tiles [tF0, tF1).  upto: STEP_TO_STAGE2 (prim..riemann2, for the adjoint's
+// [tB0, tB1), front tiles [tF0, tF1) and the fused axes' lists fr.  upto: STEP_TO_STAGE2 (prim..riemann2, for the adjoint's
 // recompute), STEP_FULL (the whole step; the fused final stage when the
 // level asks for it), STEP_FULL_STAGED (the whole step with the final
 // fluxes left in the workspace, as the species stages need).
@@ -161,7 +181,7 @@ struct SpeedOut {
 };
 
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
-                       int tF0, int tF1,
+                       int tF0, int tF1, const FrontRanges& fr,
                        const double* U, double* Unew, double* const* flux, void* work,
                        const double gamma, const double small_dens, const double small_pres,
                        int limiter, int flattening, int iters, int grav, const double g[3],

@@ -210,13 +210,14 @@ __device__ __forceinline__ void trace_body(int t, const Tile* __restrict__ tiles
   raise_flags(flags, fl);
 }
 
+// d0: the first axis (the grid's rows are axes d0, d0 + 1, ...).
 template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_trace(const Tile* __restrict__ tiles, int ntiles,
                                                 const DevBox* __restrict__ boxes,
                                                 const S* __restrict__ prim, long long LS,
                                                 S* __restrict__ work, long long LE, Gas<S> G,
-                                                const StepConsts* __restrict__ sc, int* flags) {
-  switch (blockIdx.y) {
+                                                const StepConsts* __restrict__ sc, int* flags, int d0) {
+  switch (d0 + (int)blockIdx.y) {
     case 0: trace_body<0>(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G, sc, flags); break;
     case 1: trace_body<1>(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G, sc, flags); break;
     default: trace_body<2>(xcd_tile(ntiles), tiles, boxes, prim, LS, work, LE, G, sc, flags); break;
@@ -269,14 +270,104 @@ template <class S>
 __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(8))) k_riemann1(const Tile* __restrict__ tiles, int ntiles,
                                                    const DevBox* __restrict__ boxes,
                                                    S* __restrict__ work, long long LE, Gas<S> G,
-                                                   int* flags) {
-  switch (blockIdx.y) {
+                                                   int* flags, int d0) {
+  switch (d0 + (int)blockIdx.y) {
     case 0: riemann1_body<0>(xcd_tile(ntiles), tiles, boxes, work, LE, G, flags); break;
     case 1: riemann1_body<1>(xcd_tile(ntiles), tiles, boxes, work, LE, G, flags); break;
     default: riemann1_body<2>(xcd_tile(ntiles), tiles, boxes, work, LE, G, flags); break;
   }
 }
 
+
+// O4 + O5 + O7 along x in one kernel: each wavefront traces 64 consecutive
+// zones of the traced grid, the first of them the previous wavefront's last
+// (a halo: traced, not stored), so the two states of every x face it solves
+// sit in neighbouring lanes and the low side arrives by a lane shuffle.
+// Rows are consecutive in the linear index, so the lane below holds the x
+// neighbour of every zone with x >= 0 (a zone at x = -1 solves no face).
+// Same arithmetic as trace_at and stage1_face, so the same bits as the
+// staged trace and riemann1 kernels along x.
+template <class S>
+__global__ void __launch_bounds__(XF_THREADS) k_front_x(const Tile* __restrict__ tiles, int ntiles,
+                                                    const DevBox* __restrict__ boxes, const S* __restrict__ prim,
+                                                    long long LS, S* __restrict__ work, long long LE, Gas<S> G,
+                                                    const StepConsts* __restrict__ sc, int* flags) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;  // the whole workgroup
+  const Tile tl = tiles[t];
+  const DevBox B = boxes[tl.box];
+  const int lane = threadIdx.x & 63;
+  const long long idx = (long long)tl.start + (threadIdx.x >> 6) * 63 + lane - 1;
+  const bool own = lane > 0 && idx < tl.end;
+  const bool have = own || (lane == 0 && idx >= 0 && idx < tl.end);
+  const int E0 = B.n[0] + 2, E1 = B.n[1] + 2;
+  const long long row = have ? idx / E0 : 0;
+  const int x = have ? (int)(idx - row * E0) - 1 : 0;
+  const int y = (int)(row % E1) - 1, z = (int)(row / E1) - 1;
+  S qp[5], qm[5];
+  int fl = 0;
+  if (have) {
+    trace_at<0>(B, x, y, z, idx, prim, LS, work, LE, G, sc, qp, qm, fl);
+    if (own) store_traced<0>(work, LE, B, idx, qp, qm);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qp[m] = qm[m] = S(0);
+  }
+  S L[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) L[m] = __shfl_up(qp[m], 1, 64);
+  if (own && x >= 0) stage1_face<0>(B, x, L, qm, G, work, LE, idx, fl);
+  raise_flags(flags, fl);
+}
+
+// O4 + O5 + O7 along d (y or z) in one kernel: each wavefront traces an
+// 8 x 8 patch of the x-d plane (8 consecutive x slots, 8 slots along d, the
+// first of them the previous patch's last: a halo, traced, not stored), so
+// the two states of every d face it solves sit 8 lanes apart and the low
+// side arrives by a lane shuffle.  A workgroup is 4 patches side by side in
+// x at one slot of the third axis; its index w within the box (Tile.start)
+// runs over x first, then the bands of 7 slots along d, then that third
+// axis.  Same arithmetic as trace_at and stage1_face, so the same bits as
+// the staged trace and riemann1 kernels along d.
+template <int d, class S>
+__global__ void __launch_bounds__(XF_THREADS) k_front_yz(const Tile* __restrict__ tiles, int ntiles,
+                                                     const DevBox* __restrict__ boxes, const S* __restrict__ prim,
+                                                     long long LS, S* __restrict__ work, long long LE, Gas<S> G,
+                                                     const StepConsts* __restrict__ sc, int* flags) {
+  constexpr int o = 3 - d;  // the third axis
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;  // the whole workgroup
+  const Tile tl = tiles[t];
+  const DevBox B = boxes[tl.box];
+  const int E[3] = {B.n[0] + 2, B.n[1] + 2, B.n[2] + 2};
+  const int nq = (E[0] + 31) / 32, nb = (E[d] + 6) / 7;
+  const int w = tl.start;
+  const int q = w % nq, band = (w / nq) % nb, so = w / (nq * nb);
+  const int lane = threadIdx.x & 63, i = lane & 7, j = lane >> 3;
+  const int xs = 32 * q + 8 * (int)(threadIdx.x >> 6) + i;  // slots: zone = slot - 1
+  const int ds = 7 * band + j - 1;
+  const bool act = xs < E[0] && ds >= 0 && ds < E[d];
+  const bool own = act && j >= 1;
+  int X[3];
+  X[0] = xs - 1;
+  X[d] = ds - 1;
+  X[o] = so - 1;
+  const long long e = ((long long)(X[2] + 1) * E[1] + (X[1] + 1)) * E[0] + (X[0] + 1);
+  S qp[5], qm[5];
+  int fl = 0;
+  if (act) {
+    trace_at<d>(B, X[0], X[1], X[2], e, prim, LS, work, LE, G, sc, qp, qm, fl);
+    if (own) store_traced<d>(work, LE, B, e, qp, qm);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qp[m] = qm[m] = S(0);
+  }
+  S L[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) L[m] = __shfl_up(qp[m], 8, 64);
+  if (own && X[d] >= 0) stage1_face<d>(B, X[d], L, qm, G, work, LE, e, fl);
+  raise_flags(flags, fl);
+}
 
 // O4-O7 fused and streamed along z: a workgroup owns an x-y tile of
 // ex x ey zones of the traced grid and walks it through a run of z planes.
@@ -672,8 +763,10 @@ __global__ void __launch_bounds__(MAX_TILE) k_update(const Tile* __restrict__ ti
 // O9 + O10 fused on a brick of valid zones: the final fluxes of every face
 // of the brick (its boundary faces are computed by both bricks that share
 // them) go to LDS instead of HBM, then each zone of the brick is updated
-// from them.  The arithmetic is riemann3_face and update_zone, so the
-// results are those of the staged kernels bit for bit.
+// from them and, with so.bits, its signal speed folded into the next dt's
+// maximum.  The arithmetic is riemann3_face, update_zone and
+// fold_signal_speed, so the results are those of the staged kernels bit for
+// bit.
 template <int d, class S>
 __device__ __forceinline__ void brick_faces(const Brick& K, const DevBox& B, const S* __restrict__ work,
                                             long long LE, const Gas<S>& G, const StepConsts* __restrict__ sc,
@@ -698,7 +791,7 @@ __global__ void __launch_bounds__(BRICK_THREADS) k_final_update(const Brick* __r
                                                             const StepConsts* __restrict__ sc,
                                                             const double* __restrict__ U, double* __restrict__ Unew,
                                                             double* fx, double* fy, double* fz, int grav, double g0,
-                                                            double g1, double g2, int* flags) {
+                                                            double g1, double g2, SpeedOut so, int* flags) {
   __shared__ S Fs[3 * 5 * BRICK_FACES];
   const int k = xcd_tile(nbricks);
   if (k < 0) return;
@@ -714,6 +807,7 @@ __global__ void __launch_bounds__(BRICK_THREADS) k_final_update(const Brick* __r
   const double dtdx0 = sc->dtdx[0], dtdx1 = sc->dtdx[1], dtdx2 = sc->dtdx[2];
   const int N0 = B.n[0] + 2 * NG, N1 = B.n[1] + 2 * NG, N2 = B.n[2] + 2 * NG;
   const long long NS = (long long)N0 * N1 * N2;
+  double smax_lane = 0.0;
   for (int z = threadIdx.x; z < e0 * e1 * e2; z += BRICK_THREADS) {
     const int l0 = z % e0, l1 = (z / e0) % e1, l2 = z / (e0 * e1);
     const int ix = (l2 * e1 + l1) * (e0 + 1) + l0;        // x-face below the zone
@@ -735,7 +829,11 @@ __global__ void __launch_bounds__(BRICK_THREADS) k_final_update(const Brick* __r
     update_zone(uo, fxd, fyd, fzd, dtdx0, dtdx1, dtdx2, sc, grav, g0, g1, g2, un);
 #pragma unroll
     for (int m = 0; m < 5; ++m) Unew[ui + m * NS] = un[m];
+    if (so.bits)
+      smax_lane = smax(smax_lane, fold_signal_speed(0.0, un[0], un[1], un[2], un[3], un[4], so.h[0], so.h[1],
+                                                    so.h[2], so.gamma, so.gm1, so.small_pres));
   }
+  if (so.bits) block_max_to(smax_lane, so.bits);
 }
 
 // O9 + O10 fused, streamed along z: a workgroup owns an x-y tile of
@@ -945,7 +1043,7 @@ __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restric
 
 template <class S>
 hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1, int tF0, int tF1,
-                     const double* U,
+                     const FrontRanges& fr, const double* U,
                      double* Unew, double* const* flux, void* work, Gas<S> G, const double g[3], hipStream_t s,
                      hipEvent_t* ev, int upto, const SpeedOut& so) {
   S* prim = (S*)work;
@@ -971,11 +1069,26 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
     if (ev) (void)hipEventRecord(ev[3], s);
     if (ev) (void)hipEventRecord(ev[4], s);
   } else {
-    hipLaunchKernelGGL(k_trace<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework, L.LE,
-                       G, L.consts, L.flags);
-    if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_riemann1<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
-                       L.flags);
+    // front forms 2 and 3: the x axis, or every axis, in one kernel each
+    // (timed in the trace slot); the other axes staged
+    const int nX = fr.x1 - fr.x0, nY = fr.y1 - fr.y0, nZ = fr.z1 - fr.z0;
+    const int d0 = (L.front >= 2 && nX > 0) ? 1 : 0;
+    if (d0)
+      hipLaunchKernelGGL(k_front_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX + fr.x0, nX, L.boxes,
+                         (const S*)prim, L.LS, ework, L.LE, G, L.consts, L.flags);
+    if (L.front == 3 && d0 && nY > 0 && nZ > 0) {
+      hipLaunchKernelGGL((k_front_yz<1, S>), dim3(xcd_grid(nY)), dim3(XF_THREADS), 0, s, L.tilesY + fr.y0, nY,
+                         L.boxes, (const S*)prim, L.LS, ework, L.LE, G, L.consts, L.flags);
+      hipLaunchKernelGGL((k_front_yz<2, S>), dim3(xcd_grid(nZ)), dim3(XF_THREADS), 0, s, L.tilesZ + fr.z0, nZ,
+                         L.boxes, (const S*)prim, L.LS, ework, L.LE, G, L.consts, L.flags);
+      if (ev) (void)hipEventRecord(ev[3], s);
+    } else {
+      hipLaunchKernelGGL(k_trace<S>, dim3(xcd_grid(nE), 3 - d0), blk, 0, s, TE, nE, L.boxes, prim, L.LS, ework,
+                         L.LE, G, L.consts, L.flags, d0);
+      if (ev) (void)hipEventRecord(ev[3], s);
+      hipLaunchKernelGGL(k_riemann1<S>, dim3(xcd_grid(nE), 3 - d0), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
+                         L.flags, d0);
+    }
     if (ev) (void)hipEventRecord(ev[4], s);
   }
   hipLaunchKernelGGL(k_riemann2<S>, dim3(xcd_grid(nE), 3), blk, 0, s, TE, nE, L.boxes, ework, L.LE, G,
@@ -1000,10 +1113,7 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
   if (L.fused == 1 && upto == STEP_FULL && nB > 0) {
     hipLaunchKernelGGL(k_final_update<S>, dim3(xcd_grid(nB)), dim3(BRICK_THREADS), 0, s, L.bricks + tB0, nB,
                        L.boxes, (const S*)ework, L.LE, G, L.consts, U, Unew, fx, fy, fz, G.grav, g[0], g[1], g[2],
-                       L.flags);
-    if (so.bits)  // the brick kernel has no fused speed maximum: a separate pass over Unew
-      hipLaunchKernelGGL(k_wavespeed, dim3(nE < 2048 ? nE : 2048), blk, 0, s, TE, nE, L.boxes, (const double*)Unew,
-                         so.h[0], so.h[1], so.h[2], so.gamma, so.gm1, so.small_pres, so.bits);
+                       so, L.flags);
     if (ev) (void)hipEventRecord(ev[6], s);
     if (ev) (void)hipEventRecord(ev[7], s);
     return hipGetLastError();
@@ -1081,15 +1191,16 @@ hipError_t launch_sqrt_form(const double* x, double* out, long long n, int form,
 }
 
 hipError_t launch_step(const DevLevel& L, int precision, int tS0, int tS1, int tE0, int tE1, int tB0, int tB1,
-                       int tF0, int tF1, const double* U, double* Unew, double* const* flux, void* work,
+                       int tF0, int tF1, const FrontRanges& fr, const double* U, double* Unew, double* const* flux,
+                       void* work,
                        const double gamma, const double small_dens, const double small_pres, int limiter,
                        int flattening, int iters, int grav, const double g[3], hipStream_t s, hipEvent_t* ev,
                        int upto, SpeedOut so) {
   if (precision == 1)
-    return step_impl<float>(L, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, U, Unew, flux, work,
+    return step_impl<float>(L, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, fr, U, Unew, flux, work,
                             make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                             g, s, ev, upto, so);
-  return step_impl<double>(L, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, U, Unew, flux, work,
+  return step_impl<double>(L, tS0, tS1, tE0, tE1, tB0, tB1, tF0, tF1, fr, U, Unew, flux, work,
                            make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                            g, s, ev, upto, so);
 }

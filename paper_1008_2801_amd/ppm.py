@@ -401,7 +401,8 @@ class Level:
 
     def set_front_form(self, form):
         """0: trace and stage-1 solves as two staged kernels; 1: one kernel
-        streamed along z (ppm_set_front_form)."""
+        streamed along z; 2: the x axis fused, y and z staged; 3: every
+        axis fused (ppm_set_front_form)."""
         self._check(lib().ppm_set_front_form(self.ctx, int(form)), "ppm_set_front_form")
 
     def get_front_form(self):

@@ -327,12 +327,12 @@ def test_adjoint_with_streamed_front_end_is_bitwise_the_same(precision):
     w = _valid_random(wl.layout, np.random.default_rng(31))
     dt = _dt(wl)
     outs = []
-    for front in (0, 1):
+    for front in (0, 1, 2, 3):
         lay = wl.layout
         lev = P.Level(lay)
-        if front:
+        if front == 1:
             lev.set_front_tiling(8, 4, 5)
-            lev.set_front_form(1)
+        lev.set_front_form(front)
         p = P.params(gamma=wl.gamma, grav=wl.grav, precision=precision)
         U = torch.from_numpy(wl.arena).cuda()
         lev.fill_boundary(U)
@@ -341,7 +341,8 @@ def test_adjoint_with_streamed_front_end_is_bitwise_the_same(precision):
         outs.append(Ub.cpu().numpy())
         assert lev.check_status() == 0
         lev.close()
-    assert np.array_equal(outs[0], outs[1])
+    for k in range(1, 4):
+        assert np.array_equal(outs[0], outs[k]), k
 
 
 def test_rollout_with_saved_segments_equals_recompute_bitwise():

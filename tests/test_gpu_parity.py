@@ -473,22 +473,29 @@ FRONT_FORMS = [(16, 8, 32), (4, 4, 3), (11, 11, 5), (64, 2, 64), (7, 3, 7), (1, 
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_front_forms_agree_bitwise(precision):
-    """The streamed front end (trace and stage-1 solves in one kernel, x-y
-    tiles walked along z) with tiles larger and smaller than the boxes,
-    single-zone tiles and runs that split the boxes' z extent unevenly, in
-    both launch forms and with the streamed final stage too, gives the
-    staged front end's state, flux output and next dt bit for bit: uneven
-    boxes, walls, gravity."""
+    """The fused front ends (trace and stage-1 solves in one kernel: x-y
+    tiles walked along z, with tiles larger and smaller than the boxes,
+    single-zone tiles and runs that split the boxes' z extent unevenly; the
+    x axis alone; every axis with wavefront patches), in both launch forms
+    and with the fused final stages too, give the staged front end's state,
+    flux output and next dt bit for bit: uneven boxes, walls, gravity."""
     wl = _uneven_level(seed=9, bc=(0, 0, 1, 1, 2, 2), sizes=(6, 8, 12, 20))
     wl.grav = (0.0, 0.0, -1.0)
     wl.precision = precision
     cases = [(None, 0, P.BATCHED)] + [(sh, 0, P.BATCHED) for sh in FRONT_FORMS] + \
-        [(FRONT_FORMS[1], 0, P.PER_BOX), (FRONT_FORMS[0], 2, P.BATCHED), (FRONT_FORMS[3], 1, P.PER_BOX)]
+        [(FRONT_FORMS[1], 0, P.PER_BOX), (FRONT_FORMS[0], 2, P.BATCHED), (FRONT_FORMS[3], 1, P.PER_BOX)] + \
+        [("x", 0, P.BATCHED), ("x", 0, P.PER_BOX), ("x", 1, P.BATCHED), ("x", 2, P.PER_BOX)] + \
+        [("xyz", 0, P.BATCHED), ("xyz", 0, P.PER_BOX), ("xyz", 1, P.BATCHED), ("xyz", 2, P.PER_BOX)]
     outs = []
     for shape, final, mode in cases:
         print(f"front tile {shape}, final-stage form {final}, mode {mode}, precision {precision}", flush=True)
         lev = P.Level(wl.layout)
-        if shape:
+        if shape is None:
+            lev.set_front_form(0)
+        elif shape in ("x", "xyz"):
+            lev.set_front_form(2 if shape == "x" else 3)
+            assert lev.get_front_form() == (2 if shape == "x" else 3)
+        else:
             lev.set_front_tiling(*shape)
             lev.set_front_form(1)
             assert lev.get_front_form() == 1 and lev.get_front_tiling() == shape
@@ -525,7 +532,7 @@ def test_front_tiling_rejects_oversized_tiles():
     with pytest.raises(P.PPMError, match="front_tiling"):
         lev.set_front_tiling(16, 16, 8)  # 256 zones per tile
     with pytest.raises(P.PPMError, match="front_form"):
-        lev.set_front_form(2)
+        lev.set_front_form(4)
     lev.close()
 
 
