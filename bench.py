@@ -201,6 +201,14 @@ WORKLOADS = {
 }
 
 
+def stage_units_axis(n, d):
+    """riemann1's units (faces) along axis d of one box of valid extents n."""
+    import numpy as np
+    w = np.asarray(n, dtype=np.int64)
+    e = w + 2
+    return int((w[d] + 1) * np.prod([e[t] for t in range(3) if t != d]))
+
+
 def make_workload(name):
     from paper_1008_2801_amd import inputs as I
     if name == "cfg5":
@@ -784,18 +792,22 @@ def roofline(wname, lay, prof, ms_step, precision, tiling):
             units[k] += v
     table = flops_table(wname)
     # with a fused final stage (brick or streamed form) one kernel does the
-    # riemann3 and update work, timed in the riemann3 slot; with a fused
-    # front end (any form but the staged one) the trace and riemann1 slots
-    # hold kernels that share the two stages' work, priced together
+    # riemann3 and update work, timed in the riemann3 slot.  The fused front
+    # ends are timed in the trace slot: form 2 (x fused) holds the x axis's
+    # riemann1 work there, the riemann1 slot the y and z axes'; forms 1 and 3
+    # hold all of it there
     fused = len(tiling) > 2 and tiling[2] != 0
-    ffront = len(tiling) > 3 and tiling[3] != 0
-    stages = {k: prof[k] for k in STAGES if not (fused and k == "update") and not (ffront and k == "riemann1")}
+    front = tiling[3] if len(tiling) > 3 else 0
+    stages = {k: prof[k] for k in STAGES if not (fused and k == "update") and not (front in (1, 3) and k == "riemann1")}
     flops_of = {k: table[k] * units[k] for k in stages}
     if fused:
         flops_of["riemann3"] += table["update"] * units["update"]
-    if ffront:
-        stages["trace"] = (prof["trace"][0] + prof["riemann1"][0], prof["trace"][1])
+    if front in (1, 3):
         flops_of["trace"] += table["riemann1"] * units["riemann1"]
+    elif front == 2:
+        ux = sum(stage_units_axis(lay.n(b), 0) for b in range(lay.nbox))
+        flops_of["trace"] += table["riemann1"] * ux
+        flops_of["riemann1"] -= table["riemann1"] * ux
     dom = max(stages, key=lambda k: stages[k][0])
     t_ms, cnt = stages[dom]
     mean_s = t_ms / cnt / 1e3
@@ -809,8 +821,10 @@ def roofline(wname, lay, prof, ms_step, precision, tiling):
     if fused and dom == "riemann3":
         name = ("final_update (riemann3 + update, brick form)" if tiling[2] == 1 else
                 "final_stream (riemann3 + update, streamed form)")
-    elif ffront and dom == "trace":
-        name = f"front end (trace + riemann1, {FRONT_FORMS[tiling[3]]} form)"
+    elif front and dom == "trace":
+        name = f"trace slot ({FRONT_FORMS[front]} front end: its fused kernels and any staged trace)"
+    elif front == 2 and dom == "riemann1":
+        name = "riemann1 (y and z axes)"
     r = {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
          "frac": achieved / peak,
          "traffic": rec.get("traffic_bytes_per_launch") if rec else None,
