@@ -422,33 +422,6 @@ int ppm_get_front_form(const ppm_ctx* ctx, int32_t* form);
 int ppm_set_front_tiling(ppm_ctx* ctx, int32_t sx, int32_t sy, int32_t sz);
 int ppm_get_front_tiling(const ppm_ctx* ctx, int32_t* sx, int32_t* sy, int32_t* sz);
 
-/* Diagnostic: out[i] = one of the FP64 square roots the Riemann solver
- * takes, computed on the device for n arguments x[i].  form 0: the root of
- * the wave-speed factor 1 + beta (p/p_s - 1) (>= 1 - beta > 0; the
- * Lagrangian shock speed of Colella-Glaz 1985 is C_s times it); form 1: the
- * root of gamma p rho (the Lagrangian sound speed C_s) and of the star
- * state's gamma p / rho; form 2: the FP32 root of the wave-speed factor,
- * taken of (float) x[i] and returned widened to double.  x and out are
- * device pointers of n doubles, owned by the caller; asynchronous on the
- * stream.  The kernels use the core of the compiler's correctly rounded
- * square root without its rescaling of small arguments (form 0 and 2 also
- * without the fix-up of 0 and +inf): the IEEE root for every finite
- * argument >= 2^-767 (form 2: >= 2^-96; form 1: also for 0, +inf, negative
- * and NaN arguments), which a test checks against the host's.  PPM_EINVAL
- * for n < 0, null pointers with n > 0, or another form. */
-int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream);
-
-/* Diagnostic: out[i] = a[i] / b[i] as the kernels divide in FP64 (the
- * Riemann solver, the corrected states, tracing and flattening), computed
- * on the device for n operand pairs.  a, b and out are device pointers of n
- * doubles, owned by the caller; asynchronous on the stream.  The kernels use
- * the compiler's correctly rounded division without its operand scaling;
- * it returns the IEEE quotient when the exponents of a and b lie in
- * [-900, 900] and differ by at most 700, and for zero, infinite and NaN
- * operands, which a test checks against the host's.  PPM_EINVAL for n < 0
- * or null pointers with n > 0. */
-int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n, void* stream);
-
 /* Autotuner: times the batched step as graphs and steady loops run it
  * (ppm_hydro_step_dt, the next dt left on the device; reps steps after one
  * warm-up, HIP events on the stream) from the filled state U into Unew for

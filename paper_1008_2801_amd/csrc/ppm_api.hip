@@ -847,16 +847,6 @@ int ppm_hydro_step_noalloc(ppm_ctx* ctx, const double* U, double* Unew, double* 
                          (size_t)PPM_NOALLOC_SCRATCH_BYTES, false);
 }
 
-int ppm_sqrt_values(const double* x, double* out, int64_t n, int32_t form, void* stream) {
-  if (n < 0 || (n > 0 && (!x || !out)) || form < 0 || form > 2) return PPM_EINVAL;
-  return ppm::launch_sqrt_form(x, out, n, form, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
-}
-
-int ppm_quotient_values(const double* a, const double* b, double* out, int64_t n, void* stream) {
-  if (n < 0 || (n > 0 && (!a || !b || !out))) return PPM_EINVAL;
-  return ppm::launch_quotient(a, b, out, n, (hipStream_t)stream) == hipSuccess ? PPM_OK : PPM_EHIP;
-}
-
 int ppm_set_step_form(ppm_ctx* ctx, int32_t fused) {
   if (!ctx) return PPM_EINVAL;
   if (fused < 0 || fused > 2) return ctx->fail(PPM_EINVAL, "set_step_form: fused must be 0, 1 or 2");

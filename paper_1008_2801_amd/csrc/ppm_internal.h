@@ -156,8 +156,6 @@ struct DevLevel {
 
 // Kernel launchers (ppm_kernels.hip).  Each returns the hipError_t of the launch.
 namespace ppm {
-hipError_t launch_sqrt_form(const double* x, double* out, long long n, int form, hipStream_t s);
-hipError_t launch_quotient(const double* a, const double* b, double* out, long long n, hipStream_t s);
 hipError_t launch_step_consts(const DevLevel& L, double dt, const double* dt_dev, const double h[3],
                               const double g[3], hipStream_t s);
 hipError_t launch_fill(const DevLevel& L, double* U, int desc_begin, int desc_end, long long zone_begin,

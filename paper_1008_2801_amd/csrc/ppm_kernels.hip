@@ -1127,22 +1127,6 @@ hipError_t step_impl(const DevLevel& L, int tS0, int tS1, int tE0, int tE1, int 
   return hipGetLastError();
 }
 
-// Values of the kernels' FP64 quotient for a list of operand pairs (grid-stride).
-__global__ void __launch_bounds__(256) k_quotient(const double* __restrict__ a, const double* __restrict__ b,
-                                                  double* __restrict__ out, long long n) {
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-    out[i] = qdiv(a[i], b[i]);
-}
-
-// Values of the kernels' roots for a list of arguments (grid-stride): form
-// 0 the FP64 wave-speed root, 1 the FP64 sound-speed root, 2 the FP32
-// wave-speed root of (float) x, widened back to double.
-__global__ void __launch_bounds__(256) k_sqrt_form(const double* __restrict__ x, double* __restrict__ out,
-                                                   long long n, int form) {
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
-    out[i] = form == 0 ? sqrt_wave(x[i]) : (form == 1 ? sqrt_phys(x[i]) : (double)sqrt_wave((float)x[i]));
-}
-
 }  // namespace
 
 hipError_t launch_step_consts(const DevLevel& L, double dt, const double* dt_dev, const double h[3],
@@ -1172,21 +1156,6 @@ hipError_t launch_compute_dt(const DevLevel& L, int tile_begin, int tile_end, co
     hipLaunchKernelGGL(k_wavespeed, dim3(n < 2048 ? n : 2048), dim3(L.tile), 0, s, L.tilesE + tile_begin, n, L.boxes, U,
                        h[0], h[1], h[2], gamma, gamma - 1.0, small_pres, bits);
   hipLaunchKernelGGL(k_finish_dt, dim3(1), dim3(64), 0, s, dt_dev, cfl);
-  return hipGetLastError();
-}
-
-hipError_t launch_quotient(const double* a, const double* b, double* out, long long n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const long long blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_quotient, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, s, a, b, out, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_sqrt_form(const double* x, double* out, long long n, int form, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  const long long blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_sqrt_form, dim3(blocks < 4096 ? (unsigned)blocks : 4096u), dim3(256), 0, s, x, out, n,
-                     form);
   return hipGetLastError();
 }
 

@@ -32,9 +32,12 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_hydro_step_species", "ppm_amr_create", "ppm_amr_destroy", "ppm_amr_last_error",
            "ppm_amr_sizes", "ppm_amr_fill_fine", "ppm_amr_step", "ppm_set_inflow",
            "ppm_hydro_step_adjoint_saved", "ppm_set_step_form", "ppm_get_step_form",
-           "ppm_sqrt_values", "ppm_quotient_values", "ppm_hydro_step_dt", "ppm_hydro_step_noalloc",
+           "ppm_hydro_step_dt", "ppm_hydro_step_noalloc",
            "ppm_set_stream_tiling", "ppm_get_stream_tiling", "ppm_set_front_form", "ppm_get_front_form",
            "ppm_set_front_tiling", "ppm_get_front_tiling")
+# Every exported symbol of include/ppm_diag.h (libppm_diag.so).
+DIAG_SYMBOLS = ("ppm_diag_sqrt_values", "ppm_diag_quotient_values")
+DIAG_LIB_PATH = os.path.join(HERE, "libppm_diag.so")
 NOALLOC_SCRATCH_BYTES = 128 << 20
 MAX_SPECIES = 64
 PROF_TAGS = ("fill", "dt", "prim", "flatten", "trace", "riemann1", "riemann2", "riemann3", "update")
@@ -132,8 +135,6 @@ def lib():
         L.ppm_get_front_form.argtypes = [_vp, _i32p]
         L.ppm_set_front_tiling.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.ppm_get_front_tiling.argtypes = [_vp, _i32p, _i32p, _i32p]
-        L.ppm_sqrt_values.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
-        L.ppm_quotient_values.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
         L.ppm_amr_create.argtypes = [_vp, _vp, ctypes.POINTER(_vp)]
         L.ppm_amr_destroy.argtypes = [_vp]
         L.ppm_amr_last_error.argtypes = [_vp]
@@ -210,24 +211,41 @@ def plan_cache_stats():
     return a.value, b.value, c.value
 
 
+_diag_handle = None
+
+
+def diag_lib():
+    """The arithmetic diagnostics library (include/ppm_diag.h)."""
+    global _diag_handle
+    if _diag_handle is None:
+        if not os.path.exists(DIAG_LIB_PATH):
+            raise PPMError(f"HIP library not built: {DIAG_LIB_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(DIAG_LIB_PATH)
+        _vp = ctypes.c_void_p
+        L.ppm_diag_sqrt_values.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
+        L.ppm_diag_quotient_values.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
+        _diag_handle = L
+    return _diag_handle
+
+
 def sqrt_values(x, form=0, stream=None):
     """Device values of one of the Riemann solver's square roots (form 0:
     the FP64 wave-speed factor's, 1: the FP64 sound speeds', 2: the FP32
     wave-speed factor's, of x rounded to float) for the float64 CUDA tensor
-    x (diagnostic; ppm_sqrt_values)."""
+    x (diagnostic; ppm_diag_sqrt_values)."""
     import torch
     if x.dtype != torch.float64 or not x.is_cuda or not x.is_contiguous():
         raise PPMError("sqrt_values: x must be a contiguous float64 CUDA tensor")
     out = torch.empty_like(x)
-    rc = lib().ppm_sqrt_values(_ptr(x), _ptr(out), x.numel(), int(form), _stream(stream))
+    rc = diag_lib().ppm_diag_sqrt_values(_ptr(x), _ptr(out), x.numel(), int(form), _stream(stream))
     if rc != 0:
-        raise PPMError(f"ppm_sqrt_values failed ({rc})")
+        raise PPMError(f"ppm_diag_sqrt_values failed ({rc})")
     return out
 
 
 def quotient_values(a, b, stream=None):
     """Device values of the kernels' FP64 quotient a / b for float64 CUDA
-    tensors a, b of one shape (diagnostic; ppm_quotient_values)."""
+    tensors a, b of one shape (diagnostic; ppm_diag_quotient_values)."""
     import torch
     for t in (a, b):
         if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
@@ -235,9 +253,9 @@ def quotient_values(a, b, stream=None):
     if a.shape != b.shape:
         raise PPMError("quotient_values: operands differ in shape")
     out = torch.empty_like(a)
-    rc = lib().ppm_quotient_values(_ptr(a), _ptr(b), _ptr(out), a.numel(), _stream(stream))
+    rc = diag_lib().ppm_diag_quotient_values(_ptr(a), _ptr(b), _ptr(out), a.numel(), _stream(stream))
     if rc != 0:
-        raise PPMError(f"ppm_quotient_values failed ({rc})")
+        raise PPMError(f"ppm_diag_quotient_values failed ({rc})")
     return out
 
 

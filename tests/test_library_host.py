@@ -18,8 +18,8 @@ from paper_1008_2801_amd import ppm as P
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    txt = open(os.path.join(ROOT, "include", "ppm.h")).read()
+def declared_functions(header="ppm.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ppm_[a-z_0-9]+)\s*\(", txt, flags=re.M)))
 
@@ -31,6 +31,17 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(P.SYMBOLS)
+
+
+def test_diagnostics_library_exports_its_declared_symbols():
+    """The arithmetic diagnostics live in a library of their own
+    (include/ppm_diag.h, libppm_diag.so), outside the step's ABI."""
+    names = declared_functions("ppm_diag.h")
+    assert set(names) == set(P.DIAG_SYMBOLS)
+    L = P.diag_lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert not set(names) & set(P.SYMBOLS)
 
 
 def _layouts():
