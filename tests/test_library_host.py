@@ -217,3 +217,40 @@ def test_roofline_flop_figures_are_the_op_counting_oracles():
             assert abs(v - flops[k]) <= 0.006, (wl, k, v, flops[k])
     for n in ((256, 256, 256), (16, 24, 8), (1, 3, 5)):
         assert bench.stage_units(n) == opcount.units(n), n
+
+
+def test_roofline_prices_fused_slots_by_their_kernels_work():
+    """bench.py's roofline: with the x-fused front end the trace slot holds
+    the tracing plus the x axis's stage-1 solves and the riemann1 slot the y
+    and z solves; with a fused final stage the riemann3 slot holds the
+    update's work too; the staged forms price each slot by its own stage."""
+    import bench
+    from paper_1008_2801_amd import inputs as I
+    lay = I.cfg5(nb=2, m=8).layout
+    table = bench.flops_table("cfg5")
+    units = {k: 0 for k in bench.STAGES}
+    ux = 0
+    for b in range(lay.nbox):
+        for k, v in bench.stage_units(lay.n(b)).items():
+            units[k] += v
+        ux += bench.stage_units_axis(lay.n(b), 0)
+    assert ux * 3 == units["riemann1"]  # cubes: the same faces per axis
+
+    def prof(**ms):
+        return {k: (ms.get(k, 1.0), 1) for k in bench.STAGES}
+    # staged: riemann2 dominant, priced alone
+    r = bench.roofline("cfg5", lay, prof(riemann2=9.0), 20.0, 0, [256, 0, 0, 0])
+    assert r["kernel"] == "riemann2" and r["flops_per_launch"] == table["riemann2"] * units["riemann2"]
+    # x-fused front end, its slot dominant: tracing + the x axis's solves
+    r = bench.roofline("cfg5", lay, prof(trace=9.0), 20.0, 0, [256, 0, 0, 2])
+    assert r["kernel"].startswith("trace slot")
+    assert abs(r["flops_per_launch"] - (table["trace"] * units["trace"] + table["riemann1"] * ux)) < 1e-3
+    # x-fused front end, the riemann1 slot dominant: the y and z solves only
+    r = bench.roofline("cfg5", lay, prof(riemann1=9.0), 20.0, 0, [256, 0, 0, 2])
+    assert r["kernel"].startswith("riemann1")
+    assert abs(r["flops_per_launch"] - table["riemann1"] * (units["riemann1"] - ux)) < 1e-3
+    # brick final stage dominant: riemann3 + update
+    r = bench.roofline("cfg5", lay, prof(riemann3=9.0), 20.0, 0, [256, 0, 1, 2])
+    assert r["kernel"].startswith("final_update")
+    assert abs(r["flops_per_launch"] - (table["riemann3"] * units["riemann3"] +
+                                        table["update"] * units["update"])) < 1e-3
