@@ -13,6 +13,13 @@
 // quantity, every box's grid contiguous inside a plane), so each lane of a
 // wavefront touches consecutive addresses on every load and store.
 //
+// Fused forms of some stage pairs cut that traffic and give the same bits:
+// the front end (trace + riemann1) along x with the face states exchanged
+// by lane shuffles (k_front_x, the default), also along y and z
+// (k_front_yz), or streamed along z through LDS (k_front_stream); the final
+// stage (riemann3 + update) in bricks (k_final_update) or streamed along z
+// (k_final_stream), the final fluxes kept in LDS.
+//
 // Every formula is a C expression evaluated as written (no contraction:
 // built with -ffp-contract=off).  The pointwise arithmetic (ppm_math.h)
 // uses reciprocal forms of the method's divisions, so the results agree
