@@ -130,19 +130,23 @@ __device__ __forceinline__ void flatten_body(int t, const Tile* __restrict__ til
     for (int d = 0; d < 3; ++d) {
       const long long st = stride(NS, d);
       const S* uu = prim + (1 + d) * LS + base;
+      // p at offsets -2..2 and u at -2..2 (index offset + 3, offset + 2)
+      // are read here; p at -3 and 3 only by a neighbour's coefficient at a
+      // strong compression (a branch that, away from shocks, no lane of a
+      // wave takes)
       S p[7], u[5];
 #pragma unroll
-      for (int o = -3; o <= 3; ++o) p[o + 3] = pp[o * st];
+      for (int o = -2; o <= 2; ++o) p[o + 3] = pp[o * st];
 #pragma unroll
       for (int o = -2; o <= 2; ++o) u[o + 2] = uu[o * st];
-      // shock-detector coefficient at offset o (p index o+3, u index o+2);
-      // the pressure ratio (one division) only where the zone is a strong
-      // compression, which away from shocks no lane of a wave is
+      // shock-detector coefficient at offset o; the pressure ratio (one
+      // division) only where the zone is a strong compression
       auto chit = [&](int o) -> S {
         const S dp1 = p[o + 4] - p[o + 2];
         const bool compress = (u[o + 1] - u[o + 3]) > S(0);
         const bool strong = sabs(dp1) > C033 * smin(p[o + 4], p[o + 2]);
         if (!(compress && strong)) return S(0);
+        if (o != 0) p[3 + 3 * o] = pp[3 * o * st];
         const S dp2 = p[o + 5] - p[o + 1];
         const S zeta = qdiv(sabs(dp1), smax(sabs(dp2), G.small_pres));
         return smin(smax(TEN * (zeta - C075), S(0)), ONE);
