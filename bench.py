@@ -282,10 +282,14 @@ def level_rates(wl, steps, warmup, precision, per_box=True):
     return out
 
 
-def adjoint_costs(wl, nsteps, every, reps=3, precision=0, rollout=True):
+def adjoint_costs(wl, nsteps, every, reps=10, precision=0, rollout=True):
     """Per-step forward and adjoint times (the adjoint includes its own
     recompute of the forward intermediates) and the whole checkpointed
-    roll-out, forward vs backward."""
+    roll-out, forward vs backward.  Per-step times are medians over `reps`
+    calls, each bracketed by its own events, after two untimed calls; they
+    are taken with the level's default launch configuration and again with
+    the autotuned one (the headline's), which is the one the roll-out uses."""
+    import numpy as np
     import torch
     from paper_1008_2801_amd import ppm as P
     lay = wl.layout
@@ -300,33 +304,40 @@ def adjoint_costs(wl, nsteps, every, reps=3, precision=0, rollout=True):
     lev.ensure_workspace(precision)
     lev.ensure_adjoint_workspace(precision)
 
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+    def timed(fn, before=None):
+        ts = []
+        for r in range(reps + 2):
+            if before is not None:
+                before()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
-    t_fwd = timed(lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
-    t_adj = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv))
-    # the adjoint on the intermediates the forward step left in its workspace
-    acc = 0.0
-    for r in range(reps + 1):
-        lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv, saved=True)
-        e1.record()
-        torch.cuda.synchronize()
-        if r > 0:
-            acc += e0.elapsed_time(e1)
-    t_sav = acc / reps
+            e1.record()
+            torch.cuda.synchronize()
+            if r >= 2:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    def costs():
+        t_fwd = timed(lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
+        t_adj = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv))
+        # the adjoint on the intermediates the forward step left in its workspace
+        t_sav = timed(lambda: lev.hydro_step_adjoint(U, W, Ub, wl.dx, p, dt_dev=dtv, saved=True),
+                      before=lambda: lev.hydro_step(U, V, wl.dx, p, dt_dev=dtv))
+        return t_fwd, t_adj, t_sav
+
+    d_fwd, d_adj, d_sav = costs()
+    Uf = U.clone()
+    _, _, from_cache = lev.autotune(Uf, wl.dx, p, reps=2, cache_path=AUTOTUNE_CACHE)
+    del Uf
+    t_fwd, t_adj, t_sav = costs()
     res = {"precision": "f64" if precision == 0 else "f32 reconstruction + f64 update",
+           "launch_config": launch_config(lev), "autotune_from_cache": bool(from_cache),
            "forward_step_ms": t_fwd, "adjoint_step_ms": t_adj, "adjoint_over_forward": t_adj / t_fwd,
-           "adjoint_step_saved_ms": t_sav, "adjoint_saved_over_forward": t_sav / t_fwd}
+           "adjoint_step_saved_ms": t_sav, "adjoint_saved_over_forward": t_sav / t_fwd,
+           "default_launch_config": {"forward_step_ms": d_fwd, "adjoint_step_ms": d_adj,
+                                     "adjoint_over_forward": d_adj / d_fwd, "adjoint_step_saved_ms": d_sav,
+                                     "adjoint_saved_over_forward": d_sav / d_fwd}}
     if not rollout:
         res["flags"] = lev.check_status()
         lev.close()

@@ -214,8 +214,7 @@ __device__ __forceinline__ void adj_r3_axes(const Tile* __restrict__ tiles, int 
   }
 }
 
-// FP64: asking for 3 waves per SIMD (a few spilled values) beats the 2 the
-// compiler's own register choice allows; FP32 already fits 5.
+// FP64: held to 3 waves per SIMD (it fits without spilling); FP32 fits 5.
 __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3)))
 k_adj_r3_f64(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
              const double* __restrict__ work, long long LE, double* __restrict__ aw, Gas<double> G,
@@ -265,7 +264,7 @@ __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restri
   cons_to_prim_dec(ueR, G, R, rfR, pfR);
   const int ws = wall_states<d>(B, xd, L, R);  // a replaced state gets no adjoint
   S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
-  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  riemann_vjp<d, true>(L, R, G, Fb, Lb, Rb);
   wall_states_vjp<d>(ws, Lb, Rb);
   S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
   cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
@@ -378,7 +377,9 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
     const S* bm = a + (A_U2 + (pb * 2 + 1) * 5 + m) * LE;
     const S sa = (ap[0] + am[0]) - (ap[-sd] + am[-sd]);
     const S sb = (bp[0] + bm[0]) - (bp[-sd] + bm[-sd]);
-    Fb[m] = c3 * sa + c3 * sb;
+    // formed before the solve starts (opaque): otherwise the twenty loads
+    // stay in flight, in registers, through the forward solve
+    Fb[m] = opaque(c3 * sa + c3 * sb);
   }
   S L[5], R[5];
 #pragma unroll
@@ -451,7 +452,9 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
   S phib = 0;
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    const S* p = prim + m * LS + base;
+    // reloaded (opaque address: not the registers of the first loads, which
+    // would stay live through the tracing reverse)
+    const S* p = opaque(prim + m * LS + base);
     const S as5[5] = {p[-2 * st], p[-st], p[0], p[st], p[2 * st]};
     S ab[5] = {0, 0, 0, 0, 0};
     ppm_parabola_vjp(as5, phi, G, aLb[m], aRb[m], a6b[m], ab, phib);

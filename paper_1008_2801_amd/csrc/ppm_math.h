@@ -36,7 +36,20 @@ template <class S> struct Gas {
 // ------------------------------------------------------------ helpers ------
 template <class S> PPM_HD S smax(S a, S b) { return (a < b) ? b : a; }
 template <class S> PPM_HD S smin(S a, S b) { return (b < a) ? b : a; }
-template <class S> PPM_HD S sabs(S a) { return (a < S(0)) ? -a : a; }
+// |a| (the sign bit cleared: one instruction, or free as an operand modifier)
+PPM_HD double sabs(double a) { return __builtin_fabs(a); }
+PPM_HD float sabs(float a) { return __builtin_fabsf(a); }
+// min and max of two values that are not NaN (the hardware min and max)
+PPM_HD double fmin2(double a, double b) { return __builtin_fmin(a, b); }
+PPM_HD float fmin2(float a, float b) { return __builtin_fminf(a, b); }
+// x with its sign flipped where s is negative (sign bit set)
+PPM_HD double flipsign(double x, double s) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) ^
+                                        (__builtin_bit_cast(unsigned long long, s) & 0x8000000000000000ull));
+}
+PPM_HD float flipsign(float x, float s) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(unsigned, x) ^ (__builtin_bit_cast(unsigned, s) & 0x80000000u));
+}
 PPM_HD double ssqrt(double x) { return __builtin_sqrt(x); }
 PPM_HD float ssqrt(float x) { return __builtin_sqrtf(x); }
 // a / b.  FP64 on the device: the correctly rounded division hipcc emits
@@ -124,7 +137,8 @@ PPM_HD double sqrt_phys(double x) {
 #endif
 }
 PPM_HD float sqrt_phys(float x) { return __builtin_sqrtf(x); }
-template <class S> PPM_HD S scopysign(S m, S s) { return __builtin_signbit(s) ? -m : m; }
+PPM_HD double scopysign(double m, double s) { return __builtin_copysign(m, s); }
+PPM_HD float scopysign(float m, float s) { return __builtin_copysignf(m, s); }
 // 2^-120 <= x <= 2^120 for a state's density, pressure and sound speed,
 // |u| <= 2^120 for its velocity components (no quotient divides by a
 // velocity): the magnitudes for which every quotient and root the step
@@ -279,7 +293,9 @@ PPM_HD S ppm_slope(S am, S a0, S ap, int limiter) {
   const S dc = HALF * (ap - am);
   if (!limiter) return dc;
   const S dl = a0 - am, dr = ap - a0;
-  if (same_sign(dl, dr)) return scopysign(smin(smin(sabs(dc), TWO * sabs(dl)), TWO * sabs(dr)), dc);
+  // dl dr > 0 makes dc, dl and dr nonzero and finite (or infinite), so the
+  // hardware min and the sign copy give the plain definition's value
+  if (same_sign(dl, dr)) return scopysign(fmin2(fmin2(sabs(dc), TWO * sabs(dl)), TWO * sabs(dr)), dc);
   return S(0);
 }
 

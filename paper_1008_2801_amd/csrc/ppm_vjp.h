@@ -10,6 +10,18 @@
 
 namespace ppm {
 
+// The value x, hidden from the compiler's common-subexpression elimination
+// (an empty asm statement that claims to modify x, no instruction).  A
+// reverse pass that recomputes a forward quantity from opaque(x) gets a
+// fresh value; without it the compiler would reuse the forward pass's value
+// and keep it live in registers from the forward to the reverse pass.
+template <class S> PPM_HD S opaque(S x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+
 // --------------------------------------------------------------- flux ------
 // F = flux of the rotated state g = (rho, u_n, p, u_t1, u_t2) along d (xyz
 // component order).  gb += (dF/dg)^T Fb.
@@ -97,7 +109,8 @@ PPM_HD void sample_side_vjp(S ro, S uo, S po, S C, S W, S iW, S us, S p, const G
   rob -= irhob * irho * irho;
 }
 
-// Newton steps whose records the Riemann reverse keeps in registers.
+// Newton steps whose input pressures the Riemann reverse keeps in registers
+// (the reverse of such a step recomputes its forward from that pressure).
 constexpr int RIEM_KEEP = 3;
 
 // One Newton step of the two-shock iteration, forward (returns the new p).
@@ -201,7 +214,10 @@ PPM_HD S riem_iter_vjp(S p, S cl, S cr, S pl, S pr, S ul, S ur, S ipl, S ipr, co
 }
 
 // Reverse of riemann<d>: Fb = adjoint of the flux; accumulates Lb, Rb.
-template <int d, class S>
+// REC: keep each kept Newton step's full record in registers (no forward
+// recomputation in the reverse sweep, more registers) instead of its input
+// pressure alone.
+template <int d, bool REC = false, class S>
 PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[5], S Lb[5], S Rb[5]) {
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
   const S rl = L[0], ul = L[1 + d], pl = L[4];
@@ -214,14 +230,20 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   const bool fl0 = p0r < G.small_pres;
   const S p0 = smax(p0r, G.small_pres);
   const S ipl = qdiv(ONE, pl), ipr = qdiv(ONE, pr);
-  // the first RIEM_KEEP Newton steps are recorded for the reverse sweep
-  // (fully unrolled, so the records stay in registers); later ones are
-  // recomputed from the output of the last recorded one
-  RiemIt<S> rec[RIEM_KEEP];
+  // the input pressures of the first RIEM_KEEP Newton steps (with REC their
+  // full records) are kept for the reverse sweep (fully unrolled, so they
+  // stay in registers); later steps are recomputed from the output of the
+  // last kept one
+  S pin[RIEM_KEEP];
+  RiemIt<S> rec[REC ? RIEM_KEEP : 1];
   S pst = p0;
 #pragma unroll
   for (int it = 0; it < RIEM_KEEP; ++it)
-    if (it < G.iters) pst = riem_iter_rec(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G, rec[it]);
+    if (it < G.iters) {
+      pin[it] = pst;
+      if constexpr (REC) pst = riem_iter_rec(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G, rec[it]);
+      else pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
+    }
   const S pkeep = pst;
   for (int it = RIEM_KEEP; it < G.iters; ++it) pst = riem_iter(pst, cl, cr, pl, pr, ul, ur, ipl, ipr, G);
   const S all = ONE + G.beta * (pst * ipl - ONE), alr = ONE + G.beta * (pst * ipr - ONE);
@@ -258,19 +280,24 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   S rlb = S(0), ulb = S(0), plb = S(0), clb = S(0), iwlb = S(0);
   S rrb = S(0), urb = S(0), prb = S(0), crb = S(0), iwrb = S(0);
   S usb = S(0), pstb = S(0);
-  if (us > S(0)) {
-    sample_side_vjp(rl, ul, pl, cl, wl, iwl, us, pst, G, gb[0], gb[1], gb[2], rlb, ulb, plb, clb, iwlb, usb,
-                    pstb);
-    Lb[1 + t1] += gb[3];
-    Lb[1 + t2] += gb[4];
-  } else if (us < S(0)) {
-    S uob = S(0), usbm = S(0);
-    sample_side_vjp(rr, -ur, pr, cr, wr, iwr, -us, pst, G, gb[0], -gb[1], gb[2], rrb, uob, prb, crb, iwrb,
-                    usbm, pstb);
-    urb -= uob;
-    usb -= usbm;
-    Rb[1 + t1] += gb[3];
-    Rb[1 + t2] += gb[4];
+  if (us != S(0)) {
+    // one side sampled: its inputs selected, its adjoints added to that side
+    const bool left = us > S(0);
+    const S sg = left ? ONE : -ONE;
+    S rob = S(0), uob = S(0), pob = S(0), Cb = S(0), iWb = S(0), usbs = S(0);
+    sample_side_vjp(left ? rl : rr, left ? ul : -ur, left ? pl : pr, left ? cl : cr, left ? wl : wr,
+                    left ? iwl : iwr, left ? us : -us, pst, G, gb[0], sg * gb[1], gb[2], rob, uob, pob, Cb, iWb,
+                    usbs, pstb);
+    usb = sg * usbs;
+    // selects, not branches, so that the compiler keeps the adjoints in registers
+    rlb = left ? rob : S(0); ulb = left ? uob : S(0); plb = left ? pob : S(0);
+    clb = left ? Cb : S(0); iwlb = left ? iWb : S(0);
+    rrb = left ? S(0) : rob; urb = left ? S(0) : -uob; prb = left ? S(0) : pob;
+    crb = left ? S(0) : Cb; iwrb = left ? S(0) : iWb;
+    Lb[1 + t1] += left ? gb[3] : S(0);
+    Lb[1 + t2] += left ? gb[4] : S(0);
+    Rb[1 + t1] += left ? S(0) : gb[3];
+    Rb[1 + t2] += left ? S(0) : gb[4];
   } else {
     const S h0 = HALF * gb[0], h1 = HALF * gb[1], h2 = HALF * gb[2];
     sample_side_vjp(rl, ul, pl, cl, wl, iwl, us, pst, G, h0, h1, h2, rlb, ulb, plb, clb, iwlb, usb, pstb);
@@ -311,9 +338,14 @@ PPM_HD void riemann_vjp(const S L[5], const S R[5], const Gas<S>& G, const S Fb[
   }
 #pragma unroll
   for (int k = RIEM_KEEP - 1; k >= 0; --k)
-    if (k < G.iters)
-      pb = riem_iter_vjp_rec(rec[k], cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb,
-                             iprb);
+    if (k < G.iters) {
+      if constexpr (REC)
+        pb = riem_iter_vjp_rec(rec[k], cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb, iplb,
+                               iprb);
+      else
+        pb = riem_iter_vjp(opaque(pin[k]), cl, cr, pl, pr, ul, ur, ipl, ipr, G, pb, clb, crb, plb, prb, ulb, urb,
+                           iplb, iprb);
+    }
   // acoustic guess (floor frozen)
   if (!fl0) {
     const S iD0 = qdiv(ONE, D0);
@@ -435,16 +467,17 @@ PPM_HD void ppm_slope_vjp(S am, S a0, S ap, int limiter, S sb, S& amb, S& a0b, S
     const S m1 = smin(A, B);
     const bool selA = !(B < A);
     const bool selm1 = !(C < m1);
-    const S Mb = __builtin_signbit(dc) ? -sb : sb;
+    const S Mb = flipsign(sb, dc);
     S Ab = S(0), Bb = S(0), Cb = S(0);
     if (selm1) {
       if (selA) Ab = Mb; else Bb = Mb;
     } else {
       Cb = Mb;
     }
-    dcb = (dc < S(0)) ? -Ab : Ab;
-    const S dlb = TWO * ((dl < S(0)) ? -Bb : Bb);
-    const S drb = TWO * ((dr < S(0)) ? -Cb : Cb);
+    // dc, dl, dr are nonzero here: the sign flips are the products with their signs
+    dcb = flipsign(Ab, dc);
+    const S dlb = TWO * flipsign(Bb, dl);
+    const S drb = TWO * flipsign(Cb, dr);
     a0b += dlb - drb;
     amb -= dlb;
     apb += drb;
