@@ -592,12 +592,13 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
   const DevBox B = boxes[tl.box];
   const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
   const long long NSS = (long long)NS[0] * NS[1] * NS[2];
-  const long long idx = (long long)tl.start + threadIdx.x;
+  const int idx = tl.start + (int)threadIdx.x;  // below 2^31: tile bounds are ints
   if (idx >= tl.end) return;
   int j[3];
-  j[0] = (int)(idx % NS[0]) - NG;
-  j[1] = (int)((idx / NS[0]) % NS[1]) - NG;
-  j[2] = (int)(idx / ((long long)NS[0] * NS[1])) - NG;
+  const unsigned r = div31((unsigned)idx, B.ds[0]), k = div31(r, B.ds[1]);
+  j[0] = idx - (int)r * NS[0] - NG;
+  j[1] = (int)(r - k * (unsigned)NS[1]) - NG;
+  j[2] = (int)k - NG;
   S qb[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {

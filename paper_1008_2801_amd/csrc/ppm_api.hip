@@ -370,6 +370,7 @@ void build_bricks(ppm_ctx& c) {
             K.o[d] = o[d];
             K.e[d] = std::min(E[d], n[d] - o[d]);
           }
+          brick_divisors(K);
           c.bricks.push_back(K);
         }
     c.tB_begin.push_back((int)c.bricks.size());
@@ -411,6 +412,7 @@ void build_front(ppm_ctx& c) {
           K.e[2] = ext[2][z];
           c.front_m[0] = std::max(c.front_m[0], K.e[0]);
           c.front_m[1] = std::max(c.front_m[1], K.e[1]);
+          brick_divisors(K);
           c.fbricks.push_back(K);
         }
     c.tF_begin.push_back((int)c.fbricks.size());
@@ -556,6 +558,10 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
     const long long NS = (long long)(n[0] + 2 * NG) * (n[1] + 2 * NG) * (n[2] + 2 * NG);
     const long long NE = (long long)(n[0] + 2) * (n[1] + 2) * (n[2] + 2);
     for (int d = 0; d < 3; ++d) db[b].n[d] = n[d];
+    for (int d = 0; d < 2; ++d) {
+      db[b].de[d] = make_div31((unsigned)(n[d] + 2));
+      db[b].ds[d] = make_div31((unsigned)(n[d] + 2 * NG));
+    }
     db[b].wall = 0;
     for (int d = 0; d < 3; ++d) {
       if (layout->boxes[b].lo[d] == layout->domain.lo[d] && layout->bc[2 * d] == PPM_BC_REFLECT)

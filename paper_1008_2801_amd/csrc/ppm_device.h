@@ -47,14 +47,13 @@ struct EZone {
 
 __device__ __forceinline__ bool ezone(const Tile& tl, const DevBox& B, EZone& z) {
   z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
-  const long long idx = (long long)tl.start + threadIdx.x;
+  const int idx = tl.start + (int)threadIdx.x;  // below 2^31: tile bounds are ints
   if (idx >= tl.end) return false;
   z.e = idx;
-  const int i = (int)(idx % z.E[0]);
-  const long long r = idx / z.E[0];
-  z.x[0] = i - 1;
-  z.x[1] = (int)(r % z.E[1]) - 1;
-  z.x[2] = (int)(r / z.E[1]) - 1;
+  const unsigned r = div31((unsigned)idx, B.de[0]), k = div31(r, B.de[1]);
+  z.x[0] = idx - (int)r * z.E[0] - 1;
+  z.x[1] = (int)(r - k * (unsigned)z.E[1]) - 1;
+  z.x[2] = (int)k - 1;
   return true;
 }
 

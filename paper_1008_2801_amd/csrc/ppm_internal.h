@@ -15,6 +15,24 @@ constexpr int MAX_TILE = 512;  // largest tile the kernels are built for
 constexpr int NXCD = 8;      // MI355X: 8 accelerator complex dies, 32 CUs each
 constexpr int FILL_THREADS = 256;  // threads per workgroup of the ghost-fill kernels
 
+// Division by an invariant divisor D >= 2 of dividends below 2^31
+// (Granlund and Montgomery, 1994): with l = ceil(log2 D) and
+// m = ceil(2^(31+l) / D), which is below 2^32, floor(n / D) equals
+// (n m) >> (31 + l) for every n < 2^31 — a high multiply and a shift on the
+// device instead of a division sequence.
+struct Div31 {
+  unsigned m;
+  int s;  // l - 1
+};
+inline Div31 make_div31(unsigned D) {
+  int l = 0;
+  while ((1ull << l) < D) ++l;
+  return {(unsigned)(((1ull << (31 + l)) + D - 1) / D), l - 1};
+}
+#if defined(__HIPCC__)
+__device__ __forceinline__ unsigned div31(unsigned n, Div31 q) { return __umulhi(n, q.m) >> q.s; }
+#endif
+
 // Per-box metadata on the device.
 struct DevBox {
   int n[3];           // valid extents
@@ -23,6 +41,8 @@ struct DevBox {
   long long poff;     // offset in each plane of the primitive arena (stored grid, (n+8)^3)
   long long eoff;     // offset in each plane of the traced-grid arenas ((n+2)^3)
   long long foff[3];  // element offsets in the three flux arenas
+  Div31 de[2];        // division by the traced grid's x and y extents, n + 2
+  Div31 ds[2];        // division by the stored grid's x and y extents, n + 8
 };
 
 // A tile: TILE (or fewer, at the end of a box) consecutive linear zones
@@ -77,7 +97,14 @@ constexpr int BRICK_FACES = BRICK_FACES_D(0) > BRICK_FACES_D(1)
 struct Brick {
   int box;
   int o[3], e[3];
+  Div31 d0[2], d1[2];  // division by e_x and e_x + 1, by e_y and e_y + 1
 };
+inline void brick_divisors(Brick& K) {
+  for (int k = 0; k < 2; ++k) {
+    K.d0[k] = make_div31((unsigned)(K.e[0] + k));
+    K.d1[k] = make_div31((unsigned)(K.e[1] + k));
+  }
+}
 
 // One copy of the ghost-fill plan: the dst-box-local region [lo, hi] takes
 // its values from src-box-local zone a*x + c (per axis, a in {1, -1, 0}),

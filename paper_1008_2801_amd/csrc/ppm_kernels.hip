@@ -312,9 +312,9 @@ __global__ void __launch_bounds__(XF_THREADS) k_front_x(const Tile* __restrict__
   const bool own = lane > 0 && idx < tl.end;
   const bool have = own || (lane == 0 && idx >= 0 && idx < tl.end);
   const int E0 = B.n[0] + 2, E1 = B.n[1] + 2;
-  const long long row = have ? idx / E0 : 0;
-  const int x = have ? (int)(idx - row * E0) - 1 : 0;
-  const int y = (int)(row % E1) - 1, z = (int)(row / E1) - 1;
+  const unsigned row = have ? div31((unsigned)idx, B.de[0]) : 0u, k = div31(row, B.de[1]);
+  const int x = have ? (int)(idx - (long long)row * E0) - 1 : 0;
+  const int y = (int)(row - k * (unsigned)E1) - 1, z = (int)k - 1;
   S qp[5], qm[5];
   int fl = 0;
   if (have) {
@@ -786,7 +786,8 @@ __device__ __forceinline__ void brick_faces(const Brick& K, const DevBox& B, con
   ex[d] += 1;
   const int nf = ex[0] * ex[1] * ex[2];
   for (int f = threadIdx.x; f < nf; f += BRICK_THREADS) {
-    const int x[3] = {K.o[0] + f % ex[0], K.o[1] + (f / ex[0]) % ex[1], K.o[2] + f / (ex[0] * ex[1])};
+    const unsigned r = div31((unsigned)f, K.d0[d == 0]), k = div31(r, K.d1[d == 1]);
+    const int x[3] = {K.o[0] + f - (int)r * ex[0], K.o[1] + (int)(r - k * (unsigned)ex[1]), K.o[2] + (int)k};
     S F[5];
     riemann3_face<d>(B, x, work, LE, G, sc, F, fl);
 #pragma unroll
@@ -820,7 +821,8 @@ __global__ void __launch_bounds__(BRICK_THREADS) k_final_update(const Brick* __r
   const long long NS = (long long)N0 * N1 * N2;
   double smax_lane = 0.0;
   for (int z = threadIdx.x; z < e0 * e1 * e2; z += BRICK_THREADS) {
-    const int l0 = z % e0, l1 = (z / e0) % e1, l2 = z / (e0 * e1);
+    const unsigned r = div31((unsigned)z, K.d0[0]), k = div31(r, K.d1[0]);
+    const int l0 = z - (int)r * e0, l1 = (int)(r - k * (unsigned)e1), l2 = (int)k;
     const int ix = (l2 * e1 + l1) * (e0 + 1) + l0;        // x-face below the zone
     const int iy = (l2 * (e1 + 1) + l1) * e0 + l0;        // y-face below
     const int iz = (l2 * e1 + l1) * e0 + l0;              // z-face below
