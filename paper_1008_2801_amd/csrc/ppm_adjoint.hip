@@ -414,9 +414,11 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ ti
 // primitives of its 5-zone stencil along d (GT of axis d), the sound speed
 // (CB of axis d) and the flattening coefficient (PHB of axis d).  One launch
 // per axis: the bodies of several axes in one kernel would share the
-// register budget of the largest and spill.
+// register budget of the largest and spill.  The fields are reversed in two
+// groups (the transverse velocities, then the coupled fields), which keeps
+// the FP64 kernel at 168 registers, 3 waves per SIMD (a few values spill).
 template <int d, class S>
-__global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
+__global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3))) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
                                                     const DevBox* __restrict__ boxes,
                                                     const S* __restrict__ prim, long long LS,
                                                     const S* __restrict__ work, long long LE,
@@ -433,35 +435,55 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_trace(const Tile* __restrict__
   const long long st = stride(NS, d);
   const S phi = work[E_FLAT * LE + B.eoff + z.e];
   S* a = aw + B.eoff + z.e;
-  S aL[5], aR[5], a6[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    const S* p = prim + m * LS + base;
-    ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL[m], aR[m], a6[m]);
-  }
-  const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
-  S qpb[5], qmb[5];
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    qpb[m] = a[(A_TB + (d * 2 + 0) * 5 + m) * LE];
-    qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
-  }
-  S aLb[5] = {0, 0, 0, 0, 0}, aRb[5] = {0, 0, 0, 0, 0}, a6b[5] = {0, 0, 0, 0, 0}, rb = 0, unb = 0, cb = 0;
-  trace_zone_vjp<d>(aL, aR, a6, r, un, c, SC<S>::dtdx(sc)[d], G, SC<S>::hdtg(sc), qpb, qmb, aLb, aRb, a6b, rb,
-                    unb, cb);
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  constexpr int fm[3] = {0, 1 + d, 4};
+  const S un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
+  const S dtdx = SC<S>::dtdx(sc)[d];
   S phib = 0;
-#pragma unroll
-  for (int m = 0; m < 5; ++m) {
-    // reloaded (opaque address: not the registers of the first loads, which
-    // would stay live through the tracing reverse)
+  // one field's parabola adjoint -> its stencil contributions (the stencil
+  // reloaded through an opaque address, so that the first loads' registers
+  // do not stay live in between)
+  auto stencil_out = [&](int m, S aLb, S aRb, S a6b, S centre) {
     const S* p = opaque(prim + m * LS + base);
     const S as5[5] = {p[-2 * st], p[-st], p[0], p[st], p[2 * st]};
     S ab[5] = {0, 0, 0, 0, 0};
-    ppm_parabola_vjp(as5, phi, G, aLb[m], aRb[m], a6b[m], ab, phib);
-    if (m == 0) ab[2] += rb;
-    if (m == 1 + d) ab[2] += unb;
+    ppm_parabola_vjp(as5, phi, G, aLb, aRb, a6b, ab, phib);
+    ab[2] += centre;
 #pragma unroll
     for (int o = 0; o < 5; ++o) a[(A_GT + (d * 5 + m) * 5 + o) * LE] = ab[o];
+  };
+  // the transverse velocities one at a time
+  S lambt[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = (i == 0) ? 1 + t1 : 1 + t2;
+    const S* p = opaque(prim + m * LS + base);
+    S aL, aR, a6;
+    ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL, aR, a6);
+    S aLb = 0, aRb = 0, a6b = 0;
+    trace_transverse_vjp(aL, aR, a6, un, c, dtdx, a[(A_TB + (d * 2 + 0) * 5 + m) * LE],
+                         a[(A_TB + (d * 2 + 1) * 5 + m) * LE], aLb, aRb, a6b, lambt);
+    stencil_out(m, aLb, aRb, a6b, S(0));
+  }
+  // then density, normal velocity and pressure together
+  S aL[5], aR[5], a6[5], qpb[5], qmb[5];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int m = fm[i];
+    const S* p = opaque(prim + m * LS + base);
+    ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL[m], aR[m], a6[m]);
+    qpb[m] = a[(A_TB + (d * 2 + 0) * 5 + m) * LE];
+    qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
+  }
+  const S r = prim[base];
+  S aLb[5], aRb[5], a6b[5], rb = 0, unb = 0, cb = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) aLb[fm[i]] = aRb[fm[i]] = a6b[fm[i]] = S(0);
+  trace_zone_vjp<d>(aL, aR, a6, r, un, c, dtdx, G, qpb, qmb, lambt, aLb, aRb, a6b, rb, unb, cb);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int m = fm[i];
+    stencil_out(m, aLb[m], aRb[m], a6b[m], m == 0 ? rb : (m == 1 + d ? unb : S(0)));
   }
   a[(A_CB + d) * LE] = cb;
   a[(A_PHB + d) * LE] = phib;

@@ -571,20 +571,28 @@ PPM_HD void ppm_im_vjp(S da, S a6, S sg, S Ib, S& aLb, S& dab, S& a6b, S& sgb) {
 }
 
 // ------------------------------------------------------------ tracing ------
-// Reverse of trace_zone<d>: (qpb, qmb) -> (aLb, aRb, a6b)[5], rb, unb, cb.
+// The tracing couples density, normal velocity and pressure through the
+// three waves; each transverse velocity only moves with the middle wave, so
+// its edge values depend on its own parabola and the wave speeds alone.
+// The reverse is split the same way (fewer values live at once).
+
+// Reverse of trace_zone<d> for the coupled fields 0, 1 + d and 4:
+// (qpb, qmb) of those fields -> their (aLb, aRb, a6b), rb, unb, cb.  lamb:
+// the wave-speed adjoints the transverse fields' reverses left (added here).
 template <int d, class S>
 PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S un, S c, S dtdx, const Gas<S>& G,
-                           const S* hdtg, const S qpb[5], const S qmb[5], S aLb[5], S aRb[5], S a6b[5], S& rb,
+                           const S qpb[5], const S qmb[5], const S lambt[3], S aLb[5], S aRb[5], S a6b[5], S& rb,
                            S& unb, S& cb) {
-  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-  constexpr int mn = 1 + d, m1 = 1 + t1, m2 = 1 + t2;
+  constexpr int mn = 1 + d;
+  constexpr int fm[3] = {0, mn, 4};
   S da[5], dab[5];
-  for (int m = 0; m < 5; ++m) { da[m] = aR[m] - aL[m]; dab[m] = S(0); }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { da[fm[i]] = aR[fm[i]] - aL[fm[i]]; dab[fm[i]] = S(0); }
   const S rc = r * c, c2 = c * c, ic2 = qdiv(ONE, c2), hic2 = HALF * ic2, cor = qdiv(c, r);
   const S lam[3] = {un - c, un, un + c};
   const S zero = S(0);
   S rcb = zero, c2b = zero, ic2b = zero, hic2b = zero, corb = zero;
-  S lamb[3] = {zero, zero, zero};
+  S lamb[3] = {lambt[0], lambt[1], lambt[2]};
 
   for (int side = 0; side < 2; ++side) {
     const bool hi = side == 0;
@@ -599,17 +607,14 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
       else ppm_im_vjp(da[m], a6[m], sg[k], b, aLb[m], dab[m], a6b[m], sgb[k]);
     };
     S ref[5];
-    for (int m = 0; m < 5; ++m) ref[m] = I(m, kref);
+    for (int i = 0; i < 3; ++i) ref[fm[i]] = I(fm[i], kref);
     const bool b1 = hi ? (lam[0] > zero) : (lam[0] < zero);
     const bool b2 = hi ? (lam[1] > zero) : (lam[1] < zero);
     const bool b3 = hi ? (lam[2] > zero) : (lam[2] < zero);
-    S a1 = zero, a2 = zero, a3 = zero, at1 = zero, at2 = zero;
+    S a1 = zero, a2 = zero, a3 = zero;
     S dp1 = zero, du1 = zero, dr2 = zero, dp2 = zero, dp3 = zero, du3 = zero;
     if (b1) { dp1 = ref[4] - I(4, 0); du1 = ref[mn] - I(mn, 0); a1 = (dp1 - rc * du1) * hic2; }
-    if (b2) {
-      dr2 = ref[0] - I(0, 1); dp2 = ref[4] - I(4, 1); a2 = dr2 - dp2 * ic2;
-      at1 = ref[m1] - I(m1, 1); at2 = ref[m2] - I(m2, 1);
-    }
+    if (b2) { dr2 = ref[0] - I(0, 1); dp2 = ref[4] - I(4, 1); a2 = dr2 - dp2 * ic2; }
     if (b3) { dp3 = ref[4] - I(4, 2); du3 = ref[mn] - I(mn, 2); a3 = (dp3 + rc * du3) * hic2; }
     // edge values (floors frozen; gravity is a constant shift)
     const S q0 = ref[0] - ((a1 + a3) + a2);
@@ -617,14 +622,12 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
     const S* qb = hi ? qpb : qmb;
     const S qb0 = (q0 < G.small_dens) ? zero : qb[0];
     const S qb4 = (q4 < G.small_pres) ? zero : qb[4];
-    S refb[5] = {zero, zero, zero, zero, zero};
+    S refb[5];
+    for (int i = 0; i < 3; ++i) refb[fm[i]] = zero;
     S a1b = zero, a2b = zero, a3b = zero;
     refb[0] += qb0; a1b -= qb0; a3b -= qb0; a2b -= qb0;
     refb[mn] += qb[mn]; corb += qb[mn] * (a1 - a3); a1b += qb[mn] * cor; a3b -= qb[mn] * cor;
     refb[4] += qb4; c2b -= qb4 * (a1 + a3); a1b -= qb4 * c2; a3b -= qb4 * c2;
-    refb[m1] += qb[m1];
-    refb[m2] += qb[m2];
-    const S at1b = -qb[m1], at2b = -qb[m2];
     if (b3) {
       const S dp3b = a3b * hic2, du3b = a3b * hic2 * rc;
       rcb += a3b * hic2 * du3;
@@ -637,8 +640,6 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
       ic2b -= a2b * dp2;
       refb[0] += dr2b; Ib(0, 1, -dr2b);
       refb[4] += dp2b; Ib(4, 1, -dp2b);
-      refb[m1] += at1b; Ib(m1, 1, -at1b);
-      refb[m2] += at2b; Ib(m2, 1, -at2b);
     }
     if (b1) {
       const S dp1b = a1b * hic2, du1b = -a1b * hic2 * rc;
@@ -647,13 +648,12 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
       refb[4] += dp1b; Ib(4, 0, -dp1b);
       refb[mn] += du1b; Ib(mn, 0, -du1b);
     }
-    for (int m = 0; m < 5; ++m) Ib(m, kref, refb[m]);
+    for (int i = 0; i < 3; ++i) Ib(fm[i], kref, refb[fm[i]]);
     for (int k = 0; k < 3; ++k) {
       const S lk = hi ? lam[k] : -lam[k];
       if (!(lk < zero)) lamb[k] += (hi ? sgb[k] : -sgb[k]) * dtdx;
     }
   }
-  (void)hdtg;
   unb += lamb[0] + lamb[1] + lamb[2];
   cb += lamb[2] - lamb[0];
   ic2b += HALF * hic2b;
@@ -664,7 +664,43 @@ PPM_HD void trace_zone_vjp(const S aL[5], const S aR[5], const S a6[5], S r, S u
   const S ir = qdiv(ONE, r);
   cb += corb * ir;
   rb -= corb * cor * ir;
-  for (int m = 0; m < 5; ++m) { aRb[m] += dab[m]; aLb[m] -= dab[m]; }
+  for (int i = 0; i < 3; ++i) { aRb[fm[i]] += dab[fm[i]]; aLb[fm[i]] -= dab[fm[i]]; }
+}
+
+// Reverse of trace_zone<d> for one transverse velocity field with parabola
+// (aL, aR, a6): edge adjoints qpb, qmb -> aLb, aRb, a6b; the wave-speed
+// adjoints go to lamb (to be added by the coupled fields' reverse).
+template <class S>
+PPM_HD void trace_transverse_vjp(S aL, S aR, S a6, S un, S c, S dtdx, S qpb, S qmb, S& aLb, S& aRb, S& a6b,
+                                 S lamb[3]) {
+  const S da = aR - aL;
+  S dab = S(0);
+  const S lam[3] = {un - c, un, un + c};
+  const S zero = S(0);
+  for (int side = 0; side < 2; ++side) {
+    const bool hi = side == 0;
+    const int kref = hi ? 2 : 0;
+    S sg[3], sgb[3] = {zero, zero, zero};
+    for (int k = 0; k < 3; ++k) sg[k] = smax(hi ? lam[k] : -lam[k], zero) * dtdx;
+    const bool b2 = hi ? (lam[1] > zero) : (lam[1] < zero);
+    const S qb = hi ? qpb : qmb;
+    // q = ref - at, at = ref - I(wave 2) where that wave moves toward the edge
+    S refb = qb;
+    if (b2) {
+      const S atb = -qb;
+      refb += atb;
+      if (hi) ppm_ip_vjp(da, a6, sg[1], -atb, aRb, dab, a6b, sgb[1]);
+      else ppm_im_vjp(da, a6, sg[1], -atb, aLb, dab, a6b, sgb[1]);
+    }
+    if (hi) ppm_ip_vjp(da, a6, sg[kref], refb, aRb, dab, a6b, sgb[kref]);
+    else ppm_im_vjp(da, a6, sg[kref], refb, aLb, dab, a6b, sgb[kref]);
+    for (int k = 0; k < 3; ++k) {
+      const S lk = hi ? lam[k] : -lam[k];
+      if (!(lk < zero)) lamb[k] += (hi ? sgb[k] : -sgb[k]) * dtdx;
+    }
+  }
+  aRb += dab;
+  aLb -= dab;
 }
 
 }  // namespace ppm
