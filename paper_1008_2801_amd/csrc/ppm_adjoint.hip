@@ -410,20 +410,93 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ ti
   }
 }
 
+// Trace reverse of one traced zone along axis d: the contributions of its
+// primitives' parabolas to the primitives of its 5-zone stencil, one field
+// at a time — the transverse velocities first (each alone), then density,
+// normal velocity and pressure together — handed to out(m, ab) in that
+// order (ab[o]: the contribution to the zone at offset o - 2), plus the
+// sound-speed (cb) and flattening-coefficient (phib) adjoints.  act false:
+// no memory is touched and out receives zeros (the lane still calls out,
+// which may hold workgroup barriers).
+template <int d, class S, class Out>
+__device__ __forceinline__ void trace_reverse_zone(bool act, const S* __restrict__ prim, long long LS,
+                                                   long long base, long long st, S phi, const S* a,
+                                                   long long LE, const Gas<S>& G, S dtdx, S& cb_out,
+                                                   S& phib_out, Out&& out) {
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  constexpr int fm[3] = {0, 1 + d, 4};
+  S un = 0, c = 0;
+  if (act) {
+    un = prim[(1 + d) * LS + base];
+    c = prim[5 * LS + base];
+  }
+  S phib = 0;
+  // one field's parabola adjoint -> its stencil contributions (the stencil
+  // reloaded through an opaque address, so that the first loads' registers
+  // do not stay live in between)
+  auto contrib = [&](int m, S aLb, S aRb, S a6b, S centre) {
+    S ab[5] = {0, 0, 0, 0, 0};
+    if (act) {
+      const S* p = opaque(prim + m * LS + base);
+      const S as5[5] = {p[-2 * st], p[-st], p[0], p[st], p[2 * st]};
+      ppm_parabola_vjp(as5, phi, G, aLb, aRb, a6b, ab, phib);
+      ab[2] += centre;
+    }
+    out(m, ab);
+  };
+  // the transverse velocities one at a time
+  S lambt[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = (i == 0) ? 1 + t1 : 1 + t2;
+    S aLb = 0, aRb = 0, a6b = 0;
+    if (act) {
+      const S* p = opaque(prim + m * LS + base);
+      S aL, aR, a6;
+      ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL, aR, a6);
+      trace_transverse_vjp(aL, aR, a6, un, c, dtdx, a[(A_TB + (d * 2 + 0) * 5 + m) * LE],
+                           a[(A_TB + (d * 2 + 1) * 5 + m) * LE], aLb, aRb, a6b, lambt);
+    }
+    contrib(m, aLb, aRb, a6b, S(0));
+  }
+  // then density, normal velocity and pressure together
+  S aL[5], aR[5], a6[5], qpb[5], qmb[5];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int m = fm[i];
+    aL[m] = aR[m] = a6[m] = qpb[m] = qmb[m] = S(0);
+    if (act) {
+      const S* p = opaque(prim + m * LS + base);
+      ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL[m], aR[m], a6[m]);
+      qpb[m] = a[(A_TB + (d * 2 + 0) * 5 + m) * LE];
+      qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
+    }
+  }
+  const S r = act ? prim[base] : S(1);
+  S aLb[5], aRb[5], a6b[5], rb = 0, unb = 0, cb = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) aLb[fm[i]] = aRb[fm[i]] = a6b[fm[i]] = S(0);
+  if (act) trace_zone_vjp<d>(aL, aR, a6, r, un, c, dtdx, G, qpb, qmb, lambt, aLb, aRb, a6b, rb, unb, cb);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int m = fm[i];
+    contrib(m, aLb[m], aRb[m], a6b[m], m == 0 ? rb : (m == 1 + d ? unb : S(0)));
+  }
+  cb_out = cb;
+  phib_out = phib;
+}
+
 // Trace adjoint of axis d: per traced zone, the contributions to the
 // primitives of its 5-zone stencil along d (GT of axis d), the sound speed
 // (CB of axis d) and the flattening coefficient (PHB of axis d).  One launch
 // per axis: the bodies of several axes in one kernel would share the
-// register budget of the largest and spill.  The fields are reversed in two
-// groups (the transverse velocities, then the coupled fields), which keeps
-// the FP64 kernel at 168 registers, 3 waves per SIMD (a few values spill).
+// register budget of the largest and spill.  The two field groups keep the
+// FP64 kernel at 168 registers, 3 waves per SIMD (a few values spill).
 template <int d, class S>
-__global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3))) k_adj_trace(const Tile* __restrict__ tiles, int ntiles,
-                                                    const DevBox* __restrict__ boxes,
-                                                    const S* __restrict__ prim, long long LS,
-                                                    const S* __restrict__ work, long long LE,
-                                                    S* __restrict__ aw, Gas<S> G,
-                                                    const StepConsts* __restrict__ sc) {
+__global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3)))
+k_adj_trace(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+            const S* __restrict__ prim, long long LS, const S* __restrict__ work, long long LE,
+            S* __restrict__ aw, Gas<S> G, const StepConsts* __restrict__ sc) {
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;
   const Tile tl = tiles[tt];
@@ -435,58 +508,74 @@ __global__ void __launch_bounds__(MAX_TILE) __attribute__((amdgpu_waves_per_eu(3
   const long long st = stride(NS, d);
   const S phi = work[E_FLAT * LE + B.eoff + z.e];
   S* a = aw + B.eoff + z.e;
-  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-  constexpr int fm[3] = {0, 1 + d, 4};
-  const S un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
-  const S dtdx = SC<S>::dtdx(sc)[d];
-  S phib = 0;
-  // one field's parabola adjoint -> its stencil contributions (the stencil
-  // reloaded through an opaque address, so that the first loads' registers
-  // do not stay live in between)
-  auto stencil_out = [&](int m, S aLb, S aRb, S a6b, S centre) {
-    const S* p = opaque(prim + m * LS + base);
-    const S as5[5] = {p[-2 * st], p[-st], p[0], p[st], p[2 * st]};
-    S ab[5] = {0, 0, 0, 0, 0};
-    ppm_parabola_vjp(as5, phi, G, aLb, aRb, a6b, ab, phib);
-    ab[2] += centre;
+  S cb, phib;
+  trace_reverse_zone<d>(true, prim, LS, base, st, phi, a, LE, G, SC<S>::dtdx(sc)[d], cb, phib,
+                        [&](int m, const S ab[5]) {
 #pragma unroll
-    for (int o = 0; o < 5; ++o) a[(A_GT + (d * 5 + m) * 5 + o) * LE] = ab[o];
-  };
-  // the transverse velocities one at a time
-  S lambt[3] = {0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int m = (i == 0) ? 1 + t1 : 1 + t2;
-    const S* p = opaque(prim + m * LS + base);
-    S aL, aR, a6;
-    ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL, aR, a6);
-    S aLb = 0, aRb = 0, a6b = 0;
-    trace_transverse_vjp(aL, aR, a6, un, c, dtdx, a[(A_TB + (d * 2 + 0) * 5 + m) * LE],
-                         a[(A_TB + (d * 2 + 1) * 5 + m) * LE], aLb, aRb, a6b, lambt);
-    stencil_out(m, aLb, aRb, a6b, S(0));
-  }
-  // then density, normal velocity and pressure together
-  S aL[5], aR[5], a6[5], qpb[5], qmb[5];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int m = fm[i];
-    const S* p = opaque(prim + m * LS + base);
-    ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL[m], aR[m], a6[m]);
-    qpb[m] = a[(A_TB + (d * 2 + 0) * 5 + m) * LE];
-    qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
-  }
-  const S r = prim[base];
-  S aLb[5], aRb[5], a6b[5], rb = 0, unb = 0, cb = 0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) aLb[fm[i]] = aRb[fm[i]] = a6b[fm[i]] = S(0);
-  trace_zone_vjp<d>(aL, aR, a6, r, un, c, dtdx, G, qpb, qmb, lambt, aLb, aRb, a6b, rb, unb, cb);
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int m = fm[i];
-    stencil_out(m, aLb[m], aRb[m], a6b[m], m == 0 ? rb : (m == 1 + d ? unb : S(0)));
-  }
+                          for (int o = 0; o < 5; ++o) a[(A_GT + (d * 5 + m) * 5 + o) * LE] = ab[o];
+                        });
   a[(A_CB + d) * LE] = cb;
   a[(A_PHB + d) * LE] = phib;
+}
+
+// Trace adjoint along x over runs of XF_OWNED traced zones with a two-zone
+// halo on each side (lane l: run start - 2 + l; the halo zones are traced
+// again here, not written): each field's stencil contributions are summed
+// in LDS, so that a traced zone's own GT[x][m] centre slot holds the whole
+// x part of its primitive adjoint (the gather's order of terms, the same
+// bits).  Contributions to the stored zones beyond a row's traced range
+// (x < -1 or x > n) stay in their GT slots, as in the per-zone form.
+template <class S>
+__global__ void __launch_bounds__(XF_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_adj_trace_x(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+              const S* __restrict__ prim, long long LS, const S* __restrict__ work, long long LE,
+              S* __restrict__ aw, Gas<S> G, const StepConsts* __restrict__ sc) {
+  __shared__ S buf[5][XF_THREADS];
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;  // the whole workgroup
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  const int l = threadIdx.x;
+  const int E0 = B.n[0] + 2;
+  const int NE = E0 * (B.n[1] + 2) * (B.n[2] + 2);
+  const int i = tl.start - 2 + l;
+  const bool act = i >= 0 && i < NE;
+  const bool own = i >= tl.start && i < tl.end;
+  int x = 0, y = 0, zz = 0;
+  if (act) {
+    const unsigned r = div31((unsigned)i, B.de[0]), k = div31(r, B.de[1]);
+    x = i - (int)r * E0 - 1;
+    y = (int)(r - k * (unsigned)(B.n[1] + 2)) - 1;
+    zz = (int)k - 1;
+  }
+  const long long base = act ? pidx(B, x, y, zz) : 0;
+  S* a = aw + B.eoff + (act ? i : 0);
+  const S phi = act ? work[E_FLAT * LE + B.eoff + i] : S(0);
+  S cb, phib;
+  trace_reverse_zone<0>(act, prim, LS, base, 1, phi, a, LE, G, SC<S>::dtdx(sc)[0], cb, phib,
+                        [&](int m, const S ab[5]) {
+#pragma unroll
+                          for (int o = 0; o < 5; ++o) buf[o][l] = ab[o];
+                          __syncthreads();
+                          if (own) {
+                            // zone x receives slot o + 2 of zone x - o, o = -2..2, while
+                            // that zone lies in the row's traced range
+                            S sum = S(0);
+#pragma unroll
+                            for (int o = -2; o <= 2; ++o)
+                              if (x - o >= -1 && x - o <= B.n[0]) sum += buf[o + 2][l - o];
+                            a[(A_GT + m * 5 + 2) * LE] = sum;
+#pragma unroll
+                            for (int o = 0; o < 5; ++o)
+                              if (o != 2 && (x + o - 2 < -1 || x + o - 2 > B.n[0]))
+                                a[(A_GT + m * 5 + o) * LE] = ab[o];
+                          }
+                          __syncthreads();
+                        });
+  if (own) {
+    a[A_CB * LE] = cb;
+    a[A_PHB * LE] = phib;
+  }
 }
 
 // Flattening adjoint: the derivative of phi = min_d (1 - chi_d) through the
@@ -622,8 +711,18 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_gather(const Tile* __restrict_
   j[1] = (int)(r - k * (unsigned)NS[1]) - NG;
   j[2] = (int)k - NG;
   S qb[6] = {0, 0, 0, 0, 0, 0};
+  // along x the trace adjoint left the summed contributions in each traced
+  // zone's centre slot; stored zones beyond a row's traced range read the
+  // slots of the traced zones within two
+  const bool xin = j[0] >= -1 && j[0] <= B.n[0];
+  if (xin && in_e(j, B)) {
+    const S* g = aw + B.eoff + eidx(B, j[0], j[1], j[2]);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) qb[m] = g[(A_GT + m * 5 + 2) * LE];
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    if (d == 0 && xin) continue;
 #pragma unroll
     for (int o = -2; o <= 2; ++o) {
       int y[3] = {j[0], j[1], j[2]};
@@ -734,7 +833,7 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ 
 }
 
 template <class S>
-hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, const double* Ubn, FluxBar fb,
+hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, int nX, const double* U, const double* Ubn, FluxBar fb,
                         double* Ub, const void* work, void* awork, const Gas<S>& G, int grav, const double g[3],
                         hipStream_t s) {
   const S* prim = (const S*)work;
@@ -753,8 +852,8 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, const double* U, cons
                        Ubn, fb, grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL((k_adj_trace<0, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
-                     aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_trace_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX, nX, L.boxes, prim,
+                     L.LS, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<1, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
                      aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<2, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
@@ -775,15 +874,15 @@ size_t adjoint_workspace_bytes(long long LS, long long LE, int precision) {
   return sizeof(double) * (size_t)(A_SPLANES * LS) + se * (size_t)(A_EPLANES * LE);
 }
 
-hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, const double* U, const double* Ubn,
+hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, int nX, const double* U, const double* Ubn,
                           FluxBar fb, double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s) {
   if (precision == 1)
-    return adjoint_impl<float>(L, nS, nE, U, Ubn, fb, Ub, work, awork,
+    return adjoint_impl<float>(L, nS, nE, nX, U, Ubn, fb, Ub, work, awork,
                                make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                                grav, g, s);
-  return adjoint_impl<double>(L, nS, nE, U, Ubn, fb, Ub, work, awork,
+  return adjoint_impl<double>(L, nS, nE, nX, U, Ubn, fb, Ub, work, awork,
                               make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                               grav, g, s);
 }

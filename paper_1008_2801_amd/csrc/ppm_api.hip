@@ -983,7 +983,8 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, c
   FluxBar fb{{nullptr, nullptr, nullptr}};
   if (flux_bar)
     for (int d = 0; d < 3; ++d) fb.p[d] = flux_bar[d];
-  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, U, Unew_bar, fb, U_bar, ctx->work, ctx->awork,
+  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, (int)ctx->tilesX.size(), U, Unew_bar, fb, U_bar,
+                                 ctx->work, ctx->awork,
                                  params->gamma, params->small_dens, params->small_pres, params->limiter,
                                  params->flattening, params->riemann_iters, grav, params->grav, s),
                   "adjoint");

@@ -223,7 +223,7 @@ size_t adjoint_workspace_bytes(long long LS, long long LE, int precision);
 struct FluxBar {
   const double* p[3];
 };
-hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, const double* U, const double* Ubn,
+hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, int nX, const double* U, const double* Ubn,
                           FluxBar fb, double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s);

@@ -88,6 +88,21 @@ def _uneven(seed, bc=(0, 0, 0, 0, 0, 0)):
     return I.Workload("uneven", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 1)
 
 
+def _long_rows(seed):
+    """Boxes whose traced x rows (262 and 10 zones) are longer and shorter
+    than the x trace adjoint's runs of 252 zones, walls in x."""
+    rng = np.random.default_rng(seed)
+    lay = I.tensor_tiling(np.array([260, 8]), np.array([5]), np.array([4]), bc=(2, 2, 0, 0, 0, 0))
+    L = tuple((np.array(lay.domain_hi) + 1) / 64.0)
+    S = [I.ModeSum(rng, 5, 3, L) for _ in range(5)]
+
+    def prim(x, y, z):
+        return (1.2 + 0.4 * S[0](x, y, z), 0.4 * S[1](x, y, z), 0.4 * S[2](x, y, z), 0.4 * S[3](x, y, z),
+                1.2 + 0.4 * S[4](x, y, z))
+    h = (1.0 / 64,) * 3
+    return I.Workload("long_rows", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 1)
+
+
 CASES = {
     "smooth_box": lambda: I.cfg4(10, amp=0.05),
     "sod_box": lambda: I.cfg2(12),
@@ -95,6 +110,7 @@ CASES = {
     "walls_gravity": lambda: _uneven(4, bc=(0, 0, 0, 0, 2, 2)),
     "outflow": lambda: _uneven(5, bc=(1, 1, 0, 0, 0, 0)),
     "rayleigh_taylor_boxes": lambda: I.cfg5(nb=2, m=8, precision=0),
+    "long_rows": lambda: _long_rows(6),
 }
 
 
