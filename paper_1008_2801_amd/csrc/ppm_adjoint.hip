@@ -114,6 +114,60 @@ __device__ __forceinline__ void r3_state(const S* w, long long LE, long long off
   }
 }
 
+// Reverse of the stage-3 solve of the face at zone slot x along d (a face:
+// x_d >= 0 and both transverse indices valid): from the new state's adjoint
+// of the face's two zones (through the update and its Heun source) and the
+// flux output's adjoint, the adjoints of the two corrected states (uLb of
+// zone x - e_d, uRb of zone x) and of their traced states (tLb, tRb).
+template <int d, class S>
+__device__ __forceinline__ void adj_r3_face(const DevBox& B, const EZone& z, const S* __restrict__ w, long long LE,
+                                            const Gas<S>& G, const StepConsts* __restrict__ sc,
+                                            const double* __restrict__ Ubn, const FluxBar& fbar, int grav,
+                                            double g0, double g1, double g2, S uLb[5], S uRb[5], S tLb[5],
+                                            S tRb[5]) {
+  constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+  const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
+  const S c1 = SC<S>::dt2h(sc)[t1], c2 = SC<S>::dt2h(sc)[t2];
+  // the final flux's adjoint from the pre-source adjoints of the face's two
+  // zones (the update is FP64)
+  double ufR[5], ufL[5];
+  pre_source_adjoint(Ubn, B, z.x[0], z.x[1], z.x[2], grav, sc, g0, g1, g2, ufR);
+  pre_source_adjoint(Ubn, B, z.x[0] - (d == 0), z.x[1] - (d == 1), z.x[2] - (d == 2), grav, sc, g0, g1, g2, ufL);
+  S Fb[5];
+  const double dtdx = sc->dtdx[d];
+  // plus the adjoint of the face's flux output, when given (face-centred
+  // arena of axis d: extents n + e_d, order [c][k][j][i])
+  double fo[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (fbar.p[d]) {
+    int fe[3] = {B.n[0], B.n[1], B.n[2]};
+    fe[d] += 1;
+    const long long FN = (long long)fe[0] * fe[1] * fe[2];
+    const double* q = fbar.p[d] + B.foff[d] + ((long long)z.x[2] * fe[1] + z.x[1]) * fe[0] + z.x[0];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) fo[m] = q[m * FN];
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) Fb[m] = (S)(dtdx * (ufR[m] - ufL[m]) + fo[m]);
+  S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
+  bool rfL, pfL, rfR, pfR;
+  r3_state<d>(w, LE, -sd, 0, s1, s2, c1, c2, G, qeL, ueL);
+  r3_state<d>(w, LE, 0, 1, s1, s2, c1, c2, G, qeR, ueR);
+  cons_to_prim_dec(ueL, G, L, rfL, pfL);
+  cons_to_prim_dec(ueR, G, R, rfR, pfR);
+  // a state replaced by a wall mirror gets no adjoint below, so L and R can
+  // be overwritten in place
+  const int ws = wall_states<d>(B, z.x[d], L, R);
+  S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
+  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
+  wall_states_vjp<d>(ws, Lb, Rb);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) uLb[m] = uRb[m] = tLb[m] = tRb[m] = S(0);
+  cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
+  cons_to_prim_vjp_q(R, rfR, pfR, G, Rb, uRb);
+  prim_to_cons_vjp(qeL, G, uLb, tLb);
+  prim_to_cons_vjp(qeR, G, uRb, tRb);
+}
+
 // Face slot x along d is a stage-3 face when x_d >= 0 and both transverse
 // indices are valid.  The lane of slot x writes the adjoints of the two
 // states of its face (zone x - e_d, high side; zone x, low side); every zone
@@ -151,47 +205,9 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
     }
     return;
   }
-  const long long sd = stride(z.E, d), s1 = stride(z.E, t1), s2 = stride(z.E, t2);
-  const S c1 = SC<S>::dt2h(sc)[t1], c2 = SC<S>::dt2h(sc)[t2];
-  const S* w = work + B.eoff + z.e;
-  // the final flux's adjoint from the pre-source adjoints of the face's two
-  // zones (the update is FP64)
-  double ufR[5], ufL[5];
-  pre_source_adjoint(Ubn, B, z.x[0], z.x[1], z.x[2], grav, sc, g0, g1, g2, ufR);
-  pre_source_adjoint(Ubn, B, z.x[0] - (d == 0), z.x[1] - (d == 1), z.x[2] - (d == 2), grav, sc, g0, g1, g2, ufL);
-  S Fb[5];
-  const double dtdx = sc->dtdx[d];
-  // plus the adjoint of the face's flux output, when given (face-centred
-  // arena of axis d: extents n + e_d, order [c][k][j][i])
-  double fo[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (fbar.p[d]) {
-    int fe[3] = {B.n[0], B.n[1], B.n[2]};
-    fe[d] += 1;
-    const long long FN = (long long)fe[0] * fe[1] * fe[2];
-    const double* q = fbar.p[d] + B.foff[d] + ((long long)z.x[2] * fe[1] + z.x[1]) * fe[0] + z.x[0];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) fo[m] = q[m * FN];
-  }
-#pragma unroll
-  for (int m = 0; m < 5; ++m) Fb[m] = (S)(dtdx * (ufR[m] - ufL[m]) + fo[m]);
-  S qeL[5], ueL[5], qeR[5], ueR[5], L[5], R[5];
-  bool rfL, pfL, rfR, pfR;
-  r3_state<d>(w, LE, -sd, 0, s1, s2, c1, c2, G, qeL, ueL);
-  r3_state<d>(w, LE, 0, 1, s1, s2, c1, c2, G, qeR, ueR);
-  cons_to_prim_dec(ueL, G, L, rfL, pfL);
-  cons_to_prim_dec(ueR, G, R, rfR, pfR);
-  // a state replaced by a wall mirror gets no adjoint below, so L and R can
-  // be overwritten in place
-  const int ws = wall_states<d>(B, z.x[d], L, R);
-  S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
-  riemann_vjp<d>(L, R, G, Fb, Lb, Rb);
-  wall_states_vjp<d>(ws, Lb, Rb);
-  S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0};
-  cons_to_prim_vjp_q(L, rfL, pfL, G, Lb, uLb);
-  cons_to_prim_vjp_q(R, rfR, pfR, G, Rb, uRb);
-  S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
-  prim_to_cons_vjp(qeL, G, uLb, tLb);
-  prim_to_cons_vjp(qeR, G, uRb, tRb);
+  const long long sd = stride(z.E, d);
+  S uLb[5], uRb[5], tLb[5], tRb[5];
+  adj_r3_face<d>(B, z, work + B.eoff + z.e, LE, G, sc, Ubn, fbar, grav, g0, g1, g2, uLb, uRb, tLb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_U3 + (d * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
@@ -201,17 +217,17 @@ __device__ __forceinline__ void adj_r3_body(const Tile* __restrict__ tiles, int 
   }
 }
 
+// Axes y and z (blockIdx.y 0, 1); x runs in k_adj_r3_x.
 template <class S>
 __device__ __forceinline__ void adj_r3_axes(const Tile* __restrict__ tiles, int ntiles,
                                             const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                             long long LE, S* __restrict__ aw, const Gas<S> G,
                                             const StepConsts* __restrict__ sc, const double* __restrict__ Ubn,
                                             const FluxBar& fbar, int grav, double g0, double g1, double g2) {
-  switch (blockIdx.y) {
-    case 0: adj_r3_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2); break;
-    case 1: adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2); break;
-    default: adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2); break;
-  }
+  if (blockIdx.y == 0)
+    adj_r3_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2);
+  else
+    adj_r3_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2);
 }
 
 // FP64: held to 3 waves per SIMD (it fits without spilling); FP32 fits 5.
@@ -228,6 +244,67 @@ k_adj_r3_f32(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restric
              const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, FluxBar fbar, int grav,
              double g0, double g1, double g2) {
   adj_r3_axes<float>(tiles, ntiles, boxes, work, LE, aw, G, sc, Ubn, fbar, grav, g0, g1, g2);
+}
+
+// Stage-3 reverse along x over runs of XF_OWNED traced slots: lane l takes
+// the face at slot start + l, and one lane past the run the next face, so
+// that each zone's two corrected-state adjoints (high side from the face
+// above it, low side from its own face) are added in LDS and stored as one
+// plane per field (the sum the stage-2 reverse forms, in its order: high
+// side + low side).  The traced-state adjoints are written per side as in
+// k_adj_r3_f64.
+template <class S>
+__global__ void __launch_bounds__(XF_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+k_adj_r3_x(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+           const S* __restrict__ work, long long LE, S* __restrict__ aw, Gas<S> G,
+           const StepConsts* __restrict__ sc, const double* __restrict__ Ubn, FluxBar fbar, int grav, double g0,
+           double g1, double g2) {
+  __shared__ S buf[5][XF_THREADS];
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;  // the whole workgroup
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  const int l = threadIdx.x;
+  EZone z;
+  z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
+  const int NE = z.E[0] * z.E[1] * z.E[2];
+  const int i = tl.start + l, nown = tl.end - tl.start;
+  const bool own = l < nown;
+  const bool act = l <= nown && i < NE;  // the run's slots and the next one
+  bool face = false, hi_face = false;
+  if (act) {
+    const unsigned r = div31((unsigned)i, B.de[0]), k = div31(r, B.de[1]);
+    z.e = i;
+    z.x[0] = i - (int)r * z.E[0] - 1;
+    z.x[1] = (int)(r - k * (unsigned)z.E[1]) - 1;
+    z.x[2] = (int)k - 1;
+    const bool tv = z.x[1] >= 0 && z.x[1] < B.n[1] && z.x[2] >= 0 && z.x[2] < B.n[2];
+    face = tv && z.x[0] >= 0;
+    hi_face = tv && z.x[0] + 1 <= B.n[0];
+  }
+  S uLb[5] = {0, 0, 0, 0, 0}, uRb[5] = {0, 0, 0, 0, 0}, tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
+  if (face) adj_r3_face<0>(B, z, work + B.eoff + i, LE, G, sc, Ubn, fbar, grav, g0, g1, g2, uLb, uRb, tLb, tRb);
+  S* a = aw + B.eoff + (act ? i : 0);
+  if (own) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      if (!hi_face) a[(A_TB + m) * LE] = S(0);
+      if (face) {
+        a[(A_TB + m) * LE - 1] = tLb[m];
+        a[(A_TB + 5 + m) * LE] = tRb[m];
+      } else {
+        a[(A_TB + 5 + m) * LE] = S(0);
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) buf[m][l] = uLb[m];
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+      a[(A_U3 + m) * LE] = (hi_face ? buf[m][l + 1] : S(0)) + (face ? uRb[m] : S(0));
+  }
 }
 
 // Stage-2 pair (d, t) of the face at the lane's slot: F2^{d|t} adjoint from
@@ -249,7 +326,10 @@ __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restri
   for (int m = 0; m < 5; ++m) {
     const S* up = a + (A_U3 + (r * 2 + 0) * 5 + m) * LE;
     const S* um = a + (A_U3 + (r * 2 + 1) * 5 + m) * LE;
-    Fb[m] = c2d * ((up[0] + um[0]) - (up[-sd] + um[-sd]));
+    if constexpr (r == 0)  // along x the stage-3 reverse stored each zone's two sides summed
+      Fb[m] = c2d * (up[0] - up[-sd]);
+    else
+      Fb[m] = c2d * ((up[0] + um[0]) - (up[-sd] + um[-sd]));
   }
   S ueL[5], ueR[5], L[5], R[5];
   bool rfL, pfL, rfR, pfR;
@@ -844,11 +924,13 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, int nX, const double*
   // every workspace entry is written before it is read: each reverse stage
   // writes all entries it owns, zeros included
   const int gE = xcd_grid(nE), gS = xcd_grid(nS);
+  hipLaunchKernelGGL(k_adj_r3_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX, nX, L.boxes, ework, L.LE,
+                     aw, G, L.consts, Ubn, fb, grav, g[0], g[1], g[2]);
   if constexpr (sizeof(S) == sizeof(double))
-    hipLaunchKernelGGL(k_adj_r3_f64, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
+    hipLaunchKernelGGL(k_adj_r3_f64, dim3(gE, 2), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
                        Ubn, fb, grav, g[0], g[1], g[2]);
   else
-    hipLaunchKernelGGL(k_adj_r3_f32, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
+    hipLaunchKernelGGL(k_adj_r3_f32, dim3(gE, 2), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
                        Ubn, fb, grav, g[0], g[1], g[2]);
   hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
