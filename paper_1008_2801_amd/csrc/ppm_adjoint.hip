@@ -309,14 +309,14 @@ k_adj_r3_x(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict_
 
 // Stage-2 pair (d, t) of the face at the lane's slot: F2^{d|t} adjoint from
 // the stage-3 states of the third axis r (difference along d), reverse of the
-// corrected states, adjoints of the two traced states (returned) and of the
-// corrected states (written to U2).
-template <int d, int t, class S>
+// corrected states, adjoints of the two traced states (accumulated) and of
+// the corrected states (written to U2, or with OUT returned in uLo, uRo).
+template <int d, int t, bool OUT, class S>
 __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restrict__ a, long long LE,
                                             long long sd, long long stt, const S qeL[5], const S qeR[5],
                                             const S ue0L[5], const S ue0R[5], const Gas<S>& G,
                                             const StepConsts* __restrict__ sc, const DevBox& B, int xd,
-                                            S tLb[5], S tRb[5]) {
+                                            S tLb[5], S tRb[5], S* uLo = nullptr, S* uRo = nullptr) {
   constexpr int pr = pair_index(d, t);
   constexpr int r = 3 - d - t;
   const S c3 = SC<S>::dt3h(sc)[t];
@@ -353,8 +353,13 @@ __device__ __forceinline__ void adj_r2_pair(const S* __restrict__ w, S* __restri
   prim_to_cons_vjp(qeR, G, uRb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
-    a[(A_U2 + (pr * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
-    a[(A_U2 + (pr * 2 + 1) * 5 + m) * LE] = uRb[m];
+    if constexpr (OUT) {
+      uLo[m] = uLb[m];
+      uRo[m] = uRb[m];
+    } else {
+      a[(A_U2 + (pr * 2 + 0) * 5 + m) * LE - sd] = uLb[m];
+      a[(A_U2 + (pr * 2 + 1) * 5 + m) * LE] = uRb[m];
+    }
   }
 }
 
@@ -409,8 +414,10 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
   prim_to_cons(qeL, G, ue0L);
   prim_to_cons(qeR, G, ue0R);
   S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
-  if (va) adj_r2_pair<d, t1, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, ue0L, ue0R, G, sc, B, z.x[d], tLb, tRb);
-  if (vb) adj_r2_pair<d, t2, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, ue0L, ue0R, G, sc, B, z.x[d], tLb, tRb);
+  if (va)
+    adj_r2_pair<d, t1, false, S>(w, a, LE, sd, stride(z.E, t1), qeL, qeR, ue0L, ue0R, G, sc, B, z.x[d], tLb, tRb);
+  if (vb)
+    adj_r2_pair<d, t2, false, S>(w, a, LE, sd, stride(z.E, t2), qeL, qeR, ue0L, ue0R, G, sc, B, z.x[d], tLb, tRb);
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     a[(A_TB + (d * 2 + 0) * 5 + m) * LE - sd] += tLb[m];
@@ -418,15 +425,102 @@ __device__ __forceinline__ void adj_r2_body(const Tile* __restrict__ tiles, int 
   }
 }
 
+// Axes y and z (blockIdx.y 0, 1); x runs in k_adj_r2_x.
 template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r2(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                                  long long LE, S* __restrict__ aw, Gas<S> G,
                                                  const StepConsts* __restrict__ sc) {
-  switch (blockIdx.y) {
-    case 0: adj_r2_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    case 1: adj_r2_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    default: adj_r2_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
+  if (blockIdx.y == 0)
+    adj_r2_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+  else
+    adj_r2_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+}
+
+// Stage-2 reverse along x over runs of XF_OWNED traced slots (lane l: the
+// face at slot start + l, one lane past the run the next face): per pair,
+// each zone's two corrected-state adjoints (high side from the face above,
+// low side from its own face) are added in LDS and stored as one plane per
+// field, in the order the stage-1 reverse adds them.  The traced-state
+// adjoints are accumulated per side as in k_adj_r2.
+template <class S>
+__global__ void __launch_bounds__(XF_THREADS) k_adj_r2_x(const Tile* __restrict__ tiles, int ntiles,
+                                                     const DevBox* __restrict__ boxes,
+                                                     const S* __restrict__ work, long long LE,
+                                                     S* __restrict__ aw, Gas<S> G,
+                                                     const StepConsts* __restrict__ sc) {
+  constexpr int pa = pair_index(0, 1), pb = pair_index(0, 2);
+  __shared__ S buf[5][XF_THREADS];
+  const int tt = xcd_tile(ntiles);
+  if (tt < 0) return;  // the whole workgroup
+  const Tile tl = tiles[tt];
+  const DevBox B = boxes[tl.box];
+  const int l = threadIdx.x;
+  EZone z;
+  z.E[0] = B.n[0] + 2; z.E[1] = B.n[1] + 2; z.E[2] = B.n[2] + 2;
+  const int NE = z.E[0] * z.E[1] * z.E[2];
+  const int i = tl.start + l, nown = tl.end - tl.start;
+  const bool own = l < nown;
+  const bool act = l <= nown && i < NE;  // the run's slots and the next one
+  bool ta = false, tb = false, up = false, va = false, vb = false;
+  if (act) {
+    const unsigned r = div31((unsigned)i, B.de[0]), k = div31(r, B.de[1]);
+    z.e = i;
+    z.x[0] = i - (int)r * z.E[0] - 1;
+    z.x[1] = (int)(r - k * (unsigned)z.E[1]) - 1;
+    z.x[2] = (int)k - 1;
+    ta = z.x[1] >= 0 && z.x[1] < B.n[1];
+    tb = z.x[2] >= 0 && z.x[2] < B.n[2];
+    up = z.x[0] + 1 <= B.n[0];
+    va = ta && z.x[0] >= 0;
+    vb = tb && z.x[0] >= 0;
+  }
+  S* a = aw + B.eoff + (act ? i : 0);
+  const S* w = work + B.eoff + (act ? i : 0);
+  S qeL[5], qeR[5], ue0L[5], ue0R[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) qeL[m] = qeR[m] = S(0);
+  if (va || vb) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      qeL[m] = w[(E_TRACE + m) * LE - 1];
+      qeR[m] = w[(E_TRACE + 5 + m) * LE];
+    }
+  }
+  prim_to_cons(qeL, G, ue0L);
+  prim_to_cons(qeR, G, ue0R);
+  S tLb[5] = {0, 0, 0, 0, 0}, tRb[5] = {0, 0, 0, 0, 0};
+  // one pair's corrected-state adjoints -> each owned zone's sum of sides
+  auto sides = [&](int pr, bool hi_ok, bool lo_ok, const S uL[5], const S uR[5]) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) buf[m][l] = uL[m];
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m)
+        a[(A_U2 + (pr * 2 + 0) * 5 + m) * LE] = (hi_ok ? buf[m][l + 1] : S(0)) + (lo_ok ? uR[m] : S(0));
+    }
+    __syncthreads();
+  };
+  {
+    S uL[5] = {0, 0, 0, 0, 0}, uR[5] = {0, 0, 0, 0, 0};
+    if (va)
+      adj_r2_pair<0, 1, true, S>(w, a, LE, 1, z.E[0], qeL, qeR, ue0L, ue0R, G, sc, B, z.x[0], tLb, tRb, uL, uR);
+    sides(pa, ta && up, va, uL, uR);
+  }
+  {
+    S uL[5] = {0, 0, 0, 0, 0}, uR[5] = {0, 0, 0, 0, 0};
+    if (vb)
+      adj_r2_pair<0, 2, true, S>(w, a, LE, 1, (long long)z.E[0] * z.E[1], qeL, qeR, ue0L, ue0R, G, sc, B, z.x[0],
+                                 tLb, tRb, uL, uR);
+    sides(pb, tb && up, vb, uL, uR);
+  }
+  if (own && (va || vb)) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      a[(A_TB + m) * LE - 1] += tLb[m];
+      a[(A_TB + 5 + m) * LE] += tRb[m];
+    }
   }
 }
 
@@ -455,7 +549,12 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
     const S* am = a + (A_U2 + (pa * 2 + 1) * 5 + m) * LE;
     const S* bp = a + (A_U2 + (pb * 2 + 0) * 5 + m) * LE;
     const S* bm = a + (A_U2 + (pb * 2 + 1) * 5 + m) * LE;
-    const S sa = (ap[0] + am[0]) - (ap[-sd] + am[-sd]);
+    // pairs of the x faces: the stage-2 reverse stored each zone's two sides summed
+    S sa;
+    if constexpr (da == 0)
+      sa = ap[0] - ap[-sd];
+    else
+      sa = (ap[0] + am[0]) - (ap[-sd] + am[-sd]);
     const S sb = (bp[0] + bm[0]) - (bp[-sd] + bm[-sd]);
     // formed before the solve starts (opaque): otherwise the twenty loads
     // stay in flight, in registers, through the forward solve
@@ -932,7 +1031,9 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, int nX, const double*
   else
     hipLaunchKernelGGL(k_adj_r3_f32, dim3(gE, 2), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts,
                        Ubn, fb, grav, g[0], g[1], g[2]);
-  hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r2_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX, nX, L.boxes, ework, L.LE,
+                     aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 2), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_trace_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX, nX, L.boxes, prim,
                      L.LS, ework, L.LE, aw, G, L.consts);
