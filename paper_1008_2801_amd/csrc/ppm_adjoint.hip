@@ -29,18 +29,24 @@ namespace ppm {
 namespace {
 
 // Adjoint workspace planes: traced grid (A_*) and stored grid (AS_*).  The
-// trace reverse's outputs (GT, CB, PHB) reuse the corrected-state planes,
-// which are dead once the stage-1 reverse has run.
+// trace reverse's stencil contributions (GT) reuse the stage-3
+// corrected-state planes and the first stage-2 ones: the x trace reverse,
+// which runs while the y and z stage-1 reverses' planes are still being
+// read (by its own stage-1 part), writes only the first 25, and those are
+// dead once the stage-2 reverse has run; the y and z ones are written after
+// every stage-1 reverse.  The sound-speed and flattening-coefficient
+// adjoints (CB, PHB) have planes of their own.
 constexpr int A_TB = 0;              // 30: traced-state adjoints [d][side][m]
 constexpr int A_U3 = A_TB + 30;      // 30: stage-3 corrected-state adjoints [d][side][m]
 constexpr int A_U2 = A_U3 + 30;      // 60: stage-2 corrected-state adjoints [pair][side][m]
 constexpr int A_GT = A_U3;           // 75: trace contributions [d][m][offset + 2]
-constexpr int A_CB = A_GT + 75;      // 3: sound-speed adjoint per axis
-constexpr int A_PHB = A_CB + 3;      // 3: flattening-coefficient adjoint per axis
 constexpr int A_GF = A_U2 + 60;      // 7: flattening contributions to p [offset + 3]
 constexpr int A_SEL = A_GF + 7;      // 1: axis selected by the flattening minimum (-1: none)
-constexpr int A_EPLANES = A_SEL + 1;
-static_assert(A_PHB + 3 <= A_U2 + 60, "trace reverse outputs must fit in the corrected-state planes");
+constexpr int A_CB = A_SEL + 1;      // 3: sound-speed adjoint per axis
+constexpr int A_PHB = A_CB + 3;      // 3: flattening-coefficient adjoint per axis
+constexpr int A_EPLANES = A_PHB + 3;
+static_assert(A_GT + 75 <= A_U2 + 60, "trace contributions must fit in the corrected-state planes");
+static_assert(A_GT + 25 <= A_U3 + 30, "the x trace contributions must fit in the stage-3 planes");
 constexpr int AS_UB = 0;             // 5: conserved adjoints
 constexpr int A_SPLANES = 5;
 
@@ -577,16 +583,16 @@ __device__ __forceinline__ void adj_r1_body(const Tile* __restrict__ tiles, int 
   }
 }
 
+// Axes y and z (blockIdx.y 0, 1); x runs in k_adj_r1_trace_x.
 template <class S>
 __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ tiles, int ntiles,
                                                  const DevBox* __restrict__ boxes, const S* __restrict__ work,
                                                  long long LE, S* __restrict__ aw, Gas<S> G,
                                                  const StepConsts* __restrict__ sc) {
-  switch (blockIdx.y) {
-    case 0: adj_r1_body<0, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    case 1: adj_r1_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-    default: adj_r1_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc); break;
-  }
+  if (blockIdx.y == 0)
+    adj_r1_body<1, S>(tiles, ntiles, boxes, work, LE, aw, G, sc);
+  else
+    adj_r1_body<2, S>(tiles, ntiles, boxes, work, LE, aw, G, sc);
 }
 
 // Trace reverse of one traced zone along axis d: the contributions of its
@@ -594,14 +600,15 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_r1(const Tile* __restrict__ ti
 // at a time — the transverse velocities first (each alone), then density,
 // normal velocity and pressure together — handed to out(m, ab) in that
 // order (ab[o]: the contribution to the zone at offset o - 2), plus the
-// sound-speed (cb) and flattening-coefficient (phib) adjoints.  act false:
+// sound-speed (cb) and flattening-coefficient (phib) adjoints; tbv(side, m):
+// the zone's traced-state adjoint of field m on that side.  act false:
 // no memory is touched and out receives zeros (the lane still calls out,
 // which may hold workgroup barriers).
-template <int d, class S, class Out>
+template <int d, class S, class TB, class Out>
 __device__ __forceinline__ void trace_reverse_zone(bool act, const S* __restrict__ prim, long long LS,
-                                                   long long base, long long st, S phi, const S* a,
-                                                   long long LE, const Gas<S>& G, S dtdx, S& cb_out,
-                                                   S& phib_out, Out&& out) {
+                                                   long long base, long long st, S phi, TB&& tbv,
+                                                   const Gas<S>& G, S dtdx, S& cb_out, S& phib_out,
+                                                   Out&& out) {
   constexpr int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
   constexpr int fm[3] = {0, 1 + d, 4};
   S un = 0, c = 0;
@@ -633,8 +640,7 @@ __device__ __forceinline__ void trace_reverse_zone(bool act, const S* __restrict
       const S* p = opaque(prim + m * LS + base);
       S aL, aR, a6;
       ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL, aR, a6);
-      trace_transverse_vjp(aL, aR, a6, un, c, dtdx, a[(A_TB + (d * 2 + 0) * 5 + m) * LE],
-                           a[(A_TB + (d * 2 + 1) * 5 + m) * LE], aLb, aRb, a6b, lambt);
+      trace_transverse_vjp(aL, aR, a6, un, c, dtdx, tbv(0, m), tbv(1, m), aLb, aRb, a6b, lambt);
     }
     contrib(m, aLb, aRb, a6b, S(0));
   }
@@ -647,8 +653,8 @@ __device__ __forceinline__ void trace_reverse_zone(bool act, const S* __restrict
     if (act) {
       const S* p = opaque(prim + m * LS + base);
       ppm_parabola(p[-2 * st], p[-st], p[0], p[st], p[2 * st], phi, G, aL[m], aR[m], a6[m]);
-      qpb[m] = a[(A_TB + (d * 2 + 0) * 5 + m) * LE];
-      qmb[m] = a[(A_TB + (d * 2 + 1) * 5 + m) * LE];
+      qpb[m] = tbv(0, m);
+      qmb[m] = tbv(1, m);
     }
   }
   const S r = act ? prim[base] : S(1);
@@ -688,8 +694,9 @@ k_adj_trace(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict
   const S phi = work[E_FLAT * LE + B.eoff + z.e];
   S* a = aw + B.eoff + z.e;
   S cb, phib;
-  trace_reverse_zone<d>(true, prim, LS, base, st, phi, a, LE, G, SC<S>::dtdx(sc)[d], cb, phib,
-                        [&](int m, const S ab[5]) {
+  trace_reverse_zone<d>(true, prim, LS, base, st, phi,
+                        [&](int side, int m) { return a[(A_TB + (d * 2 + side) * 5 + m) * LE]; }, G,
+                        SC<S>::dtdx(sc)[d], cb, phib, [&](int m, const S ab[5]) {
 #pragma unroll
                           for (int o = 0; o < 5; ++o) a[(A_GT + (d * 5 + m) * 5 + o) * LE] = ab[o];
                         });
@@ -697,18 +704,24 @@ k_adj_trace(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict
   a[(A_PHB + d) * LE] = phib;
 }
 
-// Trace adjoint along x over runs of XF_OWNED traced zones with a two-zone
-// halo on each side (lane l: run start - 2 + l; the halo zones are traced
-// again here, not written): each field's stencil contributions are summed
-// in LDS, so that a traced zone's own GT[x][m] centre slot holds the whole
-// x part of its primitive adjoint (the gather's order of terms, the same
-// bits).  Contributions to the stored zones beyond a row's traced range
-// (x < -1 or x > n) stay in their GT slots, as in the per-zone form.
+// Stage-1 reverse and trace adjoint along x in one kernel, over runs of
+// XF_OWNED - 1 traced zones: lane l takes slot start - 2 + l, so the run's
+// zones have two traced halo zones on each side and the last lane one more
+// slot.  Each lane first reverses the stage-1 solve of the x face at its
+// slot; the zone's traced-state adjoints are then what the stage-3 and
+// stage-2 reverses left plus the two faces' parts (the high side's from the
+// next lane, through LDS), so they are never written back.  The trace
+// reverse follows; each field's stencil contributions are summed in LDS, so
+// that a traced zone's own GT[x][m] centre slot holds the whole x part of its
+// primitive adjoint (the gather's order of terms, the same bits).
+// Contributions to the stored zones beyond a row's traced range (x < -1 or
+// x > n) stay in their GT slots, as in the per-zone form.
 template <class S>
 __global__ void __launch_bounds__(XF_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
-k_adj_trace_x(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
-              const S* __restrict__ prim, long long LS, const S* __restrict__ work, long long LE,
-              S* __restrict__ aw, Gas<S> G, const StepConsts* __restrict__ sc) {
+k_adj_r1_trace_x(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict__ boxes,
+                 const S* __restrict__ prim, long long LS, const S* __restrict__ work, long long LE,
+                 S* __restrict__ aw, Gas<S> G, const StepConsts* __restrict__ sc) {
+  constexpr int pa = pair_index(1, 0), pb = pair_index(2, 0);  // the pairs that use the x stage-1 fluxes
   __shared__ S buf[5][XF_THREADS];
   const int tt = xcd_tile(ntiles);
   if (tt < 0) return;  // the whole workgroup
@@ -718,21 +731,65 @@ k_adj_trace_x(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restri
   const int E0 = B.n[0] + 2;
   const int NE = E0 * (B.n[1] + 2) * (B.n[2] + 2);
   const int i = tl.start - 2 + l;
-  const bool act = i >= 0 && i < NE;
+  const bool slot = i >= 0 && i < NE;
+  const bool act = slot && l < XF_THREADS - 1;  // the zones this run traces
   const bool own = i >= tl.start && i < tl.end;
   int x = 0, y = 0, zz = 0;
-  if (act) {
+  if (slot) {
     const unsigned r = div31((unsigned)i, B.de[0]), k = div31(r, B.de[1]);
     x = i - (int)r * E0 - 1;
     y = (int)(r - k * (unsigned)(B.n[1] + 2)) - 1;
     zz = (int)k - 1;
   }
+  S* a = aw + B.eoff + (slot ? i : 0);
+  const S* w = work + B.eoff + (slot ? i : 0);
+  // stage-1 reverse of the face at the lane's slot (zone i - 1 high side,
+  // zone i low side)
+  const bool face = slot && x >= 0;
+  S Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
+  if (face) {
+    const S c3 = SC<S>::dt3h(sc)[0];
+    S Fb[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const S* ap = a + (A_U2 + (pa * 2 + 0) * 5 + m) * LE;
+      const S* am = a + (A_U2 + (pa * 2 + 1) * 5 + m) * LE;
+      const S* bp = a + (A_U2 + (pb * 2 + 0) * 5 + m) * LE;
+      const S* bm = a + (A_U2 + (pb * 2 + 1) * 5 + m) * LE;
+      const S sa = (ap[0] + am[0]) - (ap[-1] + am[-1]);
+      const S sb = (bp[0] + bm[0]) - (bp[-1] + bm[-1]);
+      Fb[m] = opaque(c3 * sa + c3 * sb);
+    }
+    S L[5], R[5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      L[m] = w[(E_TRACE + m) * LE - 1];
+      R[m] = w[(E_TRACE + 5 + m) * LE];
+    }
+    const int ws = wall_states<0>(B, x, L, R);
+    riemann_vjp<0>(L, R, G, Fb, Lb, Rb);
+    wall_states_vjp<0>(ws, Lb, Rb);
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) buf[m][l] = Lb[m];
+  __syncthreads();
+  // the zone's traced-state adjoints, complete
+  S qp[5] = {0, 0, 0, 0, 0}, qm[5] = {0, 0, 0, 0, 0};
+  if (act) {
+    const bool up = x + 1 <= B.n[0];  // the face above the zone is in its row
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const S p0 = a[(A_TB + m) * LE], m0 = a[(A_TB + 5 + m) * LE];
+      qp[m] = up ? p0 + buf[m][l + 1] : p0;
+      qm[m] = face ? m0 + Rb[m] : m0;
+    }
+  }
+  __syncthreads();
   const long long base = act ? pidx(B, x, y, zz) : 0;
-  S* a = aw + B.eoff + (act ? i : 0);
   const S phi = act ? work[E_FLAT * LE + B.eoff + i] : S(0);
   S cb, phib;
-  trace_reverse_zone<0>(act, prim, LS, base, 1, phi, a, LE, G, SC<S>::dtdx(sc)[0], cb, phib,
-                        [&](int m, const S ab[5]) {
+  trace_reverse_zone<0>(act, prim, LS, base, 1, phi, [&](int side, int m) { return side == 0 ? qp[m] : qm[m]; },
+                        G, SC<S>::dtdx(sc)[0], cb, phib, [&](int m, const S ab[5]) {
 #pragma unroll
                           for (int o = 0; o < 5; ++o) buf[o][l] = ab[o];
                           __syncthreads();
@@ -1012,7 +1069,8 @@ __global__ void __launch_bounds__(MAX_TILE) k_adj_fill(const Tile* __restrict__ 
 }
 
 template <class S>
-hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, int nX, const double* U, const double* Ubn, FluxBar fb,
+hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, int nX, int nXA, const double* U, const double* Ubn,
+                        FluxBar fb,
                         double* Ub, const void* work, void* awork, const Gas<S>& G, int grav, const double g[3],
                         hipStream_t s) {
   const S* prim = (const S*)work;
@@ -1034,9 +1092,9 @@ hipError_t adjoint_impl(const DevLevel& L, int nS, int nE, int nX, const double*
   hipLaunchKernelGGL(k_adj_r2_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX, nX, L.boxes, ework, L.LE,
                      aw, G, L.consts);
   hipLaunchKernelGGL(k_adj_r2<S>, dim3(gE, 2), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 3), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
-  hipLaunchKernelGGL(k_adj_trace_x<S>, dim3(xcd_grid(nX)), dim3(XF_THREADS), 0, s, L.tilesX, nX, L.boxes, prim,
-                     L.LS, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r1<S>, dim3(gE, 2), blk, 0, s, L.tilesE, nE, L.boxes, ework, L.LE, aw, G, L.consts);
+  hipLaunchKernelGGL(k_adj_r1_trace_x<S>, dim3(xcd_grid(nXA)), dim3(XF_THREADS), 0, s, L.tilesXA, nXA, L.boxes,
+                     prim, L.LS, ework, L.LE, aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<1, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
                      aw, G, L.consts);
   hipLaunchKernelGGL((k_adj_trace<2, S>), dim3(gE), blk, 0, s, L.tilesE, nE, L.boxes, prim, L.LS, ework, L.LE,
@@ -1057,15 +1115,16 @@ size_t adjoint_workspace_bytes(long long LS, long long LE, int precision) {
   return sizeof(double) * (size_t)(A_SPLANES * LS) + se * (size_t)(A_EPLANES * LE);
 }
 
-hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, int nX, const double* U, const double* Ubn,
+hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, int nX, int nXA, const double* U,
+                          const double* Ubn,
                           FluxBar fb, double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s) {
   if (precision == 1)
-    return adjoint_impl<float>(L, nS, nE, nX, U, Ubn, fb, Ub, work, awork,
+    return adjoint_impl<float>(L, nS, nE, nX, nXA, U, Ubn, fb, Ub, work, awork,
                                make_gas<float>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                                grav, g, s);
-  return adjoint_impl<double>(L, nS, nE, nX, U, Ubn, fb, Ub, work, awork,
+  return adjoint_impl<double>(L, nS, nE, nX, nXA, U, Ubn, fb, Ub, work, awork,
                               make_gas<double>(gamma, small_dens, small_pres, limiter, flattening, iters, grav),
                               grav, g, s);
 }

@@ -430,6 +430,7 @@ void build_tiles(ppm_ctx& c) {
   c.tS_begin.assign(1, 0);
   c.tE_begin.assign(1, 0);
   c.tilesX.clear();
+  c.tilesXA.clear();
   c.tX_begin.assign(1, 0);
   c.tilesY.clear();
   c.tY_begin.assign(1, 0);
@@ -441,6 +442,7 @@ void build_tiles(ppm_ctx& c) {
     add_tiles(c.tilesS, b, n[0] + 2 * NG, n[1] + 2 * NG, n[2] + 2 * NG, c.tile, c.strip_rows);
     add_tiles(c.tilesE, b, n[0] + 2, n[1] + 2, n[2] + 2, c.tile, c.strip_rows);
     add_tiles(c.tilesX, b, n[0] + 2, n[1] + 2, n[2] + 2, XF_OWNED, c.strip_rows);
+    add_tiles(c.tilesXA, b, n[0] + 2, n[1] + 2, n[2] + 2, XF_OWNED - 1, c.strip_rows);
     // front form 3: workgroup w of a box along y or z; the kernel decodes w
     for (long long w = 0; w < front_yz_groups(n[0] + 2, n[1] + 2, n[2] + 2); ++w)
       c.tilesY.push_back(Tile{b, (int)w, (int)w + 1});
@@ -632,6 +634,7 @@ int ppm_ctx_create(const ppm_layout* layout, ppm_ctx** out) {
       (e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess ||
       (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess ||
       (e = upload(&ctx->d_tilesX, ctx->tilesX)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesXA, ctx->tilesXA)) != hipSuccess ||
       (e = upload(&ctx->d_tilesY, ctx->tilesY)) != hipSuccess ||
       (e = upload(&ctx->d_tilesZ, ctx->tilesZ)) != hipSuccess ||
       (e = upload(&ctx->d_desc, ctx->plan->desc)) != hipSuccess ||
@@ -660,6 +663,7 @@ int ppm_ctx_destroy(ppm_ctx* ctx) {
   (void)hipFree(ctx->d_tilesS);
   (void)hipFree(ctx->d_tilesE);
   (void)hipFree(ctx->d_tilesX);
+  (void)hipFree(ctx->d_tilesXA);
   (void)hipFree(ctx->d_tilesY);
   (void)hipFree(ctx->d_tilesZ);
   (void)hipFree(ctx->d_bricks);
@@ -983,7 +987,8 @@ static int adjoint_step(ppm_ctx* ctx, const double* U, const double* Unew_bar, c
   FluxBar fb{{nullptr, nullptr, nullptr}};
   if (flux_bar)
     for (int d = 0; d < 3; ++d) fb.p[d] = flux_bar[d];
-  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, (int)ctx->tilesX.size(), U, Unew_bar, fb, U_bar,
+  return ctx->hip(launch_adjoint(L, params->precision, nS, nE, (int)ctx->tilesX.size(), (int)ctx->tilesXA.size(), U,
+                                 Unew_bar, fb, U_bar,
                                  ctx->work, ctx->awork,
                                  params->gamma, params->small_dens, params->small_pres, params->limiter,
                                  params->flattening, params->riemann_iters, grav, params->grav, s),
@@ -1157,15 +1162,18 @@ int ppm_set_tiling(ppm_ctx* ctx, int32_t tile, int32_t strip_rows) {
   (void)hipFree(ctx->d_tilesS);
   (void)hipFree(ctx->d_tilesE);
   (void)hipFree(ctx->d_tilesX);
+  (void)hipFree(ctx->d_tilesXA);
   (void)hipFree(ctx->d_tilesY);
   (void)hipFree(ctx->d_tilesZ);
   ctx->d_tilesS = nullptr;
   ctx->d_tilesE = nullptr;
   ctx->d_tilesX = nullptr;
+  ctx->d_tilesXA = nullptr;
   ctx->d_tilesY = nullptr;
   ctx->d_tilesZ = nullptr;
   if ((e = upload(&ctx->d_tilesS, ctx->tilesS)) != hipSuccess || (e = upload(&ctx->d_tilesE, ctx->tilesE)) != hipSuccess ||
-      (e = upload(&ctx->d_tilesX, ctx->tilesX)) != hipSuccess || (e = upload(&ctx->d_tilesY, ctx->tilesY)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesX, ctx->tilesX)) != hipSuccess ||
+      (e = upload(&ctx->d_tilesXA, ctx->tilesXA)) != hipSuccess || (e = upload(&ctx->d_tilesY, ctx->tilesY)) != hipSuccess ||
       (e = upload(&ctx->d_tilesZ, ctx->tilesZ)) != hipSuccess)
     return ctx->hip(e, "tiling upload");
   return PPM_OK;

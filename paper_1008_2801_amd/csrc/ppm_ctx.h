@@ -37,6 +37,7 @@ struct ppm_ctx {
   std::vector<Tile> tilesS, tilesE;
   std::vector<int> tS_begin, tE_begin;  // nbox + 1
   std::vector<Tile> tilesX;             // front forms 2, 3: traced-grid runs of XF_OWNED zones
+  std::vector<Tile> tilesXA;            // adjoint along x: traced-grid runs of XF_OWNED - 1 zones
   std::vector<int> tX_begin;            // nbox + 1
   std::vector<Tile> tilesY, tilesZ;     // front form 3: 8 x 8 wavefront patches (x-d planes) along y, z
   std::vector<int> tY_begin, tZ_begin;  // nbox + 1
@@ -67,6 +68,7 @@ struct ppm_ctx {
   Tile* d_tilesS = nullptr;
   Tile* d_tilesE = nullptr;
   Tile* d_tilesX = nullptr;
+  Tile* d_tilesXA = nullptr;
   Tile* d_tilesY = nullptr;
   Tile* d_tilesZ = nullptr;
   Brick* d_bricks = nullptr;
@@ -114,6 +116,7 @@ struct ppm_ctx {
     L.tilesS = d_tilesS;
     L.tilesE = d_tilesE;
     L.tilesX = d_tilesX;
+    L.tilesXA = d_tilesXA;
     L.tilesY = d_tilesY;
     L.tilesZ = d_tilesZ;
     L.desc = d_desc;

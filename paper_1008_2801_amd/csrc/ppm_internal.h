@@ -157,6 +157,7 @@ struct DevLevel {
   const Tile* tilesS;  // tiles over the stored grids
   const Tile* tilesE;  // tiles over the traced grids
   const Tile* tilesX;  // runs of XF_OWNED traced zones (front forms 2, 3)
+  const Tile* tilesXA;  // runs of XF_OWNED - 1 traced zones (adjoint along x)
   const Tile* tilesY;  // workgroups of 8 x 8 patches in x-y planes (front form 3)
   const Tile* tilesZ;  // workgroups of 8 x 8 patches in x-z planes (front form 3)
   const FillDesc* desc;
@@ -223,7 +224,8 @@ size_t adjoint_workspace_bytes(long long LS, long long LE, int precision);
 struct FluxBar {
   const double* p[3];
 };
-hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, int nX, const double* U, const double* Ubn,
+hipError_t launch_adjoint(const DevLevel& L, int precision, int nS, int nE, int nX, int nXA, const double* U,
+                          const double* Ubn,
                           FluxBar fb, double* Ub, const void* work, void* awork, double gamma, double small_dens,
                           double small_pres, int limiter, int flattening, int iters, int grav, const double g[3],
                           hipStream_t s);
