@@ -16,6 +16,13 @@
 //                 primitive conversion's adjoint -> conserved adjoints (plus,
 //                 on valid zones, Ub' through the update)
 //   adj_fill      ghost adjoints gathered into their owning valid zones
+// Along y and z the Riemann reverses run one lane per face slot and pass
+// per-zone-side planes on.  Along x, where a workgroup's lanes hold
+// neighbouring zones (runs of traced zones with halo lanes), the stage-3
+// and stage-2 reverses add each zone's two sides in LDS, and the stage-1
+// reverse and the trace reverse are one kernel that keeps each zone's
+// traced-state adjoints in registers and adds its stencil contributions in
+// LDS; every sum keeps the order of terms of the per-zone form.
 // Every reverse stage writes only the entries it owns or accumulates through
 // a gather in a fixed order: no atomics, results reproducible bit for bit.
 #include <hip/hip_runtime.h>
