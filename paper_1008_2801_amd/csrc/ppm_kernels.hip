@@ -180,14 +180,22 @@ __device__ __forceinline__ void trace_at(const DevBox& B, int x, int y, int z, l
   const int NS[3] = {B.n[0] + 2 * NG, B.n[1] + 2 * NG, B.n[2] + 2 * NG};
   const long long base = pidx(B, x, y, z);
   const long long st = stride(NS, d);
-  const S phi = work[E_FLAT * LE + B.eoff + e];
-  S aL[5], aR[5], a6[5];
+  // every stencil value loaded before any is used: the limiter's branches
+  // would otherwise keep the compiler from issuing a field's loads before the
+  // previous field's parabola, one memory round trip per field
+  S v[5][5];
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const S* a = prim + m * LS + base;
-    ppm_parabola(a[-2 * st], a[-st], a[0], a[st], a[2 * st], phi, G, aL[m], aR[m], a6[m]);
+#pragma unroll
+    for (int o = 0; o < 5; ++o) v[m][o] = a[(o - 2) * st];
   }
-  const S r = prim[base], un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
+  const S c = prim[5 * LS + base];
+  const S phi = work[E_FLAT * LE + B.eoff + e];
+  S aL[5], aR[5], a6[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) ppm_parabola(v[m][0], v[m][1], v[m][2], v[m][3], v[m][4], phi, G, aL[m], aR[m], a6[m]);
+  const S r = v[0][2], un = v[1 + d][2];
   trace_zone<d>(aL, aR, a6, r, un, c, SC<S>::dtdx(sc)[d], G, SC<S>::hdtg(sc), qp, qm, fl);
 }
 
