@@ -101,8 +101,9 @@ typedef struct ppm_graph ppm_graph;
 
 /* Context for one level layout (paper Sec. 2: replicated box metadata).
  * Validates the layout (disjoint non-empty boxes tiling the domain,
- * ngrow == 4, domain extents >= 4, periodic axes periodic on both faces;
- * boxes may be thinner than the ghost width), builds or reuses
+ * ngrow == 4, domain extents >= 4, periodic axes periodic on both faces,
+ * fewer than 2^31 zones per box with its ghost layers; boxes may be
+ * thinner than the ghost width), builds or reuses
  * the ghost-fill plan (hash-sorted intersections, cached across contexts)
  * and the tile lists, and uploads them.  Allocates device memory for them.
  * Returns PPM_EINVAL for an invalid layout, PPM_EHIP on allocation failure. */

@@ -8,7 +8,8 @@
  * correctly rounded sequences, without the operand scaling that their
  * magnitudes never need.  These entry points run exactly those sequences on
  * the device for caller-given arguments, so that a caller (the test suite)
- * can compare them with IEEE results on the host.  They are not part of the
+ * can compare them with IEEE results on the host; likewise the integer
+ * division the kernels decode zone indices with.  They are not part of the
  * step.
  *
  * All pointers are HIP device memory owned by the caller; calls are
@@ -42,6 +43,18 @@ int ppm_diag_sqrt_values(const double* x, double* out, int64_t n, int32_t form, 
  * raises PPM_FLAG_RANGE, ppm.h, for input states whose quantities could
  * leave that range).  Invalid: n < 0 or null pointers with n > 0. */
 int ppm_diag_quotient_values(const double* a, const double* b, double* out, int64_t n, void* stream);
+
+/* The division by an invariant divisor d (2 <= d < 2^31) with which every
+ * kernel decodes a linear zone index into coordinates (the row lengths of a
+ * box's grids and of its bricks), for dividends below 2^31: with
+ * l = ceil(log2 d), m = ceil(2^(31+l) / d) (below 2^32) and s = l - 1,
+ * floor(n / d) = ((n m) >> 32) >> s (Granlund and Montgomery 1994).
+ * ppm_diag_div31_params returns m and s as the library forms them (host
+ * only); ppm_diag_div31_values computes out[i] = floor(n[i] / d) on the
+ * device exactly as the kernels do (n[i] < 2^31; device pointers).
+ * Invalid: d outside [2, 2^31), null pointers, count < 0. */
+int ppm_diag_div31_params(uint32_t d, uint32_t* m, int32_t* s);
+int ppm_diag_div31_values(const uint32_t* n, uint32_t d, uint32_t* out, int64_t count, void* stream);
 
 #ifdef __cplusplus
 }

@@ -76,6 +76,11 @@ std::string validate_layout(const ppm_layout& L) {
         return "layout: box outside the domain";
       v *= n;
     }
+    // zone indices within a box (ghost layers included) are decoded in
+    // 32 bits by multiply-and-shift, exact below 2^31
+    long long stored = 1;
+    for (int d = 0; d < 3; ++d) stored *= (long long)(L.boxes[b].hi[d] - L.boxes[b].lo[d] + 1 + 2 * NG);
+    if (stored >= (1ll << 31)) return "layout: a box holds 2^31 zones or more with its ghost layers";
     vol += v;
   }
   if (vol != dvol) return "layout: boxes do not tile the domain (volume mismatch)";

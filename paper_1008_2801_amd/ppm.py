@@ -36,7 +36,8 @@ SYMBOLS = ("ppm_ctx_create", "ppm_ctx_destroy", "ppm_last_error", "ppm_layout_of
            "ppm_set_stream_tiling", "ppm_get_stream_tiling", "ppm_set_front_form", "ppm_get_front_form",
            "ppm_set_front_tiling", "ppm_get_front_tiling")
 # Every exported symbol of include/ppm_diag.h (libppm_diag.so).
-DIAG_SYMBOLS = ("ppm_diag_sqrt_values", "ppm_diag_quotient_values")
+DIAG_SYMBOLS = ("ppm_diag_sqrt_values", "ppm_diag_quotient_values", "ppm_diag_div31_params",
+                "ppm_diag_div31_values")
 DIAG_LIB_PATH = os.path.join(HERE, "libppm_diag.so")
 NOALLOC_SCRATCH_BYTES = 128 << 20
 MAX_SPECIES = 64
@@ -224,6 +225,9 @@ def diag_lib():
         _vp = ctypes.c_void_p
         L.ppm_diag_sqrt_values.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp]
         L.ppm_diag_quotient_values.argtypes = [_vp, _vp, _vp, ctypes.c_int64, _vp]
+        L.ppm_diag_div31_params.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                            ctypes.POINTER(ctypes.c_int32)]
+        L.ppm_diag_div31_values.argtypes = [_vp, ctypes.c_uint32, _vp, ctypes.c_int64, _vp]
         _diag_handle = L
     return _diag_handle
 
@@ -830,3 +834,28 @@ def rollout(U0, level, nsteps, dx, p, checkpoint_every=5, dts=None, saved=None):
     adjoint (False), or chooses by free memory (None)."""
     _, Rollout = _autograd()
     return Rollout.apply(U0, level, nsteps, dx, p, checkpoint_every, dts, saved)
+
+
+def div31_params(d):
+    """The multiplier m and shift s with which the kernels divide zone
+    indices below 2^31 by d: floor(n / d) = ((n m) >> 32) >> s (diagnostic,
+    host only; ppm_diag_div31_params)."""
+    m, sh = ctypes.c_uint32(), ctypes.c_int32()
+    rc = diag_lib().ppm_diag_div31_params(int(d), ctypes.byref(m), ctypes.byref(sh))
+    if rc != 0:
+        raise PPMError(f"ppm_diag_div31_params failed ({rc})")
+    return m.value, sh.value
+
+
+def div31_values(n, d, stream=None):
+    """Device values of the kernels' zone-index division floor(n / d) for a
+    contiguous int32 CUDA tensor n of dividends in [0, 2^31) (diagnostic;
+    ppm_diag_div31_values)."""
+    import torch
+    if n.dtype != torch.int32 or not n.is_cuda or not n.is_contiguous():
+        raise PPMError("div31_values: n must be a contiguous int32 CUDA tensor")
+    out = torch.empty_like(n)
+    rc = diag_lib().ppm_diag_div31_values(_ptr(n), int(d), _ptr(out), n.numel(), _stream(stream))
+    if rc != 0:
+        raise PPMError(f"ppm_diag_div31_values failed ({rc})")
+    return out

@@ -649,6 +649,25 @@ def test_kernel_quotient_is_the_ieee_quotient():
     assert bad.size == 0, (bad.size, a[bad[:5]], b[bad[:5]], got[bad[:5]], ref[bad[:5]])
 
 
+def test_zone_index_division_on_the_device():
+    """The kernels' zone-index division (high multiply and shift) on the
+    device equals numpy's floor division for dividends across [0, 2^31),
+    for the row lengths of boxes and bricks and for arbitrary divisors."""
+    rng = np.random.default_rng(32)
+    top = 2 ** 31 - 1
+    divisors = [3, 5, 10, 18, 33, 66, 72, 130, 136, 258, 264, 1026, 1032] + [int(v) for v in rng.integers(2, 2 ** 31,
+                                                                                                     size=12)]
+    for d in divisors:
+        base = rng.integers(0, 2 ** 31, size=200000, dtype=np.int64)
+        edges = np.array([k * d + e for k in (1, 2, 5, 999, top // d) for e in (-1, 0, 1)] + [0, 1, top, top - 1],
+                         dtype=np.int64)
+        n = np.concatenate([base, edges[(edges >= 0) & (edges <= top)]]).astype(np.int32)
+        got = P.div31_values(torch.from_numpy(n).cuda(), d).cpu().numpy()
+        ref = (n.astype(np.int64) // d).astype(np.int32)
+        bad = np.flatnonzero(got != ref)
+        assert bad.size == 0, (d, bad.size, n[bad[:5]], got[bad[:5]], ref[bad[:5]])
+
+
 @pytest.mark.parametrize("mode,precision,fused", [(P.BATCHED, 0, 0), (P.PER_BOX, 0, 0), (P.BATCHED, 1, 0),
                                                   (P.BATCHED, 0, 1), (P.BATCHED, 0, 2), (P.PER_BOX, 1, 2)])
 def test_fused_next_dt_is_compute_dt_of_the_new_state(mode, precision, fused):

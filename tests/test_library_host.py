@@ -102,6 +102,17 @@ def test_invalid_layouts_rejected(lo, hi, dom, bc):
         P.plan_build(lay)
 
 
+def test_box_beyond_32_bit_zone_indices_rejected():
+    """Zone indices within a box, ghost layers included, are 32-bit: a box
+    of 1283^3 zones (1291^3 > 2^31 with its ghosts) is refused before any
+    work, while a thinner box of the same face area passes."""
+    big = I.Layout(np.array([[0, 0, 0]]), np.array([[1282, 1282, 1282]]), (0, 0, 0), (1282, 1282, 1282), (0,) * 6)
+    with pytest.raises(P.PPMError):
+        P.plan_build(big)
+    thin = I.Layout(np.array([[0, 0, 0]]), np.array([[1282, 1282, 7]]), (0, 0, 0), (1282, 1282, 7), (0,) * 6)
+    P.plan_build(thin)
+
+
 def test_empty_layout_rejected():
     """A level without boxes has nothing to advance: the library refuses it
     (PPM_EINVAL, "no boxes") rather than building an empty plan."""
@@ -254,3 +265,26 @@ def test_roofline_prices_fused_slots_by_their_kernels_work():
     assert r["kernel"].startswith("final_update")
     assert abs(r["flops_per_launch"] - (table["riemann3"] * units["riemann3"] +
                                         table["update"] * units["update"])) < 1e-3
+
+
+def test_zone_index_division_multipliers_give_integer_division():
+    """The kernels decode zone indices (below 2^31) by a high multiply and a
+    shift with multipliers the library forms per divisor; checked against
+    Python's integer division for small, random, power-of-two-adjacent and
+    the largest divisors, at dividends around every multiple's edge."""
+    rng = np.random.default_rng(31)
+    divisors = list(range(2, 600)) + [2 ** k + e for k in range(1, 31) for e in (-1, 0, 1) if 2 <= 2 ** k + e < 2 ** 31]
+    divisors += [int(v) for v in rng.integers(2, 2 ** 31, size=300)] + [2 ** 31 - 1]
+    top = 2 ** 31 - 1
+    for d in divisors:
+        m, sh = P.div31_params(d)
+        assert 0 < m < 2 ** 32 and sh >= 0
+        ns = {0, 1, d - 1, d, d + 1, top, top - 1, top // d * d, top // d * d - 1}
+        ns.update(int(v) for v in rng.integers(0, 2 ** 31, size=40))
+        ns.update(k * d + e for k in (1, 2, 3, 7, 1000, top // d) for e in (-1, 0, 1))
+        for n in ns:
+            if 0 <= n <= top:
+                assert ((n * m) >> 32) >> sh == n // d, (d, n, m, sh)
+    for bad in (0, 1, 2 ** 31):
+        with pytest.raises(P.PPMError):
+            P.div31_params(bad)
