@@ -103,6 +103,23 @@ def _long_rows(seed):
     return I.Workload("long_rows", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 1)
 
 
+def _thin(seed, bc):
+    """Boxes of 1, 3 and 4 zones along x, 2 and 2 along y, 1 and 5 along z:
+    ghost shells span several boxes and periodic images, so the fill
+    transpose adds many ghost adjoints into one zone, and the x kernels run
+    on rows of 3 to 6 traced zones."""
+    rng = np.random.default_rng(seed)
+    lay = I.tensor_tiling(np.array([1, 3, 4]), np.array([2, 2]), np.array([1, 5]), bc=bc)
+    L = tuple((np.array(lay.domain_hi) + 1) / 16.0)
+    S = [I.ModeSum(rng, 4, 2, L) for _ in range(5)]
+
+    def prim(x, y, z):
+        return (1.0 + 0.3 * S[0](x, y, z), 0.5 * S[1](x, y, z), 0.5 * S[2](x, y, z), 0.5 * S[3](x, y, z),
+                1.0 + 0.3 * S[4](x, y, z))
+    h = (1.0 / 16,) * 3
+    return I.Workload("thin", lay, I._fill_state(lay, h, 1.4, prim), h, 1.4, 1)
+
+
 CASES = {
     "smooth_box": lambda: I.cfg4(10, amp=0.05),
     "sod_box": lambda: I.cfg2(12),
@@ -111,6 +128,8 @@ CASES = {
     "outflow": lambda: _uneven(5, bc=(1, 1, 0, 0, 0, 0)),
     "rayleigh_taylor_boxes": lambda: I.cfg5(nb=2, m=8, precision=0),
     "long_rows": lambda: _long_rows(6),
+    "thin_boxes_periodic": lambda: _thin(7, (0, 0, 0, 0, 0, 0)),
+    "thin_boxes_walls": lambda: _thin(8, (1, 1, 0, 0, 2, 2)),
 }
 
 
@@ -270,7 +289,7 @@ def test_rollout_gradient_against_central_differences():
         assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
 
 
-@pytest.mark.parametrize("case", ["smooth_box", "sod_box", "multibox", "rayleigh_taylor_boxes"])
+@pytest.mark.parametrize("case", ["smooth_box", "sod_box", "multibox", "rayleigh_taylor_boxes", "thin_boxes_walls"])
 def test_fp32_reconstruction_adjoint(case):
     """The FP32-reconstruction step's adjoint (reverse stages in FP32, the
     update's reverse and the output in FP64) against the oracle's tangent of
