@@ -372,10 +372,11 @@ def adjoint_costs(wl, nsteps, every, reps=10, precision=0, rollout=True):
 # 8 + 8, trace 3 x 8 read + 6 x 8 written, stage 1 6 x 8 + 3 x 8, stage 2
 # (6 + 3) x 8 + 6 x 8, stage 3 (6 + 6) x 8 + 3 x 8, update 3 x 8 + 8 + 8;
 # plus the hydro planes the stages read once per zone for all species
-# (density for the fractions; flattening, normal velocity and sound speed
-# per axis; stage mass fluxes and traced densities).
+# (density for the fractions; flattening, normal velocity, density and
+# pressure per axis, the last two for the sound speed; stage mass fluxes and
+# traced densities).
 SPECIES_BYTES_PER_ZONE_SPECIES = 16 + 72 + 72 + 120 + 120 + 40
-SPECIES_SHARED_BYTES_PER_ZONE = 8 + 72 + 24 + 120 + 120
+SPECIES_SHARED_BYTES_PER_ZONE = 8 + 96 + 24 + 120 + 120
 
 
 def species_costs(wl, ns, steps, warmup, precision=0):

@@ -621,7 +621,7 @@ __device__ __forceinline__ void trace_reverse_zone(bool act, const S* __restrict
   S un = 0, c = 0;
   if (act) {
     un = prim[(1 + d) * LS + base];
-    c = prim[5 * LS + base];
+    c = sound_speed(prim[base], prim[4 * LS + base], G);
   }
   S phib = 0;
   // one field's parabola adjoint -> its stencil contributions (the stencil

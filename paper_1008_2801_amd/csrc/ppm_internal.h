@@ -141,7 +141,7 @@ constexpr int E_F1 = E_TRACE + 30;  // + d*5 + m
 constexpr int E_F2 = E_F1 + 15;     // + pair*5 + m, pair = 2*d + (t > d ? t-1 : t)
 constexpr int E_F3 = E_F2 + 30;     // + d*5 + m
 constexpr int E_PLANES = E_F3 + 15;
-constexpr int P_PLANES = 6;         // rho, u, v, w, p, c
+constexpr int P_PLANES = 5;         // rho, u, v, w, p
 
 // Prescribed ghost states of inflow faces: p[face] (null if the face is not
 // an inflow face) holds 5 conserved components over the domain's extents of

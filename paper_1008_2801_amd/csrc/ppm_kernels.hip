@@ -59,7 +59,9 @@ __global__ void __launch_bounds__(64) k_step_consts(StepConsts* c, double dt, co
   if (threadIdx.x == 0) step_consts(c, dt, dt_dev, h0, h1, h2, g0, g1, g2);
 }
 
-// O2 on every stored zone: (rho, u, v, w, p, c) planes.
+// O2 on every stored zone: (rho, u, v, w, p) planes.  The sound speed is
+// formed here for the range check only: the stages that use it form it again
+// from rho and p (one plane less to write and to read).
 // t: the tile (-1: none), here and in the other stage bodies.
 template <class S>
 __device__ __forceinline__ void prim_body(int t, const Tile* __restrict__ tiles, const DevBox* __restrict__ boxes,
@@ -86,7 +88,7 @@ __device__ __forceinline__ void prim_body(int t, const Tile* __restrict__ tiles,
   if (!fin || !(r > S(0)) || !(p > S(0))) fl |= PPM_FLAG_NONPHYS;
   if (p < G.small_pres) fl |= PPM_FLAG_FLOOR;
   p = smax(p, G.small_pres);
-  const S c = ssqrt(G.gamma * p / r);
+  const S c = sound_speed(r, p, G);
   // magnitudes for which the shortened FP64 divisions and roots of the
   // later stages are the IEEE results (zero velocities included)
   if (!(in_range(r) && in_range(p) && in_range(c) && speed_in_range(vx) && speed_in_range(vy) &&
@@ -98,7 +100,6 @@ __device__ __forceinline__ void prim_body(int t, const Tile* __restrict__ tiles,
   q[2 * LS] = vy;
   q[3 * LS] = vz;
   q[4 * LS] = p;
-  q[5 * LS] = c;
   raise_flags(flags, fl);
 }
 
@@ -190,7 +191,7 @@ __device__ __forceinline__ void trace_at(const DevBox& B, int x, int y, int z, l
 #pragma unroll
     for (int o = 0; o < 5; ++o) v[m][o] = a[(o - 2) * st];
   }
-  const S c = prim[5 * LS + base];
+  const S c = sound_speed(v[0][2], v[4][2], G);
   const S phi = work[E_FLAT * LE + B.eoff + e];
   S aL[5], aR[5], a6[5];
 #pragma unroll

@@ -147,6 +147,11 @@ PPM_HD float scopysign(float m, float s) { return __builtin_copysignf(m, s); }
 // and their differences stay within 2^-800 .. 2^600).
 template <class S> PPM_HD bool in_range(S x) { return x >= S(0x1p-120) && x <= S(0x1p120); }
 template <class S> PPM_HD bool speed_in_range(S u) { return sabs(u) <= S(0x1p120); }
+// The sound speed sqrt(gamma p / rho) of a zone's primitives (IEEE division
+// and root).  The conversion forms it, and every stage that needs it forms
+// it again from the stored density and pressure, by this one expression, so
+// all of them hold the same bits.
+template <class S> PPM_HD S sound_speed(S r, S p, const Gas<S>& G) { return ssqrt(G.gamma * p / r); }
 // a b > 0: the MC slope and the CW84 limiter test the sign of a product of
 // two differences of one field.
 template <class S> PPM_HD bool same_sign(S a, S b) { return a * b > S(0); }

@@ -81,7 +81,7 @@ __device__ __forceinline__ void sp_trace_body(const Tile* __restrict__ tiles, in
   const long long base = pidx(B, z.x[0], z.x[1], z.x[2]);
   const long long st = stride(NS, d);
   const S phi = work[E_FLAT * LE + B.eoff + z.e];
-  const S un = prim[(1 + d) * LS + base], c = prim[5 * LS + base];
+  const S un = prim[(1 + d) * LS + base], c = sound_speed(prim[base], prim[4 * LS + base], G);
   const S dtdx = SC<S>::dtdx(sc)[d];
   const S zero = S(0);
   const S l1 = un - c, l2 = un, l3 = un + c;
