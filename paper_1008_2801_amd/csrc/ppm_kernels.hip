@@ -1014,25 +1014,34 @@ __global__ void __launch_bounds__(64) k_finish_dt(double* dt_dev, double cfl) {
   }
 }
 
-// O1: ghost fill over the plan.  One lane per destination ghost zone; the
-// descriptor of a lane is found by binary search in the zone-count prefix.
+// O1: ghost fill over the plan.  One lane per destination ghost zone.  A
+// lane's descriptor is the last one whose zone-count prefix does not exceed
+// the lane's zone: one binary search per wavefront for its first zone (in
+// scalar registers, so the dependent loads go through the scalar cache),
+// then each lane steps forward over the few descriptors the wavefront's 64
+// zones span.  Zone offsets within a descriptor (a slab of a ghost shell)
+// stay below 2^31, so the region is decoded in 32 bits.
 __global__ void __launch_bounds__(FILL_THREADS) k_fill(const FillDesc* __restrict__ desc,
                                                const long long* __restrict__ start, int d0, int d1,
                                                long long z0, long long z1,
                                                const DevBox* __restrict__ boxes, double* U, InflowView inf) {
   const long long gidx = z0 + (long long)blockIdx.x * FILL_THREADS + threadIdx.x;
-  if (gidx >= z1) return;
+  if (gidx >= z1) return;  // lane 0 of a wavefront has its smallest zone
+  const long long gw =
+      z0 + (long long)blockIdx.x * FILL_THREADS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x & ~63u));
   int lo = d0, hi = d1 - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= gidx) lo = mid; else hi = mid - 1;
+    if (start[mid] <= gw) lo = mid; else hi = mid - 1;
   }
+  while (lo + 1 < d1 && start[lo + 1] <= gidx) ++lo;
   const FillDesc D = desc[lo];
-  const long long l = gidx - start[lo];
-  const int ex = D.hi[0] - D.lo[0] + 1, ey = D.hi[1] - D.lo[1] + 1;
-  const int x = D.lo[0] + (int)(l % ex);
-  const int y = D.lo[1] + (int)((l / ex) % ey);
-  const int zz = D.lo[2] + (int)(l / ((long long)ex * ey));
+  const unsigned l = (unsigned)(gidx - start[lo]);
+  const unsigned ex = (unsigned)(D.hi[0] - D.lo[0] + 1), ey = (unsigned)(D.hi[1] - D.lo[1] + 1);
+  const unsigned q = l / ex, r = q / ey;
+  const int x = D.lo[0] + (int)(l - q * ex);
+  const int y = D.lo[1] + (int)(q - r * ey);
+  const int zz = D.lo[2] + (int)r;
   const int sx = D.a[0] * x + D.c[0], sy = D.a[1] * y + D.c[1], sz = D.a[2] * zz + D.c[2];
   const DevBox Bd = boxes[D.dst];
   const int dN0 = Bd.n[0] + 2 * NG, dN1 = Bd.n[1] + 2 * NG, dN2 = Bd.n[2] + 2 * NG;
