@@ -95,11 +95,11 @@ __device__ __forceinline__ void prim_body(int t, const Tile* __restrict__ tiles,
         speed_in_range(vz)))
     fl |= PPM_FLAG_RANGE;
   S* q = prim + B.poff + idx;
-  q[0] = r;
-  q[LS] = vx;
-  q[2 * LS] = vy;
-  q[3 * LS] = vz;
-  q[4 * LS] = p;
+  __builtin_nontemporal_store(r, &q[0]);
+  __builtin_nontemporal_store(vx, &q[LS]);
+  __builtin_nontemporal_store(vy, &q[2 * LS]);
+  __builtin_nontemporal_store(vz, &q[3 * LS]);
+  __builtin_nontemporal_store(p, &q[4 * LS]);
   raise_flags(flags, fl);
 }
 
@@ -255,7 +255,7 @@ __device__ __forceinline__ void stage1_face(const DevBox& B, int xd, S L[5], S R
   riemann<d>(L, R, G, F, fl);
   S* f = work + B.eoff + e;
 #pragma unroll
-  for (int m = 0; m < 5; ++m) f[(E_F1 + d * 5 + m) * LE] = F[m];
+  for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(F[m], &f[(E_F1 + d * 5 + m) * LE]);
 }
 
 // O7: F^d at d-face slots x_d in [0, n], transverse in [-1, n].
@@ -527,7 +527,7 @@ __device__ __forceinline__ void riemann2_pair(const S* __restrict__ w, S* __rest
   S F[5];
   riemann<d>(L, R, G, F, fl);
 #pragma unroll
-  for (int m = 0; m < 5; ++m) o[(E_F2 + pr * 5 + m) * LE] = F[m];
+  for (int m = 0; m < 5; ++m) __builtin_nontemporal_store(F[m], &o[(E_F2 + pr * 5 + m) * LE]);
 }
 
 template <int d, class S>

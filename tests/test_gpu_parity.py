@@ -354,7 +354,9 @@ def test_cfg2_recipe_at_64_cubed_twenty_steps_whole_grid():
 
 def test_tiling_does_not_change_results_and_autotuner_caches(tmp_path):
     """Every tile size / strip order gives the same bits; the autotuner
-    picks one of them and a second call takes it from its cache file."""
+    picks one of them (and one of the three final-stage forms, which give
+    the same bits, whichever times fastest) and a second call takes it from
+    its cache file."""
     wl = _uneven_level(seed=13)
     ref = gpu_run(wl, 2)[1]
     for tiling in [(128, 8), (512, 0), (64, 16), (256, 64)]:
@@ -368,7 +370,7 @@ def test_tiling_does_not_change_results_and_autotuner_caches(tmp_path):
     t, s, hit = lev.autotune(U, wl.dx, p, reps=1, cache_path=cache)
     assert not hit and t in (128, 256, 512) and s in (0, 8, 16, 32, 64)
     form, shape = lev.get_step_form(), lev.get_stream_tiling()
-    assert form in (0, 2)
+    assert form in (0, 1, 2)
     lev2 = P.Level(wl.layout)
     t2, s2, hit2 = lev2.autotune(U, wl.dx, p, reps=1, cache_path=cache)
     assert hit2 and (t2, s2) == (t, s) and lev2.get_tiling() == (t, s)
