@@ -680,7 +680,8 @@ __device__ __forceinline__ void trace_reverse_zone(bool act, const S* __restrict
 
 // Trace adjoint of axis d: per traced zone, the contributions to the
 // primitives of its 5-zone stencil along d (GT of axis d), the sound speed
-// (CB of axis d) and the flattening coefficient (PHB of axis d).  One launch
+// (CB of axis d) and the flattening coefficient (PHB of axis d), stored
+// non-temporally: only the gather, several launches later, reads them.  One launch
 // per axis: the bodies of several axes in one kernel would share the
 // register budget of the largest and spill.  The two field groups keep the
 // FP64 kernel at 168 registers, 3 waves per SIMD (a few values spill).
@@ -705,10 +706,10 @@ k_adj_trace(const Tile* __restrict__ tiles, int ntiles, const DevBox* __restrict
                         [&](int side, int m) { return a[(A_TB + (d * 2 + side) * 5 + m) * LE]; }, G,
                         SC<S>::dtdx(sc)[d], cb, phib, [&](int m, const S ab[5]) {
 #pragma unroll
-                          for (int o = 0; o < 5; ++o) a[(A_GT + (d * 5 + m) * 5 + o) * LE] = ab[o];
+                          for (int o = 0; o < 5; ++o) __builtin_nontemporal_store(ab[o], &a[(A_GT + (d * 5 + m) * 5 + o) * LE]);
                         });
-  a[(A_CB + d) * LE] = cb;
-  a[(A_PHB + d) * LE] = phib;
+  __builtin_nontemporal_store(cb, &a[(A_CB + d) * LE]);
+  __builtin_nontemporal_store(phib, &a[(A_PHB + d) * LE]);
 }
 
 // Stage-1 reverse and trace adjoint along x in one kernel, over runs of
